@@ -1,0 +1,366 @@
+"""Pins for the oracle: facts fixed by the paper and by mathematics, not by the
+oracle itself.  Both oracle evaluations (Python ints and plain C) are held to
+each pin.
+
+Pins used (paper = arXiv 2105.13678):
+  * Lucas-Lehmer: every tabled exponent up to 23,209 gives a Mersenne prime,
+    and no other prime exponent below 2,400 does (Sec. 3.1 asks for p = M_gamma).
+  * Table 3 shapes: CV ratio 0.0972 -> k = 10, DV ratio 0.2957 -> k = 3.
+  * Closed forms: with one-hot a = 2^s e_i, b = 1, c = 0 the MMH value is x_i
+    rotated left by s within gamma bits (2^gamma = 1 mod p); with a_i = p - 1
+    it is p - x_i; the sum S = p folds to y = 0 (canonical Z_p, eq. 2).
+  * MH special cases (eq. 4): b = 1 gives U = y + c; b = 2^gamma - 1 gives
+    U = c - y; y = 1, c = 0 gives U = b; r = gamma - 1 gives z = U >> 1.
+  * Linearity of MMH over Z_p in x and in a (eq. 2).
+  * Universality: empirical collision rate on a tiny domain within
+    1/p + 2^(1-r) (MMH bound 1/p, Sec. 2.1; multiply-shift bound for MH).
+  * Products against CPython's integer multiplication (a library routine).
+  * Status: all-ones chunk -> RELOAD (Alg. 1), even b / out-of-range seeds.
+"""
+import math
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import defn
+from paper_2105_13678_amd import synth
+
+
+def words(v, nw):
+    return defn.int_to_words(v, nw)
+
+
+def key_from_chunks(chunks, gamma, n):
+    K = 0
+    for i, x in enumerate(chunks):
+        K |= x << (i * gamma)
+    K &= (1 << n) - 1
+    return words(K, (n + 63) // 64)
+
+
+def run_both(key, n, r, gamma, a_list, b, c):
+    """Evaluate with the Python definition and the C oracle; check they agree."""
+    W = (gamma + 63) // 64
+    a_w = np.concatenate([words(ai, W) for ai in a_list])
+    st1, z1, y1, U1 = defn.hash_words(key, n, r, gamma, a_w, words(b, W), words(c, W))
+    st2, out, y2, U2 = oracle.hash(key, n, r, gamma, a_w, words(b, W), words(c, W), stages=True)
+    assert st1 == st2
+    if st1 != 0:
+        return st1, None, None, None
+    assert defn.words_to_int(out) == z1
+    assert defn.words_to_int(y2) == y1
+    assert defn.words_to_int(U2) == U1
+    return st1, z1, y1, U1
+
+
+# ---------------------------------------------------------------- Mersenne table
+
+def _lucas_lehmer(q):
+    if q == 2:
+        return True
+    m = (1 << q) - 1
+    s = 4
+    for _ in range(q - 2):
+        s = s * s - 2
+        s = (s & m) + (s >> q)  # reduction mod 2^q - 1 by folding
+        if s >= m:
+            s -= m
+    return s == 0
+
+
+def _primes_below(n):
+    sieve = bytearray([1]) * n
+    sieve[0:2] = b"\x00\x00"
+    for i in range(2, int(n ** 0.5) + 1):
+        if sieve[i]:
+            sieve[i * i::i] = bytearray(len(sieve[i * i::i]))
+    return [i for i in range(n) if sieve[i]]
+
+
+def test_mersenne_table_is_sorted_and_matches_c_copy():
+    t = defn.MERSENNE_EXPONENTS
+    assert list(t) == sorted(t) and len(set(t)) == len(t) == 52
+    # the C oracle keeps its own copy: its plan rule must pick the same gamma
+    for i, e in enumerate(t):
+        st, g, k = oracle.plan(2 * e + 5, e - 1 if e > 2 else 1)
+        want = e if e > 2 else 2
+        assert st == 0 and g == want
+
+
+def test_lucas_lehmer_small_exponents_complete():
+    tabled = set(defn.MERSENNE_EXPONENTS)
+    for q in _primes_below(2400):
+        assert _lucas_lehmer(q) == (q in tabled), q
+
+
+@pytest.mark.slow
+def test_lucas_lehmer_tabled_up_to_23209():
+    for q in defn.MERSENNE_EXPONENTS:
+        if 2400 <= q <= 23209:
+            assert _lucas_lehmer(q), q
+
+
+# ---------------------------------------------------------------- plan rule
+
+def test_plan_table3_shapes():
+    # Table 3: CV compression ratio 0.0972 -> k = 10, DV 0.2957 -> k = 3
+    n = 10 * 25964951
+    st, g, k = defn.plan_shape(n, int(math.floor(0.0972 * n)))
+    assert (st, g, k) == (0, 25964951, 10)
+    n = 3 * 74207281
+    st, g, k = defn.plan_shape(n, int(math.floor(0.2957 * n)))
+    assert (st, g, k) == (0, 74207281, 3)
+    for impl in (defn.plan_shape, oracle.plan):
+        assert impl(260_000_000, 26_000_000, 0) == (0, 30402457, 9)
+        assert impl(1 << 20, (1 << 20) // 10, 0) == (0, 110503, 10)
+
+
+def test_plan_errors():
+    for impl in (defn.plan_shape, oracle.plan):
+        assert impl(1 << 32, (1 << 32) // 10, 0)[0] == defn.ERR_NO_GAMMA
+        assert impl(100, 100, 0)[0] == defn.ERR_ARG
+        assert impl(100, 0, 0)[0] == defn.ERR_ARG
+        assert impl(100, 10, 11)[0] == defn.ERR_GAMMA   # not a Mersenne exponent
+        assert impl(100, 13, 13)[0] == defn.ERR_GAMMA   # gamma must exceed r
+        assert impl(100, 12, 13) == (0, 13, 8)
+
+
+# ---------------------------------------------------------------- products
+
+@pytest.mark.parametrize("nw", [1, 2, 3, 31, 32, 33, 63, 64, 65, 127, 500, 1031, 4099])
+def test_oracle_product_matches_cpython(nw):
+    rng = random.Random(nw)
+    for pattern in ("rand", "ones", "sparse"):
+        if pattern == "rand":
+            a = [rng.getrandbits(64) for _ in range(nw)]
+            b = [rng.getrandbits(64) for _ in range(nw)]
+        elif pattern == "ones":
+            a = [2 ** 64 - 1] * nw
+            b = [2 ** 64 - 1] * nw
+        else:
+            a = [rng.choice([0, 1, 2 ** 63, 2 ** 64 - 1]) for _ in range(nw)]
+            b = [rng.choice([0, 1, 2 ** 63, 2 ** 64 - 1]) for _ in range(nw)]
+        A = np.array(a, dtype=np.uint64)
+        B = np.array(b, dtype=np.uint64)
+        assert defn.words_to_int(oracle.mul(A, B)) == defn.words_to_int(A) * defn.words_to_int(B)
+
+
+# ---------------------------------------------------------------- closed forms
+
+GAMMAS = [5, 13, 61, 89, 127, 521, 1279, 4423]
+
+
+@pytest.mark.parametrize("gamma", GAMMAS)
+def test_one_hot_seed_rotates_chunk(gamma):
+    rng = random.Random(gamma)
+    p = (1 << gamma) - 1
+    k = 4
+    n = k * gamma
+    for _ in range(6):
+        chunks = [rng.randrange(0, p) for _ in range(k)]
+        i = rng.randrange(k)
+        s = rng.randrange(gamma)
+        a = [0] * k
+        a[i] = 1 << s
+        r = rng.randrange(1, gamma)
+        st, z, y, U = run_both(key_from_chunks(chunks, gamma, n), n, r, gamma, a, 1, 0)
+        x = chunks[i]
+        rot = ((x << s) | (x >> (gamma - s))) & p if s else x
+        rot = 0 if rot == p else rot
+        assert st == 0 and y == rot and U == rot and z == rot >> (gamma - r)
+
+
+@pytest.mark.parametrize("gamma", GAMMAS)
+def test_minus_one_seed_complements(gamma):
+    rng = random.Random(gamma + 1)
+    p = (1 << gamma) - 1
+    k = 3
+    n = k * gamma
+    chunks = [0] * k
+    i = rng.randrange(k)
+    chunks[i] = rng.randrange(1, p)
+    a = [rng.randrange(p) for _ in range(k)]
+    a[i] = p - 1
+    st, z, y, U = run_both(key_from_chunks(chunks, gamma, n), n, 1, gamma, a, 1, 0)
+    assert y == p - chunks[i] == (~chunks[i]) & p
+
+
+@pytest.mark.parametrize("gamma", GAMMAS)
+def test_sum_equal_to_p_folds_to_zero(gamma):
+    p = (1 << gamma) - 1
+    rng = random.Random(gamma + 2)
+    c = rng.randrange(1 << gamma)
+    r = rng.randrange(1, gamma)
+    n = 2 * gamma
+    st, z, y, U = run_both(key_from_chunks([p - 1, 1], gamma, n), n, r, gamma, [1, 1], 1, c)
+    assert st == 0 and y == 0 and U == c and z == c >> (gamma - r)
+    # S = 2p: also 0; S = p + 1: 1
+    st, z, y, U = run_both(key_from_chunks([p - 1, 1], gamma, n), n, r, gamma, [2, 2], 1, 0)
+    assert y == 0
+    st, z, y, U = run_both(key_from_chunks([p - 1, 2], gamma, n), n, r, gamma, [1, 1], 1, 0)
+    assert y == 1
+
+
+@pytest.mark.parametrize("gamma", GAMMAS)
+def test_mh_special_cases(gamma):
+    rng = random.Random(gamma + 3)
+    p = (1 << gamma) - 1
+    k = 3
+    n = k * gamma - rng.randrange(gamma)  # ragged tail
+    for _ in range(4):
+        chunks = [rng.randrange(p) for _ in range(k)]
+        key = key_from_chunks(chunks, gamma, n)
+        a = [rng.randrange(p + 1) for _ in range(k)]
+        c = rng.randrange(1 << gamma)
+        b = rng.randrange(1 << gamma) | 1
+        _, _, y, _ = run_both(key, n, 1, gamma, a, b, c)
+        # b = 1: U = y + c mod 2^gamma
+        _, _, _, U = run_both(key, n, gamma - 1, gamma, a, 1, c)
+        assert U == (y + c) % (1 << gamma)
+        # b = 2^gamma - 1: U = c - y mod 2^gamma
+        _, z, _, U = run_both(key, n, gamma - 1, gamma, a, (1 << gamma) - 1, c)
+        assert U == (c - y) % (1 << gamma)
+        assert z == U >> 1  # r = gamma - 1
+        # r = 1: the top bit of U
+        _, z, _, U = run_both(key, n, 1, gamma, a, b, c)
+        assert z == U >> (gamma - 1)
+    # y = 1, c = 0 gives U = b: one-hot chunk equal to 1 with a = 1
+    b = rng.randrange(1 << gamma) | 1
+    chunks = [0] * k
+    chunks[1] = 1
+    a = [0, 1, 0]
+    _, _, y, U = run_both(key_from_chunks(chunks, gamma, k * gamma), k * gamma, 2, gamma, a, b, 0)
+    assert y == 1 and U == b
+
+
+@pytest.mark.parametrize("gamma", [13, 89, 521, 4423])
+def test_mmh_linear_in_key_and_seed(gamma):
+    rng = random.Random(gamma + 4)
+    p = (1 << gamma) - 1
+    k = 5
+    n = k * gamma
+    for _ in range(4):
+        x1 = [rng.randrange(p) for _ in range(k)]
+        x2 = [rng.randrange(p) for _ in range(k)]
+        xs = [(u + v) % p for u, v in zip(x1, x2)]
+        a1 = [rng.randrange(p) for _ in range(k)]
+        a2 = [rng.randrange(p) for _ in range(k)]
+        as_ = [(u + v) % p for u, v in zip(a1, a2)]
+        y = lambda a, x: run_both(key_from_chunks(x, gamma, n), n, 1, gamma, a, 1, 0)[2]
+        assert y(a1, xs) == (y(a1, x1) + y(a1, x2)) % p
+        assert y(as_, x1) == (y(a1, x1) + y(a2, x1)) % p
+        assert y(a1, [0] * k) == 0
+
+
+# ---------------------------------------------------------------- universality
+
+def test_collision_rate_tiny_domain():
+    """Collision probability over random seeds for fixed distinct inputs.
+
+    gamma = 13, k = 2: for distinct x != x' in Z_p^2 the composed family
+    collides with probability at most 1/p + 2^(1-r) (MMH: 1/p; MH: 2^(1-r)).
+    Checked for several pairs with a 4-sigma binomial margin."""
+    gamma, k = 13, 2
+    p = (1 << gamma) - 1
+    rng = np.random.default_rng(7)
+    trials = 40000
+    for r in (3, 5, 8):
+        bound = 1.0 / p + 2.0 ** (1 - r)
+        for pair in range(3):
+            x = rng.integers(0, p, size=k)
+            xp = x.copy()
+            xp[pair % k] = (xp[pair % k] + 1 + pair) % p
+            a = rng.integers(0, p, size=(trials, k))
+            b = rng.integers(0, 1 << gamma, size=trials) | 1
+            c = rng.integers(0, 1 << gamma, size=trials)
+            y = (a[:, 0] * int(x[0]) + a[:, 1] * int(x[1])) % p
+            yp = (a[:, 0] * int(xp[0]) + a[:, 1] * int(xp[1])) % p
+            z = ((b * y + c) % (1 << gamma)) >> (gamma - r)
+            zp = ((b * yp + c) % (1 << gamma)) >> (gamma - r)
+            rate = float(np.mean(z == zp))
+            sigma = math.sqrt(bound * (1 - bound) / trials)
+            assert rate <= bound + 4 * sigma, (r, pair, rate, bound)
+    # the same family evaluated through both oracles on a few seeds
+    for t in range(20):
+        a = [int(v) for v in rng.integers(0, p, size=k)]
+        b = int(rng.integers(0, 1 << gamma)) | 1
+        c = int(rng.integers(0, 1 << gamma))
+        xs = [int(v) for v in rng.integers(0, p, size=k)]
+        st, z, y, U = run_both(key_from_chunks(xs, gamma, 2 * gamma), 2 * gamma, 5, gamma, a, b, c)
+        assert y == (a[0] * xs[0] + a[1] * xs[1]) % p
+
+
+# ---------------------------------------------------------------- status codes
+
+def test_status_codes():
+    gamma, k = 89, 3
+    p = (1 << gamma) - 1
+    n = k * gamma
+    key = key_from_chunks([5, p, 7], gamma, n)
+    assert run_both(key, n, 10, gamma, [1, 2, 3], 3, 4)[0] == defn.RELOAD
+    key = key_from_chunks([5, 6, 7], gamma, n)
+    assert run_both(key, n, 10, gamma, [1, 2, 3], 4, 4)[0] == defn.ERR_SEED_B_EVEN
+    assert run_both(key, n, 10, gamma, [1, 1 << gamma, 3], 3, 4)[0] == defn.ERR_SEED_RANGE
+    assert run_both(key, n, 10, gamma, [1, 2, 3], 3, 1 << gamma)[0] == defn.ERR_SEED_RANGE
+    # precedence: range beats even b beats reload
+    key = key_from_chunks([5, p, 7], gamma, n)
+    assert run_both(key, n, 10, gamma, [1, 1 << gamma, 3], 4, 4)[0] == defn.ERR_SEED_RANGE
+    assert run_both(key, n, 10, gamma, [1, 2, 3], 4, 4)[0] == defn.ERR_SEED_B_EVEN
+    # an all-ones chunk cut short by n is not all ones (zero padding)
+    n2 = n - 1
+    key = key_from_chunks([5, 6, p], gamma, n2)
+    assert run_both(key, n2, 10, gamma, [1, 2, 3], 3, 4)[0] == 0
+    # a seed chunk equal to 2^gamma - 1 is accepted and acts as 0 mod p
+    key = key_from_chunks([5, 6, 7], gamma, n)
+    s1 = run_both(key, n, 10, gamma, [1, p, 3], 3, 4)
+    s2 = run_both(key, n, 10, gamma, [1, 0, 3], 3, 4)
+    assert s1[0] == 0 and s1[2] == s2[2]
+
+
+def test_output_length_and_key_tail_ignored():
+    rng = random.Random(11)
+    for _ in range(50):
+        gamma = rng.choice([61, 89, 127, 521])
+        r = rng.randrange(1, gamma)
+        n = rng.randrange(r + 1, 5 * gamma)
+        st, g, k = defn.plan_shape(n, r, gamma)
+        blk = synth.single_block(rng.getrandbits(32), n, r, g, k)
+        st, out = oracle.hash(blk.key, n, r, g, blk.a, blk.b, blk.c)
+        assert st == 0 and len(out) == (r + 63) // 64
+        assert defn.words_to_int(out) >> r == 0
+        # bits past n in the last key word do not matter
+        key2 = blk.key.copy()
+        if n % 64:
+            key2[-1] |= np.uint64(((1 << 64) - 1) ^ ((1 << (n % 64)) - 1))
+            st2, out2 = oracle.hash(key2, n, r, g, blk.a, blk.b, blk.c)
+            assert st2 == 0 and np.array_equal(out, out2)
+
+
+# ---------------------------------------------------------------- random agreement
+
+def test_c_oracle_matches_definition_random():
+    rng = random.Random(5)
+    small = [e for e in defn.MERSENNE_EXPONENTS if e <= 4423]
+    for t in range(1500):
+        g = rng.choice(small)
+        r = rng.randrange(1, g) if g > 2 else 1
+        n = rng.randrange(r + 1, 9 * g + 2)
+        st, g2, k = defn.plan_shape(n, r, g)
+        assert st == 0
+        blk = synth.single_block(10_000 + t, n, r, g, k)
+        s1, z1, y1, U1 = defn.hash_words(blk.key, n, r, g, blk.a, blk.b, blk.c)
+        s2, out, y2, U2 = oracle.hash(blk.key, n, r, g, blk.a, blk.b, blk.c, stages=True)
+        assert s1 == s2 and s1 in (0, defn.RELOAD)  # tiny gamma: all-ones chunks happen
+        if s1 == 0:
+            assert defn.words_to_int(out) == z1 and defn.words_to_int(y2) == y1
+
+
+def test_c_oracle_matches_definition_one_mib_block():
+    n = 1 << 20
+    st, g, k = defn.plan_shape(n, n // 10)
+    blk = synth.single_block(1, n, n // 10, g, k)
+    s1, z1, y1, U1 = defn.hash_words(blk.key, n, n // 10, g, blk.a, blk.b, blk.c)
+    s2, out = oracle.hash(blk.key, n, n // 10, g, blk.a, blk.b, blk.c)
+    assert s1 == s2 == 0 and defn.words_to_int(out) == z1
