@@ -1,0 +1,166 @@
+/*
+ * pa.h -- C interface of libpa, the MI355X (gfx950) implementation of the
+ * MMH-MH privacy-amplification hash of Yan, Li, Mao and Chen, "An efficient
+ * hybrid hash based privacy amplification algorithm for quantum key
+ * distribution" (arXiv 2105.13678).
+ *
+ * The hash (Algorithm 1, with MMH from Sec. 2.1 eq. (2) and MH from Sec. 2.2
+ * eq. (4)):
+ *
+ *   inputs   key x of n bits; output length r (the paper's beta)
+ *   plan     gamma = Mersenne exponent with gamma > r; p = 2^gamma - 1;
+ *            k = ceil(n / gamma)                       (Sec. 4, Table 3)
+ *   split    x_i = key bits [i*gamma, (i+1)*gamma), zero past bit n
+ *   reload   some x_i == 2^gamma - 1  ->  PA_RELOAD, nothing written
+ *   MMH      y = (sum_{i<k} a_i x_i) mod p, canonical in [0, p)
+ *   MH       U = (b*y + c) mod 2^gamma;   z = U >> (gamma - r)
+ *
+ * Bit order is little-endian everywhere: key bit j is bit (j mod 64) of word
+ * j/64; bit t of chunk x_i is key bit i*gamma + t; bit t of the output z is
+ * bit gamma - r + t of U.
+ *
+ * All buffers passed to the hash entry points are DEVICE pointers on the
+ * plan's device, owned by the caller, and must stay valid until the call has
+ * completed on its stream.  Layouts (all uint64_t little-endian words):
+ *   key : ceil(n/64) words; bits >= n of the last word are ignored
+ *   a   : k chunks of W = ceil(gamma/64) words, chunk i at a + i*W
+ *   b, c: W words each; b must be odd
+ *   out : ceil(r/64) words; bits >= r of the last word are written as 0
+ * Every seed word must have its bits >= gamma (within its chunk) clear.
+ *
+ * Errors are return codes; nothing is thrown across this interface.  Errors
+ * the host can see (arguments, plan shape) return before any launch.
+ * Conditions found on the device (RELOAD, SEED_B_EVEN, SEED_RANGE) come back
+ * through a status word; on any status other than PA_OK the output buffer is
+ * left untouched.  A plan must be used by one host thread at a time.
+ */
+#ifndef PA_H
+#define PA_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pa_status {
+    PA_OK = 0,
+    PA_PENDING = 1,          /* request not finished yet (pa_poll)                       */
+    PA_RELOAD = 2,           /* a key chunk equals 2^gamma - 1: the block must be
+                                replaced (Sec. 3.1; Algorithm 1, reload branch)           */
+    PA_ERR_ARG = -1,         /* bad argument (NULL pointer, r < 1, r >= n, n < 2, ...)  */
+    PA_ERR_NO_GAMMA = -2,    /* no known Mersenne exponent exceeds r                    */
+    PA_ERR_GAMMA = -3,       /* requested gamma is not a Mersenne exponent or <= r      */
+    PA_ERR_INEXACT = -4,     /* limb width B too wide: k*L*(2^B-1)^2 >= NTT prime      */
+    PA_ERR_SEED_B_EVEN = -5, /* b is even (MH needs gcd(b, 2) = 1, Sec. 2.2 eq. (3))    */
+    PA_ERR_SEED_RANGE = -6,  /* a seed word has a bit >= gamma set                      */
+    PA_ERR_NOMEM = -7,       /* device allocation failed                                */
+    PA_ERR_DEVICE = -8,      /* a HIP call failed                                       */
+    PA_ERR_BUSY = -9,        /* no free slot / queue full                               */
+    PA_ERR_LIMIT = -10       /* shape outside the supported range (see pa_plan_create)  */
+} pa_status;
+
+/* Plan request.  gamma = 0 picks the smallest Mersenne exponent above r.
+ * B = 0 picks the default limb width (16 bits); otherwise 8 <= B <= 20. */
+typedef struct pa_params {
+    uint64_t n;       /* input key length in bits, n >= 2                    */
+    uint64_t r;       /* output length in bits, 1 <= r < n and r < gamma     */
+    uint64_t gamma;   /* Mersenne exponent, or 0 for automatic               */
+    uint32_t B;       /* limb width in bits (the paper's 2^B-ary words), 0 = auto */
+    uint32_t flags;   /* reserved, must be 0                                 */
+} pa_params;
+
+typedef struct pa_plan_info {
+    uint64_t n, r, gamma, k;
+    uint32_t B;             /* limb width                                   */
+    uint32_t log2N;         /* NTT length N = 2^log2N >= 2L - 1            */
+    uint64_t L;             /* limbs per gamma-bit number, ceil(gamma/B)    */
+    uint64_t N;
+    uint64_t key_words;     /* ceil(n/64)                                   */
+    uint64_t seed_words;    /* W = ceil(gamma/64), words per seed chunk     */
+    uint64_t a_words;       /* k * W                                        */
+    uint64_t out_words;     /* ceil(r/64)                                   */
+    uint64_t workspace_bytes; /* device memory owned by the plan            */
+    double exact_log2;      /* log2(k * L * (2^B - 1)^2), must be < 64      */
+} pa_plan_info;
+
+typedef struct pa_plan pa_plan;
+
+/* Create a plan for one (n, r) shape on HIP device `hip_device`: derives
+ * (gamma, k, L, N), checks that every convolution coefficient stays below the
+ * NTT prime 2^64 - 2^32 + 1 (PA_ERR_INEXACT otherwise), allocates the
+ * workspace and builds the twiddle tables.  Supported range: k <= 4096 and
+ * N <= 2^26 (PA_ERR_LIMIT otherwise).  On success *out owns device memory
+ * until pa_plan_destroy. */
+pa_status pa_plan_create(const pa_params *params, int hip_device, pa_plan **out);
+
+/* Derive the shape pa_plan_create would use, without touching any device:
+ * same checks and same return codes, and *info filled on PA_OK (its
+ * workspace_bytes is what pa_plan_create would allocate). */
+pa_status pa_plan_query(const pa_params *params, pa_plan_info *info);
+
+/* Fill *info with the derived shape of a plan. */
+pa_status pa_plan_get_info(const pa_plan *plan, pa_plan_info *info);
+
+/* Free a plan and its device memory.  NULL is ignored. */
+void pa_plan_destroy(pa_plan *plan);
+
+/* Hash one block (Algorithm 1) and wait for it: enqueues every kernel on
+ * `stream` (NULL = default stream), then synchronises the stream and returns
+ * the block's status.  On PA_OK, out holds z. */
+pa_status pa_hash(pa_plan *plan, const uint64_t *key, const uint64_t *a, const uint64_t *b,
+                  const uint64_t *c, uint64_t *out, hipStream_t stream);
+
+/* Same work as pa_hash but returns as soon as it is enqueued: the block's
+ * status flags are written to the device word *d_status (decode them with
+ * pa_decode_status after the stream has reached this point).  Returns PA_OK
+ * if everything was enqueued, or a host-side error. */
+pa_status pa_hash_async(pa_plan *plan, const uint64_t *key, const uint64_t *a,
+                        const uint64_t *b, const uint64_t *c, uint64_t *out,
+                        uint32_t *d_status, hipStream_t stream);
+
+/* Debug variant of pa_hash that also writes the two stage values: y (the MMH
+ * output, W words) and U (the MH value before truncation, W words), both
+ * device buffers.  Used to check the stage invariants (linearity of MMH over
+ * Z_p, affinity of U in y) without the oracle. */
+pa_status pa_hash_stages(pa_plan *plan, const uint64_t *key, const uint64_t *a,
+                         const uint64_t *b, const uint64_t *c, uint64_t *out,
+                         uint64_t *y_out, uint64_t *U_out, hipStream_t stream);
+
+/* Phases of the per-block launch sequence, for pa_plan_read_profile.  Each
+ * of the NTT phases is exactly one kernel launch. */
+typedef enum pa_phase {
+    PA_PH_PROLOGUE = 0,   /* seed checks, flag reset                         */
+    PA_PH_MMH_COL = 1,    /* unpack + forward column pass of 2k arrays, reload check */
+    PA_PH_MMH_ROW = 2,    /* row pass: k pairs forward, multiply-accumulate, inverse */
+    PA_PH_MMH_COLINV = 3, /* inverse column pass -> convolution coefficients */
+    PA_PH_FOLD = 4,       /* Mersenne fold + carry scans -> y                */
+    PA_PH_MH_COL = 5,     /* unpack + forward column pass of y and b         */
+    PA_PH_MH_ROW = 6,     /* row pass: forward, multiply, inverse            */
+    PA_PH_MH_COLINV = 7,  /* inverse column pass                             */
+    PA_PH_MH_CARRY = 8,   /* + c, carry scan mod 2^gamma -> U                 */
+    PA_PH_FINISH = 9,     /* output extraction, status                       */
+    PA_PH_COUNT = 10
+} pa_phase;
+
+/* Turn per-phase timing on (1) or off (0).  While on, every hash call on
+ * this plan records a HIP event pair around each phase on the call's stream. */
+pa_status pa_plan_set_profiling(pa_plan *plan, int enable);
+
+/* Wait for every recorded event, then return the summed milliseconds and the
+ * number of recorded calls per phase since the previous read (arrays of
+ * PA_PH_COUNT entries, host memory), and reset the sums. */
+pa_status pa_plan_read_profile(pa_plan *plan, double *ms, uint64_t *calls);
+
+/* Map a device status word written by pa_hash_async to a status code. */
+pa_status pa_decode_status(uint32_t flags);
+
+/* Static string naming a status code. */
+const char *pa_status_string(pa_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PA_H */

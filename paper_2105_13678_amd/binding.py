@@ -1,0 +1,205 @@
+"""ctypes binding of libpa (include/pa.h).  Argument marshalling only: every
+step of the hash runs in the HIP library; if the library is missing this
+module raises instead of computing anything itself.
+
+Device buffers are torch tensors (any 8-byte dtype, contiguous, on the plan's
+device); torch supplies memory and the current HIP stream, nothing else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpa.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pa.h")
+
+PA_OK, PA_PENDING, PA_RELOAD = 0, 1, 2
+PA_ERR_ARG, PA_ERR_NO_GAMMA, PA_ERR_GAMMA, PA_ERR_INEXACT = -1, -2, -3, -4
+PA_ERR_SEED_B_EVEN, PA_ERR_SEED_RANGE, PA_ERR_NOMEM, PA_ERR_DEVICE = -5, -6, -7, -8
+PA_ERR_BUSY, PA_ERR_LIMIT = -9, -10
+
+
+class PAError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})" if what else status_string(status))
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("r", ctypes.c_uint64), ("gamma", ctypes.c_uint64),
+                ("B", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("r", ctypes.c_uint64), ("gamma", ctypes.c_uint64),
+                ("k", ctypes.c_uint64), ("B", ctypes.c_uint32), ("log2N", ctypes.c_uint32),
+                ("L", ctypes.c_uint64), ("N", ctypes.c_uint64), ("key_words", ctypes.c_uint64),
+                ("seed_words", ctypes.c_uint64), ("a_words", ctypes.c_uint64),
+                ("out_words", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64),
+                ("exact_log2", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def lib():
+    """Load libpa.so (built in-tree); raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2105_13678_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.pa_plan_create.argtypes = [ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(_VP)]
+        L.pa_plan_create.restype = ctypes.c_int
+        L.pa_plan_query.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(PlanInfo)]
+        L.pa_plan_query.restype = ctypes.c_int
+        L.pa_plan_get_info.argtypes = [_VP, ctypes.POINTER(PlanInfo)]
+        L.pa_plan_get_info.restype = ctypes.c_int
+        L.pa_plan_destroy.argtypes = [_VP]
+        L.pa_plan_destroy.restype = None
+        L.pa_hash.argtypes = [_VP] * 7
+        L.pa_hash.restype = ctypes.c_int
+        L.pa_hash_async.argtypes = [_VP] * 8
+        L.pa_hash_async.restype = ctypes.c_int
+        L.pa_hash_stages.argtypes = [_VP] * 9
+        L.pa_hash_stages.restype = ctypes.c_int
+        L.pa_decode_status.argtypes = [ctypes.c_uint32]
+        L.pa_decode_status.restype = ctypes.c_int
+        L.pa_status_string.argtypes = [ctypes.c_int]
+        L.pa_status_string.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/pa.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(pa_[a-z_0-9]+)\s*\(", text, flags=re.M)
+
+
+def status_string(status: int) -> str:
+    try:
+        return lib().pa_status_string(int(status)).decode()
+    except RuntimeError:
+        return f"status {status}"
+
+
+def decode_status(flags: int) -> int:
+    return lib().pa_decode_status(int(flags) & 0xFFFFFFFF)
+
+
+def plan_query(n: int, r: int, gamma: int = 0, B: int = 0):
+    """(status, info dict or None): the shape pa_plan_create would use."""
+    prm = Params(n, r, gamma, B, 0)
+    info = PlanInfo()
+    st = lib().pa_plan_query(ctypes.byref(prm), ctypes.byref(info))
+    return st, (info.as_dict() if st == PA_OK else None)
+
+
+def _dev_ptr(t, min_words: int, what: str, device) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor")
+    if t.device.type != "cuda" or (device is not None and t.device != device):
+        raise ValueError(f"{what}: must live on {device}")
+    if t.element_size() != 8 or not t.is_contiguous():
+        raise ValueError(f"{what}: must be a contiguous 8-byte-element tensor")
+    if t.numel() < min_words:
+        raise ValueError(f"{what}: needs at least {min_words} words, got {t.numel()}")
+    return t.data_ptr()
+
+
+class Plan:
+    """One (n, r) shape on one GPU; owns its device workspace."""
+
+    def __init__(self, n: int, r: int, gamma: int = 0, B: int = 0, device: int = 0):
+        import torch
+        self._h = _VP()
+        self.device = torch.device("cuda", device)
+        prm = Params(n, r, gamma, B, 0)
+        st = lib().pa_plan_create(ctypes.byref(prm), int(device), ctypes.byref(self._h))
+        if st != PA_OK:
+            self._h = _VP()
+            raise PAError(st, "pa_plan_create")
+        info = PlanInfo()
+        lib().pa_plan_get_info(self._h, ctypes.byref(info))
+        self.info = info.as_dict()
+
+    def __getattr__(self, name):
+        info = self.__dict__.get("info")
+        if info is not None and name in info:
+            return info[name]
+        raise AttributeError(name)
+
+    def close(self):
+        if self._h:
+            lib().pa_plan_destroy(self._h)
+            self._h = _VP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _stream(self, stream):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return s.cuda_stream
+
+    def _args(self, key, a, b, c, out):
+        i = self.info
+        return (_dev_ptr(key, i["key_words"], "key", self.device),
+                _dev_ptr(a, i["a_words"], "a", self.device),
+                _dev_ptr(b, i["seed_words"], "b", self.device),
+                _dev_ptr(c, i["seed_words"], "c", self.device),
+                _dev_ptr(out, i["out_words"], "out", self.device))
+
+    def new_out(self):
+        import torch
+        return torch.zeros(self.info["out_words"], dtype=torch.int64, device=self.device)
+
+    def hash(self, key, a, b, c, out=None, stream=None):
+        """Blocking hash; returns (status, out)."""
+        if out is None:
+            out = self.new_out()
+        args = self._args(key, a, b, c, out)
+        st = lib().pa_hash(self._h, *args, self._stream(stream))
+        return st, out
+
+    def hash_async(self, key, a, b, c, out, d_status, stream=None):
+        """Enqueue only; status flags land in the 1-word device tensor d_status."""
+        import torch
+        args = self._args(key, a, b, c, out)
+        if d_status.device != self.device or d_status.numel() < 1:
+            raise ValueError("d_status must be a device tensor")
+        st = lib().pa_hash_async(self._h, *args, d_status.data_ptr(), self._stream(stream))
+        if st != PA_OK:
+            raise PAError(st, "pa_hash_async")
+        return out
+
+    def hash_stages(self, key, a, b, c, out=None, stream=None):
+        """Blocking hash that also returns the stage values (status, out, y, U)."""
+        import torch
+        if out is None:
+            out = self.new_out()
+        W = self.info["seed_words"]
+        y = torch.zeros(W, dtype=torch.int64, device=self.device)
+        U = torch.zeros(W, dtype=torch.int64, device=self.device)
+        args = self._args(key, a, b, c, out)
+        st = lib().pa_hash_stages(self._h, *args, y.data_ptr(), U.data_ptr(), self._stream(stream))
+        return st, out, y, U

@@ -1,0 +1,411 @@
+// C interface of libpa: plan creation (parameter rule of Sec. 4 / Table 3 of
+// arXiv 2105.13678), workspace layout and the per-block launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "pa_internal.hpp"
+
+namespace {
+
+// Exponents e for which 2^e - 1 is a known Mersenne prime (the paper asks for
+// p = M_gamma, Sec. 3.1 and Algorithm 1), increasing.
+const uint64_t kMersenne[] = {
+    2, 3, 5, 7, 13, 17, 19, 31, 61, 89, 107, 127, 521, 607, 1279, 2203, 2281,
+    3217, 4253, 4423, 9689, 9941, 11213, 19937, 21701, 23209, 44497, 86243,
+    110503, 132049, 216091, 756839, 859433, 1257787, 1398269, 2976221, 3021377,
+    6972593, 13466917, 20996011, 24036583, 25964951, 30402457, 32582657,
+    37156667, 42643801, 43112609, 57885161, 74207281, 77232917, 82589933,
+    136279841};
+
+constexpr uint32_t kDefaultB = 16;
+constexpr uint64_t kMaxK = 4096;
+constexpr uint32_t kMinLog2N = 6;
+constexpr uint32_t kMaxLog2N = 26;
+constexpr uint32_t kMaxLdsLog2 = 13;  // 2^13 words = 64 KiB of LDS per tile
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) return;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+pa_status plan_shape(const pa_params *prm, uint64_t *gamma, uint64_t *k, uint32_t *B) {
+    if (!prm || prm->flags != 0) return PA_ERR_ARG;
+    const uint64_t n = prm->n, r = prm->r;
+    if (n < 2 || r < 1 || r >= n) return PA_ERR_ARG;
+    uint64_t g = 0;
+    if (prm->gamma == 0) {
+        for (uint64_t e : kMersenne)
+            if (e > r) {
+                g = e;
+                break;
+            }
+        if (!g) return PA_ERR_NO_GAMMA;
+    } else {
+        bool found = false;
+        for (uint64_t e : kMersenne) found |= (e == prm->gamma);
+        if (!found || prm->gamma <= r) return PA_ERR_GAMMA;
+        g = prm->gamma;
+    }
+    uint32_t b = prm->B ? prm->B : kDefaultB;
+    if (b < 8 || b > 20) return PA_ERR_ARG;
+    *gamma = g;
+    *k = (n + g - 1) / g;
+    *B = b;
+    return PA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pa_status_string(pa_status s) {
+    switch (s) {
+        case PA_OK: return "PA_OK";
+        case PA_PENDING: return "PA_PENDING";
+        case PA_RELOAD: return "PA_RELOAD";
+        case PA_ERR_ARG: return "PA_ERR_ARG";
+        case PA_ERR_NO_GAMMA: return "PA_ERR_NO_GAMMA";
+        case PA_ERR_GAMMA: return "PA_ERR_GAMMA";
+        case PA_ERR_INEXACT: return "PA_ERR_INEXACT";
+        case PA_ERR_SEED_B_EVEN: return "PA_ERR_SEED_B_EVEN";
+        case PA_ERR_SEED_RANGE: return "PA_ERR_SEED_RANGE";
+        case PA_ERR_NOMEM: return "PA_ERR_NOMEM";
+        case PA_ERR_DEVICE: return "PA_ERR_DEVICE";
+        case PA_ERR_BUSY: return "PA_ERR_BUSY";
+        case PA_ERR_LIMIT: return "PA_ERR_LIMIT";
+    }
+    return "PA_UNKNOWN";
+}
+
+pa_status pa_decode_status(uint32_t flags) {
+    if (flags & pa::ST_SEED_RANGE) return PA_ERR_SEED_RANGE;
+    if (flags & pa::ST_B_EVEN) return PA_ERR_SEED_B_EVEN;
+    if (flags & pa::ST_RELOAD) return PA_RELOAD;
+    return PA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct Layout {
+    size_t oX, oC, oT, oS, oY, oU, oAgg, oTc, oRes, oNo, oSt, oSo, oT1, oT2, oW, total;
+};
+
+// Derive every plan quantity from the request; no device access.
+pa_status derive(const pa_params *prm, pa_plan *p, Layout *lay) {
+    uint64_t gamma, k;
+    uint32_t B;
+    pa_status st = plan_shape(prm, &gamma, &k, &B);
+    if (st != PA_OK) return st;
+    if (k > kMaxK) return PA_ERR_LIMIT;
+    const uint64_t L = (gamma + B - 1) / B;
+    // Exactness: every coefficient of sum_i a_i * x_i is at most k*L*(2^B-1)^2,
+    // which must stay below the NTT prime for the transform to be exact.
+    const unsigned __int128 bound = (unsigned __int128)k * L * (((1ull << B) - 1) * ((1ull << B) - 1));
+    if (bound >= (unsigned __int128)pa::GL_P) return PA_ERR_INEXACT;
+    uint32_t m = kMinLog2N;
+    while ((1ull << m) < 2 * L - 1) ++m;
+    if (m > kMaxLog2N) return PA_ERR_LIMIT;
+
+    p->n = prm->n;
+    p->r = prm->r;
+    p->gamma = gamma;
+    p->k = k;
+    p->B = B;
+    p->L = L;
+    p->N = 1ull << m;
+    p->W = (gamma + 63) / 64;
+    p->key_words = (prm->n + 63) / 64;
+    p->out_words = (prm->r + 63) / 64;
+    p->m = m;
+    p->m2 = (m + 3) / 2 < kMaxLdsLog2 ? (m + 3) / 2 : kMaxLdsLog2;
+    p->m1 = m - p->m2;
+    uint32_t c_lg = 4;
+    if (c_lg > p->m2) c_lg = p->m2;
+    if (p->m1 + c_lg > kMaxLdsLog2) c_lg = kMaxLdsLog2 - p->m1;
+    p->c_lg = c_lg;
+    p->s_top = (uint32_t)(gamma - (uint64_t)B * (L - 1));
+    p->e_fold = (uint32_t)((uint64_t)B * L - gamma);
+    const uint64_t Q = (64 + B - 1) / B, Q2 = (64 + p->e_fold + B - 1) / B;
+    p->M1 = L + (Q > Q2 ? Q : Q2) + 1;
+    const uint64_t digits = (p->M1 > L ? p->M1 : L) + 1;
+    p->ntiles_max = (digits + pa::SCAN_TILE - 1) / pa::SCAN_TILE + 1;
+    p->exact_log2 = std::log2((double)k) + std::log2((double)L) + 2.0 * std::log2((double)((1ull << B) - 1));
+
+    const size_t N = p->N;
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    lay->oX = carve(2 * k * N * 8);
+    lay->oC = carve(N * 8);
+    lay->oT = carve(digits * 4);
+    lay->oS = carve(p->M1 * 4);
+    lay->oY = carve(L * 4);
+    lay->oU = carve(L * 4);
+    lay->oAgg = carve(p->ntiles_max * sizeof(pa::CFn));
+    lay->oTc = carve(p->ntiles_max * 2 * 4);
+    lay->oRes = carve(sizeof(pa::ScanResult));
+    lay->oNo = carve(k * 4);
+    lay->oSt = carve(4 * 4);
+    lay->oSo = carve(4 * 4);
+    lay->oT1 = carve((N >> p->m2) / 2 * 8 * 2);
+    lay->oT2 = carve(((size_t)1 << p->m2) / 2 * 8 * 2);
+    lay->oW = carve(N * 8 * 2);
+    lay->total = off;
+    p->workspace_bytes = off;
+    return PA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pa_status pa_plan_query(const pa_params *prm, pa_plan_info *info) {
+    if (!info) return PA_ERR_ARG;
+    pa_plan tmp{};
+    Layout lay;
+    pa_status st = derive(prm, &tmp, &lay);
+    if (st != PA_OK) return st;
+    return pa_plan_get_info(&tmp, info);
+}
+
+pa_status pa_plan_create(const pa_params *prm, int hip_device, pa_plan **out) {
+    if (!out) return PA_ERR_ARG;
+    *out = nullptr;
+    pa_plan *p = new (std::nothrow) pa_plan();
+    if (!p) return PA_ERR_NOMEM;
+    Layout lay;
+    pa_status st = derive(prm, p, &lay);
+    if (st != PA_OK) {
+        delete p;
+        return st;
+    }
+    p->device = hip_device;
+    const size_t N = p->N;
+    const size_t off = lay.total;
+    const size_t oX = lay.oX, oC = lay.oC, oT = lay.oT, oS = lay.oS, oY = lay.oY, oU = lay.oU;
+    const size_t oAgg = lay.oAgg, oTc = lay.oTc, oRes = lay.oRes, oNo = lay.oNo, oSt = lay.oSt;
+    const size_t oSo = lay.oSo, oT1 = lay.oT1, oT2 = lay.oT2, oW = lay.oW;
+
+    DeviceGuard guard(hip_device);
+    if (!guard.ok) {
+        delete p;
+        return PA_ERR_DEVICE;
+    }
+    if (hipMalloc(&p->base, off) != hipSuccess) {
+        (void)hipGetLastError();
+        delete p;
+        return PA_ERR_NOMEM;
+    }
+    if (hipHostMalloc((void **)&p->h_status, 64, hipHostMallocDefault) != hipSuccess) {
+        (void)hipFree(p->base);
+        delete p;
+        return PA_ERR_NOMEM;
+    }
+    char *b = (char *)p->base;
+    p->X = (uint64_t *)(b + oX);
+    p->Cc = (uint64_t *)(b + oC);
+    p->t = (uint32_t *)(b + oT);
+    p->s = (uint32_t *)(b + oS);
+    p->y = (uint32_t *)(b + oY);
+    p->U = (uint32_t *)(b + oU);
+    p->agg = (pa::CFn *)(b + oAgg);
+    p->tcarry = (uint32_t *)(b + oTc);
+    p->res = (pa::ScanResult *)(b + oRes);
+    p->notones = (uint32_t *)(b + oNo);
+    p->status = (uint32_t *)(b + oSt);
+    p->status_out = (uint32_t *)(b + oSo);
+    const size_t h1 = (N >> p->m2) / 2, h2 = ((size_t)1 << p->m2) / 2;
+    p->tw1f = (uint64_t *)(b + oT1);
+    p->tw1i = p->tw1f + h1;
+    p->tw2f = (uint64_t *)(b + oT2);
+    p->tw2i = p->tw2f + h2;
+    p->Wf = (uint64_t *)(b + oW);
+    p->Wi = p->Wf + N;
+
+    hipStream_t s0 = nullptr;
+    if (pa::launch_twiddles(p, s0) != hipSuccess || hipStreamSynchronize(s0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(p->h_status);
+        (void)hipFree(p->base);
+        delete p;
+        return PA_ERR_DEVICE;
+    }
+    *out = p;
+    return PA_OK;
+}
+
+pa_status pa_plan_get_info(const pa_plan *p, pa_plan_info *info) {
+    if (!p || !info) return PA_ERR_ARG;
+    std::memset(info, 0, sizeof(*info));
+    info->n = p->n;
+    info->r = p->r;
+    info->gamma = p->gamma;
+    info->k = p->k;
+    info->B = p->B;
+    info->log2N = p->m;
+    info->L = p->L;
+    info->N = p->N;
+    info->key_words = p->key_words;
+    info->seed_words = p->W;
+    info->a_words = p->k * p->W;
+    info->out_words = p->out_words;
+    info->workspace_bytes = p->workspace_bytes;
+    info->exact_log2 = p->exact_log2;
+    return PA_OK;
+}
+
+void pa_plan_destroy(pa_plan *p) {
+    if (!p) return;
+    DeviceGuard guard(p->device);
+    (void)hipDeviceSynchronize();
+    if (p->pending) {
+        for (auto &e : *p->pending) {
+            (void)hipEventDestroy(e.a);
+            if (e.b) (void)hipEventDestroy(e.b);
+        }
+        delete p->pending;
+    }
+    if (p->event_pool) {
+        for (auto e : *p->event_pool) (void)hipEventDestroy(e);
+        delete p->event_pool;
+    }
+    (void)hipHostFree(p->h_status);
+    (void)hipFree(p->base);
+    delete p;
+}
+
+pa_status pa_plan_set_profiling(pa_plan *p, int enable) {
+    if (!p) return PA_ERR_ARG;
+    if (!p->pending) p->pending = new (std::nothrow) std::vector<pa_plan::EvPair>();
+    if (!p->event_pool) p->event_pool = new (std::nothrow) std::vector<hipEvent_t>();
+    if (!p->pending || !p->event_pool) return PA_ERR_NOMEM;
+    p->profiling = enable ? 1 : 0;
+    return PA_OK;
+}
+
+pa_status pa_plan_read_profile(pa_plan *p, double *ms, uint64_t *calls) {
+    if (!p || !ms || !calls) return PA_ERR_ARG;
+    for (int i = 0; i < PA_PH_COUNT; ++i) {
+        ms[i] = 0.0;
+        calls[i] = 0;
+    }
+    if (!p->pending) return PA_OK;
+    DeviceGuard guard(p->device);
+    pa_status st = PA_OK;
+    for (auto &e : *p->pending) {
+        float t = 0.f;
+        if (!e.b || hipEventSynchronize(e.b) != hipSuccess || hipEventElapsedTime(&t, e.a, e.b) != hipSuccess) {
+            (void)hipGetLastError();
+            st = PA_ERR_DEVICE;
+        } else {
+            ms[e.phase] += t;
+            calls[e.phase] += 1;
+        }
+        p->event_pool->push_back(e.a);
+        if (e.b) p->event_pool->push_back(e.b);
+    }
+    p->pending->clear();
+    return st;
+}
+
+static pa_status enqueue(pa_plan *p, const uint64_t *key, const uint64_t *a, const uint64_t *b,
+                         const uint64_t *c, uint64_t *out, uint32_t *d_status, uint64_t *y_out,
+                         uint64_t *U_out, hipStream_t st) {
+    if (!p || !key || !a || !b || !c || !out) return PA_ERR_ARG;
+    hipError_t e = pa::launch_prologue(p, a, b, c, st);
+    if (e == hipSuccess) e = pa::launch_mmh(p, key, a, st);
+    if (e == hipSuccess) e = pa::launch_fold(p, st);
+    if (e == hipSuccess) e = pa::launch_mh(p, b, c, st);
+    if (e == hipSuccess) e = pa::launch_finish(p, out, d_status, y_out, U_out, st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return PA_ERR_DEVICE;
+    }
+    return PA_OK;
+}
+
+static pa_status wait_status(pa_plan *p, hipStream_t st) {
+    if (hipMemcpyAsync(p->h_status, p->status_out, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipGetLastError();
+        return PA_ERR_DEVICE;
+    }
+    return pa_decode_status(*p->h_status);
+}
+
+pa_status pa_hash(pa_plan *p, const uint64_t *key, const uint64_t *a, const uint64_t *b, const uint64_t *c,
+                  uint64_t *out, hipStream_t st) {
+    if (!p) return PA_ERR_ARG;
+    DeviceGuard guard(p->device);
+    if (!guard.ok) return PA_ERR_DEVICE;
+    pa_status s = enqueue(p, key, a, b, c, out, nullptr, nullptr, nullptr, st);
+    if (s != PA_OK) return s;
+    return wait_status(p, st);
+}
+
+pa_status pa_hash_async(pa_plan *p, const uint64_t *key, const uint64_t *a, const uint64_t *b,
+                        const uint64_t *c, uint64_t *out, uint32_t *d_status, hipStream_t st) {
+    if (!p || !d_status) return PA_ERR_ARG;
+    DeviceGuard guard(p->device);
+    if (!guard.ok) return PA_ERR_DEVICE;
+    return enqueue(p, key, a, b, c, out, d_status, nullptr, nullptr, st);
+}
+
+pa_status pa_hash_stages(pa_plan *p, const uint64_t *key, const uint64_t *a, const uint64_t *b,
+                         const uint64_t *c, uint64_t *out, uint64_t *y_out, uint64_t *U_out,
+                         hipStream_t st) {
+    if (!p || !y_out || !U_out) return PA_ERR_ARG;
+    DeviceGuard guard(p->device);
+    if (!guard.ok) return PA_ERR_DEVICE;
+    pa_status s = enqueue(p, key, a, b, c, out, nullptr, y_out, U_out, st);
+    if (s != PA_OK) return s;
+    return wait_status(p, st);
+}
+
+}  // extern "C"
+
+namespace pa {
+
+void phase_mark(pa_plan *p, int phase, bool begin, hipStream_t st) {
+    if (!p->profiling) return;
+    hipEvent_t ev;
+    if (!p->event_pool->empty()) {
+        ev = p->event_pool->back();
+        p->event_pool->pop_back();
+    } else if (hipEventCreate(&ev) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    if (hipEventRecord(ev, st) != hipSuccess) {
+        (void)hipGetLastError();
+        p->event_pool->push_back(ev);
+        return;
+    }
+    if (begin) {
+        p->pending->push_back(pa_plan::EvPair{phase, ev, nullptr});
+    } else if (!p->pending->empty() && p->pending->back().phase == phase && !p->pending->back().b) {
+        p->pending->back().b = ev;
+    } else {
+        p->event_pool->push_back(ev);
+    }
+}
+
+}  // namespace pa

@@ -1,0 +1,79 @@
+"""CPU checks of the C interface: the library loads, exports every function
+include/pa.h declares, and its host-side plan rule (its own copy of the
+Mersenne table and the parameter rule of Sec. 4 / Table 3) agrees with the
+oracle's.  No compute call is made here."""
+import ctypes
+import math
+import random
+
+import pytest
+
+import oracle
+from oracle import defn
+from paper_2105_13678_amd import binding
+
+
+def test_library_exports_every_header_function():
+    names = binding.header_functions()
+    assert {"pa_plan_create", "pa_hash", "pa_hash_async", "pa_plan_query", "pa_status_string"} <= set(names)
+    lib = binding.lib()
+    for name in names:
+        assert hasattr(lib, name), name
+        assert ctypes.cast(getattr(lib, name), ctypes.c_void_p).value
+
+
+def test_status_strings():
+    for code, name in [(0, "PA_OK"), (2, "PA_RELOAD"), (-2, "PA_ERR_NO_GAMMA"), (-4, "PA_ERR_INEXACT"),
+                       (-5, "PA_ERR_SEED_B_EVEN"), (-6, "PA_ERR_SEED_RANGE"), (-10, "PA_ERR_LIMIT")]:
+        assert binding.status_string(code) == name
+    assert binding.decode_status(0) == 0
+    assert binding.decode_status(4) == binding.PA_RELOAD
+    assert binding.decode_status(2 | 4) == binding.PA_ERR_SEED_B_EVEN
+    assert binding.decode_status(1 | 2 | 4) == binding.PA_ERR_SEED_RANGE
+
+
+def test_plan_rule_matches_oracle():
+    rng = random.Random(3)
+    for _ in range(3000):
+        r = int(2 ** rng.uniform(0, 27.5))
+        n = r + 1 + int(2 ** rng.uniform(0, 33))
+        st_o, g_o, k_o = oracle.plan(n, r, 0)
+        st, info = binding.plan_query(n, r)
+        if st_o != 0:
+            assert st == st_o
+            continue
+        if st == binding.PA_ERR_LIMIT:
+            assert k_o > 4096 or (2 * math.ceil(g_o / 16) - 1) > (1 << 26)
+            continue
+        assert st == 0, (n, r, st)
+        assert (info["gamma"], info["k"]) == (g_o, k_o)
+
+
+@pytest.mark.parametrize("n,r,gamma,k,L,N", [
+    (1 << 20, (1 << 20) // 10, 110503, 10, 6907, 1 << 14),
+    (260_000_000, 26_000_000, 30402457, 9, 1900154, 1 << 22),
+    (10 * 25964951, 25237932, 25964951, 10, 1622810, 1 << 22),
+    (1 << 32, 1 << 27, 136279841, 32, 8517491, 1 << 25),
+])
+def test_derived_shapes(n, r, gamma, k, L, N):
+    st, info = binding.plan_query(n, r)
+    assert st == 0
+    assert (info["gamma"], info["k"], info["L"], info["N"], info["B"]) == (gamma, k, L, N, 16)
+    assert info["exact_log2"] < 64
+    assert info["out_words"] == (r + 63) // 64
+    assert info["seed_words"] == (gamma + 63) // 64
+
+
+def test_plan_errors():
+    assert binding.plan_query(1 << 32, (1 << 32) // 10)[0] == binding.PA_ERR_NO_GAMMA
+    assert binding.plan_query(100, 100)[0] == binding.PA_ERR_ARG
+    assert binding.plan_query(100, 0)[0] == binding.PA_ERR_ARG
+    assert binding.plan_query(100, 10, gamma=11)[0] == binding.PA_ERR_GAMMA
+    assert binding.plan_query(100, 13, gamma=13)[0] == binding.PA_ERR_GAMMA
+    assert binding.plan_query(1000, 10, B=7)[0] == binding.PA_ERR_ARG
+    assert binding.plan_query(1000, 10, B=21)[0] == binding.PA_ERR_ARG
+    # exactness bound k * L * (2^B - 1)^2 < 2^64 - 2^32 + 1
+    st, info = binding.plan_query(260_000_000, 26_000_000, B=20)
+    assert st == 0 and info["exact_log2"] < 64
+    assert binding.plan_query(2_600_000_000, 26_000_000, B=20)[0] == binding.PA_ERR_INEXACT
+    assert binding.plan_query(1 << 32, 200)[0] == binding.PA_ERR_LIMIT   # k > 4096

@@ -1,0 +1,262 @@
+"""GPU parity: the HIP path (through the C interface) against the CPU oracle,
+bit for bit, on seeded synthetic inputs.
+
+Every case prints its name, seed and shape before it touches the GPU.
+"""
+import hashlib
+import json
+import math
+import os
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import defn
+from paper_2105_13678_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def pa():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_2105_13678_amd as pa
+    pa.lib()
+    return pa
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def put(pa, words):
+    return pa.to_device(np.asarray(words, dtype=np.uint64))
+
+
+def run_gpu(pa, plan, blk, stages=False):
+    key, a, b, c = (put(pa, x) for x in (blk.key, blk.a, blk.b, blk.c))
+    if stages:
+        st, out, y, U = plan.hash_stages(key, a, b, c)
+        return st, pa.from_device(out), pa.from_device(y), pa.from_device(U)
+    st, out = plan.hash(key, a, b, c)
+    return st, pa.from_device(out)
+
+
+def check_block(pa, blk, B=0, stages=True, label=""):
+    say(f"[case] {label} n={blk.n} r={blk.r} gamma={blk.gamma} k={blk.k} B={B}")
+    plan = pa.Plan(blk.n, blk.r, gamma=blk.gamma, B=B)
+    try:
+        st_g, out_g, y_g, U_g = run_gpu(pa, plan, blk, stages=True)
+    finally:
+        plan.close()
+    st_o, out_o, y_o, U_o = oracle.hash(blk.key, blk.n, blk.r, blk.gamma, blk.a, blk.b, blk.c, stages=True)
+    assert st_g == st_o, (label, st_g, st_o)
+    if st_o == 0:
+        assert np.array_equal(out_g, out_o), label
+        if stages:
+            assert np.array_equal(y_g, y_o), label + " (y)"
+            assert np.array_equal(U_g, U_o), label + " (U)"
+    return st_g, out_g
+
+
+def test_small_random_shapes(pa):
+    rng = random.Random(2024)
+    gammas = [e for e in defn.MERSENNE_EXPONENTS if 2 <= e <= 23209]
+    for t in range(120):
+        g = rng.choice(gammas)
+        r = rng.randrange(1, g) if g > 2 else 1
+        n = rng.randrange(r + 1, rng.choice([2, 5, 12]) * g + 2)
+        st, g2, k = defn.plan_shape(n, r, g)
+        blk = synth.single_block(1000 + t, n, r, g, k)
+        check_block(pa, blk, label=f"random#{t}")
+
+
+@pytest.mark.parametrize("gamma", [89, 127, 521, 4423, 110503])
+def test_edge_shapes(pa, gamma):
+    cases = [
+        ("r=1", 3 * gamma, 1),
+        ("r=gamma-1", 3 * gamma, gamma - 1),
+        ("n=k*gamma", 7 * gamma, gamma // 3),
+        ("n=k*gamma-1", 7 * gamma - 1, gamma // 3),
+        ("n=gamma+1", gamma + 1, gamma // 2),
+        ("k=1", gamma - 1, gamma // 2),
+        ("n=k*gamma+1", 4 * gamma + 1, gamma // 5 + 1),
+    ]
+    for i, (label, n, r) in enumerate(cases):
+        st, g, k = defn.plan_shape(n, r, gamma)
+        assert st == 0
+        blk = synth.single_block(7 * gamma + i, n, r, g, k)
+        check_block(pa, blk, label=f"edge {label}")
+
+
+@pytest.mark.parametrize("B", [8, 11, 12, 16, 19, 20])
+def test_limb_width_invariance(pa, B):
+    """The output is the same integer for every exact limb width (B is
+    representation only, the 2^B-ary words of Sec. 2.1)."""
+    n, r = 1 << 20, (1 << 20) // 10
+    st, g, k = defn.plan_shape(n, r)
+    blk = synth.single_block(31, n, r, g, k)
+    check_block(pa, blk, B=B, label=f"B={B}")
+
+
+def test_config_one_mib_block(pa):
+    n, r = 1 << 20, (1 << 20) // 10
+    st, g, k = defn.plan_shape(n, r)
+    blk = synth.single_block(1, n, r, g, k)
+    check_block(pa, blk, label="2^20 block seed 1")
+
+
+def _chunks_key(chunks, gamma, n):
+    K = 0
+    for i, x in enumerate(chunks):
+        K |= x << (i * gamma)
+    K &= (1 << n) - 1
+    return defn.int_to_words(K, (n + 63) // 64)
+
+
+def _blk(chunks, a, b, c, gamma, n, r):
+    W = (gamma + 63) // 64
+    return synth.Block(n=n, r=r, gamma=gamma, k=len(a), key=_chunks_key(chunks, gamma, n),
+                       a=np.concatenate([defn.int_to_words(v, W) for v in a]),
+                       b=defn.int_to_words(b, W), c=defn.int_to_words(c, W))
+
+
+@pytest.mark.parametrize("gamma", [61, 89, 521, 4423, 44497, 110503])
+def test_fold_canonical_cases(pa, gamma):
+    """S = p must fold to y = 0; S = p + 1 to 1; one-hot seeds rotate a chunk
+    (2^gamma = 1 mod p); a_i = p - 1 complements."""
+    p = (1 << gamma) - 1
+    rng = random.Random(gamma)
+    c = rng.randrange(1 << gamma)
+    r = max(1, gamma // 3)
+    for label, chunks, a in [("S=p", [p - 1, 1], [1, 1]), ("S=p+1", [p - 1, 2], [1, 1]),
+                             ("S=2p", [p - 1, 1], [2, 2]), ("S=0", [0, 0], [5, 7])]:
+        blk = _blk(chunks, a, 1, c, gamma, 2 * gamma, r)
+        check_block(pa, blk, label=f"fold {label}")
+    x = rng.randrange(p)
+    s = rng.randrange(gamma)
+    blk = _blk([0, x, 0], [0, 1 << s, 0], 1, 0, gamma, 3 * gamma, r)
+    check_block(pa, blk, label="rotate")
+    blk = _blk([0, x, 0], [3, p - 1, 9], 1, 0, gamma, 3 * gamma, r)
+    check_block(pa, blk, label="complement")
+    # all-ones limbs everywhere except one bit: long carry chains in every scan
+    blk = _blk([p - 1, p - 2, p ^ 1], [p - 1, p - 1, p - 1], (1 << gamma) - 1, (1 << gamma) - 1,
+               gamma, 3 * gamma, r)
+    check_block(pa, blk, label="long carries")
+
+
+def test_status_codes_and_untouched_output(pa):
+    import torch
+    gamma = 4423
+    p = (1 << gamma) - 1
+    n, r = 3 * gamma, 100
+    plan = pa.Plan(n, r, gamma=gamma)
+    W = (gamma + 63) // 64
+    try:
+        cases = [
+            ("reload", [5, p, 7], [1, 2, 3], 3, 4, pa.PA_RELOAD),
+            ("b even", [5, 6, 7], [1, 2, 3], 4, 4, -5),
+            ("seed range a", [5, 6, 7], [1, 1 << gamma, 3], 3, 4, -6),
+            ("seed range c", [5, 6, 7], [1, 2, 3], 3, 1 << gamma, -6),
+            ("range beats reload", [5, p, 7], [1 << gamma, 2, 3], 4, 4, -6),
+        ]
+        for label, chunks, a, b, c, want in cases:
+            say(f"[case] status {label}")
+            key = put(pa, _chunks_key(chunks, gamma, n))
+            aw = np.concatenate([defn.int_to_words(v % (1 << (64 * W)), W) for v in a])
+            bw = defn.int_to_words(b % (1 << (64 * W)), W)
+            cw = defn.int_to_words(c % (1 << (64 * W)), W)
+            # bits >= 64*W cannot be represented; 1 << gamma stays inside W words here
+            out = torch.full((plan.out_words,), 0x5A5A, dtype=torch.int64, device=plan.device)
+            st, _ = plan.hash(key, put(pa, aw), put(pa, bw), put(pa, cw), out=out)
+            st_o, _ = oracle.hash(_chunks_key(chunks, gamma, n), n, r, gamma, aw, bw, cw)
+            assert st == want == st_o, (label, st, want, st_o)
+            assert bool((out == 0x5A5A).all()), label + ": output touched"
+    finally:
+        plan.close()
+
+
+def test_repeat_runs_identical_and_plan_reuse(pa):
+    n, r = 3_000_000, 400_000
+    st, g, k = defn.plan_shape(n, r)
+    plan = pa.Plan(n, r)
+    try:
+        outs = []
+        for seed in (41, 42, 41):
+            blk = synth.single_block(seed, n, r, g, k)
+            say(f"[case] reuse seed={seed} n={n} r={r}")
+            stg, out = run_gpu(pa, plan, blk)
+            st_o, out_o = oracle.hash(blk.key, n, r, g, blk.a, blk.b, blk.c)
+            assert stg == st_o == 0 and np.array_equal(out, out_o)
+            outs.append(out)
+        assert np.array_equal(outs[0], outs[2])
+    finally:
+        plan.close()
+
+
+def test_mmh_stage_linear_in_key(pa):
+    """Invariant checked without the oracle: with the seeds fixed, the MMH
+    value is Z_p-linear in the chunk vector (eq. 2): y(x + x') = y(x) + y(x')
+    mod p, where + adds chunks mod p."""
+    gamma = 110503
+    p = (1 << gamma) - 1
+    k = 5
+    n = k * gamma
+    rng = random.Random(9)
+    a = [rng.randrange(p) for _ in range(k)]
+    b = rng.randrange(1 << gamma) | 1
+    c = rng.randrange(1 << gamma)
+    x1 = [rng.randrange(p) for _ in range(k)]
+    x2 = [rng.randrange(p) for _ in range(k)]
+    xs = [(u + v) % p for u, v in zip(x1, x2)]
+    plan = pa.Plan(n, 1000, gamma=gamma)
+    ys = []
+    Us = []
+    try:
+        for label, x in (("x1", x1), ("x2", x2), ("x1+x2", xs)):
+            say(f"[case] linearity {label}")
+            blk = _blk(x, a, b, c, gamma, n, 1000)
+            st, out, y, U = run_gpu(pa, plan, blk, stages=True)
+            assert st == 0
+            ys.append(defn.words_to_int(y))
+            Us.append(defn.words_to_int(U))
+    finally:
+        plan.close()
+    assert ys[2] == (ys[0] + ys[1]) % p
+    # U is affine in y: U(y) = b*y + c mod 2^gamma
+    for y, U in zip(ys, Us):
+        assert U == (b * y + c) % (1 << gamma)
+
+
+def _digest(words):
+    return hashlib.sha256(np.ascontiguousarray(words, dtype=np.uint64).tobytes()).hexdigest()
+
+
+@pytest.mark.parametrize("name", ["single_block_2p6e8", "paper_cv_block"])
+def test_full_size_blocks_against_stored_oracle_digest(pa, name):
+    """Full-size blocks, in the launch configuration the benchmark times,
+    against digests written by tests/golden/make_golden.py (oracle only)."""
+    gold = json.load(open(os.path.join(HERE, "golden", "full_size.json")))[name]
+    n, r = gold["n"], gold["r"]
+    st, g, k = defn.plan_shape(n, r)
+    assert (g, k) == (gold["gamma"], gold["k"])
+    blk = synth.single_block(gold["seed"], n, r, g, k)
+    say(f"[case] full size {name} n={n} r={r} gamma={g} k={k}")
+    plan = pa.Plan(n, r)
+    try:
+        st_g, out, y, U = run_gpu(pa, plan, blk, stages=True)
+    finally:
+        plan.close()
+    assert st_g == gold["status"] == 0
+    assert [int(v) for v in out[:4]] == gold["out_head"]
+    assert _digest(y) == gold["y_sha256"]
+    assert _digest(U) == gold["U_sha256"]
+    assert _digest(out) == gold["out_sha256"]
