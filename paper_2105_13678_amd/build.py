@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libpa.so")
 ARCH = "gfx950"
 
 SOURCES = ["pa_api.cpp", "pa_kernels.hip"]
-HEADERS = ["pa_internal.hpp"]
+HEADERS = ["pa_internal.hpp", "ntt_device.hpp"]
 
 
 def hipcc() -> str:

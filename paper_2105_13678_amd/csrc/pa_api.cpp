@@ -132,8 +132,13 @@ pa_status derive(const pa_params *prm, pa_plan *p, Layout *lay) {
     p->key_words = (prm->n + 63) / 64;
     p->out_words = (prm->r + 63) / 64;
     p->m = m;
-    p->m2 = (m + 3) / 2 < kMaxLdsLog2 ? (m + 3) / 2 : kMaxLdsLog2;
-    p->m1 = m - p->m2;
+    // row length 2^m2 (one LDS row of at most 2^13 words), column length
+    // 2^m1 >= 8 (the column pass starts with a radix-8 step)
+    uint32_t m2 = (m + 3) / 2;
+    if (m2 > kMaxLdsLog2) m2 = kMaxLdsLog2;
+    if (m2 > m - 3) m2 = m - 3;
+    p->m2 = m2;
+    p->m1 = m - m2;
     uint32_t c_lg = 4;
     if (c_lg > p->m2) c_lg = p->m2;
     if (p->m1 + c_lg > kMaxLdsLog2) c_lg = kMaxLdsLog2 - p->m1;
@@ -165,8 +170,8 @@ pa_status derive(const pa_params *prm, pa_plan *p, Layout *lay) {
     lay->oNo = carve(k * 4);
     lay->oSt = carve(4 * 4);
     lay->oSo = carve(4 * 4);
-    lay->oT1 = carve((N >> p->m2) / 2 * 8 * 2);
-    lay->oT2 = carve(((size_t)1 << p->m2) / 2 * 8 * 2);
+    lay->oT1 = carve((N >> p->m2) * 8 * 2);
+    lay->oT2 = carve(((size_t)1 << p->m2) * 8 * 2);
     lay->oW = carve(N * 8 * 2);
     lay->total = off;
     p->workspace_bytes = off;
@@ -232,7 +237,7 @@ pa_status pa_plan_create(const pa_params *prm, int hip_device, pa_plan **out) {
     p->notones = (uint32_t *)(b + oNo);
     p->status = (uint32_t *)(b + oSt);
     p->status_out = (uint32_t *)(b + oSo);
-    const size_t h1 = (N >> p->m2) / 2, h2 = ((size_t)1 << p->m2) / 2;
+    const size_t h1 = N >> p->m2, h2 = (size_t)1 << p->m2;
     p->tw1f = (uint64_t *)(b + oT1);
     p->tw1i = p->tw1f + h1;
     p->tw2f = (uint64_t *)(b + oT2);

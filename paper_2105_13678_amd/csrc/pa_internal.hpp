@@ -132,8 +132,8 @@ struct pa_plan {
     uint32_t *notones;  // k flags: chunk i has a limb that is not all ones
     uint32_t *status;   // seed/reload flags
     uint32_t *status_out;  // final flags of the last call (pa_hash reads it back)
-    uint64_t *tw1f, *tw1i;  // omega_{N1}^j, omega_{N1}^-j, j < N1/2
-    uint64_t *tw2f, *tw2i;  // omega_{N2}^j, omega_{N2}^-j, j < N2/2
+    uint64_t *tw1f, *tw1i;  // omega_{N1}^j, omega_{N1}^-j, j < N1
+    uint64_t *tw2f, *tw2i;  // omega_{N2}^j, omega_{N2}^-j, j < N2
     uint64_t *Wf, *Wi;      // four-step twiddles, row-major in stored (bit-reversed) row order
     uint32_t *h_status;     // pinned host word
 

@@ -23,6 +23,7 @@
 // Carry propagation uses carry transfer functions f(c) = g + [c >= th]
 // (exact for carries below 2^B), composed with wavefront shuffles inside a
 // workgroup and a reduce / tile-prefix / apply sequence across workgroups.
+#include "ntt_device.hpp"
 #include "pa_internal.hpp"
 
 using namespace pa;
@@ -77,53 +78,6 @@ __device__ __forceinline__ uint64_t limbs_get64(const uint32_t *__restrict__ lim
         got += take;
     }
     return v;
-}
-
-// ------------------------------------------------------------------ LDS NTTs
-// 2^cnt_lg interleaved transforms of length 2^lg: element (q, idx) lives at
-// buf[(idx << cnt_lg) + q].  tw[j] = omega_{2^lg}^{j} (forward) or
-// omega^{-j} (inverse), j < 2^(lg-1).  Callers synchronise before the call;
-// each stage ends with a barrier.
-
-// Decimation in frequency: natural order in, bit-reversed order out.
-__device__ void lds_dif(uint64_t *buf, uint32_t lg, uint32_t cnt_lg, const uint64_t *__restrict__ tw,
-                        uint32_t tid, uint32_t nt) {
-    uint32_t total = (1u << (lg - 1)) << cnt_lg;
-    uint32_t qmask = (1u << cnt_lg) - 1;
-    for (int s = (int)lg - 1; s >= 0; --s) {
-        for (uint32_t bfly = tid; bfly < total; bfly += nt) {
-            uint32_t q = bfly & qmask;
-            uint32_t bb = bfly >> cnt_lg;
-            uint32_t j = bb & ((1u << s) - 1);
-            uint32_t i0 = ((bb >> s) << (s + 1)) + j;
-            uint32_t i1 = i0 + (1u << s);
-            uint64_t u = buf[(i0 << cnt_lg) + q], v = buf[(i1 << cnt_lg) + q];
-            buf[(i0 << cnt_lg) + q] = gl_add(u, v);
-            buf[(i1 << cnt_lg) + q] = gl_mul(gl_sub(u, v), tw[j << (lg - 1 - s)]);
-        }
-        __syncthreads();
-    }
-}
-
-// Decimation in time: bit-reversed order in, natural order out.
-__device__ void lds_dit(uint64_t *buf, uint32_t lg, uint32_t cnt_lg, const uint64_t *__restrict__ tw,
-                        uint32_t tid, uint32_t nt) {
-    uint32_t total = (1u << (lg - 1)) << cnt_lg;
-    uint32_t qmask = (1u << cnt_lg) - 1;
-    for (uint32_t s = 0; s < lg; ++s) {
-        for (uint32_t bfly = tid; bfly < total; bfly += nt) {
-            uint32_t q = bfly & qmask;
-            uint32_t bb = bfly >> cnt_lg;
-            uint32_t j = bb & ((1u << s) - 1);
-            uint32_t i0 = ((bb >> s) << (s + 1)) + j;
-            uint32_t i1 = i0 + (1u << s);
-            uint64_t u = buf[(i0 << cnt_lg) + q];
-            uint64_t v = gl_mul(buf[(i1 << cnt_lg) + q], tw[j << (lg - 1 - s)]);
-            buf[(i0 << cnt_lg) + q] = gl_add(u, v);
-            buf[(i1 << cnt_lg) + q] = gl_sub(u, v);
-        }
-        __syncthreads();
-    }
 }
 
 // ------------------------------------------------------------------ twiddles
@@ -185,41 +139,59 @@ struct ColFwdArgs {
     const uint64_t *key, *a, *b;
     const uint32_t *ylimbs;
     uint32_t *notones;
-    const uint64_t *tw;
+    const uint64_t *tw;  // omega_{N1}^e, e < N1
 };
 
 // Unpack + forward column pass.  blockIdx.y selects the array: in MMH mode
 // arrays 0..k-1 are the key chunks x_i and k..2k-1 the seed chunks a_i; in
 // MH mode array 0 is y and array 1 is b.  Limb j of a chunk is its bits
-// [jB, jB+B); limbs j >= L are the zero padding.
+// [jB, jB+B); limbs j >= L are the zero padding.  Because N >= 2L - 1, every
+// limb index >= N/2 is padding, so rows n1 >= N1/2 of the column tile are
+// zero and the first radix-8 step only unpacks its lower four inputs.
 __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
     uint64_t *lds = lds_dyn;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t arr = blockIdx.y;
-    const uint32_t cmask = (1u << A.c_lg) - 1;
-    const uint32_t cnt = (1u << A.m1) << A.c_lg;
-    const uint64_t c0 = (uint64_t)tile << A.c_lg;
+    const uint32_t c_lg = A.c_lg, lg = A.m1;
+    const uint32_t cmask = (1u << c_lg) - 1;
+    const uint64_t c0 = (uint64_t)tile << c_lg;
     const bool is_key = (A.mode == 0) && arr < A.k;
     const uint32_t full = (1u << A.B) - 1, topv = (1u << A.s_top) - 1;
+    const uint32_t lgMp = lg - 3;
+    const uint32_t ntask = (1u << lgMp) << c_lg;
     bool not_ones = false;
-    for (uint32_t e = threadIdx.x; e < cnt; e += blockDim.x) {
-        uint64_t j = ((uint64_t)(e >> A.c_lg) << A.m2) + c0 + (e & cmask);
-        uint32_t v = 0;
-        if (j < A.L) {
-            if (A.mode == 0) {
-                if (arr < A.k) {
-                    uint64_t base = (uint64_t)arr * A.gamma;
-                    uint64_t lim = min(A.n, base + A.gamma);
-                    v = bits_at(A.key, lim, base + j * A.B, A.B);
-                    not_ones |= (v != (j == A.L - 1 ? topv : full));
+    for (uint32_t task = threadIdx.x; task < ntask; task += blockDim.x) {
+        const uint32_t q = task & cmask;
+        const uint32_t n1 = task >> c_lg;
+        uint64_t v[8];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const uint64_t row = n1 + ((uint64_t)jj << lgMp);
+            const uint64_t j = (row << A.m2) + c0 + q;  // limb index
+            uint32_t x = 0;
+            if (j < A.L) {
+                if (A.mode == 0) {
+                    if (arr < A.k) {
+                        const uint64_t base = (uint64_t)arr * A.gamma;
+                        const uint64_t lim = min(A.n, base + A.gamma);
+                        x = bits_at(A.key, lim, base + j * A.B, A.B);
+                        not_ones |= (x != (j == A.L - 1 ? topv : full));
+                    } else {
+                        x = bits_at(A.a + (uint64_t)(arr - A.k) * A.W, A.gamma, j * A.B, A.B);
+                    }
                 } else {
-                    v = bits_at(A.a + (uint64_t)(arr - A.k) * A.W, A.gamma, j * A.B, A.B);
+                    x = (arr == 0) ? A.ylimbs[j] : bits_at(A.b, A.gamma, j * A.B, A.B);
                 }
-            } else {
-                v = (arr == 0) ? A.ylimbs[j] : bits_at(A.b, A.gamma, j * A.B, A.B);
             }
+            v[jj] = x;
         }
-        lds[e] = v;
+        dft_fwd8_lowhalf(v);
+        if (lg > 3) {
+#pragma unroll
+            for (int s = 1; s < 8; ++s) v[s] = fmul(v[s], A.tw[n1 * brev_small(s, 3)]);
+        }
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) lds[swz(((n1 + ((uint32_t)jj << lgMp)) << c_lg) + q)] = v[jj];
     }
     if (is_key) {
         int any = __syncthreads_or(not_ones);
@@ -227,10 +199,11 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
     } else {
         __syncthreads();
     }
-    lds_dif(lds, A.m1, A.c_lg, A.tw, threadIdx.x, blockDim.x);
+    fwd_steps_from(lds, lg, lg - 3, c_lg, A.tw, threadIdx.x, blockDim.x);
     uint64_t *out = A.X + (uint64_t)arr * A.N;
+    const uint32_t cnt = (1u << lg) << c_lg;
     for (uint32_t e = threadIdx.x; e < cnt; e += blockDim.x)
-        out[((uint64_t)(e >> A.c_lg) << A.m2) + c0 + (e & cmask)] = lds[e];
+        out[((uint64_t)(e >> c_lg) << A.m2) + c0 + (e & cmask)] = lds[swz(e)];
 }
 
 struct RowArgs {
@@ -238,89 +211,138 @@ struct RowArgs {
     uint64_t N, npairs, a_off;
     uint32_t m2;
     uint64_t *out;
-    const uint64_t *Wf, *Wi, *twf, *twi;
+    const uint64_t *Wf, *Wi, *twf, *twi;  // four-step twiddles; omega_{N2}^{+-e}, e < N2
 };
 
-// Row pass: for each pair (x_i, a_i): twiddle, forward DIF of both rows,
-// accumulate their pointwise product; then inverse DIT of the accumulated
-// row, inverse twiddle (with 1/N) and store.
+// First forward step of a row straight from global memory: four-step
+// twiddle on load, radix-8 DFT, step twiddles, into LDS.
+__device__ __forceinline__ void row_first_step(const uint64_t *__restrict__ g, const uint64_t *__restrict__ w,
+                                               uint64_t *buf, uint32_t lg, const uint64_t *__restrict__ tw,
+                                               uint32_t tid, uint32_t nt) {
+    const uint32_t lgMp = lg - 3;
+    for (uint32_t n1 = tid; n1 < (1u << lgMp); n1 += nt) {
+        uint64_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t e = n1 + ((uint32_t)j << lgMp);
+            v[j] = fmul(g[e], w[e]);
+        }
+        dft_fwd<8>(v);
+        if (lg > 3) {
+#pragma unroll
+            for (int s = 1; s < 8; ++s) v[s] = fmul(v[s], tw[n1 * brev_small(s, 3)]);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) buf[swz(n1 + ((uint32_t)j << lgMp))] = v[j];
+    }
+    __syncthreads();
+}
+
+// Last inverse step of a row straight to global memory (with the inverse
+// four-step twiddle and 1/N).
+__device__ __forceinline__ void row_last_inv_step(const uint64_t *buf, uint64_t *__restrict__ g,
+                                                  const uint64_t *__restrict__ w, uint32_t lg,
+                                                  const uint64_t *__restrict__ twi, uint32_t tid, uint32_t nt) {
+    const uint32_t lgMp = lg - 3;
+    for (uint32_t n1 = tid; n1 < (1u << lgMp); n1 += nt) {
+        uint64_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = buf[swz(n1 + ((uint32_t)j << lgMp))];
+        if (lg > 3) {
+#pragma unroll
+            for (int s = 1; s < 8; ++s) v[s] = fmul(v[s], twi[n1 * brev_small(s, 3)]);
+        }
+        dft_inv<8>(v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t e = n1 + ((uint32_t)j << lgMp);
+            g[e] = fmul(v[j], w[e]);
+        }
+    }
+}
+
+// Row pass: for each pair (x_i, a_i): four-step twiddle and forward transform
+// of both rows, accumulate their pointwise product; then the inverse
+// transform of the accumulated row, inverse twiddle (with 1/N), store.
 __global__ __launch_bounds__(512) void k_row(RowArgs A) {
     uint64_t *lds = lds_dyn;
-    const uint32_t N2 = 1u << A.m2;
+    const uint32_t lg = A.m2;
+    const uint32_t N2 = 1u << lg;
     const uint32_t T = blockDim.x;
     const uint32_t rho = xcd_tile(blockIdx.x, gridDim.x);
-    const uint64_t rbase = (uint64_t)rho << A.m2;
-    uint64_t wf[ROW_EPT], acc[ROW_EPT], xr[ROW_EPT];
+    const uint64_t rbase = (uint64_t)rho << lg;
+    const uint64_t *wf = A.Wf + rbase;
+    uint64_t acc[ROW_EPT], xr[ROW_EPT];
 #pragma unroll
     for (int q = 0; q < ROW_EPT; ++q) {
-        uint32_t e = threadIdx.x + q * T;
-        wf[q] = (e < N2) ? A.Wf[rbase + e] : 0ull;
         acc[q] = 0ull;
         xr[q] = 0ull;
     }
     for (uint64_t i = 0; i < A.npairs; ++i) {
         const uint64_t *xrow = A.X + i * A.N + rbase;
         const uint64_t *arow = xrow + A.a_off;
+        row_first_step(xrow, wf, lds, lg, A.twf, threadIdx.x, T);
+        fwd_steps_from(lds, lg, lg - 3, 0, A.twf, threadIdx.x, T);
 #pragma unroll
         for (int q = 0; q < ROW_EPT; ++q) {
             uint32_t e = threadIdx.x + q * T;
-            if (e < N2) lds[e] = gl_mul(xrow[e], wf[q]);
+            if (e < N2) xr[q] = lds[swz(e)];
         }
         __syncthreads();
-        lds_dif(lds, A.m2, 0, A.twf, threadIdx.x, T);
+        row_first_step(arow, wf, lds, lg, A.twf, threadIdx.x, T);
+        fwd_steps_from(lds, lg, lg - 3, 0, A.twf, threadIdx.x, T);
 #pragma unroll
         for (int q = 0; q < ROW_EPT; ++q) {
             uint32_t e = threadIdx.x + q * T;
-            if (e < N2) xr[q] = lds[e];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < ROW_EPT; ++q) {
-            uint32_t e = threadIdx.x + q * T;
-            if (e < N2) lds[e] = gl_mul(arow[e], wf[q]);
-        }
-        __syncthreads();
-        lds_dif(lds, A.m2, 0, A.twf, threadIdx.x, T);
-#pragma unroll
-        for (int q = 0; q < ROW_EPT; ++q) {
-            uint32_t e = threadIdx.x + q * T;
-            if (e < N2) acc[q] = gl_add(acc[q], gl_mul(xr[q], lds[e]));
+            if (e < N2) acc[q] = fadd(acc[q], fmul(xr[q], lds[swz(e)]));
         }
         __syncthreads();
     }
 #pragma unroll
     for (int q = 0; q < ROW_EPT; ++q) {
         uint32_t e = threadIdx.x + q * T;
-        if (e < N2) lds[e] = acc[q];
+        if (e < N2) lds[swz(e)] = acc[q];
     }
     __syncthreads();
-    lds_dit(lds, A.m2, 0, A.twi, threadIdx.x, T);
-#pragma unroll
-    for (int q = 0; q < ROW_EPT; ++q) {
-        uint32_t e = threadIdx.x + q * T;
-        if (e < N2) A.out[rbase + e] = gl_mul(lds[e], A.Wi[rbase + e]);
-    }
+    inv_steps_to(lds, lg, lg - 3, 0, A.twi, threadIdx.x, T);
+    row_last_inv_step(lds, A.out + rbase, A.Wi + rbase, lg, A.twi, threadIdx.x, T);
 }
 
 struct ColInvArgs {
     uint64_t *Cc;
     uint32_t m1, m2, c_lg;
-    const uint64_t *twi;
+    const uint64_t *twi;  // omega_{N1}^-e, e < N1
 };
 
-// Inverse column pass (DIT over bit-reversed rows), in place.
+// Inverse column pass (bit-reversed rows in, natural rows out), in place.
 __global__ __launch_bounds__(COL_THREADS) void k_col_inv(ColInvArgs A) {
     uint64_t *lds = lds_dyn;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t cmask = (1u << A.c_lg) - 1;
-    const uint32_t cnt = (1u << A.m1) << A.c_lg;
-    const uint64_t c0 = (uint64_t)tile << A.c_lg;
+    const uint32_t c_lg = A.c_lg, lg = A.m1;
+    const uint32_t cmask = (1u << c_lg) - 1;
+    const uint32_t cnt = (1u << lg) << c_lg;
+    const uint64_t c0 = (uint64_t)tile << c_lg;
     for (uint32_t e = threadIdx.x; e < cnt; e += blockDim.x)
-        lds[e] = A.Cc[((uint64_t)(e >> A.c_lg) << A.m2) + c0 + (e & cmask)];
+        lds[swz(e)] = A.Cc[((uint64_t)(e >> c_lg) << A.m2) + c0 + (e & cmask)];
     __syncthreads();
-    lds_dit(lds, A.m1, A.c_lg, A.twi, threadIdx.x, blockDim.x);
-    for (uint32_t e = threadIdx.x; e < cnt; e += blockDim.x)
-        A.Cc[((uint64_t)(e >> A.c_lg) << A.m2) + c0 + (e & cmask)] = lds[e];
+    inv_steps_to(lds, lg, lg - 3, c_lg, A.twi, threadIdx.x, blockDim.x);
+    const uint32_t lgMp = lg - 3;
+    const uint32_t ntask = (1u << lgMp) << c_lg;
+    for (uint32_t task = threadIdx.x; task < ntask; task += blockDim.x) {
+        const uint32_t q = task & cmask;
+        const uint32_t n1 = task >> c_lg;
+        uint64_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = lds[swz(((n1 + ((uint32_t)j << lgMp)) << c_lg) + q)];
+        if (lg > 3) {
+#pragma unroll
+            for (int s = 1; s < 8; ++s) v[s] = fmul(v[s], A.twi[n1 * brev_small(s, 3)]);
+        }
+        dft_inv<8>(v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            A.Cc[((uint64_t)(n1 + ((uint32_t)j << lgMp)) << A.m2) + c0 + q] = v[j];
+    }
 }
 
 // ------------------------------------------------------------------ carry scan
@@ -575,25 +597,42 @@ hipError_t run_scan(pa_plan *p, const uint32_t *t, uint32_t *out, uint64_t M, bo
 unsigned row_threads(const pa_plan *p) {
     unsigned n2 = 1u << p->m2;
     unsigned t = n2 / ROW_EPT;
-    return t < 64 ? 64 : t;
+    return t < 64 ? 64 : t;  // ROW_EPT elements per thread; N2 <= 8192 -> at most 512 threads
 }
 
 }  // namespace
 
 namespace pa {
 
+// Primitive 2^32-th root of unity r with r^(2^26) = 8, so that omega_64 = 8
+// and the radix-8 twiddles are powers of two.  7 generates the
+// multiplicative group of the field.
+static uint64_t canonical_root_2_32() {
+    const uint64_t r = gl_pow(7, (GL_P - 1) >> 32);
+    const uint64_t w64 = gl_pow(r, 1ull << 26);
+    uint64_t u = 0;
+    for (uint64_t e = 1; e < 64; e += 2)
+        if (gl_pow(8, e) == w64) {
+            u = e;
+            break;
+        }
+    uint64_t v = 1;
+    while ((u * v) % 64 != 1) v += 2;  // u^-1 mod 64
+    return gl_pow(r, v);
+}
+
 hipError_t launch_twiddles(pa_plan *p, hipStream_t st) {
     const uint64_t N = p->N;
-    const uint64_t w = gl_pow(7, (GL_P - 1) >> p->m);   // 7 generates the multiplicative group
+    const uint64_t w = gl_pow(canonical_root_2_32(), 1ull << (32 - p->m));
     const uint64_t winv = gl_pow(w, N - 1);
     const uint64_t ninv = gl_pow(N % GL_P, GL_P - 2);
     const uint64_t w1 = gl_pow(w, 1ull << p->m2), w1i = gl_pow(winv, 1ull << p->m2);
     const uint64_t w2 = gl_pow(w, 1ull << p->m1), w2i = gl_pow(winv, 1ull << p->m1);
-    const uint64_t h1 = 1ull << (p->m1 - 1), h2 = 1ull << (p->m2 - 1);
-    hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(h1, 256)), dim3(256), 0, st, p->tw1f, h1, w1);
-    hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(h1, 256)), dim3(256), 0, st, p->tw1i, h1, w1i);
-    hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(h2, 256)), dim3(256), 0, st, p->tw2f, h2, w2);
-    hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(h2, 256)), dim3(256), 0, st, p->tw2i, h2, w2i);
+    const uint64_t n1 = 1ull << p->m1, n2 = 1ull << p->m2;
+    hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(n1, 256)), dim3(256), 0, st, p->tw1f, n1, w1);
+    hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(n1, 256)), dim3(256), 0, st, p->tw1i, n1, w1i);
+    hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(n2, 256)), dim3(256), 0, st, p->tw2f, n2, w2);
+    hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(n2, 256)), dim3(256), 0, st, p->tw2i, n2, w2i);
     hipLaunchKernelGGL(k_tw_four, dim3(blocks_for(N, 256)), dim3(256), 0, st, p->Wf, p->Wi, p->m1, p->m2,
                        w, winv, ninv);
     return hipGetLastError();
