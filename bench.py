@@ -47,20 +47,27 @@ def log(*a):
 
 
 def ntt_work(info):
-    """Algorithmic work of the NTT kernels in radix-2 butterflies, per launch."""
-    N, m = info["N"], info["log2N"]
-    k = info["k"]
-    m2 = (m + 3) // 2 if (m + 3) // 2 < 13 else 13
-    m1 = m - m2
+    """Algorithmic work of the NTT kernels per launch: radix-2 butterflies of
+    the transforms each launch performs (N/2 * log2 of its pass length per
+    transform per prime)."""
+    N, m1, m2, k, P = info["N"], info["log2N1"], info["log2N2"], info["k"], info["nprimes"]
     half = N // 2
     return {
-        "mmh_col": 2 * k * half * m1,
-        "mmh_row": (2 * k + 1) * half * m2,
-        "mmh_colinv": half * m1,
-        "mh_col": 2 * half * m1,
-        "mh_row": 3 * half * m2,
-        "mh_colinv": half * m1,
+        "mmh_col": P * 2 * k * half * m1,
+        "mmh_row": P * (2 * k + 1) * half * m2,
+        "mmh_colinv": P * half * m1,
+        "mh_col": P * 2 * half * m1,
+        "mh_row": P * 3 * half * m2,
+        "mh_colinv": P * half * m1,
     }
+
+
+# Peak butterfly rate of the VALU for this arithmetic: a radix-2 butterfly
+# modulo a 31-bit prime is one modular addition (3 VALU instructions), one
+# subtraction (3) and one Montgomery product (5: v_mad_u64_u32, v_mul_lo_u32,
+# v_mad_u64_u32, v_sub_u32, v_min_u32), all full-rate on gfx950.
+BFLY_LANE_CYCLES = 11
+PEAK_BFLY_PER_S = CUS * LANES_PER_CU * CLOCK_GHZ * 1e9 / BFLY_LANE_CYCLES
 
 
 def cpu_baseline(blk, info, budget_chunks=2):
@@ -99,6 +106,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the timed region, copy a buffer of this many MiB with a plain device "
+                         "copy kernel (reference point for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -172,10 +182,10 @@ def main():
     roof = {
         "kernel": {"mmh_row": "k_row (MMH)", "mmh_col": "k_col_fwd (MMH)"}.get(dom, dom),
         "bound": "alu",
-        "achieved": round(bfly_per_s / 1e9, 2),
-        "peak": None,
+        "achieved": round(bfly_per_s / 1e9, 1),
+        "peak": round(PEAK_BFLY_PER_S / 1e9, 1),
         "unit": "Gbutterfly/s",
-        "frac": None,
+        "frac": round(bfly_per_s / PEAK_BFLY_PER_S, 3),
         "traffic": None,
         "duration_ms": round(dom_ms, 4),
         "butterflies_per_launch": work[dom],
@@ -191,15 +201,23 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64 (exact integer NTT mod 2^64-2^32+1)",
+        "dtype": "u32 (exact integer NTTs mod three 31-bit primes, CRT to 96-bit coefficients)",
         "data": "synthetic",
-        "config": {"workload": "single block n=2.6e8 r=n/10 (gamma=30402457, k=9, N=2^22), splitmix64 seed 2",
+        "config": {"workload": f"single block n=2.6e8 r=n/10 (gamma={g}, k={k}, B={info['B']}, "
+                               f"N=2^{info['log2N']}), splitmix64 seed 2",
                    "n": N_BITS, "r": R_BITS, "gamma": g, "k": k, "B": info["B"], "N": info["N"],
                    "parallelism": "single GPU"},
         "verified_vs_oracle_digest": verified,
         "phase_ms": {p: (round(v, 4) if v else None) for p, v in phases.items()},
         "roofline": roof,
     }
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib << 17, dtype=torch.int64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        rec["calib_copy_bytes"] = 2 * src.numel() * 8
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample) ...")
         rec["cpu_baseline"] = cpu_baseline(blk, info)

@@ -52,7 +52,7 @@ typedef enum pa_status {
     PA_ERR_ARG = -1,         /* bad argument (NULL pointer, r < 1, r >= n, n < 2, ...)  */
     PA_ERR_NO_GAMMA = -2,    /* no known Mersenne exponent exceeds r                    */
     PA_ERR_GAMMA = -3,       /* requested gamma is not a Mersenne exponent or <= r      */
-    PA_ERR_INEXACT = -4,     /* limb width B too wide: k*L*(2^B-1)^2 >= NTT prime      */
+    PA_ERR_INEXACT = -4,     /* limb width B too wide: k*L*(2^B-1)^2 >= p0*p1*p2       */
     PA_ERR_SEED_B_EVEN = -5, /* b is even (MH needs gcd(b, 2) = 1, Sec. 2.2 eq. (3))    */
     PA_ERR_SEED_RANGE = -6,  /* a seed word has a bit >= gamma set                      */
     PA_ERR_NOMEM = -7,       /* device allocation failed                                */
@@ -62,7 +62,8 @@ typedef enum pa_status {
 } pa_status;
 
 /* Plan request.  gamma = 0 picks the smallest Mersenne exponent above r.
- * B = 0 picks the default limb width (16 bits); otherwise 8 <= B <= 20. */
+ * B = 0 picks the widest limb (at most 32 bits) for which the transform is
+ * exact; otherwise 8 <= B <= 32. */
 typedef struct pa_params {
     uint64_t n;       /* input key length in bits, n >= 2                    */
     uint64_t r;       /* output length in bits, 1 <= r < n and r < gamma     */
@@ -82,17 +83,22 @@ typedef struct pa_plan_info {
     uint64_t a_words;       /* k * W                                        */
     uint64_t out_words;     /* ceil(r/64)                                   */
     uint64_t workspace_bytes; /* device memory owned by the plan            */
-    double exact_log2;      /* log2(k * L * (2^B - 1)^2), must be < 64      */
+    double exact_log2;      /* log2(k * L * (2^B - 1)^2); below log2(p0 p1 p2) = 90.69 */
+    uint32_t log2N1;        /* column-pass length 2^log2N1                  */
+    uint32_t log2N2;        /* row-pass length 2^log2N2 (N = 2^(log2N1 + log2N2)) */
+    uint32_t nprimes;       /* NTT primes per transform (3)                 */
+    uint32_t reserved;
 } pa_plan_info;
 
 typedef struct pa_plan pa_plan;
 
 /* Create a plan for one (n, r) shape on HIP device `hip_device`: derives
- * (gamma, k, L, N), checks that every convolution coefficient stays below the
- * NTT prime 2^64 - 2^32 + 1 (PA_ERR_INEXACT otherwise), allocates the
- * workspace and builds the twiddle tables.  Supported range: k <= 4096 and
- * N <= 2^26 (PA_ERR_LIMIT otherwise).  On success *out owns device memory
- * until pa_plan_destroy. */
+ * (gamma, k, B, L, N), checks that every convolution coefficient stays below
+ * the product of the three NTT primes p0 = 15*2^27+1, p1 = 63*2^25+1,
+ * p2 = 7*2^26+1 (PA_ERR_INEXACT otherwise), allocates the workspace and
+ * builds the twiddle tables.  Supported range: k <= 4096 and N <= 2^25
+ * (PA_ERR_LIMIT otherwise).  On success *out owns device memory until
+ * pa_plan_destroy. */
 pa_status pa_plan_create(const pa_params *params, int hip_device, pa_plan **out);
 
 /* Derive the shape pa_plan_create would use, without touching any device:

@@ -72,14 +72,28 @@ def _as_u64(words):
     return np.ascontiguousarray(np.asarray(words, dtype=np.uint64))
 
 
+def mod_mersenne(v: int, gamma: int) -> int:
+    """v mod (2^gamma - 1) for v >= 0 by the identity of Sec. 3.1:
+    x mod M_gamma = floor(x / 2^gamma) + x mod 2^gamma (a congruence), applied
+    until the value is below 2^gamma, then 2^gamma - 1 itself maps to 0.
+    Equal to Python's ``v % (2**gamma - 1)`` (checked in the pins), but linear
+    time where CPython's long division is quadratic."""
+    p = (1 << gamma) - 1
+    while v >> gamma:
+        v = (v & p) + (v >> gamma)
+    return 0 if v == p else v
+
+
 def mmh(a: list[int], x: list[int], p: int) -> int:
-    """Sec. 2.1 eq. (2): sum_i a_i x_i mod p."""
-    return sum(ai * xi for ai, xi in zip(a, x)) % p
+    """Sec. 2.1 eq. (2): sum_i a_i x_i mod p, with p = 2^gamma - 1."""
+    gamma = p.bit_length()
+    assert p == (1 << gamma) - 1
+    return mod_mersenne(sum(ai * xi for ai, xi in zip(a, x)), gamma)
 
 
 def mh(y: int, b: int, c: int, alpha: int, beta: int) -> int:
     """Sec. 2.2 eq. (4): ((b y + c) mod 2^alpha) div 2^(alpha - beta)."""
-    return ((b * y + c) % (1 << alpha)) >> (alpha - beta)
+    return ((b * y + c) & ((1 << alpha) - 1)) >> (alpha - beta)
 
 
 def split_key(K: int, n: int, gamma: int, k: int) -> list[int]:
@@ -101,7 +115,7 @@ def hash_ints(K: int, n: int, r: int, gamma: int, a: list[int], b: int, c: int):
     if any(xi == p for xi in x):
         return RELOAD, None, None, None
     y = mmh(a, x, p)
-    U = (b * y + c) % (1 << gamma)
+    U = (b * y + c) & ((1 << gamma) - 1)
     z = mh(y, b, c, gamma, r)
     return OK, z, y, U
 

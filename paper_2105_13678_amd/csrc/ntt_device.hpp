@@ -1,12 +1,12 @@
-// Device-side building blocks of the number-theoretic transforms over
-// P = 2^64 - 2^32 + 1: field operations with the hardware carry chain,
-// multiplication by constant powers of two, radix-2/4/8 butterflies and the
-// LDS steps of a tile transform.
+// Device building blocks of the number-theoretic transforms: Montgomery
+// arithmetic modulo three ~31-bit primes, radix-2/4/8 butterflies and the LDS
+// steps of a tile transform.
 //
-// Roots of unity: the plan picks omega_N so that omega_N^(N/64) = 8.  Then
-// omega_8 = 2^24, omega_4 = 2^48 and omega_2 = 2^96 = -1, so every twiddle
-// inside a radix-8 (or smaller) sub-transform is a power of two and costs a
-// shift-and-reduce instead of a full 64x64-bit product.
+// Every prime p satisfies p < 2^31, so a + b < 2^32 for a, b < p, and the
+// Montgomery product (R = 2^32) of any a < 2^32 with b < p is exact in 64 bits
+// before its final conditional subtraction.  On gfx950 all 32x32-bit
+// multiplies (v_mad_u64_u32, v_mul_lo_u32) are full-rate VALU instructions;
+// a modular product costs five, an addition or subtraction three.
 #pragma once
 
 #include "pa_internal.hpp"
@@ -14,180 +14,89 @@
 namespace pa {
 
 // ---------------------------------------------------------------- field ops
-// All take and return canonical values in [0, P) unless stated otherwise.
+// Values are canonical in [0, p).
 
-__device__ __forceinline__ uint64_t fadd(uint64_t a, uint64_t b) {
-    uint64_t s, t;
-    bool c1 = __builtin_add_overflow(a, b, &s);
-    bool c2 = __builtin_add_overflow(s, GL_EPS, &t);  // t = s - P (mod 2^64)
-    return (c1 | c2) ? t : s;
+// a * b * 2^-32 mod p, for a < 2^32 and b < p.
+__device__ __forceinline__ uint32_t mmul(uint32_t a, uint32_t b, const PrimeConst &M) {
+    const uint64_t t = (uint64_t)a * b;
+    const uint32_t m = (uint32_t)t * M.pinv;
+    const uint64_t u = (uint64_t)m * M.p + t;  // divisible by 2^32, below 2^33 p <= 2^64
+    const uint32_t r = (uint32_t)(u >> 32);   // r < 2p
+    return min(r, r - M.p);
 }
 
-__device__ __forceinline__ uint64_t fsub(uint64_t a, uint64_t b) {
-    uint64_t d;
-    bool c = __builtin_sub_overflow(a, b, &d);
-    return c ? d - GL_EPS : d;  // wrapped: d + P (mod 2^64)
+__device__ __forceinline__ uint32_t madd(uint32_t a, uint32_t b, const PrimeConst &M) {
+    const uint32_t s = a + b;
+    return min(s, s - M.p);
 }
 
-__device__ __forceinline__ uint64_t fneg(uint64_t a) { return a ? GL_P - a : 0ull; }
-
-// hi*2^64 + lo mod P, for any hi, lo < 2^64; canonical result.
-__device__ __forceinline__ uint64_t freduce(uint64_t lo, uint64_t hi) {
-    const uint32_t r2 = (uint32_t)hi, r3 = (uint32_t)(hi >> 32);
-    uint64_t t0;
-    bool bo = __builtin_sub_overflow(lo, (uint64_t)r3, &t0);  // lo - hi_hi (2^96 = -1)
-    t0 = bo ? t0 - GL_EPS : t0;
-    const uint64_t u = ((uint64_t)r2 << 32) - r2;             // hi_lo * (2^32 - 1) (2^64 = 2^32 - 1)
-    uint64_t r;
-    bool c = __builtin_add_overflow(t0, u, &r);
-    r = c ? r + GL_EPS : r;
-    uint64_t q;
-    bool c3 = __builtin_add_overflow(r, GL_EPS, &q);          // r >= P  <=>  r + 2^32 - 1 wraps
-    return c3 ? q : r;
-}
-
-// Product of any two 64-bit values, reduced mod P (canonical).
-__device__ __forceinline__ uint64_t fmul(uint64_t a, uint64_t b) {
-    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
-    const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
-    const uint64_t p00 = (uint64_t)a0 * b0;
-    const uint64_t t1 = (uint64_t)a0 * b1 + (p00 >> 32);
-    const uint64_t t2 = (uint64_t)a1 * b0 + (uint32_t)t1;
-    const uint64_t t3 = (uint64_t)a1 * b1 + (t1 >> 32);
-    const uint64_t hi = t3 + (t2 >> 32);
-    const uint64_t lo = (t2 << 32) | (uint32_t)p00;
-    return freduce(lo, hi);
-}
-
-// x * 2^S mod P for a compile-time 0 < S < 96.
-template <int S>
-__device__ __forceinline__ uint64_t fmul_pow2(uint64_t x) {
-    static_assert(S > 0 && S < 96, "shift out of range");
-    if constexpr (S < 64) {
-        return freduce(x << S, x >> (64 - S));
-    } else {
-        // x = xh*2^32 + xl; xh * 2^(S+32) = -xh * 2^(S-64) because 2^96 = -1
-        const uint64_t xl = x & 0xFFFFFFFFull, xh = x >> 32;
-        const uint64_t pos = freduce(0ull, xl << (S - 64));
-        return fsub(pos, xh << (S - 64));  // xh * 2^(S-64) < 2^63 < P
-    }
+__device__ __forceinline__ uint32_t msub(uint32_t a, uint32_t b, const PrimeConst &M) {
+    const uint32_t d = a - b;
+    return min(d, d + M.p);
 }
 
 // ---------------------------------------------------------------- small DFTs
-// Forward: natural order in, output slot s holds frequency bitrev(s).
-// omega_8 = 2^24, omega_4 = 2^48.
+// R-point DFTs (R = 2, 4, 8, 16) as log2(R) radix-2 stages in registers.
+// Forward (decimation in frequency): natural order in, output slot s holds
+// frequency bitrev(s).  The stage with half-size h multiplies the difference
+// at offset j by omega_{2h}^j = omega_16^(j*8/h) = M.w16[j*8/h].
 
-__device__ __forceinline__ void bfly(uint64_t &u, uint64_t &v) {
-    const uint64_t a = fadd(u, v), b = fsub(u, v);
+__device__ __forceinline__ void bfly(uint32_t &u, uint32_t &v, const PrimeConst &M) {
+    const uint32_t a = madd(u, v, M), b = msub(u, v, M);
     u = a;
     v = b;
 }
 
 template <int R>
-__device__ __forceinline__ void dft_fwd(uint64_t *v);
-
-template <>
-__device__ __forceinline__ void dft_fwd<2>(uint64_t *v) {
-    bfly(v[0], v[1]);
+__device__ __forceinline__ void dft_fwd(uint32_t *v, const PrimeConst &M) {
+#pragma unroll
+    for (int h = R / 2; h >= 1; h >>= 1) {
+#pragma unroll
+        for (int blk = 0; blk < R; blk += 2 * h) {
+#pragma unroll
+            for (int j = 0; j < h; ++j) {
+                bfly(v[blk + j], v[blk + j + h], M);
+                if (j) v[blk + j + h] = mmul(v[blk + j + h], M.w16[j * (8 / h)], M);
+            }
+        }
+    }
 }
 
-template <>
-__device__ __forceinline__ void dft_fwd<4>(uint64_t *v) {
-    bfly(v[0], v[2]);
-    bfly(v[1], v[3]);
-    v[3] = fmul_pow2<48>(v[3]);
-    bfly(v[0], v[1]);
-    bfly(v[2], v[3]);
-}
-
-template <>
-__device__ __forceinline__ void dft_fwd<8>(uint64_t *v) {
-    bfly(v[0], v[4]);
-    bfly(v[1], v[5]);
-    bfly(v[2], v[6]);
-    bfly(v[3], v[7]);
-    v[5] = fmul_pow2<24>(v[5]);
-    v[6] = fmul_pow2<48>(v[6]);
-    v[7] = fmul_pow2<72>(v[7]);
-    bfly(v[0], v[2]);
-    bfly(v[1], v[3]);
-    bfly(v[4], v[6]);
-    bfly(v[5], v[7]);
-    v[3] = fmul_pow2<48>(v[3]);
-    v[7] = fmul_pow2<48>(v[7]);
-    bfly(v[0], v[1]);
-    bfly(v[2], v[3]);
-    bfly(v[4], v[5]);
-    bfly(v[6], v[7]);
-}
-
-// Forward radix-8 DFT when v[4..7] are known to be zero (upper half of a
-// zero-padded input): the first stage is v[j+4] = v[j] * omega_8^j.
-__device__ __forceinline__ void dft_fwd8_lowhalf(uint64_t *v) {
-    v[4] = v[0];
-    v[5] = fmul_pow2<24>(v[1]);
-    v[6] = fmul_pow2<48>(v[2]);
-    v[7] = fmul_pow2<72>(v[3]);
-    bfly(v[0], v[2]);
-    bfly(v[1], v[3]);
-    bfly(v[4], v[6]);
-    bfly(v[5], v[7]);
-    v[3] = fmul_pow2<48>(v[3]);
-    v[7] = fmul_pow2<48>(v[7]);
-    bfly(v[0], v[1]);
-    bfly(v[2], v[3]);
-    bfly(v[4], v[5]);
-    bfly(v[6], v[7]);
-}
-
-// Inverse (without 1/R): input slot s holds frequency bitrev(s), natural
-// order out.  omega^-1: omega_8^-1 = -2^72, omega_8^-2 = -2^48,
-// omega_8^-3 = -2^24, omega_4^-1 = -2^48.  A negated twiddle swaps the
-// butterfly's sum and difference.
-
-// (u, v) -> (u - v, u + v): butterfly with twiddle -1 folded in
-__device__ __forceinline__ void bfly_neg(uint64_t &u, uint64_t &v) {
-    const uint64_t a = fsub(u, v), b = fadd(u, v);
-    u = a;
-    v = b;
-}
-
+// Forward DFT when the upper half of the input (v[R/2..R)) is known zero: the
+// first stage is v[j + R/2] = v[j] * omega_R^j.
 template <int R>
-__device__ __forceinline__ void dft_inv(uint64_t *v);
-
-template <>
-__device__ __forceinline__ void dft_inv<2>(uint64_t *v) {
-    bfly(v[0], v[1]);
+__device__ __forceinline__ void dft_fwd_lowhalf(uint32_t *v, const PrimeConst &M) {
+    constexpr int H = R / 2;
+#pragma unroll
+    for (int j = 0; j < H; ++j) v[j + H] = j ? mmul(v[j], M.w16[j * (8 / H)], M) : v[j];
+#pragma unroll
+    for (int h = H / 2; h >= 1; h >>= 1) {
+#pragma unroll
+        for (int blk = 0; blk < R; blk += 2 * h) {
+#pragma unroll
+            for (int j = 0; j < h; ++j) {
+                bfly(v[blk + j], v[blk + j + h], M);
+                if (j) v[blk + j + h] = mmul(v[blk + j + h], M.w16[j * (8 / h)], M);
+            }
+        }
+    }
 }
 
-template <>
-__device__ __forceinline__ void dft_inv<4>(uint64_t *v) {
-    bfly(v[0], v[1]);
-    bfly(v[2], v[3]);
-    v[3] = fmul_pow2<48>(v[3]);
-    bfly(v[0], v[2]);
-    bfly_neg(v[1], v[3]);
-}
-
-template <>
-__device__ __forceinline__ void dft_inv<8>(uint64_t *v) {
-    bfly(v[0], v[1]);
-    bfly(v[2], v[3]);
-    bfly(v[4], v[5]);
-    bfly(v[6], v[7]);
-    v[3] = fmul_pow2<48>(v[3]);
-    v[7] = fmul_pow2<48>(v[7]);
-    bfly(v[0], v[2]);
-    bfly_neg(v[1], v[3]);
-    bfly(v[4], v[6]);
-    bfly_neg(v[5], v[7]);
-    v[5] = fmul_pow2<72>(v[5]);
-    v[6] = fmul_pow2<48>(v[6]);
-    v[7] = fmul_pow2<24>(v[7]);
-    bfly(v[0], v[4]);
-    bfly_neg(v[1], v[5]);
-    bfly_neg(v[2], v[6]);
-    bfly_neg(v[3], v[7]);
+// Inverse (times R): undoes the forward stages in reverse order with
+// omega^-1 (M.w16i); bit-reversed slots in, natural order out.
+template <int R>
+__device__ __forceinline__ void dft_inv(uint32_t *v, const PrimeConst &M) {
+#pragma unroll
+    for (int h = 1; h < R; h <<= 1) {
+#pragma unroll
+        for (int blk = 0; blk < R; blk += 2 * h) {
+#pragma unroll
+            for (int j = 0; j < h; ++j) {
+                if (j) v[blk + j + h] = mmul(v[blk + j + h], M.w16i[j * (8 / h)], M);
+                bfly(v[blk + j], v[blk + j + h], M);
+            }
+        }
+    }
 }
 
 template <int R>
@@ -204,43 +113,54 @@ template <>
 struct Lg<8> {
     static constexpr int v = 3;
 };
+template <>
+struct Lg<16> {
+    static constexpr int v = 4;
+};
 
-__device__ __forceinline__ uint32_t brev_small(uint32_t s, int bits) {
-    return bits == 3 ? (((s & 1u) << 2) | (s & 2u) | ((s >> 2) & 1u)) : bits == 2 ? (((s & 1u) << 1) | ((s >> 1) & 1u)) : s;
+// bit reversal of s within `bits` bits (bits <= 4; constant-folded in unrolled loops)
+__device__ __forceinline__ constexpr uint32_t brev_small(uint32_t s, int bits) {
+    uint32_t r = 0;
+    for (int i = 0; i < bits; ++i) r |= ((s >> i) & 1u) << (bits - 1 - i);
+    return r;
 }
 
-// LDS swizzle: XOR the low 3 index bits with bits 5..7 so that the stride-8
-// accesses of the last steps spread over all banks.  A bijection on any
-// power-of-two range of at least 256 words and on every aligned 32-word block.
-__device__ __forceinline__ uint32_t swz(uint32_t i) { return i ^ ((i >> 5) & 7u); }
+// LDS swizzle for 32-bit elements: bits 6..8 of the index are XORed into
+// bits 0..2 and 3..5.  An involution that permutes each aligned 64-element
+// block, chosen so that the stride-8 accesses of the last radix-8 step and
+// the stride-64/8 pattern of the step before it hit 64 distinct banks.
+__device__ __forceinline__ uint32_t swz(uint32_t i) {
+    const uint32_t v = (i >> 6) & 7u;
+    return i ^ (v | (v << 3));
+}
 
 // ---------------------------------------------------------------- tile steps
 // A tile holds 2^cnt_lg interleaved transforms of length 2^lg: element
 // (index, q) lives at buf[swz((index << cnt_lg) + q)].
 //
-// Forward step with radix R at sub-length M = 2^lgM (DIF, Cooley-Tukey): for
-// each block b and n1 < M' = M/R the R values x[b*M + n1 + M'*n2] go through an
-// R-point DFT; slot s (frequency k2 = bitrev(s)) is multiplied by
-// omega_M^(n1*k2) and stored back at b*M + n1 + M'*s.  After all steps the
-// transform sits in bit-reversed order.  tw[e] = omega_len^e, e < len.
+// Forward step with radix R at sub-length M = 2^lgM (decimation in
+// frequency): for each block b and n1 < M' = M/R, the R values
+// x[b*M + n1 + M'*n2] go through an R-point DFT; slot s (frequency
+// k2 = bitrev(s)) is multiplied by omega_M^(n1*k2) and stored back at
+// b*M + n1 + M'*s.  After all steps the transform is in bit-reversed order.
+// tw[e] = omega_len^e (Montgomery form), e < len.
 
 template <int R, bool TW>
-__device__ __forceinline__ void fwd_task(uint64_t *buf, uint32_t task, uint32_t lg, uint32_t lgM,
-                                         uint32_t cnt_lg, const uint64_t *__restrict__ tw) {
+__device__ __forceinline__ void fwd_task(uint32_t *buf, uint32_t task, uint32_t lg, uint32_t lgM,
+                                         uint32_t cnt_lg, const uint32_t *__restrict__ tw, const PrimeConst &M) {
     constexpr int LR = Lg<R>::v;
     const uint32_t lgMp = lgM - LR;
     const uint32_t q = task & ((1u << cnt_lg) - 1);
     const uint32_t rest = task >> cnt_lg;
     const uint32_t n1 = rest & ((1u << lgMp) - 1);
     const uint32_t base = ((rest >> lgMp) << lgM) + n1;
-    uint64_t v[R];
+    uint32_t v[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) v[j] = buf[swz(((base + ((uint32_t)j << lgMp)) << cnt_lg) + q)];
-    dft_fwd<R>(v);
+    dft_fwd<R>(v, M);
     if (TW) {
 #pragma unroll
-        for (int s = 1; s < R; ++s)
-            v[s] = fmul(v[s], tw[(n1 * brev_small(s, LR)) << (lg - lgM)]);
+        for (int s = 1; s < R; ++s) v[s] = mmul(v[s], tw[(n1 * brev_small(s, LR)) << (lg - lgM)], M);
     }
 #pragma unroll
     for (int j = 0; j < R; ++j) buf[swz(((base + ((uint32_t)j << lgMp)) << cnt_lg) + q)] = v[j];
@@ -249,71 +169,74 @@ __device__ __forceinline__ void fwd_task(uint64_t *buf, uint32_t task, uint32_t 
 // Inverse of fwd_task: multiply slot s by omega_M^-(n1*k2), inverse R-point
 // DFT, natural order back.  twi[e] = omega_len^-e.
 template <int R, bool TW>
-__device__ __forceinline__ void inv_task(uint64_t *buf, uint32_t task, uint32_t lg, uint32_t lgM,
-                                         uint32_t cnt_lg, const uint64_t *__restrict__ twi) {
+__device__ __forceinline__ void inv_task(uint32_t *buf, uint32_t task, uint32_t lg, uint32_t lgM,
+                                         uint32_t cnt_lg, const uint32_t *__restrict__ twi, const PrimeConst &M) {
     constexpr int LR = Lg<R>::v;
     const uint32_t lgMp = lgM - LR;
     const uint32_t q = task & ((1u << cnt_lg) - 1);
     const uint32_t rest = task >> cnt_lg;
     const uint32_t n1 = rest & ((1u << lgMp) - 1);
     const uint32_t base = ((rest >> lgMp) << lgM) + n1;
-    uint64_t v[R];
+    uint32_t v[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) v[j] = buf[swz(((base + ((uint32_t)j << lgMp)) << cnt_lg) + q)];
     if (TW) {
 #pragma unroll
-        for (int s = 1; s < R; ++s)
-            v[s] = fmul(v[s], twi[(n1 * brev_small(s, LR)) << (lg - lgM)]);
+        for (int s = 1; s < R; ++s) v[s] = mmul(v[s], twi[(n1 * brev_small(s, LR)) << (lg - lgM)], M);
     }
-    dft_inv<R>(v);
+    dft_inv<R>(v, M);
 #pragma unroll
     for (int j = 0; j < R; ++j) buf[swz(((base + ((uint32_t)j << lgMp)) << cnt_lg) + q)] = v[j];
 }
 
 template <int R, bool TW>
-__device__ __forceinline__ void fwd_step(uint64_t *buf, uint32_t lg, uint32_t lgM, uint32_t cnt_lg,
-                                         const uint64_t *__restrict__ tw, uint32_t tid, uint32_t nt) {
+__device__ __forceinline__ void fwd_step(uint32_t *buf, uint32_t lg, uint32_t lgM, uint32_t cnt_lg,
+                                         const uint32_t *__restrict__ tw, const PrimeConst &M, uint32_t tid,
+                                         uint32_t nt) {
     const uint32_t ntask = (1u << (lg - Lg<R>::v)) << cnt_lg;
-    for (uint32_t t = tid; t < ntask; t += nt) fwd_task<R, TW>(buf, t, lg, lgM, cnt_lg, tw);
+    for (uint32_t t = tid; t < ntask; t += nt) fwd_task<R, TW>(buf, t, lg, lgM, cnt_lg, tw, M);
     __syncthreads();
 }
 
 template <int R, bool TW>
-__device__ __forceinline__ void inv_step(uint64_t *buf, uint32_t lg, uint32_t lgM, uint32_t cnt_lg,
-                                         const uint64_t *__restrict__ twi, uint32_t tid, uint32_t nt) {
+__device__ __forceinline__ void inv_step(uint32_t *buf, uint32_t lg, uint32_t lgM, uint32_t cnt_lg,
+                                         const uint32_t *__restrict__ twi, const PrimeConst &M, uint32_t tid,
+                                         uint32_t nt) {
     const uint32_t ntask = (1u << (lg - Lg<R>::v)) << cnt_lg;
-    for (uint32_t t = tid; t < ntask; t += nt) inv_task<R, TW>(buf, t, lg, lgM, cnt_lg, twi);
+    for (uint32_t t = tid; t < ntask; t += nt) inv_task<R, TW>(buf, t, lg, lgM, cnt_lg, twi, M);
     __syncthreads();
 }
 
-// Steps of a length-2^lg transform: radix-8 at lgM = lg, lg-3, ... while at
-// least 3 bits remain, then one radix-2 or radix-4 step at the bottom (whose
-// twiddles are all 1).  Runs the steps from `first_lgM` down (forward).
-__device__ __forceinline__ void fwd_steps_from(uint64_t *buf, uint32_t lg, uint32_t first_lgM, uint32_t cnt_lg,
-                                               const uint64_t *__restrict__ tw, uint32_t tid, uint32_t nt) {
+// Forward steps of a length-2^lg transform from sub-length 2^first_lgM down:
+// radix-8 while at least 3 bits remain, then one radix-2 or radix-4 step at
+// the bottom (whose twiddles are all 1).
+__device__ __forceinline__ void fwd_steps_from(uint32_t *buf, uint32_t lg, uint32_t first_lgM, uint32_t cnt_lg,
+                                               const uint32_t *__restrict__ tw, const PrimeConst &M, uint32_t tid,
+                                               uint32_t nt) {
     uint32_t lgM = first_lgM;
     while (lgM >= 3) {
         if (lgM > 3)
-            fwd_step<8, true>(buf, lg, lgM, cnt_lg, tw, tid, nt);
+            fwd_step<8, true>(buf, lg, lgM, cnt_lg, tw, M, tid, nt);
         else
-            fwd_step<8, false>(buf, lg, lgM, cnt_lg, tw, tid, nt);
+            fwd_step<8, false>(buf, lg, lgM, cnt_lg, tw, M, tid, nt);
         lgM -= 3;
     }
-    if (lgM == 2) fwd_step<4, false>(buf, lg, 2, cnt_lg, tw, tid, nt);
-    if (lgM == 1) fwd_step<2, false>(buf, lg, 1, cnt_lg, tw, tid, nt);
+    if (lgM == 2) fwd_step<4, false>(buf, lg, 2, cnt_lg, tw, M, tid, nt);
+    if (lgM == 1) fwd_step<2, false>(buf, lg, 1, cnt_lg, tw, M, tid, nt);
 }
 
-// Inverse steps bottom-up, stopping after the step at `last_lgM`.
-__device__ __forceinline__ void inv_steps_to(uint64_t *buf, uint32_t lg, uint32_t last_lgM, uint32_t cnt_lg,
-                                             const uint64_t *__restrict__ twi, uint32_t tid, uint32_t nt) {
+// Inverse steps bottom-up, up to and including sub-length 2^last_lgM.
+__device__ __forceinline__ void inv_steps_to(uint32_t *buf, uint32_t lg, uint32_t last_lgM, uint32_t cnt_lg,
+                                             const uint32_t *__restrict__ twi, const PrimeConst &M, uint32_t tid,
+                                             uint32_t nt) {
     const uint32_t r = lg % 3;
-    if (r == 2) inv_step<4, false>(buf, lg, 2, cnt_lg, twi, tid, nt);
-    if (r == 1) inv_step<2, false>(buf, lg, 1, cnt_lg, twi, tid, nt);
+    if (r == 2) inv_step<4, false>(buf, lg, 2, cnt_lg, twi, M, tid, nt);
+    if (r == 1) inv_step<2, false>(buf, lg, 1, cnt_lg, twi, M, tid, nt);
     for (uint32_t lgM = r + 3; lgM <= last_lgM; lgM += 3) {
         if (lgM > 3)
-            inv_step<8, true>(buf, lg, lgM, cnt_lg, twi, tid, nt);
+            inv_step<8, true>(buf, lg, lgM, cnt_lg, twi, M, tid, nt);
         else
-            inv_step<8, false>(buf, lg, lgM, cnt_lg, twi, tid, nt);
+            inv_step<8, false>(buf, lg, lgM, cnt_lg, twi, M, tid, nt);
     }
 }
 

@@ -21,11 +21,9 @@ const uint64_t kMersenne[] = {
     37156667, 42643801, 43112609, 57885161, 74207281, 77232917, 82589933,
     136279841};
 
-constexpr uint32_t kDefaultB = 16;
 constexpr uint64_t kMaxK = 4096;
 constexpr uint32_t kMinLog2N = 6;
-constexpr uint32_t kMaxLog2N = 26;
-constexpr uint32_t kMaxLdsLog2 = 13;  // 2^13 words = 64 KiB of LDS per tile
+constexpr uint32_t kMaxLdsLog2 = 14;  // 2^14 words = 64 KiB of LDS per tile
 
 struct DeviceGuard {
     int prev = -1;
@@ -59,11 +57,10 @@ pa_status plan_shape(const pa_params *prm, uint64_t *gamma, uint64_t *k, uint32_
         if (!found || prm->gamma <= r) return PA_ERR_GAMMA;
         g = prm->gamma;
     }
-    uint32_t b = prm->B ? prm->B : kDefaultB;
-    if (b < 8 || b > 20) return PA_ERR_ARG;
+    if (prm->B != 0 && (prm->B < 8 || prm->B > 32)) return PA_ERR_ARG;
     *gamma = g;
     *k = (n + g - 1) / g;
-    *B = b;
+    *B = prm->B;
     return PA_OK;
 }
 
@@ -102,8 +99,18 @@ pa_status pa_decode_status(uint32_t flags) {
 namespace {
 
 struct Layout {
-    size_t oX, oC, oT, oS, oY, oU, oAgg, oTc, oRes, oNo, oSt, oSo, oT1, oT2, oW, total;
+    size_t oX, oC, oC96, oT, oS, oY, oU, oAgg, oTc, oRes, oNo, oSt, oSo, oT1, oT2, oW, total;
 };
+
+// Exactness of the three-prime transform: every coefficient of the sum of the
+// k limb products is at most k*L*(2^B-1)^2 and must stay below p0*p1*p2.
+bool exact(uint64_t k, uint64_t L, uint32_t B) {
+    const unsigned __int128 P3 = (unsigned __int128)pa::PRIMES[0] * pa::PRIMES[1] * pa::PRIMES[2];
+    const unsigned __int128 lim = ((unsigned __int128)1 << B) - 1;
+    const unsigned __int128 kL = (unsigned __int128)k * L;
+    // compare k*L*lim^2 < P3 without overflow (kL < 2^45, lim^2 < 2^64)
+    return kL * lim <= (P3 - 1) / lim && kL * lim * lim < P3;
+}
 
 // Derive every plan quantity from the request; no device access.
 pa_status derive(const pa_params *prm, pa_plan *p, Layout *lay) {
@@ -112,14 +119,16 @@ pa_status derive(const pa_params *prm, pa_plan *p, Layout *lay) {
     pa_status st = plan_shape(prm, &gamma, &k, &B);
     if (st != PA_OK) return st;
     if (k > kMaxK) return PA_ERR_LIMIT;
+    if (B == 0) {
+        // widest limb that keeps the transform exact (fewest limbs)
+        B = 32;
+        while (B > 8 && !exact(k, (gamma + B - 1) / B, B)) --B;
+    }
     const uint64_t L = (gamma + B - 1) / B;
-    // Exactness: every coefficient of sum_i a_i * x_i is at most k*L*(2^B-1)^2,
-    // which must stay below the NTT prime for the transform to be exact.
-    const unsigned __int128 bound = (unsigned __int128)k * L * (((1ull << B) - 1) * ((1ull << B) - 1));
-    if (bound >= (unsigned __int128)pa::GL_P) return PA_ERR_INEXACT;
+    if (!exact(k, L, B)) return PA_ERR_INEXACT;
     uint32_t m = kMinLog2N;
     while ((1ull << m) < 2 * L - 1) ++m;
-    if (m > kMaxLog2N) return PA_ERR_LIMIT;
+    if (m > pa::MAX_LOG2N) return PA_ERR_LIMIT;
 
     p->n = prm->n;
     p->r = prm->r;
@@ -132,35 +141,44 @@ pa_status derive(const pa_params *prm, pa_plan *p, Layout *lay) {
     p->key_words = (prm->n + 63) / 64;
     p->out_words = (prm->r + 63) / 64;
     p->m = m;
-    // row length 2^m2 (one LDS row of at most 2^13 words), column length
-    // 2^m1 >= 8 (the column pass starts with a radix-8 step)
-    uint32_t m2 = (m + 3) / 2;
-    if (m2 > kMaxLdsLog2) m2 = kMaxLdsLog2;
-    if (m2 > m - 3) m2 = m - 3;
+    // rows of 2^m2 words (at most one 64 KiB LDS tile), columns of 2^m1 >= 8
+    // words.  From N = 2^15 to 2^23 rows are 4096 words (three register
+    // radix-16 steps); smaller transforms split about evenly; larger ones use
+    // the longest LDS row.
+    uint32_t m2;
+    if (m >= 15 && m <= 23)
+        m2 = 12;
+    else if (m > 23)
+        m2 = kMaxLdsLog2;
+    else
+        m2 = (m + 1) / 2;
     p->m2 = m2;
     p->m1 = m - m2;
-    uint32_t c_lg = 4;
+    uint32_t c_lg = 6;
     if (c_lg > p->m2) c_lg = p->m2;
     if (p->m1 + c_lg > kMaxLdsLog2) c_lg = kMaxLdsLog2 - p->m1;
     p->c_lg = c_lg;
     p->s_top = (uint32_t)(gamma - (uint64_t)B * (L - 1));
     p->e_fold = (uint32_t)((uint64_t)B * L - gamma);
-    const uint64_t Q = (64 + B - 1) / B, Q2 = (64 + p->e_fold + B - 1) / B;
+    const uint64_t Q = (96 + B - 1) / B, Q2 = (96 + p->e_fold + B - 1) / B;
     p->M1 = L + (Q > Q2 ? Q : Q2) + 1;
     const uint64_t digits = (p->M1 > L ? p->M1 : L) + 1;
     p->ntiles_max = (digits + pa::SCAN_TILE - 1) / pa::SCAN_TILE + 1;
     p->exact_log2 = std::log2((double)k) + std::log2((double)L) + 2.0 * std::log2((double)((1ull << B) - 1));
+    pa::init_prime_constants(p);
 
-    const size_t N = p->N;
+    const size_t N = p->N, P3 = pa::NPRIMES;
+    const size_t n1 = (size_t)1 << p->m1, n2 = (size_t)1 << p->m2;
     size_t off = 0;
     auto carve = [&](size_t bytes) {
         size_t o = off;
         off += align256(bytes);
         return o;
     };
-    lay->oX = carve(2 * k * N * 8);
-    lay->oC = carve(N * 8);
-    lay->oT = carve(digits * 4);
+    lay->oX = carve(2 * k * P3 * N * 4);
+    lay->oC = carve(P3 * N * 4);
+    lay->oC96 = carve(3 * N * 4);
+    lay->oT = carve(digits * 8);
     lay->oS = carve(p->M1 * 4);
     lay->oY = carve(L * 4);
     lay->oU = carve(L * 4);
@@ -170,9 +188,9 @@ pa_status derive(const pa_params *prm, pa_plan *p, Layout *lay) {
     lay->oNo = carve(k * 4);
     lay->oSt = carve(4 * 4);
     lay->oSo = carve(4 * 4);
-    lay->oT1 = carve((N >> p->m2) * 8 * 2);
-    lay->oT2 = carve(((size_t)1 << p->m2) * 8 * 2);
-    lay->oW = carve(N * 8 * 2);
+    lay->oT1 = carve(P3 * n1 * 4 * 2);
+    lay->oT2 = carve(P3 * n2 * 4 * 2);
+    lay->oW = carve(P3 * N * 4 * 2);
     lay->total = off;
     p->workspace_bytes = off;
     return PA_OK;
@@ -203,18 +221,15 @@ pa_status pa_plan_create(const pa_params *prm, int hip_device, pa_plan **out) {
         return st;
     }
     p->device = hip_device;
-    const size_t N = p->N;
-    const size_t off = lay.total;
-    const size_t oX = lay.oX, oC = lay.oC, oT = lay.oT, oS = lay.oS, oY = lay.oY, oU = lay.oU;
-    const size_t oAgg = lay.oAgg, oTc = lay.oTc, oRes = lay.oRes, oNo = lay.oNo, oSt = lay.oSt;
-    const size_t oSo = lay.oSo, oT1 = lay.oT1, oT2 = lay.oT2, oW = lay.oW;
+    const size_t N = p->N, P3 = pa::NPRIMES;
+    const size_t n1 = (size_t)1 << p->m1, n2 = (size_t)1 << p->m2;
 
     DeviceGuard guard(hip_device);
     if (!guard.ok) {
         delete p;
         return PA_ERR_DEVICE;
     }
-    if (hipMalloc(&p->base, off) != hipSuccess) {
+    if (hipMalloc(&p->base, lay.total) != hipSuccess) {
         (void)hipGetLastError();
         delete p;
         return PA_ERR_NOMEM;
@@ -225,25 +240,25 @@ pa_status pa_plan_create(const pa_params *prm, int hip_device, pa_plan **out) {
         return PA_ERR_NOMEM;
     }
     char *b = (char *)p->base;
-    p->X = (uint64_t *)(b + oX);
-    p->Cc = (uint64_t *)(b + oC);
-    p->t = (uint32_t *)(b + oT);
-    p->s = (uint32_t *)(b + oS);
-    p->y = (uint32_t *)(b + oY);
-    p->U = (uint32_t *)(b + oU);
-    p->agg = (pa::CFn *)(b + oAgg);
-    p->tcarry = (uint32_t *)(b + oTc);
-    p->res = (pa::ScanResult *)(b + oRes);
-    p->notones = (uint32_t *)(b + oNo);
-    p->status = (uint32_t *)(b + oSt);
-    p->status_out = (uint32_t *)(b + oSo);
-    const size_t h1 = N >> p->m2, h2 = (size_t)1 << p->m2;
-    p->tw1f = (uint64_t *)(b + oT1);
-    p->tw1i = p->tw1f + h1;
-    p->tw2f = (uint64_t *)(b + oT2);
-    p->tw2i = p->tw2f + h2;
-    p->Wf = (uint64_t *)(b + oW);
-    p->Wi = p->Wf + N;
+    p->X = (uint32_t *)(b + lay.oX);
+    p->Cc = (uint32_t *)(b + lay.oC);
+    p->C96 = (uint32_t *)(b + lay.oC96);
+    p->t = (uint64_t *)(b + lay.oT);
+    p->s = (uint32_t *)(b + lay.oS);
+    p->y = (uint32_t *)(b + lay.oY);
+    p->U = (uint32_t *)(b + lay.oU);
+    p->agg = (pa::CFn *)(b + lay.oAgg);
+    p->tcarry = (uint32_t *)(b + lay.oTc);
+    p->res = (pa::ScanResult *)(b + lay.oRes);
+    p->notones = (uint32_t *)(b + lay.oNo);
+    p->status = (uint32_t *)(b + lay.oSt);
+    p->status_out = (uint32_t *)(b + lay.oSo);
+    p->tw1f = (uint32_t *)(b + lay.oT1);
+    p->tw1i = p->tw1f + P3 * n1;
+    p->tw2f = (uint32_t *)(b + lay.oT2);
+    p->tw2i = p->tw2f + P3 * n2;
+    p->Wf = (uint32_t *)(b + lay.oW);
+    p->Wi = p->Wf + P3 * N;
 
     hipStream_t s0 = nullptr;
     if (pa::launch_twiddles(p, s0) != hipSuccess || hipStreamSynchronize(s0) != hipSuccess) {
@@ -274,6 +289,9 @@ pa_status pa_plan_get_info(const pa_plan *p, pa_plan_info *info) {
     info->out_words = p->out_words;
     info->workspace_bytes = p->workspace_bytes;
     info->exact_log2 = p->exact_log2;
+    info->log2N1 = p->m1;
+    info->log2N2 = p->m2;
+    info->nprimes = pa::NPRIMES;
     return PA_OK;
 }
 

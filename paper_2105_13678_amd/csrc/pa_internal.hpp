@@ -1,12 +1,14 @@
 // Internal declarations shared by the libpa translation units.
 //
-// Arithmetic: exact number-theoretic transforms over the prime
-// P = 2^64 - 2^32 + 1 ("Goldilocks"), whose multiplicative group has order
-// 2^32 * 3 * 5 * 17 * 257 * 65537, so power-of-two lengths up to 2^32 exist.
-// A gamma-bit number is cut into L = ceil(gamma/B) limbs of B bits (the
-// paper's 2^B-ary words, Sec. 1 and Sec. 2.1); every coefficient of the sum of
-// the k limb convolutions is below k*L*(2^B-1)^2, which the plan checks is
-// below P, so the transform result is the exact integer coefficient.
+// Arithmetic: exact convolutions of B-bit limb sequences by number-theoretic
+// transforms modulo three primes below 2^31,
+//     p0 = 15*2^27 + 1, p1 = 63*2^25 + 1, p2 = 7*2^26 + 1,
+// whose product exceeds 2^90.69; power-of-two lengths up to 2^25 exist in all
+// three.  A gamma-bit number is cut into L = ceil(gamma/B) limbs (the paper's
+// 2^B-ary words); every coefficient of the sum of the k limb convolutions is
+// at most k*L*(2^B-1)^2, which the plan checks is below p0*p1*p2, so the
+// Chinese-remainder reconstruction of the three transforms is the exact
+// integer coefficient.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,60 +20,32 @@
 
 namespace pa {
 
-constexpr uint64_t GL_P = 0xFFFFFFFF00000001ull;
-constexpr uint64_t GL_EPS = 0xFFFFFFFFull;  // 2^64 mod P
+constexpr int NPRIMES = 3;
+constexpr uint32_t PRIMES[NPRIMES] = {2013265921u, 2113929217u, 469762049u};
+constexpr uint32_t MAX_LOG2N = 25;  // largest power of two dividing every p - 1
 
-// ---------------------------------------------------------------- field ops
-// Values are kept canonical in [0, P).
+// Per-prime constants (Montgomery form x*2^32 mod p where noted).
+struct PrimeConst {
+    uint32_t p;
+    uint32_t pinv;   // -p^-1 mod 2^32
+    uint32_t one;    // 2^32 mod p (1 in Montgomery form)
+    uint32_t pad;
+    uint32_t w16[8];   // omega_16^j, j < 8, Montgomery form
+    uint32_t w16i[8];  // omega_16^-j, j < 8, Montgomery form
+};
 
-__host__ __device__ __forceinline__ uint64_t gl_add(uint64_t a, uint64_t b) {
-    uint64_t s = a + b;
-    s = (s < a) ? s + GL_EPS : s;      // wrapped past 2^64: add 2^64 mod P
-    s = (s >= GL_P) ? s - GL_P : s;
-    return s;
-}
+struct PrimeSet {
+    PrimeConst c[NPRIMES];
+};
 
-__host__ __device__ __forceinline__ uint64_t gl_sub(uint64_t a, uint64_t b) {
-    uint64_t d = a - b;
-    d = (a < b) ? d - GL_EPS : d;      // borrowed 2^64: add P, i.e. subtract 2^64 - P
-    return d;
-}
-
-// Reduce hi*2^64 + lo modulo P using 2^64 = 2^32 - 1 and 2^96 = -1 (mod P).
-__host__ __device__ __forceinline__ uint64_t gl_reduce(uint64_t lo, uint64_t hi) {
-    uint64_t hh = hi >> 32;
-    uint64_t hl = hi & 0xFFFFFFFFull;
-    uint64_t t0 = lo - hh;
-    t0 = (lo < hh) ? t0 - GL_EPS : t0;
-    uint64_t t1 = (hl << 32) - hl;
-    uint64_t r = t0 + t1;
-    r = (r < t1) ? r + GL_EPS : r;
-    r = (r >= GL_P) ? r - GL_P : r;
-    return r;
-}
-
-__host__ __device__ __forceinline__ uint64_t gl_mul(uint64_t a, uint64_t b) {
-    uint64_t a0 = a & 0xFFFFFFFFull, a1 = a >> 32;
-    uint64_t b0 = b & 0xFFFFFFFFull, b1 = b >> 32;
-    uint64_t p00 = a0 * b0;
-    uint64_t p01 = a0 * b1;
-    uint64_t p10 = a1 * b0;
-    uint64_t p11 = a1 * b1;
-    uint64_t mid = (p00 >> 32) + (p01 & 0xFFFFFFFFull) + (p10 & 0xFFFFFFFFull);
-    uint64_t lo = (mid << 32) | (p00 & 0xFFFFFFFFull);
-    uint64_t hi = p11 + (p01 >> 32) + (p10 >> 32) + (mid >> 32);
-    return gl_reduce(lo, hi);
-}
-
-__host__ __device__ __forceinline__ uint64_t gl_pow(uint64_t b, uint64_t e) {
-    uint64_t r = 1;
-    while (e) {
-        if (e & 1) r = gl_mul(r, b);
-        b = gl_mul(b, b);
-        e >>= 1;
-    }
-    return r;
-}
+// Constants for the Chinese-remainder (Garner) reconstruction.
+struct CrtConst {
+    uint32_t inv_p0_mod_p1;     // p0^-1 mod p1, Montgomery form (mod p1)
+    uint32_t p0_mod_p2;         // p0 mod p2, Montgomery form (mod p2)
+    uint32_t inv_p0p1_mod_p2;   // (p0 p1)^-1 mod p2, Montgomery form (mod p2)
+    uint32_t pad;
+    uint64_t p0p1;              // p0 * p1
+};
 
 // ---------------------------------------------------------------- carry functions
 // Carry transfer function of a run of limbs: carry_out = g + [carry_in >= th].
@@ -116,13 +90,16 @@ struct pa_plan {
     uint64_t M1;                // digit count of the folded sum before reduction
     uint64_t ntiles_max;
     double exact_log2;
+    pa::PrimeSet primes;
+    pa::CrtConst crt;
 
     // device memory (one allocation, carved)
     void *base;
     size_t workspace_bytes;
-    uint64_t *X;        // 2k arrays of N words: column-pass outputs of x_i (0..k-1) and a_i (k..2k-1)
-    uint64_t *Cc;       // N words: convolution coefficients
-    uint32_t *t;        // digit sums (max(M1, L) + pad)
+    uint32_t *X;        // 2k arrays x 3 primes x N words: column-pass outputs of x_i (0..k-1), a_i (k..2k-1)
+    uint32_t *Cc;       // 3 x N words: convolution residues
+    uint32_t *C96;      // 3 x N words: reconstructed coefficients, word planes (bits 0-31, 32-63, 64-95)
+    uint64_t *t;        // digit sums (max(M1, L) + pad)
     uint32_t *s;        // normalised limbs of the folded sum (M1)
     uint32_t *y;        // MMH output limbs (L)
     uint32_t *U;        // MH value limbs (L)
@@ -132,9 +109,9 @@ struct pa_plan {
     uint32_t *notones;  // k flags: chunk i has a limb that is not all ones
     uint32_t *status;   // seed/reload flags
     uint32_t *status_out;  // final flags of the last call (pa_hash reads it back)
-    uint64_t *tw1f, *tw1i;  // omega_{N1}^j, omega_{N1}^-j, j < N1
-    uint64_t *tw2f, *tw2i;  // omega_{N2}^j, omega_{N2}^-j, j < N2
-    uint64_t *Wf, *Wi;      // four-step twiddles, row-major in stored (bit-reversed) row order
+    uint32_t *tw1f, *tw1i;  // per prime: omega_{N1}^+-j, j < N1 (Montgomery form)
+    uint32_t *tw2f, *tw2i;  // per prime: omega_{N2}^+-j, j < N2
+    uint32_t *Wf, *Wi;      // per prime: four-step twiddles, stored (bit-reversed) row order
     uint32_t *h_status;     // pinned host word
 
     // phase profiling (pa_plan_set_profiling)
@@ -148,6 +125,9 @@ struct pa_plan {
 };
 
 namespace pa {
+
+// Host-side constant setup (pa_kernels.hip).
+void init_prime_constants(pa_plan *p);
 
 // Kernel launchers (pa_kernels.hip).  All enqueue on `st` and return the
 // first HIP error seen.

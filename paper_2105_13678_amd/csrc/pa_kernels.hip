@@ -2,38 +2,41 @@
 //
 // Pipeline for one block (Algorithm 1 of arXiv 2105.13678):
 //   MMH (Sec. 2.1 eq. 2): unpack key chunks x_i and seeds a_i into B-bit limbs,
-//        forward NTT of all 2k limb arrays, pointwise multiply-accumulate
-//        sum_i A_i * X_i in the transform domain, one inverse NTT -> exact
-//        coefficients of S = sum_i a_i x_i.
+//        forward NTT of all 2k limb arrays modulo each of three primes,
+//        pointwise multiply-accumulate sum_i A_i * X_i in the transform
+//        domain, one inverse NTT per prime, Chinese-remainder reconstruction
+//        -> exact coefficients of S = sum_i a_i x_i.
 //   fold (Sec. 3.1, x mod M = floor(x/2^gamma) + x mod 2^gamma): fold the
 //        coefficients above bit gamma onto the low part, carry-normalise,
 //        fold the small overflow back and canonicalise -> y in [0, p).
 //   MH (Sec. 2.2 eq. 4): NTT product b*y, add c while carrying the low gamma
 //        bits, keep bits [gamma - r, gamma) -> z.
 //
-// NTT of length N = N1 * N2 (four-step): a column pass does length-N1 DIF
+// NTT of length N = N1 * N2 (four-step): a column pass does length-N1
 // transforms on strided columns (LDS tile of 2^c_lg columns), a row pass does
-// the twiddle multiply and length-N2 DIF transforms on contiguous rows.  The
-// MMH row pass transforms x_i and a_i rows, accumulates their product over i
-// and immediately runs the inverse row transform on the accumulated row, so
-// the transform-domain sum never goes back to HBM.  The inverse column pass
-// (DIT) returns natural-order coefficients; 1/N is folded into the inverse
-// twiddles.
+// the four-step twiddle multiply and length-N2 transforms on contiguous rows.
+// The MMH row pass transforms x_i and a_i rows, accumulates their product
+// over i and immediately runs the inverse row transform on the accumulated
+// row, so the transform-domain sum never goes back to HBM.  The inverse
+// column pass returns natural-order residues; 1/N is folded into the inverse
+// twiddles.  Every pass runs register radix-8 steps with LDS exchanges.
 //
 // Carry propagation uses carry transfer functions f(c) = g + [c >= th]
-// (exact for carries below 2^B), composed with wavefront shuffles inside a
-// workgroup and a reduce / tile-prefix / apply sequence across workgroups.
+// (exact for the small carries that occur), composed with wavefront shuffles
+// inside a workgroup and a reduce / tile-prefix / apply sequence across
+// workgroups.
 #include "ntt_device.hpp"
 #include "pa_internal.hpp"
 
 using namespace pa;
 
-extern __shared__ uint64_t lds_dyn[];
+extern __shared__ uint32_t lds_dyn[];
 
 namespace {
 
 constexpr int COL_THREADS = 256;
 constexpr int ROW_EPT = 16;  // row elements per thread
+constexpr int ROW_MAX_THREADS = 1024;
 constexpr int PREFIX_THREADS = 1024;
 
 __device__ __forceinline__ uint32_t bitrev(uint32_t x, uint32_t bits) {
@@ -80,24 +83,48 @@ __device__ __forceinline__ uint64_t limbs_get64(const uint32_t *__restrict__ lim
     return v;
 }
 
-// ------------------------------------------------------------------ twiddles
-
-__global__ void k_tw_pow(uint64_t *dst, uint64_t count, uint64_t base) {
-    uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < count) dst[j] = gl_pow(base, j);
+__device__ __forceinline__ uint32_t mulmod_slow(uint32_t a, uint32_t b, uint32_t p) {
+    return (uint32_t)(((uint64_t)a * b) % p);
 }
 
-// Four-step twiddles in stored row order: row rho holds frequency
-// k1 = bitrev(rho); Wf = omega_N^(k1*n2), Wi = N^-1 * omega_N^-(k1*n2).
-__global__ void k_tw_four(uint64_t *Wf, uint64_t *Wi, uint32_t m1, uint32_t m2, uint64_t w,
-                          uint64_t winv, uint64_t ninv) {
-    uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >> (m1 + m2)) return;
-    uint32_t rho = (uint32_t)(idx >> m2);
-    uint32_t n2 = (uint32_t)(idx & ((1u << m2) - 1));
-    uint64_t e = (uint64_t)bitrev(rho, m1) * n2;
-    Wf[idx] = gl_pow(w, e);
-    Wi[idx] = gl_mul(ninv, gl_pow(winv, e));
+__device__ __forceinline__ uint32_t powmod_slow(uint32_t b, uint64_t e, uint32_t p) {
+    uint32_t r = 1;
+    while (e) {
+        if (e & 1) r = mulmod_slow(r, b, p);
+        b = mulmod_slow(b, b, p);
+        e >>= 1;
+    }
+    return r;
+}
+
+// ------------------------------------------------------------------ twiddles
+
+struct TwArgs {
+    uint32_t p[NPRIMES];
+    uint32_t base[NPRIMES];   // root, normal form
+    uint32_t scale[NPRIMES];  // factor, normal form (already includes 2^32 for Montgomery form)
+};
+
+// dst[q*count + j] = scale_q * base_q^j mod p_q  (blockIdx.y = prime q)
+__global__ void k_tw_pow(uint32_t *dst, uint64_t count, TwArgs A) {
+    const uint32_t q = blockIdx.y;
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < count) dst[q * count + j] = mulmod_slow(A.scale[q], powmod_slow(A.base[q], j, A.p[q]), A.p[q]);
+}
+
+// Four-step twiddles in stored row order: row rho holds column frequency
+// k1 = bitrev(rho); Wf = omega_N^(k1*n2), Wi = c * omega_N^-(k1*n2), both
+// scaled as given in the arguments (Montgomery form and 1/N folded in).
+__global__ void k_tw_four(uint32_t *Wf, uint32_t *Wi, uint32_t m1, uint32_t m2, TwArgs F, TwArgs I) {
+    const uint32_t q = blockIdx.y;
+    const uint64_t N = 1ull << (m1 + m2);
+    const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= N) return;
+    const uint32_t rho = (uint32_t)(idx >> m2);
+    const uint32_t n2 = (uint32_t)(idx & ((1u << m2) - 1));
+    const uint64_t e = (uint64_t)bitrev(rho, m1) * n2;
+    Wf[q * N + idx] = mulmod_slow(F.scale[q], powmod_slow(F.base[q], e, F.p[q]), F.p[q]);
+    Wi[q * N + idx] = mulmod_slow(I.scale[q], powmod_slow(I.base[q], e, I.p[q]), I.p[q]);
 }
 
 // ------------------------------------------------------------------ status
@@ -133,37 +160,40 @@ __global__ void k_status(const uint32_t *notones, uint64_t k, uint32_t *status) 
 // ------------------------------------------------------------------ NTT passes
 
 struct ColFwdArgs {
-    uint64_t *X;
+    uint32_t *X;
     uint64_t N, L, n, gamma, k, W;
     uint32_t m1, m2, c_lg, B, s_top, mode;  // mode 0: MMH (key chunks, seed chunks); 1: MH (y, b)
     const uint64_t *key, *a, *b;
     const uint32_t *ylimbs;
     uint32_t *notones;
-    const uint64_t *tw;  // omega_{N1}^e, e < N1
+    const uint32_t *tw;  // per prime: omega_{N1}^e, e < N1
+    PrimeSet P;
 };
 
 // Unpack + forward column pass.  blockIdx.y selects the array: in MMH mode
 // arrays 0..k-1 are the key chunks x_i and k..2k-1 the seed chunks a_i; in
-// MH mode array 0 is y and array 1 is b.  Limb j of a chunk is its bits
-// [jB, jB+B); limbs j >= L are the zero padding.  Because N >= 2L - 1, every
-// limb index >= N/2 is padding, so rows n1 >= N1/2 of the column tile are
-// zero and the first radix-8 step only unpacks its lower four inputs.
+// MH mode array 0 is y and array 1 is b.  blockIdx.z is the prime.  Limb j of
+// a chunk is its bits [jB, jB+B); limbs j >= L are the zero padding.  Since
+// N >= 2L - 1, every limb index >= N/2 is padding, so rows n1 >= N1/2 of the
+// column tile are zero and the first radix-8 step unpacks only four inputs.
 __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
-    uint64_t *lds = lds_dyn;
+    uint32_t *lds = lds_dyn;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t arr = blockIdx.y;
+    const uint32_t arr = blockIdx.y, pq = blockIdx.z;
+    const PrimeConst M = A.P.c[pq];
+    const uint32_t *tw = A.tw + ((uint64_t)pq << A.m1);
     const uint32_t c_lg = A.c_lg, lg = A.m1;
     const uint32_t cmask = (1u << c_lg) - 1;
     const uint64_t c0 = (uint64_t)tile << c_lg;
     const bool is_key = (A.mode == 0) && arr < A.k;
-    const uint32_t full = (1u << A.B) - 1, topv = (1u << A.s_top) - 1;
+    const uint32_t full = (uint32_t)((1ull << A.B) - 1), topv = (uint32_t)((1ull << A.s_top) - 1);
     const uint32_t lgMp = lg - 3;
     const uint32_t ntask = (1u << lgMp) << c_lg;
     bool not_ones = false;
     for (uint32_t task = threadIdx.x; task < ntask; task += blockDim.x) {
         const uint32_t q = task & cmask;
         const uint32_t n1 = task >> c_lg;
-        uint64_t v[8];
+        uint32_t v[8];
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
             const uint64_t row = n1 + ((uint64_t)jj << lgMp);
@@ -183,54 +213,55 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
                     x = (arr == 0) ? A.ylimbs[j] : bits_at(A.b, A.gamma, j * A.B, A.B);
                 }
             }
-            v[jj] = x;
+            v[jj] = mmul(x, M.one, M);  // x mod p
         }
-        dft_fwd8_lowhalf(v);
+        dft_fwd_lowhalf<8>(v, M);
         if (lg > 3) {
 #pragma unroll
-            for (int s = 1; s < 8; ++s) v[s] = fmul(v[s], A.tw[n1 * brev_small(s, 3)]);
+            for (int s = 1; s < 8; ++s) v[s] = mmul(v[s], tw[n1 * brev_small(s, 3)], M);
         }
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj) lds[swz(((n1 + ((uint32_t)jj << lgMp)) << c_lg) + q)] = v[jj];
     }
-    if (is_key) {
+    if (is_key && pq == 0) {
         int any = __syncthreads_or(not_ones);
         if (any && threadIdx.x == 0) A.notones[arr] = 1u;
     } else {
         __syncthreads();
     }
-    fwd_steps_from(lds, lg, lg - 3, c_lg, A.tw, threadIdx.x, blockDim.x);
-    uint64_t *out = A.X + (uint64_t)arr * A.N;
+    fwd_steps_from(lds, lg, lg - 3, c_lg, tw, M, threadIdx.x, blockDim.x);
+    uint32_t *out = A.X + ((uint64_t)arr * NPRIMES + pq) * A.N;
     const uint32_t cnt = (1u << lg) << c_lg;
     for (uint32_t e = threadIdx.x; e < cnt; e += blockDim.x)
         out[((uint64_t)(e >> c_lg) << A.m2) + c0 + (e & cmask)] = lds[swz(e)];
 }
 
 struct RowArgs {
-    const uint64_t *X;
-    uint64_t N, npairs, a_off;
+    const uint32_t *X;
+    uint64_t N, npairs, pair_stride, a_off;  // in words
     uint32_t m2;
-    uint64_t *out;
-    const uint64_t *Wf, *Wi, *twf, *twi;  // four-step twiddles; omega_{N2}^{+-e}, e < N2
+    uint32_t *out;
+    const uint32_t *Wf, *Wi, *twf, *twi;  // per prime: four-step twiddles; omega_{N2}^+-e, e < N2
+    PrimeSet P;
 };
 
 // First forward step of a row straight from global memory: four-step
 // twiddle on load, radix-8 DFT, step twiddles, into LDS.
-__device__ __forceinline__ void row_first_step(const uint64_t *__restrict__ g, const uint64_t *__restrict__ w,
-                                               uint64_t *buf, uint32_t lg, const uint64_t *__restrict__ tw,
-                                               uint32_t tid, uint32_t nt) {
+__device__ __forceinline__ void row_first_step(const uint32_t *__restrict__ g, const uint32_t *__restrict__ w,
+                                               uint32_t *buf, uint32_t lg, const uint32_t *__restrict__ tw,
+                                               const PrimeConst &M, uint32_t tid, uint32_t nt) {
     const uint32_t lgMp = lg - 3;
     for (uint32_t n1 = tid; n1 < (1u << lgMp); n1 += nt) {
-        uint64_t v[8];
+        uint32_t v[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const uint32_t e = n1 + ((uint32_t)j << lgMp);
-            v[j] = fmul(g[e], w[e]);
+            v[j] = mmul(g[e], w[e], M);
         }
-        dft_fwd<8>(v);
+        dft_fwd<8>(v, M);
         if (lg > 3) {
 #pragma unroll
-            for (int s = 1; s < 8; ++s) v[s] = fmul(v[s], tw[n1 * brev_small(s, 3)]);
+            for (int s = 1; s < 8; ++s) v[s] = mmul(v[s], tw[n1 * brev_small(s, 3)], M);
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) buf[swz(n1 + ((uint32_t)j << lgMp))] = v[j];
@@ -239,62 +270,68 @@ __device__ __forceinline__ void row_first_step(const uint64_t *__restrict__ g, c
 }
 
 // Last inverse step of a row straight to global memory (with the inverse
-// four-step twiddle and 1/N).
-__device__ __forceinline__ void row_last_inv_step(const uint64_t *buf, uint64_t *__restrict__ g,
-                                                  const uint64_t *__restrict__ w, uint32_t lg,
-                                                  const uint64_t *__restrict__ twi, uint32_t tid, uint32_t nt) {
+// four-step twiddle, 1/N and the Montgomery correction).
+__device__ __forceinline__ void row_last_inv_step(const uint32_t *buf, uint32_t *__restrict__ g,
+                                                  const uint32_t *__restrict__ w, uint32_t lg,
+                                                  const uint32_t *__restrict__ twi, const PrimeConst &M,
+                                                  uint32_t tid, uint32_t nt) {
     const uint32_t lgMp = lg - 3;
     for (uint32_t n1 = tid; n1 < (1u << lgMp); n1 += nt) {
-        uint64_t v[8];
+        uint32_t v[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) v[j] = buf[swz(n1 + ((uint32_t)j << lgMp))];
         if (lg > 3) {
 #pragma unroll
-            for (int s = 1; s < 8; ++s) v[s] = fmul(v[s], twi[n1 * brev_small(s, 3)]);
+            for (int s = 1; s < 8; ++s) v[s] = mmul(v[s], twi[n1 * brev_small(s, 3)], M);
         }
-        dft_inv<8>(v);
+        dft_inv<8>(v, M);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const uint32_t e = n1 + ((uint32_t)j << lgMp);
-            g[e] = fmul(v[j], w[e]);
+            g[e] = mmul(v[j], w[e], M);
         }
     }
 }
 
 // Row pass: for each pair (x_i, a_i): four-step twiddle and forward transform
-// of both rows, accumulate their pointwise product; then the inverse
-// transform of the accumulated row, inverse twiddle (with 1/N), store.
-__global__ __launch_bounds__(512) void k_row(RowArgs A) {
-    uint64_t *lds = lds_dyn;
+// of both rows, accumulate their pointwise (Montgomery) product; then the
+// inverse transform of the accumulated row, inverse twiddle, store.
+// blockIdx.y is the prime.
+__global__ __launch_bounds__(ROW_MAX_THREADS) void k_row(RowArgs A) {
+    uint32_t *lds = lds_dyn;
+    const uint32_t pq = blockIdx.y;
+    const PrimeConst M = A.P.c[pq];
     const uint32_t lg = A.m2;
     const uint32_t N2 = 1u << lg;
     const uint32_t T = blockDim.x;
     const uint32_t rho = xcd_tile(blockIdx.x, gridDim.x);
     const uint64_t rbase = (uint64_t)rho << lg;
-    const uint64_t *wf = A.Wf + rbase;
-    uint64_t acc[ROW_EPT], xr[ROW_EPT];
+    const uint32_t *wf = A.Wf + pq * A.N + rbase;
+    const uint32_t *twf = A.twf + ((uint64_t)pq << lg);
+    const uint32_t *twi = A.twi + ((uint64_t)pq << lg);
+    uint32_t acc[ROW_EPT], xr[ROW_EPT];
 #pragma unroll
     for (int q = 0; q < ROW_EPT; ++q) {
-        acc[q] = 0ull;
-        xr[q] = 0ull;
+        acc[q] = 0u;
+        xr[q] = 0u;
     }
     for (uint64_t i = 0; i < A.npairs; ++i) {
-        const uint64_t *xrow = A.X + i * A.N + rbase;
-        const uint64_t *arow = xrow + A.a_off;
-        row_first_step(xrow, wf, lds, lg, A.twf, threadIdx.x, T);
-        fwd_steps_from(lds, lg, lg - 3, 0, A.twf, threadIdx.x, T);
+        const uint32_t *xrow = A.X + i * A.pair_stride + pq * A.N + rbase;
+        const uint32_t *arow = xrow + A.a_off;
+        row_first_step(xrow, wf, lds, lg, twf, M, threadIdx.x, T);
+        fwd_steps_from(lds, lg, lg - 3, 0, twf, M, threadIdx.x, T);
 #pragma unroll
         for (int q = 0; q < ROW_EPT; ++q) {
             uint32_t e = threadIdx.x + q * T;
             if (e < N2) xr[q] = lds[swz(e)];
         }
         __syncthreads();
-        row_first_step(arow, wf, lds, lg, A.twf, threadIdx.x, T);
-        fwd_steps_from(lds, lg, lg - 3, 0, A.twf, threadIdx.x, T);
+        row_first_step(arow, wf, lds, lg, twf, M, threadIdx.x, T);
+        fwd_steps_from(lds, lg, lg - 3, 0, twf, M, threadIdx.x, T);
 #pragma unroll
         for (int q = 0; q < ROW_EPT; ++q) {
             uint32_t e = threadIdx.x + q * T;
-            if (e < N2) acc[q] = fadd(acc[q], fmul(xr[q], lds[swz(e)]));
+            if (e < N2) acc[q] = madd(acc[q], mmul(xr[q], lds[swz(e)], M), M);
         }
         __syncthreads();
     }
@@ -304,54 +341,229 @@ __global__ __launch_bounds__(512) void k_row(RowArgs A) {
         if (e < N2) lds[swz(e)] = acc[q];
     }
     __syncthreads();
-    inv_steps_to(lds, lg, lg - 3, 0, A.twi, threadIdx.x, T);
-    row_last_inv_step(lds, A.out + rbase, A.Wi + rbase, lg, A.twi, threadIdx.x, T);
+    inv_steps_to(lds, lg, lg - 3, 0, twi, M, threadIdx.x, T);
+    row_last_inv_step(lds, A.out + pq * A.N + rbase, A.Wi + pq * A.N + rbase, lg, twi, M, threadIdx.x, T);
+}
+
+// ---- 4096-point rows: three register radix-16 steps --------------------------
+// Thread t (256 per workgroup) owns 16 values in every step:
+//   step 1 (sub-length 4096, stride 256): elements t + 256 j (straight from
+//          global memory, four-step twiddle on load);
+//   step 2 (sub-length 256, stride 16): block t/16, offset t%16;
+//   step 3 (sub-length 16): elements 16 t .. 16 t + 15 (output in registers).
+// The x and a rows of a pair go through the steps together (two LDS
+// buffers), and their product accumulates in registers; the inverse starts
+// from those registers.  LDS addresses use an invertible XOR-linear swizzle
+// (bits 4..11 XORed into bits 0..5) that makes all three access patterns
+// free of bank conflicts for 32- and 64-bank LDS; because it is linear, each
+// thread computes the swizzled bases once and offsets them by constants.
+
+constexpr int R16_THREADS = 256;
+constexpr uint32_t R16_LEN = 4096;
+
+__device__ __forceinline__ constexpr uint32_t swz_r16(uint32_t i) {
+    return i ^ (((i >> 4) & 1u) * 11u) ^ (((i >> 5) & 1u) * 5u) ^ (((i >> 6) & 1u) * 28u) ^
+           (((i >> 7) & 1u) * 13u) ^ (((i >> 8) & 1u) * 29u) ^ (((i >> 9) & 1u) * 60u) ^
+           (((i >> 10) & 1u) * 25u) ^ (((i >> 11) & 1u) * 43u);
+}
+
+// Buffer resource over `words` 32-bit words at `base`: untyped 32-bit data
+// format (third descriptor dword 0x00020000 on gfx9-family parts); accesses
+// past the end read 0 and are not written.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const uint32_t *base, uint32_t words) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, (int)(words * 4u), 0x00020000);
+}
+
+__device__ __forceinline__ uint32_t bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+}
+
+__device__ __forceinline__ void bstore(uint32_t v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, 0);
+}
+
+__global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
+    uint32_t *bx = lds_dyn;
+    uint32_t *ba = lds_dyn + R16_LEN;
+    const uint32_t pq = blockIdx.y;
+    const PrimeConst M = A.P.c[pq];
+    const uint32_t t = threadIdx.x;
+    const uint32_t rho = xcd_tile(blockIdx.x, gridDim.x);
+    const uint64_t rbase = (uint64_t)rho * R16_LEN;
+    const uint32_t t4 = t * 4u;  // byte offset of element t in a row
+    // swizzled bases of this thread's three access patterns
+    const uint32_t s1 = swz_r16(t);                                  // t + 256 j
+    const uint32_t b2 = (t >> 4) * 256u + (t & 15u);
+    const uint32_t s2 = swz_r16(b2);                                 // b2 + 16 j
+    const uint32_t s3 = swz_r16(16u * t);                            // 16 t + j
+    const uint32_t n1b = t & 15u;
+    // loop-invariant step twiddles in registers: step 1 omega_4096^(t k2),
+    // step 2 omega_4096^(16 n1 k2)
+    const __amdgpu_buffer_rsrc_t rw = rsrc_of(A.Wf + pq * A.N + rbase, R16_LEN);
+    uint32_t t1r[16], t2r[16];
+    {
+        const __amdgpu_buffer_rsrc_t rt = rsrc_of(A.twf + (uint64_t)pq * R16_LEN, R16_LEN);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            t1r[j] = bload(rt, t4 * brev_small(j, 4), 0);
+            t2r[j] = bload(rt, (n1b * brev_small(j, 4)) << 6, 0);
+        }
+    }
+    uint32_t acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = 0u;
+
+    for (uint64_t i = 0; i < A.npairs; ++i) {
+        const uint32_t *xrow = A.X + i * A.pair_stride + pq * A.N + rbase;
+        // steps 1 and 2 for the x row (side 0) and the a row (side 1), one
+        // after the other to keep the register footprint small
+#pragma unroll 1
+        for (int side = 0; side < 2; ++side) {
+            const __amdgpu_buffer_rsrc_t rg = rsrc_of(side ? xrow + A.a_off : xrow, R16_LEN);
+            uint32_t *buf = side ? ba : bx;
+            uint32_t v[16];
+            // step 1: from global, four-step twiddle, radix-16, step twiddles
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = mmul(bload(rg, t4, 1024u * j), bload(rw, t4, 1024u * j), M);
+            dft_fwd<16>(v, M);
+#pragma unroll
+            for (int s = 1; s < 16; ++s) v[s] = mmul(v[s], t1r[s], M);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) buf[s1 ^ swz_r16(256u * j)] = v[j];
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int side = 0; side < 2; ++side) {
+            uint32_t *buf = side ? ba : bx;
+            uint32_t v[16];
+            // step 2: radix-16 on stride 16, step twiddles
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = buf[s2 ^ swz_r16(16u * j)];
+            dft_fwd<16>(v, M);
+#pragma unroll
+            for (int s = 1; s < 16; ++s) v[s] = mmul(v[s], t2r[s], M);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) buf[s2 ^ swz_r16(16u * j)] = v[j];
+        }
+        __syncthreads();
+        // step 3: radix-16 on 16 consecutive values of each row, then multiply-accumulate
+        uint32_t vx[16], va[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) vx[j] = bx[s3 ^ (uint32_t)j];
+        dft_fwd<16>(vx, M);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) va[j] = ba[s3 ^ (uint32_t)j];
+        dft_fwd<16>(va, M);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] = madd(acc[j], mmul(vx[j], va[j], M), M);
+        __syncthreads();  // the next pair overwrites the buffers
+    }
+
+    // inverse: step 3 from the accumulators, step 2, step 1 to global
+    const __amdgpu_buffer_rsrc_t rti = rsrc_of(A.twi + (uint64_t)pq * R16_LEN, R16_LEN);
+    dft_inv<16>(acc, M);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) bx[s3 ^ (uint32_t)j] = acc[j];
+    __syncthreads();
+    uint32_t v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = bx[s2 ^ swz_r16(16u * j)];
+#pragma unroll
+    for (int s = 1; s < 16; ++s) v[s] = mmul(v[s], bload(rti, (n1b * brev_small(s, 4)) << 6, 0), M);
+    dft_inv<16>(v, M);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) bx[s2 ^ swz_r16(16u * j)] = v[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = bx[s1 ^ swz_r16(256u * j)];
+#pragma unroll
+    for (int s = 1; s < 16; ++s) v[s] = mmul(v[s], bload(rti, t4 * brev_small(s, 4), 0), M);
+    dft_inv<16>(v, M);
+    const __amdgpu_buffer_rsrc_t ro = rsrc_of(A.out + pq * A.N + rbase, R16_LEN);
+    const __amdgpu_buffer_rsrc_t rwi = rsrc_of(A.Wi + pq * A.N + rbase, R16_LEN);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) bstore(mmul(v[j], bload(rwi, t4, 1024u * j), M), ro, t4, 1024u * j);
 }
 
 struct ColInvArgs {
-    uint64_t *Cc;
+    uint32_t *Cc;
+    uint64_t N;
     uint32_t m1, m2, c_lg;
-    const uint64_t *twi;  // omega_{N1}^-e, e < N1
+    const uint32_t *twi;  // per prime: omega_{N1}^-e, e < N1
+    PrimeSet P;
 };
 
 // Inverse column pass (bit-reversed rows in, natural rows out), in place.
 __global__ __launch_bounds__(COL_THREADS) void k_col_inv(ColInvArgs A) {
-    uint64_t *lds = lds_dyn;
+    uint32_t *lds = lds_dyn;
+    const uint32_t pq = blockIdx.y;
+    const PrimeConst M = A.P.c[pq];
+    const uint32_t *twi = A.twi + ((uint64_t)pq << A.m1);
+    uint32_t *cc = A.Cc + pq * A.N;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t c_lg = A.c_lg, lg = A.m1;
     const uint32_t cmask = (1u << c_lg) - 1;
     const uint32_t cnt = (1u << lg) << c_lg;
     const uint64_t c0 = (uint64_t)tile << c_lg;
     for (uint32_t e = threadIdx.x; e < cnt; e += blockDim.x)
-        lds[swz(e)] = A.Cc[((uint64_t)(e >> c_lg) << A.m2) + c0 + (e & cmask)];
+        lds[swz(e)] = cc[((uint64_t)(e >> c_lg) << A.m2) + c0 + (e & cmask)];
     __syncthreads();
-    inv_steps_to(lds, lg, lg - 3, c_lg, A.twi, threadIdx.x, blockDim.x);
+    inv_steps_to(lds, lg, lg - 3, c_lg, twi, M, threadIdx.x, blockDim.x);
     const uint32_t lgMp = lg - 3;
     const uint32_t ntask = (1u << lgMp) << c_lg;
     for (uint32_t task = threadIdx.x; task < ntask; task += blockDim.x) {
         const uint32_t q = task & cmask;
         const uint32_t n1 = task >> c_lg;
-        uint64_t v[8];
+        uint32_t v[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) v[j] = lds[swz(((n1 + ((uint32_t)j << lgMp)) << c_lg) + q)];
         if (lg > 3) {
 #pragma unroll
-            for (int s = 1; s < 8; ++s) v[s] = fmul(v[s], A.twi[n1 * brev_small(s, 3)]);
+            for (int s = 1; s < 8; ++s) v[s] = mmul(v[s], twi[n1 * brev_small(s, 3)], M);
         }
-        dft_inv<8>(v);
+        dft_inv<8>(v, M);
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            A.Cc[((uint64_t)(n1 + ((uint32_t)j << lgMp)) << A.m2) + c0 + q] = v[j];
+        for (int j = 0; j < 8; ++j) cc[((uint64_t)(n1 + ((uint32_t)j << lgMp)) << A.m2) + c0 + q] = v[j];
     }
+}
+
+// Chinese-remainder reconstruction (Garner): residues mod p0, p1, p2 of a
+// coefficient below p0 p1 p2 -> its exact value, stored as three word planes.
+__global__ void k_crt(const uint32_t *__restrict__ cc, uint32_t *c96, uint64_t N, uint64_t count, PrimeSet P,
+                      CrtConst K) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    const PrimeConst &M1 = P.c[1], &M2 = P.c[2];
+    const uint32_t r0 = cc[j], r1 = cc[N + j], r2 = cc[2 * N + j];
+    // v1 = (r1 - r0) / p0 mod p1   (r0 < p0 < p1)
+    const uint32_t v1 = mmul(msub(r1, r0, M1), K.inv_p0_mod_p1, M1);
+    // v2 = (r2 - r0 - v1 p0) / (p0 p1) mod p2
+    const uint32_t r0m = mmul(r0, M2.one, M2);
+    const uint32_t v1p0 = mmul(v1, K.p0_mod_p2, M2);
+    const uint32_t v2 = mmul(msub(msub(r2, r0m, M2), v1p0, M2), K.inv_p0p1_mod_p2, M2);
+    const unsigned __int128 c = (unsigned __int128)r0 + (unsigned __int128)v1 * PRIMES[0] +
+                                (unsigned __int128)v2 * K.p0p1;
+    c96[j] = (uint32_t)c;
+    c96[N + j] = (uint32_t)(c >> 32);
+    c96[2 * N + j] = (uint32_t)(c >> 64);
+}
+
+__device__ __forceinline__ unsigned __int128 coef(const uint32_t *__restrict__ c96, uint64_t N, uint64_t j) {
+    return (unsigned __int128)c96[j] | ((unsigned __int128)c96[N + j] << 32) |
+           ((unsigned __int128)c96[2 * N + j] << 64);
 }
 
 // ------------------------------------------------------------------ carry scan
 
 __device__ __forceinline__ CFn cf_id() { return CFn{CF_ID, CF_INF}; }
 
-__device__ __forceinline__ CFn cf_limb(uint32_t t, uint32_t B) {
-    uint32_t full = 1u << B;
-    return CFn{t >> B, full - (t & (full - 1))};
+// Carry function of one limb with digit sum t (64 bits) in base 2^B: the
+// carry out is (t + c) >> B = g + [c >= 2^B - (t mod 2^B)] for the small
+// carries c that occur (below 2^16); a threshold above that never fires.
+__device__ __forceinline__ CFn cf_limb(uint64_t t, uint32_t B) {
+    const uint64_t low = t & ((1ull << B) - 1);
+    const uint64_t th = (1ull << B) - low;
+    return CFn{(uint32_t)(t >> B), th > 0xFFFFull ? CF_INF : (uint32_t)th};
 }
 
 // hi o lo: first the lower run `lo`, then the higher run `hi`.
@@ -398,7 +610,7 @@ __device__ void block_scan(CFn f, CFn &excl, CFn &total) {
 }
 
 struct ScanArgs {
-    const uint32_t *t;   // digit sums: M regular limbs, then the top limb at index M if has_top
+    const uint64_t *t;   // digit sums: M regular limbs, then the top limb at index M if has_top
     uint32_t *out;       // normalised limbs
     uint64_t M;
     uint32_t B, has_top, s_top, dual;
@@ -447,15 +659,15 @@ __global__ __launch_bounds__(PREFIX_THREADS) void k_scan_prefix(ScanArgs A) {
         r.ov[0] = r.ov[1] = 0u;
         r.pad[0] = r.pad[1] = 0u;
         if (A.has_top) {
-            const uint32_t tt = A.t[A.M];
+            const uint64_t tt = A.t[A.M];
             for (uint32_t c = 0; c < 2; ++c) {
                 uint32_t ct = cf_eval(total, c);
-                uint32_t v = tt + ct;
+                uint64_t v = tt + ct;
                 r.carry_top[c] = ct;
-                r.ov[c] = v >> A.s_top;
+                r.ov[c] = (uint32_t)(v >> A.s_top);
             }
             r.sel = (A.dual && r.ov[1] != 0u) ? 1u : 0u;
-            A.out[A.M] = (tt + r.carry_top[r.sel]) & ((1u << A.s_top) - 1);
+            A.out[A.M] = (uint32_t)((tt + r.carry_top[r.sel]) & ((1ull << A.s_top) - 1));
         }
         *A.res = r;
     }
@@ -463,26 +675,26 @@ __global__ __launch_bounds__(PREFIX_THREADS) void k_scan_prefix(ScanArgs A) {
 
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(ScanArgs A) {
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_PER_THREAD;
-    uint32_t tv[SCAN_PER_THREAD];
+    uint64_t tv[SCAN_PER_THREAD];
     CFn f = cf_id();
 #pragma unroll
     for (int v = 0; v < SCAN_PER_THREAD; ++v) {
         uint64_t idx = base + v;
-        tv[v] = idx < A.M ? A.t[idx] : 0u;
+        tv[v] = idx < A.M ? A.t[idx] : 0ull;
         if (idx < A.M) f = cf_compose(f, cf_limb(tv[v], A.B));
     }
     CFn excl, total;
     block_scan<SCAN_THREADS>(f, excl, total);
     const uint32_t sel = A.dual ? A.res->sel : 0u;
     uint32_t carry = cf_eval(excl, A.tcarry[2 * blockIdx.x + sel]);
-    const uint32_t mask = (1u << A.B) - 1;
+    const uint64_t mask = (1ull << A.B) - 1;
 #pragma unroll
     for (int v = 0; v < SCAN_PER_THREAD; ++v) {
         uint64_t idx = base + v;
         if (idx < A.M) {
-            uint32_t val = tv[v] + carry;
-            A.out[idx] = val & mask;
-            carry = val >> A.B;
+            uint64_t val = tv[v] + carry;
+            A.out[idx] = (uint32_t)(val & mask);
+            carry = (uint32_t)(val >> A.B);
         }
     }
 }
@@ -491,35 +703,33 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(ScanArgs A) {
 
 // Digit sums of T = sum_{j<L} c_j 2^(Bj) + sum_{j>=L} c_j 2^(B(j-L)+e), which is
 // S folded once at bit gamma (2^gamma = 1 mod p; e = BL - gamma).  Each
-// coefficient is cut into B-bit pieces that land on consecutive digits.
-__global__ void k_fold_gather(const uint64_t *__restrict__ c, uint32_t *t, uint64_t M, uint64_t L,
-                              uint64_t N, uint32_t B, uint32_t e, uint32_t Q, uint32_t Q2) {
+// coefficient (below 2^91) is cut into B-bit pieces on consecutive digits.
+// ncoef bounds the coefficient index (coefficients from 2L - 1 on are zero).
+__global__ void k_fold_gather(const uint32_t *__restrict__ c96, uint64_t N, uint64_t *t, uint64_t M, uint64_t L,
+                              uint64_t ncoef, uint32_t B, uint32_t e, uint32_t Q, uint32_t Q2) {
     uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M) return;
     const uint64_t mask = (1ull << B) - 1;
     uint64_t sum = 0;
     for (uint32_t q = 0; q < Q; ++q) {
-        if (m >= q && m - q < L) sum += (c[m - q] >> (B * q)) & mask;
+        if (m >= q && m - q < L) sum += (uint64_t)(coef(c96, N, m - q) >> (B * q)) & mask;
     }
     for (uint32_t q = 0; q < Q2; ++q) {
         if (m >= q) {
             uint64_t j = L + m - q;
-            if (j < N) {
-                unsigned __int128 v = (unsigned __int128)c[j] << e;
-                sum += (uint64_t)(v >> (B * q)) & mask;
-            }
+            if (j < ncoef) sum += (uint64_t)((coef(c96, N, j) << e) >> (B * q)) & mask;
         }
     }
-    t[m] = (uint32_t)sum;
+    t[m] = sum;
 }
 
 // Second fold: T = T_lo + 2^gamma V with T_lo = T mod 2^gamma; digits of
 // T_lo + (V mod p) over L limbs (the top limb holds s_top bits).
-__global__ void k_wrap_gather(const uint32_t *__restrict__ s, uint32_t *t, uint64_t L, uint64_t M,
-                              uint32_t B, uint64_t gamma, uint32_t s_top) {
+__global__ void k_wrap_gather(const uint32_t *__restrict__ s, uint64_t *t, uint64_t L, uint64_t M, uint32_t B,
+                              uint64_t gamma, uint32_t s_top) {
     uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= L) return;
-    // V = bits [gamma, B*M) of the normalised T; it is below 2^66.
+    // V = bits [gamma, B*M) of the normalised T; it is below 2^92.
     unsigned __int128 V = 0;
     for (uint64_t idx = gamma / B; idx < M; ++idx) {
         uint64_t lo_bit = idx * B;
@@ -532,23 +742,23 @@ __global__ void k_wrap_gather(const uint32_t *__restrict__ s, uint32_t *t, uint6
         while (V >> gamma) V = (V & pm) + (V >> gamma);
         if (V == pm) V = 0;
     }
-    uint32_t lo = (m + 1 < L) ? s[m] : (s[m] & ((1u << s_top) - 1));
-    uint32_t vl = (B * m < 128) ? (uint32_t)((V >> (B * m)) & ((1ull << B) - 1)) : 0u;
+    const uint64_t lo = (m + 1 < L) ? s[m] : (s[m] & ((1ull << s_top) - 1));
+    const uint64_t vl = (B * m < 128) ? (uint64_t)((V >> (B * m)) & ((1ull << B) - 1)) : 0ull;
     t[m] = lo + vl;
 }
 
 // MH digits: pieces of the product coefficients below limb L plus the limbs of
 // c; everything at or above bit gamma is dropped later (mod 2^gamma).
-__global__ void k_mh_gather(const uint64_t *__restrict__ cc, const uint64_t *__restrict__ cseed,
-                            uint32_t *t, uint64_t L, uint32_t B, uint64_t gamma, uint32_t Q) {
+__global__ void k_mh_gather(const uint32_t *__restrict__ c96, uint64_t N, const uint64_t *__restrict__ cseed,
+                            uint64_t *t, uint64_t L, uint32_t B, uint64_t gamma, uint32_t Q) {
     uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= L) return;
     const uint64_t mask = (1ull << B) - 1;
     uint64_t sum = bits_at(cseed, gamma, m * B, B);
     for (uint32_t q = 0; q < Q; ++q) {
-        if (m >= q) sum += (cc[m - q] >> (B * q)) & mask;
+        if (m >= q) sum += (uint64_t)(coef(c96, N, m - q) >> (B * q)) & mask;
     }
-    t[m] = (uint32_t)sum;
+    t[m] = sum;
 }
 
 // ------------------------------------------------------------------ output
@@ -574,7 +784,7 @@ __global__ void k_copy_status(const uint32_t *status, uint32_t *dst) { *dst = st
 
 inline unsigned blocks_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
-hipError_t run_scan(pa_plan *p, const uint32_t *t, uint32_t *out, uint64_t M, bool top, bool dual,
+hipError_t run_scan(pa_plan *p, const uint64_t *t, uint32_t *out, uint64_t M, bool top, bool dual,
                     hipStream_t st) {
     ScanArgs A;
     A.t = t;
@@ -597,44 +807,97 @@ hipError_t run_scan(pa_plan *p, const uint32_t *t, uint32_t *out, uint64_t M, bo
 unsigned row_threads(const pa_plan *p) {
     unsigned n2 = 1u << p->m2;
     unsigned t = n2 / ROW_EPT;
-    return t < 64 ? 64 : t;  // ROW_EPT elements per thread; N2 <= 8192 -> at most 512 threads
+    return t < 64 ? 64 : t;  // ROW_EPT elements per thread; N2 <= 2^14 -> at most 1024 threads
 }
+
+// ---------------------------------------------------------------- host math
+
+uint32_t hmul(uint32_t a, uint32_t b, uint32_t p) { return (uint32_t)(((uint64_t)a * b) % p); }
+
+uint32_t hpow(uint32_t b, uint64_t e, uint32_t p) {
+    uint32_t r = 1;
+    while (e) {
+        if (e & 1) r = hmul(r, b, p);
+        b = hmul(b, b, p);
+        e >>= 1;
+    }
+    return r;
+}
+
+uint32_t hinv(uint32_t a, uint32_t p) { return hpow(a % p, p - 2, p); }
+
+uint32_t hmont(uint32_t a, uint32_t p) { return (uint32_t)(((uint64_t)(a % p) << 32) % p); }
+
+// Smallest generator of the multiplicative group mod p (p - 1 has prime
+// factors 2, 3, 5, 7 only for the primes used here).
+uint32_t hgen(uint32_t p) {
+    const uint32_t qs[4] = {2, 3, 5, 7};
+    for (uint32_t g = 2;; ++g) {
+        bool ok = true;
+        for (uint32_t q : qs)
+            if ((p - 1) % q == 0 && hpow(g, (p - 1) / q, p) == 1) ok = false;
+        if (ok) return g;
+    }
+}
+
+uint32_t root_of_unity(uint32_t p, uint32_t log2n) { return hpow(hgen(p), (uint64_t)(p - 1) >> log2n, p); }
 
 }  // namespace
 
 namespace pa {
 
-// Primitive 2^32-th root of unity r with r^(2^26) = 8, so that omega_64 = 8
-// and the radix-8 twiddles are powers of two.  7 generates the
-// multiplicative group of the field.
-static uint64_t canonical_root_2_32() {
-    const uint64_t r = gl_pow(7, (GL_P - 1) >> 32);
-    const uint64_t w64 = gl_pow(r, 1ull << 26);
-    uint64_t u = 0;
-    for (uint64_t e = 1; e < 64; e += 2)
-        if (gl_pow(8, e) == w64) {
-            u = e;
-            break;
+void init_prime_constants(pa_plan *p) {
+    for (int q = 0; q < NPRIMES; ++q) {
+        const uint32_t pr = PRIMES[q];
+        PrimeConst &C = p->primes.c[q];
+        C.p = pr;
+        uint32_t inv = 1;  // p^-1 mod 2^32 by Newton iteration
+        for (int i = 0; i < 5; ++i) inv *= 2u - pr * inv;
+        C.pinv = 0u - inv;
+        C.one = hmont(1, pr);
+        C.pad = 0;
+        const uint32_t w16 = root_of_unity(pr, 4), w16i = hinv(w16, pr);
+        uint32_t a = 1, b = 1;
+        for (int j = 0; j < 8; ++j) {
+            C.w16[j] = hmont(a, pr);
+            C.w16i[j] = hmont(b, pr);
+            a = hmul(a, w16, pr);
+            b = hmul(b, w16i, pr);
         }
-    uint64_t v = 1;
-    while ((u * v) % 64 != 1) v += 2;  // u^-1 mod 64
-    return gl_pow(r, v);
+    }
+    const uint32_t p0 = PRIMES[0], p1 = PRIMES[1], p2 = PRIMES[2];
+    p->crt.inv_p0_mod_p1 = hmont(hinv(p0 % p1, p1), p1);
+    p->crt.p0_mod_p2 = hmont(p0 % p2, p2);
+    p->crt.inv_p0p1_mod_p2 = hmont(hinv(hmul(p0 % p2, p1 % p2, p2), p2), p2);
+    p->crt.pad = 0;
+    p->crt.p0p1 = (uint64_t)p0 * p1;
 }
 
 hipError_t launch_twiddles(pa_plan *p, hipStream_t st) {
-    const uint64_t N = p->N;
-    const uint64_t w = gl_pow(canonical_root_2_32(), 1ull << (32 - p->m));
-    const uint64_t winv = gl_pow(w, N - 1);
-    const uint64_t ninv = gl_pow(N % GL_P, GL_P - 2);
-    const uint64_t w1 = gl_pow(w, 1ull << p->m2), w1i = gl_pow(winv, 1ull << p->m2);
-    const uint64_t w2 = gl_pow(w, 1ull << p->m1), w2i = gl_pow(winv, 1ull << p->m1);
-    const uint64_t n1 = 1ull << p->m1, n2 = 1ull << p->m2;
-    hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(n1, 256)), dim3(256), 0, st, p->tw1f, n1, w1);
-    hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(n1, 256)), dim3(256), 0, st, p->tw1i, n1, w1i);
-    hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(n2, 256)), dim3(256), 0, st, p->tw2f, n2, w2);
-    hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(n2, 256)), dim3(256), 0, st, p->tw2i, n2, w2i);
-    hipLaunchKernelGGL(k_tw_four, dim3(blocks_for(N, 256)), dim3(256), 0, st, p->Wf, p->Wi, p->m1, p->m2,
-                       w, winv, ninv);
+    const uint64_t N = p->N, n1 = 1ull << p->m1, n2 = 1ull << p->m2;
+    TwArgs t1f, t1i, t2f, t2i, Ff, Fi;
+    for (int q = 0; q < NPRIMES; ++q) {
+        const uint32_t pr = PRIMES[q];
+        const uint32_t w = root_of_unity(pr, p->m), wi = hinv(w, pr);
+        const uint32_t R = (uint32_t)((1ull << 32) % pr);
+        t1f.p[q] = t1i.p[q] = t2f.p[q] = t2i.p[q] = Ff.p[q] = Fi.p[q] = pr;
+        t1f.base[q] = hpow(w, n2, pr);  // omega_{N1}
+        t1i.base[q] = hpow(wi, n2, pr);
+        t2f.base[q] = hpow(w, n1, pr);  // omega_{N2}
+        t2i.base[q] = hpow(wi, n1, pr);
+        Ff.base[q] = w;
+        Fi.base[q] = wi;
+        t1f.scale[q] = t1i.scale[q] = t2f.scale[q] = t2i.scale[q] = Ff.scale[q] = R;
+        // inverse four-step twiddle: 1/N, times 2^32 to undo the Montgomery
+        // factor of the pointwise product, in Montgomery form
+        Fi.scale[q] = hmul(hmul(hinv((uint32_t)(N % pr), pr), R, pr), R, pr);
+    }
+    hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(n1, 256), NPRIMES), dim3(256), 0, st, p->tw1f, n1, t1f);
+    hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(n1, 256), NPRIMES), dim3(256), 0, st, p->tw1i, n1, t1i);
+    hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(n2, 256), NPRIMES), dim3(256), 0, st, p->tw2f, n2, t2f);
+    hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(n2, 256), NPRIMES), dim3(256), 0, st, p->tw2i, n2, t2i);
+    hipLaunchKernelGGL(k_tw_four, dim3(blocks_for(N, 256), NPRIMES), dim3(256), 0, st, p->Wf, p->Wi, p->m1, p->m2,
+                       Ff, Fi);
     return hipGetLastError();
 }
 
@@ -647,9 +910,7 @@ hipError_t launch_prologue(pa_plan *p, const uint64_t *a, const uint64_t *b, con
     return hipGetLastError();
 }
 
-hipError_t launch_mmh(pa_plan *p, const uint64_t *key, const uint64_t *a, hipStream_t st) {
-    const unsigned ncol_tiles = 1u << (p->m2 - p->c_lg);
-    const size_t col_lds = ((size_t)8 << p->m1) << p->c_lg;
+static ColFwdArgs col_args(pa_plan *p, uint32_t mode) {
     ColFwdArgs cf;
     cf.X = p->X;
     cf.N = p->N;
@@ -663,51 +924,86 @@ hipError_t launch_mmh(pa_plan *p, const uint64_t *key, const uint64_t *a, hipStr
     cf.c_lg = p->c_lg;
     cf.B = p->B;
     cf.s_top = p->s_top;
-    cf.mode = 0;
-    cf.key = key;
-    cf.a = a;
+    cf.mode = mode;
+    cf.key = nullptr;
+    cf.a = nullptr;
     cf.b = nullptr;
     cf.ylimbs = nullptr;
     cf.notones = p->notones;
     cf.tw = p->tw1f;
-    phase_mark(p, PA_PH_MMH_COL, true, st);
-    hipLaunchKernelGGL(k_col_fwd, dim3(ncol_tiles, (unsigned)(2 * p->k)), dim3(COL_THREADS), col_lds, st, cf);
-    phase_mark(p, PA_PH_MMH_COL, false, st);
-    hipLaunchKernelGGL(k_status, dim3(1), dim3(256), 0, st, p->notones, p->k, p->status);
+    cf.P = p->primes;
+    return cf;
+}
 
+static RowArgs row_args(pa_plan *p, uint64_t npairs, uint64_t a_off) {
     RowArgs ra;
     ra.X = p->X;
     ra.N = p->N;
-    ra.npairs = p->k;
-    ra.a_off = p->k * p->N;
+    ra.npairs = npairs;
+    ra.pair_stride = (uint64_t)NPRIMES * p->N;
+    ra.a_off = a_off;
     ra.m2 = p->m2;
     ra.out = p->Cc;
     ra.Wf = p->Wf;
     ra.Wi = p->Wi;
     ra.twf = p->tw2f;
     ra.twi = p->tw2i;
-    phase_mark(p, PA_PH_MMH_ROW, true, st);
-    hipLaunchKernelGGL(k_row, dim3(1u << p->m1), dim3(row_threads(p)), (size_t)8 << p->m2, st, ra);
-    phase_mark(p, PA_PH_MMH_ROW, false, st);
+    ra.P = p->primes;
+    return ra;
+}
 
+static void launch_row(pa_plan *p, const RowArgs &ra, hipStream_t st) {
+    if (p->m2 == 12)
+        hipLaunchKernelGGL(k_row16, dim3(1u << p->m1, NPRIMES), dim3(R16_THREADS), (size_t)8 * R16_LEN, st, ra);
+    else
+        hipLaunchKernelGGL(k_row, dim3(1u << p->m1, NPRIMES), dim3(row_threads(p)), (size_t)4 << p->m2, st, ra);
+}
+
+static ColInvArgs colinv_args(pa_plan *p) {
     ColInvArgs ci;
     ci.Cc = p->Cc;
+    ci.N = p->N;
     ci.m1 = p->m1;
     ci.m2 = p->m2;
     ci.c_lg = p->c_lg;
     ci.twi = p->tw1i;
+    ci.P = p->primes;
+    return ci;
+}
+
+hipError_t launch_mmh(pa_plan *p, const uint64_t *key, const uint64_t *a, hipStream_t st) {
+    const unsigned ncol_tiles = 1u << (p->m2 - p->c_lg);
+    const size_t col_lds = ((size_t)4 << p->m1) << p->c_lg;
+    ColFwdArgs cf = col_args(p, 0);
+    cf.key = key;
+    cf.a = a;
+    phase_mark(p, PA_PH_MMH_COL, true, st);
+    hipLaunchKernelGGL(k_col_fwd, dim3(ncol_tiles, (unsigned)(2 * p->k), NPRIMES), dim3(COL_THREADS), col_lds, st,
+                       cf);
+    phase_mark(p, PA_PH_MMH_COL, false, st);
+    hipLaunchKernelGGL(k_status, dim3(1), dim3(256), 0, st, p->notones, p->k, p->status);
+
+    RowArgs ra = row_args(p, p->k, p->k * NPRIMES * p->N);
+    phase_mark(p, PA_PH_MMH_ROW, true, st);
+    launch_row(p, ra, st);
+    phase_mark(p, PA_PH_MMH_ROW, false, st);
+
+    ColInvArgs ci = colinv_args(p);
     phase_mark(p, PA_PH_MMH_COLINV, true, st);
-    hipLaunchKernelGGL(k_col_inv, dim3(ncol_tiles), dim3(COL_THREADS), col_lds, st, ci);
+    hipLaunchKernelGGL(k_col_inv, dim3(ncol_tiles, NPRIMES), dim3(COL_THREADS), col_lds, st, ci);
     phase_mark(p, PA_PH_MMH_COLINV, false, st);
     return hipGetLastError();
 }
 
 hipError_t launch_fold(pa_plan *p, hipStream_t st) {
-    const uint32_t Q = (64 + p->B - 1) / p->B;
-    const uint32_t Q2 = (64 + p->e_fold + p->B - 1) / p->B;
+    const uint32_t Q = (96 + p->B - 1) / p->B;
+    const uint32_t Q2 = (96 + p->e_fold + p->B - 1) / p->B;
+    const uint64_t ncoef = 2 * p->L - 1;  // nonzero coefficients of the product
     phase_mark(p, PA_PH_FOLD, true, st);
-    hipLaunchKernelGGL(k_fold_gather, dim3(blocks_for(p->M1, 256)), dim3(256), 0, st, p->Cc, p->t, p->M1,
-                       p->L, p->N, p->B, p->e_fold, Q, Q2);
+    hipLaunchKernelGGL(k_crt, dim3(blocks_for(ncoef, 256)), dim3(256), 0, st, p->Cc, p->C96, p->N, ncoef,
+                       p->primes, p->crt);
+    hipLaunchKernelGGL(k_fold_gather, dim3(blocks_for(p->M1, 256)), dim3(256), 0, st, p->C96, p->N, p->t, p->M1,
+                       p->L, ncoef, p->B, p->e_fold, Q, Q2);
     hipError_t e = run_scan(p, p->t, p->s, p->M1, false, false, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_wrap_gather, dim3(blocks_for(p->L, 256)), dim3(256), 0, st, p->s, p->t, p->L, p->M1,
@@ -719,60 +1015,31 @@ hipError_t launch_fold(pa_plan *p, hipStream_t st) {
 
 hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, hipStream_t st) {
     const unsigned ncol_tiles = 1u << (p->m2 - p->c_lg);
-    const size_t col_lds = ((size_t)8 << p->m1) << p->c_lg;
-    ColFwdArgs cf;
-    cf.X = p->X;
-    cf.N = p->N;
-    cf.L = p->L;
-    cf.n = p->n;
-    cf.gamma = p->gamma;
-    cf.k = p->k;
-    cf.W = p->W;
-    cf.m1 = p->m1;
-    cf.m2 = p->m2;
-    cf.c_lg = p->c_lg;
-    cf.B = p->B;
-    cf.s_top = p->s_top;
-    cf.mode = 1;
-    cf.key = nullptr;
-    cf.a = nullptr;
+    const size_t col_lds = ((size_t)4 << p->m1) << p->c_lg;
+    ColFwdArgs cf = col_args(p, 1);
     cf.b = b;
     cf.ylimbs = p->y;
-    cf.notones = p->notones;
-    cf.tw = p->tw1f;
     phase_mark(p, PA_PH_MH_COL, true, st);
-    hipLaunchKernelGGL(k_col_fwd, dim3(ncol_tiles, 2u), dim3(COL_THREADS), col_lds, st, cf);
+    hipLaunchKernelGGL(k_col_fwd, dim3(ncol_tiles, 2u, NPRIMES), dim3(COL_THREADS), col_lds, st, cf);
     phase_mark(p, PA_PH_MH_COL, false, st);
 
-    RowArgs ra;
-    ra.X = p->X;
-    ra.N = p->N;
-    ra.npairs = 1;
-    ra.a_off = p->N;
-    ra.m2 = p->m2;
-    ra.out = p->Cc;
-    ra.Wf = p->Wf;
-    ra.Wi = p->Wi;
-    ra.twf = p->tw2f;
-    ra.twi = p->tw2i;
+    RowArgs ra = row_args(p, 1, (uint64_t)NPRIMES * p->N);
     phase_mark(p, PA_PH_MH_ROW, true, st);
-    hipLaunchKernelGGL(k_row, dim3(1u << p->m1), dim3(row_threads(p)), (size_t)8 << p->m2, st, ra);
+    launch_row(p, ra, st);
     phase_mark(p, PA_PH_MH_ROW, false, st);
 
-    ColInvArgs ci;
-    ci.Cc = p->Cc;
-    ci.m1 = p->m1;
-    ci.m2 = p->m2;
-    ci.c_lg = p->c_lg;
-    ci.twi = p->tw1i;
+    ColInvArgs ci = colinv_args(p);
     phase_mark(p, PA_PH_MH_COLINV, true, st);
-    hipLaunchKernelGGL(k_col_inv, dim3(ncol_tiles), dim3(COL_THREADS), col_lds, st, ci);
+    hipLaunchKernelGGL(k_col_inv, dim3(ncol_tiles, NPRIMES), dim3(COL_THREADS), col_lds, st, ci);
     phase_mark(p, PA_PH_MH_COLINV, false, st);
 
-    const uint32_t Q = (64 + p->B - 1) / p->B;
+    const uint32_t Q = (96 + p->B - 1) / p->B;
     phase_mark(p, PA_PH_MH_CARRY, true, st);
-    hipLaunchKernelGGL(k_mh_gather, dim3(blocks_for(p->L, 256)), dim3(256), 0, st, p->Cc, c, p->t, p->L, p->B,
-                       p->gamma, Q);
+    // only the coefficients below limb L matter mod 2^gamma
+    hipLaunchKernelGGL(k_crt, dim3(blocks_for(p->L, 256)), dim3(256), 0, st, p->Cc, p->C96, p->N, p->L, p->primes,
+                       p->crt);
+    hipLaunchKernelGGL(k_mh_gather, dim3(blocks_for(p->L, 256)), dim3(256), 0, st, p->C96, p->N, c, p->t, p->L,
+                       p->B, p->gamma, Q);
     hipError_t e = run_scan(p, p->t, p->U, p->L - 1, true, false, st);
     phase_mark(p, PA_PH_MH_CARRY, false, st);
     return e;

@@ -43,25 +43,45 @@ def test_plan_rule_matches_oracle():
             assert st == st_o
             continue
         if st == binding.PA_ERR_LIMIT:
-            assert k_o > 4096 or (2 * math.ceil(g_o / 16) - 1) > (1 << 26)
+            assert k_o > 4096 or (2 * math.ceil(g_o / 32) - 1) > (1 << 25)
             continue
         assert st == 0, (n, r, st)
         assert (info["gamma"], info["k"]) == (g_o, k_o)
 
 
-@pytest.mark.parametrize("n,r,gamma,k,L,N", [
-    (1 << 20, (1 << 20) // 10, 110503, 10, 6907, 1 << 14),
-    (260_000_000, 26_000_000, 30402457, 9, 1900154, 1 << 22),
-    (10 * 25964951, 25237932, 25964951, 10, 1622810, 1 << 22),
-    (1 << 32, 1 << 27, 136279841, 32, 8517491, 1 << 25),
+@pytest.mark.parametrize("n,r,gamma,k,B,L,N", [
+    (1 << 20, (1 << 20) // 10, 110503, 10, 32, 3454, 1 << 13),
+    (260_000_000, 26_000_000, 30402457, 9, 32, 950077, 1 << 21),
+    (10 * 25964951, 25237932, 25964951, 10, 32, 811405, 1 << 21),
+    (1 << 32, 1 << 27, 136279841, 32, 31, 4396124, 1 << 24),
 ])
-def test_derived_shapes(n, r, gamma, k, L, N):
+def test_derived_shapes(n, r, gamma, k, B, L, N):
     st, info = binding.plan_query(n, r)
     assert st == 0
-    assert (info["gamma"], info["k"], info["L"], info["N"], info["B"]) == (gamma, k, L, N, 16)
-    assert info["exact_log2"] < 64
+    assert (info["gamma"], info["k"], info["B"], info["L"], info["N"]) == (gamma, k, B, L, N)
+    assert info["nprimes"] == 3 and info["log2N1"] + info["log2N2"] == info["log2N"]
+    # exactness: k L (2^B - 1)^2 below the product of the three NTT primes
+    P3 = 2013265921 * 2113929217 * 469762049
+    assert k * L * (2 ** B - 1) ** 2 < P3
+    assert info["exact_log2"] < math.log2(P3)
     assert info["out_words"] == (r + 63) // 64
     assert info["seed_words"] == (gamma + 63) // 64
+    assert 2 * L - 1 <= N < 2 * (2 * L - 1) or N == 64
+
+
+def test_auto_limb_width_is_widest_exact():
+    P3 = 2013265921 * 2113929217 * 469762049
+    rng = random.Random(4)
+    for _ in range(300):
+        r = int(2 ** rng.uniform(0, 27.5))
+        n = r + 1 + int(2 ** rng.uniform(0, 32.5))
+        st, info = binding.plan_query(n, r)
+        if st != 0:
+            continue
+        g, k, B = info["gamma"], info["k"], info["B"]
+        assert k * -(-g // B) * (2 ** B - 1) ** 2 < P3
+        if B < 32:
+            assert k * -(-g // (B + 1)) * (2 ** (B + 1) - 1) ** 2 >= P3
 
 
 def test_plan_errors():
@@ -71,9 +91,9 @@ def test_plan_errors():
     assert binding.plan_query(100, 10, gamma=11)[0] == binding.PA_ERR_GAMMA
     assert binding.plan_query(100, 13, gamma=13)[0] == binding.PA_ERR_GAMMA
     assert binding.plan_query(1000, 10, B=7)[0] == binding.PA_ERR_ARG
-    assert binding.plan_query(1000, 10, B=21)[0] == binding.PA_ERR_ARG
-    # exactness bound k * L * (2^B - 1)^2 < 2^64 - 2^32 + 1
-    st, info = binding.plan_query(260_000_000, 26_000_000, B=20)
-    assert st == 0 and info["exact_log2"] < 64
-    assert binding.plan_query(2_600_000_000, 26_000_000, B=20)[0] == binding.PA_ERR_INEXACT
+    assert binding.plan_query(1000, 10, B=33)[0] == binding.PA_ERR_ARG
+    # exactness bound k * L * (2^B - 1)^2 < p0 p1 p2
+    st, info = binding.plan_query(260_000_000, 26_000_000, B=32)
+    assert st == 0
+    assert binding.plan_query(1 << 32, 1 << 27, B=32)[0] == binding.PA_ERR_INEXACT
     assert binding.plan_query(1 << 32, 200)[0] == binding.PA_ERR_LIMIT   # k > 4096

@@ -97,14 +97,27 @@ def test_edge_shapes(pa, gamma):
         check_block(pa, blk, label=f"edge {label}")
 
 
-@pytest.mark.parametrize("B", [8, 11, 12, 16, 19, 20])
+@pytest.mark.parametrize("B", [8, 11, 16, 20, 24, 29, 31, 32])
 def test_limb_width_invariance(pa, B):
     """The output is the same integer for every exact limb width (B is
-    representation only, the 2^B-ary words of Sec. 2.1)."""
+    representation only, the 2^B-ary words of Sec. 2.1); B changes L, N and
+    the transform tiling."""
     n, r = 1 << 20, (1 << 20) // 10
     st, g, k = defn.plan_shape(n, r)
     blk = synth.single_block(31, n, r, g, k)
     check_block(pa, blk, B=B, label=f"B={B}")
+
+
+@pytest.mark.parametrize("gamma,k", [(756839, 3), (1257787, 2), (3021377, 4)])
+def test_register_radix16_rows(pa, gamma, k):
+    """Shapes whose transform length (2^16 .. 2^19) selects the 4096-word
+    register radix-16 row pass, with ragged n."""
+    n = k * gamma - 12345
+    r = gamma // 7
+    st, g, kk = defn.plan_shape(n, r, gamma)
+    assert st == 0 and kk == k
+    blk = synth.single_block(gamma % 1000, n, r, g, kk)
+    check_block(pa, blk, label=f"radix16 rows gamma={gamma}")
 
 
 def test_config_one_mib_block(pa):

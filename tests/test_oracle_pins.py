@@ -127,6 +127,20 @@ def test_plan_errors():
         assert impl(100, 12, 13) == (0, 13, 8)
 
 
+# ---------------------------------------------------------------- Mersenne fold
+
+def test_mod_mersenne_matches_cpython_remainder():
+    """The fold identity of Sec. 3.1 against CPython's integer remainder."""
+    rng = random.Random(17)
+    for gamma in [2, 3, 5, 7, 13, 61, 89, 521, 4423]:
+        p = (1 << gamma) - 1
+        for v in [0, 1, p - 1, p, p + 1, 2 * p, p * p, (1 << (3 * gamma)) - 1]:
+            assert defn.mod_mersenne(v, gamma) == v % p
+        for _ in range(200):
+            v = rng.getrandbits(rng.randrange(1, 4 * gamma + 64))
+            assert defn.mod_mersenne(v, gamma) == v % p
+
+
 # ---------------------------------------------------------------- products
 
 @pytest.mark.parametrize("nw", [1, 2, 3, 31, 32, 33, 63, 64, 65, 127, 500, 1031, 4099])
