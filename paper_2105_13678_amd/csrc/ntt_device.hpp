@@ -134,9 +134,21 @@ __device__ __forceinline__ uint32_t swz(uint32_t i) {
     return i ^ (v | (v << 3));
 }
 
+// Swizzle of a tile of 2^cnt_lg interleaved transforms (cnt_lg > 0): bits
+// [cnt_lg + 3, cnt_lg + 3 + w) are XORed into bits [cnt_lg, cnt_lg + w),
+// w = 6 - cnt_lg, so that the last radix-8 step (a wave covers all columns
+// of 64 / 2^cnt_lg consecutive 8-row blocks) touches 64 distinct banks.
+// Triangular in the bit order, hence a bijection on any 2^n-word tile.
+__device__ __forceinline__ uint32_t tile_swz(uint32_t i, uint32_t cnt_lg) {
+    if (cnt_lg == 0) return swz(i);
+    if (cnt_lg >= 6) return i;
+    const uint32_t w = 6 - cnt_lg;
+    return i ^ (((i >> (cnt_lg + 3)) & ((1u << w) - 1)) << cnt_lg);
+}
+
 // ---------------------------------------------------------------- tile steps
 // A tile holds 2^cnt_lg interleaved transforms of length 2^lg: element
-// (index, q) lives at buf[swz((index << cnt_lg) + q)].
+// (index, q) lives at buf[tile_swz((index << cnt_lg) + q, cnt_lg)].
 //
 // Forward step with radix R at sub-length M = 2^lgM (decimation in
 // frequency): for each block b and n1 < M' = M/R, the R values
@@ -156,14 +168,14 @@ __device__ __forceinline__ void fwd_task(uint32_t *buf, uint32_t task, uint32_t 
     const uint32_t base = ((rest >> lgMp) << lgM) + n1;
     uint32_t v[R];
 #pragma unroll
-    for (int j = 0; j < R; ++j) v[j] = buf[swz(((base + ((uint32_t)j << lgMp)) << cnt_lg) + q)];
+    for (int j = 0; j < R; ++j) v[j] = buf[tile_swz(((base + ((uint32_t)j << lgMp)) << cnt_lg) + q, cnt_lg)];
     dft_fwd<R>(v, M);
     if (TW) {
 #pragma unroll
         for (int s = 1; s < R; ++s) v[s] = mmul(v[s], tw[(n1 * brev_small(s, LR)) << (lg - lgM)], M);
     }
 #pragma unroll
-    for (int j = 0; j < R; ++j) buf[swz(((base + ((uint32_t)j << lgMp)) << cnt_lg) + q)] = v[j];
+    for (int j = 0; j < R; ++j) buf[tile_swz(((base + ((uint32_t)j << lgMp)) << cnt_lg) + q, cnt_lg)] = v[j];
 }
 
 // Inverse of fwd_task: multiply slot s by omega_M^-(n1*k2), inverse R-point
@@ -179,14 +191,14 @@ __device__ __forceinline__ void inv_task(uint32_t *buf, uint32_t task, uint32_t 
     const uint32_t base = ((rest >> lgMp) << lgM) + n1;
     uint32_t v[R];
 #pragma unroll
-    for (int j = 0; j < R; ++j) v[j] = buf[swz(((base + ((uint32_t)j << lgMp)) << cnt_lg) + q)];
+    for (int j = 0; j < R; ++j) v[j] = buf[tile_swz(((base + ((uint32_t)j << lgMp)) << cnt_lg) + q, cnt_lg)];
     if (TW) {
 #pragma unroll
         for (int s = 1; s < R; ++s) v[s] = mmul(v[s], twi[(n1 * brev_small(s, LR)) << (lg - lgM)], M);
     }
     dft_inv<R>(v, M);
 #pragma unroll
-    for (int j = 0; j < R; ++j) buf[swz(((base + ((uint32_t)j << lgMp)) << cnt_lg) + q)] = v[j];
+    for (int j = 0; j < R; ++j) buf[tile_swz(((base + ((uint32_t)j << lgMp)) << cnt_lg) + q, cnt_lg)] = v[j];
 }
 
 template <int R, bool TW>
@@ -205,6 +217,29 @@ __device__ __forceinline__ void inv_step(uint32_t *buf, uint32_t lg, uint32_t lg
     const uint32_t ntask = (1u << (lg - Lg<R>::v)) << cnt_lg;
     for (uint32_t t = tid; t < ntask; t += nt) inv_task<R, TW>(buf, t, lg, lgM, cnt_lg, twi, M);
     __syncthreads();
+}
+
+// Sub-length of the last (twiddle-free) step of a length-2^lg transform:
+// radix 8 at 2^3 when 3 divides lg, else radix 2 at 2^1 or radix 4 at 2^2.
+__device__ __forceinline__ uint32_t last_lgM(uint32_t lg) {
+    const uint32_t r = lg % 3;
+    return r == 0 ? 3u : r;
+}
+
+// Forward radix-8 steps with twiddles from sub-length 2^from_lgM down to
+// 2^(last_lgM(lg) + 3), i.e. everything between a first and a last step.
+__device__ __forceinline__ void fwd_middle_steps(uint32_t *buf, uint32_t lg, uint32_t from_lgM, uint32_t cnt_lg,
+                                                 const uint32_t *__restrict__ tw, const PrimeConst &M,
+                                                 uint32_t tid, uint32_t nt) {
+    for (uint32_t lgM = from_lgM; lgM > last_lgM(lg); lgM -= 3) fwd_step<8, true>(buf, lg, lgM, cnt_lg, tw, M, tid, nt);
+}
+
+// Inverse radix-8 steps with twiddles from sub-length 2^(last_lgM(lg) + 3) up
+// to 2^to_lgM.
+__device__ __forceinline__ void inv_middle_steps(uint32_t *buf, uint32_t lg, uint32_t to_lgM, uint32_t cnt_lg,
+                                                 const uint32_t *__restrict__ twi, const PrimeConst &M,
+                                                 uint32_t tid, uint32_t nt) {
+    for (uint32_t lgM = last_lgM(lg) + 3; lgM <= to_lgM; lgM += 3) inv_step<8, true>(buf, lg, lgM, cnt_lg, twi, M, tid, nt);
 }
 
 // Forward steps of a length-2^lg transform from sub-length 2^first_lgM down:

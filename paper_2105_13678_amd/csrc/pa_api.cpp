@@ -154,10 +154,14 @@ pa_status derive(const pa_params *prm, pa_plan *p, Layout *lay) {
         m2 = (m + 1) / 2;
     p->m2 = m2;
     p->m1 = m - m2;
-    uint32_t c_lg = 6;
+    // forward column tiles of 16 columns (64-byte row segments, 32 KiB of
+    // LDS at 2^9 rows); the single-array inverse pass uses 8 columns for more
+    // workgroups
+    uint32_t c_lg = 4;
     if (c_lg > p->m2) c_lg = p->m2;
     if (p->m1 + c_lg > kMaxLdsLog2) c_lg = kMaxLdsLog2 - p->m1;
     p->c_lg = c_lg;
+    p->ci_lg = c_lg < 3 ? c_lg : 3;
     p->s_top = (uint32_t)(gamma - (uint64_t)B * (L - 1));
     p->e_fold = (uint32_t)((uint64_t)B * L - gamma);
     const uint64_t Q = (96 + B - 1) / B, Q2 = (96 + p->e_fold + B - 1) / B;

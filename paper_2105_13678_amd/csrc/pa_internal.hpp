@@ -85,6 +85,7 @@ struct pa_plan {
     uint64_t key_words, out_words;
     uint32_t B;
     uint32_t m, m1, m2, c_lg;   // N = 2^m = 2^m1 (column length) * 2^m2 (row length); 2^c_lg columns per tile
+    uint32_t ci_lg;             // columns per tile of the inverse column pass
     uint32_t s_top;             // bits in the top limb: gamma - B*(L-1), in [1, B]
     uint32_t e_fold;            // B*L - gamma, in [0, B)
     uint64_t M1;                // digit count of the folded sum before reduction

@@ -170,12 +170,69 @@ struct ColFwdArgs {
     PrimeSet P;
 };
 
+// 32 bits of a word array starting at bit `pos` (a funnel shift of two
+// 32-bit words); bits at positions >= lim read as 0.  w32 holds nw32 words
+// and covers bit lim - 1.
+__device__ __forceinline__ uint32_t limb32(const uint32_t *__restrict__ w32, uint64_t nw32, uint64_t lim,
+                                           uint64_t pos) {
+    if (pos >= lim) return 0u;
+    const uint64_t q = pos >> 5;
+    const uint32_t sh = (uint32_t)(pos & 31);
+    const uint32_t lo = w32[q];
+    const uint32_t hi = (sh != 0 && q + 1 < nw32) ? w32[q + 1] : 0u;
+    uint32_t v = __builtin_amdgcn_alignbit(hi, lo, sh);  // ({hi, lo} >> sh)[31:0]
+    const uint64_t rem = lim - pos;
+    if (rem < 32) v &= (1u << rem) - 1u;
+    return v;
+}
+
+// Limb j (B bits) of array `arr` of the column pass, or 0 past the last limb.
+__device__ __forceinline__ uint32_t unpack_limb(const ColFwdArgs &A, uint32_t arr, uint64_t j) {
+    if (j >= A.L) return 0u;
+    if (A.mode == 0) {
+        if (arr < A.k) {
+            const uint64_t base = (uint64_t)arr * A.gamma;
+            const uint64_t lim = min(A.n, base + A.gamma);
+            if (A.B == 32) return limb32((const uint32_t *)A.key, 2 * ((A.n + 63) >> 6), lim, base + 32 * j);
+            return bits_at(A.key, lim, base + j * A.B, A.B);
+        }
+        const uint64_t *src = A.a + (uint64_t)(arr - A.k) * A.W;
+        if (A.B == 32) return limb32((const uint32_t *)src, 2 * A.W, A.gamma, 32 * j);
+        return bits_at(src, A.gamma, j * A.B, A.B);
+    }
+    if (arr == 0) return A.ylimbs[j];
+    if (A.B == 32) return limb32((const uint32_t *)A.b, 2 * A.W, A.gamma, 32 * j);
+    return bits_at(A.b, A.gamma, j * A.B, A.B);
+}
+
+// Last (twiddle-free) forward step of a column tile, LDS -> global memory:
+// radix R at sub-length R; slot s of block b is row b*R + s.
+template <int R>
+__device__ __forceinline__ void col_last_fwd(const uint32_t *buf, uint32_t lg, uint32_t c_lg, uint32_t m2,
+                                             uint64_t c0, uint32_t *__restrict__ out, const PrimeConst &M,
+                                             uint32_t tid, uint32_t nt) {
+    constexpr int LR = Lg<R>::v;
+    const uint32_t cmask = (1u << c_lg) - 1;
+    const uint32_t ntask = (1u << (lg - LR)) << c_lg;
+    for (uint32_t task = tid; task < ntask; task += nt) {
+        const uint32_t q = task & cmask;
+        const uint32_t row0 = (task >> c_lg) << LR;
+        uint32_t v[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) v[j] = buf[tile_swz(((row0 + j) << c_lg) + q, c_lg)];
+        dft_fwd<R>(v, M);
+#pragma unroll
+        for (int j = 0; j < R; ++j) out[((uint64_t)(row0 + j) << m2) + c0 + q] = v[j];
+    }
+}
+
 // Unpack + forward column pass.  blockIdx.y selects the array: in MMH mode
 // arrays 0..k-1 are the key chunks x_i and k..2k-1 the seed chunks a_i; in
 // MH mode array 0 is y and array 1 is b.  blockIdx.z is the prime.  Limb j of
 // a chunk is its bits [jB, jB+B); limbs j >= L are the zero padding.  Since
 // N >= 2L - 1, every limb index >= N/2 is padding, so rows n1 >= N1/2 of the
 // column tile are zero and the first radix-8 step unpacks only four inputs.
+// The last step writes its rows straight to global memory.
 __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
     uint32_t *lds = lds_dyn;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -189,6 +246,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
     const uint32_t full = (uint32_t)((1ull << A.B) - 1), topv = (uint32_t)((1ull << A.s_top) - 1);
     const uint32_t lgMp = lg - 3;
     const uint32_t ntask = (1u << lgMp) << c_lg;
+    uint32_t *out = A.X + ((uint64_t)arr * NPRIMES + pq) * A.N;
     bool not_ones = false;
     for (uint32_t task = threadIdx.x; task < ntask; task += blockDim.x) {
         const uint32_t q = task & cmask;
@@ -198,30 +256,21 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
         for (int jj = 0; jj < 4; ++jj) {
             const uint64_t row = n1 + ((uint64_t)jj << lgMp);
             const uint64_t j = (row << A.m2) + c0 + q;  // limb index
-            uint32_t x = 0;
-            if (j < A.L) {
-                if (A.mode == 0) {
-                    if (arr < A.k) {
-                        const uint64_t base = (uint64_t)arr * A.gamma;
-                        const uint64_t lim = min(A.n, base + A.gamma);
-                        x = bits_at(A.key, lim, base + j * A.B, A.B);
-                        not_ones |= (x != (j == A.L - 1 ? topv : full));
-                    } else {
-                        x = bits_at(A.a + (uint64_t)(arr - A.k) * A.W, A.gamma, j * A.B, A.B);
-                    }
-                } else {
-                    x = (arr == 0) ? A.ylimbs[j] : bits_at(A.b, A.gamma, j * A.B, A.B);
-                }
-            }
+            const uint32_t x = unpack_limb(A, arr, j);
+            if (is_key && j < A.L) not_ones |= (x != (j == A.L - 1 ? topv : full));
             v[jj] = mmul(x, M.one, M);  // x mod p
         }
         dft_fwd_lowhalf<8>(v, M);
         if (lg > 3) {
 #pragma unroll
             for (int s = 1; s < 8; ++s) v[s] = mmul(v[s], tw[n1 * brev_small(s, 3)], M);
-        }
 #pragma unroll
-        for (int jj = 0; jj < 8; ++jj) lds[swz(((n1 + ((uint32_t)jj << lgMp)) << c_lg) + q)] = v[jj];
+            for (int jj = 0; jj < 8; ++jj)
+                lds[tile_swz(((n1 + ((uint32_t)jj << lgMp)) << c_lg) + q, c_lg)] = v[jj];
+        } else {
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) out[((uint64_t)jj << A.m2) + c0 + q] = v[jj];
+        }
     }
     if (is_key && pq == 0) {
         int any = __syncthreads_or(not_ones);
@@ -229,11 +278,15 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
     } else {
         __syncthreads();
     }
-    fwd_steps_from(lds, lg, lg - 3, c_lg, tw, M, threadIdx.x, blockDim.x);
-    uint32_t *out = A.X + ((uint64_t)arr * NPRIMES + pq) * A.N;
-    const uint32_t cnt = (1u << lg) << c_lg;
-    for (uint32_t e = threadIdx.x; e < cnt; e += blockDim.x)
-        out[((uint64_t)(e >> c_lg) << A.m2) + c0 + (e & cmask)] = lds[swz(e)];
+    if (lg == 3) return;
+    fwd_middle_steps(lds, lg, lg - 3, c_lg, tw, M, threadIdx.x, blockDim.x);
+    const uint32_t ll = last_lgM(lg);
+    if (ll == 3)
+        col_last_fwd<8>(lds, lg, c_lg, A.m2, c0, out, M, threadIdx.x, blockDim.x);
+    else if (ll == 2)
+        col_last_fwd<4>(lds, lg, c_lg, A.m2, c0, out, M, threadIdx.x, blockDim.x);
+    else
+        col_last_fwd<2>(lds, lg, c_lg, A.m2, c0, out, M, threadIdx.x, blockDim.x);
 }
 
 struct RowArgs {
@@ -493,7 +546,30 @@ struct ColInvArgs {
     PrimeSet P;
 };
 
-// Inverse column pass (bit-reversed rows in, natural rows out), in place.
+// First inverse step of a column tile, global memory -> LDS: the inverse of
+// the last forward step (radix R at sub-length R, no twiddles).
+template <int R>
+__device__ __forceinline__ void col_first_inv(const uint32_t *__restrict__ cc, uint32_t *buf, uint32_t lg,
+                                              uint32_t c_lg, uint32_t m2, uint64_t c0, const PrimeConst &M,
+                                              uint32_t tid, uint32_t nt) {
+    constexpr int LR = Lg<R>::v;
+    const uint32_t cmask = (1u << c_lg) - 1;
+    const uint32_t ntask = (1u << (lg - LR)) << c_lg;
+    for (uint32_t task = tid; task < ntask; task += nt) {
+        const uint32_t q = task & cmask;
+        const uint32_t row0 = (task >> c_lg) << LR;
+        uint32_t v[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) v[j] = cc[((uint64_t)(row0 + j) << m2) + c0 + q];
+        dft_inv<R>(v, M);
+#pragma unroll
+        for (int j = 0; j < R; ++j) buf[tile_swz(((row0 + j) << c_lg) + q, c_lg)] = v[j];
+    }
+    __syncthreads();
+}
+
+// Inverse column pass (bit-reversed rows in, natural rows out), in place:
+// first step straight from global memory, last step straight back.
 __global__ __launch_bounds__(COL_THREADS) void k_col_inv(ColInvArgs A) {
     uint32_t *lds = lds_dyn;
     const uint32_t pq = blockIdx.y;
@@ -503,24 +579,37 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_inv(ColInvArgs A) {
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t c_lg = A.c_lg, lg = A.m1;
     const uint32_t cmask = (1u << c_lg) - 1;
-    const uint32_t cnt = (1u << lg) << c_lg;
     const uint64_t c0 = (uint64_t)tile << c_lg;
-    for (uint32_t e = threadIdx.x; e < cnt; e += blockDim.x)
-        lds[swz(e)] = cc[((uint64_t)(e >> c_lg) << A.m2) + c0 + (e & cmask)];
-    __syncthreads();
-    inv_steps_to(lds, lg, lg - 3, c_lg, twi, M, threadIdx.x, blockDim.x);
     const uint32_t lgMp = lg - 3;
     const uint32_t ntask = (1u << lgMp) << c_lg;
+    if (lg == 3) {
+        for (uint32_t task = threadIdx.x; task < ntask; task += blockDim.x) {
+            const uint32_t q = task & cmask;
+            uint32_t v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = cc[((uint64_t)j << A.m2) + c0 + q];
+            dft_inv<8>(v, M);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) cc[((uint64_t)j << A.m2) + c0 + q] = v[j];
+        }
+        return;
+    }
+    const uint32_t ll = last_lgM(lg);
+    if (ll == 3)
+        col_first_inv<8>(cc, lds, lg, c_lg, A.m2, c0, M, threadIdx.x, blockDim.x);
+    else if (ll == 2)
+        col_first_inv<4>(cc, lds, lg, c_lg, A.m2, c0, M, threadIdx.x, blockDim.x);
+    else
+        col_first_inv<2>(cc, lds, lg, c_lg, A.m2, c0, M, threadIdx.x, blockDim.x);
+    inv_middle_steps(lds, lg, lg - 3, c_lg, twi, M, threadIdx.x, blockDim.x);
     for (uint32_t task = threadIdx.x; task < ntask; task += blockDim.x) {
         const uint32_t q = task & cmask;
         const uint32_t n1 = task >> c_lg;
         uint32_t v[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = lds[swz(((n1 + ((uint32_t)j << lgMp)) << c_lg) + q)];
-        if (lg > 3) {
+        for (int j = 0; j < 8; ++j) v[j] = lds[tile_swz(((n1 + ((uint32_t)j << lgMp)) << c_lg) + q, c_lg)];
 #pragma unroll
-            for (int s = 1; s < 8; ++s) v[s] = mmul(v[s], twi[n1 * brev_small(s, 3)], M);
-        }
+        for (int s = 1; s < 8; ++s) v[s] = mmul(v[s], twi[n1 * brev_small(s, 3)], M);
         dft_inv<8>(v, M);
 #pragma unroll
         for (int j = 0; j < 8; ++j) cc[((uint64_t)(n1 + ((uint32_t)j << lgMp)) << A.m2) + c0 + q] = v[j];
@@ -965,7 +1054,7 @@ static ColInvArgs colinv_args(pa_plan *p) {
     ci.N = p->N;
     ci.m1 = p->m1;
     ci.m2 = p->m2;
-    ci.c_lg = p->c_lg;
+    ci.c_lg = p->ci_lg;
     ci.twi = p->tw1i;
     ci.P = p->primes;
     return ci;
@@ -990,7 +1079,8 @@ hipError_t launch_mmh(pa_plan *p, const uint64_t *key, const uint64_t *a, hipStr
 
     ColInvArgs ci = colinv_args(p);
     phase_mark(p, PA_PH_MMH_COLINV, true, st);
-    hipLaunchKernelGGL(k_col_inv, dim3(ncol_tiles, NPRIMES), dim3(COL_THREADS), col_lds, st, ci);
+    hipLaunchKernelGGL(k_col_inv, dim3(1u << (p->m2 - p->ci_lg), NPRIMES), dim3(COL_THREADS),
+                       ((size_t)4 << p->m1) << p->ci_lg, st, ci);
     phase_mark(p, PA_PH_MMH_COLINV, false, st);
     return hipGetLastError();
 }
@@ -1030,7 +1120,8 @@ hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, hipStream
 
     ColInvArgs ci = colinv_args(p);
     phase_mark(p, PA_PH_MH_COLINV, true, st);
-    hipLaunchKernelGGL(k_col_inv, dim3(ncol_tiles, NPRIMES), dim3(COL_THREADS), col_lds, st, ci);
+    hipLaunchKernelGGL(k_col_inv, dim3(1u << (p->m2 - p->ci_lg), NPRIMES), dim3(COL_THREADS),
+                       ((size_t)4 << p->m1) << p->ci_lg, st, ci);
     phase_mark(p, PA_PH_MH_COLINV, false, st);
 
     const uint32_t Q = (96 + p->B - 1) / p->B;
