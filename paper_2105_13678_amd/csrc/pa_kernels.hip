@@ -65,6 +65,21 @@ __device__ __forceinline__ uint32_t bits_at(const uint64_t *__restrict__ src, ui
     return (uint32_t)(v & ((1ull << w) - 1));
 }
 
+// Buffer resource over `words` 32-bit words at `base`: untyped 32-bit data
+// format (third descriptor dword 0x00020000 on gfx9-family parts); accesses
+// past the end read 0 and are not written.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const uint32_t *base, uint32_t words) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, (int)(words * 4u), 0x00020000);
+}
+
+__device__ __forceinline__ uint32_t bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+}
+
+__device__ __forceinline__ void bstore(uint32_t v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, 0);
+}
+
 // 64 bits of a B-bit limb array starting at bit `pos`; bits >= nbits read as 0.
 __device__ __forceinline__ uint64_t limbs_get64(const uint32_t *__restrict__ limbs, uint32_t B,
                                                 uint64_t nbits, uint64_t pos) {
@@ -289,6 +304,88 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
         col_last_fwd<2>(lds, lg, c_lg, A.m2, c0, out, M, threadIdx.x, blockDim.x);
 }
 
+// ---- 512-row column tiles (N1 = 2^9), 16 columns: compile-time shape -------
+// Three radix-8 steps; task index tau = t + 256 u (u < 4) in every step:
+//   step A (sub-length 512, stride 64): q = tau & 15, n1 = tau >> 4, rows
+//          n1 + 64 j; unpacked from global memory (rows >= 256 are padding);
+//   step B (sub-length 64, stride 8): q = tau & 15, n1 = (tau >> 4) & 7,
+//          block b = tau >> 7, rows 64 b + n1 + 8 j;
+//   step C (sub-length 8): q = tau & 15, block b = tau >> 4, rows 8 b + j,
+//          written straight to global memory.
+// LDS element (row, q) lives at tile_swz(16 row + q, 4); the swizzle is
+// XOR-linear, so each task swizzles its base once and XORs constant offsets.
+
+constexpr uint32_t C9_LG = 9, C9_CLG = 4;
+
+__device__ __forceinline__ constexpr uint32_t swz_c9(uint32_t i) { return i ^ (((i >> 7) & 3u) << 4); }
+
+__global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
+    uint32_t *lds = lds_dyn;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t arr = blockIdx.y, pq = blockIdx.z;
+    const PrimeConst M = A.P.c[pq];
+    const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.tw + ((uint64_t)pq << C9_LG), 1u << C9_LG);
+    const uint64_t c0 = (uint64_t)tile << C9_CLG;
+    const bool is_key = (A.mode == 0) && arr < A.k;
+    const uint32_t full = (uint32_t)((1ull << A.B) - 1), topv = (uint32_t)((1ull << A.s_top) - 1);
+    uint32_t *out = A.X + ((uint64_t)arr * NPRIMES + pq) * A.N;
+    const uint32_t t = threadIdx.x;
+    bool not_ones = false;
+#pragma unroll 1
+    for (uint32_t u = 0; u < 4; ++u) {  // step A
+        const uint32_t tau = t + 256u * u;
+        const uint32_t q = tau & 15u, n1 = tau >> 4;
+        uint32_t v[8];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const uint64_t j = ((uint64_t)(n1 + 64u * jj) << A.m2) + c0 + q;  // limb index
+            const uint32_t x = unpack_limb(A, arr, j);
+            if (is_key && j < A.L) not_ones |= (x != (j == A.L - 1 ? topv : full));
+            v[jj] = mmul(x, M.one, M);  // x mod p
+        }
+        dft_fwd_lowhalf<8>(v, M);
+#pragma unroll
+        for (int s = 1; s < 8; ++s) v[s] = mmul(v[s], bload(rtw, (n1 * brev_small(s, 3)) << 2, 0), M);
+        const uint32_t sb = swz_c9(tau);
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) lds[sb ^ (1024u * jj)] = v[jj];
+    }
+    if (is_key && pq == 0) {
+        int any = __syncthreads_or(not_ones);
+        if (any && t == 0) A.notones[arr] = 1u;
+    } else {
+        __syncthreads();
+    }
+#pragma unroll 1
+    for (uint32_t u = 0; u < 4; ++u) {  // step B
+        const uint32_t tau = t + 256u * u;
+        const uint32_t q = tau & 15u, n1 = (tau >> 4) & 7u, b = tau >> 7;
+        const uint32_t sb = swz_c9(1024u * b + 16u * n1 + q);
+        uint32_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = lds[sb ^ swz_c9(128u * j)];
+        dft_fwd<8>(v, M);
+#pragma unroll
+        for (int s = 1; s < 8; ++s) v[s] = mmul(v[s], bload(rtw, (n1 * brev_small(s, 3)) << 5, 0), M);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) lds[sb ^ swz_c9(128u * j)] = v[j];
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (uint32_t u = 0; u < 4; ++u) {  // step C
+        const uint32_t tau = t + 256u * u;
+        const uint32_t q = tau & 15u, b = tau >> 4;
+        const uint32_t sb = swz_c9(128u * b + q);
+        uint32_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = lds[sb ^ (16u * j)];
+        dft_fwd<8>(v, M);
+        uint32_t *o = out + ((uint64_t)(8u * b) << A.m2) + c0 + q;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[(uint64_t)j << A.m2] = v[j];
+    }
+}
+
 struct RowArgs {
     const uint32_t *X;
     uint64_t N, npairs, pair_stride, a_off;  // in words
@@ -418,21 +515,6 @@ __device__ __forceinline__ constexpr uint32_t swz_r16(uint32_t i) {
     return i ^ (((i >> 4) & 1u) * 11u) ^ (((i >> 5) & 1u) * 5u) ^ (((i >> 6) & 1u) * 28u) ^
            (((i >> 7) & 1u) * 13u) ^ (((i >> 8) & 1u) * 29u) ^ (((i >> 9) & 1u) * 60u) ^
            (((i >> 10) & 1u) * 25u) ^ (((i >> 11) & 1u) * 43u);
-}
-
-// Buffer resource over `words` 32-bit words at `base`: untyped 32-bit data
-// format (third descriptor dword 0x00020000 on gfx9-family parts); accesses
-// past the end read 0 and are not written.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const uint32_t *base, uint32_t words) {
-    return __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, (int)(words * 4u), 0x00020000);
-}
-
-__device__ __forceinline__ uint32_t bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
-}
-
-__device__ __forceinline__ void bstore(uint32_t v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, 0);
 }
 
 __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
@@ -1024,6 +1106,15 @@ static ColFwdArgs col_args(pa_plan *p, uint32_t mode) {
     return cf;
 }
 
+static void launch_col_fwd(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, hipStream_t st) {
+    const unsigned ncol_tiles = 1u << (p->m2 - p->c_lg);
+    const size_t col_lds = ((size_t)4 << p->m1) << p->c_lg;
+    if (p->m1 == C9_LG && p->c_lg == C9_CLG)
+        hipLaunchKernelGGL(k_col9_fwd, dim3(ncol_tiles, narrays, NPRIMES), dim3(COL_THREADS), col_lds, st, cf);
+    else
+        hipLaunchKernelGGL(k_col_fwd, dim3(ncol_tiles, narrays, NPRIMES), dim3(COL_THREADS), col_lds, st, cf);
+}
+
 static RowArgs row_args(pa_plan *p, uint64_t npairs, uint64_t a_off) {
     RowArgs ra;
     ra.X = p->X;
@@ -1061,14 +1152,11 @@ static ColInvArgs colinv_args(pa_plan *p) {
 }
 
 hipError_t launch_mmh(pa_plan *p, const uint64_t *key, const uint64_t *a, hipStream_t st) {
-    const unsigned ncol_tiles = 1u << (p->m2 - p->c_lg);
-    const size_t col_lds = ((size_t)4 << p->m1) << p->c_lg;
     ColFwdArgs cf = col_args(p, 0);
     cf.key = key;
     cf.a = a;
     phase_mark(p, PA_PH_MMH_COL, true, st);
-    hipLaunchKernelGGL(k_col_fwd, dim3(ncol_tiles, (unsigned)(2 * p->k), NPRIMES), dim3(COL_THREADS), col_lds, st,
-                       cf);
+    launch_col_fwd(p, cf, (unsigned)(2 * p->k), st);
     phase_mark(p, PA_PH_MMH_COL, false, st);
     hipLaunchKernelGGL(k_status, dim3(1), dim3(256), 0, st, p->notones, p->k, p->status);
 
@@ -1104,13 +1192,11 @@ hipError_t launch_fold(pa_plan *p, hipStream_t st) {
 }
 
 hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, hipStream_t st) {
-    const unsigned ncol_tiles = 1u << (p->m2 - p->c_lg);
-    const size_t col_lds = ((size_t)4 << p->m1) << p->c_lg;
     ColFwdArgs cf = col_args(p, 1);
     cf.b = b;
     cf.ylimbs = p->y;
     phase_mark(p, PA_PH_MH_COL, true, st);
-    hipLaunchKernelGGL(k_col_fwd, dim3(ncol_tiles, 2u, NPRIMES), dim3(COL_THREADS), col_lds, st, cf);
+    launch_col_fwd(p, cf, 2u, st);
     phase_mark(p, PA_PH_MH_COL, false, st);
 
     RowArgs ra = row_args(p, 1, (uint64_t)NPRIMES * p->N);

@@ -120,6 +120,18 @@ def test_register_radix16_rows(pa, gamma, k):
     check_block(pa, blk, label=f"radix16 rows gamma={gamma}")
 
 
+def test_two_to_the_21_transform_two_chunks(pa):
+    """A 2^21-point transform (the shape of the 2.6e8-bit block) with k = 2
+    and a ragged tail: exercises the fixed-shape 512-row column pass and the
+    multiply-accumulate over two pairs."""
+    gamma = 20996011
+    n, r = 2 * gamma - 777, 2_000_001
+    st, g, k = defn.plan_shape(n, r, gamma)
+    assert st == 0 and k == 2
+    blk = synth.single_block(21, n, r, g, k)
+    check_block(pa, blk, label="N=2^21 k=2")
+
+
 def test_config_one_mib_block(pa):
     n, r = 1 << 20, (1 << 20) // 10
     st, g, k = defn.plan_shape(n, r)
