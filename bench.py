@@ -11,14 +11,15 @@ synchronisations.  The metric is input Mbit/s = n * steps / seconds.
 
 Prints one JSON line.  Extra objects: `roofline` for the dominant kernel
 (duration from HIP events recorded by the library on the same stream during
-the timed region) and `cpu_baseline` (the CPU oracle on a bounded sample).
+the timed region; HBM bytes per launch from the committed rocprofv3 counter
+summary when it was taken on the current sources, else null) and
+`cpu_baseline` (the CPU oracle on a bounded sample).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
 import argparse
-import ctypes
 import hashlib
 import json
 import math
@@ -34,8 +35,6 @@ sys.path.insert(0, ROOT)
 N_BITS = 260_000_000
 R_BITS = 26_000_000
 SEED = 2
-PHASES = ["prologue", "mmh_col", "mmh_row", "mmh_colinv", "fold", "mh_col", "mh_row", "mh_colinv",
-          "mh_carry", "finish"]
 
 # MI355X published peaks and unit counts
 HBM_PEAK_GBS = 8000.0
@@ -60,6 +59,18 @@ def ntt_work(info):
         "mh_row": P * 3 * half * m2,
         "mh_colinv": P * half * m1,
     }
+
+
+def kernel_name(phase, info):
+    """Symbol (as profilers print it) of the kernel a transform phase launches."""
+    stage = 0 if phase.startswith("mmh") else 1
+    if phase.endswith("_row"):
+        base = "k_row16" if info["log2N2"] == 12 else "k_row"
+    elif phase.endswith("_colinv"):
+        base = "k_col_inv"
+    else:
+        base = "k_col9_fwd" if info["log2N1"] == 9 and info["log2N2"] >= 4 else "k_col_fwd"
+    return f"{base}<{stage}>"
 
 
 # Peak butterfly rate of the VALU for this arithmetic: a radix-2 butterfly
@@ -118,7 +129,6 @@ def main():
     import torch
     import paper_2105_13678_amd as pa
     from paper_2105_13678_amd import synth
-    from paper_2105_13678_amd.binding import lib
 
     st, info = pa.plan_query(N_BITS, R_BITS)
     assert st == 0, st
@@ -133,16 +143,22 @@ def main():
     d_status = torch.zeros(max(1, K + Wm), dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream(dev)
 
+    # warmup: the first step untimed and unprofiled, the rest with every
+    # phase timed (per-phase breakdown; picks the dominant transform kernel)
     for i in range(Wm):
+        if i == 1:
+            plan.set_profiling("all")
         plan.hash_async(key, a, b, c, out, d_status[i:i + 1])
     torch.cuda.synchronize()
-    log("[bench] warmup done")
+    phases = plan.read_profile() if Wm > 1 else {}
+    plan.set_profiling([])
+    log("[bench] warmup done; per-phase ms/step: " + json.dumps({p: round(v, 4) for p, v in phases.items()}))
+    work = ntt_work(info)
+    dom = max(work, key=lambda p: phases.get(p, 0.0)) if phases else "mmh_row"
 
-    L = lib()
-    L.pa_plan_set_profiling.argtypes = [ctypes.c_void_p, ctypes.c_int]
-    L.pa_plan_read_profile.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
-                                       ctypes.POINTER(ctypes.c_uint64)]
-    L.pa_plan_set_profiling(plan._h, 1)
+    # timed region: K steps back to back; only the dominant kernel's phase
+    # carries an event pair (its duration for the roofline)
+    plan.set_profiling([dom])
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -154,13 +170,9 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1)
-    L.pa_plan_set_profiling(plan._h, 0)
-    ph_ms = (ctypes.c_double * 10)()
-    ph_n = (ctypes.c_uint64 * 10)()
-    L.pa_plan_read_profile(plan._h, ph_ms, ph_n)
-    phases = {PHASES[i]: (ph_ms[i] / ph_n[i] if ph_n[i] else None) for i in range(10)}
-    log("[bench] timed region %.3f ms (%d steps), wall %.3f s" % (ms, K, wall))
-    log("[bench] per-phase ms/step: " + json.dumps({p: round(v, 4) for p, v in phases.items() if v}))
+    dom_ms = plan.read_profile()[dom]
+    plan.set_profiling([])
+    log("[bench] timed region %.3f ms (%d steps), wall %.3f s; %s %.4f ms/launch" % (ms, K, wall, dom, dom_ms))
 
     statuses = d_status.cpu().numpy()
     assert (statuses == 0).all(), statuses
@@ -174,19 +186,20 @@ def main():
             verified = digest == gold["out_sha256"]
 
     value = N_BITS * K / (ms / 1e3) / 1e6
-    # roofline of the dominant NTT kernel (ALU bound: 64-bit modular butterflies)
-    work = ntt_work(info)
-    dom = max(work, key=lambda p: phases.get(p) or 0.0)
-    dom_ms = phases[dom]
+    # roofline of the dominant transform kernel (ALU bound: modular butterflies)
     bfly_per_s = work[dom] / (dom_ms / 1e3)
+    kname = kernel_name(dom, info)
+    from paper_2105_13678_amd.profile_summary import read_traffic
+    tr = read_traffic(os.path.join(ROOT, "profiles", "hbm_bytes_n2p6e8.md"), kname)
     roof = {
-        "kernel": {"mmh_row": "k_row (MMH)", "mmh_col": "k_col_fwd (MMH)"}.get(dom, dom),
+        "kernel": kname,
         "bound": "alu",
         "achieved": round(bfly_per_s / 1e9, 1),
         "peak": round(PEAK_BFLY_PER_S / 1e9, 1),
         "unit": "Gbutterfly/s",
         "frac": round(bfly_per_s / PEAK_BFLY_PER_S, 3),
-        "traffic": None,
+        "traffic": (tr[0] + tr[1]) if tr else None,
+        "traffic_read_write": list(tr) if tr else None,
         "duration_ms": round(dom_ms, 4),
         "butterflies_per_launch": work[dom],
     }
@@ -208,7 +221,7 @@ def main():
                    "n": N_BITS, "r": R_BITS, "gamma": g, "k": k, "B": info["B"], "N": info["N"],
                    "parallelism": "single GPU"},
         "verified_vs_oracle_digest": verified,
-        "phase_ms": {p: (round(v, 4) if v else None) for p, v in phases.items()},
+        "phase_ms_warmup": {p: round(v, 4) for p, v in phases.items()},
         "roofline": roof,
     }
     if args.calib_copy_mib:

@@ -150,9 +150,13 @@ typedef enum pa_phase {
     PA_PH_COUNT = 10
 } pa_phase;
 
-/* Turn per-phase timing on (1) or off (0).  While on, every hash call on
- * this plan records a HIP event pair around each phase on the call's stream. */
-pa_status pa_plan_set_profiling(pa_plan *plan, int enable);
+/* Per-phase timing.  phase_mask bit p (1u << PA_PH_...) set: every hash call
+ * on this plan records a HIP event pair around phase p on the call's stream;
+ * 0 turns timing off, PA_PROFILE_ALL times every phase.  Each pair costs a
+ * few microseconds of stream time, so a throughput measurement should time
+ * only the phase it reports. */
+#define PA_PROFILE_ALL ((1u << PA_PH_COUNT) - 1u)
+pa_status pa_plan_set_profiling(pa_plan *plan, uint32_t phase_mask);
 
 /* Wait for every recorded event, then return the summed milliseconds and the
  * number of recorded calls per phase since the previous read (arrays of

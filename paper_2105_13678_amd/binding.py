@@ -20,6 +20,11 @@ PA_ERR_ARG, PA_ERR_NO_GAMMA, PA_ERR_GAMMA, PA_ERR_INEXACT = -1, -2, -3, -4
 PA_ERR_SEED_B_EVEN, PA_ERR_SEED_RANGE, PA_ERR_NOMEM, PA_ERR_DEVICE = -5, -6, -7, -8
 PA_ERR_BUSY, PA_ERR_LIMIT = -9, -10
 
+# pa_phase, in order
+PHASES = ["prologue", "mmh_col", "mmh_row", "mmh_colinv", "fold", "mh_col", "mh_row", "mh_colinv",
+          "mh_carry", "finish"]
+PROFILE_ALL = (1 << len(PHASES)) - 1
+
 
 class PAError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
@@ -71,6 +76,10 @@ def lib():
         L.pa_hash_async.restype = ctypes.c_int
         L.pa_hash_stages.argtypes = [_VP] * 9
         L.pa_hash_stages.restype = ctypes.c_int
+        L.pa_plan_set_profiling.argtypes = [_VP, ctypes.c_uint32]
+        L.pa_plan_set_profiling.restype = ctypes.c_int
+        L.pa_plan_read_profile.argtypes = [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)]
+        L.pa_plan_read_profile.restype = ctypes.c_int
         L.pa_decode_status.argtypes = [ctypes.c_uint32]
         L.pa_decode_status.restype = ctypes.c_int
         L.pa_status_string.argtypes = [ctypes.c_int]
@@ -169,6 +178,23 @@ class Plan:
                 _dev_ptr(b, i["seed_words"], "b", self.device),
                 _dev_ptr(c, i["seed_words"], "c", self.device),
                 _dev_ptr(out, i["out_words"], "out", self.device))
+
+    def set_profiling(self, phases):
+        """Time the given phases (names from PHASES, or "all"; empty = off)."""
+        mask = PROFILE_ALL if phases == "all" else sum(1 << PHASES.index(p) for p in phases)
+        st = lib().pa_plan_set_profiling(self._h, mask)
+        if st != PA_OK:
+            raise PAError(st, "pa_plan_set_profiling")
+
+    def read_profile(self) -> dict:
+        """{phase: mean ms per call} over the calls since the last read (phases
+        not recorded are omitted); waits for the recorded events."""
+        ms = (ctypes.c_double * len(PHASES))()
+        n = (ctypes.c_uint64 * len(PHASES))()
+        st = lib().pa_plan_read_profile(self._h, ms, n)
+        if st != PA_OK:
+            raise PAError(st, "pa_plan_read_profile")
+        return {PHASES[i]: ms[i] / n[i] for i in range(len(PHASES)) if n[i]}
 
     def new_out(self):
         import torch

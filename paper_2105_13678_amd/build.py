@@ -22,6 +22,18 @@ ARCH = "gfx950"
 
 SOURCES = ["pa_api.cpp", "pa_kernels.hip"]
 HEADERS = ["pa_internal.hpp", "ntt_device.hpp"]
+DEVICE_SOURCES = ["pa_kernels.hip", "ntt_device.hpp"]
+
+
+def source_digest() -> str:
+    """sha256 over the device-code sources of libpa: identifies the kernels
+    a set of profiler counters was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in DEVICE_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
 
 
 def hipcc() -> str:

@@ -319,12 +319,13 @@ void pa_plan_destroy(pa_plan *p) {
     delete p;
 }
 
-pa_status pa_plan_set_profiling(pa_plan *p, int enable) {
+pa_status pa_plan_set_profiling(pa_plan *p, uint32_t phase_mask) {
     if (!p) return PA_ERR_ARG;
     if (!p->pending) p->pending = new (std::nothrow) std::vector<pa_plan::EvPair>();
     if (!p->event_pool) p->event_pool = new (std::nothrow) std::vector<hipEvent_t>();
     if (!p->pending || !p->event_pool) return PA_ERR_NOMEM;
-    p->profiling = enable ? 1 : 0;
+    if (phase_mask & ~PA_PROFILE_ALL) return PA_ERR_ARG;
+    p->profiling = phase_mask;
     return PA_OK;
 }
 
@@ -412,7 +413,7 @@ pa_status pa_hash_stages(pa_plan *p, const uint64_t *key, const uint64_t *a, con
 namespace pa {
 
 void phase_mark(pa_plan *p, int phase, bool begin, hipStream_t st) {
-    if (!p->profiling) return;
+    if (!(p->profiling >> phase & 1u)) return;
     hipEvent_t ev;
     if (!p->event_pool->empty()) {
         ev = p->event_pool->back();

@@ -116,7 +116,7 @@ struct pa_plan {
     uint32_t *h_status;     // pinned host word
 
     // phase profiling (pa_plan_set_profiling)
-    int profiling;
+    uint32_t profiling;  // phase mask
     struct EvPair {
         int phase;
         hipEvent_t a, b;

@@ -39,6 +39,11 @@ constexpr int ROW_EPT = 16;  // row elements per thread
 constexpr int ROW_MAX_THREADS = 1024;
 constexpr int PREFIX_THREADS = 1024;
 
+// The transform kernels are instantiated once per hash stage (the MMH sum of
+// eq. 2 and the MH product of eq. 4) so that profiles report the two stages'
+// launches under separate names; the code is identical.
+constexpr int STAGE_MMH = 0, STAGE_MH = 1;
+
 __device__ __forceinline__ uint32_t bitrev(uint32_t x, uint32_t bits) {
     return bits ? (__brev(x) >> (32 - bits)) : 0u;
 }
@@ -248,6 +253,7 @@ __device__ __forceinline__ void col_last_fwd(const uint32_t *buf, uint32_t lg, u
 // N >= 2L - 1, every limb index >= N/2 is padding, so rows n1 >= N1/2 of the
 // column tile are zero and the first radix-8 step unpacks only four inputs.
 // The last step writes its rows straight to global memory.
+template <int Stage>
 __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
     uint32_t *lds = lds_dyn;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -319,6 +325,7 @@ constexpr uint32_t C9_LG = 9, C9_CLG = 4;
 
 __device__ __forceinline__ constexpr uint32_t swz_c9(uint32_t i) { return i ^ (((i >> 7) & 3u) << 4); }
 
+template <int Stage>
 __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
     uint32_t *lds = lds_dyn;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -447,6 +454,7 @@ __device__ __forceinline__ void row_last_inv_step(const uint32_t *buf, uint32_t 
 // of both rows, accumulate their pointwise (Montgomery) product; then the
 // inverse transform of the accumulated row, inverse twiddle, store.
 // blockIdx.y is the prime.
+template <int Stage>
 __global__ __launch_bounds__(ROW_MAX_THREADS) void k_row(RowArgs A) {
     uint32_t *lds = lds_dyn;
     const uint32_t pq = blockIdx.y;
@@ -517,6 +525,7 @@ __device__ __forceinline__ constexpr uint32_t swz_r16(uint32_t i) {
            (((i >> 10) & 1u) * 25u) ^ (((i >> 11) & 1u) * 43u);
 }
 
+template <int Stage>
 __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
     uint32_t *bx = lds_dyn;
     uint32_t *ba = lds_dyn + R16_LEN;
@@ -652,6 +661,7 @@ __device__ __forceinline__ void col_first_inv(const uint32_t *__restrict__ cc, u
 
 // Inverse column pass (bit-reversed rows in, natural rows out), in place:
 // first step straight from global memory, last step straight back.
+template <int Stage>
 __global__ __launch_bounds__(COL_THREADS) void k_col_inv(ColInvArgs A) {
     uint32_t *lds = lds_dyn;
     const uint32_t pq = blockIdx.y;
@@ -1106,13 +1116,14 @@ static ColFwdArgs col_args(pa_plan *p, uint32_t mode) {
     return cf;
 }
 
+template <int Stage>
 static void launch_col_fwd(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, hipStream_t st) {
     const unsigned ncol_tiles = 1u << (p->m2 - p->c_lg);
     const size_t col_lds = ((size_t)4 << p->m1) << p->c_lg;
     if (p->m1 == C9_LG && p->c_lg == C9_CLG)
-        hipLaunchKernelGGL(k_col9_fwd, dim3(ncol_tiles, narrays, NPRIMES), dim3(COL_THREADS), col_lds, st, cf);
+        hipLaunchKernelGGL(k_col9_fwd<Stage>, dim3(ncol_tiles, narrays, NPRIMES), dim3(COL_THREADS), col_lds, st, cf);
     else
-        hipLaunchKernelGGL(k_col_fwd, dim3(ncol_tiles, narrays, NPRIMES), dim3(COL_THREADS), col_lds, st, cf);
+        hipLaunchKernelGGL(k_col_fwd<Stage>, dim3(ncol_tiles, narrays, NPRIMES), dim3(COL_THREADS), col_lds, st, cf);
 }
 
 static RowArgs row_args(pa_plan *p, uint64_t npairs, uint64_t a_off) {
@@ -1132,11 +1143,12 @@ static RowArgs row_args(pa_plan *p, uint64_t npairs, uint64_t a_off) {
     return ra;
 }
 
+template <int Stage>
 static void launch_row(pa_plan *p, const RowArgs &ra, hipStream_t st) {
     if (p->m2 == 12)
-        hipLaunchKernelGGL(k_row16, dim3(1u << p->m1, NPRIMES), dim3(R16_THREADS), (size_t)8 * R16_LEN, st, ra);
+        hipLaunchKernelGGL(k_row16<Stage>, dim3(1u << p->m1, NPRIMES), dim3(R16_THREADS), (size_t)8 * R16_LEN, st, ra);
     else
-        hipLaunchKernelGGL(k_row, dim3(1u << p->m1, NPRIMES), dim3(row_threads(p)), (size_t)4 << p->m2, st, ra);
+        hipLaunchKernelGGL(k_row<Stage>, dim3(1u << p->m1, NPRIMES), dim3(row_threads(p)), (size_t)4 << p->m2, st, ra);
 }
 
 static ColInvArgs colinv_args(pa_plan *p) {
@@ -1156,18 +1168,18 @@ hipError_t launch_mmh(pa_plan *p, const uint64_t *key, const uint64_t *a, hipStr
     cf.key = key;
     cf.a = a;
     phase_mark(p, PA_PH_MMH_COL, true, st);
-    launch_col_fwd(p, cf, (unsigned)(2 * p->k), st);
+    launch_col_fwd<STAGE_MMH>(p, cf, (unsigned)(2 * p->k), st);
     phase_mark(p, PA_PH_MMH_COL, false, st);
     hipLaunchKernelGGL(k_status, dim3(1), dim3(256), 0, st, p->notones, p->k, p->status);
 
     RowArgs ra = row_args(p, p->k, p->k * NPRIMES * p->N);
     phase_mark(p, PA_PH_MMH_ROW, true, st);
-    launch_row(p, ra, st);
+    launch_row<STAGE_MMH>(p, ra, st);
     phase_mark(p, PA_PH_MMH_ROW, false, st);
 
     ColInvArgs ci = colinv_args(p);
     phase_mark(p, PA_PH_MMH_COLINV, true, st);
-    hipLaunchKernelGGL(k_col_inv, dim3(1u << (p->m2 - p->ci_lg), NPRIMES), dim3(COL_THREADS),
+    hipLaunchKernelGGL(k_col_inv<STAGE_MMH>, dim3(1u << (p->m2 - p->ci_lg), NPRIMES), dim3(COL_THREADS),
                        ((size_t)4 << p->m1) << p->ci_lg, st, ci);
     phase_mark(p, PA_PH_MMH_COLINV, false, st);
     return hipGetLastError();
@@ -1196,17 +1208,17 @@ hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, hipStream
     cf.b = b;
     cf.ylimbs = p->y;
     phase_mark(p, PA_PH_MH_COL, true, st);
-    launch_col_fwd(p, cf, 2u, st);
+    launch_col_fwd<STAGE_MH>(p, cf, 2u, st);
     phase_mark(p, PA_PH_MH_COL, false, st);
 
     RowArgs ra = row_args(p, 1, (uint64_t)NPRIMES * p->N);
     phase_mark(p, PA_PH_MH_ROW, true, st);
-    launch_row(p, ra, st);
+    launch_row<STAGE_MH>(p, ra, st);
     phase_mark(p, PA_PH_MH_ROW, false, st);
 
     ColInvArgs ci = colinv_args(p);
     phase_mark(p, PA_PH_MH_COLINV, true, st);
-    hipLaunchKernelGGL(k_col_inv, dim3(1u << (p->m2 - p->ci_lg), NPRIMES), dim3(COL_THREADS),
+    hipLaunchKernelGGL(k_col_inv<STAGE_MH>, dim3(1u << (p->m2 - p->ci_lg), NPRIMES), dim3(COL_THREADS),
                        ((size_t)4 << p->m1) << p->ci_lg, st, ci);
     phase_mark(p, PA_PH_MH_COLINV, false, st);
 
