@@ -190,39 +190,54 @@ struct ColFwdArgs {
     PrimeSet P;
 };
 
-// 32 bits of a word array starting at bit `pos` (a funnel shift of two
-// 32-bit words); bits at positions >= lim read as 0.  w32 holds nw32 words
-// and covers bit lim - 1.
-__device__ __forceinline__ uint32_t limb32(const uint32_t *__restrict__ w32, uint64_t nw32, uint64_t lim,
-                                           uint64_t pos) {
-    if (pos >= lim) return 0u;
-    const uint64_t q = pos >> 5;
-    const uint32_t sh = (uint32_t)(pos & 31);
-    const uint32_t lo = w32[q];
-    const uint32_t hi = (sh != 0 && q + 1 < nw32) ? w32[q + 1] : 0u;
-    uint32_t v = __builtin_amdgcn_alignbit(hi, lo, sh);  // ({hi, lo} >> sh)[31:0]
-    const uint64_t rem = lim - pos;
-    if (rem < 32) v &= (1u << rem) - 1u;
-    return v;
+// Source of the B-bit limbs of one column-pass array, uniform over a
+// workgroup.  Limb j is bits [sh0 + j*stride, +B) of the 32-bit word stream
+// behind `rs` (a buffer resource over exactly the words the array touches,
+// so reads past them return 0), masked to the array's first `cl` valid bits
+// (relative to sh0).  Key chunks and seeds are packed bit streams
+// (stride = B); the MMH output y is one limb per word (stride = 32).
+struct LimbSrc {
+    __amdgpu_buffer_rsrc_t rs;
+    uint32_t sh0, stride, B, bmask;
+    int32_t cl;
+};
+
+__device__ __forceinline__ LimbSrc limb_src(const ColFwdArgs &A, uint32_t arr) {
+    LimbSrc S;
+    S.B = A.B;
+    S.bmask = A.B >= 32 ? ~0u : (1u << A.B) - 1u;
+    S.stride = A.B;
+    S.sh0 = 0;
+    if (A.mode == 0 && arr < A.k) {
+        const uint64_t base = (uint64_t)arr * A.gamma;
+        const uint64_t lim = min(A.n, base + A.gamma);
+        S.sh0 = (uint32_t)(base & 31);
+        S.cl = (int32_t)(lim - base);
+        S.rs = rsrc_of((const uint32_t *)A.key + (base >> 5), (uint32_t)((S.sh0 + (lim - base) + 31) >> 5));
+    } else if (A.mode == 0) {
+        S.cl = (int32_t)A.gamma;
+        S.rs = rsrc_of((const uint32_t *)(A.a + (uint64_t)(arr - A.k) * A.W), (uint32_t)((A.gamma + 31) >> 5));
+    } else if (arr == 0) {
+        S.stride = 32;
+        S.cl = (int32_t)(32 * A.L);
+        S.rs = rsrc_of(A.ylimbs, (uint32_t)A.L);
+    } else {
+        S.cl = (int32_t)A.gamma;
+        S.rs = rsrc_of((const uint32_t *)A.b, (uint32_t)((A.gamma + 31) >> 5));
+    }
+    return S;
 }
 
-// Limb j (B bits) of array `arr` of the column pass, or 0 past the last limb.
-__device__ __forceinline__ uint32_t unpack_limb(const ColFwdArgs &A, uint32_t arr, uint64_t j) {
-    if (j >= A.L) return 0u;
-    if (A.mode == 0) {
-        if (arr < A.k) {
-            const uint64_t base = (uint64_t)arr * A.gamma;
-            const uint64_t lim = min(A.n, base + A.gamma);
-            if (A.B == 32) return limb32((const uint32_t *)A.key, 2 * ((A.n + 63) >> 6), lim, base + 32 * j);
-            return bits_at(A.key, lim, base + j * A.B, A.B);
-        }
-        const uint64_t *src = A.a + (uint64_t)(arr - A.k) * A.W;
-        if (A.B == 32) return limb32((const uint32_t *)src, 2 * A.W, A.gamma, 32 * j);
-        return bits_at(src, A.gamma, j * A.B, A.B);
-    }
-    if (arr == 0) return A.ylimbs[j];
-    if (A.B == 32) return limb32((const uint32_t *)A.b, 2 * A.W, A.gamma, 32 * j);
-    return bits_at(A.b, A.gamma, j * A.B, A.B);
+// Limb j of the array (0 past its valid bits).  j * stride < 2^30 because
+// j < N <= 2^25.
+__device__ __forceinline__ uint32_t limb_at(const LimbSrc &S, uint32_t j) {
+    const uint32_t pos = S.sh0 + j * S.stride;
+    const uint32_t off = (pos >> 5) * 4u;
+    const uint32_t lo = bload(S.rs, off, 0), hi = bload(S.rs, off + 4u, 0);
+    uint32_t v = __builtin_amdgcn_alignbit(hi, lo, pos & 31u) & S.bmask;  // ({hi, lo} >> sh)[31:0]
+    const int32_t rem = S.cl - (int32_t)(j * S.stride);
+    if (rem < (int32_t)S.B) v &= rem > 0 ? (1u << rem) - 1u : 0u;
+    return v;
 }
 
 // Last (twiddle-free) forward step of a column tile, LDS -> global memory:
@@ -268,6 +283,8 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
     const uint32_t lgMp = lg - 3;
     const uint32_t ntask = (1u << lgMp) << c_lg;
     uint32_t *out = A.X + ((uint64_t)arr * NPRIMES + pq) * A.N;
+    const LimbSrc S = limb_src(A, arr);
+    const uint32_t L = (uint32_t)A.L;
     bool not_ones = false;
     for (uint32_t task = threadIdx.x; task < ntask; task += blockDim.x) {
         const uint32_t q = task & cmask;
@@ -275,10 +292,10 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
         uint32_t v[8];
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
-            const uint64_t row = n1 + ((uint64_t)jj << lgMp);
-            const uint64_t j = (row << A.m2) + c0 + q;  // limb index
-            const uint32_t x = unpack_limb(A, arr, j);
-            if (is_key && j < A.L) not_ones |= (x != (j == A.L - 1 ? topv : full));
+            const uint32_t row = n1 + ((uint32_t)jj << lgMp);
+            const uint32_t j = (row << A.m2) + (uint32_t)c0 + q;  // limb index
+            const uint32_t x = limb_at(S, j);
+            if (is_key && j < L) not_ones |= (x != (j == L - 1 ? topv : full));
             v[jj] = mmul(x, M.one, M);  // x mod p
         }
         dft_fwd_lowhalf<8>(v, M);
@@ -337,6 +354,8 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
     const uint32_t full = (uint32_t)((1ull << A.B) - 1), topv = (uint32_t)((1ull << A.s_top) - 1);
     uint32_t *out = A.X + ((uint64_t)arr * NPRIMES + pq) * A.N;
     const uint32_t t = threadIdx.x;
+    const LimbSrc S = limb_src(A, arr);
+    const uint32_t L = (uint32_t)A.L;
     bool not_ones = false;
 #pragma unroll 1
     for (uint32_t u = 0; u < 4; ++u) {  // step A
@@ -345,9 +364,9 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
         uint32_t v[8];
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
-            const uint64_t j = ((uint64_t)(n1 + 64u * jj) << A.m2) + c0 + q;  // limb index
-            const uint32_t x = unpack_limb(A, arr, j);
-            if (is_key && j < A.L) not_ones |= (x != (j == A.L - 1 ? topv : full));
+            const uint32_t j = ((n1 + 64u * jj) << A.m2) + (uint32_t)c0 + q;  // limb index
+            const uint32_t x = limb_at(S, j);
+            if (is_key && j < L) not_ones |= (x != (j == L - 1 ? topv : full));
             v[jj] = mmul(x, M.one, M);  // x mod p
         }
         dft_fwd_lowhalf<8>(v, M);
