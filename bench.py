@@ -74,10 +74,12 @@ def kernel_name(phase, info):
 
 
 # Peak butterfly rate of the VALU for this arithmetic: a radix-2 butterfly
-# modulo a 31-bit prime is one modular addition (3 VALU instructions), one
-# subtraction (3) and one Montgomery product (5: v_mad_u64_u32, v_mul_lo_u32,
-# v_mad_u64_u32, v_sub_u32, v_min_u32), all full-rate on gfx950.
-BFLY_LANE_CYCLES = 11
+# on lazily reduced residues modulo a prime below 2^30 is a sum reduced to
+# [0, 2p) (v_add_u32, v_sub_u32, v_min_u32), a difference shifted by 2p (two
+# instructions) and a Montgomery product without final subtraction
+# (v_mad_u64_u32, v_mul_lo_u32, v_mad_u64_u32): eight full-rate VALU
+# instructions on gfx950.
+BFLY_LANE_CYCLES = 8
 PEAK_BFLY_PER_S = CUS * LANES_PER_CU * CLOCK_GHZ * 1e9 / BFLY_LANE_CYCLES
 
 
@@ -214,7 +216,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32 (exact integer NTTs mod three 31-bit primes, CRT to 96-bit coefficients)",
+        "dtype": "u32 (exact integer NTTs mod three 30-bit primes, CRT to 96-bit coefficients)",
         "data": "synthetic",
         "config": {"workload": f"single block n=2.6e8 r=n/10 (gamma={g}, k={k}, B={info['B']}, "
                                f"N=2^{info['log2N']}), splitmix64 seed 2",

@@ -83,21 +83,21 @@ typedef struct pa_plan_info {
     uint64_t a_words;       /* k * W                                        */
     uint64_t out_words;     /* ceil(r/64)                                   */
     uint64_t workspace_bytes; /* device memory owned by the plan            */
-    double exact_log2;      /* log2(k * L * (2^B - 1)^2); below log2(p0 p1 p2) = 90.69 */
+    double exact_log2;      /* log2(k * L * (2^B - 1)^2); below log2(p0 p1 p2) */
     uint32_t log2N1;        /* column-pass length 2^log2N1                  */
     uint32_t log2N2;        /* row-pass length 2^log2N2 (N = 2^(log2N1 + log2N2)) */
     uint32_t nprimes;       /* NTT primes per transform (3)                 */
-    uint32_t reserved;
+    uint32_t primes[3];     /* the NTT primes p0, p1, p2 of this length     */
 } pa_plan_info;
 
 typedef struct pa_plan pa_plan;
 
 /* Create a plan for one (n, r) shape on HIP device `hip_device`: derives
  * (gamma, k, B, L, N), checks that every convolution coefficient stays below
- * the product of the three NTT primes p0 = 15*2^27+1, p1 = 63*2^25+1,
- * p2 = 7*2^26+1 (PA_ERR_INEXACT otherwise), allocates the workspace and
- * builds the twiddle tables.  Supported range: k <= 4096 and N <= 2^25
- * (PA_ERR_LIMIT otherwise).  On success *out owns device memory until
+ * the product of the three NTT primes of length N (the three largest primes
+ * below 2^30 with N | p - 1; PA_ERR_INEXACT otherwise), allocates the
+ * workspace and builds the twiddle tables.  Supported range: k <= 4096 and
+ * N <= 2^24 (PA_ERR_LIMIT otherwise).  On success *out owns device memory until
  * pa_plan_destroy. */
 pa_status pa_plan_create(const pa_params *params, int hip_device, pa_plan **out);
 

@@ -44,10 +44,12 @@ class PlanInfo(ctypes.Structure):
                 ("seed_words", ctypes.c_uint64), ("a_words", ctypes.c_uint64),
                 ("out_words", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64),
                 ("exact_log2", ctypes.c_double), ("log2N1", ctypes.c_uint32),
-                ("log2N2", ctypes.c_uint32), ("nprimes", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("log2N2", ctypes.c_uint32), ("nprimes", ctypes.c_uint32), ("primes", ctypes.c_uint32 * 3)]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["primes"] = list(self.primes)
+        return d
 
 
 _lib = None

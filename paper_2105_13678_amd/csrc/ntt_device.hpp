@@ -1,12 +1,16 @@
 // Device building blocks of the number-theoretic transforms: Montgomery
-// arithmetic modulo three ~31-bit primes, radix-2/4/8 butterflies and the LDS
-// steps of a tile transform.
+// arithmetic modulo three primes below 2^30, radix-2/4/8/16 butterflies and
+// the LDS steps of a tile transform.
 //
-// Every prime p satisfies p < 2^31, so a + b < 2^32 for a, b < p, and the
-// Montgomery product (R = 2^32) of any a < 2^32 with b < p is exact in 64 bits
-// before its final conditional subtraction.  On gfx950 all 32x32-bit
-// multiplies (v_mad_u64_u32, v_mul_lo_u32) are full-rate VALU instructions;
-// a modular product costs five, an addition or subtraction three.
+// Lazy residues.  Because every prime satisfies 4p < 2^32, transform values
+// are kept only partially reduced: forward-transform values lie in [0, 2p),
+// inverse-transform values in [0, 4p).  The Montgomery product (R = 2^32) of
+// a and b with a*b < 2^32 p is (a*b + m*p) / 2^32 < 2p with m = (a*b)(-1/p)
+// mod 2^32: three full-rate VALU instructions on gfx950 (v_mad_u64_u32,
+// v_mul_lo_u32, v_mad_u64_u32), no final subtraction.  A radix-2 butterfly
+// is then eight instructions (sum and its reduction to [0, 2p): 3; the
+// difference shifted by 2p: 2; the product: 3).  Canonical values [0, p) are
+// produced only where a consumer needs them (the Chinese-remainder step).
 #pragma once
 
 #include "pa_internal.hpp"
@@ -14,17 +18,27 @@
 namespace pa {
 
 // ---------------------------------------------------------------- field ops
-// Values are canonical in [0, p).
 
-// a * b * 2^-32 mod p, for a < 2^32 and b < p.
-__device__ __forceinline__ uint32_t mmul(uint32_t a, uint32_t b, const PrimeConst &M) {
+// a * b * 2^-32 mod p, in [0, 2p); requires a * b < 2^32 p (e.g. a < 4p and
+// b < p, or a, b < 2p).
+__device__ __forceinline__ uint32_t mont(uint32_t a, uint32_t b, const PrimeConst &M) {
     const uint64_t t = (uint64_t)a * b;
     const uint32_t m = (uint32_t)t * M.pinv;
-    const uint64_t u = (uint64_t)m * M.p + t;  // divisible by 2^32, below 2^33 p <= 2^64
-    const uint32_t r = (uint32_t)(u >> 32);   // r < 2p
-    return min(r, r - M.p);
+    return (uint32_t)(((uint64_t)m * M.p + t) >> 32);  // t + m p < 2^33 p < 2^64, divisible by 2^32
 }
 
+// [0, 4p) -> [0, 2p), same residue
+__device__ __forceinline__ uint32_t red2(uint32_t x, const PrimeConst &M) { return min(x, x - M.p2); }
+
+// [0, 2p) -> [0, p), same residue
+__device__ __forceinline__ uint32_t canon(uint32_t x, const PrimeConst &M) { return min(x, x - M.p); }
+
+// canonical a * b * 2^-32 mod p, for a < 2^32 and b < p
+__device__ __forceinline__ uint32_t mmul(uint32_t a, uint32_t b, const PrimeConst &M) {
+    return canon(mont(a, b, M), M);
+}
+
+// canonical sum and difference of canonical values
 __device__ __forceinline__ uint32_t madd(uint32_t a, uint32_t b, const PrimeConst &M) {
     const uint32_t s = a + b;
     return min(s, s - M.p);
@@ -37,66 +51,89 @@ __device__ __forceinline__ uint32_t msub(uint32_t a, uint32_t b, const PrimeCons
 
 // ---------------------------------------------------------------- small DFTs
 // R-point DFTs (R = 2, 4, 8, 16) as log2(R) radix-2 stages in registers.
-// Forward (decimation in frequency): natural order in, output slot s holds
-// frequency bitrev(s).  The stage with half-size h multiplies the difference
-// at offset j by omega_{2h}^j = omega_16^(j*8/h) = M.w16[j*8/h].
-
-__device__ __forceinline__ void bfly(uint32_t &u, uint32_t &v, const PrimeConst &M) {
-    const uint32_t a = madd(u, v, M), b = msub(u, v, M);
-    u = a;
-    v = b;
+//
+// Forward (decimation in frequency), values in [0, 2p): natural order in,
+// output slot s holds frequency bitrev(s).  The stage with half-size h
+// multiplies the difference at offset j by omega_{2h}^j = M.w16[j*8/h].
+// With TW, output slot s (s >= 1) is also multiplied by tw[s] (a step
+// twiddle, canonical Montgomery form); the multiplication is fused into the
+// last stage, whose unreduced sum and difference (< 4p) go straight into the
+// product.  With LOWHALF the upper half of the input is known to be zero, so
+// the first stage is v[j + R/2] = v[j] * omega_R^j.
+template <int R, bool LOWHALF, bool TW>
+__device__ __forceinline__ void dft_fwd_x(uint32_t *v, const uint32_t *tw, const PrimeConst &M) {
+    static_assert(!LOWHALF || R >= 4, "the zero-upper-half form needs a second stage");
+    constexpr int H = R / 2;
+    if (LOWHALF) {
+#pragma unroll
+        for (int j = 0; j < H; ++j) v[j + H] = j ? mont(v[j], M.w16[j * (8 / H)], M) : v[j];
+    }
+#pragma unroll
+    for (int h = LOWHALF ? H / 2 : H; h >= 1; h >>= 1) {
+#pragma unroll
+        for (int blk = 0; blk < R; blk += 2 * h) {
+#pragma unroll
+            for (int j = 0; j < h; ++j) {
+                const uint32_t u = v[blk + j], x = v[blk + j + h];
+                const uint32_t sum = u + x;           // < 4p
+                const uint32_t dif = u + M.p2 - x;    // (0, 4p)
+                if (TW && h == 1) {
+                    v[blk] = blk ? mont(sum, tw[blk], M) : red2(sum, M);
+                    v[blk + 1] = mont(dif, tw[blk + 1], M);
+                } else {
+                    v[blk + j] = red2(sum, M);
+                    v[blk + j + h] = j ? mont(dif, M.w16[j * (8 / h)], M) : red2(dif, M);
+                }
+            }
+        }
+    }
 }
 
 template <int R>
 __device__ __forceinline__ void dft_fwd(uint32_t *v, const PrimeConst &M) {
-#pragma unroll
-    for (int h = R / 2; h >= 1; h >>= 1) {
-#pragma unroll
-        for (int blk = 0; blk < R; blk += 2 * h) {
-#pragma unroll
-            for (int j = 0; j < h; ++j) {
-                bfly(v[blk + j], v[blk + j + h], M);
-                if (j) v[blk + j + h] = mmul(v[blk + j + h], M.w16[j * (8 / h)], M);
-            }
-        }
-    }
+    dft_fwd_x<R, false, false>(v, nullptr, M);
 }
 
-// Forward DFT when the upper half of the input (v[R/2..R)) is known zero: the
-// first stage is v[j + R/2] = v[j] * omega_R^j.
 template <int R>
-__device__ __forceinline__ void dft_fwd_lowhalf(uint32_t *v, const PrimeConst &M) {
-    constexpr int H = R / 2;
-#pragma unroll
-    for (int j = 0; j < H; ++j) v[j + H] = j ? mmul(v[j], M.w16[j * (8 / H)], M) : v[j];
-#pragma unroll
-    for (int h = H / 2; h >= 1; h >>= 1) {
-#pragma unroll
-        for (int blk = 0; blk < R; blk += 2 * h) {
-#pragma unroll
-            for (int j = 0; j < h; ++j) {
-                bfly(v[blk + j], v[blk + j + h], M);
-                if (j) v[blk + j + h] = mmul(v[blk + j + h], M.w16[j * (8 / h)], M);
-            }
-        }
-    }
+__device__ __forceinline__ void dft_fwd_tw(uint32_t *v, const uint32_t *tw, const PrimeConst &M) {
+    dft_fwd_x<R, false, true>(v, tw, M);
 }
 
-// Inverse (times R): undoes the forward stages in reverse order with
-// omega^-1 (M.w16i); bit-reversed slots in, natural order out.
-template <int R>
-__device__ __forceinline__ void dft_inv(uint32_t *v, const PrimeConst &M) {
+// Inverse (times R), values in [0, 4p): undoes the forward stages in reverse
+// order with omega^-1 (M.w16i); bit-reversed slots in, natural order out.
+// With TW, input slot s (s >= 1) is first multiplied by tw[s], fused into the
+// first stage.
+template <int R, bool TW>
+__device__ __forceinline__ void dft_inv_x(uint32_t *v, const uint32_t *tw, const PrimeConst &M) {
 #pragma unroll
     for (int h = 1; h < R; h <<= 1) {
 #pragma unroll
         for (int blk = 0; blk < R; blk += 2 * h) {
 #pragma unroll
             for (int j = 0; j < h; ++j) {
-                if (j) v[blk + j + h] = mmul(v[blk + j + h], M.w16i[j * (8 / h)], M);
-                bfly(v[blk + j], v[blk + j + h], M);
+                uint32_t a, q;  // both < 2p
+                if (TW && h == 1) {
+                    a = blk ? mont(v[blk], tw[blk], M) : red2(v[blk], M);
+                    q = mont(v[blk + 1], tw[blk + 1], M);
+                } else {
+                    a = red2(v[blk + j], M);
+                    q = j ? mont(v[blk + j + h], M.w16i[j * (8 / h)], M) : red2(v[blk + j + h], M);
+                }
+                v[blk + j] = a + q;             // < 4p
+                v[blk + j + h] = a + M.p2 - q;  // (0, 4p)
             }
         }
     }
+}
+
+template <int R>
+__device__ __forceinline__ void dft_inv(uint32_t *v, const PrimeConst &M) {
+    dft_inv_x<R, false>(v, nullptr, M);
+}
+
+template <int R>
+__device__ __forceinline__ void dft_inv_tw(uint32_t *v, const uint32_t *tw, const PrimeConst &M) {
+    dft_inv_x<R, true>(v, tw, M);
 }
 
 template <int R>
@@ -151,7 +188,7 @@ __device__ __forceinline__ uint32_t tile_swz(uint32_t i, uint32_t cnt_lg) {
 // (index, q) lives at buf[tile_swz((index << cnt_lg) + q, cnt_lg)].
 //
 // Forward step with radix R at sub-length M = 2^lgM (decimation in
-// frequency): for each block b and n1 < M' = M/R, the R values
+// frequency, values in [0, 2p)): for each block b and n1 < M' = M/R, the R values
 // x[b*M + n1 + M'*n2] go through an R-point DFT; slot s (frequency
 // k2 = bitrev(s)) is multiplied by omega_M^(n1*k2) and stored back at
 // b*M + n1 + M'*s.  After all steps the transform is in bit-reversed order.
@@ -166,20 +203,21 @@ __device__ __forceinline__ void fwd_task(uint32_t *buf, uint32_t task, uint32_t 
     const uint32_t rest = task >> cnt_lg;
     const uint32_t n1 = rest & ((1u << lgMp) - 1);
     const uint32_t base = ((rest >> lgMp) << lgM) + n1;
-    uint32_t v[R];
+    uint32_t v[R], w[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) v[j] = buf[tile_swz(((base + ((uint32_t)j << lgMp)) << cnt_lg) + q, cnt_lg)];
-    dft_fwd<R>(v, M);
     if (TW) {
 #pragma unroll
-        for (int s = 1; s < R; ++s) v[s] = mmul(v[s], tw[(n1 * brev_small(s, LR)) << (lg - lgM)], M);
+        for (int s = 1; s < R; ++s) w[s] = tw[(n1 * brev_small(s, LR)) << (lg - lgM)];
     }
+    dft_fwd_x<R, false, TW>(v, w, M);
 #pragma unroll
     for (int j = 0; j < R; ++j) buf[tile_swz(((base + ((uint32_t)j << lgMp)) << cnt_lg) + q, cnt_lg)] = v[j];
 }
 
-// Inverse of fwd_task: multiply slot s by omega_M^-(n1*k2), inverse R-point
-// DFT, natural order back.  twi[e] = omega_len^-e.
+// Inverse of fwd_task (values in [0, 4p)): multiply slot s by
+// omega_M^-(n1*k2), inverse R-point DFT, natural order back.
+// twi[e] = omega_len^-e.
 template <int R, bool TW>
 __device__ __forceinline__ void inv_task(uint32_t *buf, uint32_t task, uint32_t lg, uint32_t lgM,
                                          uint32_t cnt_lg, const uint32_t *__restrict__ twi, const PrimeConst &M) {
@@ -189,14 +227,14 @@ __device__ __forceinline__ void inv_task(uint32_t *buf, uint32_t task, uint32_t 
     const uint32_t rest = task >> cnt_lg;
     const uint32_t n1 = rest & ((1u << lgMp) - 1);
     const uint32_t base = ((rest >> lgMp) << lgM) + n1;
-    uint32_t v[R];
+    uint32_t v[R], w[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) v[j] = buf[tile_swz(((base + ((uint32_t)j << lgMp)) << cnt_lg) + q, cnt_lg)];
     if (TW) {
 #pragma unroll
-        for (int s = 1; s < R; ++s) v[s] = mmul(v[s], twi[(n1 * brev_small(s, LR)) << (lg - lgM)], M);
+        for (int s = 1; s < R; ++s) w[s] = twi[(n1 * brev_small(s, LR)) << (lg - lgM)];
     }
-    dft_inv<R>(v, M);
+    dft_inv_x<R, TW>(v, w, M);
 #pragma unroll
     for (int j = 0; j < R; ++j) buf[tile_swz(((base + ((uint32_t)j << lgMp)) << cnt_lg) + q, cnt_lg)] = v[j];
 }

@@ -102,10 +102,25 @@ struct Layout {
     size_t oX, oC, oC96, oT, oS, oY, oU, oAgg, oTc, oRes, oNo, oSt, oSo, oT1, oT2, oW, total;
 };
 
+// Transform length exponent for L limbs: the smallest m >= kMinLog2N with
+// 2^m >= 2L - 1 (the full product of two L-limb numbers fits without wrap).
+uint32_t log2_len(uint64_t L) {
+    uint32_t m = kMinLog2N;
+    while ((1ull << m) < 2 * L - 1) ++m;
+    return m;
+}
+
+// Prime triple for transforms of length 2^m (m <= MAX_LOG2N).
+const pa::PrimeTriple &triple_for(uint32_t m) {
+    for (const pa::PrimeTriple &t : pa::PRIME_TRIPLES)
+        if (m <= t.max_lg) return t;
+    return pa::PRIME_TRIPLES[sizeof(pa::PRIME_TRIPLES) / sizeof(pa::PRIME_TRIPLES[0]) - 1];
+}
+
 // Exactness of the three-prime transform: every coefficient of the sum of the
 // k limb products is at most k*L*(2^B-1)^2 and must stay below p0*p1*p2.
-bool exact(uint64_t k, uint64_t L, uint32_t B) {
-    const unsigned __int128 P3 = (unsigned __int128)pa::PRIMES[0] * pa::PRIMES[1] * pa::PRIMES[2];
+bool exact(uint64_t k, uint64_t L, uint32_t B, const pa::PrimeTriple &T) {
+    const unsigned __int128 P3 = (unsigned __int128)T.p[0] * T.p[1] * T.p[2];
     const unsigned __int128 lim = ((unsigned __int128)1 << B) - 1;
     const unsigned __int128 kL = (unsigned __int128)k * L;
     // compare k*L*lim^2 < P3 without overflow (kL < 2^45, lim^2 < 2^64)
@@ -120,15 +135,23 @@ pa_status derive(const pa_params *prm, pa_plan *p, Layout *lay) {
     if (st != PA_OK) return st;
     if (k > kMaxK) return PA_ERR_LIMIT;
     if (B == 0) {
-        // widest limb that keeps the transform exact (fewest limbs)
+        // widest limb that keeps the transform exact (fewest limbs); a
+        // narrower limb only lengthens the transform, so a length beyond the
+        // limit at B = 32 is final
         B = 32;
-        while (B > 8 && !exact(k, (gamma + B - 1) / B, B)) --B;
+        if (log2_len((gamma + B - 1) / B) > pa::MAX_LOG2N) return PA_ERR_LIMIT;
+        while (B > 8) {
+            const uint64_t Lb = (gamma + B - 1) / B;
+            const uint32_t mb = log2_len(Lb);
+            if (mb <= pa::MAX_LOG2N && exact(k, Lb, B, triple_for(mb))) break;
+            --B;
+        }
     }
     const uint64_t L = (gamma + B - 1) / B;
-    if (!exact(k, L, B)) return PA_ERR_INEXACT;
-    uint32_t m = kMinLog2N;
-    while ((1ull << m) < 2 * L - 1) ++m;
+    const uint32_t m = log2_len(L);
     if (m > pa::MAX_LOG2N) return PA_ERR_LIMIT;
+    const pa::PrimeTriple &T = triple_for(m);
+    if (!exact(k, L, B, T)) return PA_ERR_INEXACT;
 
     p->n = prm->n;
     p->r = prm->r;
@@ -169,7 +192,7 @@ pa_status derive(const pa_params *prm, pa_plan *p, Layout *lay) {
     const uint64_t digits = (p->M1 > L ? p->M1 : L) + 1;
     p->ntiles_max = (digits + pa::SCAN_TILE - 1) / pa::SCAN_TILE + 1;
     p->exact_log2 = std::log2((double)k) + std::log2((double)L) + 2.0 * std::log2((double)((1ull << B) - 1));
-    pa::init_prime_constants(p);
+    pa::init_prime_constants(p, T.p);
 
     const size_t N = p->N, P3 = pa::NPRIMES;
     const size_t n1 = (size_t)1 << p->m1, n2 = (size_t)1 << p->m2;
@@ -296,6 +319,7 @@ pa_status pa_plan_get_info(const pa_plan *p, pa_plan_info *info) {
     info->log2N1 = p->m1;
     info->log2N2 = p->m2;
     info->nprimes = pa::NPRIMES;
+    for (int q = 0; q < pa::NPRIMES; ++q) info->primes[q] = p->primes.c[q].p;
     return PA_OK;
 }
 

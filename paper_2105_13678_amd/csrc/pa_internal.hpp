@@ -1,12 +1,12 @@
 // Internal declarations shared by the libpa translation units.
 //
 // Arithmetic: exact convolutions of B-bit limb sequences by number-theoretic
-// transforms modulo three primes below 2^31,
-//     p0 = 15*2^27 + 1, p1 = 63*2^25 + 1, p2 = 7*2^26 + 1,
-// whose product exceeds 2^90.69; power-of-two lengths up to 2^25 exist in all
-// three.  A gamma-bit number is cut into L = ceil(gamma/B) limbs (the paper's
-// 2^B-ary words); every coefficient of the sum of the k limb convolutions is
-// at most k*L*(2^B-1)^2, which the plan checks is below p0*p1*p2, so the
+// transforms of length 2^m modulo three primes below 2^30 (4p < 2^32 lets the
+// transforms keep residues only partially reduced).  The primes are the
+// three largest below 2^30 with 2^m | p - 1, from a fixed table per length.
+// A gamma-bit number is cut into L = ceil(gamma/B) limbs (the paper's 2^B-ary
+// words); every coefficient of the sum of the k limb convolutions is at most
+// k*L*(2^B-1)^2, which the plan checks is below p0*p1*p2, so the
 // Chinese-remainder reconstruction of the three transforms is the exact
 // integer coefficient.
 #pragma once
@@ -21,15 +21,28 @@
 namespace pa {
 
 constexpr int NPRIMES = 3;
-constexpr uint32_t PRIMES[NPRIMES] = {2013265921u, 2113929217u, 469762049u};
-constexpr uint32_t MAX_LOG2N = 25;  // largest power of two dividing every p - 1
+constexpr uint32_t MAX_LOG2N = 24;  // longest transform with three such primes
+
+// The three largest primes p < 2^30 with 2^max_lg | p - 1 (product 2^log2P),
+// for the transform lengths 2^m, m <= max_lg, not served by an earlier row.
+struct PrimeTriple {
+    uint32_t max_lg;
+    uint32_t p[NPRIMES];
+};
+constexpr PrimeTriple PRIME_TRIPLES[] = {
+    {20, {1053818881u, 1051721729u, 1045430273u}},  // 2^89.905
+    {21, {1012924417u, 1004535809u, 998244353u}},   // 2^89.715
+    {22, {998244353u, 985661441u, 943718401u}},     // 2^89.585
+    {23, {998244353u, 897581057u, 880803841u}},     // 2^89.351
+    {24, {754974721u, 469762049u, 167772161u}},     // 2^85.621
+};
 
 // Per-prime constants (Montgomery form x*2^32 mod p where noted).
 struct PrimeConst {
     uint32_t p;
     uint32_t pinv;   // -p^-1 mod 2^32
     uint32_t one;    // 2^32 mod p (1 in Montgomery form)
-    uint32_t pad;
+    uint32_t p2;     // 2p
     uint32_t w16[8];   // omega_16^j, j < 8, Montgomery form
     uint32_t w16i[8];  // omega_16^-j, j < 8, Montgomery form
 };
@@ -127,8 +140,9 @@ struct pa_plan {
 
 namespace pa {
 
-// Host-side constant setup (pa_kernels.hip).
-void init_prime_constants(pa_plan *p);
+// Host-side constant setup (pa_kernels.hip): Montgomery constants, small
+// roots and CRT constants for the three primes of the plan's triple.
+void init_prime_constants(pa_plan *p, const uint32_t primes[NPRIMES]);
 
 // Kernel launchers (pa_kernels.hip).  All enqueue on `st` and return the
 // first HIP error seen.

@@ -296,16 +296,18 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
             const uint32_t j = (row << A.m2) + (uint32_t)c0 + q;  // limb index
             const uint32_t x = limb_at(S, j);
             if (is_key && j < L) not_ones |= (x != (j == L - 1 ? topv : full));
-            v[jj] = mmul(x, M.one, M);  // x mod p
+            v[jj] = mont(x, M.one, M);  // x mod p, in [0, 2p)
         }
-        dft_fwd_lowhalf<8>(v, M);
         if (lg > 3) {
+            uint32_t w[8];
 #pragma unroll
-            for (int s = 1; s < 8; ++s) v[s] = mmul(v[s], tw[n1 * brev_small(s, 3)], M);
+            for (int s = 1; s < 8; ++s) w[s] = tw[n1 * brev_small(s, 3)];
+            dft_fwd_x<8, true, true>(v, w, M);
 #pragma unroll
             for (int jj = 0; jj < 8; ++jj)
                 lds[tile_swz(((n1 + ((uint32_t)jj << lgMp)) << c_lg) + q, c_lg)] = v[jj];
         } else {
+            dft_fwd_x<8, true, false>(v, nullptr, M);
 #pragma unroll
             for (int jj = 0; jj < 8; ++jj) out[((uint64_t)jj << A.m2) + c0 + q] = v[jj];
         }
@@ -367,11 +369,12 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
             const uint32_t j = ((n1 + 64u * jj) << A.m2) + (uint32_t)c0 + q;  // limb index
             const uint32_t x = limb_at(S, j);
             if (is_key && j < L) not_ones |= (x != (j == L - 1 ? topv : full));
-            v[jj] = mmul(x, M.one, M);  // x mod p
+            v[jj] = mont(x, M.one, M);  // x mod p, in [0, 2p)
         }
-        dft_fwd_lowhalf<8>(v, M);
+        uint32_t w[8];
 #pragma unroll
-        for (int s = 1; s < 8; ++s) v[s] = mmul(v[s], bload(rtw, (n1 * brev_small(s, 3)) << 2, 0), M);
+        for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 2, 0);
+        dft_fwd_x<8, true, true>(v, w, M);
         const uint32_t sb = swz_c9(tau);
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj) lds[sb ^ (1024u * jj)] = v[jj];
@@ -390,9 +393,10 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
         uint32_t v[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) v[j] = lds[sb ^ swz_c9(128u * j)];
-        dft_fwd<8>(v, M);
+        uint32_t w[8];
 #pragma unroll
-        for (int s = 1; s < 8; ++s) v[s] = mmul(v[s], bload(rtw, (n1 * brev_small(s, 3)) << 5, 0), M);
+        for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 5, 0);
+        dft_fwd_tw<8>(v, w, M);
 #pragma unroll
         for (int j = 0; j < 8; ++j) lds[sb ^ swz_c9(128u * j)] = v[j];
     }
@@ -432,12 +436,15 @@ __device__ __forceinline__ void row_first_step(const uint32_t *__restrict__ g, c
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const uint32_t e = n1 + ((uint32_t)j << lgMp);
-            v[j] = mmul(g[e], w[e], M);
+            v[j] = mont(g[e], w[e], M);
         }
-        dft_fwd<8>(v, M);
         if (lg > 3) {
+            uint32_t t8[8];
 #pragma unroll
-            for (int s = 1; s < 8; ++s) v[s] = mmul(v[s], tw[n1 * brev_small(s, 3)], M);
+            for (int s = 1; s < 8; ++s) t8[s] = tw[n1 * brev_small(s, 3)];
+            dft_fwd_tw<8>(v, t8, M);
+        } else {
+            dft_fwd<8>(v, M);
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) buf[swz(n1 + ((uint32_t)j << lgMp))] = v[j];
@@ -457,14 +464,17 @@ __device__ __forceinline__ void row_last_inv_step(const uint32_t *buf, uint32_t 
 #pragma unroll
         for (int j = 0; j < 8; ++j) v[j] = buf[swz(n1 + ((uint32_t)j << lgMp))];
         if (lg > 3) {
+            uint32_t t8[8];
 #pragma unroll
-            for (int s = 1; s < 8; ++s) v[s] = mmul(v[s], twi[n1 * brev_small(s, 3)], M);
+            for (int s = 1; s < 8; ++s) t8[s] = twi[n1 * brev_small(s, 3)];
+            dft_inv_tw<8>(v, t8, M);
+        } else {
+            dft_inv<8>(v, M);
         }
-        dft_inv<8>(v, M);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const uint32_t e = n1 + ((uint32_t)j << lgMp);
-            g[e] = mmul(v[j], w[e], M);
+            g[e] = mont(v[j], w[e], M);
         }
     }
 }
@@ -508,7 +518,7 @@ __global__ __launch_bounds__(ROW_MAX_THREADS) void k_row(RowArgs A) {
 #pragma unroll
         for (int q = 0; q < ROW_EPT; ++q) {
             uint32_t e = threadIdx.x + q * T;
-            if (e < N2) acc[q] = madd(acc[q], mmul(xr[q], lds[swz(e)], M), M);
+            if (e < N2) acc[q] = red2(acc[q] + mont(xr[q], lds[swz(e)], M), M);
         }
         __syncthreads();
     }
@@ -538,6 +548,15 @@ __global__ __launch_bounds__(ROW_MAX_THREADS) void k_row(RowArgs A) {
 constexpr int R16_THREADS = 256;
 constexpr uint32_t R16_LEN = 4096;
 
+// The value of v, made opaque to the optimiser: addresses derived from it
+// inside a loop are then recomputed there (one XOR or multiply each) instead
+// of being hoisted out of the loop as dozens of live registers.  Emits no
+// instruction.
+__device__ __forceinline__ uint32_t opaque(uint32_t v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 __device__ __forceinline__ constexpr uint32_t swz_r16(uint32_t i) {
     return i ^ (((i >> 4) & 1u) * 11u) ^ (((i >> 5) & 1u) * 5u) ^ (((i >> 6) & 1u) * 28u) ^
            (((i >> 7) & 1u) * 13u) ^ (((i >> 8) & 1u) * 29u) ^ (((i >> 9) & 1u) * 60u) ^
@@ -560,17 +579,16 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
     const uint32_t s2 = swz_r16(b2);                                 // b2 + 16 j
     const uint32_t s3 = swz_r16(16u * t);                            // 16 t + j
     const uint32_t n1b = t & 15u;
-    // loop-invariant step twiddles in registers: step 1 omega_4096^(t k2),
-    // step 2 omega_4096^(16 n1 k2)
+    // loop-invariant step twiddles, held in registers (re-reading them per
+    // use costs more than it saves: the step-1 reads are strided by up to
+    // 32 bytes per lane): step 1 omega_4096^(t k2), step 2 omega_4096^(16 n1 k2)
     const __amdgpu_buffer_rsrc_t rw = rsrc_of(A.Wf + pq * A.N + rbase, R16_LEN);
+    const __amdgpu_buffer_rsrc_t rt = rsrc_of(A.twf + (uint64_t)pq * R16_LEN, R16_LEN);
     uint32_t t1r[16], t2r[16];
-    {
-        const __amdgpu_buffer_rsrc_t rt = rsrc_of(A.twf + (uint64_t)pq * R16_LEN, R16_LEN);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            t1r[j] = bload(rt, t4 * brev_small(j, 4), 0);
-            t2r[j] = bload(rt, (n1b * brev_small(j, 4)) << 6, 0);
-        }
+    for (int j = 1; j < 16; ++j) {
+        t1r[j] = bload(rt, t4 * brev_small(j, 4), 0);
+        t2r[j] = bload(rt, (n1b * brev_small(j, 4)) << 6, 0);
     }
     uint32_t acc[16];
 #pragma unroll
@@ -584,41 +602,50 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
         for (int side = 0; side < 2; ++side) {
             const __amdgpu_buffer_rsrc_t rg = rsrc_of(side ? xrow + A.a_off : xrow, R16_LEN);
             uint32_t *buf = side ? ba : bx;
-            uint32_t v[16];
-            // step 1: from global, four-step twiddle, radix-16, step twiddles
+            const uint32_t t4l = opaque(t4), s1l = opaque(s1);
+            // step 1: from global, four-step twiddle, radix-16, step twiddles.
+            // All 32 loads are issued before the first use (the scheduling
+            // barrier keeps the compiler from interleaving load, wait and
+            // use, which would expose the memory latency 16 times).
+            uint32_t v[16], wv[16];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) v[j] = mmul(bload(rg, t4, 1024u * j), bload(rw, t4, 1024u * j), M);
-            dft_fwd<16>(v, M);
+            for (int j = 0; j < 16; ++j) {
+                v[j] = bload(rg, t4l, 1024u * j);
+                wv[j] = bload(rw, t4l, 1024u * j);
+            }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int s = 1; s < 16; ++s) v[s] = mmul(v[s], t1r[s], M);
+            for (int j = 0; j < 16; ++j) v[j] = mont(v[j], wv[j], M);
+            dft_fwd_tw<16>(v, t1r, M);
 #pragma unroll
-            for (int j = 0; j < 16; ++j) buf[s1 ^ swz_r16(256u * j)] = v[j];
+            for (int j = 0; j < 16; ++j) buf[s1l ^ swz_r16(256u * j)] = v[j];
         }
         __syncthreads();
 #pragma unroll 1
         for (int side = 0; side < 2; ++side) {
             uint32_t *buf = side ? ba : bx;
+            const uint32_t s2l = opaque(s2);
             uint32_t v[16];
             // step 2: radix-16 on stride 16, step twiddles
 #pragma unroll
-            for (int j = 0; j < 16; ++j) v[j] = buf[s2 ^ swz_r16(16u * j)];
-            dft_fwd<16>(v, M);
+            for (int j = 0; j < 16; ++j) v[j] = buf[s2l ^ swz_r16(16u * j)];
+            __builtin_amdgcn_sched_barrier(0);
+            dft_fwd_tw<16>(v, t2r, M);
 #pragma unroll
-            for (int s = 1; s < 16; ++s) v[s] = mmul(v[s], t2r[s], M);
-#pragma unroll
-            for (int j = 0; j < 16; ++j) buf[s2 ^ swz_r16(16u * j)] = v[j];
+            for (int j = 0; j < 16; ++j) buf[s2l ^ swz_r16(16u * j)] = v[j];
         }
         __syncthreads();
         // step 3: radix-16 on 16 consecutive values of each row, then multiply-accumulate
         uint32_t vx[16], va[16];
+        const uint32_t s3l = opaque(s3);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) vx[j] = bx[s3 ^ (uint32_t)j];
+        for (int j = 0; j < 16; ++j) vx[j] = bx[s3l ^ (uint32_t)j];
         dft_fwd<16>(vx, M);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) va[j] = ba[s3 ^ (uint32_t)j];
+        for (int j = 0; j < 16; ++j) va[j] = ba[s3l ^ (uint32_t)j];
         dft_fwd<16>(va, M);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) acc[j] = madd(acc[j], mmul(vx[j], va[j], M), M);
+        for (int j = 0; j < 16; ++j) acc[j] = red2(acc[j] + mont(vx[j], va[j], M), M);
         __syncthreads();  // the next pair overwrites the buffers
     }
 
@@ -631,21 +658,27 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
     uint32_t v[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = bx[s2 ^ swz_r16(16u * j)];
+    uint32_t w[16];
 #pragma unroll
-    for (int s = 1; s < 16; ++s) v[s] = mmul(v[s], bload(rti, (n1b * brev_small(s, 4)) << 6, 0), M);
-    dft_inv<16>(v, M);
+    for (int s = 1; s < 16; ++s) w[s] = bload(rti, (n1b * brev_small(s, 4)) << 6, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    dft_inv_tw<16>(v, w, M);
 #pragma unroll
     for (int j = 0; j < 16; ++j) bx[s2 ^ swz_r16(16u * j)] = v[j];
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = bx[s1 ^ swz_r16(256u * j)];
-#pragma unroll
-    for (int s = 1; s < 16; ++s) v[s] = mmul(v[s], bload(rti, t4 * brev_small(s, 4), 0), M);
-    dft_inv<16>(v, M);
     const __amdgpu_buffer_rsrc_t ro = rsrc_of(A.out + pq * A.N + rbase, R16_LEN);
     const __amdgpu_buffer_rsrc_t rwi = rsrc_of(A.Wi + pq * A.N + rbase, R16_LEN);
+    uint32_t wv[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) bstore(mmul(v[j], bload(rwi, t4, 1024u * j), M), ro, t4, 1024u * j);
+    for (int s = 1; s < 16; ++s) w[s] = bload(rti, t4 * brev_small(s, 4), 0);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) wv[j] = bload(rwi, t4, 1024u * j);
+    __builtin_amdgcn_sched_barrier(0);
+    dft_inv_tw<16>(v, w, M);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) bstore(mont(v[j], wv[j], M), ro, t4, 1024u * j);
 }
 
 struct ColInvArgs {
@@ -701,7 +734,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_inv(ColInvArgs A) {
             for (int j = 0; j < 8; ++j) v[j] = cc[((uint64_t)j << A.m2) + c0 + q];
             dft_inv<8>(v, M);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) cc[((uint64_t)j << A.m2) + c0 + q] = v[j];
+            for (int j = 0; j < 8; ++j) cc[((uint64_t)j << A.m2) + c0 + q] = canon(red2(v[j], M), M);
         }
         return;
     }
@@ -719,11 +752,14 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_inv(ColInvArgs A) {
         uint32_t v[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) v[j] = lds[tile_swz(((n1 + ((uint32_t)j << lgMp)) << c_lg) + q, c_lg)];
+        uint32_t w[8];
 #pragma unroll
-        for (int s = 1; s < 8; ++s) v[s] = mmul(v[s], twi[n1 * brev_small(s, 3)], M);
-        dft_inv<8>(v, M);
+        for (int s = 1; s < 8; ++s) w[s] = twi[n1 * brev_small(s, 3)];
+        dft_inv_tw<8>(v, w, M);
+        // canonical residues for the Chinese-remainder step
 #pragma unroll
-        for (int j = 0; j < 8; ++j) cc[((uint64_t)(n1 + ((uint32_t)j << lgMp)) << A.m2) + c0 + q] = v[j];
+        for (int j = 0; j < 8; ++j)
+            cc[((uint64_t)(n1 + ((uint32_t)j << lgMp)) << A.m2) + c0 + q] = canon(red2(v[j], M), M);
     }
 }
 
@@ -734,14 +770,14 @@ __global__ void k_crt(const uint32_t *__restrict__ cc, uint32_t *c96, uint64_t N
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= count) return;
     const PrimeConst &M1 = P.c[1], &M2 = P.c[2];
-    const uint32_t r0 = cc[j], r1 = cc[N + j], r2 = cc[2 * N + j];
-    // v1 = (r1 - r0) / p0 mod p1   (r0 < p0 < p1)
-    const uint32_t v1 = mmul(msub(r1, r0, M1), K.inv_p0_mod_p1, M1);
+    const uint32_t r0 = cc[j], r1 = cc[N + j], r2 = cc[2 * N + j];  // canonical residues
+    // v1 = (r1 - r0) / p0 mod p1
+    const uint32_t v1 = mmul(msub(r1, mmul(r0, M1.one, M1), M1), K.inv_p0_mod_p1, M1);
     // v2 = (r2 - r0 - v1 p0) / (p0 p1) mod p2
     const uint32_t r0m = mmul(r0, M2.one, M2);
     const uint32_t v1p0 = mmul(v1, K.p0_mod_p2, M2);
     const uint32_t v2 = mmul(msub(msub(r2, r0m, M2), v1p0, M2), K.inv_p0p1_mod_p2, M2);
-    const unsigned __int128 c = (unsigned __int128)r0 + (unsigned __int128)v1 * PRIMES[0] +
+    const unsigned __int128 c = (unsigned __int128)r0 + (unsigned __int128)v1 * P.c[0].p +
                                 (unsigned __int128)v2 * K.p0p1;
     c96[j] = (uint32_t)c;
     c96[N + j] = (uint32_t)(c >> 32);
@@ -1030,32 +1066,29 @@ uint32_t hmont(uint32_t a, uint32_t p) { return (uint32_t)(((uint64_t)(a % p) <<
 
 // Smallest generator of the multiplicative group mod p (p - 1 has prime
 // factors 2, 3, 5, 7 only for the primes used here).
-uint32_t hgen(uint32_t p) {
-    const uint32_t qs[4] = {2, 3, 5, 7};
-    for (uint32_t g = 2;; ++g) {
-        bool ok = true;
-        for (uint32_t q : qs)
-            if ((p - 1) % q == 0 && hpow(g, (p - 1) / q, p) == 1) ok = false;
-        if (ok) return g;
-    }
+// A primitive 2^log2n-th root of unity (2^log2n | p - 1): g^((p-1)/2^log2n)
+// for a quadratic non-residue g, whose order has the full power of two of
+// p - 1 (Euler's criterion: g^((p-1)/2) = -1).
+uint32_t root_of_unity(uint32_t p, uint32_t log2n) {
+    uint32_t g = 2;
+    while (hpow(g, (p - 1) / 2, p) != p - 1) ++g;
+    return hpow(g, (uint64_t)(p - 1) >> log2n, p);
 }
-
-uint32_t root_of_unity(uint32_t p, uint32_t log2n) { return hpow(hgen(p), (uint64_t)(p - 1) >> log2n, p); }
 
 }  // namespace
 
 namespace pa {
 
-void init_prime_constants(pa_plan *p) {
+void init_prime_constants(pa_plan *p, const uint32_t primes[NPRIMES]) {
     for (int q = 0; q < NPRIMES; ++q) {
-        const uint32_t pr = PRIMES[q];
+        const uint32_t pr = primes[q];
         PrimeConst &C = p->primes.c[q];
         C.p = pr;
         uint32_t inv = 1;  // p^-1 mod 2^32 by Newton iteration
         for (int i = 0; i < 5; ++i) inv *= 2u - pr * inv;
         C.pinv = 0u - inv;
         C.one = hmont(1, pr);
-        C.pad = 0;
+        C.p2 = 2u * pr;
         const uint32_t w16 = root_of_unity(pr, 4), w16i = hinv(w16, pr);
         uint32_t a = 1, b = 1;
         for (int j = 0; j < 8; ++j) {
@@ -1065,7 +1098,7 @@ void init_prime_constants(pa_plan *p) {
             b = hmul(b, w16i, pr);
         }
     }
-    const uint32_t p0 = PRIMES[0], p1 = PRIMES[1], p2 = PRIMES[2];
+    const uint32_t p0 = primes[0], p1 = primes[1], p2 = primes[2];
     p->crt.inv_p0_mod_p1 = hmont(hinv(p0 % p1, p1), p1);
     p->crt.p0_mod_p2 = hmont(p0 % p2, p2);
     p->crt.inv_p0p1_mod_p2 = hmont(hinv(hmul(p0 % p2, p1 % p2, p2), p2), p2);
@@ -1077,7 +1110,7 @@ hipError_t launch_twiddles(pa_plan *p, hipStream_t st) {
     const uint64_t N = p->N, n1 = 1ull << p->m1, n2 = 1ull << p->m2;
     TwArgs t1f, t1i, t2f, t2i, Ff, Fi;
     for (int q = 0; q < NPRIMES; ++q) {
-        const uint32_t pr = PRIMES[q];
+        const uint32_t pr = p->primes.c[q].p;
         const uint32_t w = root_of_unity(pr, p->m), wi = hinv(w, pr);
         const uint32_t R = (uint32_t)((1ull << 32) % pr);
         t1f.p[q] = t1i.p[q] = t2f.p[q] = t2i.p[q] = Ff.p[q] = Fi.p[q] = pr;
