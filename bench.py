@@ -113,6 +113,97 @@ def cpu_baseline(blk, info, budget_chunks=2):
     }
 
 
+BATCH_SEED, BATCH_COUNT = 3, 64
+
+
+def bench_batched(args):
+    """64 blocks of uneven size (splitmix64 seed 3: n log-uniform in
+    [2^22, 2^28], r/n uniform in [0.05, 0.30]; all shapes drawn first, then
+    each block's key and seeds) hashed by one pa_hash_batched call per step,
+    against the same blocks as 64 back-to-back pa_hash_async calls on one
+    stream (plans created beforehand).  Outputs of the two must agree."""
+    import torch
+    import paper_2105_13678_amd as pa
+    from paper_2105_13678_amd import synth
+
+    def shape(n, r):  # the library's own plan rule
+        st, info = pa.plan_query(n, r)
+        assert st == 0, (n, r, st)
+        return info["gamma"], info["k"]
+
+    blocks = synth.uneven_blocks(BATCH_SEED, BATCH_COUNT, shape, 22, 28)
+    total = sum(b.n for b in blocks)
+    log(f"[bench] batched: {len(blocks)} blocks, {total} key bits")
+    dev = torch.device("cuda", 0)
+    bufs = []
+    for b in blocks:
+        key, a, bb, c = (pa.to_device(x, dev) for x in (b.key, b.a, b.b, b.c))
+        bufs.append([b.n, b.r, key, a, bb, c, pa.BatchPlan.new_out(b.r, dev)])
+    K, Wm = args.steps, max(1, args.warmup)
+    stream = torch.cuda.current_stream(dev)
+    bp = pa.BatchPlan(len(blocks), total)
+    for _ in range(Wm):
+        st, per = bp.hash(bufs)
+        assert st == 0 and all(x == 0 for x in per), per
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(K):
+        bp.hash(bufs)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t0
+    ms_b = ev0.elapsed_time(ev1) / K
+    outs_b = [x[6].clone() for x in bufs]
+
+    plans = [pa.Plan(b.n, b.r) for b in blocks]
+    d_status = torch.zeros(len(blocks), dtype=torch.int32, device=dev)
+    for _ in range(Wm):
+        for i, (p, x) in enumerate(zip(plans, bufs)):
+            p.hash_async(*x[2:7], d_status[i:i + 1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(K):
+        for i, (p, x) in enumerate(zip(plans, bufs)):
+            p.hash_async(*x[2:7], d_status[i:i + 1])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    ms_s = ev0.elapsed_time(ev1) / K
+    same = all(torch.equal(o, x[6]) for o, x in zip(outs_b, bufs))
+    assert (d_status.cpu().numpy() == 0).all()
+    for p in plans:
+        p.close()
+    bp.close()
+    log(f"[bench] batched {ms_b:.3f} ms/call (wall {wall_b / K * 1e3:.3f}), serial {ms_s:.3f} ms "
+        f"(wall {wall_s / K * 1e3:.3f})")
+    rec = {
+        "metric": "PA batched input throughput (Mbit/s), 64 uneven blocks in one call, bit-exact",
+        "value": round(total / (ms_b / 1e3) / 1e6, 1),
+        "unit": "Mbit/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": round(ms_b, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32 (exact integer NTTs mod three 30-bit primes, CRT to 96-bit coefficients)",
+        "data": "synthetic",
+        "config": {"workload": f"{len(blocks)} uneven blocks, splitmix64 seed {BATCH_SEED}, n log-uniform in "
+                               f"[2^22, 2^28], r/n in [0.05, 0.30]", "total_bits": total,
+                   "parallelism": "single GPU"},
+        "serial_per_block": {"value": round(total / (ms_s / 1e3) / 1e6, 1), "unit": "Mbit/s",
+                             "ms_per_step": round(ms_s, 4),
+                             "what": "the same blocks as back-to-back pa_hash_async calls on one stream"},
+        "speedup_vs_serial": round(ms_s / ms_b, 3),
+        "outputs_equal_serial": same,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,11 +213,16 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed region, copy a buffer of this many MiB with a plain device "
                          "copy kernel (reference point for the HBM byte counters)")
+    ap.add_argument("--workload", choices=["single", "batched"], default="single",
+                    help="single: the 2.6e8-bit block (the headline); batched: 64 uneven blocks in one "
+                         "pa_hash_batched call against the same blocks as serial calls")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(blocks are independent; see the sharding notes). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        return bench_batched(args)
 
     import torch
     import paper_2105_13678_amd as pa

@@ -134,6 +134,51 @@ pa_status pa_hash_stages(pa_plan *plan, const uint64_t *key, const uint64_t *a,
                          const uint64_t *b, const uint64_t *c, uint64_t *out,
                          uint64_t *y_out, uint64_t *U_out, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Batched hashing of independent blocks of uneven size.
+ *
+ * A QKD post-processing pipeline produces reconciled blocks of varying length
+ * and compression ratio (Sec. 4 evaluates blocks from 10^6 to 8*10^8 bits and
+ * ratios 0.0972 to 0.2957, Table 3).  pa_hash_batched hashes `count` such
+ * blocks in one call; each block is hashed exactly as pa_hash would hash it
+ * with a plan for its (n, r) (gamma and B by the plan rule, gamma = 0,
+ * B = 0).  The blocks run concurrently on the batch plan's worker streams,
+ * so blocks too small to fill the GPU alone overlap.
+ */
+typedef struct pa_block {
+    uint64_t n, r;             /* as pa_params.n, pa_params.r                  */
+    const uint64_t *key;       /* device, ceil(n/64) words, as for pa_hash     */
+    const uint64_t *a, *b, *c; /* device, k*W, W and W words, as for pa_hash   */
+    uint64_t *out;             /* device, ceil(r/64) words                     */
+} pa_block;
+
+typedef struct pa_batch_plan pa_batch_plan;
+
+/* Create a batch plan on HIP device `hip_device` for calls of at most
+ * `max_blocks` blocks with at most `max_total_bits` key bits in total.  The
+ * plan keeps the twiddle tables of every transform length it meets and one
+ * scratch arena per worker stream, grown to the largest block that worker
+ * has run (device memory owned until pa_batch_plan_destroy).  A batch plan
+ * is used by one host thread at a time. */
+pa_status pa_batch_plan_create(uint32_t max_blocks, uint64_t max_total_bits, int hip_device,
+                               pa_batch_plan **out);
+
+/* Waits for the plan's work, then frees it (NULL is a no-op). */
+void pa_batch_plan_destroy(pa_batch_plan *plan);
+
+/* Hash blocks[0..count) (host array of descriptors; device buffers as for
+ * pa_hash, valid until the call returns).  The work is ordered after earlier
+ * work on `stream`; the call returns when every block is done.
+ * per_block[i] (host) receives block i's status: a plan error (PA_ERR_ARG,
+ * PA_ERR_NO_GAMMA, PA_ERR_INEXACT, PA_ERR_LIMIT) when its (n, r) admits no
+ * plan (nothing launched for it), else the device-detected status (PA_OK,
+ * PA_RELOAD, PA_ERR_SEED_B_EVEN, PA_ERR_SEED_RANGE); outputs are written only
+ * for PA_OK.  Returns PA_ERR_LIMIT (nothing launched) if count > max_blocks
+ * or the key bits exceed max_total_bits, PA_ERR_NOMEM / PA_ERR_DEVICE on a
+ * failure of the device, else PA_OK. */
+pa_status pa_hash_batched(pa_batch_plan *plan, const pa_block *blocks, uint32_t count,
+                          pa_status *per_block, hipStream_t stream);
+
 /* Phases of the per-block launch sequence, for pa_plan_read_profile.  Each
  * of the NTT phases is exactly one kernel launch. */
 typedef enum pa_phase {

@@ -5,11 +5,11 @@ include/pa.h); this package is its Python binding plus the seeded synthetic
 input generators.  Importing the package loads nothing; the library is loaded
 on first use and a missing library is an error, never a fallback.
 """
-from .binding import (PA_OK, PA_RELOAD, PAError, Plan, decode_status, lib, plan_query,  # noqa: F401
-                      status_string)
+from .binding import (PA_OK, PA_RELOAD, BatchPlan, PAError, Plan, decode_status, lib,  # noqa: F401
+                      plan_query, status_string)
 
-__all__ = ["Plan", "PAError", "plan_query", "status_string", "decode_status", "lib", "PA_OK", "PA_RELOAD",
-           "to_device", "from_device"]
+__all__ = ["Plan", "BatchPlan", "PAError", "plan_query", "status_string", "decode_status", "lib", "PA_OK",
+           "PA_RELOAD", "to_device", "from_device"]
 
 
 def to_device(words, device="cuda"):

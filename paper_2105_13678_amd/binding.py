@@ -56,6 +56,12 @@ _lib = None
 _VP = ctypes.c_void_p
 
 
+class Block(ctypes.Structure):
+    """pa_block: one block of a batched call (device pointers)."""
+    _fields_ = [("n", ctypes.c_uint64), ("r", ctypes.c_uint64), ("key", _VP), ("a", _VP), ("b", _VP),
+                ("c", _VP), ("out", _VP)]
+
+
 def lib():
     """Load libpa.so (built in-tree); raise if it has not been built."""
     global _lib
@@ -82,6 +88,12 @@ def lib():
         L.pa_plan_set_profiling.restype = ctypes.c_int
         L.pa_plan_read_profile.argtypes = [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)]
         L.pa_plan_read_profile.restype = ctypes.c_int
+        L.pa_batch_plan_create.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(_VP)]
+        L.pa_batch_plan_create.restype = ctypes.c_int
+        L.pa_batch_plan_destroy.argtypes = [_VP]
+        L.pa_batch_plan_destroy.restype = None
+        L.pa_hash_batched.argtypes = [_VP, ctypes.POINTER(Block), ctypes.c_uint32, ctypes.POINTER(ctypes.c_int), _VP]
+        L.pa_hash_batched.restype = ctypes.c_int
         L.pa_decode_status.argtypes = [ctypes.c_uint32]
         L.pa_decode_status.restype = ctypes.c_int
         L.pa_status_string.argtypes = [ctypes.c_int]
@@ -232,3 +244,62 @@ class Plan:
         args = self._args(key, a, b, c, out)
         st = lib().pa_hash_stages(self._h, *args, y.data_ptr(), U.data_ptr(), self._stream(stream))
         return st, out, y, U
+
+
+class BatchPlan:
+    """Batched hashing of blocks of uneven (n, r) on one GPU (pa_hash_batched)."""
+
+    def __init__(self, max_blocks: int, max_total_bits: int, device: int = 0):
+        import torch
+        self._h = _VP()
+        self.device = torch.device("cuda", device)
+        self.max_blocks = max_blocks
+        st = lib().pa_batch_plan_create(int(max_blocks), int(max_total_bits), int(device), ctypes.byref(self._h))
+        if st != PA_OK:
+            self._h = _VP()
+            raise PAError(st, "pa_batch_plan_create")
+
+    def close(self):
+        if self._h:
+            lib().pa_batch_plan_destroy(self._h)
+            self._h = _VP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @staticmethod
+    def new_out(r: int, device):
+        import torch
+        return torch.zeros((r + 63) // 64, dtype=torch.int64, device=device)
+
+    def hash(self, blocks, stream=None):
+        """blocks: sequence of (n, r, key, a, b, c, out) with device tensors.
+        Returns (call status, [per-block status]).  Buffer sizes are checked
+        against each block's plan; a block whose (n, r) admits no plan is
+        passed through and gets its plan error in the per-block status."""
+        import torch
+        arr = (Block * len(blocks))()
+        for i, (n, r, key, a, b, c, out) in enumerate(blocks):
+            st, info = plan_query(n, r)
+            if st == PA_OK:
+                ptrs = (_dev_ptr(key, info["key_words"], "key", self.device),
+                        _dev_ptr(a, info["a_words"], "a", self.device),
+                        _dev_ptr(b, info["seed_words"], "b", self.device),
+                        _dev_ptr(c, info["seed_words"], "c", self.device),
+                        _dev_ptr(out, info["out_words"], "out", self.device))
+            else:
+                ptrs = tuple(t.data_ptr() if t is not None else 0 for t in (key, a, b, c, out))
+            arr[i] = Block(n, r, *ptrs)
+        per = (ctypes.c_int * len(blocks))()
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        st = lib().pa_hash_batched(self._h, arr, len(blocks), per, s.cuda_stream)
+        return st, list(per)

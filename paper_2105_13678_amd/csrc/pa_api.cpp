@@ -98,10 +98,6 @@ pa_status pa_decode_status(uint32_t flags) {
 
 namespace {
 
-struct Layout {
-    size_t oX, oC, oC96, oT, oS, oY, oU, oAgg, oTc, oRes, oNo, oSt, oSo, oT1, oT2, oW, total;
-};
-
 // Transform length exponent for L limbs: the smallest m >= kMinLog2N with
 // 2^m >= 2L - 1 (the full product of two L-limb numbers fits without wrap).
 uint32_t log2_len(uint64_t L) {
@@ -127,8 +123,12 @@ bool exact(uint64_t k, uint64_t L, uint32_t B, const pa::PrimeTriple &T) {
     return kL * lim <= (P3 - 1) / lim && kL * lim * lim < P3;
 }
 
+}  // namespace
+
+namespace pa {
+
 // Derive every plan quantity from the request; no device access.
-pa_status derive(const pa_params *prm, pa_plan *p, Layout *lay) {
+pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     uint64_t gamma, k;
     uint32_t B;
     pa_status st = plan_shape(prm, &gamma, &k, &B);
@@ -215,23 +215,70 @@ pa_status derive(const pa_params *prm, pa_plan *p, Layout *lay) {
     lay->oNo = carve(k * 4);
     lay->oSt = carve(4 * 4);
     lay->oSo = carve(4 * 4);
+    lay->scratch_bytes = off;
     lay->oT1 = carve(P3 * n1 * 4 * 2);
     lay->oT2 = carve(P3 * n2 * 4 * 2);
     lay->oW = carve(P3 * N * 4 * 2);
     lay->total = off;
+    lay->table_bytes = off - lay->scratch_bytes;
     p->workspace_bytes = off;
     return PA_OK;
 }
 
-}  // namespace
+void bind_scratch(pa_plan *p, void *scratch, const PlanLayout &lay) {
+    char *b = (char *)scratch;
+    p->X = (uint32_t *)(b + lay.oX);
+    p->Cc = (uint32_t *)(b + lay.oC);
+    p->C96 = (uint32_t *)(b + lay.oC96);
+    p->t = (uint64_t *)(b + lay.oT);
+    p->s = (uint32_t *)(b + lay.oS);
+    p->y = (uint32_t *)(b + lay.oY);
+    p->U = (uint32_t *)(b + lay.oU);
+    p->agg = (pa::CFn *)(b + lay.oAgg);
+    p->tcarry = (uint32_t *)(b + lay.oTc);
+    p->res = (pa::ScanResult *)(b + lay.oRes);
+    p->notones = (uint32_t *)(b + lay.oNo);
+    p->status = (uint32_t *)(b + lay.oSt);
+    p->status_out = (uint32_t *)(b + lay.oSo);
+}
+
+void bind_tables(pa_plan *p, void *tables, const PlanLayout &lay) {
+    char *b = (char *)tables - lay.scratch_bytes;  // table offsets follow the scratch
+    const size_t N = p->N, P3 = pa::NPRIMES;
+    const size_t n1 = (size_t)1 << p->m1, n2 = (size_t)1 << p->m2;
+    p->tw1f = (uint32_t *)(b + lay.oT1);
+    p->tw1i = p->tw1f + P3 * n1;
+    p->tw2f = (uint32_t *)(b + lay.oT2);
+    p->tw2i = p->tw2f + P3 * n2;
+    p->Wf = (uint32_t *)(b + lay.oW);
+    p->Wi = p->Wf + P3 * N;
+}
+
+pa_status enqueue_hash(pa_plan *p, const uint64_t *key, const uint64_t *a, const uint64_t *b,
+                       const uint64_t *c, uint64_t *out, uint32_t *d_status, uint64_t *y_out,
+                       uint64_t *U_out, hipStream_t st) {
+    if (!p || !key || !a || !b || !c || !out) return PA_ERR_ARG;
+    hipError_t e = pa::launch_prologue(p, a, b, c, st);
+    if (e == hipSuccess) e = pa::launch_mmh(p, key, a, st);
+    if (e == hipSuccess) e = pa::launch_fold(p, st);
+    if (e == hipSuccess) e = pa::launch_mh(p, b, c, st);
+    if (e == hipSuccess) e = pa::launch_finish(p, out, d_status, y_out, U_out, st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return PA_ERR_DEVICE;
+    }
+    return PA_OK;
+}
+
+}  // namespace pa
 
 extern "C" {
 
 pa_status pa_plan_query(const pa_params *prm, pa_plan_info *info) {
     if (!info) return PA_ERR_ARG;
     pa_plan tmp{};
-    Layout lay;
-    pa_status st = derive(prm, &tmp, &lay);
+    pa::PlanLayout lay;
+    pa_status st = pa::derive_plan(prm, &tmp, &lay);
     if (st != PA_OK) return st;
     return pa_plan_get_info(&tmp, info);
 }
@@ -241,15 +288,13 @@ pa_status pa_plan_create(const pa_params *prm, int hip_device, pa_plan **out) {
     *out = nullptr;
     pa_plan *p = new (std::nothrow) pa_plan();
     if (!p) return PA_ERR_NOMEM;
-    Layout lay;
-    pa_status st = derive(prm, p, &lay);
+    pa::PlanLayout lay;
+    pa_status st = pa::derive_plan(prm, p, &lay);
     if (st != PA_OK) {
         delete p;
         return st;
     }
     p->device = hip_device;
-    const size_t N = p->N, P3 = pa::NPRIMES;
-    const size_t n1 = (size_t)1 << p->m1, n2 = (size_t)1 << p->m2;
 
     DeviceGuard guard(hip_device);
     if (!guard.ok) {
@@ -266,26 +311,8 @@ pa_status pa_plan_create(const pa_params *prm, int hip_device, pa_plan **out) {
         delete p;
         return PA_ERR_NOMEM;
     }
-    char *b = (char *)p->base;
-    p->X = (uint32_t *)(b + lay.oX);
-    p->Cc = (uint32_t *)(b + lay.oC);
-    p->C96 = (uint32_t *)(b + lay.oC96);
-    p->t = (uint64_t *)(b + lay.oT);
-    p->s = (uint32_t *)(b + lay.oS);
-    p->y = (uint32_t *)(b + lay.oY);
-    p->U = (uint32_t *)(b + lay.oU);
-    p->agg = (pa::CFn *)(b + lay.oAgg);
-    p->tcarry = (uint32_t *)(b + lay.oTc);
-    p->res = (pa::ScanResult *)(b + lay.oRes);
-    p->notones = (uint32_t *)(b + lay.oNo);
-    p->status = (uint32_t *)(b + lay.oSt);
-    p->status_out = (uint32_t *)(b + lay.oSo);
-    p->tw1f = (uint32_t *)(b + lay.oT1);
-    p->tw1i = p->tw1f + P3 * n1;
-    p->tw2f = (uint32_t *)(b + lay.oT2);
-    p->tw2i = p->tw2f + P3 * n2;
-    p->Wf = (uint32_t *)(b + lay.oW);
-    p->Wi = p->Wf + P3 * N;
+    pa::bind_scratch(p, p->base, lay);
+    pa::bind_tables(p, (char *)p->base + lay.scratch_bytes, lay);
 
     hipStream_t s0 = nullptr;
     if (pa::launch_twiddles(p, s0) != hipSuccess || hipStreamSynchronize(s0) != hipSuccess) {
@@ -378,22 +405,6 @@ pa_status pa_plan_read_profile(pa_plan *p, double *ms, uint64_t *calls) {
     return st;
 }
 
-static pa_status enqueue(pa_plan *p, const uint64_t *key, const uint64_t *a, const uint64_t *b,
-                         const uint64_t *c, uint64_t *out, uint32_t *d_status, uint64_t *y_out,
-                         uint64_t *U_out, hipStream_t st) {
-    if (!p || !key || !a || !b || !c || !out) return PA_ERR_ARG;
-    hipError_t e = pa::launch_prologue(p, a, b, c, st);
-    if (e == hipSuccess) e = pa::launch_mmh(p, key, a, st);
-    if (e == hipSuccess) e = pa::launch_fold(p, st);
-    if (e == hipSuccess) e = pa::launch_mh(p, b, c, st);
-    if (e == hipSuccess) e = pa::launch_finish(p, out, d_status, y_out, U_out, st);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return PA_ERR_DEVICE;
-    }
-    return PA_OK;
-}
-
 static pa_status wait_status(pa_plan *p, hipStream_t st) {
     if (hipMemcpyAsync(p->h_status, p->status_out, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
@@ -408,7 +419,7 @@ pa_status pa_hash(pa_plan *p, const uint64_t *key, const uint64_t *a, const uint
     if (!p) return PA_ERR_ARG;
     DeviceGuard guard(p->device);
     if (!guard.ok) return PA_ERR_DEVICE;
-    pa_status s = enqueue(p, key, a, b, c, out, nullptr, nullptr, nullptr, st);
+    pa_status s = pa::enqueue_hash(p, key, a, b, c, out, nullptr, nullptr, nullptr, st);
     if (s != PA_OK) return s;
     return wait_status(p, st);
 }
@@ -418,7 +429,7 @@ pa_status pa_hash_async(pa_plan *p, const uint64_t *key, const uint64_t *a, cons
     if (!p || !d_status) return PA_ERR_ARG;
     DeviceGuard guard(p->device);
     if (!guard.ok) return PA_ERR_DEVICE;
-    return enqueue(p, key, a, b, c, out, d_status, nullptr, nullptr, st);
+    return pa::enqueue_hash(p, key, a, b, c, out, d_status, nullptr, nullptr, st);
 }
 
 pa_status pa_hash_stages(pa_plan *p, const uint64_t *key, const uint64_t *a, const uint64_t *b,
@@ -427,7 +438,7 @@ pa_status pa_hash_stages(pa_plan *p, const uint64_t *key, const uint64_t *a, con
     if (!p || !y_out || !U_out) return PA_ERR_ARG;
     DeviceGuard guard(p->device);
     if (!guard.ok) return PA_ERR_DEVICE;
-    pa_status s = enqueue(p, key, a, b, c, out, nullptr, y_out, U_out, st);
+    pa_status s = pa::enqueue_hash(p, key, a, b, c, out, nullptr, y_out, U_out, st);
     if (s != PA_OK) return s;
     return wait_status(p, st);
 }

@@ -140,6 +140,24 @@ struct pa_plan {
 
 namespace pa {
 
+// Offsets (bytes) of a plan's device buffers: the per-call scratch occupies
+// [0, scratch_bytes), the read-only twiddle tables (which depend only on the
+// transform length) the following table_bytes.
+struct PlanLayout {
+    size_t oX, oC, oC96, oT, oS, oY, oU, oAgg, oTc, oRes, oNo, oSt, oSo;
+    size_t oT1, oT2, oW;
+    size_t scratch_bytes, table_bytes, total;
+};
+
+// Host-side plan derivation (no device access) and buffer binding (pa_api.cpp).
+pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay);
+void bind_scratch(pa_plan *p, void *scratch, const PlanLayout &lay);
+void bind_tables(pa_plan *p, void *tables, const PlanLayout &lay);
+// Enqueue one complete hash on `st` (no synchronisation).
+pa_status enqueue_hash(pa_plan *p, const uint64_t *key, const uint64_t *a, const uint64_t *b,
+                       const uint64_t *c, uint64_t *out, uint32_t *d_status, uint64_t *y_out,
+                       uint64_t *U_out, hipStream_t st);
+
 // Host-side constant setup (pa_kernels.hip): Montgomery constants, small
 // roots and CRT constants for the three primes of the plan's triple.
 void init_prime_constants(pa_plan *p, const uint32_t primes[NPRIMES]);

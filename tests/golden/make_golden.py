@@ -4,11 +4,14 @@ Calls only the oracle (C oracle, cross-checked against the Python-int
 definition with --check-defn) on the seeded synthetic inputs, and stores
 digests of the outputs:
 
-    python tests/golden/make_golden.py [--check-defn]
+    python tests/golden/make_golden.py [--check-defn] [case ...]
 
 Cases (splitmix64 seed, n, r): the 2.6e8-bit single block (seed 2,
-r = n/10) and the paper-shaped CV block n = 10 * 25,964,951 with compression
-ratio 0.0972 (Table 3; seed 6).
+r = n/10), the paper-shaped CV block n = 10 * 25,964,951 with compression
+ratio 0.0972 (Table 3; seed 6), and one chunk of the largest Mersenne
+exponent (gamma = 136,279,841, r = 2^27, seed 7), whose products need the
+longest transform (2^24 points).  Without case names every case is
+recomputed; stored cases not named are kept.
 """
 from __future__ import annotations
 
@@ -32,6 +35,7 @@ from paper_2105_13678_amd import synth  # noqa: E402
 CASES = {
     "single_block_2p6e8": dict(seed=2, n=260_000_000, r=26_000_000),
     "paper_cv_block": dict(seed=6, n=10 * 25964951, r=int(math.floor(0.0972 * 10 * 25964951))),
+    "max_length_single_chunk": dict(seed=7, n=136279841 - 1, r=1 << 27),
 }
 
 
@@ -41,11 +45,13 @@ def digest(words: np.ndarray) -> str:
 
 def main():
     check = "--check-defn" in sys.argv
+    names = [a for a in sys.argv[1:] if not a.startswith("--")] or list(CASES)
     out = {}
     path = os.path.join(HERE, "full_size.json")
     if os.path.exists(path):
         out = json.load(open(path))
-    for name, c in CASES.items():
+    for name in names:
+        c = CASES[name]
         st, g, k = defn.plan_shape(c["n"], c["r"])
         blk = synth.single_block(c["seed"], c["n"], c["r"], g, k)
         t0 = time.time()

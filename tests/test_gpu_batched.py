@@ -1,0 +1,104 @@
+"""GPU parity of the batched entry point (pa_hash_batched): blocks of uneven
+(n, r) in one call against the CPU oracle (small blocks) and against one
+pa_hash call per block (large blocks).  Every case prints its name, seed and
+shapes before it touches the GPU."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import defn
+from paper_2105_13678_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pa():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_2105_13678_amd as pa
+    pa.lib()
+    return pa
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _shape(n, r):
+    st, g, k = defn.plan_shape(n, r)
+    return g, k
+
+
+def _dev(pa, blk):
+    key, a, b, c = (pa.to_device(np.asarray(x, dtype=np.uint64)) for x in (blk.key, blk.a, blk.b, blk.c))
+    out = pa.BatchPlan.new_out(blk.r, key.device)
+    return (blk.n, blk.r, key, a, b, c, out)
+
+
+def test_batched_small_blocks_against_oracle(pa):
+    """Ten uneven blocks (n log-uniform in [2^14, 2^20], r/n in [0.05, 0.3],
+    seed 31) plus three special blocks in the same call: one whose first key
+    chunk is all ones (RELOAD), one with an even b (SEED_B_EVEN), one whose
+    r admits no Mersenne exponent (NO_GAMMA, nothing launched)."""
+    blocks = synth.uneven_blocks(31, 10, _shape, 14, 20)
+    rel = synth.single_block(32, 5000, 300, *_shape(5000, 300))
+    rel.key[:] = np.uint64(0xFFFFFFFFFFFFFFFF)  # chunk 0 (gamma = 521 bits) all ones
+    rel.key[-1] &= np.uint64((1 << (5000 % 64)) - 1)
+    even = synth.single_block(33, 7000, 500, *_shape(7000, 500))
+    even.b[0] &= ~np.uint64(1)
+    blocks += [rel, even]
+    say("[case] batched small:", [(b.n, b.r, b.gamma, b.k) for b in blocks])
+    import torch
+    dev = [_dev(pa, b) for b in blocks]
+    dummy = torch.zeros(1, dtype=torch.int64, device="cuda")
+    dev.append((1 << 32, (1 << 32) // 10, dummy, dummy, dummy, dummy, dummy))
+    with pa.BatchPlan(16, 1 << 34) as bp:
+        st, per = bp.hash(dev)
+    assert st == 0
+    assert per[-1] == -2  # PA_ERR_NO_GAMMA
+    for blk, d, s in zip(blocks, dev, per):
+        st_o, out_o = oracle.hash(blk.key, blk.n, blk.r, blk.gamma, blk.a, blk.b, blk.c)
+        assert s == st_o, (blk.n, blk.r, s, st_o)
+        if s == 0:
+            assert np.array_equal(pa.from_device(d[6]), out_o), (blk.n, blk.r)
+    assert per[-3] == 2 and per[-2] == -5  # RELOAD, SEED_B_EVEN
+
+
+def test_batched_large_uneven_blocks_against_per_block_calls(pa):
+    """Sixteen blocks drawn like the uneven-batch workload (seed 3, n
+    log-uniform in [2^22, 2^26]): every output equals the single-block
+    pa_hash output for the same inputs, and a second call with a different
+    batch (new transform lengths, larger arenas) on the same plan still does.
+    The single-block path is the one the full-size oracle digests pin."""
+    import torch
+    with pa.BatchPlan(64, 1 << 36) as bp:
+        for seed, count in ((3, 16), (35, 6)):
+            blocks = synth.uneven_blocks(seed, count, _shape, 22, 26)
+            say(f"[case] batched large seed={seed}:", [(b.n, b.r, b.gamma, b.k) for b in blocks])
+            dev = [_dev(pa, b) for b in blocks]
+            st, per = bp.hash(dev)
+            assert st == 0 and all(s == 0 for s in per), per
+            for blk, d in zip(blocks, dev):
+                with pa.Plan(blk.n, blk.r) as plan:
+                    s1, out1 = plan.hash(*d[2:6])
+                assert s1 == 0
+                assert torch.equal(out1, d[6]), (blk.n, blk.r)
+
+
+def test_batched_call_errors(pa):
+    """Whole-call limits are checked before anything is launched."""
+    small = _dev(pa, synth.single_block(36, 1000, 100, *_shape(1000, 100)))
+    big = _dev(pa, synth.single_block(37, 1 << 21, 1000, *_shape(1 << 21, 1000)))
+    say("[case] batched call limits")
+    with pa.BatchPlan(2, 1 << 20) as bp:
+        st, _ = bp.hash([small] * 3)
+        assert st == -10  # PA_ERR_LIMIT: more blocks than the plan allows
+        st, _ = bp.hash([big])
+        assert st == -10  # PA_ERR_LIMIT: more key bits than the plan allows
+        st, per = bp.hash([small])
+        assert st == 0 and per == [0]

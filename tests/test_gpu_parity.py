@@ -285,3 +285,58 @@ def test_full_size_blocks_against_stored_oracle_digest(pa, name):
     assert _digest(y) == gold["y_sha256"]
     assert _digest(U) == gold["U_sha256"]
     assert _digest(out) == gold["out_sha256"]
+
+
+def _chunk_int(key_bytes: bytes, lo_bit: int, nbits: int, n: int) -> int:
+    """Key bits [lo_bit, lo_bit + nbits) as an int, zero at and above bit n."""
+    hi_bit = min(lo_bit + nbits, n)
+    if hi_bit <= lo_bit:
+        return 0
+    b0, b1 = lo_bit // 8, (hi_bit + 7) // 8
+    v = int.from_bytes(key_bytes[b0:b1], "little") >> (lo_bit - 8 * b0)
+    return v & ((1 << (hi_bit - lo_bit)) - 1)
+
+
+def test_largest_block_power_of_two_seeds(pa):
+    """The largest block, n = 2^32 with r = 2^27 (gamma = 136,279,841, k = 32,
+    B = 29, 2^24-point transforms), against a closed form instead of the
+    oracle: with seeds a_i = 2^(s_i) the MMH sum is y = sum_i rotl(x_i, s_i)
+    mod p (2^gamma = 1 mod p turns a power-of-two product into a rotation), and
+    with b = 2^gamma - 1 (= -1 mod 2^gamma) the MH value is U = c - y mod
+    2^gamma.  The key and c are uniform; every chunk is active."""
+    n, r = 1 << 32, 1 << 27
+    st, g, k = defn.plan_shape(n, r)
+    assert (st, g, k) == (0, 136279841, 32)
+    info = pa.plan_query(n, r)[1]
+    assert info["log2N"] == 24
+    rng = synth.SplitMix64(77)
+    key = rng.words((n + 63) // 64)
+    W = (g + 63) // 64
+    shifts = [int(v % g) for v in rng.words(k)]
+    a = np.zeros(k * W, dtype=np.uint64)
+    for i, s in enumerate(shifts):
+        a[i * W + s // 64] = np.uint64(1) << np.uint64(s % 64)
+    b = np.full(W, np.uint64(0xFFFFFFFFFFFFFFFF), dtype=np.uint64)
+    b[-1] = np.uint64((1 << (g % 64)) - 1) if g % 64 else b[-1]
+    c = rng.words(W)
+    if g % 64:
+        c[-1] &= np.uint64((1 << (g % 64)) - 1)
+    say(f"[case] largest block n=2^32 r=2^27 gamma={g} k={k} N=2^24 B={info['B']}")
+    plan = pa.Plan(n, r)
+    try:
+        st_g, out, y, U = run_gpu(pa, plan, synth.Block(n, r, g, k, key, a, b, c), stages=True)
+    finally:
+        plan.close()
+    assert st_g == 0
+    p = (1 << g) - 1
+    kb = key.tobytes()
+    ysum = 0
+    for i, s in enumerate(shifts):
+        x = _chunk_int(kb, i * g, g, n)
+        ysum += ((x << s) | (x >> (g - s))) & p
+    y_want = defn.mod_mersenne(ysum, g)
+    c_int = int.from_bytes(c.tobytes(), "little")
+    U_want = (c_int - y_want) % (1 << g)
+    assert int.from_bytes(y.tobytes(), "little") == y_want
+    assert int.from_bytes(U.tobytes(), "little") == U_want
+    assert int.from_bytes(out.tobytes(), "little") == U_want >> (g - r)
