@@ -179,6 +179,74 @@ void pa_batch_plan_destroy(pa_batch_plan *plan);
 pa_status pa_hash_batched(pa_batch_plan *plan, const pa_block *blocks, uint32_t count,
                           pa_status *per_block, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: requests from many QKD sessions hashed as they arrive.
+ *
+ * Each session agrees its random seeds a, b, c (Alg. 1's inputs) once per
+ * output class gamma and registers them with pa_server_set_seeds; they stay
+ * on the device.  A request then carries only its key (host memory in, the
+ * r-bit output to host memory out).  pa_submit queues it and returns a
+ * ticket at once; a worker thread admits requests in arrival order while one
+ * of max_inflight slots is free and the request's device memory (scratch,
+ * key, output) fits first-fit into the server's budget, and runs it on the
+ * slot's stream (key upload, hash, output download).  pa_poll returns
+ * PA_PENDING until the request is done.  A request's result is the same as
+ * pa_hash's for the same key and seeds, whatever else is in flight.
+ */
+typedef struct pa_server_cfg {
+    int device;                /* HIP device                                     */
+    uint32_t max_inflight;     /* requests running at once, 1..64 (one stream each) */
+    uint64_t hbm_budget_bytes; /* device memory for admitted requests, allocated
+                                  once at creation (twiddle tables and resident
+                                  seeds are outside it)                          */
+} pa_server_cfg;
+
+typedef struct pa_request {
+    uint64_t n, r;             /* as pa_params.n, pa_params.r (gamma, B by the plan rule) */
+    uint32_t session;          /* seeds registered for (session, gamma)          */
+    uint32_t reserved;
+    const uint64_t *key;       /* host, ceil(n/64) words; pinned (hipHostMalloc) for
+                                  an asynchronous upload; valid until done      */
+    uint64_t *out;             /* host, ceil(r/64) words; written when done,
+                                  meaningful for PA_OK                           */
+} pa_request;
+
+typedef struct pa_timing {
+    double queued_ms;          /* submission -> admission (host clock)           */
+    double device_ms;          /* key upload start -> output download end (HIP events) */
+    double total_ms;           /* submission -> completion seen by the worker    */
+} pa_timing;
+
+typedef struct pa_server pa_server;
+
+/* Create a server (allocates the budget, starts the worker thread). */
+pa_status pa_server_create(const pa_server_cfg *cfg, pa_server **out);
+
+/* Stop accepting requests, finish the queued and running ones, free
+ * everything (NULL is a no-op).  Tickets not yet polled are dropped. */
+void pa_server_destroy(pa_server *server);
+
+/* Register the seeds of `session` for output class `gamma` (a tabled Mersenne
+ * exponent, PA_ERR_GAMMA otherwise): a = kmax chunks of W = ceil(gamma/64)
+ * words (requests of this class need k <= kmax), b and c W words each, host
+ * memory, copied before the call returns.  Validity (bits >= gamma clear,
+ * b odd) is checked per request on the device, as for pa_hash.  Seeds once
+ * registered are not replaced (PA_ERR_BUSY). */
+pa_status pa_server_set_seeds(pa_server *server, uint32_t session, uint64_t gamma, uint64_t kmax,
+                              const uint64_t *a, const uint64_t *b, const uint64_t *c);
+
+/* Queue a request; *ticket identifies it.  Returns at once: a plan error for
+ * (n, r), PA_ERR_ARG when the session has no seeds for the request's gamma
+ * (or too few chunks), PA_ERR_LIMIT when the request alone exceeds the
+ * budget, PA_ERR_BUSY while the server is stopping, else PA_OK. */
+pa_status pa_submit(pa_server *server, const pa_request *request, uint64_t *ticket);
+
+/* PA_PENDING while the request is queued or running; PA_OK once it is done,
+ * with its status in *result (as pa_hash would return it) and, if timing is
+ * not NULL, its timing.  A ticket is reported done once; polling it again,
+ * or an unknown ticket, gives PA_ERR_ARG. */
+pa_status pa_poll(pa_server *server, uint64_t ticket, pa_status *result, pa_timing *timing);
+
 /* Phases of the per-block launch sequence, for pa_plan_read_profile.  Each
  * of the NTT phases is exactly one kernel launch. */
 typedef enum pa_phase {

@@ -5,10 +5,10 @@ include/pa.h); this package is its Python binding plus the seeded synthetic
 input generators.  Importing the package loads nothing; the library is loaded
 on first use and a missing library is an error, never a fallback.
 """
-from .binding import (PA_OK, PA_RELOAD, BatchPlan, PAError, Plan, decode_status, lib,  # noqa: F401
-                      plan_query, status_string)
+from .binding import (PA_OK, PA_PENDING, PA_RELOAD, BatchPlan, PAError, Plan, Server,  # noqa: F401
+                      decode_status, lib, plan_query, status_string)
 
-__all__ = ["Plan", "BatchPlan", "PAError", "plan_query", "status_string", "decode_status", "lib", "PA_OK",
+__all__ = ["Plan", "BatchPlan", "Server", "PAError", "plan_query", "status_string", "decode_status", "lib", "PA_OK",
            "PA_RELOAD", "to_device", "from_device"]
 
 

@@ -56,6 +56,19 @@ _lib = None
 _VP = ctypes.c_void_p
 
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("max_inflight", ctypes.c_uint32), ("hbm_budget_bytes", ctypes.c_uint64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("r", ctypes.c_uint64), ("session", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("key", _VP), ("out", _VP)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("queued_ms", ctypes.c_double), ("device_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+
 class Block(ctypes.Structure):
     """pa_block: one block of a batched call (device pointers)."""
     _fields_ = [("n", ctypes.c_uint64), ("r", ctypes.c_uint64), ("key", _VP), ("a", _VP), ("b", _VP),
@@ -94,6 +107,16 @@ def lib():
         L.pa_batch_plan_destroy.restype = None
         L.pa_hash_batched.argtypes = [_VP, ctypes.POINTER(Block), ctypes.c_uint32, ctypes.POINTER(ctypes.c_int), _VP]
         L.pa_hash_batched.restype = ctypes.c_int
+        L.pa_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(_VP)]
+        L.pa_server_create.restype = ctypes.c_int
+        L.pa_server_destroy.argtypes = [_VP]
+        L.pa_server_destroy.restype = None
+        L.pa_server_set_seeds.argtypes = [_VP, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, _VP, _VP, _VP]
+        L.pa_server_set_seeds.restype = ctypes.c_int
+        L.pa_submit.argtypes = [_VP, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+        L.pa_submit.restype = ctypes.c_int
+        L.pa_poll.argtypes = [_VP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Timing)]
+        L.pa_poll.restype = ctypes.c_int
         L.pa_decode_status.argtypes = [ctypes.c_uint32]
         L.pa_decode_status.restype = ctypes.c_int
         L.pa_status_string.argtypes = [ctypes.c_int]
@@ -303,3 +326,91 @@ class BatchPlan:
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         st = lib().pa_hash_batched(self._h, arr, len(blocks), per, s.cuda_stream)
         return st, list(per)
+
+
+def _host_ptr(x, min_words: int, what: str) -> int:
+    """Address of a host buffer: a contiguous uint64/int64 numpy array or a
+    CPU torch tensor (pinned for asynchronous copies)."""
+    import numpy as np
+    try:
+        import torch
+        if isinstance(x, torch.Tensor):
+            if x.device.type != "cpu" or x.element_size() != 8 or not x.is_contiguous():
+                raise ValueError(f"{what}: needs a contiguous 8-byte CPU tensor")
+            if x.numel() < min_words:
+                raise ValueError(f"{what}: needs at least {min_words} words")
+            return x.data_ptr()
+    except ImportError:
+        pass
+    if not isinstance(x, np.ndarray) or x.dtype.itemsize != 8 or not x.flags["C_CONTIGUOUS"]:
+        raise ValueError(f"{what}: needs a contiguous 8-byte numpy array")
+    if x.size < min_words:
+        raise ValueError(f"{what}: needs at least {min_words} words")
+    return x.ctypes.data
+
+
+class Server:
+    """Serving loop (pa_server_*): submit requests, poll tickets."""
+
+    def __init__(self, max_inflight: int, hbm_budget_bytes: int, device: int = 0):
+        self._h = _VP()
+        self._live = {}  # ticket -> buffers kept alive until the request is done
+        cfg = ServerCfg(int(device), int(max_inflight), int(hbm_budget_bytes))
+        st = lib().pa_server_create(ctypes.byref(cfg), ctypes.byref(self._h))
+        if st != PA_OK:
+            self._h = _VP()
+            raise PAError(st, "pa_server_create")
+
+    def close(self):
+        if self._h:
+            lib().pa_server_destroy(self._h)
+            self._h = _VP()
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_seeds(self, session: int, gamma: int, kmax: int, a, b, c) -> int:
+        W = (gamma + 63) // 64
+        return lib().pa_server_set_seeds(self._h, session, gamma, kmax, _host_ptr(a, kmax * W, "a"),
+                                         _host_ptr(b, W, "b"), _host_ptr(c, W, "c"))
+
+    def submit(self, n: int, r: int, session: int, key, out):
+        """(status, ticket); key and out are host buffers kept alive here
+        until the ticket is polled done."""
+        req = Request(n, r, session, 0, _host_ptr(key, (n + 63) // 64, "key"), _host_ptr(out, (r + 63) // 64, "out"))
+        t = ctypes.c_uint64(0)
+        st = lib().pa_submit(self._h, ctypes.byref(req), ctypes.byref(t))
+        if st == PA_OK:
+            self._live[t.value] = (key, out)
+        return st, t.value
+
+    def poll(self, ticket: int):
+        """(poll status, request status, timing dict or None)."""
+        res = ctypes.c_int(0)
+        tm = Timing()
+        st = lib().pa_poll(self._h, ticket, ctypes.byref(res), ctypes.byref(tm))
+        if st == PA_OK:
+            self._live.pop(ticket, None)
+            return st, res.value, {"queued_ms": tm.queued_ms, "device_ms": tm.device_ms, "total_ms": tm.total_ms}
+        return st, None, None
+
+    def wait(self, ticket: int, timeout_s: float = 60.0, sleep_s: float = 0.0002):
+        import time
+        t_end = time.monotonic() + timeout_s
+        while True:
+            st, res, tm = self.poll(ticket)
+            if st != PA_PENDING:
+                return st, res, tm
+            if time.monotonic() > t_end:
+                raise TimeoutError(f"ticket {ticket} not done after {timeout_s} s")
+            time.sleep(sleep_s)

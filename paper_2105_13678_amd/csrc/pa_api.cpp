@@ -448,7 +448,7 @@ pa_status pa_hash_stages(pa_plan *p, const uint64_t *key, const uint64_t *a, con
 namespace pa {
 
 void phase_mark(pa_plan *p, int phase, bool begin, hipStream_t st) {
-    if (!(p->profiling >> phase & 1u)) return;
+    if (!(p->profiling >> phase & 1u) || !p->pending || !p->event_pool) return;
     hipEvent_t ev;
     if (!p->event_pool->empty()) {
         ev = p->event_pool->back();

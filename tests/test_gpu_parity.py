@@ -265,7 +265,7 @@ def _digest(words):
     return hashlib.sha256(np.ascontiguousarray(words, dtype=np.uint64).tobytes()).hexdigest()
 
 
-@pytest.mark.parametrize("name", ["single_block_2p6e8", "paper_cv_block"])
+@pytest.mark.parametrize("name", ["single_block_2p6e8", "paper_cv_block", "max_length_single_chunk"])
 def test_full_size_blocks_against_stored_oracle_digest(pa, name):
     """Full-size blocks, in the launch configuration the benchmark times,
     against digests written by tests/golden/make_golden.py (oracle only)."""
