@@ -184,7 +184,9 @@ pa_status pa_hash_batched(pa_batch_plan *plan, const pa_block *blocks, uint32_t 
  *
  * Each session agrees its random seeds a, b, c (Alg. 1's inputs) once per
  * output class gamma and registers them with pa_server_set_seeds; they stay
- * on the device.  A request then carries only its key (host memory in, the
+ * on the device, and so do their transforms (built the first time a request
+ * of a given transform shape needs them, outside the budget), so a request
+ * costs k + 3 transforms instead of 2k + 4.  A request then carries only its key (host memory in, the
  * r-bit output to host memory out).  pa_submit queues it and returns a
  * ticket at once; a worker thread admits requests in arrival order while one
  * of max_inflight slots is free and the request's device memory (scratch,

@@ -126,6 +126,8 @@ struct pa_plan {
     uint32_t *tw1f, *tw1i;  // per prime: omega_{N1}^+-j, j < N1 (Montgomery form)
     uint32_t *tw2f, *tw2i;  // per prime: omega_{N2}^+-j, j < N2
     uint32_t *Wf, *Wi;      // per prime: four-step twiddles, stored (bit-reversed) row order
+    const uint32_t *res_a;  // resident seed transforms (k x 3 x N words) or null
+    const uint32_t *res_b;  // resident transform of b (3 x N words) or null
     uint32_t *h_status;     // pinned host word
 
     // phase profiling (pa_plan_set_profiling)
@@ -172,6 +174,8 @@ hipError_t launch_fold(pa_plan *p, hipStream_t st);
 hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, hipStream_t st);
 hipError_t launch_finish(pa_plan *p, uint64_t *out, uint32_t *d_status, uint64_t *y_out,
                          uint64_t *U_out, hipStream_t st);
+hipError_t launch_seed_transforms(pa_plan *p, const uint64_t *a, uint64_t kmax, const uint64_t *b,
+                                  uint32_t *dst_a, uint32_t *dst_b, hipStream_t st);
 
 // Marks the start or end of a phase on `st` when profiling is on (pa_api.cpp).
 void phase_mark(pa_plan *p, int phase, bool begin, hipStream_t st);

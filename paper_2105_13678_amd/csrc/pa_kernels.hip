@@ -183,6 +183,7 @@ struct ColFwdArgs {
     uint32_t *X;
     uint64_t N, L, n, gamma, k, W;
     uint32_t m1, m2, c_lg, B, s_top, mode;  // mode 0: MMH (key chunks, seed chunks); 1: MH (y, b)
+    uint32_t arr0;  // source array of grid row 0 (outputs are numbered from grid row 0)
     const uint64_t *key, *a, *b;
     const uint32_t *ylimbs;
     uint32_t *notones;
@@ -272,7 +273,7 @@ template <int Stage>
 __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
     uint32_t *lds = lds_dyn;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t arr = blockIdx.y, pq = blockIdx.z;
+    const uint32_t arr = blockIdx.y + A.arr0, pq = blockIdx.z;
     const PrimeConst M = A.P.c[pq];
     const uint32_t *tw = A.tw + ((uint64_t)pq << A.m1);
     const uint32_t c_lg = A.c_lg, lg = A.m1;
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
     const uint32_t full = (uint32_t)((1ull << A.B) - 1), topv = (uint32_t)((1ull << A.s_top) - 1);
     const uint32_t lgMp = lg - 3;
     const uint32_t ntask = (1u << lgMp) << c_lg;
-    uint32_t *out = A.X + ((uint64_t)arr * NPRIMES + pq) * A.N;
+    uint32_t *out = A.X + ((uint64_t)blockIdx.y * NPRIMES + pq) * A.N;
     const LimbSrc S = limb_src(A, arr);
     const uint32_t L = (uint32_t)A.L;
     bool not_ones = false;
@@ -348,13 +349,13 @@ template <int Stage>
 __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
     uint32_t *lds = lds_dyn;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t arr = blockIdx.y, pq = blockIdx.z;
+    const uint32_t arr = blockIdx.y + A.arr0, pq = blockIdx.z;
     const PrimeConst M = A.P.c[pq];
     const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.tw + ((uint64_t)pq << C9_LG), 1u << C9_LG);
     const uint64_t c0 = (uint64_t)tile << C9_CLG;
     const bool is_key = (A.mode == 0) && arr < A.k;
     const uint32_t full = (uint32_t)((1ull << A.B) - 1), topv = (uint32_t)((1ull << A.s_top) - 1);
-    uint32_t *out = A.X + ((uint64_t)arr * NPRIMES + pq) * A.N;
+    uint32_t *out = A.X + ((uint64_t)blockIdx.y * NPRIMES + pq) * A.N;
     const uint32_t t = threadIdx.x;
     const LimbSrc S = limb_src(A, arr);
     const uint32_t L = (uint32_t)A.L;
@@ -418,7 +419,8 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
 
 struct RowArgs {
     const uint32_t *X;
-    uint64_t N, npairs, pair_stride, a_off;  // in words
+    const uint32_t *A;  // seed-side transforms: pair i at A + i * pair_stride
+    uint64_t N, npairs, pair_stride;  // in words
     uint32_t m2;
     uint32_t *out;
     const uint32_t *Wf, *Wi, *twf, *twi;  // per prime: four-step twiddles; omega_{N2}^+-e, e < N2
@@ -504,7 +506,7 @@ __global__ __launch_bounds__(ROW_MAX_THREADS) void k_row(RowArgs A) {
     }
     for (uint64_t i = 0; i < A.npairs; ++i) {
         const uint32_t *xrow = A.X + i * A.pair_stride + pq * A.N + rbase;
-        const uint32_t *arow = xrow + A.a_off;
+        const uint32_t *arow = A.A + i * A.pair_stride + pq * A.N + rbase;
         row_first_step(xrow, wf, lds, lg, twf, M, threadIdx.x, T);
         fwd_steps_from(lds, lg, lg - 3, 0, twf, M, threadIdx.x, T);
 #pragma unroll
@@ -596,11 +598,12 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
 
     for (uint64_t i = 0; i < A.npairs; ++i) {
         const uint32_t *xrow = A.X + i * A.pair_stride + pq * A.N + rbase;
+        const uint32_t *arow = A.A + i * A.pair_stride + pq * A.N + rbase;
         // steps 1 and 2 for the x row (side 0) and the a row (side 1), one
         // after the other to keep the register footprint small
 #pragma unroll 1
         for (int side = 0; side < 2; ++side) {
-            const __amdgpu_buffer_rsrc_t rg = rsrc_of(side ? xrow + A.a_off : xrow, R16_LEN);
+            const __amdgpu_buffer_rsrc_t rg = rsrc_of(side ? arow : xrow, R16_LEN);
             uint32_t *buf = side ? ba : bx;
             const uint32_t t4l = opaque(t4), s1l = opaque(s1);
             // step 1: from global, four-step twiddle, radix-16, step twiddles.
@@ -1158,6 +1161,7 @@ static ColFwdArgs col_args(pa_plan *p, uint32_t mode) {
     cf.B = p->B;
     cf.s_top = p->s_top;
     cf.mode = mode;
+    cf.arr0 = 0;
     cf.key = nullptr;
     cf.a = nullptr;
     cf.b = nullptr;
@@ -1178,13 +1182,13 @@ static void launch_col_fwd(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, h
         hipLaunchKernelGGL(k_col_fwd<Stage>, dim3(ncol_tiles, narrays, NPRIMES), dim3(COL_THREADS), col_lds, st, cf);
 }
 
-static RowArgs row_args(pa_plan *p, uint64_t npairs, uint64_t a_off) {
+static RowArgs row_args(pa_plan *p, uint64_t npairs, const uint32_t *seed_side) {
     RowArgs ra;
     ra.X = p->X;
+    ra.A = seed_side;
     ra.N = p->N;
     ra.npairs = npairs;
     ra.pair_stride = (uint64_t)NPRIMES * p->N;
-    ra.a_off = a_off;
     ra.m2 = p->m2;
     ra.out = p->Cc;
     ra.Wf = p->Wf;
@@ -1220,11 +1224,12 @@ hipError_t launch_mmh(pa_plan *p, const uint64_t *key, const uint64_t *a, hipStr
     cf.key = key;
     cf.a = a;
     phase_mark(p, PA_PH_MMH_COL, true, st);
-    launch_col_fwd<STAGE_MMH>(p, cf, (unsigned)(2 * p->k), st);
+    // with resident seed transforms only the k key chunks are transformed
+    launch_col_fwd<STAGE_MMH>(p, cf, (unsigned)(p->res_a ? p->k : 2 * p->k), st);
     phase_mark(p, PA_PH_MMH_COL, false, st);
     hipLaunchKernelGGL(k_status, dim3(1), dim3(256), 0, st, p->notones, p->k, p->status);
 
-    RowArgs ra = row_args(p, p->k, p->k * NPRIMES * p->N);
+    RowArgs ra = row_args(p, p->k, p->res_a ? p->res_a : p->X + p->k * NPRIMES * p->N);
     phase_mark(p, PA_PH_MMH_ROW, true, st);
     launch_row<STAGE_MMH>(p, ra, st);
     phase_mark(p, PA_PH_MMH_ROW, false, st);
@@ -1260,10 +1265,10 @@ hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, hipStream
     cf.b = b;
     cf.ylimbs = p->y;
     phase_mark(p, PA_PH_MH_COL, true, st);
-    launch_col_fwd<STAGE_MH>(p, cf, 2u, st);
+    launch_col_fwd<STAGE_MH>(p, cf, p->res_b ? 1u : 2u, st);
     phase_mark(p, PA_PH_MH_COL, false, st);
 
-    RowArgs ra = row_args(p, 1, (uint64_t)NPRIMES * p->N);
+    RowArgs ra = row_args(p, 1, p->res_b ? p->res_b : p->X + (uint64_t)NPRIMES * p->N);
     phase_mark(p, PA_PH_MH_ROW, true, st);
     launch_row<STAGE_MH>(p, ra, st);
     phase_mark(p, PA_PH_MH_ROW, false, st);
@@ -1299,6 +1304,26 @@ hipError_t launch_finish(pa_plan *p, uint64_t *out, uint32_t *d_status, uint64_t
                            p->B, p->status);
     hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(1), 0, st, p->status, d_status ? d_status : p->status_out);
     phase_mark(p, PA_PH_FINISH, false, st);
+    return hipGetLastError();
+}
+
+// Column-pass outputs of a session's seeds, computed once and kept: the k_max
+// seed chunks a_i (MMH stage) into dst_a (k_max x 3 x N words) and b (MH
+// stage) into dst_b (3 x N words), for transforms of p's shape.  A hash with
+// p->res_a / p->res_b set then transforms only its key chunks and y.
+hipError_t launch_seed_transforms(pa_plan *p, const uint64_t *a, uint64_t kmax, const uint64_t *b,
+                                  uint32_t *dst_a, uint32_t *dst_b, hipStream_t st) {
+    ColFwdArgs cf = col_args(p, 0);
+    cf.X = dst_a;
+    cf.k = kmax;
+    cf.arr0 = (uint32_t)kmax;  // arrays kmax .. 2 kmax - 1 are the seed chunks
+    cf.a = a;
+    launch_col_fwd<STAGE_MMH>(p, cf, (unsigned)kmax, st);
+    ColFwdArgs cb = col_args(p, 1);
+    cb.X = dst_b;
+    cb.arr0 = 1;  // array 1 of the MH stage is b
+    cb.b = b;
+    launch_col_fwd<STAGE_MH>(p, cb, 1u, st);
     return hipGetLastError();
 }
 

@@ -3,9 +3,10 @@
 // pa_submit queues a request (host key in, host output out) and returns a
 // ticket at once; a worker thread admits queued requests in arrival order
 // while a worker slot and the device-memory budget allow, and runs each one
-// on its slot's stream: key upload, the hash (with the session's seeds, which
-// stay resident on the device), output and status download, completion
-// event.  pa_poll reports PA_PENDING until the request is done, then its
+// on its slot's stream: key upload, the hash (with the session's seeds and
+// their transforms, which stay resident on the device, so a request costs
+// k + 3 transforms instead of 2k + 4), output and status download,
+// completion event.  pa_poll reports PA_PENDING until the request is done, then its
 // status and timing.  Each admitted request's device memory (scratch, key,
 // output) is placed first-fit in one arena of the configured budget, so the
 // budget is exact.  Twiddle tables are built once per transform length and
@@ -38,6 +39,9 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Seeds {
     uint64_t gamma, kmax;
     uint64_t *d_a, *d_b, *d_c;  // one device allocation: kmax*W + W + W words
+    // column-pass transforms of a (kmax x 3 x N words) and b (3 x N words),
+    // per transform shape (limb width B << 8 | log2 N), built on first use
+    std::map<uint32_t, uint32_t *> trans;
 };
 
 struct Request {
@@ -135,13 +139,40 @@ void finish(pa_server *s, Request &r, pa_status st, double device_ms) {
     s->done[r.ticket] = d;
 }
 
+// Resident seed transforms of sd for r's shape; built synchronously on `st`
+// the first time (worker thread only).
+uint32_t *seed_transforms(Seeds &sd, Request &r, hipStream_t st) {
+    const uint32_t key = r.plan.B << 8 | r.plan.m;
+    auto it = sd.trans.find(key);
+    if (it != sd.trans.end()) return it->second;
+    const size_t words = (size_t)(sd.kmax + 1) * pa::NPRIMES * r.plan.N;
+    uint32_t *d = nullptr;
+    if (hipMalloc((void **)&d, words * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    uint32_t *db = d + (size_t)sd.kmax * pa::NPRIMES * r.plan.N;
+    if (pa::launch_seed_transforms(&r.plan, sd.d_a, sd.kmax, sd.d_b, d, db, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(d);
+        return nullptr;
+    }
+    sd.trans[key] = d;
+    return d;
+}
+
 // Enqueue request r on slot sl (worker thread).  Returns PA_OK or an error
 // (then nothing of r is in flight).
-pa_status launch(pa_server *s, Slot &sl, Request &r, const Seeds &sd) {
+pa_status launch(pa_server *s, Slot &sl, Request &r, Seeds &sd) {
     // r's arena range: scratch, then the key, then the output
     void *tb = tables_for(s, r, sl.st);
     if (!tb) return PA_ERR_NOMEM;
     pa::bind_tables(&r.plan, tb, r.lay);
+    uint32_t *tr = seed_transforms(sd, r, sl.st);
+    if (!tr) return PA_ERR_NOMEM;
+    r.plan.res_a = tr;
+    r.plan.res_b = tr + (size_t)sd.kmax * pa::NPRIMES * r.plan.N;
     char *base = (char *)s->arena + r.offset;
     pa::bind_scratch(&r.plan, base, r.lay);
     uint64_t *d_key = (uint64_t *)(base + r.lay.scratch_bytes);
@@ -206,8 +237,9 @@ void worker_main(pa_server *s) {
             Request r = head;
             r.offset = off;
             s->queue.pop_front();
-            auto it = s->seeds.find(seed_key(r.req.session, r.plan.gamma));
-            Seeds sd = it->second;  // presence checked at submission; seeds are never removed
+            // presence checked at submission; seeds are never removed, and map
+            // nodes stay put, so the reference outlives the lock
+            Seeds &sd = s->seeds.find(seed_key(r.req.session, r.plan.gamma))->second;
             r.t_admit = Clock::now();
             free_slot->busy = true;
             free_slot->cur = r;
@@ -255,7 +287,10 @@ void release(pa_server *s) {
         if (sl.st) (void)hipStreamDestroy(sl.st);
     }
     for (auto &t : s->tables) (void)hipFree(t.second);
-    for (auto &kv : s->seeds) (void)hipFree(kv.second.d_a);
+    for (auto &kv : s->seeds) {
+        (void)hipFree(kv.second.d_a);
+        for (auto &t : kv.second.trans) (void)hipFree(t.second);
+    }
     if (s->arena) (void)hipFree(s->arena);
     (void)hipGetLastError();
     delete s;
@@ -344,7 +379,12 @@ pa_status pa_server_set_seeds(pa_server *s, uint32_t session, uint64_t gamma, ui
         (void)hipFree(d);
         return PA_ERR_BUSY;
     }
-    s->seeds[key] = Seeds{gamma, kmax, d, d + kmax * W, d + (kmax + 1) * W};
+    Seeds &sd = s->seeds[key];
+    sd.gamma = gamma;
+    sd.kmax = kmax;
+    sd.d_a = d;
+    sd.d_b = d + kmax * W;
+    sd.d_c = d + (kmax + 1) * W;
     return PA_OK;
 }
 
