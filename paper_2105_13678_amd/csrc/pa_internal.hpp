@@ -70,18 +70,10 @@ struct CFn {
 constexpr uint32_t CF_INF = 0xFFFFFFFFu;
 constexpr uint32_t CF_ID = 0xFFFFFFFFu;
 
-// Result block written by the tile-prefix kernel of a carry scan.
-struct ScanResult {
-    uint32_t carry_top[2];  // carry into the top limb for global carry-in 0 and 1
-    uint32_t ov[2];         // value above the top limb's width for carry-in 0 and 1
-    uint32_t sel;           // dual mode: 1 if the carry-in-1 variant is selected
-    uint32_t final_carry;   // carry out of the last regular limb (carry-in 0)
-    uint32_t pad[2];
-};
-
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_PER_THREAD = 16;
-constexpr int SCAN_TILE = SCAN_THREADS * SCAN_PER_THREAD;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_PER_THREAD;  // digits normalised per workgroup
+constexpr int DIG_TILE = SCAN_THREADS;  // digits (one per thread) per carry aggregate
 
 // Device status flag bits (written by the prologue and status kernels).
 constexpr uint32_t ST_SEED_RANGE = 1u;
@@ -112,14 +104,12 @@ struct pa_plan {
     size_t workspace_bytes;
     uint32_t *X;        // 2k arrays x 3 primes x N words: column-pass outputs of x_i (0..k-1), a_i (k..2k-1)
     uint32_t *Cc;       // 3 x N words: convolution residues
-    uint32_t *C96;      // 3 x N words: reconstructed coefficients, word planes (bits 0-31, 32-63, 64-95)
     uint64_t *t;        // digit sums (max(M1, L) + pad)
     uint32_t *s;        // normalised limbs of the folded sum (M1)
     uint32_t *y;        // MMH output limbs (L)
     uint32_t *U;        // MH value limbs (L)
-    pa::CFn *agg;       // per-tile carry functions
-    uint32_t *tcarry;   // per-tile carry-in, two variants
-    pa::ScanResult *res;
+    uint32_t *C96;      // 3 x N words: reconstructed coefficients, word planes (bits 0-31, 32-63, 64-95)
+    pa::CFn *agg;       // carry functions of DIG_TILE-digit tiles
     uint32_t *notones;  // k flags: chunk i has a limb that is not all ones
     uint32_t *status;   // seed/reload flags
     uint32_t *status_out;  // final flags of the last call (pa_hash reads it back)
@@ -146,7 +136,7 @@ namespace pa {
 // [0, scratch_bytes), the read-only twiddle tables (which depend only on the
 // transform length) the following table_bytes.
 struct PlanLayout {
-    size_t oX, oC, oC96, oT, oS, oY, oU, oAgg, oTc, oRes, oNo, oSt, oSo;
+    size_t oX, oC, oC96, oT, oS, oY, oU, oAgg, oNo, oSt, oSo;
     size_t oT1, oT2, oW;
     size_t scratch_bytes, table_bytes, total;
 };

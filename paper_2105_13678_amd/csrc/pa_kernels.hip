@@ -37,7 +37,6 @@ namespace {
 constexpr int COL_THREADS = 256;
 constexpr int ROW_EPT = 16;  // row elements per thread
 constexpr int ROW_MAX_THREADS = 1024;
-constexpr int PREFIX_THREADS = 1024;
 
 // The transform kernels are instantiated once per hash stage (the MMH sum of
 // eq. 2 and the MH product of eq. 4) so that profiles report the two stages'
@@ -766,32 +765,6 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_inv(ColInvArgs A) {
     }
 }
 
-// Chinese-remainder reconstruction (Garner): residues mod p0, p1, p2 of a
-// coefficient below p0 p1 p2 -> its exact value, stored as three word planes.
-__global__ void k_crt(const uint32_t *__restrict__ cc, uint32_t *c96, uint64_t N, uint64_t count, PrimeSet P,
-                      CrtConst K) {
-    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= count) return;
-    const PrimeConst &M1 = P.c[1], &M2 = P.c[2];
-    const uint32_t r0 = cc[j], r1 = cc[N + j], r2 = cc[2 * N + j];  // canonical residues
-    // v1 = (r1 - r0) / p0 mod p1
-    const uint32_t v1 = mmul(msub(r1, mmul(r0, M1.one, M1), M1), K.inv_p0_mod_p1, M1);
-    // v2 = (r2 - r0 - v1 p0) / (p0 p1) mod p2
-    const uint32_t r0m = mmul(r0, M2.one, M2);
-    const uint32_t v1p0 = mmul(v1, K.p0_mod_p2, M2);
-    const uint32_t v2 = mmul(msub(msub(r2, r0m, M2), v1p0, M2), K.inv_p0p1_mod_p2, M2);
-    const unsigned __int128 c = (unsigned __int128)r0 + (unsigned __int128)v1 * P.c[0].p +
-                                (unsigned __int128)v2 * K.p0p1;
-    c96[j] = (uint32_t)c;
-    c96[N + j] = (uint32_t)(c >> 32);
-    c96[2 * N + j] = (uint32_t)(c >> 64);
-}
-
-__device__ __forceinline__ unsigned __int128 coef(const uint32_t *__restrict__ c96, uint64_t N, uint64_t j) {
-    return (unsigned __int128)c96[j] | ((unsigned __int128)c96[N + j] << 32) |
-           ((unsigned __int128)c96[2 * N + j] << 64);
-}
-
 // ------------------------------------------------------------------ carry scan
 
 __device__ __forceinline__ CFn cf_id() { return CFn{CF_ID, CF_INF}; }
@@ -854,125 +827,82 @@ struct ScanArgs {
     uint64_t M;
     uint32_t B, has_top, s_top, dual;
     uint64_t ntiles;
-    CFn *agg;
-    uint32_t *tcarry;
-    ScanResult *res;
+    const CFn *agg;
 };
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(ScanArgs A) {
-    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_PER_THREAD;
-    CFn f = cf_id();
-#pragma unroll
-    for (int v = 0; v < SCAN_PER_THREAD; ++v) {
-        uint64_t idx = base + v;
-        if (idx < A.M) f = cf_compose(f, cf_limb(A.t[idx], A.B));
-    }
-    CFn excl, total;
-    block_scan<SCAN_THREADS>(f, excl, total);
-    if (threadIdx.x == 0) A.agg[blockIdx.x] = total;
+// ------------------------------------------------------------------ fused digit tiles
+// A carry normalisation runs in two launches (after the Chinese-remainder
+// kernel where the digits come from product coefficients).  The digit kernel
+// produces one digit sum per thread and the composed carry function of each
+// DIG_TILE-digit tile; the apply kernel composes the aggregates of the tiles
+// before its own SCAN_TILE digits (and of all tiles, for the top limb), then
+// normalises them.  No workgroup waits for another.
+
+// Chinese-remainder reconstruction (Garner): canonical residues mod p0, p1,
+// p2 of a coefficient below p0 p1 p2 -> its exact value, as three word planes.
+__global__ void k_crt(const uint32_t *__restrict__ cc, uint32_t *c96, uint64_t N, uint64_t count, PrimeSet P,
+                      CrtConst K) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    const PrimeConst &M1 = P.c[1], &M2 = P.c[2];
+    const uint32_t r0 = cc[j], r1 = cc[N + j], r2 = cc[2 * N + j];
+    // v1 = (r1 - r0) / p0 mod p1
+    const uint32_t v1 = mmul(msub(r1, mmul(r0, M1.one, M1), M1), K.inv_p0_mod_p1, M1);
+    // v2 = (r2 - r0 - v1 p0) / (p0 p1) mod p2
+    const uint32_t r0m = mmul(r0, M2.one, M2);
+    const uint32_t v1p0 = mmul(v1, K.p0_mod_p2, M2);
+    const uint32_t v2 = mmul(msub(msub(r2, r0m, M2), v1p0, M2), K.inv_p0p1_mod_p2, M2);
+    const unsigned __int128 c = (unsigned __int128)r0 + (unsigned __int128)v1 * P.c[0].p +
+                                (unsigned __int128)v2 * K.p0p1;
+    c96[j] = (uint32_t)c;
+    c96[N + j] = (uint32_t)(c >> 32);
+    c96[2 * N + j] = (uint32_t)(c >> 64);
 }
 
-// One workgroup: carry into every tile for global carry-in 0 (and 1 in dual
-// mode), then the top limb and the selection of the dual variant.
-__global__ __launch_bounds__(PREFIX_THREADS) void k_scan_prefix(ScanArgs A) {
-    const uint64_t per = (A.ntiles + PREFIX_THREADS - 1) / PREFIX_THREADS;
-    const uint64_t t0 = min((uint64_t)threadIdx.x * per, A.ntiles);
-    const uint64_t t1 = min(t0 + per, A.ntiles);
-    CFn f = cf_id();
-    for (uint64_t j = t0; j < t1; ++j) f = cf_compose(f, A.agg[j]);
-    CFn excl, total;
-    block_scan<PREFIX_THREADS>(f, excl, total);
-    const uint32_t nvar = A.dual ? 2u : 1u;
-    for (uint32_t c = 0; c < nvar; ++c) {
-        uint32_t carry = cf_eval(excl, c);
-        for (uint64_t j = t0; j < t1; ++j) {
-            A.tcarry[2 * j + c] = carry;
-            carry = cf_eval(A.agg[j], carry);
-        }
-    }
-    if (threadIdx.x == 0) {
-        ScanResult r;
-        r.final_carry = cf_eval(total, 0u);
-        r.sel = 0u;
-        r.carry_top[0] = r.carry_top[1] = 0u;
-        r.ov[0] = r.ov[1] = 0u;
-        r.pad[0] = r.pad[1] = 0u;
-        if (A.has_top) {
-            const uint64_t tt = A.t[A.M];
-            for (uint32_t c = 0; c < 2; ++c) {
-                uint32_t ct = cf_eval(total, c);
-                uint64_t v = tt + ct;
-                r.carry_top[c] = ct;
-                r.ov[c] = (uint32_t)(v >> A.s_top);
-            }
-            r.sel = (A.dual && r.ov[1] != 0u) ? 1u : 0u;
-            A.out[A.M] = (uint32_t)((tt + r.carry_top[r.sel]) & ((1ull << A.s_top) - 1));
-        }
-        *A.res = r;
-    }
+__device__ __forceinline__ unsigned __int128 coef(const uint32_t *__restrict__ c96, uint64_t N, uint64_t j) {
+    return (unsigned __int128)c96[j] | ((unsigned __int128)c96[N + j] << 32) |
+           ((unsigned __int128)c96[2 * N + j] << 64);
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(ScanArgs A) {
-    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_PER_THREAD;
-    uint64_t tv[SCAN_PER_THREAD];
-    CFn f = cf_id();
-#pragma unroll
-    for (int v = 0; v < SCAN_PER_THREAD; ++v) {
-        uint64_t idx = base + v;
-        tv[v] = idx < A.M ? A.t[idx] : 0ull;
-        if (idx < A.M) f = cf_compose(f, cf_limb(tv[v], A.B));
-    }
-    CFn excl, total;
-    block_scan<SCAN_THREADS>(f, excl, total);
-    const uint32_t sel = A.dual ? A.res->sel : 0u;
-    uint32_t carry = cf_eval(excl, A.tcarry[2 * blockIdx.x + sel]);
+constexpr int DIG_FOLD = 0, DIG_WRAP = 1, DIG_MH = 2;
+
+struct DigitArgs {
+    const uint32_t *c96;  // product coefficients, three word planes (FOLD, MH)
+    const uint32_t *s;    // normalised limbs of the folded sum (WRAP)
+    const uint64_t *cseed;  // c (MH)
+    uint64_t *t;          // digit sums out
+    CFn *agg;             // tile carry functions out
+    uint64_t N, ndig, M;  // digits produced; digits in the carry chain (the rest is the top limb)
+    uint64_t L, ncoef, gamma, M1;
+    uint32_t B, e, Q, Q2, s_top;
+};
+
+// Digit m of the FOLD sum T = sum_{j<L} c_j 2^(Bj) + sum_{j>=L} c_j 2^(B(j-L)+e)
+// (S folded once at bit gamma; 2^gamma = 1 mod p, e = BL - gamma): the B-bit
+// pieces of the coefficients that overlap digit m.
+__device__ __forceinline__ uint64_t fold_digit(const DigitArgs &A, uint64_t m) {
     const uint64_t mask = (1ull << A.B) - 1;
-#pragma unroll
-    for (int v = 0; v < SCAN_PER_THREAD; ++v) {
-        uint64_t idx = base + v;
-        if (idx < A.M) {
-            uint64_t val = tv[v] + carry;
-            A.out[idx] = (uint32_t)(val & mask);
-            carry = (uint32_t)(val >> A.B);
-        }
-    }
-}
-
-// ------------------------------------------------------------------ fold / MH digits
-
-// Digit sums of T = sum_{j<L} c_j 2^(Bj) + sum_{j>=L} c_j 2^(B(j-L)+e), which is
-// S folded once at bit gamma (2^gamma = 1 mod p; e = BL - gamma).  Each
-// coefficient (below 2^91) is cut into B-bit pieces on consecutive digits.
-// ncoef bounds the coefficient index (coefficients from 2L - 1 on are zero).
-__global__ void k_fold_gather(const uint32_t *__restrict__ c96, uint64_t N, uint64_t *t, uint64_t M, uint64_t L,
-                              uint64_t ncoef, uint32_t B, uint32_t e, uint32_t Q, uint32_t Q2) {
-    uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M) return;
-    const uint64_t mask = (1ull << B) - 1;
     uint64_t sum = 0;
-    for (uint32_t q = 0; q < Q; ++q) {
-        if (m >= q && m - q < L) sum += (uint64_t)(coef(c96, N, m - q) >> (B * q)) & mask;
-    }
-    for (uint32_t q = 0; q < Q2; ++q) {
+    for (uint32_t q = 0; q < A.Q; ++q)
+        if (m >= q && m - q < A.L) sum += (uint64_t)(coef(A.c96, A.N, m - q) >> (A.B * q)) & mask;
+    for (uint32_t q = 0; q < A.Q2; ++q) {
         if (m >= q) {
-            uint64_t j = L + m - q;
-            if (j < ncoef) sum += (uint64_t)((coef(c96, N, j) << e) >> (B * q)) & mask;
+            const uint64_t j = A.L + m - q;
+            if (j < A.ncoef) sum += (uint64_t)((coef(A.c96, A.N, j) << A.e) >> (A.B * q)) & mask;
         }
     }
-    t[m] = sum;
+    return sum;
 }
 
-// Second fold: T = T_lo + 2^gamma V with T_lo = T mod 2^gamma; digits of
-// T_lo + (V mod p) over L limbs (the top limb holds s_top bits).
-__global__ void k_wrap_gather(const uint32_t *__restrict__ s, uint64_t *t, uint64_t L, uint64_t M, uint32_t B,
-                              uint64_t gamma, uint32_t s_top) {
-    uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= L) return;
-    // V = bits [gamma, B*M) of the normalised T; it is below 2^92.
+// WRAP digit m < L: T = T_lo + 2^gamma V with T_lo = T mod 2^gamma (V < 2^92);
+// the digits of T_lo + (V mod p).
+__device__ __forceinline__ uint64_t wrap_digit(const DigitArgs &A, uint64_t m) {
+    const uint32_t B = A.B;
+    const uint64_t gamma = A.gamma;
     unsigned __int128 V = 0;
-    for (uint64_t idx = gamma / B; idx < M; ++idx) {
-        uint64_t lo_bit = idx * B;
-        unsigned __int128 limb = s[idx];
+    for (uint64_t idx = gamma / B; idx < A.M1; ++idx) {
+        const uint64_t lo_bit = idx * B;
+        const unsigned __int128 limb = A.s[idx];
         if (lo_bit < gamma) V += limb >> (gamma - lo_bit);
         else if (lo_bit - gamma < 128) V += limb << (lo_bit - gamma);  // higher limbs are zero
     }
@@ -981,23 +911,89 @@ __global__ void k_wrap_gather(const uint32_t *__restrict__ s, uint64_t *t, uint6
         while (V >> gamma) V = (V & pm) + (V >> gamma);
         if (V == pm) V = 0;
     }
-    const uint64_t lo = (m + 1 < L) ? s[m] : (s[m] & ((1ull << s_top) - 1));
+    const uint64_t lo = (m + 1 < A.L) ? A.s[m] : (A.s[m] & ((1ull << A.s_top) - 1));
     const uint64_t vl = (B * m < 128) ? (uint64_t)((V >> (B * m)) & ((1ull << B) - 1)) : 0ull;
-    t[m] = lo + vl;
+    return lo + vl;
 }
 
-// MH digits: pieces of the product coefficients below limb L plus the limbs of
-// c; everything at or above bit gamma is dropped later (mod 2^gamma).
-__global__ void k_mh_gather(const uint32_t *__restrict__ c96, uint64_t N, const uint64_t *__restrict__ cseed,
-                            uint64_t *t, uint64_t L, uint32_t B, uint64_t gamma, uint32_t Q) {
-    uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= L) return;
-    const uint64_t mask = (1ull << B) - 1;
-    uint64_t sum = bits_at(cseed, gamma, m * B, B);
-    for (uint32_t q = 0; q < Q; ++q) {
-        if (m >= q) sum += (uint64_t)(coef(c96, N, m - q) >> (B * q)) & mask;
+// MH digit m < L: the limbs of c plus the pieces of the product coefficients
+// below limb L (everything at or above bit gamma is dropped, mod 2^gamma).
+__device__ __forceinline__ uint64_t mh_digit(const DigitArgs &A, uint64_t m) {
+    const uint64_t mask = (1ull << A.B) - 1;
+    uint64_t sum = bits_at(A.cseed, A.gamma, m * A.B, A.B);
+    for (uint32_t q = 0; q < A.Q; ++q)
+        if (m >= q) sum += (uint64_t)(coef(A.c96, A.N, m - q) >> (A.B * q)) & mask;
+    return sum;
+}
+
+// One digit per thread; workgroup b covers digits [b DIG_TILE, +DIG_TILE) and
+// writes their composed carry function (digits below M only).
+template <int MODE>
+__global__ __launch_bounds__(SCAN_THREADS) void k_digit_tile(DigitArgs A) {
+    const uint64_t m = (uint64_t)blockIdx.x * DIG_TILE + threadIdx.x;
+    CFn f = cf_id();
+    if (m < A.ndig) {
+        const uint64_t d = MODE == DIG_FOLD ? fold_digit(A, m) : MODE == DIG_WRAP ? wrap_digit(A, m) : mh_digit(A, m);
+        A.t[m] = d;
+        if (m < A.M) f = cf_limb(d, A.B);
     }
-    t[m] = sum;
+    CFn excl, total;
+    block_scan<SCAN_THREADS>(f, excl, total);
+    if (threadIdx.x == 0) A.agg[blockIdx.x] = total;
+}
+
+// Normalise one tile of a carry chain: carry into the tile = the composed
+// functions of all earlier tiles evaluated at the chain's carry-in; with a
+// top limb (index M, s_top bits) every workgroup also evaluates the whole
+// chain, and in dual mode takes carry-in 1 when carry-in 0 leaves a nonzero
+// value above the top limb's width (see launch_fold).  Workgroup 0 writes the
+// top limb.  Launched with max(1, ntiles) workgroups.
+__global__ __launch_bounds__(SCAN_THREADS) void k_carry_apply(ScanArgs A) {
+    const uint64_t b = blockIdx.x;
+    const uint64_t nagg = (A.M + DIG_TILE - 1) / DIG_TILE;  // digit-tile aggregates of the chain
+    const uint64_t first = b * (SCAN_TILE / DIG_TILE);       // those before this workgroup's digits
+    const uint64_t per = (nagg + SCAN_THREADS - 1) / SCAN_THREADS;
+    const uint64_t j0 = min((uint64_t)threadIdx.x * per, nagg), j1 = min(j0 + per, nagg);
+    CFn fb = cf_id(), fa = cf_id();
+    for (uint64_t j = j0; j < j1; ++j) {
+        const CFn g = A.agg[j];
+        if (j < first) fb = cf_compose(fb, g);
+        fa = cf_compose(fa, g);
+    }
+    CFn ex, before, all;
+    block_scan<SCAN_THREADS>(fb, ex, before);
+    block_scan<SCAN_THREADS>(fa, ex, all);
+    uint32_t sel = 0;
+    if (A.has_top) {
+        const uint64_t tt = A.t[A.M];
+        const uint32_t ct0 = cf_eval(all, 0u), ct1 = cf_eval(all, 1u);
+        sel = (A.dual && ((tt + ct1) >> A.s_top) != 0u) ? 1u : 0u;
+        if (b == 0 && threadIdx.x == 0)
+            A.out[A.M] = (uint32_t)((tt + (sel ? ct1 : ct0)) & ((1ull << A.s_top) - 1));
+    }
+    if (b >= A.ntiles) return;
+    const uint64_t base = b * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_PER_THREAD;
+    uint64_t tv[SCAN_PER_THREAD];
+    CFn f = cf_id();
+#pragma unroll
+    for (int v = 0; v < SCAN_PER_THREAD; ++v) {
+        const uint64_t idx = base + v;
+        tv[v] = idx < A.M ? A.t[idx] : 0ull;
+        if (idx < A.M) f = cf_compose(f, cf_limb(tv[v], A.B));
+    }
+    CFn excl, total;
+    block_scan<SCAN_THREADS>(f, excl, total);
+    uint32_t carry = cf_eval(excl, cf_eval(before, sel));
+    const uint64_t mask = (1ull << A.B) - 1;
+#pragma unroll
+    for (int v = 0; v < SCAN_PER_THREAD; ++v) {
+        const uint64_t idx = base + v;
+        if (idx < A.M) {
+            const uint64_t val = tv[v] + carry;
+            A.out[idx] = (uint32_t)(val & mask);
+            carry = (uint32_t)(val >> A.B);
+        }
+    }
 }
 
 // ------------------------------------------------------------------ output
@@ -1022,26 +1018,6 @@ __global__ void k_pack(const uint32_t *__restrict__ limbs, uint64_t *out, uint64
 __global__ void k_copy_status(const uint32_t *status, uint32_t *dst) { *dst = status[1]; }
 
 inline unsigned blocks_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
-
-hipError_t run_scan(pa_plan *p, const uint64_t *t, uint32_t *out, uint64_t M, bool top, bool dual,
-                    hipStream_t st) {
-    ScanArgs A;
-    A.t = t;
-    A.out = out;
-    A.M = M;
-    A.B = p->B;
-    A.has_top = top ? 1u : 0u;
-    A.s_top = p->s_top;
-    A.dual = dual ? 1u : 0u;
-    A.ntiles = (M + SCAN_TILE - 1) / SCAN_TILE;
-    A.agg = p->agg;
-    A.tcarry = p->tcarry;
-    A.res = p->res;
-    if (A.ntiles) hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)A.ntiles), dim3(SCAN_THREADS), 0, st, A);
-    hipLaunchKernelGGL(k_scan_prefix, dim3(1), dim3(PREFIX_THREADS), 0, st, A);
-    if (A.ntiles) hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)A.ntiles), dim3(SCAN_THREADS), 0, st, A);
-    return hipGetLastError();
-}
 
 unsigned row_threads(const pa_plan *p) {
     unsigned n2 = 1u << p->m2;
@@ -1242,20 +1218,61 @@ hipError_t launch_mmh(pa_plan *p, const uint64_t *key, const uint64_t *a, hipStr
     return hipGetLastError();
 }
 
+static DigitArgs digit_args(pa_plan *p) {
+    DigitArgs A;
+    A.c96 = p->C96;
+    A.s = p->s;
+    A.cseed = nullptr;
+    A.t = p->t;
+    A.agg = p->agg;
+    A.N = p->N;
+    A.L = p->L;
+    A.ncoef = 2 * p->L - 1;  // nonzero coefficients of the product
+    A.gamma = p->gamma;
+    A.M1 = p->M1;
+    A.B = p->B;
+    A.e = p->e_fold;
+    A.Q = (96 + p->B - 1) / p->B;
+    A.Q2 = (96 + p->e_fold + p->B - 1) / p->B;
+    A.s_top = p->s_top;
+    return A;
+}
+
+// Carry normalisation of the digit sums A.t[0..M) (plus the top limb at M if
+// top) into `out`: the tile kernel (digits and tile aggregates), then apply.
+template <int MODE>
+static hipError_t run_carry(pa_plan *p, DigitArgs A, uint32_t *out, uint64_t ndig, uint64_t M, bool top,
+                            bool dual, hipStream_t st) {
+    A.ndig = ndig;
+    A.M = M;
+    const uint64_t tiles_t = (ndig + DIG_TILE - 1) / DIG_TILE;
+    if (tiles_t) hipLaunchKernelGGL(k_digit_tile<MODE>, dim3((unsigned)tiles_t), dim3(SCAN_THREADS), 0, st, A);
+    ScanArgs S;
+    S.t = p->t;
+    S.out = out;
+    S.M = M;
+    S.B = p->B;
+    S.has_top = top ? 1u : 0u;
+    S.s_top = p->s_top;
+    S.dual = dual ? 1u : 0u;
+    S.ntiles = (M + SCAN_TILE - 1) / SCAN_TILE;
+    S.agg = p->agg;
+    const unsigned grid = (unsigned)(S.ntiles ? S.ntiles : 1);
+    hipLaunchKernelGGL(k_carry_apply, dim3(grid), dim3(SCAN_THREADS), 0, st, S);
+    return hipGetLastError();
+}
+
 hipError_t launch_fold(pa_plan *p, hipStream_t st) {
-    const uint32_t Q = (96 + p->B - 1) / p->B;
-    const uint32_t Q2 = (96 + p->e_fold + p->B - 1) / p->B;
-    const uint64_t ncoef = 2 * p->L - 1;  // nonzero coefficients of the product
     phase_mark(p, PA_PH_FOLD, true, st);
+    const uint64_t ncoef = 2 * p->L - 1;  // nonzero coefficients of the product
     hipLaunchKernelGGL(k_crt, dim3(blocks_for(ncoef, 256)), dim3(256), 0, st, p->Cc, p->C96, p->N, ncoef,
                        p->primes, p->crt);
-    hipLaunchKernelGGL(k_fold_gather, dim3(blocks_for(p->M1, 256)), dim3(256), 0, st, p->C96, p->N, p->t, p->M1,
-                       p->L, ncoef, p->B, p->e_fold, Q, Q2);
-    hipError_t e = run_scan(p, p->t, p->s, p->M1, false, false, st);
+    // first fold at bit gamma, normalised over M1 digits (the sum fits: no carry out)
+    hipError_t e = run_carry<DIG_FOLD>(p, digit_args(p), p->s, p->M1, p->M1, false, false, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_wrap_gather, dim3(blocks_for(p->L, 256)), dim3(256), 0, st, p->s, p->t, p->L, p->M1,
-                       p->B, p->gamma, p->s_top);
-    e = run_scan(p, p->t, p->y, p->L - 1, true, true, st);
+    // second fold: y = T_lo + (V mod p) over L limbs; the dual evaluation (carry-in
+    // 0 or 1) selects S or S + 1 - 2^gamma, which maps a sum equal to p to 0
+    e = run_carry<DIG_WRAP>(p, digit_args(p), p->y, p->L, p->L - 1, true, true, st);
     phase_mark(p, PA_PH_FOLD, false, st);
     return e;
 }
@@ -1279,14 +1296,13 @@ hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, hipStream
                        ((size_t)4 << p->m1) << p->ci_lg, st, ci);
     phase_mark(p, PA_PH_MH_COLINV, false, st);
 
-    const uint32_t Q = (96 + p->B - 1) / p->B;
     phase_mark(p, PA_PH_MH_CARRY, true, st);
     // only the coefficients below limb L matter mod 2^gamma
     hipLaunchKernelGGL(k_crt, dim3(blocks_for(p->L, 256)), dim3(256), 0, st, p->Cc, p->C96, p->N, p->L, p->primes,
                        p->crt);
-    hipLaunchKernelGGL(k_mh_gather, dim3(blocks_for(p->L, 256)), dim3(256), 0, st, p->C96, p->N, c, p->t, p->L,
-                       p->B, p->gamma, Q);
-    hipError_t e = run_scan(p, p->t, p->U, p->L - 1, true, false, st);
+    DigitArgs A = digit_args(p);
+    A.cseed = c;
+    hipError_t e = run_carry<DIG_MH>(p, A, p->U, p->L, p->L - 1, true, false, st);
     phase_mark(p, PA_PH_MH_CARRY, false, st);
     return e;
 }
