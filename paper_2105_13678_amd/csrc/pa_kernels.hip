@@ -278,7 +278,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
     const uint32_t c_lg = A.c_lg, lg = A.m1;
     const uint32_t cmask = (1u << c_lg) - 1;
     const uint64_t c0 = (uint64_t)tile << c_lg;
-    const bool is_key = (A.mode == 0) && arr < A.k;
+    const bool is_key = (A.mode == 0) && arr < A.k && pq == 0;  // the reload check runs once per chunk
     const uint32_t full = (uint32_t)((1ull << A.B) - 1), topv = (uint32_t)((1ull << A.s_top) - 1);
     const uint32_t lgMp = lg - 3;
     const uint32_t ntask = (1u << lgMp) << c_lg;
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
             for (int jj = 0; jj < 8; ++jj) out[((uint64_t)jj << A.m2) + c0 + q] = v[jj];
         }
     }
-    if (is_key && pq == 0) {
+    if (is_key) {
         int any = __syncthreads_or(not_ones);
         if (any && threadIdx.x == 0) A.notones[arr] = 1u;
     } else {
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
     const PrimeConst M = A.P.c[pq];
     const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.tw + ((uint64_t)pq << C9_LG), 1u << C9_LG);
     const uint64_t c0 = (uint64_t)tile << C9_CLG;
-    const bool is_key = (A.mode == 0) && arr < A.k;
+    const bool is_key = (A.mode == 0) && arr < A.k && pq == 0;  // the reload check runs once per chunk
     const uint32_t full = (uint32_t)((1ull << A.B) - 1), topv = (uint32_t)((1ull << A.s_top) - 1);
     uint32_t *out = A.X + ((uint64_t)blockIdx.y * NPRIMES + pq) * A.N;
     const uint32_t t = threadIdx.x;
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj) lds[sb ^ (1024u * jj)] = v[jj];
     }
-    if (is_key && pq == 0) {
+    if (is_key) {
         int any = __syncthreads_or(not_ones);
         if (any && t == 0) A.notones[arr] = 1u;
     } else {
@@ -838,6 +838,68 @@ struct ScanArgs {
 // before its own SCAN_TILE digits (and of all tiles, for the top limb), then
 // normalises them.  No workgroup waits for another.
 
+// Inverse column pass for 512-row tiles of 16 columns (N1 = 2^9), the mirror
+// of k_col9_fwd with the same task decomposition and LDS layout: the
+// sub-length-8 step straight from global memory, the sub-length-64 step, and
+// the sub-length-512 step straight back to global memory as canonical
+// residues.  Inverse twiddles multiply a task's inputs (fused into the first
+// DIT stage).
+template <int Stage>
+__global__ __launch_bounds__(COL_THREADS) void k_col9_inv(ColInvArgs A) {
+    uint32_t *lds = lds_dyn;
+    const uint32_t pq = blockIdx.y;
+    const PrimeConst M = A.P.c[pq];
+    const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.twi + ((uint64_t)pq << C9_LG), 1u << C9_LG);
+    uint32_t *cc = A.Cc + pq * A.N;
+    const uint64_t c0 = (uint64_t)xcd_tile(blockIdx.x, gridDim.x) << C9_CLG;
+    const uint32_t t = threadIdx.x;
+#pragma unroll 1
+    for (uint32_t u = 0; u < 4; ++u) {  // sub-length 8: rows 8 b + j
+        const uint32_t tau = t + 256u * u;
+        const uint32_t q = tau & 15u, b = tau >> 4;
+        const uint32_t *src = cc + ((uint64_t)(8u * b) << A.m2) + c0 + q;
+        uint32_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = src[(uint64_t)j << A.m2];
+        dft_inv<8>(v, M);
+        const uint32_t sb = swz_c9(128u * b + q);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) lds[sb ^ (16u * j)] = v[j];
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (uint32_t u = 0; u < 4; ++u) {  // sub-length 64: rows 64 b + n1 + 8 j
+        const uint32_t tau = t + 256u * u;
+        const uint32_t q = tau & 15u, n1 = (tau >> 4) & 7u, b = tau >> 7;
+        const uint32_t sb = swz_c9(1024u * b + 16u * n1 + q);
+        uint32_t v[8], w[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = lds[sb ^ swz_c9(128u * j)];
+#pragma unroll
+        for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 5, 0);
+        dft_inv_tw<8>(v, w, M);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) lds[sb ^ swz_c9(128u * j)] = v[j];
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (uint32_t u = 0; u < 4; ++u) {  // sub-length 512: rows n1 + 64 j, to global memory
+        const uint32_t tau = t + 256u * u;
+        const uint32_t q = tau & 15u, n1 = tau >> 4;
+        const uint32_t sb = swz_c9(tau);
+        uint32_t v[8], w[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = lds[sb ^ (1024u * j)];
+#pragma unroll
+        for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 2, 0);
+        dft_inv_tw<8>(v, w, M);
+        uint32_t *dst = cc + ((uint64_t)n1 << A.m2) + c0 + q;
+        // canonical residues for the Chinese-remainder step
+#pragma unroll
+        for (int j = 0; j < 8; ++j) dst[(uint64_t)(64u * j) << A.m2] = canon(red2(v[j], M), M);
+    }
+}
+
 // Chinese-remainder reconstruction (Garner): canonical residues mod p0, p1,
 // p2 of a coefficient below p0 p1 p2 -> its exact value, as three word planes.
 __global__ void k_crt(const uint32_t *__restrict__ cc, uint32_t *c96, uint64_t N, uint64_t count, PrimeSet P,
@@ -1195,6 +1257,16 @@ static ColInvArgs colinv_args(pa_plan *p) {
     return ci;
 }
 
+template <int Stage>
+static void launch_col_inv(pa_plan *p, const ColInvArgs &ci, hipStream_t st) {
+    if (p->m1 == C9_LG && p->m2 >= C9_CLG)
+        hipLaunchKernelGGL(k_col9_inv<Stage>, dim3(1u << (p->m2 - C9_CLG), NPRIMES), dim3(COL_THREADS),
+                           (size_t)4 << (C9_LG + C9_CLG), st, ci);
+    else
+        hipLaunchKernelGGL(k_col_inv<Stage>, dim3(1u << (p->m2 - p->ci_lg), NPRIMES), dim3(COL_THREADS),
+                           ((size_t)4 << p->m1) << p->ci_lg, st, ci);
+}
+
 hipError_t launch_mmh(pa_plan *p, const uint64_t *key, const uint64_t *a, hipStream_t st) {
     ColFwdArgs cf = col_args(p, 0);
     cf.key = key;
@@ -1212,8 +1284,7 @@ hipError_t launch_mmh(pa_plan *p, const uint64_t *key, const uint64_t *a, hipStr
 
     ColInvArgs ci = colinv_args(p);
     phase_mark(p, PA_PH_MMH_COLINV, true, st);
-    hipLaunchKernelGGL(k_col_inv<STAGE_MMH>, dim3(1u << (p->m2 - p->ci_lg), NPRIMES), dim3(COL_THREADS),
-                       ((size_t)4 << p->m1) << p->ci_lg, st, ci);
+    launch_col_inv<STAGE_MMH>(p, ci, st);
     phase_mark(p, PA_PH_MMH_COLINV, false, st);
     return hipGetLastError();
 }
@@ -1292,8 +1363,7 @@ hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, hipStream
 
     ColInvArgs ci = colinv_args(p);
     phase_mark(p, PA_PH_MH_COLINV, true, st);
-    hipLaunchKernelGGL(k_col_inv<STAGE_MH>, dim3(1u << (p->m2 - p->ci_lg), NPRIMES), dim3(COL_THREADS),
-                       ((size_t)4 << p->m1) << p->ci_lg, st, ci);
+    launch_col_inv<STAGE_MH>(p, ci, st);
     phase_mark(p, PA_PH_MH_COLINV, false, st);
 
     phase_mark(p, PA_PH_MH_CARRY, true, st);
