@@ -217,6 +217,7 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     lay->oT1 = carve(P3 * n1 * 4 * 2);
     lay->oT2 = carve(P3 * n2 * 4 * 2);
     lay->oW = carve(P3 * N * 4 * 2);
+    lay->oR16 = carve(P3 * pa::R16_TW * 4 * 2);
     lay->total = off;
     lay->table_bytes = off - lay->scratch_bytes;
     p->workspace_bytes = off;
@@ -248,6 +249,8 @@ void bind_tables(pa_plan *p, void *tables, const PlanLayout &lay) {
     p->tw2i = p->tw2f + P3 * n2;
     p->Wf = (uint32_t *)(b + lay.oW);
     p->Wi = p->Wf + P3 * N;
+    p->R16f = (uint32_t *)(b + lay.oR16);
+    p->R16i = p->R16f + P3 * pa::R16_TW;
 }
 
 pa_status enqueue_hash(pa_plan *p, const uint64_t *key, const uint64_t *a, const uint64_t *b,

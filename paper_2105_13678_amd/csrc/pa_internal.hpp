@@ -74,6 +74,7 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_PER_THREAD = 16;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_PER_THREAD;  // digits normalised per workgroup
 constexpr int DIG_TILE = SCAN_THREADS;  // digits (one per thread) per carry aggregate
+constexpr uint32_t R16_TW = 16 * 256 + 16 * 16;  // words per prime of the row-kernel step-twiddle table
 
 // Device status flag bits (written by the prologue and status kernels).
 constexpr uint32_t ST_SEED_RANGE = 1u;
@@ -116,6 +117,8 @@ struct pa_plan {
     uint32_t *tw1f, *tw1i;  // per prime: omega_{N1}^+-j, j < N1 (Montgomery form)
     uint32_t *tw2f, *tw2i;  // per prime: omega_{N2}^+-j, j < N2
     uint32_t *Wf, *Wi;      // per prime: four-step twiddles, stored (bit-reversed) row order
+    uint32_t *R16f, *R16i;  // per prime: step twiddles of the 4096-point row kernel in thread order
+                            // (R16_TW words: [j][t] omega^(t brev(j)), then [j][n1] omega^(16 n1 brev(j)))
     const uint32_t *res_a;  // resident seed transforms (k x 3 x N words) or null
     const uint32_t *res_b;  // resident transform of b (3 x N words) or null
     uint32_t *h_status;     // pinned host word
@@ -137,7 +140,7 @@ namespace pa {
 // transform length) the following table_bytes.
 struct PlanLayout {
     size_t oX, oC, oC96, oT, oS, oY, oU, oAgg, oNo, oSt, oSo;
-    size_t oT1, oT2, oW;
+    size_t oT1, oT2, oW, oR16;
     size_t scratch_bytes, table_bytes, total;
 };
 

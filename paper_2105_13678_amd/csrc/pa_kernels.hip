@@ -146,6 +146,23 @@ __global__ void k_tw_four(uint32_t *Wf, uint32_t *Wi, uint32_t m1, uint32_t m2, 
     Wi[q * N + idx] = mulmod_slow(I.scale[q], powmod_slow(I.base[q], e, I.p[q]), I.p[q]);
 }
 
+// Step twiddles of the 4096-point row kernel rearranged so that the lanes of
+// a wave read consecutive words: [j][t] = omega_4096^(t brev4(j)) for the
+// 256 threads, then [j][n1] = omega_4096^(16 n1 brev4(j)) for n1 < 16.
+__global__ void k_tw_r16(const uint32_t *tw, uint32_t *dst) {
+    const uint32_t q = blockIdx.y;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= R16_TW) return;
+    uint32_t e;
+    if (i < 4096u) {
+        e = (i & 255u) * brev_small(i >> 8, 4);
+    } else {
+        const uint32_t k = i - 4096u;
+        e = 16u * (k & 15u) * brev_small(k >> 4, 4);
+    }
+    dst[q * R16_TW + i] = tw[q * 4096u + e];
+}
+
 // ------------------------------------------------------------------ status
 
 // Clears the chunk flags and checks the seeds: any bit >= gamma in a seed
@@ -423,6 +440,7 @@ struct RowArgs {
     uint32_t m2;
     uint32_t *out;
     const uint32_t *Wf, *Wi, *twf, *twi;  // per prime: four-step twiddles; omega_{N2}^+-e, e < N2
+    const uint32_t *r16f, *r16i;          // per prime: step twiddles of k_row16 in thread order
     PrimeSet P;
 };
 
@@ -580,17 +598,10 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
     const uint32_t s2 = swz_r16(b2);                                 // b2 + 16 j
     const uint32_t s3 = swz_r16(16u * t);                            // 16 t + j
     const uint32_t n1b = t & 15u;
-    // loop-invariant step twiddles, held in registers (re-reading them per
-    // use costs more than it saves: the step-1 reads are strided by up to
-    // 32 bytes per lane): step 1 omega_4096^(t k2), step 2 omega_4096^(16 n1 k2)
+    // step twiddles (step 1 omega_4096^(t k2), step 2 omega_4096^(16 n1 k2))
+    // from a table in thread order, so each is one coalesced load per use
     const __amdgpu_buffer_rsrc_t rw = rsrc_of(A.Wf + pq * A.N + rbase, R16_LEN);
-    const __amdgpu_buffer_rsrc_t rt = rsrc_of(A.twf + (uint64_t)pq * R16_LEN, R16_LEN);
-    uint32_t t1r[16], t2r[16];
-#pragma unroll
-    for (int j = 1; j < 16; ++j) {
-        t1r[j] = bload(rt, t4 * brev_small(j, 4), 0);
-        t2r[j] = bload(rt, (n1b * brev_small(j, 4)) << 6, 0);
-    }
+    const __amdgpu_buffer_rsrc_t rt = rsrc_of(A.r16f + pq * R16_TW, R16_TW);
     uint32_t acc[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) acc[j] = 0u;
@@ -609,16 +620,18 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
             // All 32 loads are issued before the first use (the scheduling
             // barrier keeps the compiler from interleaving load, wait and
             // use, which would expose the memory latency 16 times).
-            uint32_t v[16], wv[16];
+            uint32_t v[16], wv[16], w[16];
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 v[j] = bload(rg, t4l, 1024u * j);
                 wv[j] = bload(rw, t4l, 1024u * j);
             }
+#pragma unroll
+            for (int j = 1; j < 16; ++j) w[j] = bload(rt, t4l, 1024u * j);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int j = 0; j < 16; ++j) v[j] = mont(v[j], wv[j], M);
-            dft_fwd_tw<16>(v, t1r, M);
+            dft_fwd_tw<16>(v, w, M);
 #pragma unroll
             for (int j = 0; j < 16; ++j) buf[s1l ^ swz_r16(256u * j)] = v[j];
         }
@@ -626,13 +639,15 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
 #pragma unroll 1
         for (int side = 0; side < 2; ++side) {
             uint32_t *buf = side ? ba : bx;
-            const uint32_t s2l = opaque(s2);
-            uint32_t v[16];
+            const uint32_t s2l = opaque(s2), n4l = opaque(4u * n1b);
+            uint32_t v[16], w[16];
             // step 2: radix-16 on stride 16, step twiddles
 #pragma unroll
             for (int j = 0; j < 16; ++j) v[j] = buf[s2l ^ swz_r16(16u * j)];
+#pragma unroll
+            for (int j = 1; j < 16; ++j) w[j] = bload(rt, n4l, 16384u + 64u * j);
             __builtin_amdgcn_sched_barrier(0);
-            dft_fwd_tw<16>(v, t2r, M);
+            dft_fwd_tw<16>(v, w, M);
 #pragma unroll
             for (int j = 0; j < 16; ++j) buf[s2l ^ swz_r16(16u * j)] = v[j];
         }
@@ -652,7 +667,7 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
     }
 
     // inverse: step 3 from the accumulators, step 2, step 1 to global
-    const __amdgpu_buffer_rsrc_t rti = rsrc_of(A.twi + (uint64_t)pq * R16_LEN, R16_LEN);
+    const __amdgpu_buffer_rsrc_t rti = rsrc_of(A.r16i + pq * R16_TW, R16_TW);
     dft_inv<16>(acc, M);
 #pragma unroll
     for (int j = 0; j < 16; ++j) bx[s3 ^ (uint32_t)j] = acc[j];
@@ -662,7 +677,7 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
     for (int j = 0; j < 16; ++j) v[j] = bx[s2 ^ swz_r16(16u * j)];
     uint32_t w[16];
 #pragma unroll
-    for (int s = 1; s < 16; ++s) w[s] = bload(rti, (n1b * brev_small(s, 4)) << 6, 0);
+    for (int s = 1; s < 16; ++s) w[s] = bload(rti, 4u * n1b, 16384u + 64u * s);
     __builtin_amdgcn_sched_barrier(0);
     dft_inv_tw<16>(v, w, M);
 #pragma unroll
@@ -674,7 +689,7 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
     const __amdgpu_buffer_rsrc_t rwi = rsrc_of(A.Wi + pq * A.N + rbase, R16_LEN);
     uint32_t wv[16];
 #pragma unroll
-    for (int s = 1; s < 16; ++s) w[s] = bload(rti, t4 * brev_small(s, 4), 0);
+    for (int s = 1; s < 16; ++s) w[s] = bload(rti, t4, 1024u * s);
 #pragma unroll
     for (int j = 0; j < 16; ++j) wv[j] = bload(rwi, t4, 1024u * j);
     __builtin_amdgcn_sched_barrier(0);
@@ -1172,6 +1187,10 @@ hipError_t launch_twiddles(pa_plan *p, hipStream_t st) {
     hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(n2, 256), NPRIMES), dim3(256), 0, st, p->tw2i, n2, t2i);
     hipLaunchKernelGGL(k_tw_four, dim3(blocks_for(N, 256), NPRIMES), dim3(256), 0, st, p->Wf, p->Wi, p->m1, p->m2,
                        Ff, Fi);
+    if (p->m2 == 12) {
+        hipLaunchKernelGGL(k_tw_r16, dim3(blocks_for(R16_TW, 256), NPRIMES), dim3(256), 0, st, p->tw2f, p->R16f);
+        hipLaunchKernelGGL(k_tw_r16, dim3(blocks_for(R16_TW, 256), NPRIMES), dim3(256), 0, st, p->tw2i, p->R16i);
+    }
     return hipGetLastError();
 }
 
@@ -1233,6 +1252,8 @@ static RowArgs row_args(pa_plan *p, uint64_t npairs, const uint32_t *seed_side) 
     ra.Wi = p->Wi;
     ra.twf = p->tw2f;
     ra.twi = p->tw2i;
+    ra.r16f = p->R16f;
+    ra.r16i = p->R16i;
     ra.P = p->primes;
     return ra;
 }
