@@ -190,7 +190,7 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     const uint64_t Q = (96 + B - 1) / B, Q2 = (96 + p->e_fold + B - 1) / B;
     p->M1 = L + (Q > Q2 ? Q : Q2) + 1;
     const uint64_t digits = (p->M1 > L ? p->M1 : L) + 1;
-    p->ntiles_max = (digits + pa::DIG_TILE - 1) / pa::DIG_TILE + 1;
+    p->ntiles_max = (digits + pa::CARRY_TILE - 1) / pa::CARRY_TILE + 1;
     p->exact_log2 = std::log2((double)k) + std::log2((double)L) + 2.0 * std::log2((double)((1ull << B) - 1));
     pa::init_prime_constants(p, T.p);
 
@@ -210,6 +210,7 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     lay->oY = carve(L * 4);
     lay->oU = carve(L * 4);
     lay->oAgg = carve(p->ntiles_max * sizeof(pa::CFn));
+    lay->oCin = carve(p->ntiles_max * 4);
     lay->oNo = carve(k * 4);
     lay->oSt = carve(4 * 4);
     lay->oSo = carve(4 * 4);
@@ -234,6 +235,7 @@ void bind_scratch(pa_plan *p, void *scratch, const PlanLayout &lay) {
     p->y = (uint32_t *)(b + lay.oY);
     p->U = (uint32_t *)(b + lay.oU);
     p->agg = (pa::CFn *)(b + lay.oAgg);
+    p->cin = (uint32_t *)(b + lay.oCin);
     p->notones = (uint32_t *)(b + lay.oNo);
     p->status = (uint32_t *)(b + lay.oSt);
     p->status_out = (uint32_t *)(b + lay.oSo);

@@ -836,22 +836,15 @@ __device__ void block_scan(CFn f, CFn &excl, CFn &total) {
     __syncthreads();
 }
 
-struct ScanArgs {
-    const uint64_t *t;   // digit sums: M regular limbs, then the top limb at index M if has_top
-    uint32_t *out;       // normalised limbs
-    uint64_t M;
-    uint32_t B, has_top, s_top, dual;
-    uint64_t ntiles;
-    const CFn *agg;
-};
 
 // ------------------------------------------------------------------ fused digit tiles
-// A carry normalisation runs in two launches (after the Chinese-remainder
+// A carry normalisation runs in three launches (after the Chinese-remainder
 // kernel where the digits come from product coefficients).  The digit kernel
-// produces one digit sum per thread and the composed carry function of each
-// DIG_TILE-digit tile; the apply kernel composes the aggregates of the tiles
-// before its own SCAN_TILE digits (and of all tiles, for the top limb), then
-// normalises them.  No workgroup waits for another.
+// produces the digit sums (CARRY_PER_THREAD consecutive digits per thread)
+// and the composed carry function of each CARRY_TILE-digit tile; a single
+// workgroup composes the tile functions into the carry into every tile (and
+// handles the top limb); the apply kernel normalises each tile from its carry.
+// No workgroup waits for another.
 
 // Inverse column pass for 512-row tiles of 16 columns (N1 = 2^9), the mirror
 // of k_col9_fwd with the same task decomposition and LDS layout: the
@@ -1003,67 +996,80 @@ __device__ __forceinline__ uint64_t mh_digit(const DigitArgs &A, uint64_t m) {
     return sum;
 }
 
-// One digit per thread; workgroup b covers digits [b DIG_TILE, +DIG_TILE) and
-// writes their composed carry function (digits below M only).
+// Workgroup b covers digits [b CARRY_TILE, +CARRY_TILE), thread t the
+// CARRY_PER_THREAD digits from b CARRY_TILE + t CARRY_PER_THREAD; writes the
+// digit sums and the tile's composed carry function (digits below M only).
 template <int MODE>
 __global__ __launch_bounds__(SCAN_THREADS) void k_digit_tile(DigitArgs A) {
-    const uint64_t m = (uint64_t)blockIdx.x * DIG_TILE + threadIdx.x;
+    const uint64_t base = (uint64_t)blockIdx.x * CARRY_TILE + (uint64_t)threadIdx.x * CARRY_PER_THREAD;
     CFn f = cf_id();
-    if (m < A.ndig) {
-        const uint64_t d = MODE == DIG_FOLD ? fold_digit(A, m) : MODE == DIG_WRAP ? wrap_digit(A, m) : mh_digit(A, m);
-        A.t[m] = d;
-        if (m < A.M) f = cf_limb(d, A.B);
+#pragma unroll
+    for (int v = 0; v < CARRY_PER_THREAD; ++v) {
+        const uint64_t m = base + v;
+        if (m < A.ndig) {
+            const uint64_t d =
+                MODE == DIG_FOLD ? fold_digit(A, m) : MODE == DIG_WRAP ? wrap_digit(A, m) : mh_digit(A, m);
+            A.t[m] = d;
+            if (m < A.M) f = cf_compose(f, cf_limb(d, A.B));
+        }
     }
     CFn excl, total;
     block_scan<SCAN_THREADS>(f, excl, total);
     if (threadIdx.x == 0) A.agg[blockIdx.x] = total;
 }
 
-// Normalise one tile of a carry chain: carry into the tile = the composed
-// functions of all earlier tiles evaluated at the chain's carry-in; with a
-// top limb (index M, s_top bits) every workgroup also evaluates the whole
-// chain, and in dual mode takes carry-in 1 when carry-in 0 leaves a nonzero
-// value above the top limb's width (see launch_fold).  Workgroup 0 writes the
-// top limb.  Launched with max(1, ntiles) workgroups.
-__global__ __launch_bounds__(SCAN_THREADS) void k_carry_apply(ScanArgs A) {
-    const uint64_t b = blockIdx.x;
-    const uint64_t nagg = (A.M + DIG_TILE - 1) / DIG_TILE;  // digit-tile aggregates of the chain
-    const uint64_t first = b * (SCAN_TILE / DIG_TILE);       // those before this workgroup's digits
-    const uint64_t per = (nagg + SCAN_THREADS - 1) / SCAN_THREADS;
-    const uint64_t j0 = min((uint64_t)threadIdx.x * per, nagg), j1 = min(j0 + per, nagg);
-    CFn fb = cf_id(), fa = cf_id();
-    for (uint64_t j = j0; j < j1; ++j) {
-        const CFn g = A.agg[j];
-        if (j < first) fb = cf_compose(fb, g);
-        fa = cf_compose(fa, g);
-    }
-    CFn ex, before, all;
-    block_scan<SCAN_THREADS>(fb, ex, before);
-    block_scan<SCAN_THREADS>(fa, ex, all);
+struct ScanArgs {
+    const uint64_t *t;   // digit sums: M regular limbs, then the top limb at index M if has_top
+    uint32_t *out;       // normalised limbs
+    uint64_t M;
+    uint32_t B, has_top, s_top, dual;
+    uint64_t ntiles;     // ceil(M / CARRY_TILE)
+    const CFn *agg;
+    uint32_t *cin;
+};
+
+// One workgroup: the carry into every tile.  With a top limb (index M, s_top
+// bits) the whole chain is evaluated for carry-in 0 and 1; in dual mode the
+// chain takes carry-in 1 when carry-in 0 leaves a nonzero value above the top
+// limb's width (see launch_fold).  Writes the top limb.
+__global__ __launch_bounds__(PREFIX_THREADS) void k_carry_prefix(ScanArgs A) {
+    const uint64_t per = (A.ntiles + PREFIX_THREADS - 1) / PREFIX_THREADS;
+    const uint64_t j0 = min((uint64_t)threadIdx.x * per, A.ntiles), j1 = min(j0 + per, A.ntiles);
+    CFn f = cf_id();
+    for (uint64_t j = j0; j < j1; ++j) f = cf_compose(f, A.agg[j]);
+    CFn excl, total;
+    block_scan<PREFIX_THREADS>(f, excl, total);
     uint32_t sel = 0;
     if (A.has_top) {
         const uint64_t tt = A.t[A.M];
-        const uint32_t ct0 = cf_eval(all, 0u), ct1 = cf_eval(all, 1u);
+        const uint32_t ct0 = cf_eval(total, 0u), ct1 = cf_eval(total, 1u);
         sel = (A.dual && ((tt + ct1) >> A.s_top) != 0u) ? 1u : 0u;
-        if (b == 0 && threadIdx.x == 0)
-            A.out[A.M] = (uint32_t)((tt + (sel ? ct1 : ct0)) & ((1ull << A.s_top) - 1));
+        if (threadIdx.x == 0) A.out[A.M] = (uint32_t)((tt + (sel ? ct1 : ct0)) & ((1ull << A.s_top) - 1));
     }
-    if (b >= A.ntiles) return;
-    const uint64_t base = b * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_PER_THREAD;
-    uint64_t tv[SCAN_PER_THREAD];
+    uint32_t carry = cf_eval(excl, sel);
+    for (uint64_t j = j0; j < j1; ++j) {
+        A.cin[j] = carry;
+        carry = cf_eval(A.agg[j], carry);
+    }
+}
+
+// Normalise one tile from its carry-in.
+__global__ __launch_bounds__(SCAN_THREADS) void k_carry_apply(ScanArgs A) {
+    const uint64_t base = (uint64_t)blockIdx.x * CARRY_TILE + (uint64_t)threadIdx.x * CARRY_PER_THREAD;
+    uint64_t tv[CARRY_PER_THREAD];
     CFn f = cf_id();
 #pragma unroll
-    for (int v = 0; v < SCAN_PER_THREAD; ++v) {
+    for (int v = 0; v < CARRY_PER_THREAD; ++v) {
         const uint64_t idx = base + v;
         tv[v] = idx < A.M ? A.t[idx] : 0ull;
         if (idx < A.M) f = cf_compose(f, cf_limb(tv[v], A.B));
     }
     CFn excl, total;
     block_scan<SCAN_THREADS>(f, excl, total);
-    uint32_t carry = cf_eval(excl, cf_eval(before, sel));
+    uint32_t carry = cf_eval(excl, A.cin[blockIdx.x]);
     const uint64_t mask = (1ull << A.B) - 1;
 #pragma unroll
-    for (int v = 0; v < SCAN_PER_THREAD; ++v) {
+    for (int v = 0; v < CARRY_PER_THREAD; ++v) {
         const uint64_t idx = base + v;
         if (idx < A.M) {
             const uint64_t val = tv[v] + carry;
@@ -1337,7 +1343,7 @@ static hipError_t run_carry(pa_plan *p, DigitArgs A, uint32_t *out, uint64_t ndi
                             bool dual, hipStream_t st) {
     A.ndig = ndig;
     A.M = M;
-    const uint64_t tiles_t = (ndig + DIG_TILE - 1) / DIG_TILE;
+    const uint64_t tiles_t = (ndig + CARRY_TILE - 1) / CARRY_TILE;
     if (tiles_t) hipLaunchKernelGGL(k_digit_tile<MODE>, dim3((unsigned)tiles_t), dim3(SCAN_THREADS), 0, st, A);
     ScanArgs S;
     S.t = p->t;
@@ -1347,10 +1353,11 @@ static hipError_t run_carry(pa_plan *p, DigitArgs A, uint32_t *out, uint64_t ndi
     S.has_top = top ? 1u : 0u;
     S.s_top = p->s_top;
     S.dual = dual ? 1u : 0u;
-    S.ntiles = (M + SCAN_TILE - 1) / SCAN_TILE;
+    S.ntiles = (M + CARRY_TILE - 1) / CARRY_TILE;
     S.agg = p->agg;
-    const unsigned grid = (unsigned)(S.ntiles ? S.ntiles : 1);
-    hipLaunchKernelGGL(k_carry_apply, dim3(grid), dim3(SCAN_THREADS), 0, st, S);
+    S.cin = p->cin;
+    hipLaunchKernelGGL(k_carry_prefix, dim3(1), dim3(PREFIX_THREADS), 0, st, S);
+    if (S.ntiles) hipLaunchKernelGGL(k_carry_apply, dim3((unsigned)S.ntiles), dim3(SCAN_THREADS), 0, st, S);
     return hipGetLastError();
 }
 
