@@ -8,9 +8,10 @@ digests of the outputs:
 
 Cases (splitmix64 seed, n, r): the 2.6e8-bit single block (seed 2,
 r = n/10), the paper-shaped CV block n = 10 * 25,964,951 with compression
-ratio 0.0972 (Table 3; seed 6), and one chunk of the largest Mersenne
-exponent (gamma = 136,279,841, r = 2^27, seed 7), whose products need the
-longest transform (2^24 points).  Without case names every case is
+ratio 0.0972 (Table 3; seed 6), one chunk of the largest Mersenne exponent
+(gamma = 136,279,841, r = 2^27, seed 7), whose products need the longest
+transform (2^24 points), and single chunks of gamma = 37,156,667 and
+74,207,281 (seeds 8 and 9; 2^22- and 2^23-point transforms).  Without case names every case is
 recomputed; stored cases not named are kept.
 """
 from __future__ import annotations
@@ -36,6 +37,8 @@ CASES = {
     "single_block_2p6e8": dict(seed=2, n=260_000_000, r=26_000_000),
     "paper_cv_block": dict(seed=6, n=10 * 25964951, r=int(math.floor(0.0972 * 10 * 25964951))),
     "max_length_single_chunk": dict(seed=7, n=136279841 - 1, r=1 << 27),
+    "len_2p22_single_chunk": dict(seed=8, n=37156667 - 1, r=37156667 - 2),
+    "len_2p23_single_chunk": dict(seed=9, n=74207281 - 1, r=74207281 - 2),
 }
 
 

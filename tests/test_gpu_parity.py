@@ -108,10 +108,10 @@ def test_limb_width_invariance(pa, B):
     check_block(pa, blk, B=B, label=f"B={B}")
 
 
-@pytest.mark.parametrize("gamma,k", [(756839, 3), (1257787, 2), (3021377, 4)])
+@pytest.mark.parametrize("gamma,k", [(756839, 3), (1257787, 2), (3021377, 4), (6972593, 2), (13466917, 2)])
 def test_register_radix16_rows(pa, gamma, k):
-    """Shapes whose transform length (2^16 .. 2^19) selects the 4096-word
-    register radix-16 row pass, with ragged n."""
+    """Shapes whose transform length (2^16 .. 2^20) selects the 4096-word
+    register radix-16 row pass (and columns of 2^4 .. 2^8 rows), with ragged n."""
     n = k * gamma - 12345
     r = gamma // 7
     st, g, kk = defn.plan_shape(n, r, gamma)
@@ -265,7 +265,8 @@ def _digest(words):
     return hashlib.sha256(np.ascontiguousarray(words, dtype=np.uint64).tobytes()).hexdigest()
 
 
-@pytest.mark.parametrize("name", ["single_block_2p6e8", "paper_cv_block", "max_length_single_chunk"])
+@pytest.mark.parametrize("name", ["single_block_2p6e8", "paper_cv_block", "max_length_single_chunk",
+                                  "len_2p22_single_chunk", "len_2p23_single_chunk"])
 def test_full_size_blocks_against_stored_oracle_digest(pa, name):
     """Full-size blocks, in the launch configuration the benchmark times,
     against digests written by tests/golden/make_golden.py (oracle only)."""
