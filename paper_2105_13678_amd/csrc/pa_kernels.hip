@@ -347,6 +347,8 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
 }
 
 // ---- 512-row column tiles (N1 = 2^9), 16 columns: compile-time shape -------
+// A workgroup unpacks its tile's limbs once and transforms them for each of
+// the three primes in turn.
 // Three radix-8 steps; task index tau = t + 256 u (u < 4) in every step:
 //   step A (sub-length 512, stride 64): q = tau & 15, n1 = tau >> 4, rows
 //          n1 + 64 j; unpacked from global memory (rows >= 256 are padding);
@@ -365,71 +367,84 @@ template <int Stage>
 __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
     uint32_t *lds = lds_dyn;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t arr = blockIdx.y + A.arr0, pq = blockIdx.z;
-    const PrimeConst M = A.P.c[pq];
-    const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.tw + ((uint64_t)pq << C9_LG), 1u << C9_LG);
+    const uint32_t arr = blockIdx.y + A.arr0;
     const uint64_t c0 = (uint64_t)tile << C9_CLG;
-    const bool is_key = (A.mode == 0) && arr < A.k && pq == 0;  // the reload check runs once per chunk
+    const bool is_key = (A.mode == 0) && arr < A.k;
     const uint32_t full = (uint32_t)((1ull << A.B) - 1), topv = (uint32_t)((1ull << A.s_top) - 1);
-    uint32_t *out = A.X + ((uint64_t)blockIdx.y * NPRIMES + pq) * A.N;
     const uint32_t t = threadIdx.x;
-    const LimbSrc S = limb_src(A, arr);
-    const uint32_t L = (uint32_t)A.L;
-    bool not_ones = false;
-#pragma unroll 1
-    for (uint32_t u = 0; u < 4; ++u) {  // step A
-        const uint32_t tau = t + 256u * u;
-        const uint32_t q = tau & 15u, n1 = tau >> 4;
-        uint32_t v[8];
+    // the tile's 16 limbs per thread (the nonzero half: rows n1 + 64 jj, jj < 4,
+    // of the four step-A tasks), unpacked once and transformed for each prime
+    uint32_t x[4][4];
+    {
+        const LimbSrc S = limb_src(A, arr);
+        const uint32_t L = (uint32_t)A.L;
+        bool not_ones = false;
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            const uint32_t j = ((n1 + 64u * jj) << A.m2) + (uint32_t)c0 + q;  // limb index
-            const uint32_t x = limb_at(S, j);
-            if (is_key && j < L) not_ones |= (x != (j == L - 1 ? topv : full));
-            v[jj] = mont(x, M.one, M);  // x mod p, in [0, 2p)
+        for (uint32_t u = 0; u < 4; ++u) {
+            const uint32_t tau = t + 256u * u;
+            const uint32_t q = tau & 15u, n1 = tau >> 4;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const uint32_t j = ((n1 + 64u * jj) << A.m2) + (uint32_t)c0 + q;  // limb index
+                x[u][jj] = limb_at(S, j);
+                if (is_key && j < L) not_ones |= (x[u][jj] != (j == L - 1 ? topv : full));
+            }
         }
-        uint32_t w[8];
-#pragma unroll
-        for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 2, 0);
-        dft_fwd_x<8, true, true>(v, w, M);
-        const uint32_t sb = swz_c9(tau);
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) lds[sb ^ (1024u * jj)] = v[jj];
+        if (is_key) {
+            int any = __syncthreads_or(not_ones);
+            if (any && t == 0) A.notones[arr] = 1u;
+        }
     }
-    if (is_key) {
-        int any = __syncthreads_or(not_ones);
-        if (any && t == 0) A.notones[arr] = 1u;
-    } else {
+#pragma unroll 1
+    for (uint32_t pq = 0; pq < NPRIMES; ++pq) {
+        const PrimeConst M = A.P.c[pq];
+        const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.tw + ((uint64_t)pq << C9_LG), 1u << C9_LG);
+        uint32_t *out = A.X + ((uint64_t)blockIdx.y * NPRIMES + pq) * A.N;
+        if (pq) __syncthreads();  // the previous prime's last step has read the buffer
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {  // step A
+            const uint32_t tau = t + 256u * u;
+            const uint32_t n1 = tau >> 4;
+            uint32_t v[8], w[8];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) v[jj] = mont(x[u][jj], M.one, M);  // x mod p, in [0, 2p)
+#pragma unroll
+            for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 2, 0);
+            dft_fwd_x<8, true, true>(v, w, M);
+            const uint32_t sb = swz_c9(tau);
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) lds[sb ^ (1024u * jj)] = v[jj];
+        }
         __syncthreads();
-    }
 #pragma unroll 1
-    for (uint32_t u = 0; u < 4; ++u) {  // step B
-        const uint32_t tau = t + 256u * u;
-        const uint32_t q = tau & 15u, n1 = (tau >> 4) & 7u, b = tau >> 7;
-        const uint32_t sb = swz_c9(1024u * b + 16u * n1 + q);
-        uint32_t v[8];
+        for (uint32_t u = 0; u < 4; ++u) {  // step B
+            const uint32_t tau = t + 256u * u;
+            const uint32_t q = tau & 15u, n1 = (tau >> 4) & 7u, b = tau >> 7;
+            const uint32_t sb = swz_c9(1024u * b + 16u * n1 + q);
+            uint32_t v[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = lds[sb ^ swz_c9(128u * j)];
-        uint32_t w[8];
+            for (int j = 0; j < 8; ++j) v[j] = lds[sb ^ swz_c9(128u * j)];
+            uint32_t w[8];
 #pragma unroll
-        for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 5, 0);
-        dft_fwd_tw<8>(v, w, M);
+            for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 5, 0);
+            dft_fwd_tw<8>(v, w, M);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) lds[sb ^ swz_c9(128u * j)] = v[j];
-    }
-    __syncthreads();
+            for (int j = 0; j < 8; ++j) lds[sb ^ swz_c9(128u * j)] = v[j];
+        }
+        __syncthreads();
 #pragma unroll 1
-    for (uint32_t u = 0; u < 4; ++u) {  // step C
-        const uint32_t tau = t + 256u * u;
-        const uint32_t q = tau & 15u, b = tau >> 4;
-        const uint32_t sb = swz_c9(128u * b + q);
-        uint32_t v[8];
+        for (uint32_t u = 0; u < 4; ++u) {  // step C
+            const uint32_t tau = t + 256u * u;
+            const uint32_t q = tau & 15u, b = tau >> 4;
+            const uint32_t sb = swz_c9(128u * b + q);
+            uint32_t v[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = lds[sb ^ (16u * j)];
-        dft_fwd<8>(v, M);
-        uint32_t *o = out + ((uint64_t)(8u * b) << A.m2) + c0 + q;
+            for (int j = 0; j < 8; ++j) v[j] = lds[sb ^ (16u * j)];
+            dft_fwd<8>(v, M);
+            uint32_t *o = out + ((uint64_t)(8u * b) << A.m2) + c0 + q;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) o[(uint64_t)j << A.m2] = v[j];
+            for (int j = 0; j < 8; ++j) o[(uint64_t)j << A.m2] = v[j];
+        }
     }
 }
 
@@ -1239,8 +1254,8 @@ template <int Stage>
 static void launch_col_fwd(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, hipStream_t st) {
     const unsigned ncol_tiles = 1u << (p->m2 - p->c_lg);
     const size_t col_lds = ((size_t)4 << p->m1) << p->c_lg;
-    if (p->m1 == C9_LG && p->c_lg == C9_CLG)
-        hipLaunchKernelGGL(k_col9_fwd<Stage>, dim3(ncol_tiles, narrays, NPRIMES), dim3(COL_THREADS), col_lds, st, cf);
+    if (p->m1 == C9_LG && p->c_lg == C9_CLG)  // all three primes per workgroup
+        hipLaunchKernelGGL(k_col9_fwd<Stage>, dim3(ncol_tiles, narrays, 1), dim3(COL_THREADS), col_lds, st, cf);
     else
         hipLaunchKernelGGL(k_col_fwd<Stage>, dim3(ncol_tiles, narrays, NPRIMES), dim3(COL_THREADS), col_lds, st, cf);
 }
