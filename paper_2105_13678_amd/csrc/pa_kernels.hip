@@ -855,8 +855,8 @@ __device__ void block_scan(CFn f, CFn &excl, CFn &total) {
 // ------------------------------------------------------------------ fused digit tiles
 // A carry normalisation runs in three launches (after the Chinese-remainder
 // kernel where the digits come from product coefficients).  The digit kernel
-// produces the digit sums (CARRY_PER_THREAD consecutive digits per thread)
-// and the composed carry function of each CARRY_TILE-digit tile; a single
+// produces the digit sums (one per thread) and the composed carry function
+// of each CARRY_TILE-digit tile; a single
 // workgroup composes the tile functions into the carry into every tile (and
 // handles the top limb); the apply kernel normalises each tile from its carry.
 // No workgroup waits for another.
@@ -1011,25 +1011,20 @@ __device__ __forceinline__ uint64_t mh_digit(const DigitArgs &A, uint64_t m) {
     return sum;
 }
 
-// Workgroup b covers digits [b CARRY_TILE, +CARRY_TILE), thread t the
-// CARRY_PER_THREAD digits from b CARRY_TILE + t CARRY_PER_THREAD; writes the
-// digit sums and the tile's composed carry function (digits below M only).
+// Workgroup b covers digits [b CARRY_TILE, +CARRY_TILE), one per thread
+// (many waves in flight: the digits gather from several coefficients); writes
+// the digit sums and the tile's composed carry function (digits below M only).
 template <int MODE>
-__global__ __launch_bounds__(SCAN_THREADS) void k_digit_tile(DigitArgs A) {
-    const uint64_t base = (uint64_t)blockIdx.x * CARRY_TILE + (uint64_t)threadIdx.x * CARRY_PER_THREAD;
+__global__ __launch_bounds__(CARRY_TILE) void k_digit_tile(DigitArgs A) {
+    const uint64_t m = (uint64_t)blockIdx.x * CARRY_TILE + threadIdx.x;
     CFn f = cf_id();
-#pragma unroll
-    for (int v = 0; v < CARRY_PER_THREAD; ++v) {
-        const uint64_t m = base + v;
-        if (m < A.ndig) {
-            const uint64_t d =
-                MODE == DIG_FOLD ? fold_digit(A, m) : MODE == DIG_WRAP ? wrap_digit(A, m) : mh_digit(A, m);
-            A.t[m] = d;
-            if (m < A.M) f = cf_compose(f, cf_limb(d, A.B));
-        }
+    if (m < A.ndig) {
+        const uint64_t d = MODE == DIG_FOLD ? fold_digit(A, m) : MODE == DIG_WRAP ? wrap_digit(A, m) : mh_digit(A, m);
+        A.t[m] = d;
+        if (m < A.M) f = cf_limb(d, A.B);
     }
     CFn excl, total;
-    block_scan<SCAN_THREADS>(f, excl, total);
+    block_scan<CARRY_TILE>(f, excl, total);
     if (threadIdx.x == 0) A.agg[blockIdx.x] = total;
 }
 
@@ -1359,7 +1354,7 @@ static hipError_t run_carry(pa_plan *p, DigitArgs A, uint32_t *out, uint64_t ndi
     A.ndig = ndig;
     A.M = M;
     const uint64_t tiles_t = (ndig + CARRY_TILE - 1) / CARRY_TILE;
-    if (tiles_t) hipLaunchKernelGGL(k_digit_tile<MODE>, dim3((unsigned)tiles_t), dim3(SCAN_THREADS), 0, st, A);
+    if (tiles_t) hipLaunchKernelGGL(k_digit_tile<MODE>, dim3((unsigned)tiles_t), dim3(CARRY_TILE), 0, st, A);
     ScanArgs S;
     S.t = p->t;
     S.out = out;
