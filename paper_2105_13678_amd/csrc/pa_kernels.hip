@@ -186,13 +186,6 @@ __global__ void k_prologue(const uint64_t *a, const uint64_t *b, const uint64_t 
 }
 
 // After the MMH column pass: RELOAD if some chunk had only all-ones limbs.
-__global__ void k_status(const uint32_t *notones, uint64_t k, uint32_t *status) {
-    bool reload = false;
-    for (uint64_t i = threadIdx.x; i < k; i += blockDim.x) reload |= (notones[i] == 0u);
-    int any = __syncthreads_or(reload);
-    if (threadIdx.x == 0) status[1] = status[0] | (any ? ST_RELOAD : 0u);
-}
-
 // ------------------------------------------------------------------ NTT passes
 
 struct ColFwdArgs {
@@ -925,9 +918,17 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_inv(ColInvArgs A) {
 
 // Chinese-remainder reconstruction (Garner): canonical residues mod p0, p1,
 // p2 of a coefficient below p0 p1 p2 -> its exact value, as three word planes.
+// With notones set, workgroup 0 also finishes the status word: RELOAD when
+// some key chunk had no limb that is not all ones (Sec. 3.1 reload rule).
 __global__ void k_crt(const uint32_t *__restrict__ cc, uint32_t *c96, uint64_t N, uint64_t count, PrimeSet P,
-                      CrtConst K) {
+                      CrtConst K, const uint32_t *notones, uint64_t k, uint32_t *status) {
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (notones && blockIdx.x == 0) {
+        bool reload = false;
+        for (uint64_t i = threadIdx.x; i < k; i += blockDim.x) reload |= (notones[i] == 0u);
+        const int any = __syncthreads_or(reload);
+        if (threadIdx.x == 0) status[1] = status[0] | (any ? ST_RELOAD : 0u);
+    }
     if (j >= count) return;
     const PrimeConst &M1 = P.c[1], &M2 = P.c[2];
     const uint32_t r0 = cc[j], r1 = cc[N + j], r2 = cc[2 * N + j];
@@ -1091,9 +1092,11 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_carry_apply(ScanArgs A) {
 
 // ------------------------------------------------------------------ output
 
+// Also copies the final status word to `dst` (workgroup 0).
 __global__ void k_extract(const uint32_t *__restrict__ U, uint64_t *out, uint64_t out_words, uint64_t r,
-                          uint64_t gamma, uint32_t B, const uint32_t *status) {
+                          uint64_t gamma, uint32_t B, const uint32_t *status, uint32_t *dst) {
     uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w == 0) *dst = status[1];
     if (w >= out_words || status[1] != 0u) return;
     uint64_t v = limbs_get64(U, B, gamma, gamma - r + 64 * w);
     uint64_t left = r - 64 * w;
@@ -1108,7 +1111,6 @@ __global__ void k_pack(const uint32_t *__restrict__ limbs, uint64_t *out, uint64
     out[w] = limbs_get64(limbs, B, gamma, 64 * w);
 }
 
-__global__ void k_copy_status(const uint32_t *status, uint32_t *dst) { *dst = status[1]; }
 
 inline unsigned blocks_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
@@ -1312,7 +1314,6 @@ hipError_t launch_mmh(pa_plan *p, const uint64_t *key, const uint64_t *a, hipStr
     // with resident seed transforms only the k key chunks are transformed
     launch_col_fwd<STAGE_MMH>(p, cf, (unsigned)(p->res_a ? p->k : 2 * p->k), st);
     phase_mark(p, PA_PH_MMH_COL, false, st);
-    hipLaunchKernelGGL(k_status, dim3(1), dim3(256), 0, st, p->notones, p->k, p->status);
 
     RowArgs ra = row_args(p, p->k, p->res_a ? p->res_a : p->X + p->k * NPRIMES * p->N);
     phase_mark(p, PA_PH_MMH_ROW, true, st);
@@ -1375,7 +1376,7 @@ hipError_t launch_fold(pa_plan *p, hipStream_t st) {
     phase_mark(p, PA_PH_FOLD, true, st);
     const uint64_t ncoef = 2 * p->L - 1;  // nonzero coefficients of the product
     hipLaunchKernelGGL(k_crt, dim3(blocks_for(ncoef, 256)), dim3(256), 0, st, p->Cc, p->C96, p->N, ncoef,
-                       p->primes, p->crt);
+                       p->primes, p->crt, p->notones, p->k, p->status);
     // first fold at bit gamma, normalised over M1 digits (the sum fits: no carry out)
     hipError_t e = run_carry<DIG_FOLD>(p, digit_args(p), p->s, p->M1, p->M1, false, false, st);
     if (e != hipSuccess) return e;
@@ -1407,7 +1408,7 @@ hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, hipStream
     phase_mark(p, PA_PH_MH_CARRY, true, st);
     // only the coefficients below limb L matter mod 2^gamma
     hipLaunchKernelGGL(k_crt, dim3(blocks_for(p->L, 256)), dim3(256), 0, st, p->Cc, p->C96, p->N, p->L, p->primes,
-                       p->crt);
+                       p->crt, nullptr, 0, p->status);
     DigitArgs A = digit_args(p);
     A.cseed = c;
     hipError_t e = run_carry<DIG_MH>(p, A, p->U, p->L, p->L - 1, true, false, st);
@@ -1419,14 +1420,13 @@ hipError_t launch_finish(pa_plan *p, uint64_t *out, uint32_t *d_status, uint64_t
                          hipStream_t st) {
     phase_mark(p, PA_PH_FINISH, true, st);
     hipLaunchKernelGGL(k_extract, dim3(blocks_for(p->out_words, 256)), dim3(256), 0, st, p->U, out,
-                       p->out_words, p->r, p->gamma, p->B, p->status);
+                       p->out_words, p->r, p->gamma, p->B, p->status, d_status ? d_status : p->status_out);
     if (y_out)
         hipLaunchKernelGGL(k_pack, dim3(blocks_for(p->W, 256)), dim3(256), 0, st, p->y, y_out, p->W, p->gamma,
                            p->B, p->status);
     if (U_out)
         hipLaunchKernelGGL(k_pack, dim3(blocks_for(p->W, 256)), dim3(256), 0, st, p->U, U_out, p->W, p->gamma,
                            p->B, p->status);
-    hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(1), 0, st, p->status, d_status ? d_status : p->status_out);
     phase_mark(p, PA_PH_FINISH, false, st);
     return hipGetLastError();
 }
