@@ -61,6 +61,48 @@ def ntt_work(info):
     }
 
 
+def pipelined(pa, plan0, key, a, b, c, K, S, dev, gold_digest):
+    """K independent hashes of the block spread round-robin over S streams
+    (one plan and output buffer each), forked from and joined to the current
+    stream: consecutive blocks overlap, so one block's latency-bound phases
+    (carry chains, small transforms) run beside another's transforms."""
+    import torch
+    plans = [plan0] + [pa.Plan(N_BITS, R_BITS, device=0) for _ in range(S - 1)]
+    outs = [p.new_out() for p in plans]
+    streams = [torch.cuda.Stream(dev) for _ in range(S)]
+    d_status = torch.zeros(K + 2 * S, dtype=torch.int32, device=dev)
+    main = torch.cuda.current_stream(dev)
+
+    def run(base, count):
+        ev = torch.cuda.Event()
+        ev.record(main)
+        for s in streams:
+            s.wait_event(ev)
+        for i in range(count):
+            j = i % S
+            plans[j].hash_async(key, a, b, c, outs[j], d_status[base + i:base + i + 1], stream=streams[j])
+        for s in streams:
+            e = torch.cuda.Event()
+            e.record(s)
+            main.wait_event(e)
+
+    run(0, 2 * S)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(main)
+    run(2 * S, K)
+    e1.record(main)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / K
+    assert (d_status.cpu().numpy() == 0).all()
+    digests = {hashlib.sha256(pa.from_device(o).tobytes()).hexdigest() for o in outs}
+    for p in plans[1:]:
+        p.close()
+    return {"streams": S, "ms_per_step": round(ms, 4), "value": round(N_BITS / (ms / 1e3) / 1e6, 1),
+            "unit": "Mbit/s",
+            "verified_vs_oracle_digest": (digests == {gold_digest}) if gold_digest else None}
+
+
 def kernel_name(phase, info):
     """Symbol (as profilers print it) of the kernel a transform phase launches."""
     stage = 0 if phase.startswith("mmh") else 1
@@ -322,6 +364,9 @@ def main():
                          "pa_hash_batched call against the same blocks as serial calls; serving: Poisson "
                          "arrivals from 16 sessions through the serving loop (latency percentiles)")
     ap.add_argument("--requests", type=int, default=600, help="serving: number of Poisson arrivals")
+    ap.add_argument("--pipeline", type=int, default=3,
+                    help="single: also time the same K steps spread over this many streams (one plan "
+                         "each), reported as `pipelined`; 1 disables")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -384,12 +429,13 @@ def main():
     assert (statuses == 0).all(), statuses
     out_h = pa.from_device(out)
     digest = hashlib.sha256(out_h.tobytes()).hexdigest()
-    verified = None
+    verified, gold_digest = None, None
     gpath = os.path.join(ROOT, "tests", "golden", "full_size.json")
     if os.path.exists(gpath):
         gold = json.load(open(gpath)).get("single_block_2p6e8")
         if gold:
-            verified = digest == gold["out_sha256"]
+            gold_digest = gold["out_sha256"]
+            verified = digest == gold_digest
 
     value = N_BITS * K / (ms / 1e3) / 1e6
     # roofline of the dominant transform kernel (ALU bound: modular butterflies)
@@ -430,6 +476,8 @@ def main():
         "phase_ms_warmup": {p: round(v, 4) for p, v in phases.items()},
         "roofline": roof,
     }
+    if args.pipeline > 1:
+        rec["pipelined"] = pipelined(pa, plan, key, a, b, c, K, args.pipeline, dev, gold_digest=gold_digest)
     if args.calib_copy_mib:
         src = torch.ones(args.calib_copy_mib << 17, dtype=torch.int64, device=dev)
         dst = torch.empty_like(src)
