@@ -210,7 +210,6 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     lay->oY = carve(L * 4);
     lay->oU = carve(L * 4);
     lay->oAgg = carve(p->ntiles_max * sizeof(pa::CFn));
-    lay->oCin = carve(p->ntiles_max * 4);
     lay->oNo = carve(k * 4);
     lay->oSt = carve(4 * 4);
     lay->oSo = carve(4 * 4);
@@ -235,7 +234,6 @@ void bind_scratch(pa_plan *p, void *scratch, const PlanLayout &lay) {
     p->y = (uint32_t *)(b + lay.oY);
     p->U = (uint32_t *)(b + lay.oU);
     p->agg = (pa::CFn *)(b + lay.oAgg);
-    p->cin = (uint32_t *)(b + lay.oCin);
     p->notones = (uint32_t *)(b + lay.oNo);
     p->status = (uint32_t *)(b + lay.oSt);
     p->status_out = (uint32_t *)(b + lay.oSo);

@@ -73,7 +73,6 @@ constexpr uint32_t CF_ID = 0xFFFFFFFFu;
 constexpr int SCAN_THREADS = 256;
 constexpr int CARRY_PER_THREAD = 4;                          // consecutive digits per thread
 constexpr int CARRY_TILE = SCAN_THREADS * CARRY_PER_THREAD;  // digits per workgroup and per aggregate
-constexpr int PREFIX_THREADS = 1024;                         // the single workgroup of the tile prefix
 constexpr uint32_t R16_TW = 16 * 256 + 16 * 16;  // words per prime of the row-kernel step-twiddle table
 
 // Device status flag bits (written by the prologue and status kernels).
@@ -111,7 +110,6 @@ struct pa_plan {
     uint32_t *U;        // MH value limbs (L)
     uint32_t *C96;      // 3 x N words: reconstructed coefficients, word planes (bits 0-31, 32-63, 64-95)
     pa::CFn *agg;       // carry functions of CARRY_TILE-digit tiles
-    uint32_t *cin;      // carry into each tile (selected variant)
     uint32_t *notones;  // k flags: chunk i has a limb that is not all ones
     uint32_t *status;   // seed/reload flags
     uint32_t *status_out;  // final flags of the last call (pa_hash reads it back)
@@ -140,7 +138,7 @@ namespace pa {
 // [0, scratch_bytes), the read-only twiddle tables (which depend only on the
 // transform length) the following table_bytes.
 struct PlanLayout {
-    size_t oX, oC, oC96, oT, oS, oY, oU, oAgg, oCin, oNo, oSt, oSo;
+    size_t oX, oC, oC96, oT, oS, oY, oU, oAgg, oNo, oSt, oSo;
     size_t oT1, oT2, oW, oR16;
     size_t scratch_bytes, table_bytes, total;
 };

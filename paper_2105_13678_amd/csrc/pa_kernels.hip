@@ -846,13 +846,12 @@ __device__ void block_scan(CFn f, CFn &excl, CFn &total) {
 
 
 // ------------------------------------------------------------------ fused digit tiles
-// A carry normalisation runs in three launches (after the Chinese-remainder
+// A carry normalisation runs in two launches (after the Chinese-remainder
 // kernel where the digits come from product coefficients).  The digit kernel
 // produces the digit sums (one per thread) and the composed carry function
-// of each CARRY_TILE-digit tile; a single
-// workgroup composes the tile functions into the carry into every tile (and
-// handles the top limb); the apply kernel normalises each tile from its carry.
-// No workgroup waits for another.
+// of each CARRY_TILE-digit tile; the apply kernel composes the functions of
+// the tiles before its own into its carry-in (and handles the top limb), then
+// normalises its tile.  No workgroup waits for another.
 
 // Inverse column pass for 512-row tiles of 16 columns (N1 = 2^9), the mirror
 // of k_col9_fwd with the same task decomposition and LDS layout: the
@@ -1036,37 +1035,39 @@ struct ScanArgs {
     uint32_t B, has_top, s_top, dual;
     uint64_t ntiles;     // ceil(M / CARRY_TILE)
     const CFn *agg;
-    uint32_t *cin;
 };
 
-// One workgroup: the carry into every tile.  With a top limb (index M, s_top
-// bits) the whole chain is evaluated for carry-in 0 and 1; in dual mode the
-// chain takes carry-in 1 when carry-in 0 leaves a nonzero value above the top
-// limb's width (see launch_fold).  Writes the top limb.
-__global__ __launch_bounds__(PREFIX_THREADS) void k_carry_prefix(ScanArgs A) {
-    const uint64_t per = (A.ntiles + PREFIX_THREADS - 1) / PREFIX_THREADS;
+// Normalise one tile.  The carry into the tile is the composition of the
+// aggregates of all earlier tiles evaluated at the chain's carry-in (every
+// workgroup composes them itself: a few per thread, no second pass).  With a
+// top limb (index M, s_top bits) the whole chain is also evaluated for
+// carry-in 0 and 1; in dual mode the chain takes carry-in 1 when carry-in 0
+// leaves a nonzero value above the top limb's width (see launch_fold), and
+// workgroup 0 writes the top limb.  Launched with max(1, ntiles) workgroups.
+__global__ __launch_bounds__(SCAN_THREADS) void k_carry_apply(ScanArgs A) {
+    const uint64_t b = blockIdx.x;
+    const uint64_t per = (A.ntiles + SCAN_THREADS - 1) / SCAN_THREADS;
     const uint64_t j0 = min((uint64_t)threadIdx.x * per, A.ntiles), j1 = min(j0 + per, A.ntiles);
-    CFn f = cf_id();
-    for (uint64_t j = j0; j < j1; ++j) f = cf_compose(f, A.agg[j]);
-    CFn excl, total;
-    block_scan<PREFIX_THREADS>(f, excl, total);
+    CFn fb = cf_id(), fa = cf_id();
+    for (uint64_t j = j0; j < j1; ++j) {
+        const CFn g = A.agg[j];
+        if (j < b) fb = cf_compose(fb, g);
+        fa = cf_compose(fa, g);
+    }
+    CFn ex, before;
+    block_scan<SCAN_THREADS>(fb, ex, before);
     uint32_t sel = 0;
     if (A.has_top) {
+        CFn all;
+        block_scan<SCAN_THREADS>(fa, ex, all);
         const uint64_t tt = A.t[A.M];
-        const uint32_t ct0 = cf_eval(total, 0u), ct1 = cf_eval(total, 1u);
+        const uint32_t ct0 = cf_eval(all, 0u), ct1 = cf_eval(all, 1u);
         sel = (A.dual && ((tt + ct1) >> A.s_top) != 0u) ? 1u : 0u;
-        if (threadIdx.x == 0) A.out[A.M] = (uint32_t)((tt + (sel ? ct1 : ct0)) & ((1ull << A.s_top) - 1));
+        if (b == 0 && threadIdx.x == 0)
+            A.out[A.M] = (uint32_t)((tt + (sel ? ct1 : ct0)) & ((1ull << A.s_top) - 1));
     }
-    uint32_t carry = cf_eval(excl, sel);
-    for (uint64_t j = j0; j < j1; ++j) {
-        A.cin[j] = carry;
-        carry = cf_eval(A.agg[j], carry);
-    }
-}
-
-// Normalise one tile from its carry-in.
-__global__ __launch_bounds__(SCAN_THREADS) void k_carry_apply(ScanArgs A) {
-    const uint64_t base = (uint64_t)blockIdx.x * CARRY_TILE + (uint64_t)threadIdx.x * CARRY_PER_THREAD;
+    if (b >= A.ntiles) return;
+    const uint64_t base = b * CARRY_TILE + (uint64_t)threadIdx.x * CARRY_PER_THREAD;
     uint64_t tv[CARRY_PER_THREAD];
     CFn f = cf_id();
 #pragma unroll
@@ -1077,7 +1078,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_carry_apply(ScanArgs A) {
     }
     CFn excl, total;
     block_scan<SCAN_THREADS>(f, excl, total);
-    uint32_t carry = cf_eval(excl, A.cin[blockIdx.x]);
+    uint32_t carry = cf_eval(excl, cf_eval(before, sel));
     const uint64_t mask = (1ull << A.B) - 1;
 #pragma unroll
     for (int v = 0; v < CARRY_PER_THREAD; ++v) {
@@ -1366,9 +1367,7 @@ static hipError_t run_carry(pa_plan *p, DigitArgs A, uint32_t *out, uint64_t ndi
     S.dual = dual ? 1u : 0u;
     S.ntiles = (M + CARRY_TILE - 1) / CARRY_TILE;
     S.agg = p->agg;
-    S.cin = p->cin;
-    hipLaunchKernelGGL(k_carry_prefix, dim3(1), dim3(PREFIX_THREADS), 0, st, S);
-    if (S.ntiles) hipLaunchKernelGGL(k_carry_apply, dim3((unsigned)S.ntiles), dim3(SCAN_THREADS), 0, st, S);
+    hipLaunchKernelGGL(k_carry_apply, dim3((unsigned)(S.ntiles ? S.ntiles : 1)), dim3(SCAN_THREADS), 0, st, S);
     return hipGetLastError();
 }
 
