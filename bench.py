@@ -152,7 +152,46 @@ def cpu_baseline(blk, info, budget_chunks=2):
                    f"({n_s} bits, gamma={g}, r={R_BITS}, same seeds): {dt:.2f} s for {budget_chunks + 1} "
                    f"products, scaled x{(k + 1) / (budget_chunks + 1):.3f} to the k={k} block"),
         "status": int(st),
+        "host": {"cpu_model": cpu_model(), "nproc": os.cpu_count()},
     }
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def step_stats(plan, key, a, b, c, out, K, dev):
+    """Per-step times (HIP events around each step, on the plan's stream):
+    median and minimum of K steps, and the same steps each preceded by the
+    key's upload from pinned host memory (the PCIe-inclusive figure)."""
+    import torch
+    d_status = torch.zeros(2 * K, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(2 * K)]
+    host_key = key.cpu().pin_memory()
+    for i in range(K):
+        evs[i][0].record(stream)
+        plan.hash_async(key, a, b, c, out, d_status[i:i + 1])
+        evs[i][1].record(stream)
+    for i in range(K, 2 * K):
+        evs[i][0].record(stream)
+        key.copy_(host_key, non_blocking=True)
+        plan.hash_async(key, a, b, c, out, d_status[i:i + 1])
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    assert (d_status.cpu().numpy() == 0).all()
+    t = sorted(e0.elapsed_time(e1) for e0, e1 in evs[:K])
+    u = sorted(e0.elapsed_time(e1) for e0, e1 in evs[K:])
+    return {"step_ms_median": round(t[K // 2], 4), "step_ms_min": round(t[0], 4),
+            "with_key_upload": {"step_ms_median": round(u[K // 2], 4),
+                                "value": round(N_BITS / (u[K // 2] / 1e3) / 1e6, 1), "unit": "Mbit/s",
+                                "what": "each step preceded by the 32.5 MB key upload from pinned host memory"}}
 
 
 BATCH_SEED, BATCH_COUNT = 3, 64
@@ -451,6 +490,8 @@ def main():
         "unit": "Gbutterfly/s",
         "frac": round(bfly_per_s / PEAK_BFLY_PER_S, 3),
         "traffic": (tr[0] + tr[1]) if tr else None,
+        "hbm_gbs": round((tr[0] + tr[1]) / (dom_ms / 1e3) / 1e9, 1) if tr else None,
+        "hbm_frac": round((tr[0] + tr[1]) / (dom_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 3) if tr else None,
         "traffic_read_write": list(tr) if tr else None,
         "duration_ms": round(dom_ms, 4),
         "butterflies_per_launch": work[dom],
@@ -476,6 +517,7 @@ def main():
         "phase_ms_warmup": {p: round(v, 4) for p, v in phases.items()},
         "roofline": roof,
     }
+    rec.update(step_stats(plan, key, a, b, c, out, K, dev))
     if args.pipeline > 1:
         rec["pipelined"] = pipelined(pa, plan, key, a, b, c, K, args.pipeline, dev, gold_digest=gold_digest)
     if args.calib_copy_mib:
