@@ -403,6 +403,9 @@ def main():
                          "pa_hash_batched call against the same blocks as serial calls; serving: Poisson "
                          "arrivals from 16 sessions through the serving loop (latency percentiles)")
     ap.add_argument("--requests", type=int, default=600, help="serving: number of Poisson arrivals")
+    ap.add_argument("--core-only", action="store_true",
+                    help="single: time only the K main steps (no per-step statistics, key-upload or pipelined "
+                         "passes), so that a profiler sees exactly those launches")
     ap.add_argument("--pipeline", type=int, default=3,
                     help="single: also time the same K steps spread over this many streams (one plan "
                          "each), reported as `pipelined`; 1 disables")
@@ -517,8 +520,9 @@ def main():
         "phase_ms_warmup": {p: round(v, 4) for p, v in phases.items()},
         "roofline": roof,
     }
-    rec.update(step_stats(plan, key, a, b, c, out, K, dev))
-    if args.pipeline > 1:
+    if not args.core_only:
+        rec.update(step_stats(plan, key, a, b, c, out, K, dev))
+    if args.pipeline > 1 and not args.core_only:
         rec["pipelined"] = pipelined(pa, plan, key, a, b, c, K, args.pipeline, dev, gold_digest=gold_digest)
     if args.calib_copy_mib:
         src = torch.ones(args.calib_copy_mib << 17, dtype=torch.int64, device=dev)

@@ -984,6 +984,8 @@ __device__ __forceinline__ uint64_t fold_digit(const DigitArgs &A, uint64_t m) {
 __device__ __forceinline__ uint64_t wrap_digit(const DigitArgs &A, uint64_t m) {
     const uint32_t B = A.B;
     const uint64_t gamma = A.gamma;
+    const uint64_t lo = (m + 1 < A.L) ? A.s[m] : (A.s[m] & ((1ull << A.s_top) - 1));
+    if (B * m >= 128) return lo;  // V < 2^92 only reaches the lowest digits
     unsigned __int128 V = 0;
     for (uint64_t idx = gamma / B; idx < A.M1; ++idx) {
         const uint64_t lo_bit = idx * B;
@@ -996,9 +998,7 @@ __device__ __forceinline__ uint64_t wrap_digit(const DigitArgs &A, uint64_t m) {
         while (V >> gamma) V = (V & pm) + (V >> gamma);
         if (V == pm) V = 0;
     }
-    const uint64_t lo = (m + 1 < A.L) ? A.s[m] : (A.s[m] & ((1ull << A.s_top) - 1));
-    const uint64_t vl = (B * m < 128) ? (uint64_t)((V >> (B * m)) & ((1ull << B) - 1)) : 0ull;
-    return lo + vl;
+    return lo + (uint64_t)((V >> (B * m)) & ((1ull << B) - 1));
 }
 
 // MH digit m < L: the limbs of c plus the pieces of the product coefficients
