@@ -79,6 +79,21 @@ def test_small_random_shapes(pa):
         check_block(pa, blk, label=f"random#{t}")
 
 
+@pytest.mark.parametrize("gamma", [61, 521, 9689])
+def test_maximum_chunk_count(pa, gamma):
+    """k = 4096 chunks (the plan's limit) with a ragged last chunk: the
+    multiply-accumulate runs over 4096 pairs, the column pass over 8192
+    arrays, and the reload flag over 4096 chunks."""
+    k = 4096
+    n, r = k * gamma - 3, gamma // 2
+    st, g, kk = defn.plan_shape(n, r, gamma)
+    assert st == 0 and kk == k
+    assert pa.plan_query(n, r, gamma)[0] == 0
+    assert pa.plan_query(n + gamma, r, gamma)[0] == -10  # k = 4097: PA_ERR_LIMIT
+    blk = synth.single_block(4096 + gamma, n, r, g, kk)
+    check_block(pa, blk, label=f"k=4096 gamma={gamma}")
+
+
 @pytest.mark.parametrize("gamma", [89, 127, 521, 4423, 110503])
 def test_edge_shapes(pa, gamma):
     cases = [
