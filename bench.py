@@ -109,7 +109,7 @@ def kernel_name(phase, info):
     if phase.endswith("_row"):
         base = "k_row16" if info["log2N2"] == 12 else "k_row"
     elif phase.endswith("_colinv"):
-        base = "k_col_inv"
+        base = "k_col9_inv" if info["log2N1"] == 9 and info["log2N2"] >= 4 else "k_col_inv"
     else:
         base = "k_col9_fwd" if info["log2N1"] == 9 and info["log2N2"] >= 4 else "k_col_fwd"
     return f"{base}<{stage}>"
@@ -285,6 +285,60 @@ def bench_batched(args):
     print(json.dumps(rec), flush=True)
 
 
+LENGTH_BLOCKS = [(800_000_000, 80_000_000, 6), (1 << 32, 1 << 27, 7)]
+
+
+def bench_lengths(args):
+    """Blocks whose product length 2L - 1 falls just above a power of two:
+    the paper's largest CV block (n = 8e8, r = n/10: 2L - 1 = 0.62 * 2^23) and
+    the 2^32-bit block (r = 2^27: 0.52 * 2^24), each hashed with the plan
+    rule's transform length 3 * 2^m and with power-of-two lengths only
+    (PA_FLAG_POW2_LENGTHS), same inputs; outputs must agree."""
+    import torch
+    import paper_2105_13678_amd as pa
+    from paper_2105_13678_amd import synth
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    K, Wm = args.steps, max(1, args.warmup)
+    rows = []
+    for n, r, seed in LENGTH_BLOCKS:
+        st, info = pa.plan_query(n, r)
+        assert st == 0, st
+        blk = synth.single_block(seed, n, r, info["gamma"], info["k"])
+        key, a, b, c = (pa.to_device(x, dev) for x in (blk.key, blk.a, blk.b, blk.c))
+        del blk
+        res = {}
+        for label, flags in (("radix3", 0), ("pow2", pa.PA_FLAG_POW2_LENGTHS)):
+            plan = pa.Plan(n, r, device=0, flags=flags)
+            out = plan.new_out()
+            d_status = torch.zeros(K + Wm, dtype=torch.int32, device=dev)
+            for i in range(Wm):
+                plan.hash_async(key, a, b, c, out, d_status[i:i + 1])
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            for i in range(K):
+                plan.hash_async(key, a, b, c, out, d_status[Wm + i:Wm + i + 1])
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            assert (d_status.cpu().numpy() == 0).all()
+            ms = ev0.elapsed_time(ev1) / K
+            res[label] = {"ms_per_block": round(ms, 3), "value": round(n / (ms / 1e3) / 1e6, 1), "B": plan.B,
+                          "N": plan.N, "out": out.clone()}
+            log(f"[bench] lengths n={n} r={r} {label}: N={plan.N} B={plan.B} {ms:.3f} ms")
+            plan.close()
+        same = torch.equal(res["radix3"].pop("out"), res["pow2"].pop("out"))
+        rows.append({"n": n, "r": r, "gamma": info["gamma"], "k": info["k"], "radix3": res["radix3"],
+                     "pow2": res["pow2"], "speedup": round(res["pow2"]["ms_per_block"] / res["radix3"]["ms_per_block"], 3),
+                     "outputs_equal": same})
+        del key, a, b, c
+        torch.cuda.empty_cache()
+    rec = {"metric": "PA input throughput (Mbit/s) with transform lengths 3 * 2^m vs 2^m, bit-exact",
+           "unit": "Mbit/s", "n_gpus": 1, "steps": K, "warmup": Wm, "higher_is_better": True,
+           "data": "synthetic", "blocks": rows}
+    print(json.dumps(rec), flush=True)
+
+
 SERVE_SEED, SERVE_SESSIONS, SERVE_RATE = 4, 16, 44.1
 SERVE_GAMMAS = [2976221, 3021377, 6972593, 13466917, 20996011, 24036583, 25964951, 30402457]
 
@@ -398,10 +452,11 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed region, copy a buffer of this many MiB with a plain device "
                          "copy kernel (reference point for the HBM byte counters)")
-    ap.add_argument("--workload", choices=["single", "batched", "serving"], default="single",
+    ap.add_argument("--workload", choices=["single", "batched", "serving", "lengths"], default="single",
                     help="single: the 2.6e8-bit block (the headline); batched: 64 uneven blocks in one "
                          "pa_hash_batched call against the same blocks as serial calls; serving: Poisson "
-                         "arrivals from 16 sessions through the serving loop (latency percentiles)")
+                         "arrivals from 16 sessions through the serving loop (latency percentiles); lengths: "
+                         "the 8e8- and 2^32-bit blocks with transform lengths 3 * 2^m against 2^m")
     ap.add_argument("--requests", type=int, default=600, help="serving: number of Poisson arrivals")
     ap.add_argument("--core-only", action="store_true",
                     help="single: time only the K main steps (no per-step statistics, key-upload or pipelined "
@@ -418,6 +473,8 @@ def main():
         return bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "lengths":
+        return bench_lengths(args)
 
     import torch
     import paper_2105_13678_amd as pa

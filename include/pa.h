@@ -62,20 +62,25 @@ typedef enum pa_status {
 } pa_status;
 
 /* Plan request.  gamma = 0 picks the smallest Mersenne exponent above r.
- * B = 0 picks the widest limb (at most 32 bits) for which the transform is
- * exact; otherwise 8 <= B <= 32. */
+ * The product of two L-limb numbers needs a cyclic convolution of length
+ * N >= 2L - 1; N is either a power of two or three times one (a radix-3 step
+ * over three power-of-two transforms), whichever is cheaper among the exact
+ * choices.  B = 0 picks the limb width (at most 32 bits) that gives the
+ * cheapest exact transform, the widest among equals; otherwise 8 <= B <= 32.
+ * The output never depends on B or N. */
+#define PA_FLAG_POW2_LENGTHS 1u /* flags: power-of-two transform lengths only */
 typedef struct pa_params {
     uint64_t n;       /* input key length in bits, n >= 2                    */
     uint64_t r;       /* output length in bits, 1 <= r < n and r < gamma     */
     uint64_t gamma;   /* Mersenne exponent, or 0 for automatic               */
     uint32_t B;       /* limb width in bits (the paper's 2^B-ary words), 0 = auto */
-    uint32_t flags;   /* reserved, must be 0                                 */
+    uint32_t flags;   /* 0 or PA_FLAG_POW2_LENGTHS                          */
 } pa_params;
 
 typedef struct pa_plan_info {
     uint64_t n, r, gamma, k;
     uint32_t B;             /* limb width                                   */
-    uint32_t log2N;         /* NTT length N = 2^log2N >= 2L - 1            */
+    uint32_t log2N;         /* NTT length N = len_factor * 2^log2N >= 2L - 1 */
     uint64_t L;             /* limbs per gamma-bit number, ceil(gamma/B)    */
     uint64_t N;
     uint64_t key_words;     /* ceil(n/64)                                   */
@@ -85,9 +90,10 @@ typedef struct pa_plan_info {
     uint64_t workspace_bytes; /* device memory owned by the plan            */
     double exact_log2;      /* log2(k * L * (2^B - 1)^2); below log2(p0 p1 p2) */
     uint32_t log2N1;        /* column-pass length 2^log2N1                  */
-    uint32_t log2N2;        /* row-pass length 2^log2N2 (N = 2^(log2N1 + log2N2)) */
+    uint32_t log2N2;        /* row-pass length 2^log2N2 (2^log2N = 2^(log2N1 + log2N2)) */
     uint32_t nprimes;       /* NTT primes per transform (3)                 */
     uint32_t primes[3];     /* the NTT primes p0, p1, p2 of this length     */
+    uint32_t len_factor;    /* 1, or 3 for the lengths N = 3 * 2^log2N      */
 } pa_plan_info;
 
 typedef struct pa_plan pa_plan;
@@ -97,8 +103,8 @@ typedef struct pa_plan pa_plan;
  * the product of the three NTT primes of length N (the three largest primes
  * below 2^30 with N | p - 1; PA_ERR_INEXACT otherwise), allocates the
  * workspace and builds the twiddle tables.  Supported range: k <= 4096 and
- * N <= 2^24 (PA_ERR_LIMIT otherwise).  On success *out owns device memory until
- * pa_plan_destroy. */
+ * N <= 2^24 or N = 3 * 2^m <= 3 * 2^23 (PA_ERR_LIMIT otherwise).  On success
+ * *out owns device memory until pa_plan_destroy. */
 pa_status pa_plan_create(const pa_params *params, int hip_device, pa_plan **out);
 
 /* Derive the shape pa_plan_create would use, without touching any device:

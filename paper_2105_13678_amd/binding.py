@@ -19,6 +19,7 @@ PA_OK, PA_PENDING, PA_RELOAD = 0, 1, 2
 PA_ERR_ARG, PA_ERR_NO_GAMMA, PA_ERR_GAMMA, PA_ERR_INEXACT = -1, -2, -3, -4
 PA_ERR_SEED_B_EVEN, PA_ERR_SEED_RANGE, PA_ERR_NOMEM, PA_ERR_DEVICE = -5, -6, -7, -8
 PA_ERR_BUSY, PA_ERR_LIMIT = -9, -10
+PA_FLAG_POW2_LENGTHS = 1  # pa_params.flags: power-of-two transform lengths only
 
 # pa_phase, in order
 PHASES = ["prologue", "mmh_col", "mmh_row", "mmh_colinv", "fold", "mh_col", "mh_row", "mh_colinv",
@@ -44,7 +45,8 @@ class PlanInfo(ctypes.Structure):
                 ("seed_words", ctypes.c_uint64), ("a_words", ctypes.c_uint64),
                 ("out_words", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64),
                 ("exact_log2", ctypes.c_double), ("log2N1", ctypes.c_uint32),
-                ("log2N2", ctypes.c_uint32), ("nprimes", ctypes.c_uint32), ("primes", ctypes.c_uint32 * 3)]
+                ("log2N2", ctypes.c_uint32), ("nprimes", ctypes.c_uint32), ("primes", ctypes.c_uint32 * 3),
+                ("len_factor", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_}
@@ -143,9 +145,9 @@ def decode_status(flags: int) -> int:
     return lib().pa_decode_status(int(flags) & 0xFFFFFFFF)
 
 
-def plan_query(n: int, r: int, gamma: int = 0, B: int = 0):
+def plan_query(n: int, r: int, gamma: int = 0, B: int = 0, flags: int = 0):
     """(status, info dict or None): the shape pa_plan_create would use."""
-    prm = Params(n, r, gamma, B, 0)
+    prm = Params(n, r, gamma, B, flags)
     info = PlanInfo()
     st = lib().pa_plan_query(ctypes.byref(prm), ctypes.byref(info))
     return st, (info.as_dict() if st == PA_OK else None)
@@ -167,11 +169,11 @@ def _dev_ptr(t, min_words: int, what: str, device) -> int:
 class Plan:
     """One (n, r) shape on one GPU; owns its device workspace."""
 
-    def __init__(self, n: int, r: int, gamma: int = 0, B: int = 0, device: int = 0):
+    def __init__(self, n: int, r: int, gamma: int = 0, B: int = 0, device: int = 0, flags: int = 0):
         import torch
         self._h = _VP()
         self.device = torch.device("cuda", device)
-        prm = Params(n, r, gamma, B, 0)
+        prm = Params(n, r, gamma, B, flags)
         st = lib().pa_plan_create(ctypes.byref(prm), int(device), ctypes.byref(self._h))
         if st != PA_OK:
             self._h = _VP()

@@ -40,7 +40,7 @@ struct DeviceGuard {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 pa_status plan_shape(const pa_params *prm, uint64_t *gamma, uint64_t *k, uint32_t *B) {
-    if (!prm || prm->flags != 0) return PA_ERR_ARG;
+    if (!prm || (prm->flags & ~PA_FLAG_POW2_LENGTHS) != 0) return PA_ERR_ARG;
     const uint64_t n = prm->n, r = prm->r;
     if (n < 2 || r < 1 || r >= n) return PA_ERR_ARG;
     uint64_t g = 0;
@@ -99,18 +99,25 @@ pa_status pa_decode_status(uint32_t flags) {
 namespace {
 
 // Transform length exponent for L limbs: the smallest m >= kMinLog2N with
-// 2^m >= 2L - 1 (the full product of two L-limb numbers fits without wrap).
-uint32_t log2_len(uint64_t L) {
+// f * 2^m >= 2L - 1 (f = 1 or 3; the full product of two L-limb numbers fits
+// without wrap).
+uint32_t log2_len(uint64_t L, uint32_t f = 1) {
     uint32_t m = kMinLog2N;
-    while ((1ull << m) < 2 * L - 1) ++m;
+    while ((uint64_t)f << m < 2 * L - 1) ++m;
     return m;
 }
 
-// Prime triple for transforms of length 2^m (m <= MAX_LOG2N).
-const pa::PrimeTriple &triple_for(uint32_t m) {
+// Prime triple for transforms of length 2^m (mix = 0, m <= MAX_LOG2N) or
+// 3 * 2^m (mix = 1, m <= MAX_LOG2N_MIX); null beyond those lengths.
+const pa::PrimeTriple *triple_for(uint32_t m, uint32_t mix) {
+    if (mix) {
+        for (const pa::PrimeTriple &t : pa::PRIME_TRIPLES_3)
+            if (m <= t.max_lg) return &t;
+        return nullptr;
+    }
     for (const pa::PrimeTriple &t : pa::PRIME_TRIPLES)
-        if (m <= t.max_lg) return t;
-    return pa::PRIME_TRIPLES[sizeof(pa::PRIME_TRIPLES) / sizeof(pa::PRIME_TRIPLES[0]) - 1];
+        if (m <= t.max_lg) return &t;
+    return nullptr;
 }
 
 // Exactness of the three-prime transform: every coefficient of the sum of the
@@ -134,24 +141,53 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     pa_status st = plan_shape(prm, &gamma, &k, &B);
     if (st != PA_OK) return st;
     if (k > kMaxK) return PA_ERR_LIMIT;
-    if (B == 0) {
-        // widest limb that keeps the transform exact (fewest limbs); a
-        // narrower limb only lengthens the transform, so a length beyond the
-        // limit at B = 32 is final
-        B = 32;
-        if (log2_len((gamma + B - 1) / B) > pa::MAX_LOG2N) return PA_ERR_LIMIT;
-        while (B > 8) {
-            const uint64_t Lb = (gamma + B - 1) / B;
-            const uint32_t mb = log2_len(Lb);
-            if (mb <= pa::MAX_LOG2N && exact(k, Lb, B, triple_for(mb))) break;
-            --B;
+    const bool pow2_only = (prm->flags & PA_FLAG_POW2_LENGTHS) != 0;
+    // Candidate lengths for limb width b: the shortest 2^m and 3 * 2^m that
+    // hold the product, each with its own primes.  Cost model: butterflies
+    // N log2 N, plus one pass over N for the radix-3 step.  `seen` records
+    // whether some candidate length was within the supported range.
+    bool seen = false;
+    auto choose = [&](uint32_t b, uint32_t *m_out, uint32_t *mix_out, double *cost_out) {
+        const uint64_t Lb = (gamma + b - 1) / b;
+        bool ok = false;
+        for (uint32_t mx = 0; mx < (pow2_only ? 1u : 2u); ++mx) {
+            const uint32_t mb = log2_len(Lb, mx ? 3 : 1);
+            const pa::PrimeTriple *T = triple_for(mb, mx);
+            if (!T) continue;
+            seen = true;
+            if (!exact(k, Lb, b, *T)) continue;
+            const double Nl = (double)((uint64_t)(mx ? 3 : 1) << mb);
+            const double cost = Nl * (std::log2(Nl) + (mx ? 1.0 : 0.0));
+            if (!ok || cost < *cost_out) {
+                ok = true;
+                *m_out = mb;
+                *mix_out = mx;
+                *cost_out = cost;
+            }
         }
+        return ok;
+    };
+    uint32_t m = 0, mix = 0;
+    if (B == 0) {
+        // cheapest exact transform over all limb widths, the widest among equals
+        double best = 0.0;
+        for (uint32_t b = 32; b >= 8; --b) {
+            uint32_t mb, mx;
+            double cost;
+            if (choose(b, &mb, &mx, &cost) && (B == 0 || cost < best)) {
+                B = b;
+                m = mb;
+                mix = mx;
+                best = cost;
+            }
+        }
+        if (B == 0) return seen ? PA_ERR_INEXACT : PA_ERR_LIMIT;
+    } else {
+        double cost;
+        if (!choose(B, &m, &mix, &cost)) return seen ? PA_ERR_INEXACT : PA_ERR_LIMIT;
     }
     const uint64_t L = (gamma + B - 1) / B;
-    const uint32_t m = log2_len(L);
-    if (m > pa::MAX_LOG2N) return PA_ERR_LIMIT;
-    const pa::PrimeTriple &T = triple_for(m);
-    if (!exact(k, L, B, T)) return PA_ERR_INEXACT;
+    const pa::PrimeTriple &T = *triple_for(m, mix);
 
     p->n = prm->n;
     p->r = prm->r;
@@ -159,7 +195,9 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     p->k = k;
     p->B = B;
     p->L = L;
-    p->N = 1ull << m;
+    p->mix = mix;
+    p->Nsub = 1ull << m;
+    p->N = (mix ? 3ull : 1ull) << m;
     p->W = (gamma + 63) / 64;
     p->key_words = (prm->n + 63) / 64;
     p->out_words = (prm->r + 63) / 64;
@@ -218,6 +256,7 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     lay->oT2 = carve(P3 * n2 * 4 * 2);
     lay->oW = carve(P3 * N * 4 * 2);
     lay->oR16 = carve(P3 * pa::R16_TW * 4 * 2);
+    lay->oG3 = carve(mix ? 3 * P3 * 3 * n1 * 4 : 0);
     lay->total = off;
     lay->table_bytes = off - lay->scratch_bytes;
     p->workspace_bytes = off;
@@ -251,6 +290,7 @@ void bind_tables(pa_plan *p, void *tables, const PlanLayout &lay) {
     p->Wi = p->Wf + P3 * N;
     p->R16f = (uint32_t *)(b + lay.oR16);
     p->R16i = p->R16f + P3 * pa::R16_TW;
+    p->G3 = p->mix ? (uint32_t *)(b + lay.oG3) : nullptr;
 }
 
 pa_status enqueue_hash(pa_plan *p, const uint64_t *key, const uint64_t *a, const uint64_t *b,
@@ -346,6 +386,7 @@ pa_status pa_plan_get_info(const pa_plan *p, pa_plan_info *info) {
     info->log2N2 = p->m2;
     info->nprimes = pa::NPRIMES;
     for (int q = 0; q < pa::NPRIMES; ++q) info->primes[q] = p->primes.c[q].p;
+    info->len_factor = p->mix ? 3 : 1;
     return PA_OK;
 }
 

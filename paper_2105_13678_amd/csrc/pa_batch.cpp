@@ -23,7 +23,7 @@ namespace {
 constexpr int kLanes = 4;  // worker streams (one per hardware queue HIP gives a process by default)
 
 struct Tables {
-    uint32_t m;
+    uint32_t len;  // pa::len_key of the transform length
     void *base;
 };
 
@@ -79,7 +79,7 @@ void destroy(pa_batch_plan *bp) {
 // Twiddle tables for plan p's transform length, built on `st` when new.
 void *tables_for(pa_batch_plan *bp, pa_plan *p, const pa::PlanLayout &lay, hipStream_t st) {
     for (Tables &t : bp->tables)
-        if (t.m == p->m) return t.base;
+        if (t.len == pa::len_key(*p)) return t.base;
     void *base = nullptr;
     if (hipMalloc(&base, lay.table_bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -91,7 +91,7 @@ void *tables_for(pa_batch_plan *bp, pa_plan *p, const pa::PlanLayout &lay, hipSt
         (void)hipFree(base);
         return nullptr;
     }
-    bp->tables.push_back(Tables{p->m, base});
+    bp->tables.push_back(Tables{pa::len_key(*p), base});
     return base;
 }
 

@@ -1,9 +1,10 @@
 // Internal declarations shared by the libpa translation units.
 //
 // Arithmetic: exact convolutions of B-bit limb sequences by number-theoretic
-// transforms of length 2^m modulo three primes below 2^30 (4p < 2^32 lets the
-// transforms keep residues only partially reduced).  The primes are the
-// three largest below 2^30 with 2^m | p - 1, from a fixed table per length.
+// transforms of length N = 2^m or N = 3 * 2^m modulo three primes below 2^30
+// (4p < 2^32 lets the transforms keep residues only partially reduced).  The
+// primes are the three largest below 2^30 with N | p - 1, from a fixed table
+// per length.
 // A gamma-bit number is cut into L = ceil(gamma/B) limbs (the paper's 2^B-ary
 // words); every coefficient of the sum of the k limb convolutions is at most
 // k*L*(2^B-1)^2, which the plan checks is below p0*p1*p2, so the
@@ -21,7 +22,8 @@
 namespace pa {
 
 constexpr int NPRIMES = 3;
-constexpr uint32_t MAX_LOG2N = 24;  // longest transform with three such primes
+constexpr uint32_t MAX_LOG2N = 24;      // longest power-of-two transform with three such primes
+constexpr uint32_t MAX_LOG2N_MIX = 23;  // longest transform 3 * 2^m
 
 // The three largest primes p < 2^30 with 2^max_lg | p - 1 (product 2^log2P),
 // for the transform lengths 2^m, m <= max_lg, not served by an earlier row.
@@ -35,6 +37,16 @@ constexpr PrimeTriple PRIME_TRIPLES[] = {
     {22, {998244353u, 985661441u, 943718401u}},     // 2^89.585
     {23, {998244353u, 897581057u, 880803841u}},     // 2^89.351
     {24, {754974721u, 469762049u, 167772161u}},     // 2^85.621
+};
+// The same for the lengths 3 * 2^m: the three largest primes p < 2^30 with
+// 3 * 2^max_lg | p - 1.
+constexpr PrimeTriple PRIME_TRIPLES_3[] = {
+    {18, {1073479681u, 1062469633u, 1056178177u}},  // 2^89.961
+    {19, {1053818881u, 1049100289u, 1012924417u}},  // 2^89.855
+    {20, {1053818881u, 1012924417u, 975175681u}},   // 2^89.750
+    {21, {1012924417u, 975175681u, 962592769u}},    // 2^89.619
+    {22, {943718401u, 918552577u, 880803841u}},     // 2^89.303
+    {23, {880803841u, 754974721u, 377487361u}},     // 2^87.698
 };
 
 // Per-prime constants (Montgomery form x*2^32 mod p where noted).
@@ -58,6 +70,14 @@ struct CrtConst {
     uint32_t inv_p0p1_mod_p2;   // (p0 p1)^-1 mod p2, Montgomery form (mod p2)
     uint32_t pad;
     uint64_t p0p1;              // p0 * p1
+};
+
+// Inverse radix-3 step of the lengths N = 3 * 2^m (Montgomery form, per
+// prime): with w = omega_3 = omega_N^(N/3), the outputs s0 + w^-n0 u1 +
+// w^-2n0 u2 (n0 = 1, 2) are s0 - (u1 + u2)/2 +- h (u1 - u2), h = (w^-1 - w^-2)/2.
+struct Mix3Const {
+    uint32_t neg_half[NPRIMES];  // -1/2 mod p
+    uint32_t h[NPRIMES];
 };
 
 // ---------------------------------------------------------------- carry functions
@@ -89,7 +109,9 @@ struct pa_plan {
     uint64_t n, r, gamma, k, L, N, W;
     uint64_t key_words, out_words;
     uint32_t B;
-    uint32_t m, m1, m2, c_lg;   // N = 2^m = 2^m1 (column length) * 2^m2 (row length); 2^c_lg columns per tile
+    uint32_t mix;               // 1: N = 3 * 2^m (a radix-3 step over three length-2^m transforms); 0: N = 2^m
+    uint64_t Nsub;              // 2^m: length of the power-of-two transforms
+    uint32_t m, m1, m2, c_lg;   // 2^m = 2^m1 (column length) * 2^m2 (row length); 2^c_lg columns per tile
     uint32_t ci_lg;             // columns per tile of the inverse column pass
     uint32_t s_top;             // bits in the top limb: gamma - B*(L-1), in [1, B]
     uint32_t e_fold;            // B*L - gamma, in [0, B)
@@ -98,6 +120,7 @@ struct pa_plan {
     double exact_log2;
     pa::PrimeSet primes;
     pa::CrtConst crt;
+    pa::Mix3Const mix3;
 
     // device memory (one allocation, carved)
     void *base;
@@ -118,6 +141,8 @@ struct pa_plan {
     uint32_t *Wf, *Wi;      // per prime: four-step twiddles, stored (bit-reversed) row order
     uint32_t *R16f, *R16i;  // per prime: step twiddles of the 4096-point row kernel in thread order
                             // (R16_TW words: [j][t] omega^(t brev(j)), then [j][n1] omega^(16 n1 brev(j)))
+    uint32_t *G3;           // N = 3 * 2^m only: three tables of NPRIMES x 3 x N1 words, entry
+                            // [q][k0][r] = omega_N^(k0 r N2), omega_N^(k0 (r N2 + N/3)), omega_N^(-k0 r N2)
     const uint32_t *res_a;  // resident seed transforms (k x 3 x N words) or null
     const uint32_t *res_b;  // resident transform of b (3 x N words) or null
     uint32_t *h_status;     // pinned host word
@@ -139,9 +164,12 @@ namespace pa {
 // transform length) the following table_bytes.
 struct PlanLayout {
     size_t oX, oC, oC96, oT, oS, oY, oU, oAgg, oNo, oSt, oSo;
-    size_t oT1, oT2, oW, oR16;
+    size_t oT1, oT2, oW, oR16, oG3;
     size_t scratch_bytes, table_bytes, total;
 };
+
+// Identifies a plan's transform length (and so its primes and twiddle tables).
+inline uint32_t len_key(const pa_plan &p) { return p.mix << 7 | p.m; }
 
 // Host-side plan derivation (no device access) and buffer binding (pa_api.cpp).
 pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay);

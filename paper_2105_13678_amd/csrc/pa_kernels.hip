@@ -131,19 +131,43 @@ __global__ void k_tw_pow(uint32_t *dst, uint64_t count, TwArgs A) {
     if (j < count) dst[q * count + j] = mulmod_slow(A.scale[q], powmod_slow(A.base[q], j, A.p[q]), A.p[q]);
 }
 
-// Four-step twiddles in stored row order: row rho holds column frequency
-// k1 = bitrev(rho); Wf = omega_N^(k1*n2), Wi = c * omega_N^-(k1*n2), both
-// scaled as given in the arguments (Montgomery form and 1/N folded in).
-__global__ void k_tw_four(uint32_t *Wf, uint32_t *Wi, uint32_t m1, uint32_t m2, TwArgs F, TwArgs I) {
+// Four-step twiddles in stored row order, N = sub * 2^(m1 + m2) words per
+// prime (sub = 1, or 3 for three length-2^(m1+m2) transforms side by side):
+// row rho = k0 * 2^m1 + r of transform k0 holds column frequency k1 =
+// bitrev(r); Wf = omega_N^(e), Wi = c * omega_N^(-e) with e = (sub*k1 + k0)*n2,
+// i.e. the four-step twiddle omega_{N/sub}^(k1*n2) times the column part
+// omega_N^(k0*n2) of the radix-3 twiddle omega_N^(k0*n); both scaled as given
+// in the arguments (Montgomery form and 1/N folded in).
+__global__ void k_tw_four(uint32_t *Wf, uint32_t *Wi, uint32_t m1, uint32_t m2, uint32_t sub, TwArgs F, TwArgs I) {
     const uint32_t q = blockIdx.y;
-    const uint64_t N = 1ull << (m1 + m2);
+    const uint64_t N = (uint64_t)sub << (m1 + m2);
     const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= N) return;
     const uint32_t rho = (uint32_t)(idx >> m2);
     const uint32_t n2 = (uint32_t)(idx & ((1u << m2) - 1));
-    const uint64_t e = (uint64_t)bitrev(rho, m1) * n2;
+    const uint32_t k0 = rho >> m1, r = rho & ((1u << m1) - 1);
+    const uint64_t e = ((uint64_t)sub * bitrev(r, m1) + k0) * n2;
     Wf[q * N + idx] = mulmod_slow(F.scale[q], powmod_slow(F.base[q], e, F.p[q]), F.p[q]);
     Wi[q * N + idx] = mulmod_slow(I.scale[q], powmod_slow(I.base[q], e, I.p[q]), I.p[q]);
+}
+
+// Row parts of the radix-3 twiddles of the lengths N = 3 * 2^m (m = m1 + m2),
+// per prime q and transform k0 < 3, indexed by the column-pass row r < 2^m1:
+// g[0] = omega_N^(k0 r N2) and g[1] = omega_N^(k0 (r N2 + N/3)) (forward;
+// the second includes omega_3^k0), g[2] = omega_N^(-k0 r N2) (inverse), each
+// table NPRIMES x 3 x 2^m1 words, Montgomery form (scale of the arguments).
+__global__ void k_tw_g3(uint32_t *g, uint32_t m1, uint32_t m2, TwArgs F, TwArgs I) {
+    const uint32_t q = blockIdx.y;
+    const uint32_t n1 = 1u << m1;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3u * n1) return;
+    const uint32_t k0 = i >> m1, r = i & (n1 - 1);
+    const uint64_t e = (uint64_t)k0 * ((uint64_t)r << m2);
+    const uint64_t e3 = (uint64_t)k0 * (((uint64_t)r << m2) + (1ull << (m1 + m2)));
+    const size_t tab = (size_t)NPRIMES * 3 * n1;
+    g[q * 3 * n1 + i] = mulmod_slow(F.scale[q], powmod_slow(F.base[q], e, F.p[q]), F.p[q]);
+    g[tab + q * 3 * n1 + i] = mulmod_slow(F.scale[q], powmod_slow(F.base[q], e3, F.p[q]), F.p[q]);
+    g[2 * tab + q * 3 * n1 + i] = mulmod_slow(I.scale[q], powmod_slow(I.base[q], e, I.p[q]), I.p[q]);
 }
 
 // Step twiddles of the 4096-point row kernel rearranged so that the lanes of
@@ -197,6 +221,8 @@ struct ColFwdArgs {
     const uint32_t *ylimbs;
     uint32_t *notones;
     const uint32_t *tw;  // per prime: omega_{N1}^e, e < N1
+    uint64_t Nsub;       // length of the power-of-two transforms (N or N/3)
+    const uint32_t *g3;  // N = 3 Nsub: the radix-3 row twiddle tables (k_tw_g3)
     PrimeSet P;
 };
 
@@ -274,50 +300,81 @@ __device__ __forceinline__ void col_last_fwd(const uint32_t *buf, uint32_t lg, u
 // Unpack + forward column pass.  blockIdx.y selects the array: in MMH mode
 // arrays 0..k-1 are the key chunks x_i and k..2k-1 the seed chunks a_i; in
 // MH mode array 0 is y and array 1 is b.  blockIdx.z is the prime.  Limb j of
-// a chunk is its bits [jB, jB+B); limbs j >= L are the zero padding.  Since
-// N >= 2L - 1, every limb index >= N/2 is padding, so rows n1 >= N1/2 of the
-// column tile are zero and the first radix-8 step unpacks only four inputs.
+// a chunk is its bits [jB, jB+B); limbs j >= L are the zero padding.
+// N = 2^m (MIX false): since N >= 2L - 1, every limb index >= N/2 is padding,
+// so rows n1 >= N1/2 of the column tile are zero and the first radix-8 step
+// unpacks only four inputs.
+// N = 3 Nsub (MIX true; blockIdx.y = 3 * array + k0): the workgroup computes
+// transform k0 of the radix-3 split, whose input at n < Nsub is
+// (x_n + omega_3^k0 x_(n+Nsub)) omega_N^(k0 n); x_(n+2Nsub) is padding since
+// L <= Nsub * 3/2.  Only the row part omega_N^(k0 r N2) of the twiddle (n =
+// r N2 + c) is applied here; the column part omega_N^(k0 c) rides on the
+// four-step twiddle of the row pass.
 // The last step writes its rows straight to global memory.
-template <int Stage>
+template <int Stage, bool MIX>
 __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
     uint32_t *lds = lds_dyn;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t arr = blockIdx.y + A.arr0, pq = blockIdx.z;
+    const uint32_t arr_local = MIX ? blockIdx.y / 3u : blockIdx.y;
+    const uint32_t k0 = MIX ? blockIdx.y - 3u * arr_local : 0u;
+    const uint32_t arr = arr_local + A.arr0, pq = blockIdx.z;
     const PrimeConst M = A.P.c[pq];
     const uint32_t *tw = A.tw + ((uint64_t)pq << A.m1);
     const uint32_t c_lg = A.c_lg, lg = A.m1;
     const uint32_t cmask = (1u << c_lg) - 1;
     const uint64_t c0 = (uint64_t)tile << c_lg;
-    const bool is_key = (A.mode == 0) && arr < A.k && pq == 0;  // the reload check runs once per chunk
+    // the reload check runs once per chunk
+    const bool is_key = (A.mode == 0) && arr < A.k && pq == 0 && k0 == 0;
     const uint32_t full = (uint32_t)((1ull << A.B) - 1), topv = (uint32_t)((1ull << A.s_top) - 1);
     const uint32_t lgMp = lg - 3;
     const uint32_t ntask = (1u << lgMp) << c_lg;
-    uint32_t *out = A.X + ((uint64_t)blockIdx.y * NPRIMES + pq) * A.N;
+    uint32_t *out = A.X + ((uint64_t)arr_local * NPRIMES + pq) * A.N + (uint64_t)k0 * A.Nsub;
     const LimbSrc S = limb_src(A, arr);
     const uint32_t L = (uint32_t)A.L;
+    const uint32_t Ns = (uint32_t)A.Nsub;
+    const uint32_t *g0 = nullptr, *g1 = nullptr;
+    if (MIX) {
+        const size_t tab = (size_t)NPRIMES * 3 << lg;
+        g0 = A.g3 + (((size_t)pq * 3 + k0) << lg);
+        g1 = g0 + tab;
+    }
     bool not_ones = false;
     for (uint32_t task = threadIdx.x; task < ntask; task += blockDim.x) {
         const uint32_t q = task & cmask;
         const uint32_t n1 = task >> c_lg;
         uint32_t v[8];
+        if (MIX) {
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            const uint32_t row = n1 + ((uint32_t)jj << lgMp);
-            const uint32_t j = (row << A.m2) + (uint32_t)c0 + q;  // limb index
-            const uint32_t x = limb_at(S, j);
-            if (is_key && j < L) not_ones |= (x != (j == L - 1 ? topv : full));
-            v[jj] = mont(x, M.one, M);  // x mod p, in [0, 2p)
+            for (int jj = 0; jj < 8; ++jj) {
+                const uint32_t row = n1 + ((uint32_t)jj << lgMp);
+                const uint32_t j = (row << A.m2) + (uint32_t)c0 + q;  // index in the transform
+                const uint32_t x0 = limb_at(S, j), x1 = limb_at(S, j + Ns);
+                if (is_key) {
+                    if (j < L) not_ones |= (x0 != (j == L - 1 ? topv : full));
+                    if (j + Ns < L) not_ones |= (x1 != (j + Ns == L - 1 ? topv : full));
+                }
+                v[jj] = red2(mont(x0, g0[row], M) + mont(x1, g1[row], M), M);  // in [0, 2p)
+            }
+        } else {
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const uint32_t row = n1 + ((uint32_t)jj << lgMp);
+                const uint32_t j = (row << A.m2) + (uint32_t)c0 + q;  // limb index
+                const uint32_t x = limb_at(S, j);
+                if (is_key && j < L) not_ones |= (x != (j == L - 1 ? topv : full));
+                v[jj] = mont(x, M.one, M);  // x mod p, in [0, 2p)
+            }
         }
         if (lg > 3) {
             uint32_t w[8];
 #pragma unroll
             for (int s = 1; s < 8; ++s) w[s] = tw[n1 * brev_small(s, 3)];
-            dft_fwd_x<8, true, true>(v, w, M);
+            dft_fwd_x<8, !MIX, true>(v, w, M);
 #pragma unroll
             for (int jj = 0; jj < 8; ++jj)
                 lds[tile_swz(((n1 + ((uint32_t)jj << lgMp)) << c_lg) + q, c_lg)] = v[jj];
         } else {
-            dft_fwd_x<8, true, false>(v, nullptr, M);
+            dft_fwd_x<8, !MIX, false>(v, nullptr, M);
 #pragma unroll
             for (int jj = 0; jj < 8; ++jj) out[((uint64_t)jj << A.m2) + c0 + q] = v[jj];
         }
@@ -711,6 +768,7 @@ struct ColInvArgs {
     uint64_t N;
     uint32_t m1, m2, c_lg;
     const uint32_t *twi;  // per prime: omega_{N1}^-e, e < N1
+    uint64_t Nsub;        // words per transform: blockIdx.z's transform starts at z * Nsub
     PrimeSet P;
 };
 
@@ -744,7 +802,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_inv(ColInvArgs A) {
     const uint32_t pq = blockIdx.y;
     const PrimeConst M = A.P.c[pq];
     const uint32_t *twi = A.twi + ((uint64_t)pq << A.m1);
-    uint32_t *cc = A.Cc + pq * A.N;
+    uint32_t *cc = A.Cc + pq * A.N + blockIdx.z * A.Nsub;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t c_lg = A.c_lg, lg = A.m1;
     const uint32_t cmask = (1u << c_lg) - 1;
@@ -865,7 +923,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_inv(ColInvArgs A) {
     const uint32_t pq = blockIdx.y;
     const PrimeConst M = A.P.c[pq];
     const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.twi + ((uint64_t)pq << C9_LG), 1u << C9_LG);
-    uint32_t *cc = A.Cc + pq * A.N;
+    uint32_t *cc = A.Cc + pq * A.N + blockIdx.z * A.Nsub;
     const uint64_t c0 = (uint64_t)xcd_tile(blockIdx.x, gridDim.x) << C9_CLG;
     const uint32_t t = threadIdx.x;
 #pragma unroll 1
@@ -915,6 +973,20 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_inv(ColInvArgs A) {
     }
 }
 
+// Garner's reconstruction: canonical residues r_q mod p_q of a value below
+// p0 p1 p2 -> the value.
+__device__ __forceinline__ unsigned __int128 garner(uint32_t r0, uint32_t r1, uint32_t r2, const PrimeSet &P,
+                                                    const CrtConst &K) {
+    const PrimeConst &M1 = P.c[1], &M2 = P.c[2];
+    // v1 = (r1 - r0) / p0 mod p1
+    const uint32_t v1 = mmul(msub(r1, mmul(r0, M1.one, M1), M1), K.inv_p0_mod_p1, M1);
+    // v2 = (r2 - r0 - v1 p0) / (p0 p1) mod p2
+    const uint32_t r0m = mmul(r0, M2.one, M2);
+    const uint32_t v1p0 = mmul(v1, K.p0_mod_p2, M2);
+    const uint32_t v2 = mmul(msub(msub(r2, r0m, M2), v1p0, M2), K.inv_p0p1_mod_p2, M2);
+    return (unsigned __int128)r0 + (unsigned __int128)v1 * P.c[0].p + (unsigned __int128)v2 * K.p0p1;
+}
+
 // Chinese-remainder reconstruction (Garner): canonical residues mod p0, p1,
 // p2 of a coefficient below p0 p1 p2 -> its exact value, as three word planes.
 // With notones set, workgroup 0 also finishes the status word: RELOAD when
@@ -929,19 +1001,66 @@ __global__ void k_crt(const uint32_t *__restrict__ cc, uint32_t *c96, uint64_t N
         if (threadIdx.x == 0) status[1] = status[0] | (any ? ST_RELOAD : 0u);
     }
     if (j >= count) return;
-    const PrimeConst &M1 = P.c[1], &M2 = P.c[2];
-    const uint32_t r0 = cc[j], r1 = cc[N + j], r2 = cc[2 * N + j];
-    // v1 = (r1 - r0) / p0 mod p1
-    const uint32_t v1 = mmul(msub(r1, mmul(r0, M1.one, M1), M1), K.inv_p0_mod_p1, M1);
-    // v2 = (r2 - r0 - v1 p0) / (p0 p1) mod p2
-    const uint32_t r0m = mmul(r0, M2.one, M2);
-    const uint32_t v1p0 = mmul(v1, K.p0_mod_p2, M2);
-    const uint32_t v2 = mmul(msub(msub(r2, r0m, M2), v1p0, M2), K.inv_p0p1_mod_p2, M2);
-    const unsigned __int128 c = (unsigned __int128)r0 + (unsigned __int128)v1 * P.c[0].p +
-                                (unsigned __int128)v2 * K.p0p1;
+    const unsigned __int128 c = garner(cc[j], cc[N + j], cc[2 * N + j], P, K);
     c96[j] = (uint32_t)c;
     c96[N + j] = (uint32_t)(c >> 32);
     c96[2 * N + j] = (uint32_t)(c >> 64);
+}
+
+struct Crt3Args {
+    const uint32_t *cc;  // 3 primes x N residues: three inverse transforms of Nsub words each
+    uint32_t *c96;
+    uint64_t N, Nsub, count;
+    uint32_t m1, m2;
+    const uint32_t *gi;  // inverse radix-3 row twiddles [q][k0][r] (third k_tw_g3 table)
+    PrimeSet P;
+    CrtConst K;
+    Mix3Const X;
+    const uint32_t *notones;
+    uint64_t k;
+    uint32_t *status;
+};
+
+// The same reconstruction for N = 3 Nsub, fused with the inverse radix-3
+// step: thread j1 < Nsub takes the residues s_k0 at j1 of the three inverse
+// transforms (canonical, 1/N and the column part omega_N^(-k0 c) of the
+// twiddle already applied), multiplies s_1, s_2 by the row part
+// omega_N^(-k0 r N2) (j1 = r N2 + c), runs the 3-point inverse DFT and
+// reconstructs the coefficients j1 + n0 Nsub (n0 < 3) below `count`.
+__global__ void k_crt3(Crt3Args A) {
+    const uint64_t j1 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (A.notones && blockIdx.x == 0) {
+        bool reload = false;
+        for (uint64_t i = threadIdx.x; i < A.k; i += blockDim.x) reload |= (A.notones[i] == 0u);
+        const int any = __syncthreads_or(reload);
+        if (threadIdx.x == 0) A.status[1] = A.status[0] | (any ? ST_RELOAD : 0u);
+    }
+    if (j1 >= A.Nsub || j1 >= A.count) return;
+    const uint32_t r = (uint32_t)(j1 >> A.m2);
+    uint32_t x[3][NPRIMES];  // [n0][prime], canonical
+#pragma unroll
+    for (int q = 0; q < NPRIMES; ++q) {
+        const PrimeConst &M = A.P.c[q];
+        const uint32_t *c = A.cc + q * A.N + j1;
+        const uint32_t s0 = c[0], s1 = c[A.Nsub], s2 = c[2 * A.Nsub];
+        const uint32_t *gi = A.gi + (((size_t)q * 3) << A.m1);
+        const uint32_t u1 = mont(s1, gi[(1u << A.m1) + r], M);  // [0, 2p)
+        const uint32_t u2 = mont(s2, gi[(2u << A.m1) + r], M);
+        const uint32_t a = mont(u1 + u2, A.X.neg_half[q], M);    // -(u1 + u2)/2
+        const uint32_t d = mont(u1 + M.p2 - u2, A.X.h[q], M);    // h (u1 - u2)
+        x[0][q] = canon(red2(s0 + red2(u1 + u2, M), M), M);
+        x[1][q] = canon(red2(s0 + red2(a + d, M), M), M);
+        x[2][q] = canon(red2(s0 + red2(a + M.p2 - d, M), M), M);
+    }
+#pragma unroll
+    for (int n0 = 0; n0 < 3; ++n0) {
+        const uint64_t j = j1 + (uint64_t)n0 * A.Nsub;
+        if (j >= A.count) break;
+        const unsigned __int128 c = garner(x[n0][0], x[n0][1], x[n0][2], A.P, A.K);
+        A.c96[j] = (uint32_t)c;
+        A.c96[A.N + j] = (uint32_t)(c >> 32);
+        A.c96[2 * A.N + j] = (uint32_t)(c >> 64);
+    }
 }
 
 __device__ __forceinline__ unsigned __int128 coef(const uint32_t *__restrict__ c96, uint64_t N, uint64_t j) {
@@ -1139,8 +1258,6 @@ uint32_t hinv(uint32_t a, uint32_t p) { return hpow(a % p, p - 2, p); }
 
 uint32_t hmont(uint32_t a, uint32_t p) { return (uint32_t)(((uint64_t)(a % p) << 32) % p); }
 
-// Smallest generator of the multiplicative group mod p (p - 1 has prime
-// factors 2, 3, 5, 7 only for the primes used here).
 // A primitive 2^log2n-th root of unity (2^log2n | p - 1): g^((p-1)/2^log2n)
 // for a quadratic non-residue g, whose order has the full power of two of
 // p - 1 (Euler's criterion: g^((p-1)/2) = -1).
@@ -1148,6 +1265,23 @@ uint32_t root_of_unity(uint32_t p, uint32_t log2n) {
     uint32_t g = 2;
     while (hpow(g, (p - 1) / 2, p) != p - 1) ++g;
     return hpow(g, (uint64_t)(p - 1) >> log2n, p);
+}
+
+// A primitive root of unity of order 2^log2n (mix = 0) or 3 * 2^log2n (mix =
+// 1; 3 * 2^log2n | p - 1).  For mix = 1 it is w^a c with w = root_of_unity(p,
+// log2n), a = 3^-1 mod 2^log2n and c = h^((p-1)/3) != 1 for the smallest such
+// h: its cube is w itself, so the three power-of-two transforms of the
+// radix-3 split use exactly the roots (and the radix-16 constants) of the
+// plain length-2^log2n transform.
+uint32_t root_of_len(uint32_t p, uint32_t log2n, uint32_t mix) {
+    const uint32_t w = root_of_unity(p, log2n);
+    if (!mix) return w;
+    uint64_t inv3 = 3;  // 3^-1 mod 2^64 by Newton iteration (3 * 3 = 1 mod 8)
+    for (int i = 0; i < 5; ++i) inv3 *= 2 - 3 * inv3;
+    const uint64_t a = inv3 & ((1ull << log2n) - 1);
+    uint32_t c = 1;
+    for (uint32_t h = 2; c == 1; ++h) c = hpow(h, (p - 1) / 3, p);
+    return hmul(hpow(w, a, p), c, p);
 }
 
 }  // namespace
@@ -1179,23 +1313,35 @@ void init_prime_constants(pa_plan *p, const uint32_t primes[NPRIMES]) {
     p->crt.inv_p0p1_mod_p2 = hmont(hinv(hmul(p0 % p2, p1 % p2, p2), p2), p2);
     p->crt.pad = 0;
     p->crt.p0p1 = (uint64_t)p0 * p1;
+    for (int q = 0; q < NPRIMES; ++q) {
+        const uint32_t pr = primes[q];
+        p->mix3.neg_half[q] = hmont((pr - 1) / 2, pr);
+        p->mix3.h[q] = 0;
+        if (p->mix) {
+            const uint32_t w3 = hpow(root_of_len(pr, p->m, 1), p->Nsub, pr);  // omega_N^(N/3) = omega_3
+            const uint32_t w3sq = hmul(w3, w3, pr);                         // omega_3^-1
+            // (omega_3^-1 - omega_3^-2) / 2
+            p->mix3.h[q] = hmont(hmul((w3sq + pr - w3) % pr, (pr + 1) / 2, pr), pr);
+        }
+    }
 }
 
 hipError_t launch_twiddles(pa_plan *p, hipStream_t st) {
     const uint64_t N = p->N, n1 = 1ull << p->m1, n2 = 1ull << p->m2;
-    TwArgs t1f, t1i, t2f, t2i, Ff, Fi;
+    const uint32_t sub = p->mix ? 3u : 1u;  // omega_{N/sub} = omega_N^sub
+    TwArgs t1f, t1i, t2f, t2i, Ff, Fi, Gi;
     for (int q = 0; q < NPRIMES; ++q) {
         const uint32_t pr = p->primes.c[q].p;
-        const uint32_t w = root_of_unity(pr, p->m), wi = hinv(w, pr);
+        const uint32_t w = root_of_len(pr, p->m, p->mix), wi = hinv(w, pr);
         const uint32_t R = (uint32_t)((1ull << 32) % pr);
-        t1f.p[q] = t1i.p[q] = t2f.p[q] = t2i.p[q] = Ff.p[q] = Fi.p[q] = pr;
-        t1f.base[q] = hpow(w, n2, pr);  // omega_{N1}
-        t1i.base[q] = hpow(wi, n2, pr);
-        t2f.base[q] = hpow(w, n1, pr);  // omega_{N2}
-        t2i.base[q] = hpow(wi, n1, pr);
+        t1f.p[q] = t1i.p[q] = t2f.p[q] = t2i.p[q] = Ff.p[q] = Fi.p[q] = Gi.p[q] = pr;
+        t1f.base[q] = hpow(w, (uint64_t)sub * n2, pr);  // omega_{N1}
+        t1i.base[q] = hpow(wi, (uint64_t)sub * n2, pr);
+        t2f.base[q] = hpow(w, (uint64_t)sub * n1, pr);  // omega_{N2}
+        t2i.base[q] = hpow(wi, (uint64_t)sub * n1, pr);
         Ff.base[q] = w;
-        Fi.base[q] = wi;
-        t1f.scale[q] = t1i.scale[q] = t2f.scale[q] = t2i.scale[q] = Ff.scale[q] = R;
+        Fi.base[q] = Gi.base[q] = wi;
+        t1f.scale[q] = t1i.scale[q] = t2f.scale[q] = t2i.scale[q] = Ff.scale[q] = Gi.scale[q] = R;
         // inverse four-step twiddle: 1/N, times 2^32 to undo the Montgomery
         // factor of the pointwise product, in Montgomery form
         Fi.scale[q] = hmul(hmul(hinv((uint32_t)(N % pr), pr), R, pr), R, pr);
@@ -1205,7 +1351,10 @@ hipError_t launch_twiddles(pa_plan *p, hipStream_t st) {
     hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(n2, 256), NPRIMES), dim3(256), 0, st, p->tw2f, n2, t2f);
     hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(n2, 256), NPRIMES), dim3(256), 0, st, p->tw2i, n2, t2i);
     hipLaunchKernelGGL(k_tw_four, dim3(blocks_for(N, 256), NPRIMES), dim3(256), 0, st, p->Wf, p->Wi, p->m1, p->m2,
-                       Ff, Fi);
+                       sub, Ff, Fi);
+    if (p->mix)
+        hipLaunchKernelGGL(k_tw_g3, dim3(blocks_for(3 * n1, 256), NPRIMES), dim3(256), 0, st, p->G3, p->m1, p->m2,
+                           Ff, Gi);
     if (p->m2 == 12) {
         hipLaunchKernelGGL(k_tw_r16, dim3(blocks_for(R16_TW, 256), NPRIMES), dim3(256), 0, st, p->tw2f, p->R16f);
         hipLaunchKernelGGL(k_tw_r16, dim3(blocks_for(R16_TW, 256), NPRIMES), dim3(256), 0, st, p->tw2i, p->R16i);
@@ -1244,6 +1393,8 @@ static ColFwdArgs col_args(pa_plan *p, uint32_t mode) {
     cf.ylimbs = nullptr;
     cf.notones = p->notones;
     cf.tw = p->tw1f;
+    cf.Nsub = p->Nsub;
+    cf.g3 = p->G3;
     cf.P = p->primes;
     return cf;
 }
@@ -1252,10 +1403,14 @@ template <int Stage>
 static void launch_col_fwd(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, hipStream_t st) {
     const unsigned ncol_tiles = 1u << (p->m2 - p->c_lg);
     const size_t col_lds = ((size_t)4 << p->m1) << p->c_lg;
-    if (p->m1 == C9_LG && p->c_lg == C9_CLG)  // all three primes per workgroup
+    if (p->mix)  // one workgroup per (tile, array, radix-3 branch, prime)
+        hipLaunchKernelGGL((k_col_fwd<Stage, true>), dim3(ncol_tiles, 3 * narrays, NPRIMES), dim3(COL_THREADS),
+                           col_lds, st, cf);
+    else if (p->m1 == C9_LG && p->c_lg == C9_CLG)  // all three primes per workgroup
         hipLaunchKernelGGL(k_col9_fwd<Stage>, dim3(ncol_tiles, narrays, 1), dim3(COL_THREADS), col_lds, st, cf);
     else
-        hipLaunchKernelGGL(k_col_fwd<Stage>, dim3(ncol_tiles, narrays, NPRIMES), dim3(COL_THREADS), col_lds, st, cf);
+        hipLaunchKernelGGL((k_col_fwd<Stage, false>), dim3(ncol_tiles, narrays, NPRIMES), dim3(COL_THREADS),
+                           col_lds, st, cf);
 }
 
 static RowArgs row_args(pa_plan *p, uint64_t npairs, const uint32_t *seed_side) {
@@ -1279,10 +1434,11 @@ static RowArgs row_args(pa_plan *p, uint64_t npairs, const uint32_t *seed_side) 
 
 template <int Stage>
 static void launch_row(pa_plan *p, const RowArgs &ra, hipStream_t st) {
+    const unsigned rows = (unsigned)(p->N >> p->m2);  // 2^m1, or 3 * 2^m1 for N = 3 * 2^m
     if (p->m2 == 12)
-        hipLaunchKernelGGL(k_row16<Stage>, dim3(1u << p->m1, NPRIMES), dim3(R16_THREADS), (size_t)8 * R16_LEN, st, ra);
+        hipLaunchKernelGGL(k_row16<Stage>, dim3(rows, NPRIMES), dim3(R16_THREADS), (size_t)8 * R16_LEN, st, ra);
     else
-        hipLaunchKernelGGL(k_row<Stage>, dim3(1u << p->m1, NPRIMES), dim3(row_threads(p)), (size_t)4 << p->m2, st, ra);
+        hipLaunchKernelGGL(k_row<Stage>, dim3(rows, NPRIMES), dim3(row_threads(p)), (size_t)4 << p->m2, st, ra);
 }
 
 static ColInvArgs colinv_args(pa_plan *p) {
@@ -1293,17 +1449,19 @@ static ColInvArgs colinv_args(pa_plan *p) {
     ci.m2 = p->m2;
     ci.c_lg = p->ci_lg;
     ci.twi = p->tw1i;
+    ci.Nsub = p->Nsub;
     ci.P = p->primes;
     return ci;
 }
 
 template <int Stage>
 static void launch_col_inv(pa_plan *p, const ColInvArgs &ci, hipStream_t st) {
+    const unsigned nsub = p->mix ? 3u : 1u;  // blockIdx.z: transform of the radix-3 split
     if (p->m1 == C9_LG && p->m2 >= C9_CLG)
-        hipLaunchKernelGGL(k_col9_inv<Stage>, dim3(1u << (p->m2 - C9_CLG), NPRIMES), dim3(COL_THREADS),
+        hipLaunchKernelGGL(k_col9_inv<Stage>, dim3(1u << (p->m2 - C9_CLG), NPRIMES, nsub), dim3(COL_THREADS),
                            (size_t)4 << (C9_LG + C9_CLG), st, ci);
     else
-        hipLaunchKernelGGL(k_col_inv<Stage>, dim3(1u << (p->m2 - p->ci_lg), NPRIMES), dim3(COL_THREADS),
+        hipLaunchKernelGGL(k_col_inv<Stage>, dim3(1u << (p->m2 - p->ci_lg), NPRIMES, nsub), dim3(COL_THREADS),
                            ((size_t)4 << p->m1) << p->ci_lg, st, ci);
 }
 
@@ -1371,11 +1529,36 @@ static hipError_t run_carry(pa_plan *p, DigitArgs A, uint32_t *out, uint64_t ndi
     return hipGetLastError();
 }
 
+// Coefficients [0, count) of the convolution from the residues in Cc (with
+// notones: also the RELOAD status).
+static void launch_crt(pa_plan *p, uint64_t count, const uint32_t *notones, hipStream_t st) {
+    if (!p->mix) {
+        hipLaunchKernelGGL(k_crt, dim3(blocks_for(count, 256)), dim3(256), 0, st, p->Cc, p->C96, p->N, count,
+                           p->primes, p->crt, notones, notones ? p->k : 0, p->status);
+        return;
+    }
+    Crt3Args A;
+    A.cc = p->Cc;
+    A.c96 = p->C96;
+    A.N = p->N;
+    A.Nsub = p->Nsub;
+    A.count = count;
+    A.m1 = p->m1;
+    A.m2 = p->m2;
+    A.gi = p->G3 + (size_t)2 * NPRIMES * 3 * ((size_t)1 << p->m1);
+    A.P = p->primes;
+    A.K = p->crt;
+    A.X = p->mix3;
+    A.notones = notones;
+    A.k = notones ? p->k : 0;
+    A.status = p->status;
+    hipLaunchKernelGGL(k_crt3, dim3(blocks_for(count < p->Nsub ? count : p->Nsub, 256)), dim3(256), 0, st, A);
+}
+
 hipError_t launch_fold(pa_plan *p, hipStream_t st) {
     phase_mark(p, PA_PH_FOLD, true, st);
     const uint64_t ncoef = 2 * p->L - 1;  // nonzero coefficients of the product
-    hipLaunchKernelGGL(k_crt, dim3(blocks_for(ncoef, 256)), dim3(256), 0, st, p->Cc, p->C96, p->N, ncoef,
-                       p->primes, p->crt, p->notones, p->k, p->status);
+    launch_crt(p, ncoef, p->notones, st);
     // first fold at bit gamma, normalised over M1 digits (the sum fits: no carry out)
     hipError_t e = run_carry<DIG_FOLD>(p, digit_args(p), p->s, p->M1, p->M1, false, false, st);
     if (e != hipSuccess) return e;
@@ -1406,8 +1589,7 @@ hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, hipStream
 
     phase_mark(p, PA_PH_MH_CARRY, true, st);
     // only the coefficients below limb L matter mod 2^gamma
-    hipLaunchKernelGGL(k_crt, dim3(blocks_for(p->L, 256)), dim3(256), 0, st, p->Cc, p->C96, p->N, p->L, p->primes,
-                       p->crt, nullptr, 0, p->status);
+    launch_crt(p, p->L, nullptr, st);
     DigitArgs A = digit_args(p);
     A.cseed = c;
     hipError_t e = run_carry<DIG_MH>(p, A, p->U, p->L, p->L - 1, true, false, st);

@@ -40,7 +40,7 @@ struct Seeds {
     uint64_t gamma, kmax;
     uint64_t *d_a, *d_b, *d_c;  // one device allocation: kmax*W + W + W words
     // column-pass transforms of a (kmax x 3 x N words) and b (3 x N words),
-    // per transform shape (limb width B << 8 | log2 N), built on first use
+    // per transform shape (limb width B << 8 | pa::len_key), built on first use
     std::map<uint32_t, uint32_t *> trans;
 };
 
@@ -112,7 +112,7 @@ uint64_t seed_key(uint32_t session, uint64_t gamma) { return ((uint64_t)session 
 // first time (worker thread only).
 void *tables_for(pa_server *s, Request &r, hipStream_t st) {
     for (auto &t : s->tables)
-        if (t.first == r.plan.m) return t.second;
+        if (t.first == pa::len_key(r.plan)) return t.second;
     void *base = nullptr;
     if (hipMalloc(&base, r.lay.table_bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -124,7 +124,7 @@ void *tables_for(pa_server *s, Request &r, hipStream_t st) {
         (void)hipFree(base);
         return nullptr;
     }
-    s->tables.emplace_back(r.plan.m, base);
+    s->tables.emplace_back(pa::len_key(r.plan), base);
     return base;
 }
 
@@ -142,7 +142,7 @@ void finish(pa_server *s, Request &r, pa_status st, double device_ms) {
 // Resident seed transforms of sd for r's shape; built synchronously on `st`
 // the first time (worker thread only).
 uint32_t *seed_transforms(Seeds &sd, Request &r, hipStream_t st) {
-    const uint32_t key = r.plan.B << 8 | r.plan.m;
+    const uint32_t key = r.plan.B << 8 | pa::len_key(r.plan);
     auto it = sd.trans.find(key);
     if (it != sd.trans.end()) return it->second;
     const size_t words = (size_t)(sd.kmax + 1) * pa::NPRIMES * r.plan.N;

@@ -43,25 +43,32 @@ def test_plan_rule_matches_oracle():
             assert st == st_o
             continue
         if st == binding.PA_ERR_LIMIT:
-            assert k_o > 4096 or (2 * math.ceil(g_o / 32) - 1) > (1 << 24)
+            assert k_o > 4096 or (2 * math.ceil(g_o / 32) - 1) > 3 << 23
             continue
         assert st == 0, (n, r, st)
         assert (info["gamma"], info["k"]) == (g_o, k_o)
 
 
-@pytest.mark.parametrize("n,r,gamma,k,B,L,N", [
-    (1 << 20, (1 << 20) // 10, 110503, 10, 32, 3454, 1 << 13),
-    (260_000_000, 26_000_000, 30402457, 9, 32, 950077, 1 << 21),
-    (10 * 25964951, 25237932, 25964951, 10, 32, 811405, 1 << 21),
-    (1 << 32, 1 << 27, 136279841, 32, 29, 4699305, 1 << 24),
+@pytest.mark.parametrize("n,r,flags,gamma,k,B,L,N", [
+    (1 << 20, (1 << 20) // 10, 0, 110503, 10, 32, 3454, 1 << 13),
+    (260_000_000, 26_000_000, 0, 30402457, 9, 32, 950077, 1 << 21),
+    (10 * 25964951, 25237932, 0, 25964951, 10, 32, 811405, 1 << 21),
+    # the paper's largest CV block (8e8 bits, r = n/10): 3 * 2^21 instead of 2^23
+    (800_000_000, 80_000_000, 0, 82589933, 10, 32, 2580936, 3 << 21),
+    (800_000_000, 80_000_000, 1, 82589933, 10, 32, 2580936, 1 << 23),
+    # the largest block: 3 * 2^22 at B = 31 instead of 2^24 at B = 29
+    (1 << 32, 1 << 27, 0, 136279841, 32, 31, 4396124, 3 << 22),
+    (1 << 32, 1 << 27, 1, 136279841, 32, 29, 4699305, 1 << 24),
 ])
-def test_derived_shapes(n, r, gamma, k, B, L, N):
-    st, info = binding.plan_query(n, r)
+def test_derived_shapes(n, r, flags, gamma, k, B, L, N):
+    st, info = binding.plan_query(n, r, flags=flags)
     assert st == 0
     assert (info["gamma"], info["k"], info["B"], info["L"], info["N"]) == (gamma, k, B, L, N)
+    f = info["len_factor"]
     assert info["nprimes"] == 3 and info["log2N1"] + info["log2N2"] == info["log2N"]
-    # the primes: the three largest below 2^30 with 2^max(log2N, 20) | p - 1
-    assert sorted(info["primes"]) == sorted(largest_ntt_primes(max(info["log2N"], 20)))
+    assert N == f << info["log2N"] and f in (1, 3) and (flags == 0 or f == 1)
+    # the primes: the three largest below 2^30 with f * 2^max(log2N, 20 or 18) | p - 1
+    assert sorted(info["primes"]) == sorted(largest_ntt_primes(max(info["log2N"], 20 if f == 1 else 18), f=f))
     # exactness: k L (2^B - 1)^2 below the product of the three NTT primes
     P3 = math.prod(info["primes"])
     assert k * L * (2 ** B - 1) ** 2 < P3
@@ -94,11 +101,12 @@ def is_prime(n: int) -> bool:
     return True
 
 
-def largest_ntt_primes(m: int, count: int = 3) -> list[int]:
-    """The `count` largest primes p < 2^30 with 2^m | p - 1, by search."""
-    out, c = [], ((1 << 30) - 2) >> m
+def largest_ntt_primes(m: int, count: int = 3, f: int = 1) -> list[int]:
+    """The `count` largest primes p < 2^30 with f * 2^m | p - 1, by search."""
+    step = f << m
+    out, c = [], ((1 << 30) - 2) // step
     while len(out) < count and c > 0:
-        p = (c << m) + 1
+        p = c * step + 1
         if is_prime(p):
             out.append(p)
         c -= 1
@@ -108,27 +116,37 @@ def largest_ntt_primes(m: int, count: int = 3) -> list[int]:
 def test_prime_triples_are_the_largest_with_the_roots():
     """Every plan's primes are below 2^30 (so 4p < 2^32), prime, have the
     transform's roots of unity, and are the largest such (one triple serves
-    every length up to 2^20)."""
+    every length up to 2^20, and every length 3 * 2^m up to 3 * 2^18)."""
     seen = set()
     rng = random.Random(5)
-    for _ in range(400):
+    for _ in range(600):
         r = int(2 ** rng.uniform(0, 27.0))
         n = r + 1 + int(2 ** rng.uniform(0, 31))
         st, info = binding.plan_query(n, r)
         if st != 0:
             continue
-        m = info["log2N"]
+        m, f = info["log2N"], info["len_factor"]
         for p in info["primes"]:
-            assert p < (1 << 30) and (p - 1) % (1 << m) == 0 and is_prime(p)
-        if m not in seen:
-            assert sorted(info["primes"]) == sorted(largest_ntt_primes(max(m, 20)))
-            seen.add(m)
-    assert len(seen) >= 8
+            assert p < (1 << 30) and (p - 1) % (f << m) == 0 and is_prime(p)
+        if (m, f) not in seen:
+            assert sorted(info["primes"]) == sorted(largest_ntt_primes(max(m, 20 if f == 1 else 18), f=f))
+            seen.add((m, f))
+    assert len({m for m, f in seen if f == 1}) >= 8 and len({m for m, f in seen if f == 3}) >= 6
 
 
-def test_auto_limb_width_is_widest_exact():
+def length_cost(info) -> float:
+    """The plan rule's cost of a transform length: N log2 N butterflies, plus
+    one pass over N for the radix-3 step of the lengths 3 * 2^m."""
+    N = info["N"]
+    return N * (math.log2(N) + (1.0 if info["len_factor"] == 3 else 0.0))
+
+
+def test_auto_limb_width_is_cheapest_exact():
+    """B = 0 picks, over all limb widths, the cheapest exact transform
+    length (each width with the shortest exact length of either form), the
+    widest width among equal costs."""
     rng = random.Random(4)
-    for _ in range(300):
+    for _ in range(120):
         r = int(2 ** rng.uniform(0, 27.5))
         n = r + 1 + int(2 ** rng.uniform(0, 32.5))
         st, info = binding.plan_query(n, r)
@@ -136,9 +154,40 @@ def test_auto_limb_width_is_widest_exact():
             continue
         g, k, B = info["gamma"], info["k"], info["B"]
         assert k * -(-g // B) * (2 ** B - 1) ** 2 < math.prod(info["primes"])
+        assert 2 * info["L"] - 1 <= info["N"]
+        c = length_cost(info)
+        for b in range(8, 33):
+            if b == B:
+                continue
+            st_b, info_b = binding.plan_query(n, r, B=b)
+            if st_b != 0:
+                assert st_b in (binding.PA_ERR_INEXACT, binding.PA_ERR_LIMIT)
+                continue
+            assert length_cost(info_b) >= c if b < B else length_cost(info_b) > c, (n, r, b, B)
+
+
+def test_power_of_two_flag():
+    """PA_FLAG_POW2_LENGTHS restricts the plan to lengths 2^m; the old rule
+    (widest exact B) then holds; other flag bits are rejected."""
+    rng = random.Random(6)
+    mixed = 0
+    for _ in range(200):
+        r = int(2 ** rng.uniform(0, 27.5))
+        n = r + 1 + int(2 ** rng.uniform(0, 32.5))
+        st, info = binding.plan_query(n, r, flags=binding.PA_FLAG_POW2_LENGTHS)
+        st0, info0 = binding.plan_query(n, r)
+        assert (st == 0) == (st0 == 0)
+        if st != 0:
+            continue
+        mixed += info0["len_factor"] == 3
+        assert info["len_factor"] == 1 and info["N"] == 1 << info["log2N"]
+        assert length_cost(info0) <= length_cost(info)
+        B = info["B"]
         if B < 32:
-            # one bit wider is inexact with the primes of its own length, or too long
-            assert binding.plan_query(n, r, B=B + 1)[0] in (binding.PA_ERR_INEXACT, binding.PA_ERR_LIMIT)
+            assert binding.plan_query(n, r, B=B + 1, flags=binding.PA_FLAG_POW2_LENGTHS)[0] in (
+                binding.PA_ERR_INEXACT, binding.PA_ERR_LIMIT)
+    assert mixed > 20
+    assert binding.plan_query(1000, 10, flags=2)[0] == binding.PA_ERR_ARG
 
 
 def test_plan_errors():

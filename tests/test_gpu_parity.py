@@ -50,9 +50,9 @@ def run_gpu(pa, plan, blk, stages=False):
     return st, pa.from_device(out)
 
 
-def check_block(pa, blk, B=0, stages=True, label=""):
-    say(f"[case] {label} n={blk.n} r={blk.r} gamma={blk.gamma} k={blk.k} B={B}")
-    plan = pa.Plan(blk.n, blk.r, gamma=blk.gamma, B=B)
+def check_block(pa, blk, B=0, stages=True, label="", flags=0):
+    say(f"[case] {label} n={blk.n} r={blk.r} gamma={blk.gamma} k={blk.k} B={B} flags={flags}")
+    plan = pa.Plan(blk.n, blk.r, gamma=blk.gamma, B=B, flags=flags)
     try:
         st_g, out_g, y_g, U_g = run_gpu(pa, plan, blk, stages=True)
     finally:
@@ -145,6 +145,52 @@ def test_two_to_the_21_transform_two_chunks(pa):
     assert st == 0 and k == 2
     blk = synth.single_block(21, n, r, g, k)
     check_block(pa, blk, label="N=2^21 k=2")
+
+
+# (gamma, k) whose transform length is 3 * 2^m, m = 6 .. 16: column passes of
+# 2^3 .. 2^7 rows (the 8-row one single-step), rows of 2^3 .. 2^12 words.
+RADIX3_SHAPES = [(2203, 2), (4253, 3), (9689, 1), (19937, 2), (44497, 3), (86243, 2), (132049, 3),
+                 (756839, 2), (1257787, 3), (2976221, 2)]
+
+
+@pytest.mark.parametrize("gamma,k", RADIX3_SHAPES)
+def test_radix3_lengths_against_oracle(pa, gamma, k):
+    """Lengths N = 3 * 2^m (radix-3 step fused into the unpacking column
+    pass and into the Chinese-remainder step), ragged n, against the oracle;
+    then the same block on power-of-two lengths."""
+    n, r = k * gamma - 7, gamma // 3
+    st, g, kk = defn.plan_shape(n, r, gamma)
+    assert st == 0 and kk == k
+    info = pa.plan_query(n, r, gamma)[1]
+    assert info["len_factor"] == 3, info
+    blk = synth.single_block(3 * gamma + k, n, r, g, kk)
+    _, out3 = check_block(pa, blk, label=f"radix-3 N={info['N']} gamma={gamma} k={k}")
+    _, out2 = check_block(pa, blk, label=f"power-of-two gamma={gamma} k={k}", flags=pa.PA_FLAG_POW2_LENGTHS)
+    assert np.array_equal(out3, out2)
+
+
+@pytest.mark.parametrize("n,r", [(3 * 20996011 - 99, 14_000_000), (800_000_000, 80_000_000)])
+def test_radix3_against_power_of_two_lengths(pa, n, r):
+    """Larger radix-3 shapes (3 * 2^19 with 128-row columns and 4096-word
+    register rows; the paper's 8e8-bit CV block at 3 * 2^21 with 512-row
+    columns) against the same block on power-of-two lengths (2^21, 2^23),
+    output and both stage values."""
+    st, g, k = defn.plan_shape(n, r)
+    assert st == 0
+    i3, i2 = pa.plan_query(n, r)[1], pa.plan_query(n, r, flags=pa.PA_FLAG_POW2_LENGTHS)[1]
+    assert i3["len_factor"] == 3 and i2["len_factor"] == 1 and i3["N"] < i2["N"]
+    blk = synth.single_block(5, n, r, g, k)
+    res = []
+    for flags in (0, pa.PA_FLAG_POW2_LENGTHS):
+        say(f"[case] radix-3 vs power-of-two n={n} r={r} gamma={g} k={k} flags={flags}")
+        plan = pa.Plan(n, r, flags=flags)
+        try:
+            res.append(run_gpu(pa, plan, blk, stages=True))
+        finally:
+            plan.close()
+    assert res[0][0] == res[1][0] == 0
+    for a3, a2 in zip(res[0][1:], res[1][1:]):
+        assert np.array_equal(a3, a2)
 
 
 def test_config_one_mib_block(pa):
@@ -280,18 +326,23 @@ def _digest(words):
     return hashlib.sha256(np.ascontiguousarray(words, dtype=np.uint64).tobytes()).hexdigest()
 
 
+@pytest.mark.parametrize("flags", [0, 1])
 @pytest.mark.parametrize("name", ["single_block_2p6e8", "paper_cv_block", "max_length_single_chunk",
                                   "len_2p22_single_chunk", "len_2p23_single_chunk"])
-def test_full_size_blocks_against_stored_oracle_digest(pa, name):
+def test_full_size_blocks_against_stored_oracle_digest(pa, name, flags):
     """Full-size blocks, in the launch configuration the benchmark times,
-    against digests written by tests/golden/make_golden.py (oracle only)."""
+    against digests written by tests/golden/make_golden.py (oracle only);
+    with flags = 1 (PA_FLAG_POW2_LENGTHS) also on power-of-two lengths where
+    the plan rule picks a length 3 * 2^m."""
     gold = json.load(open(os.path.join(HERE, "golden", "full_size.json")))[name]
     n, r = gold["n"], gold["r"]
     st, g, k = defn.plan_shape(n, r)
     assert (g, k) == (gold["gamma"], gold["k"])
+    if flags and pa.plan_query(n, r)[1]["len_factor"] == 1:
+        pytest.skip("the plan rule already picks a power-of-two length")
     blk = synth.single_block(gold["seed"], n, r, g, k)
-    say(f"[case] full size {name} n={n} r={r} gamma={g} k={k}")
-    plan = pa.Plan(n, r)
+    say(f"[case] full size {name} n={n} r={r} gamma={g} k={k} flags={flags}")
+    plan = pa.Plan(n, r, flags=flags)
     try:
         st_g, out, y, U = run_gpu(pa, plan, blk, stages=True)
     finally:
@@ -314,8 +365,9 @@ def _chunk_int(key_bytes: bytes, lo_bit: int, nbits: int, n: int) -> int:
 
 
 def test_largest_block_power_of_two_seeds(pa):
-    """The largest block, n = 2^32 with r = 2^27 (gamma = 136,279,841, k = 32,
-    B = 29, 2^24-point transforms), against a closed form instead of the
+    """The largest block, n = 2^32 with r = 2^27 (gamma = 136,279,841, k = 32;
+    B = 31 with 3 * 2^22-point transforms, and B = 29 with 2^24-point ones
+    under PA_FLAG_POW2_LENGTHS), against a closed form instead of the
     oracle: with seeds a_i = 2^(s_i) the MMH sum is y = sum_i rotl(x_i, s_i)
     mod p (2^gamma = 1 mod p turns a power-of-two product into a rotation), and
     with b = 2^gamma - 1 (= -1 mod 2^gamma) the MH value is U = c - y mod
@@ -324,7 +376,8 @@ def test_largest_block_power_of_two_seeds(pa):
     st, g, k = defn.plan_shape(n, r)
     assert (st, g, k) == (0, 136279841, 32)
     info = pa.plan_query(n, r)[1]
-    assert info["log2N"] == 24
+    info2 = pa.plan_query(n, r, flags=pa.PA_FLAG_POW2_LENGTHS)[1]
+    assert (info["N"], info["B"], info2["N"], info2["B"]) == (3 << 22, 31, 1 << 24, 29)
     rng = synth.SplitMix64(77)
     key = rng.words((n + 63) // 64)
     W = (g + 63) // 64
@@ -337,13 +390,18 @@ def test_largest_block_power_of_two_seeds(pa):
     c = rng.words(W)
     if g % 64:
         c[-1] &= np.uint64((1 << (g % 64)) - 1)
-    say(f"[case] largest block n=2^32 r=2^27 gamma={g} k={k} N=2^24 B={info['B']}")
-    plan = pa.Plan(n, r)
-    try:
-        st_g, out, y, U = run_gpu(pa, plan, synth.Block(n, r, g, k, key, a, b, c), stages=True)
-    finally:
-        plan.close()
-    assert st_g == 0
+    runs = []
+    for flags, inf in ((0, info), (pa.PA_FLAG_POW2_LENGTHS, info2)):
+        say(f"[case] largest block n=2^32 r=2^27 gamma={g} k={k} N={inf['N']} B={inf['B']}")
+        plan = pa.Plan(n, r, flags=flags)
+        try:
+            runs.append(run_gpu(pa, plan, synth.Block(n, r, g, k, key, a, b, c), stages=True))
+        finally:
+            plan.close()
+    assert runs[0][0] == runs[1][0] == 0
+    for a3, a2 in zip(runs[0][1:], runs[1][1:]):
+        assert np.array_equal(a3, a2)
+    st_g, out, y, U = runs[0]
     p = (1 << g) - 1
     kb = key.tobytes()
     ysum = 0
