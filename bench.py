@@ -301,14 +301,16 @@ def bench_lengths(args):
     stream = torch.cuda.current_stream(dev)
     K, Wm = args.steps, max(1, args.warmup)
     rows = []
-    for n, r, seed in LENGTH_BLOCKS:
+    blocks = LENGTH_BLOCKS if args.block is None else [LENGTH_BLOCKS[args.block]]
+    modes = [m for m in (("radix3", 0), ("pow2", pa.PA_FLAG_POW2_LENGTHS)) if args.mode in (None, m[0])]
+    for n, r, seed in blocks:
         st, info = pa.plan_query(n, r)
         assert st == 0, st
         blk = synth.single_block(seed, n, r, info["gamma"], info["k"])
         key, a, b, c = (pa.to_device(x, dev) for x in (blk.key, blk.a, blk.b, blk.c))
         del blk
         res = {}
-        for label, flags in (("radix3", 0), ("pow2", pa.PA_FLAG_POW2_LENGTHS)):
+        for label, flags in modes:
             plan = pa.Plan(n, r, device=0, flags=flags)
             out = plan.new_out()
             d_status = torch.zeros(K + Wm, dtype=torch.int32, device=dev)
@@ -327,10 +329,14 @@ def bench_lengths(args):
                           "N": plan.N, "out": out.clone()}
             log(f"[bench] lengths n={n} r={r} {label}: N={plan.N} B={plan.B} {ms:.3f} ms")
             plan.close()
-        same = torch.equal(res["radix3"].pop("out"), res["pow2"].pop("out"))
-        rows.append({"n": n, "r": r, "gamma": info["gamma"], "k": info["k"], "radix3": res["radix3"],
-                     "pow2": res["pow2"], "speedup": round(res["pow2"]["ms_per_block"] / res["radix3"]["ms_per_block"], 3),
-                     "outputs_equal": same})
+        row = {"n": n, "r": r, "gamma": info["gamma"], "k": info["k"]}
+        if len(res) == 2:
+            row["outputs_equal"] = torch.equal(res["radix3"]["out"], res["pow2"]["out"])
+            row["speedup"] = round(res["pow2"]["ms_per_block"] / res["radix3"]["ms_per_block"], 3)
+        for label in res:
+            res[label].pop("out")
+            row[label] = res[label]
+        rows.append(row)
         del key, a, b, c
         torch.cuda.empty_cache()
     rec = {"metric": "PA input throughput (Mbit/s) with transform lengths 3 * 2^m vs 2^m, bit-exact",
@@ -458,6 +464,9 @@ def main():
                          "arrivals from 16 sessions through the serving loop (latency percentiles); lengths: "
                          "the 8e8- and 2^32-bit blocks with transform lengths 3 * 2^m against 2^m")
     ap.add_argument("--requests", type=int, default=600, help="serving: number of Poisson arrivals")
+    ap.add_argument("--block", type=int, choices=range(len(LENGTH_BLOCKS)), default=None,
+                    help="lengths: run only this block (0: 8e8 bits, 1: 2^32 bits)")
+    ap.add_argument("--mode", choices=["radix3", "pow2"], default=None, help="lengths: run only this length form")
     ap.add_argument("--core-only", action="store_true",
                     help="single: time only the K main steps (no per-step statistics, key-upload or pipelined "
                          "passes), so that a profiler sees exactly those launches")

@@ -47,6 +47,15 @@ __device__ __forceinline__ uint32_t bitrev(uint32_t x, uint32_t bits) {
     return bits ? (__brev(x) >> (32 - bits)) : 0u;
 }
 
+// The value of v, made opaque to the optimiser: addresses derived from it
+// inside a loop are then recomputed there (one XOR or multiply each) instead
+// of being hoisted out of the loop as dozens of live registers.  Emits no
+// instruction.
+__device__ __forceinline__ uint32_t opaque(uint32_t v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 // Workgroup b of a G-workgroup grid is dispatched to XCD b % 8; hand each XCD
 // a contiguous range of tiles so neighbouring tiles share that XCD's L2.
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t G) {
@@ -398,10 +407,13 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
 
 // ---- 512-row column tiles (N1 = 2^9), 16 columns: compile-time shape -------
 // A workgroup unpacks its tile's limbs once and transforms them for each of
-// the three primes in turn.
+// the three primes in turn (and, for N = 3 Nsub, for each of the three
+// transforms of the radix-3 split: nine transforms per unpack).
 // Three radix-8 steps; task index tau = t + 256 u (u < 4) in every step:
 //   step A (sub-length 512, stride 64): q = tau & 15, n1 = tau >> 4, rows
-//          n1 + 64 j; unpacked from global memory (rows >= 256 are padding);
+//          n1 + 64 j; from the unpacked limbs (power-of-two N: rows >= 256
+//          are padding; N = 3 Nsub: all rows carry x_n, rows < 256 also
+//          x_(n+Nsub), combined with the row part of the radix-3 twiddle);
 //   step B (sub-length 64, stride 8): q = tau & 15, n1 = (tau >> 4) & 7,
 //          block b = tau >> 7, rows 64 b + n1 + 8 j;
 //   step C (sub-length 8): q = tau & 15, block b = tau >> 4, rows 8 b + j,
@@ -413,8 +425,10 @@ constexpr uint32_t C9_LG = 9, C9_CLG = 4;
 
 __device__ __forceinline__ constexpr uint32_t swz_c9(uint32_t i) { return i ^ (((i >> 7) & 3u) << 4); }
 
-template <int Stage>
+template <int Stage, bool MIX>
 __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
+    constexpr uint32_t NSUB = MIX ? 3u : 1u;
+    constexpr int X0_ROWS = MIX ? 8 : 4;  // step-A rows of a task holding x_n (x_(n+Nsub): rows < 4)
     uint32_t *lds = lds_dyn;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t arr = blockIdx.y + A.arr0;
@@ -422,9 +436,9 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
     const bool is_key = (A.mode == 0) && arr < A.k;
     const uint32_t full = (uint32_t)((1ull << A.B) - 1), topv = (uint32_t)((1ull << A.s_top) - 1);
     const uint32_t t = threadIdx.x;
-    // the tile's 16 limbs per thread (the nonzero half: rows n1 + 64 jj, jj < 4,
-    // of the four step-A tasks), unpacked once and transformed for each prime
-    uint32_t x[4][4];
+    const uint32_t Ns = (uint32_t)A.Nsub;
+    // the tile's limbs of the four step-A tasks, unpacked once
+    uint32_t x[4][X0_ROWS], x1[4][MIX ? 4 : 1];
     {
         const LimbSrc S = limb_src(A, arr);
         const uint32_t L = (uint32_t)A.L;
@@ -434,11 +448,17 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
             const uint32_t tau = t + 256u * u;
             const uint32_t q = tau & 15u, n1 = tau >> 4;
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
+            for (int jj = 0; jj < X0_ROWS; ++jj) {
                 const uint32_t j = ((n1 + 64u * jj) << A.m2) + (uint32_t)c0 + q;  // limb index
                 x[u][jj] = limb_at(S, j);
                 if (is_key && j < L) not_ones |= (x[u][jj] != (j == L - 1 ? topv : full));
+                if constexpr (MIX) {
+                    if (jj >= 4) continue;
+                    x1[u][jj] = limb_at(S, j + Ns);
+                    if (is_key && j + Ns < L) not_ones |= (x1[u][jj] != (j + Ns == L - 1 ? topv : full));
+                }
             }
+            if constexpr (MIX) __builtin_amdgcn_sched_barrier(0);  // 24 limb loads in flight at most
         }
         if (is_key) {
             int any = __syncthreads_or(not_ones);
@@ -446,21 +466,42 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
         }
     }
 #pragma unroll 1
-    for (uint32_t pq = 0; pq < NPRIMES; ++pq) {
+    for (uint32_t it = 0; it < NSUB * NPRIMES; ++it) {
+        const uint32_t k0 = it / NPRIMES, pq = it - NPRIMES * k0;
         const PrimeConst M = A.P.c[pq];
         const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.tw + ((uint64_t)pq << C9_LG), 1u << C9_LG);
-        uint32_t *out = A.X + ((uint64_t)blockIdx.y * NPRIMES + pq) * A.N;
-        if (pq) __syncthreads();  // the previous prime's last step has read the buffer
+        uint32_t *out = A.X + ((uint64_t)blockIdx.y * NPRIMES + pq) * A.N + (uint64_t)k0 * Ns;
+        // radix-3 row twiddles of transform k0 (tables g0, g1 of k_tw_g3)
+        __amdgpu_buffer_rsrc_t rg0 = rtw, rg1 = rtw;
+        if constexpr (MIX) {
+            const uint32_t *g0 = A.g3 + (((size_t)pq * 3 + k0) << C9_LG);
+            rg0 = rsrc_of(g0, 1u << C9_LG);
+            rg1 = rsrc_of(g0 + ((size_t)NPRIMES * 3 << C9_LG), 1u << C9_LG);
+        }
+        if (it) __syncthreads();  // the previous transform's last step has read the buffer
+        const uint32_t tl = MIX ? opaque(t) : t;  // radix-3 split: recompute the task addresses per transform
 #pragma unroll
         for (uint32_t u = 0; u < 4; ++u) {  // step A
-            const uint32_t tau = t + 256u * u;
+            const uint32_t tau = tl + 256u * u;
             const uint32_t n1 = tau >> 4;
             uint32_t v[8], w[8];
+            if constexpr (MIX) {
+                uint32_t ga[8], gb[4];
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj) v[jj] = mont(x[u][jj], M.one, M);  // x mod p, in [0, 2p)
+                for (int jj = 0; jj < 8; ++jj) ga[jj] = bload(rg0, (n1 + 64u * jj) << 2, 0);
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) gb[jj] = bload(rg1, (n1 + 64u * jj) << 2, 0);
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj)
+                    v[jj] = jj < 4 ? red2(mont(x[u][jj], ga[jj], M) + mont(x1[u][jj & 3], gb[jj & 3], M), M)
+                                   : mont(x[u][jj], ga[jj], M);  // in [0, 2p)
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) v[jj] = mont(x[u][jj], M.one, M);  // x mod p, in [0, 2p)
+            }
 #pragma unroll
             for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 2, 0);
-            dft_fwd_x<8, true, true>(v, w, M);
+            dft_fwd_x<8, !MIX, true>(v, w, M);
             const uint32_t sb = swz_c9(tau);
 #pragma unroll
             for (int jj = 0; jj < 8; ++jj) lds[sb ^ (1024u * jj)] = v[jj];
@@ -632,14 +673,6 @@ __global__ __launch_bounds__(ROW_MAX_THREADS) void k_row(RowArgs A) {
 constexpr int R16_THREADS = 256;
 constexpr uint32_t R16_LEN = 4096;
 
-// The value of v, made opaque to the optimiser: addresses derived from it
-// inside a loop are then recomputed there (one XOR or multiply each) instead
-// of being hoisted out of the loop as dozens of live registers.  Emits no
-// instruction.
-__device__ __forceinline__ uint32_t opaque(uint32_t v) {
-    asm volatile("" : "+v"(v));
-    return v;
-}
 
 __device__ __forceinline__ constexpr uint32_t swz_r16(uint32_t i) {
     return i ^ (((i >> 4) & 1u) * 11u) ^ (((i >> 5) & 1u) * 5u) ^ (((i >> 6) & 1u) * 28u) ^
@@ -1403,11 +1436,16 @@ template <int Stage>
 static void launch_col_fwd(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, hipStream_t st) {
     const unsigned ncol_tiles = 1u << (p->m2 - p->c_lg);
     const size_t col_lds = ((size_t)4 << p->m1) << p->c_lg;
-    if (p->mix)  // one workgroup per (tile, array, radix-3 branch, prime)
+    const bool c9 = p->m1 == C9_LG && p->c_lg == C9_CLG;
+    if (c9 && p->mix)  // all three primes and radix-3 transforms per workgroup
+        hipLaunchKernelGGL((k_col9_fwd<Stage, true>), dim3(ncol_tiles, narrays, 1), dim3(COL_THREADS), col_lds, st,
+                           cf);
+    else if (c9)  // all three primes per workgroup
+        hipLaunchKernelGGL((k_col9_fwd<Stage, false>), dim3(ncol_tiles, narrays, 1), dim3(COL_THREADS), col_lds, st,
+                           cf);
+    else if (p->mix)  // one workgroup per (tile, array, radix-3 transform, prime)
         hipLaunchKernelGGL((k_col_fwd<Stage, true>), dim3(ncol_tiles, 3 * narrays, NPRIMES), dim3(COL_THREADS),
                            col_lds, st, cf);
-    else if (p->m1 == C9_LG && p->c_lg == C9_CLG)  // all three primes per workgroup
-        hipLaunchKernelGGL(k_col9_fwd<Stage>, dim3(ncol_tiles, narrays, 1), dim3(COL_THREADS), col_lds, st, cf);
     else
         hipLaunchKernelGGL((k_col_fwd<Stage, false>), dim3(ncol_tiles, narrays, NPRIMES), dim3(COL_THREADS),
                            col_lds, st, cf);
