@@ -308,101 +308,118 @@ __device__ __forceinline__ void col_last_fwd(const uint32_t *buf, uint32_t lg, u
 
 // Unpack + forward column pass.  blockIdx.y selects the array: in MMH mode
 // arrays 0..k-1 are the key chunks x_i and k..2k-1 the seed chunks a_i; in
-// MH mode array 0 is y and array 1 is b.  blockIdx.z is the prime.  Limb j of
-// a chunk is its bits [jB, jB+B); limbs j >= L are the zero padding.
+// MH mode array 0 is y and array 1 is b.  Limb j of a chunk is its bits
+// [jB, jB+B); limbs j >= L are the zero padding.  A workgroup unpacks the
+// limbs of its tile once (TPT first-step tasks per thread, held in
+// registers) and then transforms them for each prime in turn.
 // N = 2^m (MIX false): since N >= 2L - 1, every limb index >= N/2 is padding,
 // so rows n1 >= N1/2 of the column tile are zero and the first radix-8 step
 // unpacks only four inputs.
-// N = 3 Nsub (MIX true; blockIdx.y = 3 * array + k0): the workgroup computes
-// transform k0 of the radix-3 split, whose input at n < Nsub is
-// (x_n + omega_3^k0 x_(n+Nsub)) omega_N^(k0 n); x_(n+2Nsub) is padding since
-// L <= Nsub * 3/2.  Only the row part omega_N^(k0 r N2) of the twiddle (n =
-// r N2 + c) is applied here; the column part omega_N^(k0 c) rides on the
-// four-step twiddle of the row pass.
+// N = 3 Nsub (MIX true): for each of the three transforms k0 of the radix-3
+// split as well, whose input at n < Nsub is (x_n + omega_3^k0 x_(n+Nsub))
+// omega_N^(k0 n); x_(n+2Nsub) is padding since L <= Nsub * 3/2, and
+// x_(n+Nsub) only reaches rows < N1/2.  Only the row part omega_N^(k0 r N2)
+// of the twiddle (n = r N2 + c) is applied here; the column part
+// omega_N^(k0 c) rides on the four-step twiddle of the row pass.
 // The last step writes its rows straight to global memory.
-template <int Stage, bool MIX>
+template <int Stage, bool MIX, int TPT>
 __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
+    constexpr uint32_t NSUB = MIX ? 3u : 1u;
+    constexpr int XR = MIX ? 8 : 4;  // first-step rows of a task that hold x_n
     uint32_t *lds = lds_dyn;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t arr_local = MIX ? blockIdx.y / 3u : blockIdx.y;
-    const uint32_t k0 = MIX ? blockIdx.y - 3u * arr_local : 0u;
-    const uint32_t arr = arr_local + A.arr0, pq = blockIdx.z;
-    const PrimeConst M = A.P.c[pq];
-    const uint32_t *tw = A.tw + ((uint64_t)pq << A.m1);
+    const uint32_t arr = blockIdx.y + A.arr0;
     const uint32_t c_lg = A.c_lg, lg = A.m1;
     const uint32_t cmask = (1u << c_lg) - 1;
     const uint64_t c0 = (uint64_t)tile << c_lg;
-    // the reload check runs once per chunk
-    const bool is_key = (A.mode == 0) && arr < A.k && pq == 0 && k0 == 0;
+    const bool is_key = (A.mode == 0) && arr < A.k;
     const uint32_t full = (uint32_t)((1ull << A.B) - 1), topv = (uint32_t)((1ull << A.s_top) - 1);
     const uint32_t lgMp = lg - 3;
-    const uint32_t ntask = (1u << lgMp) << c_lg;
-    uint32_t *out = A.X + ((uint64_t)arr_local * NPRIMES + pq) * A.N + (uint64_t)k0 * A.Nsub;
-    const LimbSrc S = limb_src(A, arr);
-    const uint32_t L = (uint32_t)A.L;
+    const uint32_t ntask = (1u << lgMp) << c_lg;  // at most TPT * COL_THREADS
     const uint32_t Ns = (uint32_t)A.Nsub;
-    const uint32_t *g0 = nullptr, *g1 = nullptr;
-    if (MIX) {
-        const size_t tab = (size_t)NPRIMES * 3 << lg;
-        g0 = A.g3 + (((size_t)pq * 3 + k0) << lg);
-        g1 = g0 + tab;
-    }
-    bool not_ones = false;
-    for (uint32_t task = threadIdx.x; task < ntask; task += blockDim.x) {
-        const uint32_t q = task & cmask;
-        const uint32_t n1 = task >> c_lg;
-        uint32_t v[8];
-        if (MIX) {
+    const uint32_t t = threadIdx.x;
+    uint32_t x[TPT][XR], x1[TPT][MIX ? 4 : 1];
+    {
+        const LimbSrc S = limb_src(A, arr);
+        const uint32_t L = (uint32_t)A.L;
+        bool not_ones = false;
 #pragma unroll
-            for (int jj = 0; jj < 8; ++jj) {
-                const uint32_t row = n1 + ((uint32_t)jj << lgMp);
-                const uint32_t j = (row << A.m2) + (uint32_t)c0 + q;  // index in the transform
-                const uint32_t x0 = limb_at(S, j), x1 = limb_at(S, j + Ns);
-                if (is_key) {
-                    if (j < L) not_ones |= (x0 != (j == L - 1 ? topv : full));
-                    if (j + Ns < L) not_ones |= (x1 != (j + Ns == L - 1 ? topv : full));
+        for (int u = 0; u < TPT; ++u) {
+            const uint32_t task = t + COL_THREADS * u;
+            const uint32_t q = task & cmask, n1 = task >> c_lg;
+#pragma unroll
+            for (int jj = 0; jj < XR; ++jj) {
+                const uint32_t j = ((n1 + ((uint32_t)jj << lgMp)) << A.m2) + (uint32_t)c0 + q;  // limb index
+                x[u][jj] = task < ntask ? limb_at(S, j) : 0u;
+                if (is_key && task < ntask && j < L) not_ones |= (x[u][jj] != (j == L - 1 ? topv : full));
+                if constexpr (MIX) {
+                    if (jj >= 4) continue;
+                    x1[u][jj] = task < ntask ? limb_at(S, j + Ns) : 0u;
+                    if (is_key && task < ntask && j + Ns < L)
+                        not_ones |= (x1[u][jj] != (j + Ns == L - 1 ? topv : full));
                 }
-                v[jj] = red2(mont(x0, g0[row], M) + mont(x1, g1[row], M), M);  // in [0, 2p)
-            }
-        } else {
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                const uint32_t row = n1 + ((uint32_t)jj << lgMp);
-                const uint32_t j = (row << A.m2) + (uint32_t)c0 + q;  // limb index
-                const uint32_t x = limb_at(S, j);
-                if (is_key && j < L) not_ones |= (x != (j == L - 1 ? topv : full));
-                v[jj] = mont(x, M.one, M);  // x mod p, in [0, 2p)
             }
         }
-        if (lg > 3) {
-            uint32_t w[8];
-#pragma unroll
-            for (int s = 1; s < 8; ++s) w[s] = tw[n1 * brev_small(s, 3)];
-            dft_fwd_x<8, !MIX, true>(v, w, M);
-#pragma unroll
-            for (int jj = 0; jj < 8; ++jj)
-                lds[tile_swz(((n1 + ((uint32_t)jj << lgMp)) << c_lg) + q, c_lg)] = v[jj];
-        } else {
-            dft_fwd_x<8, !MIX, false>(v, nullptr, M);
-#pragma unroll
-            for (int jj = 0; jj < 8; ++jj) out[((uint64_t)jj << A.m2) + c0 + q] = v[jj];
+        if (is_key) {
+            int any = __syncthreads_or(not_ones);
+            if (any && t == 0) A.notones[arr] = 1u;
         }
     }
-    if (is_key) {
-        int any = __syncthreads_or(not_ones);
-        if (any && threadIdx.x == 0) A.notones[arr] = 1u;
-    } else {
+#pragma unroll 1
+    for (uint32_t it = 0; it < NSUB * NPRIMES; ++it) {
+        const uint32_t k0 = it / NPRIMES, pq = it - NPRIMES * k0;
+        const PrimeConst M = A.P.c[pq];
+        const uint32_t *tw = A.tw + ((uint64_t)pq << lg);
+        uint32_t *out = A.X + ((uint64_t)blockIdx.y * NPRIMES + pq) * A.N + (uint64_t)k0 * Ns;
+        const uint32_t *g0 = nullptr, *g1 = nullptr;  // radix-3 row twiddles of transform k0 (k_tw_g3)
+        if constexpr (MIX) {
+            g0 = A.g3 + (((size_t)pq * 3 + k0) << lg);
+            g1 = g0 + ((size_t)NPRIMES * 3 << lg);
+        }
+        if (it) __syncthreads();  // the previous transform's last step has read the buffer
+        const uint32_t tl = opaque(t);  // task addresses are recomputed per transform, not kept live
+#pragma unroll
+        for (int u = 0; u < TPT; ++u) {
+            const uint32_t task = tl + COL_THREADS * u;
+            if (task >= ntask) continue;
+            const uint32_t q = task & cmask, n1 = task >> c_lg;
+            uint32_t v[8];
+            if constexpr (MIX) {
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) {
+                    const uint32_t row = n1 + ((uint32_t)jj << lgMp);
+                    v[jj] = jj < 4 ? red2(mont(x[u][jj], g0[row], M) + mont(x1[u][jj & 3], g1[row], M), M)
+                                   : mont(x[u][jj], g0[row], M);  // in [0, 2p)
+                }
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) v[jj] = mont(x[u][jj], M.one, M);  // x mod p, in [0, 2p)
+            }
+            if (lg > 3) {
+                uint32_t w[8];
+#pragma unroll
+                for (int s = 1; s < 8; ++s) w[s] = tw[n1 * brev_small(s, 3)];
+                dft_fwd_x<8, !MIX, true>(v, w, M);
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj)
+                    lds[tile_swz(((n1 + ((uint32_t)jj << lgMp)) << c_lg) + q, c_lg)] = v[jj];
+            } else {
+                dft_fwd_x<8, !MIX, false>(v, nullptr, M);
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) out[((uint64_t)jj << A.m2) + c0 + q] = v[jj];
+            }
+        }
+        if (lg == 3) continue;  // single-step transform: written straight to global memory
         __syncthreads();
+        fwd_middle_steps(lds, lg, lg - 3, c_lg, tw, M, tl, COL_THREADS);
+        const uint32_t ll = last_lgM(lg);
+        if (ll == 3)
+            col_last_fwd<8>(lds, lg, c_lg, A.m2, c0, out, M, tl, COL_THREADS);
+        else if (ll == 2)
+            col_last_fwd<4>(lds, lg, c_lg, A.m2, c0, out, M, tl, COL_THREADS);
+        else
+            col_last_fwd<2>(lds, lg, c_lg, A.m2, c0, out, M, tl, COL_THREADS);
     }
-    if (lg == 3) return;
-    fwd_middle_steps(lds, lg, lg - 3, c_lg, tw, M, threadIdx.x, blockDim.x);
-    const uint32_t ll = last_lgM(lg);
-    if (ll == 3)
-        col_last_fwd<8>(lds, lg, c_lg, A.m2, c0, out, M, threadIdx.x, blockDim.x);
-    else if (ll == 2)
-        col_last_fwd<4>(lds, lg, c_lg, A.m2, c0, out, M, threadIdx.x, blockDim.x);
-    else
-        col_last_fwd<2>(lds, lg, c_lg, A.m2, c0, out, M, threadIdx.x, blockDim.x);
 }
 
 // ---- 512-row column tiles (N1 = 2^9), 16 columns: compile-time shape -------
@@ -1432,6 +1449,23 @@ static ColFwdArgs col_args(pa_plan *p, uint32_t mode) {
     return cf;
 }
 
+// Column pass of any shape: one workgroup per (tile, array), first-step tasks
+// per thread as the tile needs (2^(m1 - 3 + c_lg) tasks, m1 + c_lg <= 14).
+template <int Stage, bool MIX>
+static void launch_col_fwd_generic(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, hipStream_t st) {
+    const dim3 grid(1u << (p->m2 - p->c_lg), narrays, 1);
+    const size_t col_lds = ((size_t)4 << p->m1) << p->c_lg;
+    const uint32_t ntask = (1u << (p->m1 - 3)) << p->c_lg;
+    if (ntask <= COL_THREADS)
+        hipLaunchKernelGGL((k_col_fwd<Stage, MIX, 1>), grid, dim3(COL_THREADS), col_lds, st, cf);
+    else if (ntask <= 2 * COL_THREADS)
+        hipLaunchKernelGGL((k_col_fwd<Stage, MIX, 2>), grid, dim3(COL_THREADS), col_lds, st, cf);
+    else if (ntask <= 4 * COL_THREADS)
+        hipLaunchKernelGGL((k_col_fwd<Stage, MIX, 4>), grid, dim3(COL_THREADS), col_lds, st, cf);
+    else
+        hipLaunchKernelGGL((k_col_fwd<Stage, MIX, 8>), grid, dim3(COL_THREADS), col_lds, st, cf);
+}
+
 template <int Stage>
 static void launch_col_fwd(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, hipStream_t st) {
     const unsigned ncol_tiles = 1u << (p->m2 - p->c_lg);
@@ -1443,12 +1477,10 @@ static void launch_col_fwd(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, h
     else if (c9)  // all three primes per workgroup
         hipLaunchKernelGGL((k_col9_fwd<Stage, false>), dim3(ncol_tiles, narrays, 1), dim3(COL_THREADS), col_lds, st,
                            cf);
-    else if (p->mix)  // one workgroup per (tile, array, radix-3 transform, prime)
-        hipLaunchKernelGGL((k_col_fwd<Stage, true>), dim3(ncol_tiles, 3 * narrays, NPRIMES), dim3(COL_THREADS),
-                           col_lds, st, cf);
+    else if (p->mix)
+        launch_col_fwd_generic<Stage, true>(p, cf, narrays, st);
     else
-        hipLaunchKernelGGL((k_col_fwd<Stage, false>), dim3(ncol_tiles, narrays, NPRIMES), dim3(COL_THREADS),
-                           col_lds, st, cf);
+        launch_col_fwd_generic<Stage, false>(p, cf, narrays, st);
 }
 
 static RowArgs row_args(pa_plan *p, uint64_t npairs, const uint32_t *seed_side) {
