@@ -928,6 +928,31 @@ __device__ __forceinline__ CFn cf_shfl_up(CFn f, int d) {
     return CFn{(uint32_t)__shfl_up((int)f.g, d, 64), (uint32_t)__shfl_up((int)f.th, d, 64)};
 }
 
+__device__ __forceinline__ CFn cf_shfl_down(CFn f, int d) {
+    return CFn{(uint32_t)__shfl_down((int)f.g, d, 64), (uint32_t)__shfl_down((int)f.th, d, 64)};
+}
+
+// Block-wide ordered composition of the threads' carry functions (thread 0
+// first); the result is valid in thread 0.  NT threads, multiple of 64.
+template <int NT>
+__device__ CFn block_reduce(CFn f) {
+    __shared__ CFn wsum[NT / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    CFn w = f;
+    // lane l composes lanes [l, l + 2d) from its own [l, l + d) and lane l + d's
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const CFn o = cf_shfl_down(w, d);
+        if (lane + d < 64) w = cf_compose(w, o);
+    }
+    if (lane == 0) wsum[wid] = w;
+    __syncthreads();
+    CFn tot = cf_id();
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NT / 64; ++i) tot = cf_compose(tot, wsum[i]);
+    return tot;
+}
+
 // Block-wide scan of carry functions.  Returns the exclusive prefix for the
 // calling thread and the block total.  NT threads, multiple of 64.
 template <int NT>
@@ -1135,6 +1160,24 @@ struct DigitArgs {
 // (S folded once at bit gamma; 2^gamma = 1 mod p, e = BL - gamma): the B-bit
 // pieces of the coefficients that overlap digit m.
 __device__ __forceinline__ uint64_t fold_digit(const DigitArgs &A, uint64_t m) {
+    if (A.B == 32) {
+        // the B-bit pieces are the coefficients' 32-bit word planes; the
+        // folded part is shifted left by e < 32 (a funnel shift of two planes)
+        uint64_t sum = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < 3; ++q)
+            if (m >= q && m - q < A.L) sum += A.c96[q * A.N + m - q];
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+            if (q >= A.Q2 || m < q) continue;
+            const uint64_t j = A.L + m - q;
+            if (j >= A.ncoef) continue;
+            const uint32_t hi = q < 3 ? A.c96[q * A.N + j] : 0u;
+            const uint32_t lo = q >= 1 ? A.c96[(q - 1) * A.N + j] : 0u;
+            sum += A.e ? __builtin_amdgcn_alignbit(hi, lo, 32u - A.e) : hi;
+        }
+        return sum;
+    }
     const uint64_t mask = (1ull << A.B) - 1;
     uint64_t sum = 0;
     for (uint32_t q = 0; q < A.Q; ++q)
@@ -1173,6 +1216,16 @@ __device__ __forceinline__ uint64_t wrap_digit(const DigitArgs &A, uint64_t m) {
 // MH digit m < L: the limbs of c plus the pieces of the product coefficients
 // below limb L (everything at or above bit gamma is dropped, mod 2^gamma).
 __device__ __forceinline__ uint64_t mh_digit(const DigitArgs &A, uint64_t m) {
+    if (A.B == 32) {  // c's limb m is its 32-bit word m (bits >= gamma masked); pieces are word planes
+        const uint64_t bit = 32 * m;
+        uint32_t cw = bit < A.gamma ? ((const uint32_t *)A.cseed)[m] : 0u;
+        if (bit + 32 > A.gamma && bit < A.gamma) cw &= (1u << (A.gamma - bit)) - 1u;
+        uint64_t sum = cw;
+#pragma unroll
+        for (uint32_t q = 0; q < 3; ++q)
+            if (m >= q) sum += A.c96[q * A.N + m - q];
+        return sum;
+    }
     const uint64_t mask = (1ull << A.B) - 1;
     uint64_t sum = bits_at(A.cseed, A.gamma, m * A.B, A.B);
     for (uint32_t q = 0; q < A.Q; ++q)
@@ -1192,8 +1245,7 @@ __global__ __launch_bounds__(CARRY_TILE) void k_digit_tile(DigitArgs A) {
         A.t[m] = d;
         if (m < A.M) f = cf_limb(d, A.B);
     }
-    CFn excl, total;
-    block_scan<CARRY_TILE>(f, excl, total);
+    const CFn total = block_reduce<CARRY_TILE>(f);
     if (threadIdx.x == 0) A.agg[blockIdx.x] = total;
 }
 
