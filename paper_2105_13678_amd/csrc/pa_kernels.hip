@@ -56,6 +56,11 @@ __device__ __forceinline__ uint32_t opaque(uint32_t v) {
     return v;
 }
 
+// The word at byte address a of an LDS array.  With a statically sized
+// array its base is a compile-time constant that folds into the ds
+// instruction (dynamic LDS would cost one add per access).
+__device__ __forceinline__ uint32_t &lds_word(uint32_t *lds, uint32_t a) { return *(uint32_t *)((char *)lds + a); }
+
 // Workgroup b of a G-workgroup grid is dispatched to XCD b % 8; hand each XCD
 // a contiguous range of tiles so neighbouring tiles share that XCD's L2.
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t G) {
@@ -446,7 +451,7 @@ template <int Stage, bool MIX>
 __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
     constexpr uint32_t NSUB = MIX ? 3u : 1u;
     constexpr int X0_ROWS = MIX ? 8 : 4;  // step-A rows of a task holding x_n (x_(n+Nsub): rows < 4)
-    uint32_t *lds = lds_dyn;
+    __shared__ uint32_t L9[1u << (C9_LG + C9_CLG)];  // one 512 x 16 tile
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t arr = blockIdx.y + A.arr0;
     const uint64_t c0 = (uint64_t)tile << C9_CLG;
@@ -521,7 +526,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
             dft_fwd_x<8, !MIX, true>(v, w, M);
             const uint32_t sb = swz_c9(tau);
 #pragma unroll
-            for (int jj = 0; jj < 8; ++jj) lds[sb ^ (1024u * jj)] = v[jj];
+            for (int jj = 0; jj < 8; ++jj) lds_word(L9, (sb ^ (1024u * jj)) << 2) = v[jj];
         }
         __syncthreads();
 #pragma unroll 1
@@ -531,13 +536,13 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
             const uint32_t sb = swz_c9(1024u * b + 16u * n1 + q);
             uint32_t v[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = lds[sb ^ swz_c9(128u * j)];
+            for (int j = 0; j < 8; ++j) v[j] = lds_word(L9, (sb ^ swz_c9(128u * j)) << 2);
             uint32_t w[8];
 #pragma unroll
             for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 5, 0);
             dft_fwd_tw<8>(v, w, M);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) lds[sb ^ swz_c9(128u * j)] = v[j];
+            for (int j = 0; j < 8; ++j) lds_word(L9, (sb ^ swz_c9(128u * j)) << 2) = v[j];
         }
         __syncthreads();
 #pragma unroll 1
@@ -547,7 +552,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
             const uint32_t sb = swz_c9(128u * b + q);
             uint32_t v[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = lds[sb ^ (16u * j)];
+            for (int j = 0; j < 8; ++j) v[j] = lds_word(L9, (sb ^ (16u * j)) << 2);
             dft_fwd<8>(v, M);
             uint32_t *o = out + ((uint64_t)(8u * b) << A.m2) + c0 + q;
 #pragma unroll
@@ -689,6 +694,8 @@ __global__ __launch_bounds__(ROW_MAX_THREADS) void k_row(RowArgs A) {
 
 constexpr int R16_THREADS = 256;
 constexpr uint32_t R16_LEN = 4096;
+constexpr uint32_t R16_BA = 4 * R16_LEN;  // byte offset of the second row buffer
+
 
 
 __device__ __forceinline__ constexpr uint32_t swz_r16(uint32_t i) {
@@ -699,8 +706,11 @@ __device__ __forceinline__ constexpr uint32_t swz_r16(uint32_t i) {
 
 template <int Stage>
 __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
-    uint32_t *bx = lds_dyn;
-    uint32_t *ba = lds_dyn + R16_LEN;
+    __shared__ uint32_t L16[2 * R16_LEN];
+    // LDS: the x row's buffer at byte 0, the a row's at byte R16_BA.  Accesses
+    // go through byte addresses base ^ (4 * swz(offset)): one XOR each, the
+    // buffer base folded in beforehand (bit 14 is disjoint from every
+    // swizzled offset, so adding it commutes with the XOR).
     const uint32_t pq = blockIdx.y;
     const PrimeConst M = A.P.c[pq];
     const uint32_t t = threadIdx.x;
@@ -712,6 +722,7 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
     const uint32_t b2 = (t >> 4) * 256u + (t & 15u);
     const uint32_t s2 = swz_r16(b2);                                 // b2 + 16 j
     const uint32_t s3 = swz_r16(16u * t);                            // 16 t + j
+    const uint32_t s1b = s1 << 2, s2b = s2 << 2, s3b = s3 << 2;        // byte addresses
     const uint32_t n1b = t & 15u;
     // step twiddles (step 1 omega_4096^(t k2), step 2 omega_4096^(16 n1 k2))
     // from a table in thread order, so each is one coalesced load per use
@@ -729,8 +740,7 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
 #pragma unroll 1
         for (int side = 0; side < 2; ++side) {
             const __amdgpu_buffer_rsrc_t rg = rsrc_of(side ? arow : xrow, R16_LEN);
-            uint32_t *buf = side ? ba : bx;
-            const uint32_t t4l = opaque(t4), s1l = opaque(s1);
+            const uint32_t t4l = opaque(t4), a1 = opaque((side ? R16_BA : 0u) + s1b);
             // step 1: from global, four-step twiddle, radix-16, step twiddles.
             // All 32 loads are issued before the first use (the scheduling
             // barrier keeps the compiler from interleaving load, wait and
@@ -748,33 +758,32 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
             for (int j = 0; j < 16; ++j) v[j] = mont(v[j], wv[j], M);
             dft_fwd_tw<16>(v, w, M);
 #pragma unroll
-            for (int j = 0; j < 16; ++j) buf[s1l ^ swz_r16(256u * j)] = v[j];
+            for (int j = 0; j < 16; ++j) lds_word(L16, a1 ^ (swz_r16(256u * j) << 2)) = v[j];
         }
         __syncthreads();
 #pragma unroll 1
         for (int side = 0; side < 2; ++side) {
-            uint32_t *buf = side ? ba : bx;
-            const uint32_t s2l = opaque(s2), n4l = opaque(4u * n1b);
+            const uint32_t a2 = opaque((side ? R16_BA : 0u) + s2b), n4l = opaque(4u * n1b);
             uint32_t v[16], w[16];
             // step 2: radix-16 on stride 16, step twiddles
 #pragma unroll
-            for (int j = 0; j < 16; ++j) v[j] = buf[s2l ^ swz_r16(16u * j)];
+            for (int j = 0; j < 16; ++j) v[j] = lds_word(L16, a2 ^ (swz_r16(16u * j) << 2));
 #pragma unroll
             for (int j = 1; j < 16; ++j) w[j] = bload(rt, n4l, 16384u + 64u * j);
             __builtin_amdgcn_sched_barrier(0);
             dft_fwd_tw<16>(v, w, M);
 #pragma unroll
-            for (int j = 0; j < 16; ++j) buf[s2l ^ swz_r16(16u * j)] = v[j];
+            for (int j = 0; j < 16; ++j) lds_word(L16, a2 ^ (swz_r16(16u * j) << 2)) = v[j];
         }
         __syncthreads();
         // step 3: radix-16 on 16 consecutive values of each row, then multiply-accumulate
         uint32_t vx[16], va[16];
-        const uint32_t s3l = opaque(s3);
+        const uint32_t a3 = opaque(s3b);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) vx[j] = bx[s3l ^ (uint32_t)j];
+        for (int j = 0; j < 16; ++j) vx[j] = lds_word(L16, a3 ^ (4u * j));
         dft_fwd<16>(vx, M);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) va[j] = ba[s3l ^ (uint32_t)j];
+        for (int j = 0; j < 16; ++j) va[j] = lds_word(L16, R16_BA + (a3 ^ (4u * j)));
         dft_fwd<16>(va, M);
 #pragma unroll
         for (int j = 0; j < 16; ++j) acc[j] = red2(acc[j] + mont(vx[j], va[j], M), M);
@@ -785,21 +794,21 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
     const __amdgpu_buffer_rsrc_t rti = rsrc_of(A.r16i + pq * R16_TW, R16_TW);
     dft_inv<16>(acc, M);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) bx[s3 ^ (uint32_t)j] = acc[j];
+    for (int j = 0; j < 16; ++j) lds_word(L16, s3b ^ (4u * j)) = acc[j];
     __syncthreads();
     uint32_t v[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = bx[s2 ^ swz_r16(16u * j)];
+    for (int j = 0; j < 16; ++j) v[j] = lds_word(L16, s2b ^ (swz_r16(16u * j) << 2));
     uint32_t w[16];
 #pragma unroll
     for (int s = 1; s < 16; ++s) w[s] = bload(rti, 4u * n1b, 16384u + 64u * s);
     __builtin_amdgcn_sched_barrier(0);
     dft_inv_tw<16>(v, w, M);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) bx[s2 ^ swz_r16(16u * j)] = v[j];
+    for (int j = 0; j < 16; ++j) lds_word(L16, s2b ^ (swz_r16(16u * j) << 2)) = v[j];
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = bx[s1 ^ swz_r16(256u * j)];
+    for (int j = 0; j < 16; ++j) v[j] = lds_word(L16, s1b ^ (swz_r16(256u * j) << 2));
     const __amdgpu_buffer_rsrc_t ro = rsrc_of(A.out + pq * A.N + rbase, R16_LEN);
     const __amdgpu_buffer_rsrc_t rwi = rsrc_of(A.Wi + pq * A.N + rbase, R16_LEN);
     uint32_t wv[16];
@@ -994,7 +1003,7 @@ __device__ void block_scan(CFn f, CFn &excl, CFn &total) {
 // DIT stage).
 template <int Stage>
 __global__ __launch_bounds__(COL_THREADS) void k_col9_inv(ColInvArgs A) {
-    uint32_t *lds = lds_dyn;
+    __shared__ uint32_t L9[1u << (C9_LG + C9_CLG)];  // one 512 x 16 tile
     const uint32_t pq = blockIdx.y;
     const PrimeConst M = A.P.c[pq];
     const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.twi + ((uint64_t)pq << C9_LG), 1u << C9_LG);
@@ -1012,7 +1021,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_inv(ColInvArgs A) {
         dft_inv<8>(v, M);
         const uint32_t sb = swz_c9(128u * b + q);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) lds[sb ^ (16u * j)] = v[j];
+        for (int j = 0; j < 8; ++j) lds_word(L9, (sb ^ (16u * j)) << 2) = v[j];
     }
     __syncthreads();
 #pragma unroll 1
@@ -1022,12 +1031,12 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_inv(ColInvArgs A) {
         const uint32_t sb = swz_c9(1024u * b + 16u * n1 + q);
         uint32_t v[8], w[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = lds[sb ^ swz_c9(128u * j)];
+        for (int j = 0; j < 8; ++j) v[j] = lds_word(L9, (sb ^ swz_c9(128u * j)) << 2);
 #pragma unroll
         for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 5, 0);
         dft_inv_tw<8>(v, w, M);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) lds[sb ^ swz_c9(128u * j)] = v[j];
+        for (int j = 0; j < 8; ++j) lds_word(L9, (sb ^ swz_c9(128u * j)) << 2) = v[j];
     }
     __syncthreads();
 #pragma unroll 1
@@ -1037,7 +1046,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_inv(ColInvArgs A) {
         const uint32_t sb = swz_c9(tau);
         uint32_t v[8], w[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = lds[sb ^ (1024u * j)];
+        for (int j = 0; j < 8; ++j) v[j] = lds_word(L9, (sb ^ (1024u * j)) << 2);
 #pragma unroll
         for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 2, 0);
         dft_inv_tw<8>(v, w, M);
@@ -1521,14 +1530,11 @@ static void launch_col_fwd_generic(pa_plan *p, const ColFwdArgs &cf, unsigned na
 template <int Stage>
 static void launch_col_fwd(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, hipStream_t st) {
     const unsigned ncol_tiles = 1u << (p->m2 - p->c_lg);
-    const size_t col_lds = ((size_t)4 << p->m1) << p->c_lg;
-    const bool c9 = p->m1 == C9_LG && p->c_lg == C9_CLG;
+    const bool c9 = p->m1 == C9_LG && p->c_lg == C9_CLG;  // 512 x 16 tiles in static LDS
     if (c9 && p->mix)  // all three primes and radix-3 transforms per workgroup
-        hipLaunchKernelGGL((k_col9_fwd<Stage, true>), dim3(ncol_tiles, narrays, 1), dim3(COL_THREADS), col_lds, st,
-                           cf);
+        hipLaunchKernelGGL((k_col9_fwd<Stage, true>), dim3(ncol_tiles, narrays, 1), dim3(COL_THREADS), 0, st, cf);
     else if (c9)  // all three primes per workgroup
-        hipLaunchKernelGGL((k_col9_fwd<Stage, false>), dim3(ncol_tiles, narrays, 1), dim3(COL_THREADS), col_lds, st,
-                           cf);
+        hipLaunchKernelGGL((k_col9_fwd<Stage, false>), dim3(ncol_tiles, narrays, 1), dim3(COL_THREADS), 0, st, cf);
     else if (p->mix)
         launch_col_fwd_generic<Stage, true>(p, cf, narrays, st);
     else
@@ -1558,7 +1564,7 @@ template <int Stage>
 static void launch_row(pa_plan *p, const RowArgs &ra, hipStream_t st) {
     const unsigned rows = (unsigned)(p->N >> p->m2);  // 2^m1, or 3 * 2^m1 for N = 3 * 2^m
     if (p->m2 == 12)
-        hipLaunchKernelGGL(k_row16<Stage>, dim3(rows, NPRIMES), dim3(R16_THREADS), (size_t)8 * R16_LEN, st, ra);
+        hipLaunchKernelGGL(k_row16<Stage>, dim3(rows, NPRIMES), dim3(R16_THREADS), 0, st, ra);
     else
         hipLaunchKernelGGL(k_row<Stage>, dim3(rows, NPRIMES), dim3(row_threads(p)), (size_t)4 << p->m2, st, ra);
 }
@@ -1580,8 +1586,8 @@ template <int Stage>
 static void launch_col_inv(pa_plan *p, const ColInvArgs &ci, hipStream_t st) {
     const unsigned nsub = p->mix ? 3u : 1u;  // blockIdx.z: transform of the radix-3 split
     if (p->m1 == C9_LG && p->m2 >= C9_CLG)
-        hipLaunchKernelGGL(k_col9_inv<Stage>, dim3(1u << (p->m2 - C9_CLG), NPRIMES, nsub), dim3(COL_THREADS),
-                           (size_t)4 << (C9_LG + C9_CLG), st, ci);
+        hipLaunchKernelGGL(k_col9_inv<Stage>, dim3(1u << (p->m2 - C9_CLG), NPRIMES, nsub), dim3(COL_THREADS), 0, st,
+                           ci);
     else
         hipLaunchKernelGGL(k_col_inv<Stage>, dim3(1u << (p->m2 - p->ci_lg), NPRIMES, nsub), dim3(COL_THREADS),
                            ((size_t)4 << p->m1) << p->ci_lg, st, ci);
