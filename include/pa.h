@@ -68,13 +68,18 @@ typedef enum pa_status {
  * choices.  B = 0 picks the limb width (at most 32 bits) that gives the
  * cheapest exact transform, the widest among equals; otherwise 8 <= B <= 32.
  * The output never depends on B or N. */
-#define PA_FLAG_POW2_LENGTHS 1u /* flags: power-of-two transform lengths only */
+#define PA_FLAG_POW2_LENGTHS 1u   /* flags: power-of-two transform lengths only   */
+#define PA_FLAG_RADIX3_LENGTHS 2u /* flags: lengths 3 * 2^m only                  */
 typedef struct pa_params {
     uint64_t n;       /* input key length in bits, n >= 2                    */
     uint64_t r;       /* output length in bits, 1 <= r < n and r < gamma     */
     uint64_t gamma;   /* Mersenne exponent, or 0 for automatic               */
     uint32_t B;       /* limb width in bits (the paper's 2^B-ary words), 0 = auto */
-    uint32_t flags;   /* 0 or PA_FLAG_POW2_LENGTHS                          */
+    uint32_t flags;   /* 0, PA_FLAG_POW2_LENGTHS or PA_FLAG_RADIX3_LENGTHS  */
+    uint32_t col_lg;  /* columns per tile of the key-chunk column pass,
+                         2^col_lg; 0 = automatic; otherwise at most the row
+                         length 2^log2N2, with log2N1 + col_lg <= 14       */
+    uint32_t reserved; /* must be 0                                          */
 } pa_params;
 
 typedef struct pa_plan_info {
@@ -94,6 +99,7 @@ typedef struct pa_plan_info {
     uint32_t nprimes;       /* NTT primes per transform (3)                 */
     uint32_t primes[3];     /* the NTT primes p0, p1, p2 of this length     */
     uint32_t len_factor;    /* 1, or 3 for the lengths N = 3 * 2^log2N      */
+    uint32_t col_lg;        /* column-tile width exponent of the key-chunk pass */
 } pa_plan_info;
 
 typedef struct pa_plan pa_plan;
@@ -184,6 +190,36 @@ void pa_batch_plan_destroy(pa_batch_plan *plan);
  * failure of the device, else PA_OK. */
 pa_status pa_hash_batched(pa_batch_plan *plan, const pa_block *blocks, uint32_t count,
                           pa_status *per_block, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Autotuning.  The limb width B (the 2^B-ary words of Sec. 2.1), the
+ * transform length form (2^m or 3 * 2^m) and the column-tile width change
+ * only the speed of a hash, never its output.  The plan rule picks them from
+ * a cost model; these calls pick them by timing instead. */
+
+/* Time every candidate shape for *params on HIP device `hip_device` and
+ * return the fastest in *best (B, flags and col_lg set explicitly; n, r,
+ * gamma copied) and its time per hash in *best_ms (nullable).  Candidates:
+ * for each length form admitted by params->flags, the plan rule's limb width
+ * for that form (or params->B), with the rule's column-tile width and its
+ * neighbours (or params->col_lg).  Each candidate gets its own plan, one
+ * warm-up hash and `reps` (1..1000) timed hashes of an all-zero key with
+ * zero seeds (b = 1) on a private stream; the device must have room for
+ * one plan at a time.  Blocks until done.  Returns the plan errors of
+ * *params, PA_ERR_ARG, PA_ERR_NOMEM (no candidate fitted) or PA_ERR_DEVICE. */
+pa_status pa_plan_tune(const pa_params *params, int hip_device, uint32_t reps, pa_params *best,
+                       double *best_ms);
+
+/* Tune a batch plan for the shapes of blocks[0..count): for each (gamma, k)
+ * class not tuned before, pa_plan_tune on the first block of that class
+ * (`reps` timed hashes per candidate); later pa_hash_batched calls build
+ * every block of a tuned class with the tuned limb width, length form and
+ * column-tile width.  Blocks whose (n, r) admits no plan are skipped.  Uses
+ * the plan's device; blocks until done; the key and seed buffers of the
+ * blocks are not read.  *tuned (nullable) receives the number of classes
+ * tuned by this call. */
+pa_status pa_batch_plan_tune(pa_batch_plan *plan, const pa_block *blocks, uint32_t count, uint32_t reps,
+                             uint32_t *tuned);
 
 /* ------------------------------------------------------------------------
  * Serving: requests from many QKD sessions hashed as they arrive.

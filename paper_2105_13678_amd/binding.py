@@ -20,6 +20,7 @@ PA_ERR_ARG, PA_ERR_NO_GAMMA, PA_ERR_GAMMA, PA_ERR_INEXACT = -1, -2, -3, -4
 PA_ERR_SEED_B_EVEN, PA_ERR_SEED_RANGE, PA_ERR_NOMEM, PA_ERR_DEVICE = -5, -6, -7, -8
 PA_ERR_BUSY, PA_ERR_LIMIT = -9, -10
 PA_FLAG_POW2_LENGTHS = 1  # pa_params.flags: power-of-two transform lengths only
+PA_FLAG_RADIX3_LENGTHS = 2  # pa_params.flags: lengths 3 * 2^m only
 
 # pa_phase, in order
 PHASES = ["prologue", "mmh_col", "mmh_row", "mmh_colinv", "fold", "mh_col", "mh_row", "mh_colinv",
@@ -35,7 +36,8 @@ class PAError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("r", ctypes.c_uint64), ("gamma", ctypes.c_uint64),
-                ("B", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+                ("B", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("col_lg", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -46,7 +48,7 @@ class PlanInfo(ctypes.Structure):
                 ("out_words", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64),
                 ("exact_log2", ctypes.c_double), ("log2N1", ctypes.c_uint32),
                 ("log2N2", ctypes.c_uint32), ("nprimes", ctypes.c_uint32), ("primes", ctypes.c_uint32 * 3),
-                ("len_factor", ctypes.c_uint32)]
+                ("len_factor", ctypes.c_uint32), ("col_lg", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_}
@@ -109,6 +111,12 @@ def lib():
         L.pa_batch_plan_destroy.restype = None
         L.pa_hash_batched.argtypes = [_VP, ctypes.POINTER(Block), ctypes.c_uint32, ctypes.POINTER(ctypes.c_int), _VP]
         L.pa_hash_batched.restype = ctypes.c_int
+        L.pa_plan_tune.argtypes = [ctypes.POINTER(Params), ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(Params),
+                                   ctypes.POINTER(ctypes.c_double)]
+        L.pa_plan_tune.restype = ctypes.c_int
+        L.pa_batch_plan_tune.argtypes = [_VP, ctypes.POINTER(Block), ctypes.c_uint32, ctypes.c_uint32,
+                                         ctypes.POINTER(ctypes.c_uint32)]
+        L.pa_batch_plan_tune.restype = ctypes.c_int
         L.pa_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(_VP)]
         L.pa_server_create.restype = ctypes.c_int
         L.pa_server_destroy.argtypes = [_VP]
@@ -145,12 +153,25 @@ def decode_status(flags: int) -> int:
     return lib().pa_decode_status(int(flags) & 0xFFFFFFFF)
 
 
-def plan_query(n: int, r: int, gamma: int = 0, B: int = 0, flags: int = 0):
+def plan_query(n: int, r: int, gamma: int = 0, B: int = 0, flags: int = 0, col_lg: int = 0):
     """(status, info dict or None): the shape pa_plan_create would use."""
-    prm = Params(n, r, gamma, B, flags)
+    prm = Params(n, r, gamma, B, flags, col_lg, 0)
     info = PlanInfo()
     st = lib().pa_plan_query(ctypes.byref(prm), ctypes.byref(info))
     return st, (info.as_dict() if st == PA_OK else None)
+
+
+def plan_tune(n: int, r: int, reps: int = 5, device: int = 0, gamma: int = 0, B: int = 0, flags: int = 0,
+              col_lg: int = 0):
+    """Time the candidate shapes of (n, r) on the device (pa_plan_tune);
+    returns (params dict with B, flags and col_lg set, ms per hash)."""
+    prm = Params(n, r, gamma, B, flags, col_lg, 0)
+    best = Params()
+    ms = ctypes.c_double()
+    st = lib().pa_plan_tune(ctypes.byref(prm), int(device), int(reps), ctypes.byref(best), ctypes.byref(ms))
+    if st != PA_OK:
+        raise PAError(st, "pa_plan_tune")
+    return {name: getattr(best, name) for name, _ in Params._fields_ if name != "reserved"}, ms.value
 
 
 def _dev_ptr(t, min_words: int, what: str, device) -> int:
@@ -169,11 +190,12 @@ def _dev_ptr(t, min_words: int, what: str, device) -> int:
 class Plan:
     """One (n, r) shape on one GPU; owns its device workspace."""
 
-    def __init__(self, n: int, r: int, gamma: int = 0, B: int = 0, device: int = 0, flags: int = 0):
+    def __init__(self, n: int, r: int, gamma: int = 0, B: int = 0, device: int = 0, flags: int = 0,
+                 col_lg: int = 0):
         import torch
         self._h = _VP()
         self.device = torch.device("cuda", device)
-        prm = Params(n, r, gamma, B, flags)
+        prm = Params(n, r, gamma, B, flags, col_lg, 0)
         st = lib().pa_plan_create(ctypes.byref(prm), int(device), ctypes.byref(self._h))
         if st != PA_OK:
             self._h = _VP()
@@ -328,6 +350,19 @@ class BatchPlan:
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         st = lib().pa_hash_batched(self._h, arr, len(blocks), per, s.cuda_stream)
         return st, list(per)
+
+    def tune(self, blocks, reps: int = 5) -> int:
+        """Autotune the (gamma, k) classes of blocks (sequence of (n, r, ...);
+        only n and r are read) for later hash calls; returns the number of
+        classes tuned now (pa_batch_plan_tune)."""
+        arr = (Block * len(blocks))()
+        for i, blk in enumerate(blocks):
+            arr[i] = Block(blk[0], blk[1], 0, 0, 0, 0, 0)
+        tuned = ctypes.c_uint32()
+        st = lib().pa_batch_plan_tune(self._h, arr, len(blocks), int(reps), ctypes.byref(tuned))
+        if st != PA_OK:
+            raise PAError(st, "pa_batch_plan_tune")
+        return tuned.value
 
 
 def _host_ptr(x, min_words: int, what: str) -> int:

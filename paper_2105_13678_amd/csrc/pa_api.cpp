@@ -40,7 +40,8 @@ struct DeviceGuard {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 pa_status plan_shape(const pa_params *prm, uint64_t *gamma, uint64_t *k, uint32_t *B) {
-    if (!prm || (prm->flags & ~PA_FLAG_POW2_LENGTHS) != 0) return PA_ERR_ARG;
+    const uint32_t both = PA_FLAG_POW2_LENGTHS | PA_FLAG_RADIX3_LENGTHS;
+    if (!prm || (prm->flags & ~both) != 0 || (prm->flags & both) == both || prm->reserved != 0) return PA_ERR_ARG;
     const uint64_t n = prm->n, r = prm->r;
     if (n < 2 || r < 1 || r >= n) return PA_ERR_ARG;
     uint64_t g = 0;
@@ -141,7 +142,8 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     pa_status st = plan_shape(prm, &gamma, &k, &B);
     if (st != PA_OK) return st;
     if (k > kMaxK) return PA_ERR_LIMIT;
-    const bool pow2_only = (prm->flags & PA_FLAG_POW2_LENGTHS) != 0;
+    const uint32_t mx_lo = (prm->flags & PA_FLAG_RADIX3_LENGTHS) ? 1u : 0u;
+    const uint32_t mx_hi = (prm->flags & PA_FLAG_POW2_LENGTHS) ? 1u : 2u;
     // Candidate lengths for limb width b: the shortest 2^m and 3 * 2^m that
     // hold the product, each with its own primes.  Cost model: butterflies
     // N log2 N, plus one pass over N for the radix-3 step.  `seen` records
@@ -150,7 +152,7 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     auto choose = [&](uint32_t b, uint32_t *m_out, uint32_t *mix_out, double *cost_out) {
         const uint64_t Lb = (gamma + b - 1) / b;
         bool ok = false;
-        for (uint32_t mx = 0; mx < (pow2_only ? 1u : 2u); ++mx) {
+        for (uint32_t mx = mx_lo; mx < mx_hi; ++mx) {
             const uint32_t mb = log2_len(Lb, mx ? 3 : 1);
             const pa::PrimeTriple *T = triple_for(mb, mx);
             if (!T) continue;
@@ -215,14 +217,27 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
         m2 = (m + 1) / 2;
     p->m2 = m2;
     p->m1 = m - m2;
-    // forward column tiles of 16 columns (64-byte row segments, 32 KiB of
-    // LDS at 2^9 rows); the single-array inverse pass uses 8 columns for more
-    // workgroups
-    uint32_t c_lg = 4;
-    if (c_lg > p->m2) c_lg = p->m2;
-    if (p->m1 + c_lg > kMaxLdsLog2) c_lg = kMaxLdsLog2 - p->m1;
-    p->c_lg = c_lg;
-    p->ci_lg = c_lg < 3 ? c_lg : 3;
+    // Column tiles of 2^c columns x 2^m1 rows (at most 2^14 words of LDS).
+    // The MH-stage forward pass (two arrays) uses 16 columns (64-byte row
+    // segments), the single-array inverse pass 8 (more workgroups).  The
+    // key-chunk pass widens short columns towards 256 first-step tasks per
+    // tile (one per thread) while its 2k arrays still give at least 512
+    // workgroups; a request may fix its width (col_lg, e.g. from pa_plan_tune).
+    auto fit = [&](uint32_t c) {
+        if (c > p->m2) c = p->m2;
+        if (p->m1 + c > kMaxLdsLog2) c = kMaxLdsLog2 - p->m1;
+        return c;
+    };
+    const uint32_t c_mh = fit(4);
+    uint32_t c_mmh = fit(p->m1 < 7 ? 11 - p->m1 : 4);
+    while (c_mmh > c_mh && ((uint64_t)2 * k << (p->m2 - c_mmh)) < 512) --c_mmh;
+    if (prm->col_lg) {
+        if (prm->col_lg > p->m2 || p->m1 + prm->col_lg > kMaxLdsLog2) return PA_ERR_ARG;
+        c_mmh = prm->col_lg;
+    }
+    p->c_lg = c_mmh;
+    p->c_lg_mh = c_mh;
+    p->ci_lg = c_mh < 3 ? c_mh : 3;
     p->s_top = (uint32_t)(gamma - (uint64_t)B * (L - 1));
     p->e_fold = (uint32_t)((uint64_t)B * L - gamma);
     const uint64_t Q = (96 + B - 1) / B, Q2 = (96 + p->e_fold + B - 1) / B;
@@ -387,6 +402,7 @@ pa_status pa_plan_get_info(const pa_plan *p, pa_plan_info *info) {
     info->nprimes = pa::NPRIMES;
     for (int q = 0; q < pa::NPRIMES; ++q) info->primes[q] = p->primes.c[q].p;
     info->len_factor = p->mix ? 3 : 1;
+    info->col_lg = p->c_lg;
     return PA_OK;
 }
 

@@ -13,7 +13,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "pa_internal.hpp"
@@ -57,6 +59,9 @@ struct pa_batch_plan {
     hipEvent_t fork;
     uint32_t *d_status;  // max_blocks words
     uint32_t *h_status;  // pinned copy
+    // tuned shapes (pa_batch_plan_tune): (gamma, k) -> limb width, length
+    // form and column-tile width
+    std::map<std::pair<uint64_t, uint64_t>, pa_params> tuned;
 };
 
 namespace {
@@ -148,8 +153,17 @@ pa_status pa_hash_batched(pa_batch_plan *bp, const pa_block *blocks, uint32_t co
     std::vector<uint32_t> order;
     for (uint32_t i = 0; i < count; ++i) {
         const pa_block &bk = blocks[i];
-        pa_params prm{bk.n, bk.r, 0, 0, 0};
+        pa_params prm{bk.n, bk.r, 0, 0, 0, 0, 0};
         per_block[i] = pa::derive_plan(&prm, &plans[i], &lays[i]);
+        if (per_block[i] == PA_OK && !bp->tuned.empty()) {
+            auto it = bp->tuned.find({plans[i].gamma, plans[i].k});
+            if (it != bp->tuned.end()) {
+                prm.B = it->second.B;
+                prm.flags = it->second.flags;
+                prm.col_lg = it->second.col_lg;
+                per_block[i] = pa::derive_plan(&prm, &plans[i], &lays[i]);
+            }
+        }
         if (per_block[i] == PA_OK && (!bk.key || !bk.a || !bk.b || !bk.c || !bk.out)) per_block[i] = PA_ERR_ARG;
         if (per_block[i] != PA_OK) continue;
         plans[i].device = bp->device;
@@ -224,6 +238,26 @@ pa_status pa_hash_batched(pa_batch_plan *bp, const pa_block *blocks, uint32_t co
         return PA_ERR_DEVICE;
     }
     for (uint32_t i : order) per_block[i] = pa_decode_status(bp->h_status[i]);
+    return PA_OK;
+}
+
+pa_status pa_batch_plan_tune(pa_batch_plan *bp, const pa_block *blocks, uint32_t count, uint32_t reps,
+                             uint32_t *tuned) {
+    if (tuned) *tuned = 0;
+    if (!bp || (!blocks && count) || reps == 0) return PA_ERR_ARG;
+    for (uint32_t i = 0; i < count; ++i) {
+        pa_params prm{blocks[i].n, blocks[i].r, 0, 0, 0, 0, 0};
+        pa_plan p{};
+        pa::PlanLayout lay;
+        if (pa::derive_plan(&prm, &p, &lay) != PA_OK) continue;
+        const std::pair<uint64_t, uint64_t> key{p.gamma, p.k};
+        if (bp->tuned.count(key)) continue;
+        pa_params best{};
+        const pa_status st = pa_plan_tune(&prm, bp->device, reps, &best, nullptr);
+        if (st != PA_OK) return st;
+        bp->tuned[key] = best;
+        if (tuned) ++*tuned;
+    }
     return PA_OK;
 }
 

@@ -111,7 +111,8 @@ struct pa_plan {
     uint32_t B;
     uint32_t mix;               // 1: N = 3 * 2^m (a radix-3 step over three length-2^m transforms); 0: N = 2^m
     uint64_t Nsub;              // 2^m: length of the power-of-two transforms
-    uint32_t m, m1, m2, c_lg;   // 2^m = 2^m1 (column length) * 2^m2 (row length); 2^c_lg columns per tile
+    uint32_t m, m1, m2;         // 2^m = 2^m1 (column length) * 2^m2 (row length)
+    uint32_t c_lg, c_lg_mh;     // 2^c columns per tile of the forward column pass: key chunks and seeds; MH stage
     uint32_t ci_lg;             // columns per tile of the inverse column pass
     uint32_t s_top;             // bits in the top limb: gamma - B*(L-1), in [1, B]
     uint32_t e_fold;            // B*L - gamma, in [0, B)

@@ -1493,7 +1493,7 @@ static ColFwdArgs col_args(pa_plan *p, uint32_t mode) {
     cf.W = p->W;
     cf.m1 = p->m1;
     cf.m2 = p->m2;
-    cf.c_lg = p->c_lg;
+    cf.c_lg = mode == 0 ? p->c_lg : p->c_lg_mh;
     cf.B = p->B;
     cf.s_top = p->s_top;
     cf.mode = mode;
@@ -1514,9 +1514,9 @@ static ColFwdArgs col_args(pa_plan *p, uint32_t mode) {
 // per thread as the tile needs (2^(m1 - 3 + c_lg) tasks, m1 + c_lg <= 14).
 template <int Stage, bool MIX>
 static void launch_col_fwd_generic(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, hipStream_t st) {
-    const dim3 grid(1u << (p->m2 - p->c_lg), narrays, 1);
-    const size_t col_lds = ((size_t)4 << p->m1) << p->c_lg;
-    const uint32_t ntask = (1u << (p->m1 - 3)) << p->c_lg;
+    const dim3 grid(1u << (p->m2 - cf.c_lg), narrays, 1);
+    const size_t col_lds = ((size_t)4 << p->m1) << cf.c_lg;
+    const uint32_t ntask = (1u << (p->m1 - 3)) << cf.c_lg;
     if (ntask <= COL_THREADS)
         hipLaunchKernelGGL((k_col_fwd<Stage, MIX, 1>), grid, dim3(COL_THREADS), col_lds, st, cf);
     else if (ntask <= 2 * COL_THREADS)
@@ -1529,8 +1529,8 @@ static void launch_col_fwd_generic(pa_plan *p, const ColFwdArgs &cf, unsigned na
 
 template <int Stage>
 static void launch_col_fwd(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, hipStream_t st) {
-    const unsigned ncol_tiles = 1u << (p->m2 - p->c_lg);
-    const bool c9 = p->m1 == C9_LG && p->c_lg == C9_CLG;  // 512 x 16 tiles in static LDS
+    const unsigned ncol_tiles = 1u << (p->m2 - cf.c_lg);
+    const bool c9 = p->m1 == C9_LG && cf.c_lg == C9_CLG;  // 512 x 16 tiles in static LDS
     if (c9 && p->mix)  // all three primes and radix-3 transforms per workgroup
         hipLaunchKernelGGL((k_col9_fwd<Stage, true>), dim3(ncol_tiles, narrays, 1), dim3(COL_THREADS), 0, st, cf);
     else if (c9)  // all three primes per workgroup

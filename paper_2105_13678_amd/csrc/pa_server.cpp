@@ -352,7 +352,7 @@ pa_status pa_server_set_seeds(pa_server *s, uint32_t session, uint64_t gamma, ui
                               const uint64_t *b, const uint64_t *c) {
     if (!s || !a || !b || !c || kmax == 0 || kmax > 4096) return PA_ERR_ARG;
     // gamma must be a tabled Mersenne exponent: ask the plan rule with r = 1
-    pa_params prm{gamma + 1, 1, gamma, 0, 0};
+    pa_params prm{gamma + 1, 1, gamma, 0, 0, 0, 0};
     pa_plan tmp{};
     pa::PlanLayout lay;
     pa_status st = pa::derive_plan(&prm, &tmp, &lay);
@@ -392,7 +392,7 @@ pa_status pa_submit(pa_server *s, const pa_request *req, uint64_t *ticket) {
     if (!s || !req || !ticket || !req->key || !req->out) return PA_ERR_ARG;
     Request r{};
     r.req = *req;
-    pa_params prm{req->n, req->r, 0, 0, 0};
+    pa_params prm{req->n, req->r, 0, 0, 0, 0, 0};
     pa_status st = pa::derive_plan(&prm, &r.plan, &r.lay);
     if (st != PA_OK) return st;
     r.plan.device = s->cfg.device;

@@ -168,7 +168,7 @@ def test_auto_limb_width_is_cheapest_exact():
 
 def test_power_of_two_flag():
     """PA_FLAG_POW2_LENGTHS restricts the plan to lengths 2^m; the old rule
-    (widest exact B) then holds; other flag bits are rejected."""
+    (widest exact B) then holds; unknown flag bits are rejected."""
     rng = random.Random(6)
     mixed = 0
     for _ in range(200):
@@ -187,7 +187,7 @@ def test_power_of_two_flag():
             assert binding.plan_query(n, r, B=B + 1, flags=binding.PA_FLAG_POW2_LENGTHS)[0] in (
                 binding.PA_ERR_INEXACT, binding.PA_ERR_LIMIT)
     assert mixed > 20
-    assert binding.plan_query(1000, 10, flags=2)[0] == binding.PA_ERR_ARG
+    assert binding.plan_query(1000, 10, flags=4)[0] == binding.PA_ERR_ARG
 
 
 def test_plan_errors():
@@ -203,3 +203,28 @@ def test_plan_errors():
     assert st == 0
     assert binding.plan_query(1 << 32, 1 << 27, B=32)[0] == binding.PA_ERR_INEXACT
     assert binding.plan_query(1 << 32, 200)[0] == binding.PA_ERR_LIMIT   # k > 4096
+
+
+def test_length_form_flags_and_tile_width():
+    """PA_FLAG_RADIX3_LENGTHS forces lengths 3 * 2^m, both flags together are
+    rejected, as is a nonzero reserved word; col_lg fixes the key-chunk
+    column-tile width within the tile limits (2^col_lg <= row length,
+    log2N1 + col_lg <= 14) and is reported back; the automatic width widens
+    short columns."""
+    n, r = 18_802_622, 2_288_514  # gamma = 2,976,221, k = 7
+    st, i3 = binding.plan_query(n, r, flags=binding.PA_FLAG_RADIX3_LENGTHS)
+    assert st == 0 and i3["len_factor"] == 3 and i3["N"] == 3 << 16
+    st, i2 = binding.plan_query(n, r, flags=binding.PA_FLAG_POW2_LENGTHS)
+    assert st == 0 and i2["len_factor"] == 1 and i2["N"] == 1 << 18
+    assert binding.plan_query(n, r, flags=3)[0] == binding.PA_ERR_ARG
+    prm = binding.Params(n, r, 0, 0, 0, 0, 1)
+    info = binding.PlanInfo()
+    assert binding.lib().pa_plan_query(ctypes.byref(prm), ctypes.byref(info)) == binding.PA_ERR_ARG
+    # automatic width: 2^16-point rows of 16 rows widen to 64 columns (14 arrays)
+    assert (i3["log2N1"], i3["log2N2"], i3["col_lg"]) == (4, 12, 6)
+    assert binding.plan_query(260_000_000, 26_000_000)[1]["col_lg"] == 4
+    for c in (1, 3, 8, 10):
+        st, info = binding.plan_query(n, r, flags=binding.PA_FLAG_RADIX3_LENGTHS, col_lg=c)
+        assert st == 0 and info["col_lg"] == c
+    assert binding.plan_query(n, r, flags=binding.PA_FLAG_RADIX3_LENGTHS, col_lg=11)[0] == binding.PA_ERR_ARG  # 4 + 11 > 14
+    assert binding.plan_query(1 << 20, 1 << 16, col_lg=13)[0] == binding.PA_ERR_ARG  # wider than a row

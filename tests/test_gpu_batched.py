@@ -102,3 +102,26 @@ def test_batched_call_errors(pa):
         assert st == -10  # PA_ERR_LIMIT: more key bits than the plan allows
         st, per = bp.hash([small])
         assert st == 0 and per == [0]
+
+
+def test_batched_tuned_equals_untuned(pa):
+    """After pa_batch_plan_tune the same blocks (now built with the tuned
+    limb width, length form and tile width per (gamma, k) class) hash to the
+    same outputs."""
+    import torch
+    blocks = synth.uneven_blocks(41, 8, _shape, 18, 23)
+    say("[case] batched tuned:", [(b.n, b.r, b.gamma, b.k) for b in blocks])
+    dev = [_dev(pa, b) for b in blocks]
+    with pa.BatchPlan(16, 1 << 30) as bp:
+        st, per = bp.hash(dev)
+        assert st == 0 and all(x == 0 for x in per), per
+        outs = [d[6].clone() for d in dev]
+        for d in dev:
+            d[6].zero_()
+        ntuned = bp.tune(dev, reps=2)
+        assert 1 <= ntuned <= len(blocks)
+        assert bp.tune(dev, reps=2) == 0  # classes are tuned once
+        st, per = bp.hash(dev)
+        assert st == 0 and all(x == 0 for x in per), per
+        for o, d in zip(outs, dev):
+            assert torch.equal(o, d[6])

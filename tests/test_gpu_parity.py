@@ -50,9 +50,9 @@ def run_gpu(pa, plan, blk, stages=False):
     return st, pa.from_device(out)
 
 
-def check_block(pa, blk, B=0, stages=True, label="", flags=0):
-    say(f"[case] {label} n={blk.n} r={blk.r} gamma={blk.gamma} k={blk.k} B={B} flags={flags}")
-    plan = pa.Plan(blk.n, blk.r, gamma=blk.gamma, B=B, flags=flags)
+def check_block(pa, blk, B=0, stages=True, label="", flags=0, col_lg=0):
+    say(f"[case] {label} n={blk.n} r={blk.r} gamma={blk.gamma} k={blk.k} B={B} flags={flags} col_lg={col_lg}")
+    plan = pa.Plan(blk.n, blk.r, gamma=blk.gamma, B=B, flags=flags, col_lg=col_lg)
     try:
         st_g, out_g, y_g, U_g = run_gpu(pa, plan, blk, stages=True)
     finally:
@@ -191,6 +191,45 @@ def test_radix3_against_power_of_two_lengths(pa, n, r):
     assert res[0][0] == res[1][0] == 0
     for a3, a2 in zip(res[0][1:], res[1][1:]):
         assert np.array_equal(a3, a2)
+
+
+@pytest.mark.parametrize("gamma,k,flags", [(2976221, 7, 2), (2976221, 7, 1), (132049, 3, 2), (20996011, 2, 2),
+                                           (44497, 5, 1)])
+def test_column_tile_widths(pa, gamma, k, flags):
+    """Every admissible column-tile width of the key-chunk column pass
+    (2^1 .. 2^min(row, 14 - column) columns; 1 to 8 first-step tasks per
+    thread, idle threads where a tile has fewer tasks than threads) gives the
+    oracle's output, for both length forms."""
+    n, r = k * gamma - 5, gamma // 5
+    st, g, kk = defn.plan_shape(n, r, gamma)
+    assert st == 0 and kk == k
+    info = pa.plan_query(n, r, gamma, flags=flags)[1]
+    blk = synth.single_block(11 * k + flags, n, r, g, kk)
+    st_o, out_o = oracle.hash(blk.key, n, r, g, blk.a, blk.b, blk.c)
+    hi = min(info["log2N2"], 14 - info["log2N1"])
+    for c in sorted({1, 2, hi // 2, hi - 1, hi} - {0}):
+        say(f"[case] tile width gamma={gamma} k={k} flags={flags} N={info['N']} col_lg={c}")
+        plan = pa.Plan(n, r, gamma=gamma, flags=flags, col_lg=c)
+        try:
+            st_g, out = run_gpu(pa, plan, blk)
+        finally:
+            plan.close()
+        assert st_g == st_o == 0
+        assert np.array_equal(out, out_o), c
+
+
+def test_tuned_plans_match(pa):
+    """pa_plan_tune returns an exact shape (explicit B, length form, tile
+    width) whose output equals the oracle's."""
+    for n, r in ((18_802_622, 2_288_514), (5_000_000, 300_000)):
+        st, g, k = defn.plan_shape(n, r)
+        say(f"[case] tune n={n} r={r}")
+        best, ms = pa.plan_tune(n, r, reps=2)
+        assert best["B"] >= 8 and best["flags"] in (1, 2) and best["col_lg"] >= 1 and ms > 0
+        info = pa.plan_query(n, r, B=best["B"], flags=best["flags"], col_lg=best["col_lg"])[1]
+        assert info["k"] * info["L"] * (2 ** info["B"] - 1) ** 2 < math.prod(info["primes"])
+        blk = synth.single_block(77, n, r, g, k)
+        check_block(pa, blk, B=best["B"], flags=best["flags"], stages=False, label="tuned", col_lg=best["col_lg"])
 
 
 def test_config_one_mib_block(pa):
