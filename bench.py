@@ -276,6 +276,7 @@ def bench_batched(args):
     same_t = all(torch.equal(o, x[6]) for o, x in zip(outs_b, bufs))
     bp.close()
     log(f"[bench] batched autotuned ({ntuned} classes, {tune_s:.1f} s): {ms_t:.3f} ms/call")
+    small = batched_small_blocks(pa, synth, dev, K, Wm)
     log(f"[bench] batched {ms_b:.3f} ms/call (wall {wall_b / K * 1e3:.3f}), serial {ms_s:.3f} ms "
         f"(wall {wall_s / K * 1e3:.3f})")
     rec = {
@@ -302,6 +303,7 @@ def bench_batched(args):
         "autotuned": {"value": round(total / (ms_t / 1e3) / 1e6, 1), "unit": "Mbit/s", "ms_per_step": round(ms_t, 4),
                       "classes_tuned": ntuned, "tuning_seconds": round(tune_s, 2), "outputs_equal": same_t,
                       "what": "the same call after pa_batch_plan_tune (one-time device timing per (gamma, k) class)"},
+        "small_blocks": small,
     }
     print(json.dumps(rec), flush=True)
 
@@ -364,6 +366,48 @@ def bench_lengths(args):
            "unit": "Mbit/s", "n_gpus": 1, "steps": K, "warmup": Wm, "higher_is_better": True,
            "data": "synthetic", "blocks": rows}
     print(json.dumps(rec), flush=True)
+
+
+def batched_small_blocks(pa, synth, dev, K, Wm):
+    """64 small blocks (seed 7, n log-uniform in [2^14, 2^18]), where the
+    host's kernel launches, not the GPU, bound a batched call: wall time per
+    call with plain launches and with the captured graph replayed
+    (pa_batch_plan_set_graphs); outputs must agree."""
+    import torch
+
+    def shape(n, r):
+        st, info = pa.plan_query(n, r)
+        assert st == 0, (n, r, st)
+        return info["gamma"], info["k"]
+
+    blocks = synth.uneven_blocks(7, 64, shape, 14, 18)
+    total = sum(b.n for b in blocks)
+    bufs = []
+    for b in blocks:
+        key, a, bb, c = (pa.to_device(x, dev) for x in (b.key, b.a, b.b, b.c))
+        bufs.append([b.n, b.r, key, a, bb, c, pa.BatchPlan.new_out(b.r, dev)])
+    res = {"blocks": len(blocks), "total_bits": total}
+    outs = None
+    with pa.BatchPlan(len(blocks), total) as bp:
+        for label, graphs in (("launches", False), ("graph", True)):
+            bp.set_graphs(graphs)
+            for _ in range(Wm):
+                st, per = bp.hash(bufs)
+                assert st == 0 and all(x == 0 for x in per), per
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(K):
+                bp.hash(bufs)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / K * 1e3
+            cur = [x[6].clone() for x in bufs]
+            if outs is None:
+                outs = cur
+            res[label] = {"wall_ms_per_call": round(ms, 4), "value": round(total / (ms / 1e3) / 1e6, 1),
+                          "unit": "Mbit/s"}
+            log(f"[bench] small blocks ({total} bits) {label}: {ms:.3f} ms/call (wall)")
+        res["outputs_equal"] = all(torch.equal(a, b) for a, b in zip(outs, cur))
+    return res
 
 
 SERVE_SEED, SERVE_SESSIONS, SERVE_RATE = 4, 16, 44.1

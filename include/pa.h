@@ -191,6 +191,19 @@ void pa_batch_plan_destroy(pa_batch_plan *plan);
 pa_status pa_hash_batched(pa_batch_plan *plan, const pa_block *blocks, uint32_t count,
                           pa_status *per_block, hipStream_t stream);
 
+/* Graph replay for repeated batches (enable = 1; 0 turns it off and frees
+ * the graphs).  With it on, pa_hash_batched captures the kernel launches of
+ * a block list (fork to the worker streams, every block's kernels, join) into
+ * a HIP graph the first time it meets that exact list (same descriptors:
+ * shapes and buffer addresses) and replays the graph for later calls with
+ * the same list, which saves the host-side launch cost of small blocks.  At
+ * most 8 lists are kept (least recently used dropped); growing a worker's
+ * scratch arena, building tables for a new length or tuning a class
+ * (pa_batch_plan_tune) makes the kept graphs stale, and they are captured
+ * again when next used.  The results are those of the launches without a
+ * graph; the status copy runs outside the graph. */
+pa_status pa_batch_plan_set_graphs(pa_batch_plan *plan, int enable);
+
 /* ------------------------------------------------------------------------
  * Autotuning.  The limb width B (the 2^B-ary words of Sec. 2.1), the
  * transform length form (2^m or 3 * 2^m) and the column-tile width change

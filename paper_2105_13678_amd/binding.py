@@ -117,6 +117,8 @@ def lib():
         L.pa_batch_plan_tune.argtypes = [_VP, ctypes.POINTER(Block), ctypes.c_uint32, ctypes.c_uint32,
                                          ctypes.POINTER(ctypes.c_uint32)]
         L.pa_batch_plan_tune.restype = ctypes.c_int
+        L.pa_batch_plan_set_graphs.argtypes = [_VP, ctypes.c_int]
+        L.pa_batch_plan_set_graphs.restype = ctypes.c_int
         L.pa_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(_VP)]
         L.pa_server_create.restype = ctypes.c_int
         L.pa_server_destroy.argtypes = [_VP]
@@ -350,6 +352,12 @@ class BatchPlan:
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         st = lib().pa_hash_batched(self._h, arr, len(blocks), per, s.cuda_stream)
         return st, list(per)
+
+    def set_graphs(self, enable: bool = True):
+        """Capture block lists into HIP graphs and replay them (pa_batch_plan_set_graphs)."""
+        st = lib().pa_batch_plan_set_graphs(self._h, 1 if enable else 0)
+        if st != PA_OK:
+            raise PAError(st, "pa_batch_plan_set_graphs")
 
     def tune(self, blocks, reps: int = 5) -> int:
         """Autotune the (gamma, k) classes of blocks (sequence of (n, r, ...);

@@ -7,7 +7,9 @@
 // (longest first, each to the least-loaded stream), forks the workers from
 // the caller's stream, enqueues every block's kernel sequence on its worker,
 // and joins back.  Blocks whose transforms cannot fill the GPU alone (short
-// rows, single-workgroup scan steps) then run side by side.
+// rows, single-workgroup scan steps) then run side by side.  With graphs on,
+// the fork / launches / join of a block list is captured once into a HIP
+// graph and replayed by later calls with the same list.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,6 +38,19 @@ struct Lane {
     size_t bytes = 0;
 };
 
+// A captured block list: replayable while no arena or table it points into
+// has been reallocated (epoch).
+struct Captured {
+    std::vector<pa_block> blocks;
+    uint64_t epoch;
+    hipGraphExec_t exec;
+};
+constexpr size_t kMaxGraphs = 8;
+
+bool same_blocks(const std::vector<pa_block> &v, const pa_block *b, uint32_t count) {
+    return v.size() == count && std::memcmp(v.data(), b, count * sizeof(pa_block)) == 0;
+}
+
 struct DeviceGuard {
     int prev = -1;
     bool ok = false;
@@ -62,11 +77,27 @@ struct pa_batch_plan {
     // tuned shapes (pa_batch_plan_tune): (gamma, k) -> limb width, length
     // form and column-tile width
     std::map<std::pair<uint64_t, uint64_t>, pa_params> tuned;
+    // graph replay (pa_batch_plan_set_graphs)
+    bool graphs_on = false;
+    hipStream_t cap = nullptr;                 // capture / replay origin stream
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    uint64_t epoch = 0;                        // bumped on every arena or table allocation
+    std::vector<Captured> graphs;              // most recently used last
 };
 
 namespace {
 
+void drop_graphs(pa_batch_plan *bp) {
+    for (Captured &c : bp->graphs) (void)hipGraphExecDestroy(c.exec);
+    bp->graphs.clear();
+}
+
 void destroy(pa_batch_plan *bp) {
+    if (bp->cap) (void)hipStreamSynchronize(bp->cap);
+    drop_graphs(bp);
+    if (bp->cap) (void)hipStreamDestroy(bp->cap);
+    if (bp->ev_in) (void)hipEventDestroy(bp->ev_in);
+    if (bp->ev_out) (void)hipEventDestroy(bp->ev_out);
     for (Lane &l : bp->lanes) {
         if (l.st) (void)hipStreamSynchronize(l.st);
         if (l.arena) (void)hipFree(l.arena);
@@ -97,6 +128,7 @@ void *tables_for(pa_batch_plan *bp, pa_plan *p, const pa::PlanLayout &lay, hipSt
         return nullptr;
     }
     bp->tables.push_back(Tables{pa::len_key(*p), base});
+    ++bp->epoch;
     return base;
 }
 
@@ -116,6 +148,9 @@ pa_status pa_batch_plan_create(uint32_t max_blocks, uint64_t max_total_bits, int
     bp->max_blocks = max_blocks;
     bp->max_total_bits = max_total_bits;
     bool ok = hipEventCreateWithFlags(&bp->fork, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&bp->cap, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&bp->ev_in, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&bp->ev_out, hipEventDisableTiming) == hipSuccess;
     for (Lane &l : bp->lanes) {
         ok = ok && hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&l.done, hipEventDisableTiming) == hipSuccess;
@@ -196,14 +231,17 @@ pa_status pa_hash_batched(pa_batch_plan *bp, const pa_block *blocks, uint32_t co
         Lane &ln = bp->lanes[l];
         if (need[l] <= ln.bytes) continue;
         // grow: the arena may still be in use by an earlier call on this worker
+        // (or by a replayed graph, which runs outside the worker streams)
         if (ln.arena) {
-            if (hipStreamSynchronize(ln.st) != hipSuccess || hipFree(ln.arena) != hipSuccess) {
+            if (hipStreamSynchronize(ln.st) != hipSuccess || hipStreamSynchronize(bp->cap) != hipSuccess ||
+                hipFree(ln.arena) != hipSuccess) {
                 (void)hipGetLastError();
                 return PA_ERR_DEVICE;
             }
             ln.arena = nullptr;
             ln.bytes = 0;
         }
+        ++bp->epoch;
         if (hipMalloc(&ln.arena, need[l]) != hipSuccess) {
             (void)hipGetLastError();
             ln.arena = nullptr;
@@ -212,25 +250,77 @@ pa_status pa_hash_batched(pa_batch_plan *bp, const pa_block *blocks, uint32_t co
         ln.bytes = need[l];
     }
 
-    // fork, enqueue, join
-    if (hipEventRecord(bp->fork, stream) != hipSuccess) return PA_ERR_DEVICE;
-    bool used[kLanes] = {};
-    for (uint32_t i : order) used[lane_of[i]] = true;
-    for (int l = 0; l < kLanes; ++l)
-        if (used[l] && hipStreamWaitEvent(bp->lanes[l].st, bp->fork, 0) != hipSuccess) return PA_ERR_DEVICE;
-    for (uint32_t i : order) {
-        const pa_block &bk = blocks[i];
-        Lane &ln = bp->lanes[lane_of[i]];
-        pa::bind_scratch(&plans[i], ln.arena, lays[i]);
-        pa_status s = pa::enqueue_hash(&plans[i], bk.key, bk.a, bk.b, bk.c, bk.out, bp->d_status + i, nullptr,
-                                       nullptr, ln.st);
+    // fork from `origin`, enqueue every block on its worker, join back
+    auto enqueue_all = [&](hipStream_t origin) -> pa_status {
+        if (hipEventRecord(bp->fork, origin) != hipSuccess) return PA_ERR_DEVICE;
+        bool used[kLanes] = {};
+        for (uint32_t i : order) used[lane_of[i]] = true;
+        for (int l = 0; l < kLanes; ++l)
+            if (used[l] && hipStreamWaitEvent(bp->lanes[l].st, bp->fork, 0) != hipSuccess) return PA_ERR_DEVICE;
+        for (uint32_t i : order) {
+            const pa_block &bk = blocks[i];
+            Lane &ln = bp->lanes[lane_of[i]];
+            pa::bind_scratch(&plans[i], ln.arena, lays[i]);
+            pa_status s = pa::enqueue_hash(&plans[i], bk.key, bk.a, bk.b, bk.c, bk.out, bp->d_status + i, nullptr,
+                                           nullptr, ln.st);
+            if (s != PA_OK) return s;
+        }
+        for (int l = 0; l < kLanes; ++l) {
+            if (!used[l]) continue;
+            if (hipEventRecord(bp->lanes[l].done, bp->lanes[l].st) != hipSuccess ||
+                hipStreamWaitEvent(origin, bp->lanes[l].done, 0) != hipSuccess)
+                return PA_ERR_DEVICE;
+        }
+        return PA_OK;
+    };
+    if (!bp->graphs_on) {
+        const pa_status s = enqueue_all(stream);
         if (s != PA_OK) return s;
-    }
-    for (int l = 0; l < kLanes; ++l) {
-        if (!used[l]) continue;
-        if (hipEventRecord(bp->lanes[l].done, bp->lanes[l].st) != hipSuccess ||
-            hipStreamWaitEvent(stream, bp->lanes[l].done, 0) != hipSuccess)
+    } else {
+        // replay the captured list, or capture it now (tables and arenas are
+        // in place, so nothing below allocates); `cap` runs after `stream`'s
+        // earlier work and `stream` continues after the graph
+        hipGraphExec_t exec = nullptr;
+        for (size_t g = 0; g < bp->graphs.size(); ++g) {
+            if (bp->graphs[g].epoch == bp->epoch && same_blocks(bp->graphs[g].blocks, blocks, count)) {
+                Captured c = bp->graphs[g];
+                bp->graphs.erase(bp->graphs.begin() + (long)g);
+                bp->graphs.push_back(c);
+                exec = c.exec;
+                break;
+            }
+        }
+        if (hipEventRecord(bp->ev_in, stream) != hipSuccess || hipStreamWaitEvent(bp->cap, bp->ev_in, 0) != hipSuccess)
             return PA_ERR_DEVICE;
+        if (!exec) {
+            hipGraph_t graph = nullptr;
+            if (hipStreamBeginCapture(bp->cap, hipStreamCaptureModeRelaxed) != hipSuccess) return PA_ERR_DEVICE;
+            const pa_status s = enqueue_all(bp->cap);
+            const hipError_t e = hipStreamEndCapture(bp->cap, &graph);
+            if (s != PA_OK || e != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                (void)hipGetLastError();
+                return s != PA_OK ? s : PA_ERR_DEVICE;
+            }
+            const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ei != hipSuccess) {
+                (void)hipGetLastError();
+                return PA_ERR_DEVICE;
+            }
+            if (bp->graphs.size() >= kMaxGraphs) {
+                // the evicted graph may still run: wait for the plan's work first
+                if (hipStreamSynchronize(bp->cap) != hipSuccess) return PA_ERR_DEVICE;
+                (void)hipGraphExecDestroy(bp->graphs.front().exec);
+                bp->graphs.erase(bp->graphs.begin());
+            }
+            bp->graphs.push_back(Captured{std::vector<pa_block>(blocks, blocks + count), bp->epoch, exec});
+        }
+        if (hipGraphLaunch(exec, bp->cap) != hipSuccess || hipEventRecord(bp->ev_out, bp->cap) != hipSuccess ||
+            hipStreamWaitEvent(stream, bp->ev_out, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            return PA_ERR_DEVICE;
+        }
     }
     if (hipMemcpyAsync(bp->h_status, bp->d_status, (size_t)count * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess) {
@@ -238,6 +328,18 @@ pa_status pa_hash_batched(pa_batch_plan *bp, const pa_block *blocks, uint32_t co
         return PA_ERR_DEVICE;
     }
     for (uint32_t i : order) per_block[i] = pa_decode_status(bp->h_status[i]);
+    return PA_OK;
+}
+
+pa_status pa_batch_plan_set_graphs(pa_batch_plan *bp, int enable) {
+    if (!bp) return PA_ERR_ARG;
+    DeviceGuard guard(bp->device);
+    if (!guard.ok) return PA_ERR_DEVICE;
+    if (!enable) {
+        if (hipStreamSynchronize(bp->cap) != hipSuccess) return PA_ERR_DEVICE;
+        drop_graphs(bp);
+    }
+    bp->graphs_on = enable != 0;
     return PA_OK;
 }
 
@@ -256,6 +358,7 @@ pa_status pa_batch_plan_tune(pa_batch_plan *bp, const pa_block *blocks, uint32_t
         const pa_status st = pa_plan_tune(&prm, bp->device, reps, &best, nullptr);
         if (st != PA_OK) return st;
         bp->tuned[key] = best;
+        ++bp->epoch;  // captured graphs of this class's blocks are stale
         if (tuned) ++*tuned;
     }
     return PA_OK;

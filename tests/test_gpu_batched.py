@@ -125,3 +125,53 @@ def test_batched_tuned_equals_untuned(pa):
         assert st == 0 and all(x == 0 for x in per), per
         for o, d in zip(outs, dev):
             assert torch.equal(o, d[6])
+
+
+def test_batched_graph_replay(pa):
+    """With graphs on, repeated calls replay the captured launches: every
+    replay (with unrelated eager work and output clearing in between) gives
+    the eager result; new key contents in the same buffers are read by the
+    replay (checked against the oracle); a different block list (another
+    output buffer) is captured anew; turning graphs off returns to plain
+    launches."""
+    import torch
+    blocks = synth.uneven_blocks(51, 12, _shape, 14, 20)
+    say("[case] batched graph replay:", [(b.n, b.r, b.gamma, b.k) for b in blocks])
+    dev = [_dev(pa, b) for b in blocks]
+    with pa.BatchPlan(16, 1 << 30) as bp:
+        st, per = bp.hash(dev)
+        assert st == 0 and all(x == 0 for x in per), per
+        ref = [d[6].clone() for d in dev]
+        bp.set_graphs(True)
+        for rep in range(4):
+            for d in dev:
+                d[6].zero_()
+            junk = torch.arange(1 << 20, device="cuda", dtype=torch.int64).sum()
+            torch.cuda.synchronize()
+            assert int(junk) == (1 << 20) * ((1 << 20) - 1) // 2
+            st, per = bp.hash(dev)
+            assert st == 0 and all(x == 0 for x in per), (rep, per)
+            for i, (o, d) in enumerate(zip(ref, dev)):
+                assert torch.equal(o, d[6]), (rep, i)
+        # new key bits in block 0's buffer, same list: the replay reads them
+        b0 = blocks[0]
+        key2 = synth.SplitMix64(999).words(len(b0.key))
+        if b0.n % 64:
+            key2[-1] &= np.uint64((1 << (b0.n % 64)) - 1)
+        dev[0][2].copy_(pa.to_device(key2))
+        st, per = bp.hash(dev)
+        st_o, out_o = oracle.hash(key2, b0.n, b0.r, b0.gamma, b0.a, b0.b, b0.c)
+        assert st == 0 and per[0] == st_o == 0
+        assert np.array_equal(pa.from_device(dev[0][6]), out_o)
+        # a different list (block 1 writes elsewhere) is captured anew
+        alt = pa.BatchPlan.new_out(blocks[1].r, dev[1][6].device)
+        dev2 = list(dev)
+        dev2[1] = dev[1][:6] + (alt,)
+        st, per = bp.hash(dev2)
+        assert st == 0 and torch.equal(alt, ref[1])
+        bp.set_graphs(False)
+        for d in dev:
+            d[6].zero_()
+        dev[0][2].copy_(pa.to_device(b0.key))
+        st, per = bp.hash(dev)
+        assert st == 0 and all(torch.equal(o, d[6]) for o, d in zip(ref, dev))
