@@ -327,14 +327,18 @@ __device__ __forceinline__ void col_last_fwd(const uint32_t *buf, uint32_t lg, u
 // of the twiddle (n = r N2 + c) is applied here; the column part
 // omega_N^(k0 c) rides on the four-step twiddle of the row pass.
 // The last step writes its rows straight to global memory.
-template <int Stage, bool MIX, int TPT>
+// LG, CLG (nonzero): the column length 2^m1 and tile width 2^c_lg fixed at
+// compile time for the common tile shapes (shifts, masks and swizzles fold
+// into constants; the tile lives in static LDS).
+template <int Stage, bool MIX, int TPT, int LG = 0, int CLG = 0>
 __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
     constexpr uint32_t NSUB = MIX ? 3u : 1u;
     constexpr int XR = MIX ? 8 : 4;  // first-step rows of a task that hold x_n
-    uint32_t *lds = lds_dyn;
+    __shared__ uint32_t Lt[LG && CLG ? 1u << (LG + CLG) : 1u];
+    uint32_t *lds = LG && CLG ? Lt : lds_dyn;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t arr = blockIdx.y + A.arr0;
-    const uint32_t c_lg = A.c_lg, lg = A.m1;
+    const uint32_t c_lg = CLG ? (uint32_t)CLG : A.c_lg, lg = LG ? (uint32_t)LG : A.m1;
     const uint32_t cmask = (1u << c_lg) - 1;
     const uint64_t c0 = (uint64_t)tile << c_lg;
     const bool is_key = (A.mode == 0) && arr < A.k;
@@ -1517,6 +1521,19 @@ static void launch_col_fwd_generic(pa_plan *p, const ColFwdArgs &cf, unsigned na
     const dim3 grid(1u << (p->m2 - cf.c_lg), narrays, 1);
     const size_t col_lds = ((size_t)4 << p->m1) << cf.c_lg;
     const uint32_t ntask = (1u << (p->m1 - 3)) << cf.c_lg;
+    // common tile shapes (2^m1 rows x 2^c_lg columns) with compile-time sizes
+#define PA_COL_FIXED(LGv, CLGv)                                                                              \
+    if (p->m1 == LGv && cf.c_lg == CLGv) {                                                                   \
+        constexpr int T = (1 << (LGv - 3 + CLGv)) <= COL_THREADS ? 1 : (1 << (LGv - 3 + CLGv)) / COL_THREADS; \
+        hipLaunchKernelGGL((k_col_fwd<Stage, MIX, T, LGv, CLGv>), grid, dim3(COL_THREADS), 0, st, cf);        \
+        return;                                                                                              \
+    }
+    PA_COL_FIXED(3, 4) PA_COL_FIXED(3, 7) PA_COL_FIXED(3, 8)
+    PA_COL_FIXED(4, 4) PA_COL_FIXED(4, 6) PA_COL_FIXED(4, 7)
+    PA_COL_FIXED(5, 4) PA_COL_FIXED(5, 6)
+    PA_COL_FIXED(6, 4) PA_COL_FIXED(6, 5)
+    PA_COL_FIXED(7, 4) PA_COL_FIXED(8, 4) PA_COL_FIXED(10, 4)
+#undef PA_COL_FIXED
     if (ntask <= COL_THREADS)
         hipLaunchKernelGGL((k_col_fwd<Stage, MIX, 1>), grid, dim3(COL_THREADS), col_lds, st, cf);
     else if (ntask <= 2 * COL_THREADS)
