@@ -294,7 +294,7 @@ __device__ __forceinline__ uint32_t limb_at(const LimbSrc &S, uint32_t j) {
 // radix R at sub-length R; slot s of block b is row b*R + s.
 template <int R>
 __device__ __forceinline__ void col_last_fwd(const uint32_t *buf, uint32_t lg, uint32_t c_lg, uint32_t m2,
-                                             uint64_t c0, uint32_t *__restrict__ out, const PrimeConst &M,
+                                             uint64_t c0, __amdgpu_buffer_rsrc_t out, const PrimeConst &M,
                                              uint32_t tid, uint32_t nt) {
     constexpr int LR = Lg<R>::v;
     const uint32_t cmask = (1u << c_lg) - 1;
@@ -306,8 +306,9 @@ __device__ __forceinline__ void col_last_fwd(const uint32_t *buf, uint32_t lg, u
 #pragma unroll
         for (int j = 0; j < R; ++j) v[j] = buf[tile_swz(((row0 + j) << c_lg) + q, c_lg)];
         dft_fwd<R>(v, M);
+        const uint32_t vo = ((row0 << m2) + (uint32_t)c0 + q) << 2;
 #pragma unroll
-        for (int j = 0; j < R; ++j) out[((uint64_t)(row0 + j) << m2) + c0 + q] = v[j];
+        for (int j = 0; j < R; ++j) bstore(v[j], out, vo, ((uint32_t)j << m2) << 2);
     }
 }
 
@@ -380,6 +381,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
         const PrimeConst M = A.P.c[pq];
         const uint32_t *tw = A.tw + ((uint64_t)pq << lg);
         uint32_t *out = A.X + ((uint64_t)blockIdx.y * NPRIMES + pq) * A.N + (uint64_t)k0 * Ns;
+        const __amdgpu_buffer_rsrc_t ro = rsrc_of(out, Ns);  // this transform's Nsub words
         const uint32_t *g0 = nullptr, *g1 = nullptr;  // radix-3 row twiddles of transform k0 (k_tw_g3)
         if constexpr (MIX) {
             g0 = A.g3 + (((size_t)pq * 3 + k0) << lg);
@@ -423,11 +425,11 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
         fwd_middle_steps(lds, lg, lg - 3, c_lg, tw, M, tl, COL_THREADS);
         const uint32_t ll = last_lgM(lg);
         if (ll == 3)
-            col_last_fwd<8>(lds, lg, c_lg, A.m2, c0, out, M, tl, COL_THREADS);
+            col_last_fwd<8>(lds, lg, c_lg, A.m2, c0, ro, M, tl, COL_THREADS);
         else if (ll == 2)
-            col_last_fwd<4>(lds, lg, c_lg, A.m2, c0, out, M, tl, COL_THREADS);
+            col_last_fwd<4>(lds, lg, c_lg, A.m2, c0, ro, M, tl, COL_THREADS);
         else
-            col_last_fwd<2>(lds, lg, c_lg, A.m2, c0, out, M, tl, COL_THREADS);
+            col_last_fwd<2>(lds, lg, c_lg, A.m2, c0, ro, M, tl, COL_THREADS);
     }
 }
 
@@ -497,6 +499,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
         const PrimeConst M = A.P.c[pq];
         const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.tw + ((uint64_t)pq << C9_LG), 1u << C9_LG);
         uint32_t *out = A.X + ((uint64_t)blockIdx.y * NPRIMES + pq) * A.N + (uint64_t)k0 * Ns;
+        const __amdgpu_buffer_rsrc_t ro = rsrc_of(out, Ns);  // this transform's Nsub words
         // radix-3 row twiddles of transform k0 (tables g0, g1 of k_tw_g3)
         __amdgpu_buffer_rsrc_t rg0 = rtw, rg1 = rtw;
         if constexpr (MIX) {
@@ -558,9 +561,10 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) v[j] = lds_word(L9, (sb ^ (16u * j)) << 2);
             dft_fwd<8>(v, M);
-            uint32_t *o = out + ((uint64_t)(8u * b) << A.m2) + c0 + q;
+            // buffer stores: lane offset plus a uniform row offset (no 64-bit address math)
+            const uint32_t vo = (((8u * b) << A.m2) + (uint32_t)c0 + q) << 2;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) o[(uint64_t)j << A.m2] = v[j];
+            for (int j = 0; j < 8; ++j) bstore(v[j], ro, vo, ((uint32_t)j << A.m2) << 2);
         }
     }
 }
@@ -1011,17 +1015,19 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_inv(ColInvArgs A) {
     const uint32_t pq = blockIdx.y;
     const PrimeConst M = A.P.c[pq];
     const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.twi + ((uint64_t)pq << C9_LG), 1u << C9_LG);
-    uint32_t *cc = A.Cc + pq * A.N + blockIdx.z * A.Nsub;
-    const uint64_t c0 = (uint64_t)xcd_tile(blockIdx.x, gridDim.x) << C9_CLG;
+    // this transform's Nsub words, through a buffer resource: lane offset plus
+    // a uniform row offset per access
+    const __amdgpu_buffer_rsrc_t rc = rsrc_of(A.Cc + pq * A.N + blockIdx.z * A.Nsub, (uint32_t)A.Nsub);
+    const uint32_t c0 = xcd_tile(blockIdx.x, gridDim.x) << C9_CLG;
     const uint32_t t = threadIdx.x;
 #pragma unroll 1
     for (uint32_t u = 0; u < 4; ++u) {  // sub-length 8: rows 8 b + j
         const uint32_t tau = t + 256u * u;
         const uint32_t q = tau & 15u, b = tau >> 4;
-        const uint32_t *src = cc + ((uint64_t)(8u * b) << A.m2) + c0 + q;
+        const uint32_t vo = (((8u * b) << A.m2) + c0 + q) << 2;
         uint32_t v[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = src[(uint64_t)j << A.m2];
+        for (int j = 0; j < 8; ++j) v[j] = bload(rc, vo, ((uint32_t)j << A.m2) << 2);
         dft_inv<8>(v, M);
         const uint32_t sb = swz_c9(128u * b + q);
 #pragma unroll
@@ -1054,10 +1060,10 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_inv(ColInvArgs A) {
 #pragma unroll
         for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 2, 0);
         dft_inv_tw<8>(v, w, M);
-        uint32_t *dst = cc + ((uint64_t)n1 << A.m2) + c0 + q;
+        const uint32_t vo = ((n1 << A.m2) + c0 + q) << 2;
         // canonical residues for the Chinese-remainder step
 #pragma unroll
-        for (int j = 0; j < 8; ++j) dst[(uint64_t)(64u * j) << A.m2] = canon(red2(v[j], M), M);
+        for (int j = 0; j < 8; ++j) bstore(canon(red2(v[j], M), M), rc, vo, ((64u * j) << A.m2) << 2);
     }
 }
 
