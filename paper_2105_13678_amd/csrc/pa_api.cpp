@@ -25,18 +25,6 @@ constexpr uint64_t kMaxK = 4096;
 constexpr uint32_t kMinLog2N = 6;
 constexpr uint32_t kMaxLdsLog2 = 14;  // 2^14 words = 64 KiB of LDS per tile
 
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) return;
-        ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 pa_status plan_shape(const pa_params *prm, uint64_t *gamma, uint64_t *k, uint32_t *B) {
@@ -350,7 +338,7 @@ pa_status pa_plan_create(const pa_params *prm, int hip_device, pa_plan **out) {
     }
     p->device = hip_device;
 
-    DeviceGuard guard(hip_device);
+    pa::DeviceGuard guard(hip_device);
     if (!guard.ok) {
         delete p;
         return PA_ERR_DEVICE;
@@ -408,7 +396,7 @@ pa_status pa_plan_get_info(const pa_plan *p, pa_plan_info *info) {
 
 void pa_plan_destroy(pa_plan *p) {
     if (!p) return;
-    DeviceGuard guard(p->device);
+    pa::DeviceGuard guard(p->device);
     (void)hipDeviceSynchronize();
     if (p->pending) {
         for (auto &e : *p->pending) {
@@ -443,7 +431,7 @@ pa_status pa_plan_read_profile(pa_plan *p, double *ms, uint64_t *calls) {
         calls[i] = 0;
     }
     if (!p->pending) return PA_OK;
-    DeviceGuard guard(p->device);
+    pa::DeviceGuard guard(p->device);
     pa_status st = PA_OK;
     for (auto &e : *p->pending) {
         float t = 0.f;
@@ -473,7 +461,7 @@ static pa_status wait_status(pa_plan *p, hipStream_t st) {
 pa_status pa_hash(pa_plan *p, const uint64_t *key, const uint64_t *a, const uint64_t *b, const uint64_t *c,
                   uint64_t *out, hipStream_t st) {
     if (!p) return PA_ERR_ARG;
-    DeviceGuard guard(p->device);
+    pa::DeviceGuard guard(p->device);
     if (!guard.ok) return PA_ERR_DEVICE;
     pa_status s = pa::enqueue_hash(p, key, a, b, c, out, nullptr, nullptr, nullptr, st);
     if (s != PA_OK) return s;
@@ -483,7 +471,7 @@ pa_status pa_hash(pa_plan *p, const uint64_t *key, const uint64_t *a, const uint
 pa_status pa_hash_async(pa_plan *p, const uint64_t *key, const uint64_t *a, const uint64_t *b,
                         const uint64_t *c, uint64_t *out, uint32_t *d_status, hipStream_t st) {
     if (!p || !d_status) return PA_ERR_ARG;
-    DeviceGuard guard(p->device);
+    pa::DeviceGuard guard(p->device);
     if (!guard.ok) return PA_ERR_DEVICE;
     return pa::enqueue_hash(p, key, a, b, c, out, d_status, nullptr, nullptr, st);
 }
@@ -492,7 +480,7 @@ pa_status pa_hash_stages(pa_plan *p, const uint64_t *key, const uint64_t *a, con
                          const uint64_t *c, uint64_t *out, uint64_t *y_out, uint64_t *U_out,
                          hipStream_t st) {
     if (!p || !y_out || !U_out) return PA_ERR_ARG;
-    DeviceGuard guard(p->device);
+    pa::DeviceGuard guard(p->device);
     if (!guard.ok) return PA_ERR_DEVICE;
     pa_status s = pa::enqueue_hash(p, key, a, b, c, out, nullptr, y_out, U_out, st);
     if (s != PA_OK) return s;

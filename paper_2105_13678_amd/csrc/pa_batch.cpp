@@ -51,18 +51,6 @@ bool same_blocks(const std::vector<pa_block> &v, const pa_block *b, uint32_t cou
     return v.size() == count && std::memcmp(v.data(), b, count * sizeof(pa_block)) == 0;
 }
 
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) return;
-        ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
 }  // namespace
 
 struct pa_batch_plan {
@@ -140,7 +128,7 @@ pa_status pa_batch_plan_create(uint32_t max_blocks, uint64_t max_total_bits, int
                                pa_batch_plan **out) {
     if (!out || max_blocks == 0 || max_total_bits == 0) return PA_ERR_ARG;
     *out = nullptr;
-    DeviceGuard guard(hip_device);
+    pa::DeviceGuard guard(hip_device);
     if (!guard.ok) return PA_ERR_DEVICE;
     pa_batch_plan *bp = new (std::nothrow) pa_batch_plan();
     if (!bp) return PA_ERR_NOMEM;
@@ -167,7 +155,7 @@ pa_status pa_batch_plan_create(uint32_t max_blocks, uint64_t max_total_bits, int
 
 void pa_batch_plan_destroy(pa_batch_plan *bp) {
     if (!bp) return;
-    DeviceGuard guard(bp->device);
+    pa::DeviceGuard guard(bp->device);
     destroy(bp);
 }
 
@@ -178,7 +166,7 @@ pa_status pa_hash_batched(pa_batch_plan *bp, const pa_block *blocks, uint32_t co
     uint64_t total = 0;
     for (uint32_t i = 0; i < count; ++i) total += blocks[i].n;
     if (total > bp->max_total_bits) return PA_ERR_LIMIT;
-    DeviceGuard guard(bp->device);
+    pa::DeviceGuard guard(bp->device);
     if (!guard.ok) return PA_ERR_DEVICE;
 
     // host side: derive every block's plan; host-detectable errors end there
@@ -333,7 +321,7 @@ pa_status pa_hash_batched(pa_batch_plan *bp, const pa_block *blocks, uint32_t co
 
 pa_status pa_batch_plan_set_graphs(pa_batch_plan *bp, int enable) {
     if (!bp) return PA_ERR_ARG;
-    DeviceGuard guard(bp->device);
+    pa::DeviceGuard guard(bp->device);
     if (!guard.ok) return PA_ERR_DEVICE;
     if (!enable) {
         if (hipStreamSynchronize(bp->cap) != hipSuccess) return PA_ERR_DEVICE;

@@ -169,6 +169,22 @@ struct PlanLayout {
     size_t scratch_bytes, table_bytes, total;
 };
 
+// Makes `dev` the current HIP device for a scope and restores the previous
+// one on exit (the entry points may be called with another device current).
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) return;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+    DeviceGuard(const DeviceGuard &) = delete;
+    DeviceGuard &operator=(const DeviceGuard &) = delete;
+};
+
 // Identifies a plan's transform length (and so its primes and twiddle tables).
 inline uint32_t len_key(const pa_plan &p) { return p.mix << 7 | p.m; }
 

@@ -266,18 +266,6 @@ void worker_main(pa_server *s) {
     }
 }
 
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) return;
-        ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
 void release(pa_server *s) {
     for (Slot &sl : s->slots) {
         if (sl.st) (void)hipStreamSynchronize(sl.st);
@@ -304,7 +292,7 @@ pa_status pa_server_create(const pa_server_cfg *cfg, pa_server **out) {
     if (!cfg || !out || cfg->max_inflight == 0 || cfg->max_inflight > 64 || cfg->hbm_budget_bytes == 0)
         return PA_ERR_ARG;
     *out = nullptr;
-    DeviceGuard guard(cfg->device);
+    pa::DeviceGuard guard(cfg->device);
     if (!guard.ok) return PA_ERR_DEVICE;
     pa_server *s = new (std::nothrow) pa_server();
     if (!s) return PA_ERR_NOMEM;
@@ -344,7 +332,7 @@ void pa_server_destroy(pa_server *s) {
     }
     s->cv.notify_all();
     if (s->worker.joinable()) s->worker.join();
-    DeviceGuard guard(s->cfg.device);
+    pa::DeviceGuard guard(s->cfg.device);
     release(s);
 }
 
@@ -358,7 +346,7 @@ pa_status pa_server_set_seeds(pa_server *s, uint32_t session, uint64_t gamma, ui
     pa_status st = pa::derive_plan(&prm, &tmp, &lay);
     if (st != PA_OK && st != PA_ERR_INEXACT && st != PA_ERR_LIMIT) return st;
     const uint64_t W = (gamma + 63) / 64;
-    DeviceGuard guard(s->cfg.device);
+    pa::DeviceGuard guard(s->cfg.device);
     if (!guard.ok) return PA_ERR_DEVICE;
     const size_t words = (size_t)(kmax + 2) * W;
     uint64_t *d = nullptr;

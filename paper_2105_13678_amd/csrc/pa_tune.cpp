@@ -12,18 +12,6 @@
 
 namespace {
 
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) return;
-        ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
 // Device buffers of one synthetic block: all-zero key and seeds except an
 // odd b (valid inputs; the kernels' work does not depend on the values).
 struct Inputs {
@@ -93,7 +81,7 @@ pa_status pa_plan_tune(const pa_params *params, int hip_device, uint32_t reps, p
     }
     if (cands.empty()) return PA_ERR_INEXACT;
 
-    DeviceGuard guard(hip_device);
+    pa::DeviceGuard guard(hip_device);
     if (!guard.ok) return PA_ERR_DEVICE;
     Inputs in(base);
     if (!in.ok) return PA_ERR_NOMEM;
