@@ -152,17 +152,29 @@ __global__ void k_tw_pow(uint32_t *dst, uint64_t count, TwArgs A) {
 // i.e. the four-step twiddle omega_{N/sub}^(k1*n2) times the column part
 // omega_N^(k0*n2) of the radix-3 twiddle omega_N^(k0*n); both scaled as given
 // in the arguments (Montgomery form and 1/N folded in).
+// Each thread writes TW4_RUN consecutive n2 of one row (2^m2 >= 8): the
+// first power directly, the rest as successive products.
+constexpr uint32_t TW4_RUN = 8;
+
 __global__ void k_tw_four(uint32_t *Wf, uint32_t *Wi, uint32_t m1, uint32_t m2, uint32_t sub, TwArgs F, TwArgs I) {
     const uint32_t q = blockIdx.y;
     const uint64_t N = (uint64_t)sub << (m1 + m2);
-    const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= N) return;
-    const uint32_t rho = (uint32_t)(idx >> m2);
-    const uint32_t n2 = (uint32_t)(idx & ((1u << m2) - 1));
+    const uint64_t idx0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * TW4_RUN;
+    if (idx0 >= N) return;
+    const uint32_t rho = (uint32_t)(idx0 >> m2);
+    const uint32_t n2 = (uint32_t)(idx0 & ((1u << m2) - 1));
     const uint32_t k0 = rho >> m1, r = rho & ((1u << m1) - 1);
-    const uint64_t e = ((uint64_t)sub * bitrev(r, m1) + k0) * n2;
-    Wf[q * N + idx] = mulmod_slow(F.scale[q], powmod_slow(F.base[q], e, F.p[q]), F.p[q]);
-    Wi[q * N + idx] = mulmod_slow(I.scale[q], powmod_slow(I.base[q], e, I.p[q]), I.p[q]);
+    const uint64_t g = (uint64_t)sub * bitrev(r, m1) + k0;  // row exponent: entry n2 is omega^(g n2)
+    const uint32_t pf = F.p[q], pi = I.p[q];
+    const uint32_t sf = powmod_slow(F.base[q], g, pf), si = powmod_slow(I.base[q], g, pi);
+    uint32_t cf = mulmod_slow(F.scale[q], powmod_slow(sf, n2, pf), pf);
+    uint32_t ci = mulmod_slow(I.scale[q], powmod_slow(si, n2, pi), pi);
+    for (uint32_t j = 0; j < TW4_RUN; ++j) {
+        Wf[q * N + idx0 + j] = cf;
+        Wi[q * N + idx0 + j] = ci;
+        cf = mulmod_slow(cf, sf, pf);
+        ci = mulmod_slow(ci, si, pi);
+    }
 }
 
 // Row parts of the radix-3 twiddles of the lengths N = 3 * 2^m (m = m1 + m2),
@@ -1471,8 +1483,8 @@ hipError_t launch_twiddles(pa_plan *p, hipStream_t st) {
     hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(n1, 256), NPRIMES), dim3(256), 0, st, p->tw1i, n1, t1i);
     hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(n2, 256), NPRIMES), dim3(256), 0, st, p->tw2f, n2, t2f);
     hipLaunchKernelGGL(k_tw_pow, dim3(blocks_for(n2, 256), NPRIMES), dim3(256), 0, st, p->tw2i, n2, t2i);
-    hipLaunchKernelGGL(k_tw_four, dim3(blocks_for(N, 256), NPRIMES), dim3(256), 0, st, p->Wf, p->Wi, p->m1, p->m2,
-                       sub, Ff, Fi);
+    hipLaunchKernelGGL(k_tw_four, dim3(blocks_for(N / TW4_RUN, 256), NPRIMES), dim3(256), 0, st, p->Wf, p->Wi,
+                       p->m1, p->m2, sub, Ff, Fi);
     if (p->mix)
         hipLaunchKernelGGL(k_tw_g3, dim3(blocks_for(3 * n1, 256), NPRIMES), dim3(256), 0, st, p->G3, p->m1, p->m2,
                            Ff, Gi);
