@@ -103,6 +103,37 @@ def pipelined(pa, plan0, key, a, b, c, K, S, dev, gold_digest):
             "verified_vs_oracle_digest": (digests == {gold_digest}) if gold_digest else None}
 
 
+def small_block(pa, synth, dev, K):
+    """The small single block (n = 2^20, r = n/10, splitmix64 seed 1): K
+    back-to-back hashes on one stream, checked against the oracle's stored
+    digest.  Latency-bound: its transforms cannot fill the GPU."""
+    import torch
+    n, r = 1 << 20, (1 << 20) // 10
+    st, info = pa.plan_query(n, r)
+    blk = synth.single_block(1, n, r, info["gamma"], info["k"])
+    key, a, b, c = (pa.to_device(x, dev) for x in (blk.key, blk.a, blk.b, blk.c))
+    plan = pa.Plan(n, r, device=0)
+    out = plan.new_out()
+    ds = torch.zeros(K + 3, dtype=torch.int32, device=dev)
+    for i in range(3):
+        plan.hash_async(key, a, b, c, out, ds[i:i + 1])
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(K):
+        plan.hash_async(key, a, b, c, out, ds[3 + i:4 + i])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / K * 1e3
+    assert (ds.cpu().numpy() == 0).all()
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "full_size.json")))["single_block_2p20"]
+    ok = hashlib.sha256(pa.from_device(out).tobytes()).hexdigest() == gold["out_sha256"]
+    plan.close()
+    return {"us_per_block": round(us, 1), "value": round(n / (us / 1e6) / 1e6, 1), "unit": "Mbit/s",
+            "N": info["N"], "verified_vs_oracle_digest": ok}
+
+
 def kernel_name(phase, info):
     """Symbol (as profilers print it) of the kernel a transform phase launches."""
     stage = 0 if phase.startswith("mmh") else 1
@@ -655,6 +686,8 @@ def main():
         rec.update(step_stats(plan, key, a, b, c, out, K, dev))
     if args.pipeline > 1 and not args.core_only:
         rec["pipelined"] = pipelined(pa, plan, key, a, b, c, K, args.pipeline, dev, gold_digest=gold_digest)
+    if not args.core_only:
+        rec["small_block_2p20"] = small_block(pa, synth, dev, K)
     if args.calib_copy_mib:
         src = torch.ones(args.calib_copy_mib << 17, dtype=torch.int64, device=dev)
         dst = torch.empty_like(src)

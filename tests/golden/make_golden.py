@@ -6,8 +6,8 @@ digests of the outputs:
 
     python tests/golden/make_golden.py [--check-defn] [case ...]
 
-Cases (splitmix64 seed, n, r): the 2.6e8-bit single block (seed 2,
-r = n/10), the paper-shaped CV block n = 10 * 25,964,951 with compression
+Cases (splitmix64 seed, n, r): the 2^20-bit single block (seed 1, r = n/10),
+the 2.6e8-bit single block (seed 2, r = n/10), the paper-shaped CV block n = 10 * 25,964,951 with compression
 ratio 0.0972 (Table 3; seed 6), one chunk of the largest Mersenne exponent
 (gamma = 136,279,841, r = 2^27, seed 7), whose products need the longest
 transform (2^24 points), and single chunks of gamma = 37,156,667 and
@@ -34,6 +34,7 @@ from oracle import defn  # noqa: E402
 from paper_2105_13678_amd import synth  # noqa: E402
 
 CASES = {
+    "single_block_2p20": dict(seed=1, n=1 << 20, r=(1 << 20) // 10),
     "single_block_2p6e8": dict(seed=2, n=260_000_000, r=26_000_000),
     "paper_cv_block": dict(seed=6, n=10 * 25964951, r=int(math.floor(0.0972 * 10 * 25964951))),
     "max_length_single_chunk": dict(seed=7, n=136279841 - 1, r=1 << 27),

@@ -366,8 +366,8 @@ def _digest(words):
 
 
 @pytest.mark.parametrize("flags", [0, 1])
-@pytest.mark.parametrize("name", ["single_block_2p6e8", "paper_cv_block", "max_length_single_chunk",
-                                  "len_2p22_single_chunk", "len_2p23_single_chunk"])
+@pytest.mark.parametrize("name", ["single_block_2p20", "single_block_2p6e8", "paper_cv_block",
+                                  "max_length_single_chunk", "len_2p22_single_chunk", "len_2p23_single_chunk"])
 def test_full_size_blocks_against_stored_oracle_digest(pa, name, flags):
     """Full-size blocks, in the launch configuration the benchmark times,
     against digests written by tests/golden/make_golden.py (oracle only);
