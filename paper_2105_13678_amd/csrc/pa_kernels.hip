@@ -589,6 +589,7 @@ struct RowArgs {
     uint32_t *out;
     const uint32_t *Wf, *Wi, *twf, *twi;  // per prime: four-step twiddles; omega_{N2}^+-e, e < N2
     const uint32_t *r16f, *r16i;          // per prime: step twiddles of k_row16 in thread order
+    uint32_t row_group;                   // k_row: threads per pair group
     PrimeSet P;
 };
 
@@ -649,7 +650,11 @@ __device__ __forceinline__ void row_last_inv_step(const uint32_t *buf, uint32_t 
 // Row pass: for each pair (x_i, a_i): four-step twiddle and forward transform
 // of both rows, accumulate their pointwise (Montgomery) product; then the
 // inverse transform of the accumulated row, inverse twiddle, store.
-// blockIdx.y is the prime.
+// blockIdx.y is the prime.  Short rows need fewer threads than a wave: the
+// workgroup then runs G groups of A.row_group threads, group g taking the
+// pairs i = g (mod G) with its own LDS row, and the groups' sums are added
+// before the inverse transform (all threads pass the same barriers: a group
+// without a pair in a round transforms a stand-in pair and discards it).
 template <int Stage>
 __global__ __launch_bounds__(ROW_MAX_THREADS) void k_row(RowArgs A) {
     uint32_t *lds = lds_dyn;
@@ -658,6 +663,9 @@ __global__ __launch_bounds__(ROW_MAX_THREADS) void k_row(RowArgs A) {
     const uint32_t lg = A.m2;
     const uint32_t N2 = 1u << lg;
     const uint32_t T = blockDim.x;
+    const uint32_t Tg = A.row_group, G = T / Tg;  // blockDim.x = G * Tg, Tg * ROW_EPT >= N2
+    const uint32_t g = threadIdx.x / Tg, tg = threadIdx.x - g * Tg;
+    uint32_t *buf = lds + g * N2;
     const uint32_t rho = xcd_tile(blockIdx.x, gridDim.x);
     const uint64_t rbase = (uint64_t)rho << lg;
     const uint32_t *wf = A.Wf + pq * A.N + rbase;
@@ -669,32 +677,47 @@ __global__ __launch_bounds__(ROW_MAX_THREADS) void k_row(RowArgs A) {
         acc[q] = 0u;
         xr[q] = 0u;
     }
-    for (uint64_t i = 0; i < A.npairs; ++i) {
+    for (uint64_t i0 = 0; i0 < A.npairs; i0 += G) {
+        const bool active = i0 + g < A.npairs;
+        const uint64_t i = active ? i0 + g : A.npairs - 1;
         const uint32_t *xrow = A.X + i * A.pair_stride + pq * A.N + rbase;
         const uint32_t *arow = A.A + i * A.pair_stride + pq * A.N + rbase;
-        row_first_step(xrow, wf, lds, lg, twf, M, threadIdx.x, T);
-        fwd_steps_from(lds, lg, lg - 3, 0, twf, M, threadIdx.x, T);
+        row_first_step(xrow, wf, buf, lg, twf, M, tg, Tg);
+        fwd_steps_from(buf, lg, lg - 3, 0, twf, M, tg, Tg);
 #pragma unroll
         for (int q = 0; q < ROW_EPT; ++q) {
-            uint32_t e = threadIdx.x + q * T;
-            if (e < N2) xr[q] = lds[swz(e)];
+            uint32_t e = tg + q * Tg;
+            if (e < N2) xr[q] = buf[swz(e)];
         }
         __syncthreads();
-        row_first_step(arow, wf, lds, lg, twf, M, threadIdx.x, T);
-        fwd_steps_from(lds, lg, lg - 3, 0, twf, M, threadIdx.x, T);
+        row_first_step(arow, wf, buf, lg, twf, M, tg, Tg);
+        fwd_steps_from(buf, lg, lg - 3, 0, twf, M, tg, Tg);
 #pragma unroll
         for (int q = 0; q < ROW_EPT; ++q) {
-            uint32_t e = threadIdx.x + q * T;
-            if (e < N2) acc[q] = red2(acc[q] + mont(xr[q], lds[swz(e)], M), M);
+            uint32_t e = tg + q * Tg;
+            if (active && e < N2) acc[q] = red2(acc[q] + mont(xr[q], buf[swz(e)], M), M);
         }
         __syncthreads();
     }
 #pragma unroll
     for (int q = 0; q < ROW_EPT; ++q) {
-        uint32_t e = threadIdx.x + q * T;
-        if (e < N2) lds[swz(e)] = acc[q];
+        uint32_t e = tg + q * Tg;
+        if (e < N2) buf[swz(e)] = acc[q];
     }
     __syncthreads();
+    if (G > 1) {  // add the groups' sums into group 0's row
+        if (g == 0) {
+#pragma unroll
+            for (int q = 0; q < ROW_EPT; ++q) {
+                uint32_t e = tg + q * Tg;
+                if (e >= N2) continue;
+                uint32_t v = acc[q];
+                for (uint32_t h = 1; h < G; ++h) v = red2(v + lds[h * N2 + swz(e)], M);
+                lds[swz(e)] = v;
+            }
+        }
+        __syncthreads();
+    }
     inv_steps_to(lds, lg, lg - 3, 0, twi, M, threadIdx.x, T);
     row_last_inv_step(lds, A.out + pq * A.N + rbase, A.Wi + pq * A.N + rbase, lg, twi, M, threadIdx.x, T);
 }
@@ -1367,10 +1390,21 @@ __global__ void k_pack(const uint32_t *__restrict__ limbs, uint64_t *out, uint64
 
 inline unsigned blocks_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
-unsigned row_threads(const pa_plan *p) {
-    unsigned n2 = 1u << p->m2;
-    unsigned t = n2 / ROW_EPT;
-    return t < 64 ? 64 : t;  // ROW_EPT elements per thread; N2 <= 2^14 -> at most 1024 threads
+// Pair groups of the generic row kernel: rows shorter than 2048 words run
+// several pairs side by side, a group per pair with one thread per radix-8
+// task (N2/8), up to 256 threads; otherwise one group of N2/16 threads
+// (ROW_EPT elements each), at least 64.
+unsigned row_groups(const pa_plan *p, uint64_t npairs) {
+    const unsigned t = (1u << p->m2) / 8;
+    unsigned g = t == 0 || t >= 256 ? 1u : 256u / t;
+    return npairs < g ? (unsigned)npairs : g;
+}
+
+unsigned row_group_threads(const pa_plan *p, uint64_t npairs) {
+    const unsigned n2 = 1u << p->m2;
+    if (row_groups(p, npairs) > 1) return n2 / 8;
+    const unsigned t = n2 / ROW_EPT;
+    return t < 64 ? 64 : t;  // N2 <= 2^14 -> at most 1024 threads
 }
 
 // ---------------------------------------------------------------- host math
@@ -1591,6 +1625,7 @@ static RowArgs row_args(pa_plan *p, uint64_t npairs, const uint32_t *seed_side) 
     ra.twi = p->tw2i;
     ra.r16f = p->R16f;
     ra.r16i = p->R16i;
+    ra.row_group = row_group_threads(p, npairs);
     ra.P = p->primes;
     return ra;
 }
@@ -1598,10 +1633,13 @@ static RowArgs row_args(pa_plan *p, uint64_t npairs, const uint32_t *seed_side) 
 template <int Stage>
 static void launch_row(pa_plan *p, const RowArgs &ra, hipStream_t st) {
     const unsigned rows = (unsigned)(p->N >> p->m2);  // 2^m1, or 3 * 2^m1 for N = 3 * 2^m
-    if (p->m2 == 12)
+    if (p->m2 == 12) {
         hipLaunchKernelGGL(k_row16<Stage>, dim3(rows, NPRIMES), dim3(R16_THREADS), 0, st, ra);
-    else
-        hipLaunchKernelGGL(k_row<Stage>, dim3(rows, NPRIMES), dim3(row_threads(p)), (size_t)4 << p->m2, st, ra);
+    } else {
+        const unsigned groups = row_groups(p, ra.npairs);
+        hipLaunchKernelGGL(k_row<Stage>, dim3(rows, NPRIMES), dim3(groups * ra.row_group),
+                           (size_t)groups * 4 << p->m2, st, ra);
+    }
 }
 
 static ColInvArgs colinv_args(pa_plan *p) {
