@@ -27,6 +27,13 @@ __device__ __forceinline__ uint32_t mont(uint32_t a, uint32_t b, const PrimeCons
     return (uint32_t)(((uint64_t)m * M.p + t) >> 32);  // t + m p < 2^33 p < 2^64, divisible by 2^32
 }
 
+// T * 2^-32 mod p for a 64-bit T < 2^64 - 2^32 p (Montgomery reduction of a
+// sum of raw products); the result is below T / 2^32 + p.
+__device__ __forceinline__ uint32_t redc64(uint64_t T, const PrimeConst &M) {
+    const uint32_t m = (uint32_t)T * M.pinv;
+    return (uint32_t)((T + (uint64_t)m * M.p) >> 32);
+}
+
 // [0, 4p) -> [0, 2p), same residue
 __device__ __forceinline__ uint32_t red2(uint32_t x, const PrimeConst &M) { return min(x, x - M.p2); }
 

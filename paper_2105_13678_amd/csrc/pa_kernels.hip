@@ -771,9 +771,16 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
     // from a table in thread order, so each is one coalesced load per use
     const __amdgpu_buffer_rsrc_t rw = rsrc_of(A.Wf + pq * A.N + rbase, R16_LEN);
     const __amdgpu_buffer_rsrc_t rt = rsrc_of(A.r16f + pq * R16_TW, R16_TW);
+    // the transform-domain sum: acc in [0, 2p), plus up to three raw products
+    // (each below 4p^2 < 2^62) pending in 64 bits, reduced together
     uint32_t acc[16];
+    uint64_t pend[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc[j] = 0u;
+    for (int j = 0; j < 16; ++j) {
+        acc[j] = 0u;
+        pend[j] = 0ull;
+    }
+    uint32_t npend = 0;
 
     for (uint64_t i = 0; i < A.npairs; ++i) {
         const uint32_t *xrow = A.X + i * A.pair_stride + pq * A.N + rbase;
@@ -829,7 +836,16 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
         for (int j = 0; j < 16; ++j) va[j] = lds_word(L16, R16_BA + (a3 ^ (4u * j)));
         dft_fwd<16>(va, M);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) acc[j] = red2(acc[j] + mont(vx[j], va[j], M), M);
+        for (int j = 0; j < 16; ++j) pend[j] += (uint64_t)vx[j] * va[j];
+        if (++npend == 3 || i + 1 == A.npairs) {
+            // 3 * 4p^2 + 2^32 p < 2^64, and the reduction is below 4p
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                acc[j] = red2(acc[j] + red2(redc64(pend[j], M), M), M);
+                pend[j] = 0ull;
+            }
+            npend = 0;
+        }
         __syncthreads();  // the next pair overwrites the buffers
     }
 
