@@ -1319,6 +1319,110 @@ __global__ __launch_bounds__(CARRY_TILE) void k_digit_tile(DigitArgs A) {
     if (threadIdx.x == 0) A.agg[blockIdx.x] = total;
 }
 
+// The same digits straight from the convolution residues, for transform
+// lengths N = 2^m (coefficients in natural order): the workgroup first
+// reconstructs, with Garner's method, every coefficient its CARRY_TILE digits
+// draw on into LDS (a digit takes pieces of up to DIG_HALO + 1 coefficients
+// at or below its own index), then forms the digit sums from there.  Slot s
+// of `lo` holds coefficient m0 - DIG_HALO + s of the range [0, L) and slot s
+// of `hi` coefficient L + m0 - DIG_HALO + s of [L, 2L - 1) (FOLD only),
+// zero outside those ranges.  With notones, workgroup 0 also finishes the
+// status word (Sec. 3.1 reload rule).
+constexpr int DIG_HALO = 16;  // >= pieces per coefficient - 1 (at most 12 for B >= 8)
+
+struct DigitCrtArgs {
+    DigitArgs D;
+    const uint32_t *cc;  // 3 primes x N canonical residues
+    PrimeSet P;
+    CrtConst K;
+    const uint32_t *notones;
+    uint64_t k;
+    uint32_t *status;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(CARRY_TILE) void k_digit_crt(DigitCrtArgs A) {
+    constexpr int SPAN = CARRY_TILE + DIG_HALO;
+    constexpr int HS = MODE == DIG_FOLD ? SPAN : 1;  // the high range: FOLD only
+    __shared__ uint32_t lo[3][SPAN];
+    __shared__ uint32_t hi[3][HS];
+    const DigitArgs &D = A.D;
+    const uint32_t t = threadIdx.x;
+    const uint64_t m0 = (uint64_t)blockIdx.x * CARRY_TILE;
+    if (A.notones && blockIdx.x == 0) {
+        bool reload = false;
+        for (uint64_t i = t; i < A.k; i += CARRY_TILE) reload |= (A.notones[i] == 0u);
+        const int any = __syncthreads_or(reload);
+        if (t == 0) A.status[1] = A.status[0] | (any ? ST_RELOAD : 0u);
+    }
+    const uint32_t *cc = A.cc;
+    for (uint32_t sl = t; sl < (uint32_t)SPAN; sl += CARRY_TILE) {
+        const bool pos = m0 + sl >= (uint64_t)DIG_HALO;
+        const uint64_t j = m0 + sl - DIG_HALO;  // meaningful when pos
+        unsigned __int128 c = 0;
+        if (pos && j < D.L) c = garner(cc[j], cc[D.N + j], cc[2 * D.N + j], A.P, A.K);
+        lo[0][sl] = (uint32_t)c;
+        lo[1][sl] = (uint32_t)(c >> 32);
+        lo[2][sl] = (uint32_t)(c >> 64);
+        if constexpr (MODE == DIG_FOLD) {
+            const uint64_t jh = D.L + j;
+            unsigned __int128 h = 0;
+            if (pos && jh < D.ncoef) h = garner(cc[jh], cc[D.N + jh], cc[2 * D.N + jh], A.P, A.K);
+            hi[0][sl] = (uint32_t)h;
+            hi[1][sl] = (uint32_t)(h >> 32);
+            hi[2][sl] = (uint32_t)(h >> 64);
+        }
+    }
+    __syncthreads();
+    const uint64_t m = m0 + t;
+    CFn f = cf_id();
+    if (m < D.ndig) {
+        const uint32_t s0 = t + DIG_HALO;  // slot of coefficient m; m - q is at s0 - q
+        uint64_t d = 0;
+        if (D.B == 32) {
+#pragma unroll
+            for (uint32_t q = 0; q < 3; ++q) d += lo[q][s0 - q];
+            if constexpr (MODE == DIG_FOLD) {
+                // the folded part shifted left by e < 32: a funnel shift of two planes
+#pragma unroll
+                for (uint32_t q = 0; q < 4; ++q) {
+                    if (q >= D.Q2) continue;
+                    const uint32_t h = q < 3 ? hi[q][s0 - q] : 0u;
+                    const uint32_t l = q >= 1 ? hi[q - 1][s0 - q] : 0u;
+                    d += D.e ? __builtin_amdgcn_alignbit(h, l, 32u - D.e) : h;
+                }
+            } else {
+                const uint64_t bit = 32 * m;
+                uint32_t cw = bit < D.gamma ? ((const uint32_t *)D.cseed)[m] : 0u;
+                if (bit + 32 > D.gamma && bit < D.gamma) cw &= (1u << (D.gamma - bit)) - 1u;
+                d += cw;
+            }
+        } else {
+            const uint64_t mask = (1ull << D.B) - 1;
+            for (uint32_t q = 0; q < D.Q; ++q) {
+                const uint32_t sl = s0 - q;
+                const unsigned __int128 c = (unsigned __int128)lo[0][sl] | ((unsigned __int128)lo[1][sl] << 32) |
+                                            ((unsigned __int128)lo[2][sl] << 64);
+                d += (uint64_t)(c >> (D.B * q)) & mask;
+            }
+            if constexpr (MODE == DIG_FOLD) {
+                for (uint32_t q = 0; q < D.Q2; ++q) {
+                    const uint32_t sl = s0 - q;
+                    const unsigned __int128 h = (unsigned __int128)hi[0][sl] | ((unsigned __int128)hi[1][sl] << 32) |
+                                                ((unsigned __int128)hi[2][sl] << 64);
+                    d += (uint64_t)((h << D.e) >> (D.B * q)) & mask;
+                }
+            } else {
+                d += bits_at(D.cseed, D.gamma, m * D.B, D.B);
+            }
+        }
+        D.t[m] = d;
+        if (m < D.M) f = cf_limb(d, D.B);
+    }
+    const CFn total = block_reduce<CARRY_TILE>(f);
+    if (t == 0) D.agg[blockIdx.x] = total;
+}
+
 struct ScanArgs {
     const uint64_t *t;   // digit sums: M regular limbs, then the top limb at index M if has_top
     uint32_t *out;       // normalised limbs
@@ -1337,6 +1441,11 @@ struct ScanArgs {
 // workgroup 0 writes the top limb.  Launched with max(1, ntiles) workgroups.
 __global__ __launch_bounds__(SCAN_THREADS) void k_carry_apply(ScanArgs A) {
     const uint64_t b = blockIdx.x;
+    // the tile's digit sums first: their loads overlap the composition below
+    const uint64_t base = b * CARRY_TILE + (uint64_t)threadIdx.x * CARRY_PER_THREAD;
+    uint64_t tv[CARRY_PER_THREAD];
+#pragma unroll
+    for (int v = 0; v < CARRY_PER_THREAD; ++v) tv[v] = base + v < A.M ? A.t[base + v] : 0ull;
     const uint64_t per = (A.ntiles + SCAN_THREADS - 1) / SCAN_THREADS;
     const uint64_t j0 = min((uint64_t)threadIdx.x * per, A.ntiles), j1 = min(j0 + per, A.ntiles);
     CFn fb = cf_id(), fa = cf_id();
@@ -1358,15 +1467,10 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_carry_apply(ScanArgs A) {
             A.out[A.M] = (uint32_t)((tt + (sel ? ct1 : ct0)) & ((1ull << A.s_top) - 1));
     }
     if (b >= A.ntiles) return;
-    const uint64_t base = b * CARRY_TILE + (uint64_t)threadIdx.x * CARRY_PER_THREAD;
-    uint64_t tv[CARRY_PER_THREAD];
     CFn f = cf_id();
 #pragma unroll
-    for (int v = 0; v < CARRY_PER_THREAD; ++v) {
-        const uint64_t idx = base + v;
-        tv[v] = idx < A.M ? A.t[idx] : 0ull;
-        if (idx < A.M) f = cf_compose(f, cf_limb(tv[v], A.B));
-    }
+    for (int v = 0; v < CARRY_PER_THREAD; ++v)
+        if (base + v < A.M) f = cf_compose(f, cf_limb(tv[v], A.B));
     CFn excl, total;
     block_scan<SCAN_THREADS>(f, excl, total);
     uint32_t carry = cf_eval(excl, cf_eval(before, sel));
@@ -1725,12 +1829,22 @@ static DigitArgs digit_args(pa_plan *p) {
 
 // Carry normalisation of the digit sums A.t[0..M) (plus the top limb at M if
 // top) into `out`: the tile kernel (digits and tile aggregates), then apply.
+// With `crt` the digits come straight from the residues (k_digit_crt, for
+// N = 2^m), else from the coefficient word planes.
 template <int MODE>
 static hipError_t run_carry(pa_plan *p, DigitArgs A, uint32_t *out, uint64_t ndig, uint64_t M, bool top,
-                            bool dual, hipStream_t st) {
+                            bool dual, hipStream_t st, DigitCrtArgs *crt = nullptr) {
     A.ndig = ndig;
     A.M = M;
-    const uint64_t tiles_t = (ndig + CARRY_TILE - 1) / CARRY_TILE;
+    uint64_t tiles_t = (ndig + CARRY_TILE - 1) / CARRY_TILE;
+    if constexpr (MODE != DIG_WRAP) {
+        if (tiles_t && crt) {
+            crt->D = A;
+            hipLaunchKernelGGL(k_digit_crt<MODE>, dim3((unsigned)tiles_t), dim3(CARRY_TILE), 0, st, *crt);
+            crt = nullptr;
+            tiles_t = 0;
+        }
+    }
     if (tiles_t) hipLaunchKernelGGL(k_digit_tile<MODE>, dim3((unsigned)tiles_t), dim3(CARRY_TILE), 0, st, A);
     ScanArgs S;
     S.t = p->t;
@@ -1772,12 +1886,27 @@ static void launch_crt(pa_plan *p, uint64_t count, const uint32_t *notones, hipS
     hipLaunchKernelGGL(k_crt3, dim3(blocks_for(count < p->Nsub ? count : p->Nsub, 256)), dim3(256), 0, st, A);
 }
 
+// Reconstruction inside the digit kernel (N = 2^m); nullptr for N = 3 * 2^m,
+// whose coefficients need the inverse radix-3 step of k_crt3 first.
+static DigitCrtArgs *residue_digits(pa_plan *p, DigitCrtArgs &C, const uint32_t *notones) {
+    if (p->mix) return nullptr;
+    C.cc = p->Cc;
+    C.P = p->primes;
+    C.K = p->crt;
+    C.notones = notones;
+    C.k = notones ? p->k : 0;
+    C.status = p->status;
+    return &C;
+}
+
 hipError_t launch_fold(pa_plan *p, hipStream_t st) {
     phase_mark(p, PA_PH_FOLD, true, st);
     const uint64_t ncoef = 2 * p->L - 1;  // nonzero coefficients of the product
-    launch_crt(p, ncoef, p->notones, st);
+    DigitCrtArgs C;
+    DigitCrtArgs *crt = residue_digits(p, C, p->notones);
+    if (!crt) launch_crt(p, ncoef, p->notones, st);
     // first fold at bit gamma, normalised over M1 digits (the sum fits: no carry out)
-    hipError_t e = run_carry<DIG_FOLD>(p, digit_args(p), p->s, p->M1, p->M1, false, false, st);
+    hipError_t e = run_carry<DIG_FOLD>(p, digit_args(p), p->s, p->M1, p->M1, false, false, st, crt);
     if (e != hipSuccess) return e;
     // second fold: y = T_lo + (V mod p) over L limbs; the dual evaluation (carry-in
     // 0 or 1) selects S or S + 1 - 2^gamma, which maps a sum equal to p to 0
@@ -1806,10 +1935,12 @@ hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, hipStream
 
     phase_mark(p, PA_PH_MH_CARRY, true, st);
     // only the coefficients below limb L matter mod 2^gamma
-    launch_crt(p, p->L, nullptr, st);
+    DigitCrtArgs C;
+    DigitCrtArgs *crt = residue_digits(p, C, nullptr);
+    if (!crt) launch_crt(p, p->L, nullptr, st);
     DigitArgs A = digit_args(p);
     A.cseed = c;
-    hipError_t e = run_carry<DIG_MH>(p, A, p->U, p->L, p->L - 1, true, false, st);
+    hipError_t e = run_carry<DIG_MH>(p, A, p->U, p->L, p->L - 1, true, false, st, crt);
     phase_mark(p, PA_PH_MH_CARRY, false, st);
     return e;
 }
