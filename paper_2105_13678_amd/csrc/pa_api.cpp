@@ -245,12 +245,12 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     };
     lay->oX = carve(2 * k * P3 * N * 4);
     lay->oC = carve(P3 * N * 4);
-    lay->oC96 = carve(3 * N * 4);
+    lay->oC96 = carve(mix ? 3 * N * 4 : 0);
     lay->oT = carve(digits * 8);
     lay->oS = carve(p->M1 * 4);
     lay->oY = carve(L * 4);
     lay->oU = carve(L * 4);
-    lay->oAgg = carve(p->ntiles_max * sizeof(pa::CFn));
+    lay->oAgg = carve(2 * p->ntiles_max * sizeof(pa::CFn));  // fold and wrap chains
     lay->oNo = carve(k * 4);
     lay->oSt = carve(4 * 4);
     lay->oSo = carve(4 * 4);
@@ -276,6 +276,7 @@ void bind_scratch(pa_plan *p, void *scratch, const PlanLayout &lay) {
     p->y = (uint32_t *)(b + lay.oY);
     p->U = (uint32_t *)(b + lay.oU);
     p->agg = (pa::CFn *)(b + lay.oAgg);
+    p->agg_w = p->agg + p->ntiles_max;
     p->notones = (uint32_t *)(b + lay.oNo);
     p->status = (uint32_t *)(b + lay.oSt);
     p->status_out = (uint32_t *)(b + lay.oSo);

@@ -132,8 +132,10 @@ struct pa_plan {
     uint32_t *s;        // normalised limbs of the folded sum (M1)
     uint32_t *y;        // MMH output limbs (L)
     uint32_t *U;        // MH value limbs (L)
-    uint32_t *C96;      // 3 x N words: reconstructed coefficients, word planes (bits 0-31, 32-63, 64-95)
+    uint32_t *C96;      // N = 3 * 2^m only: 3 x N words, reconstructed coefficients as word planes
+                        // (bits 0-31, 32-63, 64-95); for N = 2^m the digit kernels reconstruct them
     pa::CFn *agg;       // carry functions of CARRY_TILE-digit tiles
+    pa::CFn *agg_w;     // the same for the wrap chain (second fold)
     uint32_t *notones;  // k flags: chunk i has a limb that is not all ones
     uint32_t *status;   // seed/reload flags
     uint32_t *status_out;  // final flags of the last call (pa_hash reads it back)

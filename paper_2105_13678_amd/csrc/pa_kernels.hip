@@ -1213,16 +1213,15 @@ __device__ __forceinline__ unsigned __int128 coef(const uint32_t *__restrict__ c
            ((unsigned __int128)c96[2 * N + j] << 64);
 }
 
-constexpr int DIG_FOLD = 0, DIG_WRAP = 1, DIG_MH = 2;
+constexpr int DIG_FOLD = 0, DIG_MH = 2;
 
 struct DigitArgs {
     const uint32_t *c96;  // product coefficients, three word planes (FOLD, MH)
-    const uint32_t *s;    // normalised limbs of the folded sum (WRAP)
     const uint64_t *cseed;  // c (MH)
     uint64_t *t;          // digit sums out
     CFn *agg;             // tile carry functions out
     uint64_t N, ndig, M;  // digits produced; digits in the carry chain (the rest is the top limb)
-    uint64_t L, ncoef, gamma, M1;
+    uint64_t L, ncoef, gamma;
     uint32_t B, e, Q, Q2, s_top;
 };
 
@@ -1261,17 +1260,15 @@ __device__ __forceinline__ uint64_t fold_digit(const DigitArgs &A, uint64_t m) {
     return sum;
 }
 
-// WRAP digit m < L: T = T_lo + 2^gamma V with T_lo = T mod 2^gamma (V < 2^92);
-// the digits of T_lo + (V mod p).
-__device__ __forceinline__ uint64_t wrap_digit(const DigitArgs &A, uint64_t m) {
-    const uint32_t B = A.B;
-    const uint64_t gamma = A.gamma;
-    const uint64_t lo = (m + 1 < A.L) ? A.s[m] : (A.s[m] & ((1ull << A.s_top) - 1));
-    if (B * m >= 128) return lo;  // V < 2^92 only reaches the lowest digits
+// The second fold (Sec. 3.1): with the folded sum normalised into limbs s
+// (M1 of them), T = T_lo + 2^gamma V with T_lo = T mod 2^gamma and V < 2^92;
+// returns V mod p (p = 2^gamma - 1), which the wrap chain adds to T_lo.
+__device__ __forceinline__ unsigned __int128 wrap_value(const uint32_t *__restrict__ s, uint64_t gamma, uint32_t B,
+                                                        uint64_t M1) {
     unsigned __int128 V = 0;
-    for (uint64_t idx = gamma / B; idx < A.M1; ++idx) {
+    for (uint64_t idx = gamma / B; idx < M1; ++idx) {
         const uint64_t lo_bit = idx * B;
-        const unsigned __int128 limb = A.s[idx];
+        const unsigned __int128 limb = s[idx];
         if (lo_bit < gamma) V += limb >> (gamma - lo_bit);
         else if (lo_bit - gamma < 128) V += limb << (lo_bit - gamma);  // higher limbs are zero
     }
@@ -1280,7 +1277,7 @@ __device__ __forceinline__ uint64_t wrap_digit(const DigitArgs &A, uint64_t m) {
         while (V >> gamma) V = (V & pm) + (V >> gamma);
         if (V == pm) V = 0;
     }
-    return lo + (uint64_t)((V >> (B * m)) & ((1ull << B) - 1));
+    return V;
 }
 
 // MH digit m < L: the limbs of c plus the pieces of the product coefficients
@@ -1311,7 +1308,7 @@ __global__ __launch_bounds__(CARRY_TILE) void k_digit_tile(DigitArgs A) {
     const uint64_t m = (uint64_t)blockIdx.x * CARRY_TILE + threadIdx.x;
     CFn f = cf_id();
     if (m < A.ndig) {
-        const uint64_t d = MODE == DIG_FOLD ? fold_digit(A, m) : MODE == DIG_WRAP ? wrap_digit(A, m) : mh_digit(A, m);
+        const uint64_t d = MODE == DIG_FOLD ? fold_digit(A, m) : mh_digit(A, m);
         A.t[m] = d;
         if (m < A.M) f = cf_limb(d, A.B);
     }
@@ -1423,13 +1420,20 @@ __global__ __launch_bounds__(CARRY_TILE) void k_digit_crt(DigitCrtArgs A) {
     if (t == 0) D.agg[blockIdx.x] = total;
 }
 
+constexpr int APPLY_PLAIN = 0, APPLY_FOLD = 1, APPLY_WRAP = 2;
+
 struct ScanArgs {
     const uint64_t *t;   // digit sums: M regular limbs, then the top limb at index M if has_top
     uint32_t *out;       // normalised limbs
     uint64_t M;
     uint32_t B, has_top, s_top, dual;
     uint64_t ntiles;     // ceil(M / CARRY_TILE)
-    const CFn *agg;
+    const CFn *agg;      // tile carry functions of this chain
+    CFn *agg_w;          // FOLD: tile carry functions of the wrap chain, out
+    uint64_t Mw;         // FOLD: regular digits of the wrap chain (L - 1)
+    const uint32_t *s;   // WRAP: normalised limbs of the folded sum (M1)
+    uint64_t gamma, M1;  // WRAP
+    uint32_t qv;         // FOLD, WRAP: wrap digits below qv = ceil(128 / B) take pieces of V mod p
 };
 
 // Normalise one tile.  The carry into the tile is the composition of the
@@ -1439,13 +1443,33 @@ struct ScanArgs {
 // carry-in 0 and 1; in dual mode the chain takes carry-in 1 when carry-in 0
 // leaves a nonzero value above the top limb's width (see launch_fold), and
 // workgroup 0 writes the top limb.  Launched with max(1, ntiles) workgroups.
+//
+// APPLY_FOLD also composes, per tile, the carry functions of the limbs it
+// writes as digits of the wrap chain (digits [qv, Mw) only), into agg_w.
+// APPLY_WRAP runs the wrap chain itself: its digits are read from the limbs
+// s of the folded sum, the lowest qv with the pieces of V mod p added and the
+// top one cut to s_top bits; the carry functions of digits [0, qv), which
+// depend on V, are composed here (thread 0 prepends them to the aggregates).
+template <int AM>
 __global__ __launch_bounds__(SCAN_THREADS) void k_carry_apply(ScanArgs A) {
     const uint64_t b = blockIdx.x;
+    const uint64_t mask = (1ull << A.B) - 1;
+    unsigned __int128 W = 0;
+    if constexpr (AM == APPLY_WRAP) W = wrap_value(A.s, A.gamma, A.B, A.M1);
+    auto digit = [&](uint64_t m) -> uint64_t {  // m <= M
+        if constexpr (AM == APPLY_WRAP) {
+            uint64_t d = m < A.M ? A.s[m] : (A.s[m] & ((1ull << A.s_top) - 1));
+            if (m < A.qv) d += (uint64_t)(W >> (A.B * m)) & mask;
+            return d;
+        } else {
+            return A.t[m];
+        }
+    };
     // the tile's digit sums first: their loads overlap the composition below
     const uint64_t base = b * CARRY_TILE + (uint64_t)threadIdx.x * CARRY_PER_THREAD;
     uint64_t tv[CARRY_PER_THREAD];
 #pragma unroll
-    for (int v = 0; v < CARRY_PER_THREAD; ++v) tv[v] = base + v < A.M ? A.t[base + v] : 0ull;
+    for (int v = 0; v < CARRY_PER_THREAD; ++v) tv[v] = base + v < A.M ? digit(base + v) : 0ull;
     const uint64_t per = (A.ntiles + SCAN_THREADS - 1) / SCAN_THREADS;
     const uint64_t j0 = min((uint64_t)threadIdx.x * per, A.ntiles), j1 = min(j0 + per, A.ntiles);
     CFn fb = cf_id(), fa = cf_id();
@@ -1454,13 +1478,22 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_carry_apply(ScanArgs A) {
         if (j < b) fb = cf_compose(fb, g);
         fa = cf_compose(fa, g);
     }
+    if constexpr (AM == APPLY_WRAP) {
+        if (threadIdx.x == 0) {  // thread 0's aggregates start at tile 0
+            CFn low = cf_id();
+            const uint64_t nl = A.qv < A.M ? A.qv : A.M;
+            for (uint64_t m = 0; m < nl; ++m) low = cf_compose(low, cf_limb(digit(m), A.B));
+            if (b > 0) fb = cf_compose(low, fb);
+            fa = cf_compose(low, fa);
+        }
+    }
     CFn ex, before;
     block_scan<SCAN_THREADS>(fb, ex, before);
     uint32_t sel = 0;
     if (A.has_top) {
         CFn all;
         block_scan<SCAN_THREADS>(fa, ex, all);
-        const uint64_t tt = A.t[A.M];
+        const uint64_t tt = digit(A.M);
         const uint32_t ct0 = cf_eval(all, 0u), ct1 = cf_eval(all, 1u);
         sel = (A.dual && ((tt + ct1) >> A.s_top) != 0u) ? 1u : 0u;
         if (b == 0 && threadIdx.x == 0)
@@ -1474,15 +1507,21 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_carry_apply(ScanArgs A) {
     CFn excl, total;
     block_scan<SCAN_THREADS>(f, excl, total);
     uint32_t carry = cf_eval(excl, cf_eval(before, sel));
-    const uint64_t mask = (1ull << A.B) - 1;
+    CFn fw = cf_id();
 #pragma unroll
     for (int v = 0; v < CARRY_PER_THREAD; ++v) {
         const uint64_t idx = base + v;
         if (idx < A.M) {
             const uint64_t val = tv[v] + carry;
-            A.out[idx] = (uint32_t)(val & mask);
+            const uint32_t limb = (uint32_t)(val & mask);
+            A.out[idx] = limb;
             carry = (uint32_t)(val >> A.B);
+            if (AM == APPLY_FOLD && idx >= A.qv && idx < A.Mw) fw = cf_compose(fw, cf_limb(limb, A.B));
         }
+    }
+    if constexpr (AM == APPLY_FOLD) {
+        const CFn tw = block_reduce<SCAN_THREADS>(fw);
+        if (threadIdx.x == 0) A.agg_w[b] = tw;
     }
 }
 
@@ -1810,7 +1849,6 @@ hipError_t launch_mmh(pa_plan *p, const uint64_t *key, const uint64_t *a, hipStr
 static DigitArgs digit_args(pa_plan *p) {
     DigitArgs A;
     A.c96 = p->C96;
-    A.s = p->s;
     A.cseed = nullptr;
     A.t = p->t;
     A.agg = p->agg;
@@ -1818,7 +1856,6 @@ static DigitArgs digit_args(pa_plan *p) {
     A.L = p->L;
     A.ncoef = 2 * p->L - 1;  // nonzero coefficients of the product
     A.gamma = p->gamma;
-    A.M1 = p->M1;
     A.B = p->B;
     A.e = p->e_fold;
     A.Q = (96 + p->B - 1) / p->B;
@@ -1827,25 +1864,7 @@ static DigitArgs digit_args(pa_plan *p) {
     return A;
 }
 
-// Carry normalisation of the digit sums A.t[0..M) (plus the top limb at M if
-// top) into `out`: the tile kernel (digits and tile aggregates), then apply.
-// With `crt` the digits come straight from the residues (k_digit_crt, for
-// N = 2^m), else from the coefficient word planes.
-template <int MODE>
-static hipError_t run_carry(pa_plan *p, DigitArgs A, uint32_t *out, uint64_t ndig, uint64_t M, bool top,
-                            bool dual, hipStream_t st, DigitCrtArgs *crt = nullptr) {
-    A.ndig = ndig;
-    A.M = M;
-    uint64_t tiles_t = (ndig + CARRY_TILE - 1) / CARRY_TILE;
-    if constexpr (MODE != DIG_WRAP) {
-        if (tiles_t && crt) {
-            crt->D = A;
-            hipLaunchKernelGGL(k_digit_crt<MODE>, dim3((unsigned)tiles_t), dim3(CARRY_TILE), 0, st, *crt);
-            crt = nullptr;
-            tiles_t = 0;
-        }
-    }
-    if (tiles_t) hipLaunchKernelGGL(k_digit_tile<MODE>, dim3((unsigned)tiles_t), dim3(CARRY_TILE), 0, st, A);
+static ScanArgs scan_args(pa_plan *p, uint32_t *out, uint64_t M, bool top, bool dual) {
     ScanArgs S;
     S.t = p->t;
     S.out = out;
@@ -1856,7 +1875,38 @@ static hipError_t run_carry(pa_plan *p, DigitArgs A, uint32_t *out, uint64_t ndi
     S.dual = dual ? 1u : 0u;
     S.ntiles = (M + CARRY_TILE - 1) / CARRY_TILE;
     S.agg = p->agg;
-    hipLaunchKernelGGL(k_carry_apply, dim3((unsigned)(S.ntiles ? S.ntiles : 1)), dim3(SCAN_THREADS), 0, st, S);
+    S.agg_w = p->agg_w;
+    S.Mw = p->L - 1;
+    S.s = p->s;
+    S.gamma = p->gamma;
+    S.M1 = p->M1;
+    S.qv = (128 + p->B - 1) / p->B;
+    return S;
+}
+
+template <int AM>
+static void launch_apply(const ScanArgs &S, hipStream_t st) {
+    hipLaunchKernelGGL(k_carry_apply<AM>, dim3((unsigned)(S.ntiles ? S.ntiles : 1)), dim3(SCAN_THREADS), 0, st, S);
+}
+
+// Carry normalisation of the digit sums A.t[0..M) (plus the top limb at M if
+// top) into `out`: the tile kernel (digits and tile aggregates), then apply
+// (for FOLD also the wrap chain's tile aggregates).  With `crt` the digits
+// come straight from the residues (k_digit_crt, for N = 2^m), else from the
+// coefficient word planes.
+template <int MODE>
+static hipError_t run_carry(pa_plan *p, DigitArgs A, uint32_t *out, uint64_t ndig, uint64_t M, bool top,
+                            bool dual, hipStream_t st, DigitCrtArgs *crt) {
+    A.ndig = ndig;
+    A.M = M;
+    const uint64_t tiles_t = (ndig + CARRY_TILE - 1) / CARRY_TILE;
+    if (tiles_t && crt) {
+        crt->D = A;
+        hipLaunchKernelGGL(k_digit_crt<MODE>, dim3((unsigned)tiles_t), dim3(CARRY_TILE), 0, st, *crt);
+    } else if (tiles_t) {
+        hipLaunchKernelGGL(k_digit_tile<MODE>, dim3((unsigned)tiles_t), dim3(CARRY_TILE), 0, st, A);
+    }
+    launch_apply<MODE == DIG_FOLD ? APPLY_FOLD : APPLY_PLAIN>(scan_args(p, out, M, top, dual), st);
     return hipGetLastError();
 }
 
@@ -1908,9 +1958,14 @@ hipError_t launch_fold(pa_plan *p, hipStream_t st) {
     // first fold at bit gamma, normalised over M1 digits (the sum fits: no carry out)
     hipError_t e = run_carry<DIG_FOLD>(p, digit_args(p), p->s, p->M1, p->M1, false, false, st, crt);
     if (e != hipSuccess) return e;
-    // second fold: y = T_lo + (V mod p) over L limbs; the dual evaluation (carry-in
-    // 0 or 1) selects S or S + 1 - 2^gamma, which maps a sum equal to p to 0
-    e = run_carry<DIG_WRAP>(p, digit_args(p), p->y, p->L, p->L - 1, true, true, st);
+    // second fold: y = T_lo + (V mod p) over L limbs, straight from the limbs of the
+    // first (whose apply left the wrap chain's tile aggregates); the dual
+    // evaluation (carry-in 0 or 1) selects S or S + 1 - 2^gamma, which maps a
+    // sum equal to p to 0
+    ScanArgs S = scan_args(p, p->y, p->L - 1, true, true);
+    S.agg = p->agg_w;
+    launch_apply<APPLY_WRAP>(S, st);
+    e = hipGetLastError();
     phase_mark(p, PA_PH_FOLD, false, st);
     return e;
 }
