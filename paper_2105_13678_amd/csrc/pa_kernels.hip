@@ -887,6 +887,7 @@ struct ColInvArgs {
     uint32_t m1, m2, c_lg;
     const uint32_t *twi;  // per prime: omega_{N1}^-e, e < N1
     uint64_t Nsub;        // words per transform: blockIdx.z's transform starts at z * Nsub
+    uint32_t row_lim;     // output rows below row_lim are stored (the rest is not needed)
     PrimeSet P;
 };
 
@@ -960,7 +961,8 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_inv(ColInvArgs A) {
         // canonical residues for the Chinese-remainder step
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-            cc[((uint64_t)(n1 + ((uint32_t)j << lgMp)) << A.m2) + c0 + q] = canon(red2(v[j], M), M);
+            if (n1 + ((uint32_t)j << lgMp) < A.row_lim)
+                cc[((uint64_t)(n1 + ((uint32_t)j << lgMp)) << A.m2) + c0 + q] = canon(red2(v[j], M), M);
     }
 }
 
@@ -1114,7 +1116,8 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_inv(ColInvArgs A) {
         const uint32_t vo = ((n1 << A.m2) + c0 + q) << 2;
         // canonical residues for the Chinese-remainder step
 #pragma unroll
-        for (int j = 0; j < 8; ++j) bstore(canon(red2(v[j], M), M), rc, vo, ((64u * j) << A.m2) << 2);
+        for (int j = 0; j < 8; ++j)
+            if (n1 + 64u * j < A.row_lim) bstore(canon(red2(v[j], M), M), rc, vo, ((64u * j) << A.m2) << 2);
     }
 }
 
@@ -1454,8 +1457,20 @@ template <int AM>
 __global__ __launch_bounds__(SCAN_THREADS) void k_carry_apply(ScanArgs A) {
     const uint64_t b = blockIdx.x;
     const uint64_t mask = (1ull << A.B) - 1;
+    // the tile's digit sums (WRAP: limbs) first: their loads overlap the
+    // composition below
+    const uint64_t base = b * CARRY_TILE + (uint64_t)threadIdx.x * CARRY_PER_THREAD;
+    uint64_t tv[CARRY_PER_THREAD];
+#pragma unroll
+    for (int v = 0; v < CARRY_PER_THREAD; ++v)
+        tv[v] = base + v < A.M ? (AM == APPLY_WRAP ? (uint64_t)A.s[base + v] : A.t[base + v]) : 0ull;
     unsigned __int128 W = 0;
-    if constexpr (AM == APPLY_WRAP) W = wrap_value(A.s, A.gamma, A.B, A.M1);
+    if constexpr (AM == APPLY_WRAP) {
+        W = wrap_value(A.s, A.gamma, A.B, A.M1);
+#pragma unroll
+        for (int v = 0; v < CARRY_PER_THREAD; ++v)
+            if (base + v < A.qv && base + v < A.M) tv[v] += (uint64_t)(W >> (A.B * (base + v))) & mask;
+    }
     auto digit = [&](uint64_t m) -> uint64_t {  // m <= M
         if constexpr (AM == APPLY_WRAP) {
             uint64_t d = m < A.M ? A.s[m] : (A.s[m] & ((1ull << A.s_top) - 1));
@@ -1465,13 +1480,10 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_carry_apply(ScanArgs A) {
             return A.t[m];
         }
     };
-    // the tile's digit sums first: their loads overlap the composition below
-    const uint64_t base = b * CARRY_TILE + (uint64_t)threadIdx.x * CARRY_PER_THREAD;
-    uint64_t tv[CARRY_PER_THREAD];
-#pragma unroll
-    for (int v = 0; v < CARRY_PER_THREAD; ++v) tv[v] = base + v < A.M ? digit(base + v) : 0ull;
+    // aggregates of the tiles before this one (and, with a top limb, of all)
     const uint64_t per = (A.ntiles + SCAN_THREADS - 1) / SCAN_THREADS;
-    const uint64_t j0 = min((uint64_t)threadIdx.x * per, A.ntiles), j1 = min(j0 + per, A.ntiles);
+    const uint64_t jn = A.has_top ? A.ntiles : min(b, A.ntiles);
+    const uint64_t j0 = min((uint64_t)threadIdx.x * per, jn), j1 = min(j0 + per, jn);
     CFn fb = cf_id(), fa = cf_id();
     for (uint64_t j = j0; j < j1; ++j) {
         const CFn g = A.agg[j];
@@ -1810,6 +1822,7 @@ static ColInvArgs colinv_args(pa_plan *p) {
     ci.c_lg = p->ci_lg;
     ci.twi = p->tw1i;
     ci.Nsub = p->Nsub;
+    ci.row_lim = 1u << p->m1;
     ci.P = p->primes;
     return ci;
 }
@@ -1984,6 +1997,9 @@ hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, hipStream
     phase_mark(p, PA_PH_MH_ROW, false, st);
 
     ColInvArgs ci = colinv_args(p);
+    // mod 2^gamma only the coefficients below limb L count: rows below ceil(L / N2)
+    // (with N = 3 * 2^m every row of the three transforms feeds some of them)
+    if (!p->mix) ci.row_lim = (uint32_t)((p->L + (1ull << p->m2) - 1) >> p->m2);
     phase_mark(p, PA_PH_MH_COLINV, true, st);
     launch_col_inv<STAGE_MH>(p, ci, st);
     phase_mark(p, PA_PH_MH_COLINV, false, st);
