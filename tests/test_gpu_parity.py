@@ -254,12 +254,14 @@ def _blk(chunks, a, b, c, gamma, n, r):
                        b=defn.int_to_words(b, W), c=defn.int_to_words(c, W))
 
 
+@pytest.mark.parametrize("flags", [1, 2])
 @pytest.mark.parametrize("B", [0, 8, 13])
 @pytest.mark.parametrize("gamma", [61, 89, 521, 4423, 44497, 110503])
-def test_fold_canonical_cases(pa, gamma, B):
+def test_fold_canonical_cases(pa, gamma, B, flags):
     """S = p must fold to y = 0; S = p + 1 to 1; one-hot seeds rotate a chunk
     (2^gamma = 1 mod p); a_i = p - 1 complements.  Narrow limbs (B = 8, 13)
-    spread the second fold's V mod p over up to 16 limbs."""
+    spread the second fold's V mod p over up to 16 limbs; both length forms
+    (flags 1: 2^m, 2: 3 * 2^m) reconstruct the coefficients differently."""
     p = (1 << gamma) - 1
     rng = random.Random(gamma)
     c = rng.randrange(1 << gamma)
@@ -267,17 +269,17 @@ def test_fold_canonical_cases(pa, gamma, B):
     for label, chunks, a in [("S=p", [p - 1, 1], [1, 1]), ("S=p+1", [p - 1, 2], [1, 1]),
                              ("S=2p", [p - 1, 1], [2, 2]), ("S=0", [0, 0], [5, 7])]:
         blk = _blk(chunks, a, 1, c, gamma, 2 * gamma, r)
-        check_block(pa, blk, B=B, label=f"fold {label}")
+        check_block(pa, blk, B=B, flags=flags, label=f"fold {label}")
     x = rng.randrange(p)
     s = rng.randrange(gamma)
     blk = _blk([0, x, 0], [0, 1 << s, 0], 1, 0, gamma, 3 * gamma, r)
-    check_block(pa, blk, B=B, label="rotate")
+    check_block(pa, blk, B=B, flags=flags, label="rotate")
     blk = _blk([0, x, 0], [3, p - 1, 9], 1, 0, gamma, 3 * gamma, r)
-    check_block(pa, blk, B=B, label="complement")
+    check_block(pa, blk, B=B, flags=flags, label="complement")
     # all-ones limbs everywhere except one bit: long carry chains in every scan
     blk = _blk([p - 1, p - 2, p ^ 1], [p - 1, p - 1, p - 1], (1 << gamma) - 1, (1 << gamma) - 1,
                gamma, 3 * gamma, r)
-    check_block(pa, blk, B=B, label="long carries")
+    check_block(pa, blk, B=B, flags=flags, label="long carries")
 
 
 def test_status_codes_and_untouched_output(pa):
