@@ -25,14 +25,25 @@ HEADERS = ["pa_internal.hpp", "ntt_device.hpp"]
 DEVICE_SOURCES = ["pa_kernels.hip", "ntt_device.hpp"]
 
 
+def _code_only(text: str) -> str:
+    """The source with comments removed and white space collapsed (the device
+    sources hold no string literals), so that edits of comments alone keep
+    the digest."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def source_digest() -> str:
-    """sha256 over the device-code sources of libpa: identifies the kernels
-    a set of profiler counters was taken on."""
+    """sha256 over the code of libpa's device sources (comments and white
+    space ignored): identifies the kernels a set of profiler counters was
+    taken on."""
     import hashlib
     h = hashlib.sha256()
     for name in DEVICE_SOURCES:
-        with open(os.path.join(CSRC, name), "rb") as fh:
-            h.update(name.encode() + b"\0" + fh.read())
+        with open(os.path.join(CSRC, name), encoding="utf-8") as fh:
+            h.update(name.encode() + b"\0" + _code_only(fh.read()).encode())
     return h.hexdigest()
 
 

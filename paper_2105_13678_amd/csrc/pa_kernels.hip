@@ -1048,14 +1048,6 @@ __device__ void block_scan(CFn f, CFn &excl, CFn &total) {
 }
 
 
-// ------------------------------------------------------------------ fused digit tiles
-// A carry normalisation runs in two launches (after the Chinese-remainder
-// kernel where the digits come from product coefficients).  The digit kernel
-// produces the digit sums (one per thread) and the composed carry function
-// of each CARRY_TILE-digit tile; the apply kernel composes the functions of
-// the tiles before its own into its carry-in (and handles the top limb), then
-// normalises its tile.  No workgroup waits for another.
-
 // Inverse column pass for 512-row tiles of 16 columns (N1 = 2^9), the mirror
 // of k_col9_fwd with the same task decomposition and LDS layout: the
 // sub-length-8 step straight from global memory, the sub-length-64 step, and
@@ -1216,6 +1208,15 @@ __device__ __forceinline__ unsigned __int128 coef(const uint32_t *__restrict__ c
            ((unsigned __int128)c96[2 * N + j] << 64);
 }
 
+// ------------------------------------------------------------------ carry chains
+// A carry normalisation runs in two launches.  The digit kernel produces the
+// digit sums (one per thread) and the composed carry function of each
+// CARRY_TILE-digit tile: straight from the residues for N = 2^m
+// (k_digit_crt), from the reconstructed coefficient planes for N = 3 * 2^m
+// (k_digit_tile after k_crt3).  The apply kernel composes the functions of
+// the tiles before its own into its carry-in (and handles the top limb), then
+// normalises its tile.  No workgroup waits for another.  The second fold has
+// no digit kernel: the first fold's apply leaves its tile functions.
 constexpr int DIG_FOLD = 0, DIG_MH = 2;
 
 struct DigitArgs {
