@@ -42,6 +42,7 @@ constexpr int ROW_MAX_THREADS = 1024;
 // eq. 2 and the MH product of eq. 4) so that profiles report the two stages'
 // launches under separate names; the code is identical.
 constexpr int STAGE_MMH = 0, STAGE_MH = 1;
+constexpr unsigned MH_COL_ZSPLIT = 3;  // workgroups per tile of the MH forward column pass
 
 __device__ __forceinline__ uint32_t bitrev(uint32_t x, uint32_t bits) {
     return bits ? (__brev(x) >> (32 - bits)) : 0u;
@@ -387,8 +388,12 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
             if (any && t == 0) A.notones[arr] = 1u;
         }
     }
+    // the transforms (primes x radix-3 branches) of this workgroup's z slice:
+    // gridDim.z divides NSUB * NPRIMES
+    const uint32_t per_z = NSUB * NPRIMES / gridDim.z;
+    const uint32_t it0 = blockIdx.z * per_z, it1 = it0 + per_z;
 #pragma unroll 1
-    for (uint32_t it = 0; it < NSUB * NPRIMES; ++it) {
+    for (uint32_t it = it0; it < it1; ++it) {
         const uint32_t k0 = it / NPRIMES, pq = it - NPRIMES * k0;
         const PrimeConst M = A.P.c[pq];
         const uint32_t *tw = A.tw + ((uint64_t)pq << lg);
@@ -399,7 +404,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
             g0 = A.g3 + (((size_t)pq * 3 + k0) << lg);
             g1 = g0 + ((size_t)NPRIMES * 3 << lg);
         }
-        if (it) __syncthreads();  // the previous transform's last step has read the buffer
+        if (it != it0) __syncthreads();  // the previous transform's last step has read the buffer
         const uint32_t tl = opaque(t);  // task addresses are recomputed per transform, not kept live
 #pragma unroll
         for (int u = 0; u < TPT; ++u) {
@@ -505,8 +510,12 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
             if (any && t == 0) A.notones[arr] = 1u;
         }
     }
+    // the transforms (primes x radix-3 branches) of this workgroup's z slice:
+    // gridDim.z divides NSUB * NPRIMES
+    const uint32_t per_z = NSUB * NPRIMES / gridDim.z;
+    const uint32_t it0 = blockIdx.z * per_z, it1 = it0 + per_z;
 #pragma unroll 1
-    for (uint32_t it = 0; it < NSUB * NPRIMES; ++it) {
+    for (uint32_t it = it0; it < it1; ++it) {
         const uint32_t k0 = it / NPRIMES, pq = it - NPRIMES * k0;
         const PrimeConst M = A.P.c[pq];
         const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.tw + ((uint64_t)pq << C9_LG), 1u << C9_LG);
@@ -519,7 +528,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
             rg0 = rsrc_of(g0, 1u << C9_LG);
             rg1 = rsrc_of(g0 + ((size_t)NPRIMES * 3 << C9_LG), 1u << C9_LG);
         }
-        if (it) __syncthreads();  // the previous transform's last step has read the buffer
+        if (it != it0) __syncthreads();  // the previous transform's last step has read the buffer
         const uint32_t tl = MIX ? opaque(t) : t;  // radix-3 split: recompute the task addresses per transform
 #pragma unroll
         for (uint32_t u = 0; u < 4; ++u) {  // step A
@@ -1741,8 +1750,9 @@ static ColFwdArgs col_args(pa_plan *p, uint32_t mode) {
 // Column pass of any shape: one workgroup per (tile, array), first-step tasks
 // per thread as the tile needs (2^(m1 - 3 + c_lg) tasks, m1 + c_lg <= 14).
 template <int Stage, bool MIX>
-static void launch_col_fwd_generic(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, hipStream_t st) {
-    const dim3 grid(1u << (p->m2 - cf.c_lg), narrays, 1);
+static void launch_col_fwd_generic(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, unsigned zsplit,
+                                   hipStream_t st) {
+    const dim3 grid(1u << (p->m2 - cf.c_lg), narrays, zsplit);
     const size_t col_lds = ((size_t)4 << p->m1) << cf.c_lg;
     const uint32_t ntask = (1u << (p->m1 - 3)) << cf.c_lg;
     // common tile shapes (2^m1 rows x 2^c_lg columns) with compile-time sizes
@@ -1768,18 +1778,23 @@ static void launch_col_fwd_generic(pa_plan *p, const ColFwdArgs &cf, unsigned na
         hipLaunchKernelGGL((k_col_fwd<Stage, MIX, 8>), grid, dim3(COL_THREADS), col_lds, st, cf);
 }
 
+// zsplit (1 or 3) workgroups share a tile's transforms, each taking the
+// primes (and radix-3 branches) of its slice: more workgroups for passes with
+// few arrays, at the cost of unpacking the tile's limbs once per slice.
 template <int Stage>
-static void launch_col_fwd(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, hipStream_t st) {
+static void launch_col_fwd(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, unsigned zsplit, hipStream_t st) {
     const unsigned ncol_tiles = 1u << (p->m2 - cf.c_lg);
     const bool c9 = p->m1 == C9_LG && cf.c_lg == C9_CLG;  // 512 x 16 tiles in static LDS
-    if (c9 && p->mix)  // all three primes and radix-3 transforms per workgroup
-        hipLaunchKernelGGL((k_col9_fwd<Stage, true>), dim3(ncol_tiles, narrays, 1), dim3(COL_THREADS), 0, st, cf);
-    else if (c9)  // all three primes per workgroup
-        hipLaunchKernelGGL((k_col9_fwd<Stage, false>), dim3(ncol_tiles, narrays, 1), dim3(COL_THREADS), 0, st, cf);
+    if (c9 && p->mix)  // three primes and radix-3 transforms per tile
+        hipLaunchKernelGGL((k_col9_fwd<Stage, true>), dim3(ncol_tiles, narrays, zsplit), dim3(COL_THREADS), 0, st,
+                           cf);
+    else if (c9)  // three primes per tile
+        hipLaunchKernelGGL((k_col9_fwd<Stage, false>), dim3(ncol_tiles, narrays, zsplit), dim3(COL_THREADS), 0, st,
+                           cf);
     else if (p->mix)
-        launch_col_fwd_generic<Stage, true>(p, cf, narrays, st);
+        launch_col_fwd_generic<Stage, true>(p, cf, narrays, zsplit, st);
     else
-        launch_col_fwd_generic<Stage, false>(p, cf, narrays, st);
+        launch_col_fwd_generic<Stage, false>(p, cf, narrays, zsplit, st);
 }
 
 static RowArgs row_args(pa_plan *p, uint64_t npairs, const uint32_t *seed_side) {
@@ -1845,7 +1860,7 @@ hipError_t launch_mmh(pa_plan *p, const uint64_t *key, const uint64_t *a, hipStr
     cf.a = a;
     phase_mark(p, PA_PH_MMH_COL, true, st);
     // with resident seed transforms only the k key chunks are transformed
-    launch_col_fwd<STAGE_MMH>(p, cf, (unsigned)(p->res_a ? p->k : 2 * p->k), st);
+    launch_col_fwd<STAGE_MMH>(p, cf, (unsigned)(p->res_a ? p->k : 2 * p->k), 1u, st);
     phase_mark(p, PA_PH_MMH_COL, false, st);
 
     RowArgs ra = row_args(p, p->k, p->res_a ? p->res_a : p->X + p->k * NPRIMES * p->N);
@@ -1989,7 +2004,8 @@ hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, hipStream
     cf.b = b;
     cf.ylimbs = p->y;
     phase_mark(p, PA_PH_MH_COL, true, st);
-    launch_col_fwd<STAGE_MH>(p, cf, p->res_b ? 1u : 2u, st);
+    // one or two arrays: a workgroup per prime fills the GPU
+    launch_col_fwd<STAGE_MH>(p, cf, p->res_b ? 1u : 2u, MH_COL_ZSPLIT, st);
     phase_mark(p, PA_PH_MH_COL, false, st);
 
     RowArgs ra = row_args(p, 1, p->res_b ? p->res_b : p->X + (uint64_t)NPRIMES * p->N);
@@ -2043,12 +2059,12 @@ hipError_t launch_seed_transforms(pa_plan *p, const uint64_t *a, uint64_t kmax, 
     cf.k = kmax;
     cf.arr0 = (uint32_t)kmax;  // arrays kmax .. 2 kmax - 1 are the seed chunks
     cf.a = a;
-    launch_col_fwd<STAGE_MMH>(p, cf, (unsigned)kmax, st);
+    launch_col_fwd<STAGE_MMH>(p, cf, (unsigned)kmax, 1u, st);
     ColFwdArgs cb = col_args(p, 1);
     cb.X = dst_b;
     cb.arr0 = 1;  // array 1 of the MH stage is b
     cb.b = b;
-    launch_col_fwd<STAGE_MH>(p, cb, 1u, st);
+    launch_col_fwd<STAGE_MH>(p, cb, 1u, MH_COL_ZSPLIT, st);
     return hipGetLastError();
 }
 
