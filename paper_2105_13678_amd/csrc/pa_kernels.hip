@@ -1136,26 +1136,6 @@ __device__ __forceinline__ unsigned __int128 garner(uint32_t r0, uint32_t r1, ui
     return (unsigned __int128)r0 + (unsigned __int128)v1 * P.c[0].p + (unsigned __int128)v2 * K.p0p1;
 }
 
-// Chinese-remainder reconstruction (Garner): canonical residues mod p0, p1,
-// p2 of a coefficient below p0 p1 p2 -> its exact value, as three word planes.
-// With notones set, workgroup 0 also finishes the status word: RELOAD when
-// some key chunk had no limb that is not all ones (Sec. 3.1 reload rule).
-__global__ void k_crt(const uint32_t *__restrict__ cc, uint32_t *c96, uint64_t N, uint64_t count, PrimeSet P,
-                      CrtConst K, const uint32_t *notones, uint64_t k, uint32_t *status) {
-    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (notones && blockIdx.x == 0) {
-        bool reload = false;
-        for (uint64_t i = threadIdx.x; i < k; i += blockDim.x) reload |= (notones[i] == 0u);
-        const int any = __syncthreads_or(reload);
-        if (threadIdx.x == 0) status[1] = status[0] | (any ? ST_RELOAD : 0u);
-    }
-    if (j >= count) return;
-    const unsigned __int128 c = garner(cc[j], cc[N + j], cc[2 * N + j], P, K);
-    c96[j] = (uint32_t)c;
-    c96[N + j] = (uint32_t)(c >> 32);
-    c96[2 * N + j] = (uint32_t)(c >> 64);
-}
-
 struct Crt3Args {
     const uint32_t *cc;  // 3 primes x N residues: three inverse transforms of Nsub words each
     uint32_t *c96;
@@ -1939,14 +1919,10 @@ static hipError_t run_carry(pa_plan *p, DigitArgs A, uint32_t *out, uint64_t ndi
     return hipGetLastError();
 }
 
-// Coefficients [0, count) of the convolution from the residues in Cc (with
-// notones: also the RELOAD status).
-static void launch_crt(pa_plan *p, uint64_t count, const uint32_t *notones, hipStream_t st) {
-    if (!p->mix) {
-        hipLaunchKernelGGL(k_crt, dim3(blocks_for(count, 256)), dim3(256), 0, st, p->Cc, p->C96, p->N, count,
-                           p->primes, p->crt, notones, notones ? p->k : 0, p->status);
-        return;
-    }
+// Coefficients [0, count) of the convolution for N = 3 * 2^m from the
+// residues in Cc, as word planes in C96 (with notones: also the RELOAD
+// status).  For N = 2^m the digit kernels reconstruct the coefficients.
+static void launch_crt3(pa_plan *p, uint64_t count, const uint32_t *notones, hipStream_t st) {
     Crt3Args A;
     A.cc = p->Cc;
     A.c96 = p->C96;
@@ -1983,7 +1959,7 @@ hipError_t launch_fold(pa_plan *p, hipStream_t st) {
     const uint64_t ncoef = 2 * p->L - 1;  // nonzero coefficients of the product
     DigitCrtArgs C;
     DigitCrtArgs *crt = residue_digits(p, C, p->notones);
-    if (!crt) launch_crt(p, ncoef, p->notones, st);
+    if (!crt) launch_crt3(p, ncoef, p->notones, st);
     // first fold at bit gamma, normalised over M1 digits (the sum fits: no carry out)
     hipError_t e = run_carry<DIG_FOLD>(p, digit_args(p), p->s, p->M1, p->M1, false, false, st, crt);
     if (e != hipSuccess) return e;
@@ -2025,7 +2001,7 @@ hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, hipStream
     // only the coefficients below limb L matter mod 2^gamma
     DigitCrtArgs C;
     DigitCrtArgs *crt = residue_digits(p, C, nullptr);
-    if (!crt) launch_crt(p, p->L, nullptr, st);
+    if (!crt) launch_crt3(p, p->L, nullptr, st);
     DigitArgs A = digit_args(p);
     A.cseed = c;
     hipError_t e = run_carry<DIG_MH>(p, A, p->U, p->L, p->L - 1, true, false, st, crt);
