@@ -1293,6 +1293,7 @@ __device__ __forceinline__ uint64_t mh_digit(const DigitArgs &A, uint64_t m) {
     return sum;
 }
 
+// Digits from the coefficients' word planes (N = 3 * 2^m, after k_crt3).
 // Workgroup b covers digits [b CARRY_TILE, +CARRY_TILE), one per thread
 // (many waves in flight: the digits gather from several coefficients); writes
 // the digit sums and the tile's composed carry function (digits below M only).
@@ -1433,9 +1434,10 @@ struct ScanArgs {
 // aggregates of all earlier tiles evaluated at the chain's carry-in (every
 // workgroup composes them itself: a few per thread, no second pass).  With a
 // top limb (index M, s_top bits) the whole chain is also evaluated for
-// carry-in 0 and 1; in dual mode the chain takes carry-in 1 when carry-in 0
-// leaves a nonzero value above the top limb's width (see launch_fold), and
-// workgroup 0 writes the top limb.  Launched with max(1, ntiles) workgroups.
+// carry-in 0 and 1; in dual mode the chain takes carry-in 1 when carry-in 1
+// leaves a nonzero value above the top limb's width, i.e. when the sum is at
+// least p (see launch_fold), and workgroup 0 writes the top limb.  Launched
+// with max(1, ntiles) workgroups.
 //
 // APPLY_FOLD also composes, per tile, the carry functions of the limbs it
 // writes as digits of the wrap chain (digits [qv, Mw) only), into agg_w.
