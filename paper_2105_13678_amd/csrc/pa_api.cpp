@@ -210,14 +210,16 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     // segments), the single-array inverse pass 8 (more workgroups).  The
     // key-chunk pass widens short columns towards 256 first-step tasks per
     // tile (one per thread) while its 2k arrays still give at least 512
-    // workgroups; a request may fix its width (col_lg, e.g. from pa_plan_tune).
+    // workgroups, and takes 8 columns of 1024 rows (4 first-step tasks per
+    // thread; 16 such columns need the whole 64 KiB of LDS and about twice the
+    // registers); a request may fix its width (col_lg, e.g. from pa_plan_tune).
     auto fit = [&](uint32_t c) {
         if (c > p->m2) c = p->m2;
         if (p->m1 + c > kMaxLdsLog2) c = kMaxLdsLog2 - p->m1;
         return c;
     };
     const uint32_t c_mh = fit(4);
-    uint32_t c_mmh = fit(p->m1 < 7 ? 11 - p->m1 : 4);
+    uint32_t c_mmh = fit(p->m1 < 7 ? 11 - p->m1 : p->m1 == 10 ? 3 : 4);
     while (c_mmh > c_mh && ((uint64_t)2 * k << (p->m2 - c_mmh)) < 512) --c_mmh;
     if (prm->col_lg) {
         if (prm->col_lg > p->m2 || p->m1 + prm->col_lg > kMaxLdsLog2) return PA_ERR_ARG;

@@ -1748,7 +1748,7 @@ static void launch_col_fwd_generic(pa_plan *p, const ColFwdArgs &cf, unsigned na
     PA_COL_FIXED(4, 4) PA_COL_FIXED(4, 6) PA_COL_FIXED(4, 7)
     PA_COL_FIXED(5, 4) PA_COL_FIXED(5, 6)
     PA_COL_FIXED(6, 4) PA_COL_FIXED(6, 5)
-    PA_COL_FIXED(7, 4) PA_COL_FIXED(8, 4) PA_COL_FIXED(10, 4)
+    PA_COL_FIXED(7, 4) PA_COL_FIXED(8, 4) PA_COL_FIXED(10, 3) PA_COL_FIXED(10, 4)
 #undef PA_COL_FIXED
     if (ntask <= COL_THREADS)
         hipLaunchKernelGGL((k_col_fwd<Stage, MIX, 1>), grid, dim3(COL_THREADS), col_lds, st, cf);

@@ -210,7 +210,7 @@ def test_length_form_flags_and_tile_width():
     rejected, as is a nonzero reserved word; col_lg fixes the key-chunk
     column-tile width within the tile limits (2^col_lg <= row length,
     log2N1 + col_lg <= 14) and is reported back; the automatic width widens
-    short columns."""
+    short columns and narrows columns of 1024 rows to 8."""
     n, r = 18_802_622, 2_288_514  # gamma = 2,976,221, k = 7
     st, i3 = binding.plan_query(n, r, flags=binding.PA_FLAG_RADIX3_LENGTHS)
     assert st == 0 and i3["len_factor"] == 3 and i3["N"] == 3 << 16
@@ -223,6 +223,9 @@ def test_length_form_flags_and_tile_width():
     # automatic width: 2^16-point rows of 16 rows widen to 64 columns (14 arrays)
     assert (i3["log2N1"], i3["log2N2"], i3["col_lg"]) == (4, 12, 6)
     assert binding.plan_query(260_000_000, 26_000_000)[1]["col_lg"] == 4
+    # columns of 1024 rows (the 2^32-bit block, N = 3 * 2^22): 8 columns
+    i_big = binding.plan_query(1 << 32, 1 << 27)[1]
+    assert (i_big["log2N1"], i_big["log2N2"], i_big["col_lg"]) == (10, 12, 3)
     for c in (1, 3, 8, 10):
         st, info = binding.plan_query(n, r, flags=binding.PA_FLAG_RADIX3_LENGTHS, col_lg=c)
         assert st == 0 and info["col_lg"] == c
