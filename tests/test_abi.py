@@ -231,3 +231,20 @@ def test_length_form_flags_and_tile_width():
         assert st == 0 and info["col_lg"] == c
     assert binding.plan_query(n, r, flags=binding.PA_FLAG_RADIX3_LENGTHS, col_lg=11)[0] == binding.PA_ERR_ARG  # 4 + 11 > 14
     assert binding.plan_query(1 << 20, 1 << 16, col_lg=13)[0] == binding.PA_ERR_ARG  # wider than a row
+
+
+def test_profile_digest_covers_code_only(tmp_path):
+    """bench.py reports a kernel's HBM bytes only while the profile summary was
+    taken on the current device sources: the digest covers their code, so an
+    edit of comments or white space keeps it and any code edit changes it."""
+    from paper_2105_13678_amd import build, profile_summary
+    code = "__global__ void k(int *p) {\n    p[0] = 1;  // one\n}\n/* block\n   comment */\n"
+    assert build._code_only(code) == build._code_only("__global__ void k(int *p) { p[0] = 1; }")
+    assert build._code_only(code) != build._code_only(code.replace("p[0] = 1", "p[0] = 2"))
+    digest = build.source_digest()
+    summary = tmp_path / "hbm.md"
+    summary.write_text(f"    traffic k_row16<0> fetch=10 write=20 sources={digest}\n"
+                       f"    traffic k_other fetch=1 write=2 sources={'0' * 64}\n")
+    assert profile_summary.read_traffic(str(summary), "k_row16<0>") == (10, 20)
+    assert profile_summary.read_traffic(str(summary), "k_other") is None  # taken on other sources
+    assert profile_summary.read_traffic(str(tmp_path / "absent.md"), "k_row16<0>") is None
