@@ -207,7 +207,8 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     p->m1 = m - m2;
     // Column tiles of 2^c columns x 2^m1 rows (at most 2^14 words of LDS).
     // The MH-stage forward pass (two arrays) uses 16 columns (64-byte row
-    // segments), the single-array inverse pass 8 (more workgroups).  The
+    // segments; 8 for columns of 1024 rows), the single-array inverse pass 8
+    // (more workgroups).  The
     // key-chunk pass widens short columns towards 256 first-step tasks per
     // tile (one per thread) while its 2k arrays still give at least 512
     // workgroups, and takes 8 columns of 1024 rows (4 first-step tasks per
@@ -218,7 +219,7 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
         if (p->m1 + c > kMaxLdsLog2) c = kMaxLdsLog2 - p->m1;
         return c;
     };
-    const uint32_t c_mh = fit(4);
+    const uint32_t c_mh = fit(p->m1 == 10 ? 3 : 4);
     uint32_t c_mmh = fit(p->m1 < 7 ? 11 - p->m1 : p->m1 == 10 ? 3 : 4);
     while (c_mmh > c_mh && ((uint64_t)2 * k << (p->m2 - c_mmh)) < 512) --c_mmh;
     if (prm->col_lg) {

@@ -590,6 +590,138 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
     }
 }
 
+// Column pass for 1024-row tiles of 8 columns (N1 = 2^10): the 512-row
+// kernel's scheme with one more row bit.  Step A: radix-8 across rows 128
+// apart straight from the unpacked limbs, times omega_1024^(n1 brev(s));
+// step B: radix-8 across rows 16 apart, times omega_128^(n1 brev(s)); step
+// C: radix-16 on 16 consecutive rows, straight to global memory.  Output row
+// 128 s_A + 16 s_B + s_C holds frequency brev3(s_A) + 8 brev3(s_B) +
+// 64 brev4(s_C): natural order in, bit-reversed order out, as every column
+// pass.  LDS word of (row, column) row * 8 + column, swizzled by swz_c10
+// (conflict-free for the three access patterns).
+constexpr uint32_t C10_LG = 10, C10_CLG = 3;
+__device__ __forceinline__ constexpr uint32_t swz_c10(uint32_t i) { return i ^ (((i >> 7) & 7u) << 3); }
+
+template <int Stage, bool MIX>
+__global__ __launch_bounds__(COL_THREADS) void k_col10_fwd(ColFwdArgs A) {
+    constexpr uint32_t NSUB = MIX ? 3u : 1u;
+    constexpr int X0_ROWS = MIX ? 8 : 4;  // step-A rows of a task holding x_n (x_(n+Nsub): rows < 4)
+    __shared__ uint32_t L10[1u << (C10_LG + C10_CLG)];  // one 1024 x 8 tile
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t arr = blockIdx.y + A.arr0;
+    const uint64_t c0 = (uint64_t)tile << C10_CLG;
+    const bool is_key = (A.mode == 0) && arr < A.k;
+    const uint32_t full = (uint32_t)((1ull << A.B) - 1), topv = (uint32_t)((1ull << A.s_top) - 1);
+    const uint32_t t = threadIdx.x;
+    const uint32_t Ns = (uint32_t)A.Nsub;
+    // the tile's limbs of the four step-A tasks, unpacked once
+    uint32_t x[4][X0_ROWS], x1[4][MIX ? 4 : 1];
+    {
+        const LimbSrc S = limb_src(A, arr);
+        const uint32_t L = (uint32_t)A.L;
+        bool not_ones = false;
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            const uint32_t tau = t + 256u * u;
+            const uint32_t q = tau & 7u, n1 = tau >> 3;
+#pragma unroll
+            for (int jj = 0; jj < X0_ROWS; ++jj) {
+                const uint32_t j = ((n1 + 128u * jj) << A.m2) + (uint32_t)c0 + q;  // limb index
+                x[u][jj] = limb_at(S, j);
+                if (is_key && j < L) not_ones |= (x[u][jj] != (j == L - 1 ? topv : full));
+                if constexpr (MIX) {
+                    if (jj >= 4) continue;
+                    x1[u][jj] = limb_at(S, j + Ns);
+                    if (is_key && j + Ns < L) not_ones |= (x1[u][jj] != (j + Ns == L - 1 ? topv : full));
+                }
+            }
+            if constexpr (MIX) __builtin_amdgcn_sched_barrier(0);  // 24 limb loads in flight at most
+        }
+        if (is_key) {
+            int any = __syncthreads_or(not_ones);
+            if (any && t == 0) A.notones[arr] = 1u;
+        }
+    }
+    // the transforms (primes x radix-3 branches) of this workgroup's z slice:
+    // gridDim.z divides NSUB * NPRIMES
+    const uint32_t per_z = NSUB * NPRIMES / gridDim.z;
+    const uint32_t it0 = blockIdx.z * per_z, it1 = it0 + per_z;
+#pragma unroll 1
+    for (uint32_t it = it0; it < it1; ++it) {
+        const uint32_t k0 = it / NPRIMES, pq = it - NPRIMES * k0;
+        const PrimeConst M = A.P.c[pq];
+        const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.tw + ((uint64_t)pq << C10_LG), 1u << C10_LG);
+        uint32_t *out = A.X + ((uint64_t)blockIdx.y * NPRIMES + pq) * A.N + (uint64_t)k0 * Ns;
+        const __amdgpu_buffer_rsrc_t ro = rsrc_of(out, Ns);  // this transform's Nsub words
+        // radix-3 row twiddles of transform k0 (tables g0, g1 of k_tw_g3)
+        __amdgpu_buffer_rsrc_t rg0 = rtw, rg1 = rtw;
+        if constexpr (MIX) {
+            const uint32_t *g0 = A.g3 + (((size_t)pq * 3 + k0) << C10_LG);
+            rg0 = rsrc_of(g0, 1u << C10_LG);
+            rg1 = rsrc_of(g0 + ((size_t)NPRIMES * 3 << C10_LG), 1u << C10_LG);
+        }
+        if (it != it0) __syncthreads();  // the previous transform's last step has read the buffer
+        const uint32_t tl = MIX ? opaque(t) : t;  // radix-3 split: recompute the task addresses per transform
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {  // step A: rows n1 + 128 j
+            const uint32_t tau = tl + 256u * u;
+            const uint32_t n1 = tau >> 3;
+            uint32_t v[8], w[8];
+            if constexpr (MIX) {
+                uint32_t ga[8], gb[4];
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) ga[jj] = bload(rg0, (n1 + 128u * jj) << 2, 0);
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) gb[jj] = bload(rg1, (n1 + 128u * jj) << 2, 0);
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj)
+                    v[jj] = jj < 4 ? red2(mont(x[u][jj], ga[jj], M) + mont(x1[u][jj & 3], gb[jj & 3], M), M)
+                                   : mont(x[u][jj], ga[jj], M);  // in [0, 2p)
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) v[jj] = mont(x[u][jj], M.one, M);  // x mod p, in [0, 2p)
+            }
+#pragma unroll
+            for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 2, 0);
+            dft_fwd_x<8, !MIX, true>(v, w, M);
+            const uint32_t sb = swz_c10(tau);  // word of (row n1 + 128 s, column q): tau + 1024 s
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) lds_word(L10, (sb ^ (1024u * jj)) << 2) = v[jj];
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (uint32_t u = 0; u < 4; ++u) {  // step B: rows 128 b + n1 + 16 j
+            const uint32_t tau = t + 256u * u;
+            const uint32_t q = tau & 7u, n1 = (tau >> 3) & 15u, b = tau >> 7;
+            const uint32_t sb = swz_c10(1024u * b + 8u * n1 + q);
+            uint32_t v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = lds_word(L10, (sb ^ swz_c10(128u * j)) << 2);
+            uint32_t w[8];
+#pragma unroll
+            for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 5, 0);
+            dft_fwd_tw<8>(v, w, M);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) lds_word(L10, (sb ^ swz_c10(128u * j)) << 2) = v[j];
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (uint32_t u = 0; u < 2; ++u) {  // step C: rows 16 b + j, to global memory
+            const uint32_t tau = t + 256u * u;
+            const uint32_t q = tau & 7u, b = tau >> 3;
+            const uint32_t sb = swz_c10(128u * b + q);
+            uint32_t v[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = lds_word(L10, (sb ^ (8u * j)) << 2);
+            dft_fwd<16>(v, M);
+            // buffer stores: lane offset plus a uniform row offset (no 64-bit address math)
+            const uint32_t vo = (((16u * b) << A.m2) + (uint32_t)c0 + q) << 2;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) bstore(v[j], ro, vo, ((uint32_t)j << A.m2) << 2);
+        }
+    }
+}
+
 struct RowArgs {
     const uint32_t *X;
     const uint32_t *A;  // seed-side transforms: pair i at A + i * pair_stride
@@ -1767,7 +1899,17 @@ template <int Stage>
 static void launch_col_fwd(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, unsigned zsplit, hipStream_t st) {
     const unsigned ncol_tiles = 1u << (p->m2 - cf.c_lg);
     const bool c9 = p->m1 == C9_LG && cf.c_lg == C9_CLG;  // 512 x 16 tiles in static LDS
-    if (c9 && p->mix)  // three primes and radix-3 transforms per tile
+    // 1024 x 8 tiles in static LDS: for 2^m lengths and the MH stage (measured
+    // faster there); the radix-3 key-chunk pass runs the generic kernel's
+    // compile-time 1024 x 8 instance, which measured faster for it
+    const bool c10 = p->m1 == C10_LG && cf.c_lg == C10_CLG && (!p->mix || Stage == STAGE_MH);
+    if (c10 && p->mix)
+        hipLaunchKernelGGL((k_col10_fwd<Stage, true>), dim3(ncol_tiles, narrays, zsplit), dim3(COL_THREADS), 0, st,
+                           cf);
+    else if (c10)
+        hipLaunchKernelGGL((k_col10_fwd<Stage, false>), dim3(ncol_tiles, narrays, zsplit), dim3(COL_THREADS), 0, st,
+                           cf);
+    else if (c9 && p->mix)  // three primes and radix-3 transforms per tile
         hipLaunchKernelGGL((k_col9_fwd<Stage, true>), dim3(ncol_tiles, narrays, zsplit), dim3(COL_THREADS), 0, st,
                            cf);
     else if (c9)  // three primes per tile

@@ -407,21 +407,16 @@ def _chunk_int(key_bytes: bytes, lo_bit: int, nbits: int, n: int) -> int:
     return v & ((1 << (hi_bit - lo_bit)) - 1)
 
 
-def test_largest_block_power_of_two_seeds(pa):
-    """The largest block, n = 2^32 with r = 2^27 (gamma = 136,279,841, k = 32;
-    B = 31 with 3 * 2^22-point transforms, and B = 29 with 2^24-point ones
-    under PA_FLAG_POW2_LENGTHS), against a closed form instead of the
-    oracle: with seeds a_i = 2^(s_i) the MMH sum is y = sum_i rotl(x_i, s_i)
-    mod p (2^gamma = 1 mod p turns a power-of-two product into a rotation), and
-    with b = 2^gamma - 1 (= -1 mod 2^gamma) the MH value is U = c - y mod
-    2^gamma.  The key and c are uniform; every chunk is active."""
-    n, r = 1 << 32, 1 << 27
+def _rotation_closed_form(pa, n, r, seed, label):
+    """Hash one block with seeds a_i = 2^(s_i) and b = 2^gamma - 1 on both
+    length forms (the plan rule's and, flagged, the other) and check both
+    against a closed form instead of the oracle: the MMH sum is
+    y = sum_i rotl(x_i, s_i) mod p (2^gamma = 1 mod p turns a power-of-two
+    product into a rotation) and, with b = -1 mod 2^gamma, the MH value is
+    U = c - y mod 2^gamma.  The key and c are uniform; every chunk is active."""
     st, g, k = defn.plan_shape(n, r)
-    assert (st, g, k) == (0, 136279841, 32)
-    info = pa.plan_query(n, r)[1]
-    info2 = pa.plan_query(n, r, flags=pa.PA_FLAG_POW2_LENGTHS)[1]
-    assert (info["N"], info["B"], info2["N"], info2["B"]) == (3 << 22, 31, 1 << 24, 29)
-    rng = synth.SplitMix64(77)
+    assert st == 0
+    rng = synth.SplitMix64(seed)
     key = rng.words((n + 63) // 64)
     W = (g + 63) // 64
     shifts = [int(v % g) for v in rng.words(k)]
@@ -434,8 +429,9 @@ def test_largest_block_power_of_two_seeds(pa):
     if g % 64:
         c[-1] &= np.uint64((1 << (g % 64)) - 1)
     runs = []
-    for flags, inf in ((0, info), (pa.PA_FLAG_POW2_LENGTHS, info2)):
-        say(f"[case] largest block n=2^32 r=2^27 gamma={g} k={k} N={inf['N']} B={inf['B']}")
+    for flags in (pa.PA_FLAG_RADIX3_LENGTHS, pa.PA_FLAG_POW2_LENGTHS):
+        inf = pa.plan_query(n, r, flags=flags)[1]
+        say(f"[case] {label} n={n} r={r} gamma={g} k={k} N={inf['N']} B={inf['B']} flags={flags}")
         plan = pa.Plan(n, r, flags=flags)
         try:
             runs.append(run_gpu(pa, plan, synth.Block(n, r, g, k, key, a, b, c), stages=True))
@@ -457,3 +453,30 @@ def test_largest_block_power_of_two_seeds(pa):
     assert int.from_bytes(y.tobytes(), "little") == y_want
     assert int.from_bytes(U.tobytes(), "little") == U_want
     assert int.from_bytes(out.tobytes(), "little") == U_want >> (g - r)
+
+
+def test_largest_block_power_of_two_seeds(pa):
+    """The largest block, n = 2^32 with r = 2^27 (gamma = 136,279,841, k = 32;
+    B = 31 with 3 * 2^22-point transforms, and B = 29 with 2^24-point ones
+    under PA_FLAG_POW2_LENGTHS), against the rotation closed form."""
+    n, r = 1 << 32, 1 << 27
+    assert defn.plan_shape(n, r) == (0, 136279841, 32)
+    info = pa.plan_query(n, r)[1]
+    info2 = pa.plan_query(n, r, flags=pa.PA_FLAG_POW2_LENGTHS)[1]
+    assert (info["N"], info["B"], info2["N"], info2["B"]) == (3 << 22, 31, 1 << 24, 29)
+    _rotation_closed_form(pa, n, r, 77, "largest block")
+
+
+def test_power_of_two_seeds_1024_row_columns(pa):
+    """n = 5e8, r = 5e7 (gamma = 57,885,161, k = 9): the plan rule's 2^22-point
+    transforms have columns of 1024 rows (the 1024 x 8 column kernel) and
+    rows of 4096; the radix-3 form 3 * 2^21 runs the 512-row kernels.  Both
+    against the rotation closed form."""
+    n, r = 500_000_000, 50_000_000
+    assert defn.plan_shape(n, r) == (0, 57885161, 9)
+    i2 = pa.plan_query(n, r, flags=pa.PA_FLAG_POW2_LENGTHS)[1]
+    i3 = pa.plan_query(n, r, flags=pa.PA_FLAG_RADIX3_LENGTHS)[1]
+    assert (i2["N"], i2["log2N1"], i2["log2N2"], i2["col_lg"]) == (1 << 22, 10, 12, 3)
+    assert (i3["N"], i3["log2N1"]) == (3 << 21, 9)
+    assert pa.plan_query(n, r)[1]["N"] == 1 << 22
+    _rotation_closed_form(pa, n, r, 78, "1024-row columns")
