@@ -1254,6 +1254,71 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_inv(ColInvArgs A) {
     }
 }
 
+// Inverse column pass for 1024-row tiles of 8 columns (N1 = 2^10), the mirror
+// of k_col10_fwd: radix-16 on 16 consecutive (bit-reversed) rows straight
+// from global memory, radix-8 across rows 16 apart, radix-8 across rows 128
+// apart straight back to global memory as canonical residues (rows below
+// row_lim).  Inverse twiddles multiply a task's inputs (fused into the first
+// DIT stage).
+template <int Stage>
+__global__ __launch_bounds__(COL_THREADS) void k_col10_inv(ColInvArgs A) {
+    __shared__ uint32_t L10[1u << (C10_LG + C10_CLG)];  // one 1024 x 8 tile
+    const uint32_t pq = blockIdx.y;
+    const PrimeConst M = A.P.c[pq];
+    const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.twi + ((uint64_t)pq << C10_LG), 1u << C10_LG);
+    // this transform's Nsub words, through a buffer resource: lane offset plus
+    // a uniform row offset per access
+    const __amdgpu_buffer_rsrc_t rc = rsrc_of(A.Cc + pq * A.N + blockIdx.z * A.Nsub, (uint32_t)A.Nsub);
+    const uint32_t c0 = xcd_tile(blockIdx.x, gridDim.x) << C10_CLG;
+    const uint32_t t = threadIdx.x;
+#pragma unroll 1
+    for (uint32_t u = 0; u < 2; ++u) {  // sub-length 16: rows 16 b + j
+        const uint32_t tau = t + 256u * u;
+        const uint32_t q = tau & 7u, b = tau >> 3;
+        const uint32_t vo = (((16u * b) << A.m2) + c0 + q) << 2;
+        uint32_t v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = bload(rc, vo, ((uint32_t)j << A.m2) << 2);
+        dft_inv<16>(v, M);
+        const uint32_t sb = swz_c10(128u * b + q);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) lds_word(L10, (sb ^ (8u * j)) << 2) = v[j];
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (uint32_t u = 0; u < 4; ++u) {  // sub-length 128: rows 128 b + n1 + 16 j
+        const uint32_t tau = t + 256u * u;
+        const uint32_t q = tau & 7u, n1 = (tau >> 3) & 15u, b = tau >> 7;
+        const uint32_t sb = swz_c10(1024u * b + 8u * n1 + q);
+        uint32_t v[8], w[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = lds_word(L10, (sb ^ swz_c10(128u * j)) << 2);
+#pragma unroll
+        for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 5, 0);
+        dft_inv_tw<8>(v, w, M);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) lds_word(L10, (sb ^ swz_c10(128u * j)) << 2) = v[j];
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (uint32_t u = 0; u < 4; ++u) {  // sub-length 1024: rows n1 + 128 j, to global memory
+        const uint32_t tau = t + 256u * u;
+        const uint32_t q = tau & 7u, n1 = tau >> 3;
+        const uint32_t sb = swz_c10(tau);
+        uint32_t v[8], w[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = lds_word(L10, (sb ^ (1024u * j)) << 2);
+#pragma unroll
+        for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 2, 0);
+        dft_inv_tw<8>(v, w, M);
+        const uint32_t vo = ((n1 << A.m2) + c0 + q) << 2;
+        // canonical residues for the Chinese-remainder step
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (n1 + 128u * j < A.row_lim) bstore(canon(red2(v[j], M), M), rc, vo, ((128u * j) << A.m2) << 2);
+    }
+}
+
 // Garner's reconstruction: canonical residues r_q mod p_q of a value below
 // p0 p1 p2 -> the value.
 __device__ __forceinline__ unsigned __int128 garner(uint32_t r0, uint32_t r1, uint32_t r2, const PrimeSet &P,
@@ -1973,6 +2038,9 @@ static void launch_col_inv(pa_plan *p, const ColInvArgs &ci, hipStream_t st) {
     if (p->m1 == C9_LG && p->m2 >= C9_CLG)
         hipLaunchKernelGGL(k_col9_inv<Stage>, dim3(1u << (p->m2 - C9_CLG), NPRIMES, nsub), dim3(COL_THREADS), 0, st,
                            ci);
+    else if (p->m1 == C10_LG && p->m2 >= C10_CLG)
+        hipLaunchKernelGGL(k_col10_inv<Stage>, dim3(1u << (p->m2 - C10_CLG), NPRIMES, nsub), dim3(COL_THREADS), 0,
+                           st, ci);
     else
         hipLaunchKernelGGL(k_col_inv<Stage>, dim3(1u << (p->m2 - p->ci_lg), NPRIMES, nsub), dim3(COL_THREADS),
                            ((size_t)4 << p->m1) << p->ci_lg, st, ci);
