@@ -223,9 +223,12 @@ def test_length_form_flags_and_tile_width():
     # automatic width: 2^16-point rows of 16 rows widen to 64 columns (14 arrays)
     assert (i3["log2N1"], i3["log2N2"], i3["col_lg"]) == (4, 12, 6)
     assert binding.plan_query(260_000_000, 26_000_000)[1]["col_lg"] == 4
-    # columns of 1024 rows (the 2^32-bit block, N = 3 * 2^22): 8 columns
+    # columns of 1024 rows (the 2^32-bit block, N = 3 * 2^22; the 5e8-bit
+    # block, N = 2^22): 8 columns
     i_big = binding.plan_query(1 << 32, 1 << 27)[1]
     assert (i_big["log2N1"], i_big["log2N2"], i_big["col_lg"]) == (10, 12, 3)
+    i_5e8 = binding.plan_query(500_000_000, 50_000_000)[1]
+    assert (i_5e8["N"], i_5e8["log2N1"], i_5e8["log2N2"], i_5e8["col_lg"]) == (1 << 22, 10, 12, 3)
     for c in (1, 3, 8, 10):
         st, info = binding.plan_query(n, r, flags=binding.PA_FLAG_RADIX3_LENGTHS, col_lg=c)
         assert st == 0 and info["col_lg"] == c
