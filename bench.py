@@ -339,15 +339,17 @@ def bench_batched(args):
     print(json.dumps(rec), flush=True)
 
 
-LENGTH_BLOCKS = [(800_000_000, 80_000_000, 6), (1 << 32, 1 << 27, 7)]
+LENGTH_BLOCKS = [(800_000_000, 80_000_000, 6), (1 << 32, 1 << 27, 7), (500_000_000, 50_000_000, 5)]
 
 
 def bench_lengths(args):
-    """Blocks whose product length 2L - 1 falls just above a power of two:
-    the paper's largest CV block (n = 8e8, r = n/10: 2L - 1 = 0.62 * 2^23) and
-    the 2^32-bit block (r = 2^27: 0.52 * 2^24), each hashed with the plan
-    rule's transform length 3 * 2^m and with power-of-two lengths only
-    (PA_FLAG_POW2_LENGTHS), same inputs; outputs must agree."""
+    """Blocks hashed with transform lengths 3 * 2^m (PA_FLAG_RADIX3_LENGTHS)
+    and 2^m (PA_FLAG_POW2_LENGTHS), same inputs; outputs must agree.  Two
+    product lengths 2L - 1 fall just above a power of two, where the plan
+    rule takes 3 * 2^m: the paper's largest CV block (n = 8e8, r = n/10:
+    0.62 * 2^23) and the 2^32-bit block (r = 2^27: 0.52 * 2^24); one falls
+    below, where it takes 2^m: n = 5e8, r = n/10 (0.86 * 2^22, columns of
+    1024 rows).  `rule` names the plan rule's form."""
     import torch
     import paper_2105_13678_amd as pa
     from paper_2105_13678_amd import synth
@@ -356,7 +358,8 @@ def bench_lengths(args):
     K, Wm = args.steps, max(1, args.warmup)
     rows = []
     blocks = LENGTH_BLOCKS if args.block is None else [LENGTH_BLOCKS[args.block]]
-    modes = [m for m in (("radix3", 0), ("pow2", pa.PA_FLAG_POW2_LENGTHS)) if args.mode in (None, m[0])]
+    modes = [m for m in (("radix3", pa.PA_FLAG_RADIX3_LENGTHS), ("pow2", pa.PA_FLAG_POW2_LENGTHS))
+             if args.mode in (None, m[0])]
     for n, r, seed in blocks:
         st, info = pa.plan_query(n, r)
         assert st == 0, st
@@ -383,7 +386,8 @@ def bench_lengths(args):
                           "N": plan.N, "out": out.clone()}
             log(f"[bench] lengths n={n} r={r} {label}: N={plan.N} B={plan.B} {ms:.3f} ms")
             plan.close()
-        row = {"n": n, "r": r, "gamma": info["gamma"], "k": info["k"]}
+        row = {"n": n, "r": r, "gamma": info["gamma"], "k": info["k"],
+               "rule": "radix3" if info["len_factor"] == 3 else "pow2"}
         if len(res) == 2:
             row["outputs_equal"] = torch.equal(res["radix3"]["out"], res["pow2"]["out"])
             row["speedup"] = round(res["pow2"]["ms_per_block"] / res["radix3"]["ms_per_block"], 3)
@@ -558,10 +562,10 @@ def main():
                     help="single: the 2.6e8-bit block (the headline); batched: 64 uneven blocks in one "
                          "pa_hash_batched call against the same blocks as serial calls; serving: Poisson "
                          "arrivals from 16 sessions through the serving loop (latency percentiles); lengths: "
-                         "the 8e8- and 2^32-bit blocks with transform lengths 3 * 2^m against 2^m")
+                         "the 8e8-, 2^32- and 5e8-bit blocks with transform lengths 3 * 2^m against 2^m")
     ap.add_argument("--requests", type=int, default=600, help="serving: number of Poisson arrivals")
     ap.add_argument("--block", type=int, choices=range(len(LENGTH_BLOCKS)), default=None,
-                    help="lengths: run only this block (0: 8e8 bits, 1: 2^32 bits)")
+                    help="lengths: run only this block (0: 8e8 bits, 1: 2^32 bits, 2: 5e8 bits)")
     ap.add_argument("--mode", choices=["radix3", "pow2"], default=None, help="lengths: run only this length form")
     ap.add_argument("--core-only", action="store_true",
                     help="single: time only the K main steps (no per-step statistics, key-upload or pipelined "
