@@ -147,6 +147,43 @@ pa_status pa_hash_stages(pa_plan *plan, const uint64_t *key, const uint64_t *a,
                          uint64_t *y_out, uint64_t *U_out, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Hashing without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops or harnesses that
+ * forbid hipMalloc).
+ *
+ * pa_hash_noalloc does the work of pa_hash_async for the shape *params would
+ * give pa_plan_create, without a plan: the plan is derived on the host and
+ * every device buffer the hash needs beyond the caller's (transform arrays,
+ * residues, digit sums, carry functions, flags and the twiddle tables of the
+ * transform length) lives in one static device array of
+ * PA_NOALLOC_MAX_BYTES bytes per GPU, owned by the library and held until
+ * the process ends.  The call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine), enqueues every kernel on `stream` (which
+ * must belong to `hip_device`; NULL = default stream) and returns; the
+ * block's status flags go to the caller's device word *d_status (decode
+ * with pa_decode_status once the stream has reached this point).
+ *
+ * The array keeps the last call's contents: the twiddle tables of the last
+ * transform length are reused when the next call on that GPU has the same
+ * length (a key in the array says which length they are for, checked on the
+ * device), everything else is rewritten by each call.  All calls on one GPU
+ * share the array: calls that overlap on one GPU (on different streams
+ * without ordering between them, or from several host threads) race and
+ * give wrong results; order them.
+ *
+ * Arguments and layouts as for pa_hash_async (device buffers owned by the
+ * caller, valid until the stream has passed the call).  Returns the plan
+ * errors of *params (PA_ERR_ARG, PA_ERR_NO_GAMMA, PA_ERR_GAMMA,
+ * PA_ERR_INEXACT, PA_ERR_LIMIT), PA_ERR_ARG for a NULL pointer or a device
+ * number outside 0..63, PA_ERR_LIMIT when the block's buffers (256 bytes +
+ * pa_plan_info.workspace_bytes) exceed PA_NOALLOC_MAX_BYTES (nothing
+ * launched), PA_ERR_DEVICE when a HIP call fails, else PA_OK. */
+#define PA_NOALLOC_MAX_BYTES (64u << 20)
+pa_status pa_hash_noalloc(const pa_params *params, int hip_device, const uint64_t *key, const uint64_t *a,
+                          const uint64_t *b, const uint64_t *c, uint64_t *out, uint32_t *d_status,
+                          hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Batched hashing of independent blocks of uneven size.
  *
  * A QKD post-processing pipeline produces reconciled blocks of varying length

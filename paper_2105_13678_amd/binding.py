@@ -101,6 +101,8 @@ def lib():
         L.pa_hash_async.restype = ctypes.c_int
         L.pa_hash_stages.argtypes = [_VP] * 9
         L.pa_hash_stages.restype = ctypes.c_int
+        L.pa_hash_noalloc.argtypes = [ctypes.POINTER(Params), ctypes.c_int] + [_VP] * 7
+        L.pa_hash_noalloc.restype = ctypes.c_int
         L.pa_plan_set_profiling.argtypes = [_VP, ctypes.c_uint32]
         L.pa_plan_set_profiling.restype = ctypes.c_int
         L.pa_plan_read_profile.argtypes = [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)]
@@ -293,6 +295,30 @@ class Plan:
         args = self._args(key, a, b, c, out)
         st = lib().pa_hash_stages(self._h, *args, y.data_ptr(), U.data_ptr(), self._stream(stream))
         return st, out, y, U
+
+
+NOALLOC_MAX_BYTES = 64 << 20  # PA_NOALLOC_MAX_BYTES
+
+
+def hash_noalloc(n: int, r: int, key, a, b, c, out, d_status, device: int = 0, gamma: int = 0, B: int = 0,
+                 flags: int = 0, col_lg: int = 0, stream=None) -> int:
+    """pa_hash_noalloc: enqueue the hash of one block without a plan and
+    without any allocation (the library's static device array holds every
+    buffer); status flags land in the 1-word device tensor d_status.
+    Returns the call's status (host-side errors only)."""
+    import torch
+    st, info = plan_query(n, r, gamma, B, flags, col_lg)
+    if st != PA_OK:
+        return st
+    dev = torch.device("cuda", device)
+    args = (_dev_ptr(key, info["key_words"], "key", dev), _dev_ptr(a, info["a_words"], "a", dev),
+            _dev_ptr(b, info["seed_words"], "b", dev), _dev_ptr(c, info["seed_words"], "c", dev),
+            _dev_ptr(out, info["out_words"], "out", dev))
+    if d_status.device != dev or d_status.numel() < 1:
+        raise ValueError("d_status must be a device tensor")
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    prm = Params(n, r, gamma, B, flags, col_lg, 0)
+    return lib().pa_hash_noalloc(ctypes.byref(prm), int(device), *args, d_status.data_ptr(), s.cuda_stream)
 
 
 class BatchPlan:

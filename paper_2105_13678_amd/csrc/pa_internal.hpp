@@ -205,7 +205,9 @@ void init_prime_constants(pa_plan *p, const uint32_t primes[NPRIMES]);
 
 // Kernel launchers (pa_kernels.hip).  All enqueue on `st` and return the
 // first HIP error seen.
-hipError_t launch_twiddles(pa_plan *p, hipStream_t st);
+// With hdr (a device word): skip the build when *hdr == want, else build and
+// then set *hdr = want (tables kept in memory that outlives one call).
+hipError_t launch_twiddles(pa_plan *p, hipStream_t st, uint32_t *hdr = nullptr, uint32_t want = 0);
 hipError_t launch_prologue(pa_plan *p, const uint64_t *a, const uint64_t *b, const uint64_t *c,
                            hipStream_t st);
 hipError_t launch_mmh(pa_plan *p, const uint64_t *key, const uint64_t *a, hipStream_t st);
