@@ -32,7 +32,7 @@ def build(force: bool = False) -> str:
     """Compile the C oracle with gcc into oracle/liboracle.so."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-pthread",
                                "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
@@ -49,6 +49,9 @@ def _load():
         lib.oracle_hash.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
                                     ctypes.c_uint64] + [ctypes.c_void_p] * 6
         lib.oracle_hash.restype = ctypes.c_int
+        lib.oracle_hash_threads.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
+                                            ctypes.c_uint64] + [ctypes.c_void_p] * 6 + [ctypes.c_int]
+        lib.oracle_hash_threads.restype = ctypes.c_int
         lib.oracle_mul.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                    ctypes.c_void_p]
         lib.oracle_mul.restype = ctypes.c_int
@@ -68,12 +71,13 @@ def plan(n: int, r: int, gamma: int = 0):
     return st, g.value, k.value
 
 
-def hash(key, n: int, r: int, gamma: int, a, b, c, stages: bool = False):
+def hash(key, n: int, r: int, gamma: int, a, b, c, stages: bool = False, threads: int = 1):
     """Evaluate the hash with the C oracle.
 
     key: ceil(n/64) uint64 words; a: k*W words; b, c: W words, W = ceil(gamma/64).
     Returns (status, out) or, with ``stages``, (status, out, y, U) where out is
-    ceil(r/64) uint64 words and y, U are W-word arrays."""
+    ceil(r/64) uint64 words and y, U are W-word arrays.  threads > 1 spreads
+    the k products of the MMH sum over that many threads (same result)."""
     W = (gamma + 63) // 64
     key = np.ascontiguousarray(key, dtype=np.uint64)
     a = np.ascontiguousarray(a, dtype=np.uint64)
@@ -82,8 +86,12 @@ def hash(key, n: int, r: int, gamma: int, a, b, c, stages: bool = False):
     out = np.zeros((r + 63) // 64, dtype=np.uint64)
     y = np.zeros(W, dtype=np.uint64) if stages else None
     U = np.zeros(W, dtype=np.uint64) if stages else None
-    st = _load().oracle_hash(_ptr(key), n, r, gamma, _ptr(a), _ptr(b), _ptr(c), _ptr(out),
-                             _ptr(y), _ptr(U))
+    if threads > 1:
+        st = _load().oracle_hash_threads(_ptr(key), n, r, gamma, _ptr(a), _ptr(b), _ptr(c), _ptr(out),
+                                         _ptr(y), _ptr(U), int(threads))
+    else:
+        st = _load().oracle_hash(_ptr(key), n, r, gamma, _ptr(a), _ptr(b), _ptr(c), _ptr(out),
+                                 _ptr(y), _ptr(U))
     if stages:
         return st, out, y, U
     return st, out

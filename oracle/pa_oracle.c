@@ -23,6 +23,7 @@
  * if any seed word has bits >= gamma set, else SEED_B_EVEN (-5) if b is even,
  * else RELOAD (2) if some chunk is all ones, else OK (0).
  */
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -218,6 +219,35 @@ static void mod_mersenne(u64 *v, size_t nv, u64 gamma, size_t W) {
     if (all_ones) memset(v, 0, W * sizeof(u64));
 }
 
+/* The terms a_i x_i of the MMH sum (Sec. 2.1 eq. 2) for i in [i0, i1), added
+ * into S (ns words).  Integer addition is exact and associative, so partial
+ * sums over disjoint ranges of i add up to the same S. */
+struct partial_sum {
+    const u64 *key, *a;
+    u64 n, g, i0, i1;
+    size_t W, ns;
+    u64 *S;
+    int err;
+};
+
+static void *add_terms(void *arg) {
+    struct partial_sum *P = (struct partial_sum *)arg;
+    u64 *x = (u64 *)calloc(P->W, sizeof(u64));
+    u64 *prod = (u64 *)calloc(2 * P->W, sizeof(u64));
+    if (!x || !prod) P->err = 1;
+    for (u64 i = P->i0; i < P->i1 && !P->err; i++) {
+        extract_bits(P->key, P->n, i * P->g, P->g, x, P->W);
+        if (mul_equal(P->a + i * P->W, x, P->W, prod)) { P->err = 1; break; }
+        add_into(P->S, P->ns, prod, 2 * P->W);
+    }
+    free(x);
+    free(prod);
+    return NULL;
+}
+
+static int hash_impl(const u64 *key, u64 n, u64 r, u64 gamma, const u64 *a, const u64 *b, const u64 *c,
+                     u64 *out, u64 *y_out, u64 *U_out, int nthreads);
+
 /*
  * Full hash.  key: ceil(n/64) words; a: k*W words; b, c: W words, W = ceil(gamma/64);
  * out: ceil(r/64) words.  y_out and U_out (W words each, may be NULL) receive
@@ -225,6 +255,19 @@ static void mod_mersenne(u64 *v, size_t nv, u64 gamma, size_t W) {
  */
 int oracle_hash(const u64 *key, u64 n, u64 r, u64 gamma, const u64 *a, const u64 *b,
                 const u64 *c, u64 *out, u64 *y_out, u64 *U_out) {
+    return hash_impl(key, n, r, gamma, a, b, c, out, y_out, U_out, 1);
+}
+
+/* The same with the k products of the MMH sum spread over up to `nthreads`
+ * threads (contiguous ranges of i, each summed apart, then the partial sums
+ * added); every other step as in oracle_hash.  For timing on several cores. */
+int oracle_hash_threads(const u64 *key, u64 n, u64 r, u64 gamma, const u64 *a, const u64 *b,
+                        const u64 *c, u64 *out, u64 *y_out, u64 *U_out, int nthreads) {
+    return hash_impl(key, n, r, gamma, a, b, c, out, y_out, U_out, nthreads < 1 ? 1 : nthreads);
+}
+
+static int hash_impl(const u64 *key, u64 n, u64 r, u64 gamma, const u64 *a, const u64 *b, const u64 *c,
+                     u64 *out, u64 *y_out, u64 *U_out, int nthreads) {
     u64 g, k;
     int st = oracle_plan(n, r, gamma, &g, &k);
     if (st) return st;
@@ -255,12 +298,43 @@ int oracle_hash(const u64 *key, u64 n, u64 r, u64 gamma, const u64 *a, const u64
         if (all_ones) { free(x); free(prod); free(S); return O_RELOAD; }
     }
 
-    /* S = sum_i a_i x_i, exact */
-    for (u64 i = 0; i < k; i++) {
-        extract_bits(key, n, i * g, g, x, W);
-        if (mul_equal(a + i * W, x, W, prod)) { free(x); free(prod); free(S); return O_ERR_NOMEM; }
-        add_into(S, ns, prod, 2 * W);
+    /* S = sum_i a_i x_i, exact: T contiguous ranges of i, one partial sum each */
+    u64 T = (u64)nthreads < k ? (u64)nthreads : k;
+    struct partial_sum *parts = (struct partial_sum *)calloc(T, sizeof(struct partial_sum));
+    pthread_t *tid = (pthread_t *)calloc(T, sizeof(pthread_t));
+    int bad = !parts || !tid;
+    for (u64 t = 0; t < T && !bad; t++) {
+        struct partial_sum *P = &parts[t];
+        P->key = key;
+        P->a = a;
+        P->n = n;
+        P->g = g;
+        P->i0 = k * t / T;
+        P->i1 = k * (t + 1) / T;
+        P->W = W;
+        P->ns = ns;
+        P->S = t == 0 ? S : (u64 *)calloc(ns, sizeof(u64));
+        if (!P->S) bad = 1;
     }
+    u64 started = 0; /* threads 1..started were created */
+    for (u64 t = 1; t < T && !bad; t++) {
+        if (pthread_create(&tid[t], NULL, add_terms, &parts[t]))
+            bad = 1;
+        else
+            started = t;
+    }
+    if (!bad) add_terms(&parts[0]);
+    for (u64 t = 1; t <= started; t++) pthread_join(tid[t], NULL);
+    for (u64 t = 0; t < T && parts; t++) {
+        bad |= parts[t].err;
+        if (t > 0 && parts[t].S) {
+            if (!bad) add_into(S, ns, parts[t].S, ns);
+            free(parts[t].S);
+        }
+    }
+    free(parts);
+    free(tid);
+    if (bad) { free(x); free(prod); free(S); return O_ERR_NOMEM; }
     /* y = S mod p */
     mod_mersenne(S, ns, g, W);
     if (y_out) memcpy(y_out, S, W * sizeof(u64));

@@ -378,3 +378,26 @@ def test_c_oracle_matches_definition_one_mib_block():
     s1, z1, y1, U1 = defn.hash_words(blk.key, n, n // 10, g, blk.a, blk.b, blk.c)
     s2, out = oracle.hash(blk.key, n, n // 10, g, blk.a, blk.b, blk.c)
     assert s1 == s2 == 0 and defn.words_to_int(out) == z1
+
+
+def test_threaded_oracle_matches_single_thread():
+    """The threaded evaluation (the k products of the MMH sum over several
+    threads, partial sums added) gives the single-threaded oracle's output
+    and stage values for k = 1 .. 13 and thread counts 2 .. 16, statuses
+    included (an all-ones chunk reloads)."""
+    rng = random.Random(77)
+    for t in range(40):
+        g = rng.choice([89, 521, 4423, 9689, 44497])
+        k = rng.randrange(1, 14)
+        n = k * g - rng.randrange(0, g // 2)
+        r = rng.randrange(1, g)
+        st, gg, kk = defn.plan_shape(n, r, g)
+        blk = synth.single_block(500 + t, n, r, gg, kk)
+        if t % 13 == 5:
+            blk.key[:] = np.uint64(0xFFFFFFFFFFFFFFFF)
+            synth.mask_tail(blk.key, n)
+        want = oracle.hash(blk.key, n, r, gg, blk.a, blk.b, blk.c, stages=True)
+        got = oracle.hash(blk.key, n, r, gg, blk.a, blk.b, blk.c, stages=True, threads=rng.choice([2, 3, 5, 16]))
+        assert got[0] == want[0], (t, got[0], want[0])
+        for x, y in zip(got[1:], want[1:]):
+            assert np.array_equal(x, y), t
