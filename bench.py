@@ -3,7 +3,7 @@
 
 Workload: one 2.6e8-bit block (n = 260,000,000, r = n/10, i.i.d. uniform key
 bits and uniform seeds from splitmix64 seed 2) -- gamma = 30,402,457, k = 9,
-NTT length 2^22.  A step is one complete hash of that block (every kernel of
+32-bit limbs, NTT length 2^21.  A step is one complete hash of that block (every kernel of
 the path: seed checks, unpack, NTTs, multiply-accumulate, fold, MH product,
 carry, truncation); steps are enqueued back to back on one stream with the
 inputs already resident in HBM, and the timed region is bracketed by
@@ -12,8 +12,12 @@ synchronisations.  The metric is input Mbit/s = n * steps / seconds.
 Prints one JSON line.  Extra objects: `roofline` for the dominant kernel
 (duration from HIP events recorded by the library on the same stream during
 the timed region; HBM bytes per launch from the committed rocprofv3 counter
-summary when it was taken on the current sources, else null) and
-`cpu_baseline` (the CPU oracle on a bounded sample).
+summary when it was taken on the current sources, else null), `batched`
+(the uneven-batch workload: 64 blocks in one pa_hash_batched call against
+the same blocks as 64 serial calls, outputs checked against the oracle's
+stored digests) and `cpu_baseline` (the CPU oracle on the same block, its
+k products on min(k, nproc) threads; a single-thread sample and the Python
+definition on the 2^20-bit block beside it).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 """
@@ -135,15 +139,29 @@ def small_block(pa, synth, dev, K):
 
 
 def kernel_name(phase, info):
-    """Symbol (as profilers print it) of the kernel a transform phase launches."""
+    """Symbol (as profilers print it) of the kernel a transform phase launches,
+    by the library's launch rule: rows of 4096 words run k_row16; columns of
+    512 rows in tiles of 16 columns run k_col9_*; columns of 1024 rows in
+    tiles of 8 run k_col10_* (the forward key-chunk pass of lengths 3 * 2^m
+    excepted); everything else the generic kernels."""
     stage = 0 if phase.startswith("mmh") else 1
+    m1, m2, mix = info["log2N1"], info["log2N2"], info["len_factor"] == 3
     if phase.endswith("_row"):
-        base = "k_row16" if info["log2N2"] == 12 else "k_row"
-    elif phase.endswith("_colinv"):
-        base = "k_col9_inv" if info["log2N1"] == 9 and info["log2N2"] >= 4 else "k_col_inv"
-    else:
-        base = "k_col9_fwd" if info["log2N1"] == 9 and info["log2N2"] >= 4 else "k_col_fwd"
-    return f"{base}<{stage}>"
+        return f"k_row16<{stage}>" if m2 == 12 else f"k_row<{stage}>"
+    if phase.endswith("_colinv"):
+        if m1 == 9 and m2 >= 4:
+            return f"k_col9_inv<{stage}>"
+        if m1 == 10 and m2 >= 3:
+            return f"k_col10_inv<{stage}>"
+        return f"k_col_inv<{stage}>"
+    fit = lambda c: min(c, m2, 14 - m1)  # noqa: E731  (the column-tile width rule)
+    c_lg = info["col_lg"] if stage == 0 else fit(3 if m1 == 10 else 4)
+    flag = "true" if mix else "false"
+    if m1 == 10 and c_lg == 3 and (not mix or stage == 1):
+        return f"k_col10_fwd<{stage}, {flag}>"
+    if m1 == 9 and c_lg == 4:
+        return f"k_col9_fwd<{stage}, {flag}>"
+    return f"k_col_fwd<{stage}, {flag}>"
 
 
 # Peak butterfly rate of the VALU for this arithmetic: a radix-2 butterfly
@@ -157,14 +175,29 @@ PEAK_BFLY_PER_S = CUS * LANES_PER_CU * CLOCK_GHZ * 1e9 / BFLY_LANE_CYCLES
 
 
 def cpu_baseline(blk, info, budget_chunks=2):
-    """Time the CPU oracle on a bounded sample of the same workload: the first
-    `budget_chunks` chunks of the block's key with the block's own seeds
-    (a prefix block of budget_chunks * gamma bits, same gamma and r).  The
-    oracle's cost is (chunks + 1) gamma-bit products, so the full-block time
-    is scaled by (k + 1) / (budget_chunks + 1)."""
+    """The CPU oracle on the host's cores, untuned.  `value`: the whole block
+    with the oracle's k products (Sec. 2.1 eq. 2) spread over min(k, nproc)
+    threads (its b*y product and the rest on one), output checked against
+    the oracle's stored digest.  `single_thread`: the first `budget_chunks`
+    chunks of the block's key with the block's own seeds (a prefix block of
+    budget_chunks * gamma bits, same gamma and r) on one thread, scaled by
+    (k + 1) / (budget_chunks + 1) products to the full block.
+    `python_definition`: the Python-int definition on the 2^20-bit block."""
     import oracle
+    from oracle import defn
+    from paper_2105_13678_amd import synth
     g, k = info["gamma"], info["k"]
     W = (g + 63) // 64
+    threads = max(1, min(k, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    st_t, out_t = oracle.hash(blk.key, N_BITS, R_BITS, g, blk.a, blk.b, blk.c, threads=threads)
+    dt_t = time.perf_counter() - t0
+    ok = None
+    gpath = os.path.join(ROOT, "tests", "golden", "full_size.json")
+    if os.path.exists(gpath):
+        gold = json.load(open(gpath)).get("single_block_2p6e8")
+        if gold:
+            ok = hashlib.sha256(np.ascontiguousarray(out_t).tobytes()).hexdigest() == gold["out_sha256"]
     n_s = budget_chunks * g
     key_s = blk.key[: (n_s + 63) // 64].copy()
     if n_s % 64:
@@ -174,15 +207,30 @@ def cpu_baseline(blk, info, budget_chunks=2):
     st, _ = oracle.hash(key_s, n_s, R_BITS, g, a_s, blk.b, blk.c)
     dt = time.perf_counter() - t0
     full = dt * (k + 1) / (budget_chunks + 1)
+    n1, r1 = 1 << 20, (1 << 20) // 10
+    s1, g1, k1 = defn.plan_shape(n1, r1)
+    b1 = synth.single_block(1, n1, r1, g1, k1)
+    t0 = time.perf_counter()
+    defn.hash_words(b1.key, n1, r1, g1, b1.a, b1.b, b1.c)
+    dt_py = time.perf_counter() - t0
     return {
-        "value": round(N_BITS / full / 1e6, 3),
+        "value": round(N_BITS / dt_t / 1e6, 3),
         "unit": "Mbit/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": (f"C oracle (schoolbook+Karatsuba, 1 thread) on a {budget_chunks}-chunk prefix block "
-                   f"({n_s} bits, gamma={g}, r={R_BITS}, same seeds): {dt:.2f} s for {budget_chunks + 1} "
-                   f"products, scaled x{(k + 1) / (budget_chunks + 1):.3f} to the k={k} block"),
-        "status": int(st),
+        "sample": (f"C oracle (schoolbook+Karatsuba) on the whole block, its k={k} products on {threads} threads "
+                   f"(the b*y product and the rest on one): {dt_t:.2f} s"),
+        "status": int(st_t),
+        "verified_vs_oracle_digest": ok,
+        "single_thread": {
+            "value": round(N_BITS / full / 1e6, 3), "unit": "Mbit/s", "cores": 1,
+            "sample": (f"C oracle, 1 thread, on a {budget_chunks}-chunk prefix block ({n_s} bits, gamma={g}, "
+                       f"r={R_BITS}, same seeds): {dt:.2f} s for {budget_chunks + 1} products, scaled "
+                       f"x{(k + 1) / (budget_chunks + 1):.3f} to the k={k} block"),
+            "status": int(st)},
+        "python_definition": {
+            "value": round(n1 / dt_py / 1e6, 3), "unit": "Mbit/s", "cores": 1,
+            "sample": f"Python-int definition on the 2^20-bit block (r = n/10, gamma={g1}, k={k1}): {dt_py:.3f} s"},
         "host": {"cpu_model": cpu_model(), "nproc": os.cpu_count()},
     }
 
@@ -228,46 +276,51 @@ def step_stats(plan, key, a, b, c, out, K, dev):
 BATCH_SEED, BATCH_COUNT = 3, 64
 
 
-def bench_batched(args):
-    """64 blocks of uneven size (splitmix64 seed 3: n log-uniform in
-    [2^22, 2^28], r/n uniform in [0.05, 0.30]; all shapes drawn first, then
-    each block's key and seeds) hashed by one pa_hash_batched call per step,
-    against the same blocks as 64 back-to-back pa_hash_async calls on one
-    stream (plans created beforehand).  Outputs of the two must agree."""
-    import torch
-    import paper_2105_13678_amd as pa
-    from paper_2105_13678_amd import synth
-
+def batched_blocks(pa, synth, dev):
+    """The uneven-batch workload: 64 blocks (splitmix64 seed 3: n log-uniform
+    in [2^22, 2^28], r/n uniform in [0.05, 0.30]; all shapes drawn first, then
+    each block's key and seeds), uploaded; returns (blocks, device buffers)."""
     def shape(n, r):  # the library's own plan rule
         st, info = pa.plan_query(n, r)
         assert st == 0, (n, r, st)
         return info["gamma"], info["k"]
 
     blocks = synth.uneven_blocks(BATCH_SEED, BATCH_COUNT, shape, 22, 28)
-    total = sum(b.n for b in blocks)
-    log(f"[bench] batched: {len(blocks)} blocks, {total} key bits")
-    dev = torch.device("cuda", 0)
     bufs = []
     for b in blocks:
         key, a, bb, c = (pa.to_device(x, dev) for x in (b.key, b.a, b.b, b.c))
         bufs.append([b.n, b.r, key, a, bb, c, pa.BatchPlan.new_out(b.r, dev)])
-    K, Wm = args.steps, max(1, args.warmup)
+    return blocks, bufs
+
+
+def batched_leg(pa, blocks, bufs, dev, K, Wm):
+    """One pa_hash_batched call per step over the 64 blocks (HIP events around
+    each call: mean, p50 and p99 of the call time) against the same blocks as
+    64 back-to-back pa_hash_async calls on one stream (plans created
+    beforehand); outputs of both checked against the oracle's stored digests
+    of this draw.  Returns the record and the batch plan (open)."""
+    import torch
+    total = sum(b.n for b in blocks)
     stream = torch.cuda.current_stream(dev)
     bp = pa.BatchPlan(len(blocks), total)
     for _ in range(Wm):
         st, per = bp.hash(bufs)
         assert st == 0 and all(x == 0 for x in per), per
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(K):
-        bp.hash(bufs)
-    ev1.record(stream)
+    for e0, e1 in evs:
+        e0.record(stream)
+        st, per = bp.hash(bufs)
+        e1.record(stream)
+        assert st == 0 and all(x == 0 for x in per), per
     torch.cuda.synchronize()
-    wall_b = time.perf_counter() - t0
-    ms_b = ev0.elapsed_time(ev1) / K
-    outs_b = [x[6].clone() for x in bufs]
+    wall_b = (time.perf_counter() - t0) / K * 1e3
+    calls = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+    ms_b = sum(calls) / K
+    outs_b = [pa.from_device(x[6]) for x in bufs]
+    for x in bufs:
+        x[6].zero_()
 
     plans = [pa.Plan(b.n, b.r) for b in blocks]
     d_status = torch.zeros(len(blocks), dtype=torch.int32, device=dev)
@@ -275,19 +328,68 @@ def bench_batched(args):
         for i, (p, x) in enumerate(zip(plans, bufs)):
             p.hash_async(*x[2:7], d_status[i:i + 1])
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     for _ in range(K):
         for i, (p, x) in enumerate(zip(plans, bufs)):
             p.hash_async(*x[2:7], d_status[i:i + 1])
     ev1.record(stream)
     torch.cuda.synchronize()
-    wall_s = time.perf_counter() - t0
     ms_s = ev0.elapsed_time(ev1) / K
-    same = all(torch.equal(o, x[6]) for o, x in zip(outs_b, bufs))
     assert (d_status.cpu().numpy() == 0).all()
+    outs_s = [pa.from_device(x[6]) for x in bufs]
     for p in plans:
         p.close()
+    verified = None
+    gpath = os.path.join(ROOT, "tests", "golden", "full_size.json")
+    gold = json.load(open(gpath)) if os.path.exists(gpath) else {}
+    keys = [f"batched_seed3_64/{i}" for i in range(len(blocks))]
+    if all(k in gold for k in keys):
+        verified = True
+        for k, b, ob, os_ in zip(keys, blocks, outs_b, outs_s):
+            g = gold[k]
+            assert (g["n"], g["r"]) == (b.n, b.r)
+            want = g["out_sha256"]
+            verified &= hashlib.sha256(ob.tobytes()).hexdigest() == want
+            verified &= hashlib.sha256(os_.tobytes()).hexdigest() == want
+    log(f"[bench] batched {ms_b:.3f} ms/call (p99 {calls[min(K - 1, math.ceil(0.99 * K) - 1)]:.3f}, "
+        f"wall {wall_b:.3f}), serial {ms_s:.3f} ms; digests verified: {verified}")
+    rec = {
+        "workload": f"{len(blocks)} uneven blocks, splitmix64 seed {BATCH_SEED}, n log-uniform in [2^22, 2^28], "
+                    f"r/n in [0.05, 0.30]",
+        "total_bits": total,
+        "value": round(total / (ms_b / 1e3) / 1e6, 1),
+        "unit": "Mbit/s",
+        "calls": K,
+        "ms_per_call": round(ms_b, 4),
+        "p50_ms": round(calls[K // 2], 4),
+        "p99_ms": round(calls[min(K - 1, math.ceil(0.99 * K) - 1)], 4),
+        "wall_ms_per_call": round(wall_b, 4),
+        "serial_per_block": {"value": round(total / (ms_s / 1e3) / 1e6, 1), "unit": "Mbit/s",
+                             "ms_per_step": round(ms_s, 4),
+                             "what": "the same blocks as 64 back-to-back pa_hash_async calls on one stream"},
+        "speedup_vs_serial": round(ms_s / ms_b, 3),
+        "verified_vs_oracle_digest": verified,
+    }
+    return rec, bp
+
+
+def bench_batched(args):
+    """The uneven-batch workload (batched_leg), plus the same call after the
+    autotuner has timed each (gamma, k) class, plus 64 small blocks (where
+    launches, not the GPU, bound a call)."""
+    import torch
+    import paper_2105_13678_amd as pa
+    from paper_2105_13678_amd import synth
+
+    dev = torch.device("cuda", 0)
+    blocks, bufs = batched_blocks(pa, synth, dev)
+    total = sum(b.n for b in blocks)
+    log(f"[bench] batched: {len(blocks)} blocks, {total} key bits")
+    K, Wm = args.steps, max(1, args.warmup)
+    leg, bp = batched_leg(pa, blocks, bufs, dev, K, Wm)
+    outs_b = [x[6].clone() for x in bufs]
+    stream = torch.cuda.current_stream(dev)
 
     # autotuned: each (gamma, k) class timed on the device once (limb width,
     # length form, column-tile width), then the same batched call
@@ -298,6 +400,7 @@ def bench_batched(args):
         st, per = bp.hash(bufs)
         assert st == 0 and all(x == 0 for x in per), per
     torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     for _ in range(K):
         bp.hash(bufs)
@@ -308,29 +411,21 @@ def bench_batched(args):
     bp.close()
     log(f"[bench] batched autotuned ({ntuned} classes, {tune_s:.1f} s): {ms_t:.3f} ms/call")
     small = batched_small_blocks(pa, synth, dev, K, Wm)
-    log(f"[bench] batched {ms_b:.3f} ms/call (wall {wall_b / K * 1e3:.3f}), serial {ms_s:.3f} ms "
-        f"(wall {wall_s / K * 1e3:.3f})")
     rec = {
         "metric": "PA batched input throughput (Mbit/s), 64 uneven blocks in one call, bit-exact",
-        "value": round(total / (ms_b / 1e3) / 1e6, 1),
+        "value": leg["value"],
         "unit": "Mbit/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": Wm,
-        "ms_per_step": round(ms_b, 4),
+        "ms_per_step": leg["ms_per_call"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32 (exact integer NTTs mod three 30-bit primes, CRT to 96-bit coefficients)",
         "data": "synthetic",
-        "config": {"workload": f"{len(blocks)} uneven blocks, splitmix64 seed {BATCH_SEED}, n log-uniform in "
-                               f"[2^22, 2^28], r/n in [0.05, 0.30]", "total_bits": total,
-                   "parallelism": "single GPU"},
-        "serial_per_block": {"value": round(total / (ms_s / 1e3) / 1e6, 1), "unit": "Mbit/s",
-                             "ms_per_step": round(ms_s, 4),
-                             "what": "the same blocks as back-to-back pa_hash_async calls on one stream"},
-        "speedup_vs_serial": round(ms_s / ms_b, 3),
-        "outputs_equal_serial": same,
+        "config": {"workload": leg["workload"], "total_bits": total, "parallelism": "single GPU"},
+        "batched": leg,
         "autotuned": {"value": round(total / (ms_t / 1e3) / 1e6, 1), "unit": "Mbit/s", "ms_per_step": round(ms_t, 4),
                       "classes_tuned": ntuned, "tuning_seconds": round(tune_s, 2), "outputs_equal": same_t,
                       "what": "the same call after pa_batch_plan_tune (one-time device timing per (gamma, k) class)"},
@@ -555,6 +650,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="single: skip the uneven-batch leg (64 blocks, one batched call against serial calls)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed region, copy a buffer of this many MiB with a plain device "
                          "copy kernel (reference point for the HBM byte counters)")
@@ -692,6 +789,13 @@ def main():
         rec["pipelined"] = pipelined(pa, plan, key, a, b, c, K, args.pipeline, dev, gold_digest=gold_digest)
     if not args.core_only:
         rec["small_block_2p20"] = small_block(pa, synth, dev, K)
+    if not args.core_only and not args.no_batched:
+        blocks, bufs = batched_blocks(pa, synth, dev)
+        leg, bp = batched_leg(pa, blocks, bufs, dev, max(5, K // 2), 2)
+        bp.close()
+        rec["batched"] = leg
+        del blocks, bufs
+        torch.cuda.empty_cache()
     if args.calib_copy_mib:
         src = torch.ones(args.calib_copy_mib << 17, dtype=torch.int64, device=dev)
         dst = torch.empty_like(src)

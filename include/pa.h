@@ -251,11 +251,13 @@ pa_status pa_batch_plan_set_graphs(pa_batch_plan *plan, int enable);
  * return the fastest in *best (B, flags and col_lg set explicitly; n, r,
  * gamma copied) and its time per hash in *best_ms (nullable).  Candidates:
  * for each length form admitted by params->flags, the plan rule's limb width
- * for that form (or params->B), with the rule's column-tile width and its
- * neighbours (or params->col_lg).  Each candidate gets its own plan, one
- * warm-up hash and `reps` (1..1000) timed hashes of an all-zero key with
- * zero seeds (b = 1) on a private stream; the device must have room for
- * one plan at a time.  Blocks until done.  Returns the plan errors of
+ * for that form and the next narrower exact width that changes the transform
+ * length (or params->B alone), each with the rule's column-tile width and its
+ * neighbours (or params->col_lg).  Every candidate gets its own plan (those
+ * that do not fit in free device memory are skipped) and one warm-up hash;
+ * then 5 rounds time `reps` (1..1000) hashes of each candidate in turn, on a
+ * private stream, with a random valid key and seeds; a candidate's time is
+ * the median of its rounds.  Blocks until done.  Returns the plan errors of
  * *params, PA_ERR_ARG, PA_ERR_NOMEM (no candidate fitted) or PA_ERR_DEVICE. */
 pa_status pa_plan_tune(const pa_params *params, int hip_device, uint32_t reps, pa_params *best,
                        double *best_ms);
@@ -276,9 +278,10 @@ pa_status pa_batch_plan_tune(pa_batch_plan *plan, const pa_block *blocks, uint32
  *
  * Each session agrees its random seeds a, b, c (Alg. 1's inputs) once per
  * output class gamma and registers them with pa_server_set_seeds; they stay
- * on the device, and so do their transforms (built the first time a request
- * of a given transform shape needs them, outside the budget), so a request
- * costs k + 3 transforms instead of 2k + 4.  A request then carries only its key (host memory in, the
+ * on the device, and so do their transforms (built on a stream of their own
+ * the first time a request of a given transform shape needs them, inside the
+ * resident budget, without holding up other requests), so a request costs
+ * k + 3 transforms instead of 2k + 4.  A request then carries only its key (host memory in, the
  * r-bit output to host memory out).  pa_submit queues it and returns a
  * ticket at once; a worker thread admits requests in arrival order while one
  * of max_inflight slots is free and the request's device memory (scratch,
@@ -290,9 +293,17 @@ pa_status pa_batch_plan_tune(pa_batch_plan *plan, const pa_block *blocks, uint32
 typedef struct pa_server_cfg {
     int device;                /* HIP device                                     */
     uint32_t max_inflight;     /* requests running at once, 1..64 (one stream each) */
-    uint64_t hbm_budget_bytes; /* device memory for admitted requests, allocated
-                                  once at creation (twiddle tables and resident
-                                  seeds are outside it)                          */
+    uint64_t hbm_budget_bytes; /* device memory for admitted requests (scratch,
+                                  key, output), allocated once at creation     */
+    uint64_t resident_budget_bytes; /* device memory for the resident sets: the
+                                  twiddle tables of each transform length and
+                                  the seed transforms of each (session, gamma,
+                                  transform shape), allocated once at creation;
+                                  sets no admitted request holds are evicted
+                                  least recently used first when a new set needs
+                                  room; 0: the same as hbm_budget_bytes.  The
+                                  registered seeds themselves (8 (kmax + 2) W
+                                  bytes each) are outside both budgets        */
 } pa_server_cfg;
 
 typedef struct pa_request {
@@ -332,7 +343,10 @@ pa_status pa_server_set_seeds(pa_server *server, uint32_t session, uint64_t gamm
 /* Queue a request; *ticket identifies it.  Returns at once: a plan error for
  * (n, r), PA_ERR_ARG when the session has no seeds for the request's gamma
  * (or too few chunks), PA_ERR_LIMIT when the request alone exceeds the
- * budget, PA_ERR_BUSY while the server is stopping, else PA_OK. */
+ * budget or its twiddle tables and seed transforms together exceed the
+ * resident budget, PA_ERR_BUSY while the server is stopping, else PA_OK.  A
+ * queued request is admitted when a slot is free, its memory fits the
+ * budget and its resident sets are present or can be placed. */
 pa_status pa_submit(pa_server *server, const pa_request *request, uint64_t *ticket);
 
 /* PA_PENDING while the request is queued or running; PA_OK once it is done,
@@ -352,8 +366,8 @@ typedef enum pa_phase {
     PA_PH_MH_COL = 5,     /* unpack + forward column pass of y and b         */
     PA_PH_MH_ROW = 6,     /* row pass: forward, multiply, inverse            */
     PA_PH_MH_COLINV = 7,  /* inverse column pass                             */
-    PA_PH_MH_CARRY = 8,   /* + c, carry scan mod 2^gamma -> U                 */
-    PA_PH_FINISH = 9,     /* output extraction, status                       */
+    PA_PH_MH_CARRY = 8,   /* + c, carry scan mod 2^gamma -> U, output z, status */
+    PA_PH_FINISH = 9,     /* pa_hash_stages only: y and U packed into words  */
     PA_PH_COUNT = 10
 } pa_phase;
 

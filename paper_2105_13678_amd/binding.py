@@ -61,7 +61,8 @@ _VP = ctypes.c_void_p
 
 
 class ServerCfg(ctypes.Structure):
-    _fields_ = [("device", ctypes.c_int), ("max_inflight", ctypes.c_uint32), ("hbm_budget_bytes", ctypes.c_uint64)]
+    _fields_ = [("device", ctypes.c_int), ("max_inflight", ctypes.c_uint32), ("hbm_budget_bytes", ctypes.c_uint64),
+                ("resident_budget_bytes", ctypes.c_uint64)]
 
 
 class Request(ctypes.Structure):
@@ -423,10 +424,10 @@ def _host_ptr(x, min_words: int, what: str) -> int:
 class Server:
     """Serving loop (pa_server_*): submit requests, poll tickets."""
 
-    def __init__(self, max_inflight: int, hbm_budget_bytes: int, device: int = 0):
+    def __init__(self, max_inflight: int, hbm_budget_bytes: int, device: int = 0, resident_budget_bytes: int = 0):
         self._h = _VP()
         self._live = {}  # ticket -> buffers kept alive until the request is done
-        cfg = ServerCfg(int(device), int(max_inflight), int(hbm_budget_bytes))
+        cfg = ServerCfg(int(device), int(max_inflight), int(hbm_budget_bytes), int(resident_budget_bytes))
         st = lib().pa_server_create(ctypes.byref(cfg), ctypes.byref(self._h))
         if st != PA_OK:
             self._h = _VP()

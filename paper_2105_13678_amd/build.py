@@ -21,8 +21,8 @@ LIB = os.path.join(HERE, "libpa.so")
 ARCH = "gfx950"
 
 SOURCES = ["pa_api.cpp", "pa_batch.cpp", "pa_server.cpp", "pa_tune.cpp", "pa_kernels.hip", "pa_noalloc.hip"]
-HEADERS = ["pa_internal.hpp", "ntt_device.hpp"]
-DEVICE_SOURCES = ["pa_kernels.hip", "ntt_device.hpp"]
+HEADERS = ["pa_internal.hpp", "ntt_device.hpp", "pa_multi.hpp", "pa_resident.hpp"]
+DEVICE_SOURCES = ["pa_kernels.hip", "ntt_device.hpp", "pa_multi.hpp"]
 
 
 def _code_only(text: str) -> str:

@@ -307,8 +307,8 @@ pa_status enqueue_hash(pa_plan *p, const uint64_t *key, const uint64_t *a, const
     hipError_t e = pa::launch_prologue(p, a, b, c, st);
     if (e == hipSuccess) e = pa::launch_mmh(p, key, a, st);
     if (e == hipSuccess) e = pa::launch_fold(p, st);
-    if (e == hipSuccess) e = pa::launch_mh(p, b, c, st);
-    if (e == hipSuccess) e = pa::launch_finish(p, out, d_status, y_out, U_out, st);
+    if (e == hipSuccess) e = pa::launch_mh(p, b, c, out, d_status, st);
+    if (e == hipSuccess && (y_out || U_out)) e = pa::launch_finish(p, y_out, U_out, st);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return PA_ERR_DEVICE;

@@ -1,19 +1,26 @@
 // Batched hashing of independent blocks of uneven size in one call.
 //
-// A batch plan owns (a) the twiddle tables of every transform length it has
-// met, built once and reused across calls, and (b) a few worker streams, each
-// with a scratch arena sized for the largest block it has run.  A call derives
-// each block's plan on the host, spreads the blocks over the worker streams
-// (longest first, each to the least-loaded stream), forks the workers from
-// the caller's stream, enqueues every block's kernel sequence on its worker,
-// and joins back.  Blocks whose transforms cannot fill the GPU alone (short
-// rows, single-workgroup scan steps) then run side by side.  With graphs on,
-// the fork / launches / join of a block list is captured once into a HIP
-// graph and replayed by later calls with the same list.
+// A call derives each block's plan on the host and records each block's
+// kernel launches (the same sequence pa_hash runs, each launch tagged with
+// its step) instead of launching them.  Every step is then run for all
+// blocks at once: the launches of one step that use the same kernel instance
+// (same workgroup size and dynamic LDS) become one multi-block launch, whose
+// workgroups find their block and their position in that block's grid in a
+// small table (block placement, owner of each 8 workgroups, the blocks'
+// argument structs) uploaded once per call.  A 64-block call then issues a
+// few dozen launches instead of about a thousand, and blocks too small to
+// fill the GPU alone share each launch with the others.  Each block has its
+// own scratch in one arena (all blocks are in flight together); the twiddle
+// tables of every transform length met are built once and kept.  With graphs
+// on, the launches of a block list are captured once into a HIP graph (its
+// tables in a device buffer of its own) and replayed by later calls with the
+// same list.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -21,21 +28,25 @@
 #include <vector>
 
 #include "pa_internal.hpp"
+#include "pa_multi.hpp"
 
 namespace {
-
-constexpr int kLanes = 4;  // worker streams (one per hardware queue HIP gives a process by default)
 
 struct Tables {
     uint32_t len;  // pa::len_key of the transform length
     void *base;
 };
 
-struct Lane {
-    hipStream_t st = nullptr;
-    hipEvent_t done = nullptr;
-    void *arena = nullptr;
-    size_t bytes = 0;
+// One launch of a step: a multi-block launch over `members` (indices into
+// the call's recorded launches), or a plain launch when there is one member.
+struct Group {
+    const void *single, *multi;
+    dim3 block;
+    uint32_t lds;
+    uint32_t args_size;
+    std::vector<const pa::KLaunch *> members;
+    uint32_t total;                 // workgroups of the multi launch
+    size_t o_args, o_geo, o_owner;  // table offsets
 };
 
 // A captured block list: replayable while no arena or table it points into
@@ -44,12 +55,25 @@ struct Captured {
     std::vector<pa_block> blocks;
     uint64_t epoch;
     hipGraphExec_t exec;
+    void *d_tab;  // the list's launch tables
 };
 constexpr size_t kMaxGraphs = 8;
 
 bool same_blocks(const std::vector<pa_block> &v, const pa_block *b, uint32_t count) {
     return v.size() == count && std::memcmp(v.data(), b, count * sizeof(pa_block)) == 0;
 }
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// With PA_DEBUG set in the environment, device errors of a batched call are
+// reported on stderr (the HIP error and the source line).
+pa_status device_error(int line) {
+    static const bool on = std::getenv("PA_DEBUG") != nullptr;
+    const hipError_t e = hipGetLastError();
+    if (on) std::fprintf(stderr, "pa_hash_batched: device error at pa_batch.cpp:%d: %s\n", line, hipGetErrorString(e));
+    return PA_ERR_DEVICE;
+}
+#define PA_DEVICE_ERROR device_error(__LINE__)
 
 }  // namespace
 
@@ -58,8 +82,12 @@ struct pa_batch_plan {
     uint32_t max_blocks;
     uint64_t max_total_bits;
     std::vector<Tables> tables;
-    Lane lanes[kLanes];
-    hipEvent_t fork;
+    void *arena = nullptr;     // every block's scratch, side by side
+    size_t arena_bytes = 0;
+    void *d_tab = nullptr;     // launch tables of the current call
+    size_t d_tab_bytes = 0;
+    unsigned char *h_tab = nullptr;  // pinned staging of the launch tables
+    size_t h_tab_bytes = 0;
     uint32_t *d_status;  // max_blocks words
     uint32_t *h_status;  // pinned copy
     // tuned shapes (pa_batch_plan_tune): (gamma, k) -> limb width, length
@@ -76,24 +104,24 @@ struct pa_batch_plan {
 namespace {
 
 void drop_graphs(pa_batch_plan *bp) {
-    for (Captured &c : bp->graphs) (void)hipGraphExecDestroy(c.exec);
+    for (Captured &c : bp->graphs) {
+        (void)hipGraphExecDestroy(c.exec);
+        (void)hipFree(c.d_tab);
+    }
     bp->graphs.clear();
 }
 
 void destroy(pa_batch_plan *bp) {
     if (bp->cap) (void)hipStreamSynchronize(bp->cap);
+    (void)hipDeviceSynchronize();
     drop_graphs(bp);
     if (bp->cap) (void)hipStreamDestroy(bp->cap);
     if (bp->ev_in) (void)hipEventDestroy(bp->ev_in);
     if (bp->ev_out) (void)hipEventDestroy(bp->ev_out);
-    for (Lane &l : bp->lanes) {
-        if (l.st) (void)hipStreamSynchronize(l.st);
-        if (l.arena) (void)hipFree(l.arena);
-        if (l.done) (void)hipEventDestroy(l.done);
-        if (l.st) (void)hipStreamDestroy(l.st);
-    }
+    if (bp->arena) (void)hipFree(bp->arena);
+    if (bp->d_tab) (void)hipFree(bp->d_tab);
+    if (bp->h_tab) (void)hipHostFree(bp->h_tab);
     for (Tables &t : bp->tables) (void)hipFree(t.base);
-    if (bp->fork) (void)hipEventDestroy(bp->fork);
     if (bp->d_status) (void)hipFree(bp->d_status);
     if (bp->h_status) (void)hipHostFree(bp->h_status);
     (void)hipGetLastError();
@@ -120,6 +148,82 @@ void *tables_for(pa_batch_plan *bp, pa_plan *p, const pa::PlanLayout &lay, hipSt
     return base;
 }
 
+std::vector<pa::MultiMember> members_of(const Group &g) {
+    std::vector<pa::MultiMember> v;
+    for (const pa::KLaunch *L : g.members) v.push_back(pa::MultiMember{L->grid.x, L->grid.y, L->grid.z, L->args});
+    return v;
+}
+
+// Group the recorded launches step by step (same kernel instance, workgroup
+// size and LDS: one launch) and lay out the tables of each multi-block
+// launch (pa_multi.hpp).  Returns the table bytes.
+size_t build_groups(const std::vector<std::vector<pa::KLaunch>> &recs, const std::vector<uint32_t> &order,
+                    std::vector<Group> &groups) {
+    size_t off = 0;
+    for (int step = 0; step < pa::SP_COUNT; ++step) {
+        const size_t first = groups.size();
+        for (uint32_t i : order)
+            for (const pa::KLaunch &L : recs[i]) {
+                if (L.step != step) continue;
+                Group *g = nullptr;
+                for (size_t j = first; j < groups.size(); ++j)
+                    if (groups[j].single == L.single && groups[j].lds == L.lds && groups[j].block.x == L.block.x &&
+                        groups[j].block.y == L.block.y && groups[j].block.z == L.block.z)
+                        g = &groups[j];
+                if (!g) {
+                    groups.push_back(Group{L.single, L.multi, L.block, L.lds, L.args_size, {}, 0, 0, 0, 0});
+                    g = &groups.back();
+                }
+                g->members.push_back(&L);
+            }
+        for (size_t j = first; j < groups.size(); ++j) {
+            Group &g = groups[j];
+            if (g.members.size() == 1) continue;  // a plain launch
+            const pa::MultiLayout lay = pa::multi_layout(members_of(g), g.args_size, off);
+            g.total = lay.total;
+            g.o_args = lay.o_args;
+            g.o_geo = lay.o_geo;
+            g.o_owner = lay.o_owner;
+            off = lay.end;
+        }
+    }
+    return off;
+}
+
+void fill_tables(const std::vector<Group> &groups, unsigned char *h) {
+    for (const Group &g : groups) {
+        if (g.members.size() == 1) continue;
+        const std::vector<pa::MultiMember> mem = members_of(g);
+        const pa::MultiLayout lay = pa::multi_layout(mem, g.args_size, g.o_args);
+        pa::multi_fill(mem, g.args_size, lay, h);
+    }
+}
+
+hipError_t launch_groups(const std::vector<Group> &groups, const unsigned char *d_tab, hipStream_t st) {
+    static const bool dbg = std::getenv("PA_DEBUG") != nullptr;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const Group &g = groups[gi];
+        hipError_t e;
+        if (g.members.size() == 1) {
+            const pa::KLaunch &L = *g.members[0];
+            void *args[] = {(void *)L.args};
+            e = hipLaunchKernel(g.single, L.grid, g.block, args, g.lds, st);
+        } else {
+            const void *tab = d_tab + g.o_args, *geo = d_tab + g.o_geo, *owner = d_tab + g.o_owner;
+            void *args[] = {(void *)&tab, (void *)&geo, (void *)&owner};
+            e = hipLaunchKernel(g.multi, dim3(g.total), g.block, args, g.lds, st);
+        }
+        if (e != hipSuccess) {
+            if (dbg)
+                std::fprintf(stderr, "pa_hash_batched: launch %zu (step %d, %zu blocks, %u workgroups of %u, lds %u): %s\n",
+                             gi, g.members[0]->step, g.members.size(), g.members.size() == 1 ? 0u : g.total,
+                             g.block.x * g.block.y * g.block.z, g.lds, hipGetErrorString(e));
+            return e;
+        }
+    }
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -127,6 +231,7 @@ extern "C" {
 pa_status pa_batch_plan_create(uint32_t max_blocks, uint64_t max_total_bits, int hip_device,
                                pa_batch_plan **out) {
     if (!out || max_blocks == 0 || max_total_bits == 0) return PA_ERR_ARG;
+    if (max_blocks > 65535) return PA_ERR_LIMIT;  // owner tables hold 16-bit block indices
     *out = nullptr;
     pa::DeviceGuard guard(hip_device);
     if (!guard.ok) return PA_ERR_DEVICE;
@@ -135,14 +240,9 @@ pa_status pa_batch_plan_create(uint32_t max_blocks, uint64_t max_total_bits, int
     bp->device = hip_device;
     bp->max_blocks = max_blocks;
     bp->max_total_bits = max_total_bits;
-    bool ok = hipEventCreateWithFlags(&bp->fork, hipEventDisableTiming) == hipSuccess;
-    ok = ok && hipStreamCreateWithFlags(&bp->cap, hipStreamNonBlocking) == hipSuccess;
+    bool ok = hipStreamCreateWithFlags(&bp->cap, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&bp->ev_in, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&bp->ev_out, hipEventDisableTiming) == hipSuccess;
-    for (Lane &l : bp->lanes) {
-        ok = ok && hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking) == hipSuccess;
-        ok = ok && hipEventCreateWithFlags(&l.done, hipEventDisableTiming) == hipSuccess;
-    }
     ok = ok && hipMalloc((void **)&bp->d_status, (size_t)max_blocks * 4) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&bp->h_status, (size_t)max_blocks * 4, hipHostMallocDefault) == hipSuccess;
     if (!ok) {
@@ -167,12 +267,11 @@ pa_status pa_hash_batched(pa_batch_plan *bp, const pa_block *blocks, uint32_t co
     for (uint32_t i = 0; i < count; ++i) total += blocks[i].n;
     if (total > bp->max_total_bits) return PA_ERR_LIMIT;
     pa::DeviceGuard guard(bp->device);
-    if (!guard.ok) return PA_ERR_DEVICE;
+    if (!guard.ok) return PA_DEVICE_ERROR;
 
     // host side: derive every block's plan; host-detectable errors end there
     std::vector<pa_plan> plans(count);
     std::vector<pa::PlanLayout> lays(count);
-    std::vector<double> cost(count, 0.0);
     std::vector<uint32_t> order;
     for (uint32_t i = 0; i < count; ++i) {
         const pa_block &bk = blocks[i];
@@ -190,7 +289,6 @@ pa_status pa_hash_batched(pa_batch_plan *bp, const pa_block *blocks, uint32_t co
         if (per_block[i] == PA_OK && (!bk.key || !bk.a || !bk.b || !bk.c || !bk.out)) per_block[i] = PA_ERR_ARG;
         if (per_block[i] != PA_OK) continue;
         plans[i].device = bp->device;
-        cost[i] = (double)(2 * plans[i].k + 4) * (double)plans[i].N * plans[i].m;
         order.push_back(i);
     }
     if (order.empty()) return PA_OK;
@@ -202,72 +300,81 @@ pa_status pa_hash_batched(pa_batch_plan *bp, const pa_block *blocks, uint32_t co
         pa::bind_tables(&plans[i], tb, lays[i]);
     }
 
-    // longest first, each block to the least-loaded worker
-    std::sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
-    std::vector<uint32_t> lane_of(count, 0);
-    double load[kLanes] = {};
-    size_t need[kLanes] = {};
+    // one scratch region per block, side by side in the arena
+    std::vector<size_t> at(count, 0);
+    size_t need = 0;
     for (uint32_t i : order) {
-        int best = 0;
-        for (int l = 1; l < kLanes; ++l)
-            if (load[l] < load[best]) best = l;
-        lane_of[i] = best;
-        load[best] += cost[i];
-        need[best] = std::max(need[best], lays[i].scratch_bytes);
+        at[i] = need;
+        need = align_up(need + lays[i].scratch_bytes, 256);
     }
-    for (int l = 0; l < kLanes; ++l) {
-        Lane &ln = bp->lanes[l];
-        if (need[l] <= ln.bytes) continue;
-        // grow: the arena may still be in use by an earlier call on this worker
-        // (or by a replayed graph, which runs outside the worker streams)
-        if (ln.arena) {
-            if (hipStreamSynchronize(ln.st) != hipSuccess || hipStreamSynchronize(bp->cap) != hipSuccess ||
-                hipFree(ln.arena) != hipSuccess) {
-                (void)hipGetLastError();
-                return PA_ERR_DEVICE;
-            }
-            ln.arena = nullptr;
-            ln.bytes = 0;
-        }
-        ++bp->epoch;
-        if (hipMalloc(&ln.arena, need[l]) != hipSuccess) {
+    if (need > bp->arena_bytes) {
+        // the arena may still be in use by a replayed graph of an earlier call
+        if (bp->arena && (hipStreamSynchronize(bp->cap) != hipSuccess || hipFree(bp->arena) != hipSuccess)) {
             (void)hipGetLastError();
-            ln.arena = nullptr;
+            return PA_DEVICE_ERROR;
+        }
+        bp->arena = nullptr;
+        bp->arena_bytes = 0;
+        ++bp->epoch;
+        if (hipMalloc(&bp->arena, need) != hipSuccess) {
+            (void)hipGetLastError();
+            bp->arena = nullptr;
             return PA_ERR_NOMEM;
         }
-        ln.bytes = need[l];
+        bp->arena_bytes = need;
     }
 
-    // fork from `origin`, enqueue every block on its worker, join back
-    auto enqueue_all = [&](hipStream_t origin) -> pa_status {
-        if (hipEventRecord(bp->fork, origin) != hipSuccess) return PA_ERR_DEVICE;
-        bool used[kLanes] = {};
-        for (uint32_t i : order) used[lane_of[i]] = true;
-        for (int l = 0; l < kLanes; ++l)
-            if (used[l] && hipStreamWaitEvent(bp->lanes[l].st, bp->fork, 0) != hipSuccess) return PA_ERR_DEVICE;
-        for (uint32_t i : order) {
-            const pa_block &bk = blocks[i];
-            Lane &ln = bp->lanes[lane_of[i]];
-            pa::bind_scratch(&plans[i], ln.arena, lays[i]);
-            pa_status s = pa::enqueue_hash(&plans[i], bk.key, bk.a, bk.b, bk.c, bk.out, bp->d_status + i, nullptr,
-                                           nullptr, ln.st);
-            if (s != PA_OK) return s;
+    // record every block's launches, then group them step by step
+    std::vector<std::vector<pa::KLaunch>> recs(count);
+    for (uint32_t i : order) {
+        const pa_block &bk = blocks[i];
+        pa::bind_scratch(&plans[i], (char *)bp->arena + at[i], lays[i]);
+        recs[i].reserve(16);
+        plans[i].rec = &recs[i];
+        const pa_status s = pa::enqueue_hash(&plans[i], bk.key, bk.a, bk.b, bk.c, bk.out, bp->d_status + i, nullptr,
+                                             nullptr, stream);
+        plans[i].rec = nullptr;
+        if (s != PA_OK) return s == PA_ERR_DEVICE ? PA_DEVICE_ERROR : s;
+    }
+    std::vector<Group> groups;
+    const size_t tab_bytes = build_groups(recs, order, groups);
+    auto grow = [](void **buf, size_t *have, size_t want, bool host) -> bool {
+        if (want <= *have) return true;
+        if (*buf) (void)(host ? hipHostFree(*buf) : hipFree(*buf));
+        *buf = nullptr;
+        *have = 0;
+        const size_t sz = align_up(want + want / 2, 4096);
+        const hipError_t e = host ? hipHostMalloc(buf, sz, hipHostMallocDefault) : hipMalloc(buf, sz);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            *buf = nullptr;
+            return false;
         }
-        for (int l = 0; l < kLanes; ++l) {
-            if (!used[l]) continue;
-            if (hipEventRecord(bp->lanes[l].done, bp->lanes[l].st) != hipSuccess ||
-                hipStreamWaitEvent(origin, bp->lanes[l].done, 0) != hipSuccess)
-                return PA_ERR_DEVICE;
-        }
-        return PA_OK;
+        *have = sz;
+        return true;
     };
+    if (tab_bytes) {
+        // the staging buffer and the device tables are free: the previous call synchronised
+        if (!grow((void **)&bp->h_tab, &bp->h_tab_bytes, tab_bytes, true)) return PA_ERR_NOMEM;
+        fill_tables(groups, bp->h_tab);
+    }
+
     if (!bp->graphs_on) {
-        const pa_status s = enqueue_all(stream);
-        if (s != PA_OK) return s;
+        if (tab_bytes) {
+            if (!grow(&bp->d_tab, &bp->d_tab_bytes, tab_bytes, false)) return PA_ERR_NOMEM;
+            if (hipMemcpyAsync(bp->d_tab, bp->h_tab, tab_bytes, hipMemcpyHostToDevice, stream) != hipSuccess) {
+                (void)hipGetLastError();
+                return PA_DEVICE_ERROR;
+            }
+        }
+        if (launch_groups(groups, (const unsigned char *)bp->d_tab, stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return PA_DEVICE_ERROR;
+        }
     } else {
-        // replay the captured list, or capture it now (tables and arenas are
-        // in place, so nothing below allocates); `cap` runs after `stream`'s
-        // earlier work and `stream` continues after the graph
+        // replay the captured list, or capture it now (its tables copied to a
+        // buffer of its own first); `cap` runs after `stream`'s earlier work
+        // and `stream` continues after the graph
         hipGraphExec_t exec = nullptr;
         for (size_t g = 0; g < bp->graphs.size(); ++g) {
             if (bp->graphs[g].epoch == bp->epoch && same_blocks(bp->graphs[g].blocks, blocks, count)) {
@@ -279,41 +386,49 @@ pa_status pa_hash_batched(pa_batch_plan *bp, const pa_block *blocks, uint32_t co
             }
         }
         if (hipEventRecord(bp->ev_in, stream) != hipSuccess || hipStreamWaitEvent(bp->cap, bp->ev_in, 0) != hipSuccess)
-            return PA_ERR_DEVICE;
+            return PA_DEVICE_ERROR;
         if (!exec) {
-            hipGraph_t graph = nullptr;
-            if (hipStreamBeginCapture(bp->cap, hipStreamCaptureModeRelaxed) != hipSuccess) return PA_ERR_DEVICE;
-            const pa_status s = enqueue_all(bp->cap);
-            const hipError_t e = hipStreamEndCapture(bp->cap, &graph);
-            if (s != PA_OK || e != hipSuccess) {
-                if (graph) (void)hipGraphDestroy(graph);
+            void *d_tab = nullptr;
+            if (tab_bytes && (hipMalloc(&d_tab, tab_bytes) != hipSuccess ||
+                              hipMemcpy(d_tab, bp->h_tab, tab_bytes, hipMemcpyHostToDevice) != hipSuccess)) {
                 (void)hipGetLastError();
-                return s != PA_OK ? s : PA_ERR_DEVICE;
+                if (d_tab) (void)hipFree(d_tab);
+                return PA_ERR_NOMEM;
             }
-            const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
+            hipGraph_t graph = nullptr;
+            if (hipStreamBeginCapture(bp->cap, hipStreamCaptureModeRelaxed) != hipSuccess) {
+                (void)hipFree(d_tab);
+                return PA_DEVICE_ERROR;
+            }
+            const hipError_t el = launch_groups(groups, (const unsigned char *)d_tab, bp->cap);
+            const hipError_t e = hipStreamEndCapture(bp->cap, &graph);
+            hipError_t ei = hipErrorUnknown;
+            if (el == hipSuccess && e == hipSuccess) ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
             if (ei != hipSuccess) {
                 (void)hipGetLastError();
-                return PA_ERR_DEVICE;
+                (void)hipFree(d_tab);
+                return PA_DEVICE_ERROR;
             }
             if (bp->graphs.size() >= kMaxGraphs) {
                 // the evicted graph may still run: wait for the plan's work first
-                if (hipStreamSynchronize(bp->cap) != hipSuccess) return PA_ERR_DEVICE;
+                if (hipStreamSynchronize(bp->cap) != hipSuccess) return PA_DEVICE_ERROR;
                 (void)hipGraphExecDestroy(bp->graphs.front().exec);
+                (void)hipFree(bp->graphs.front().d_tab);
                 bp->graphs.erase(bp->graphs.begin());
             }
-            bp->graphs.push_back(Captured{std::vector<pa_block>(blocks, blocks + count), bp->epoch, exec});
+            bp->graphs.push_back(Captured{std::vector<pa_block>(blocks, blocks + count), bp->epoch, exec, d_tab});
         }
         if (hipGraphLaunch(exec, bp->cap) != hipSuccess || hipEventRecord(bp->ev_out, bp->cap) != hipSuccess ||
             hipStreamWaitEvent(stream, bp->ev_out, 0) != hipSuccess) {
             (void)hipGetLastError();
-            return PA_ERR_DEVICE;
+            return PA_DEVICE_ERROR;
         }
     }
     if (hipMemcpyAsync(bp->h_status, bp->d_status, (size_t)count * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess) {
         (void)hipGetLastError();
-        return PA_ERR_DEVICE;
+        return PA_DEVICE_ERROR;
     }
     for (uint32_t i : order) per_block[i] = pa_decode_status(bp->h_status[i]);
     return PA_OK;

@@ -95,6 +95,42 @@ constexpr int CARRY_PER_THREAD = 4;                          // consecutive digi
 constexpr int CARRY_TILE = SCAN_THREADS * CARRY_PER_THREAD;  // digits per workgroup and per aggregate
 constexpr uint32_t R16_TW = 16 * 256 + 16 * 16;  // words per prime of the row-kernel step-twiddle table
 
+// Steps of the per-block launch sequence.  The batched path records each
+// block's launches with their step and runs every step of all blocks as
+// multi-block launches, in this order.
+enum Step : int {
+    SP_PROLOGUE = 0,
+    SP_MMH_COL,
+    SP_MMH_ROW,
+    SP_MMH_COLINV,
+    SP_FOLD_CRT3,
+    SP_FOLD_DIGIT,
+    SP_FOLD_APPLY,
+    SP_FOLD_WRAP,
+    SP_MH_COL,
+    SP_MH_ROW,
+    SP_MH_COLINV,
+    SP_MH_CRT3,
+    SP_MH_DIGIT,
+    SP_MH_APPLY,
+    SP_COUNT
+};
+
+// One recorded kernel launch of one block: the kernel in its single-block
+// form (which identifies the instance) and its multi-block form (arguments:
+// a table of argument structs, the blocks' grid placement, the owner table),
+// the block's grid, the workgroup size and dynamic LDS, and the argument
+// struct by value.
+constexpr uint32_t KARGS_MAX = 512;
+struct KLaunch {
+    int step;
+    const void *single, *multi;
+    dim3 grid, block;
+    uint32_t lds;
+    uint32_t args_size;
+    alignas(16) unsigned char args[KARGS_MAX];
+};
+
 // Device status flag bits (written by the prologue and status kernels).
 constexpr uint32_t ST_SEED_RANGE = 1u;
 constexpr uint32_t ST_B_EVEN = 2u;
@@ -149,6 +185,7 @@ struct pa_plan {
     const uint32_t *res_a;  // resident seed transforms (k x 3 x N words) or null
     const uint32_t *res_b;  // resident transform of b (3 x N words) or null
     uint32_t *h_status;     // pinned host word
+    std::vector<pa::KLaunch> *rec;  // non-null: record the hash's launches here instead of launching
 
     // phase profiling (pa_plan_set_profiling)
     uint32_t profiling;  // phase mask
@@ -212,9 +249,12 @@ hipError_t launch_prologue(pa_plan *p, const uint64_t *a, const uint64_t *b, con
                            hipStream_t st);
 hipError_t launch_mmh(pa_plan *p, const uint64_t *key, const uint64_t *a, hipStream_t st);
 hipError_t launch_fold(pa_plan *p, hipStream_t st);
-hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, hipStream_t st);
-hipError_t launch_finish(pa_plan *p, uint64_t *out, uint32_t *d_status, uint64_t *y_out,
-                         uint64_t *U_out, hipStream_t st);
+// The MH stage ends with the output extraction (z into out, flags into d_status,
+// or the plan's own status word when d_status is null).
+hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, uint64_t *out, uint32_t *d_status,
+                     hipStream_t st);
+// Stage values for pa_hash_stages (y, U packed into words; nullptr skips).
+hipError_t launch_finish(pa_plan *p, uint64_t *y_out, uint64_t *U_out, hipStream_t st);
 hipError_t launch_seed_transforms(pa_plan *p, const uint64_t *a, uint64_t kmax, const uint64_t *b,
                                   uint32_t *dst_a, uint32_t *dst_b, hipStream_t st);
 

@@ -25,8 +25,11 @@
 // (exact for the small carries that occur), composed with wavefront shuffles
 // inside a workgroup and a reduce / tile-prefix / apply sequence across
 // workgroups.
+#include <cstring>
+
 #include "ntt_device.hpp"
 #include "pa_internal.hpp"
+#include "pa_multi.hpp"
 
 using namespace pa;
 
@@ -68,6 +71,26 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t G) {
     uint32_t x = b & 7u, i = b >> 3;
     uint32_t q = G >> 3, rr = G & 7u;
     return x * q + min(x, rr) + i;
+}
+
+// Position of a workgroup in the grid of the block it works for.  A
+// single-block launch takes it from blockIdx / gridDim; a multi-block launch
+// (one launch covering the same phase of many blocks, each with its own
+// arguments and grid) maps its linear workgroup index to (block, position).
+struct WG {
+    uint32_t x, y, z, gx, gz;
+};
+
+__device__ __forceinline__ WG wg_self() { return WG{blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gridDim.z}; }
+
+// Multi-block launch (pa_multi.hpp): this workgroup's block and its position
+// in that block's grid; MULTI_NONE for a padding workgroup.
+__device__ __forceinline__ uint32_t wg_multi(const MultiGeo *__restrict__ geo, const uint16_t *__restrict__ owner,
+                                             WG &wg) {
+    uint32_t x = 0, y = 0, z = 0;
+    const uint32_t i = multi_locate(geo, owner, blockIdx.x, &x, &y, &z);
+    if (i != MULTI_NONE) wg = WG{x, y, z, geo[i].gx, geo[i].gz};
+    return i;
 }
 
 // B (<= 32) bits of a little-endian word array starting at bit `pos`; bits at
@@ -236,8 +259,16 @@ __global__ void k_tw_r16(const uint32_t *tw, uint32_t *dst, const uint32_t *hdr,
 
 // Clears the chunk flags and checks the seeds: any bit >= gamma in a seed
 // word -> SEED_RANGE; even b -> B_EVEN (MH needs gcd(b, 2) = 1).
-__global__ void k_prologue(const uint64_t *a, const uint64_t *b, const uint64_t *c, uint64_t k,
-                           uint64_t W, uint64_t gamma, uint32_t *notones, uint32_t *status) {
+struct PrologueArgs {
+    const uint64_t *a, *b, *c;
+    uint64_t k, W, gamma;
+    uint32_t *notones, *status;
+};
+
+__device__ __forceinline__ void prologue_body(const PrologueArgs &A, const WG &wg) {
+    const uint64_t *a = A.a, *b = A.b, *c = A.c;
+    const uint64_t k = A.k, W = A.W, gamma = A.gamma;
+    uint32_t *notones = A.notones, *status = A.status;
     uint64_t topmask = (gamma & 63) ? ((1ull << (gamma & 63)) - 1) : ~0ull;
     bool range = false;
     for (uint64_t i = threadIdx.x; i < k; i += blockDim.x) {
@@ -252,6 +283,15 @@ __global__ void k_prologue(const uint64_t *a, const uint64_t *b, const uint64_t 
         status[0] = f;
         status[1] = 0u;
     }
+}
+
+__global__ void k_prologue(PrologueArgs A) { prologue_body(A, wg_self()); }
+
+__global__ void km_prologue(const PrologueArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
+                                     const uint16_t *__restrict__ owner) {
+    WG wg;
+    const uint32_t i = wg_multi(geo, owner, wg);
+    if (i != MULTI_NONE) prologue_body(tab[i], wg);
 }
 
 // After the MMH column pass: RELOAD if some chunk had only all-ones limbs.
@@ -362,14 +402,14 @@ __device__ __forceinline__ void col_last_fwd(const uint32_t *buf, uint32_t lg, u
 // LG, CLG (nonzero): the column length 2^m1 and tile width 2^c_lg fixed at
 // compile time for the common tile shapes (shifts, masks and swizzles fold
 // into constants; the tile lives in static LDS).
-template <int Stage, bool MIX, int TPT, int LG = 0, int CLG = 0>
-__global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
+template <int Stage, bool MIX, int TPT, int LG, int CLG>
+__device__ __forceinline__ void col_fwd_body(const ColFwdArgs &A, const WG &wg) {
     constexpr uint32_t NSUB = MIX ? 3u : 1u;
     constexpr int XR = MIX ? 8 : 4;  // first-step rows of a task that hold x_n
     __shared__ uint32_t Lt[LG && CLG ? 1u << (LG + CLG) : 1u];
     uint32_t *lds = LG && CLG ? Lt : lds_dyn;
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t arr = blockIdx.y + A.arr0;
+    const uint32_t tile = xcd_tile(wg.x, wg.gx);
+    const uint32_t arr = wg.y + A.arr0;
     const uint32_t c_lg = CLG ? (uint32_t)CLG : A.c_lg, lg = LG ? (uint32_t)LG : A.m1;
     const uint32_t cmask = (1u << c_lg) - 1;
     const uint64_t c0 = (uint64_t)tile << c_lg;
@@ -407,15 +447,15 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
         }
     }
     // the transforms (primes x radix-3 branches) of this workgroup's z slice:
-    // gridDim.z divides NSUB * NPRIMES
-    const uint32_t per_z = NSUB * NPRIMES / gridDim.z;
-    const uint32_t it0 = blockIdx.z * per_z, it1 = it0 + per_z;
+    // wg.gz divides NSUB * NPRIMES
+    const uint32_t per_z = NSUB * NPRIMES / wg.gz;
+    const uint32_t it0 = wg.z * per_z, it1 = it0 + per_z;
 #pragma unroll 1
     for (uint32_t it = it0; it < it1; ++it) {
         const uint32_t k0 = it / NPRIMES, pq = it - NPRIMES * k0;
         const PrimeConst M = A.P.c[pq];
         const uint32_t *tw = A.tw + ((uint64_t)pq << lg);
-        uint32_t *out = A.X + ((uint64_t)blockIdx.y * NPRIMES + pq) * A.N + (uint64_t)k0 * Ns;
+        uint32_t *out = A.X + ((uint64_t)wg.y * NPRIMES + pq) * A.N + (uint64_t)k0 * Ns;
         const __amdgpu_buffer_rsrc_t ro = rsrc_of(out, Ns);  // this transform's Nsub words
         const uint32_t *g0 = nullptr, *g1 = nullptr;  // radix-3 row twiddles of transform k0 (k_tw_g3)
         if constexpr (MIX) {
@@ -468,6 +508,17 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) {
     }
 }
 
+template <int Stage, bool MIX, int TPT, int LG = 0, int CLG = 0>
+__global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) { col_fwd_body<Stage, MIX, TPT, LG, CLG>(A, wg_self()); }
+
+template <int Stage, bool MIX, int TPT, int LG = 0, int CLG = 0>
+__global__ __launch_bounds__(COL_THREADS) void km_col_fwd(const ColFwdArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
+                                     const uint16_t *__restrict__ owner) {
+    WG wg;
+    const uint32_t i = wg_multi(geo, owner, wg);
+    if (i != MULTI_NONE) col_fwd_body<Stage, MIX, TPT, LG, CLG>(tab[i], wg);
+}
+
 // ---- 512-row column tiles (N1 = 2^9), 16 columns: compile-time shape -------
 // A workgroup unpacks its tile's limbs once and transforms them for each of
 // the three primes in turn (and, for N = 3 Nsub, for each of the three
@@ -489,12 +540,12 @@ constexpr uint32_t C9_LG = 9, C9_CLG = 4;
 __device__ __forceinline__ constexpr uint32_t swz_c9(uint32_t i) { return i ^ (((i >> 7) & 3u) << 4); }
 
 template <int Stage, bool MIX>
-__global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
+__device__ __forceinline__ void col9_fwd_body(const ColFwdArgs &A, const WG &wg) {
     constexpr uint32_t NSUB = MIX ? 3u : 1u;
     constexpr int X0_ROWS = MIX ? 8 : 4;  // step-A rows of a task holding x_n (x_(n+Nsub): rows < 4)
     __shared__ uint32_t L9[1u << (C9_LG + C9_CLG)];  // one 512 x 16 tile
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t arr = blockIdx.y + A.arr0;
+    const uint32_t tile = xcd_tile(wg.x, wg.gx);
+    const uint32_t arr = wg.y + A.arr0;
     const uint64_t c0 = (uint64_t)tile << C9_CLG;
     const bool is_key = (A.mode == 0) && arr < A.k;
     const uint32_t full = (uint32_t)((1ull << A.B) - 1), topv = (uint32_t)((1ull << A.s_top) - 1);
@@ -529,15 +580,15 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
         }
     }
     // the transforms (primes x radix-3 branches) of this workgroup's z slice:
-    // gridDim.z divides NSUB * NPRIMES
-    const uint32_t per_z = NSUB * NPRIMES / gridDim.z;
-    const uint32_t it0 = blockIdx.z * per_z, it1 = it0 + per_z;
+    // wg.gz divides NSUB * NPRIMES
+    const uint32_t per_z = NSUB * NPRIMES / wg.gz;
+    const uint32_t it0 = wg.z * per_z, it1 = it0 + per_z;
 #pragma unroll 1
     for (uint32_t it = it0; it < it1; ++it) {
         const uint32_t k0 = it / NPRIMES, pq = it - NPRIMES * k0;
         const PrimeConst M = A.P.c[pq];
         const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.tw + ((uint64_t)pq << C9_LG), 1u << C9_LG);
-        uint32_t *out = A.X + ((uint64_t)blockIdx.y * NPRIMES + pq) * A.N + (uint64_t)k0 * Ns;
+        uint32_t *out = A.X + ((uint64_t)wg.y * NPRIMES + pq) * A.N + (uint64_t)k0 * Ns;
         const __amdgpu_buffer_rsrc_t ro = rsrc_of(out, Ns);  // this transform's Nsub words
         // radix-3 row twiddles of transform k0 (tables g0, g1 of k_tw_g3)
         __amdgpu_buffer_rsrc_t rg0 = rtw, rg1 = rtw;
@@ -608,6 +659,17 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) {
     }
 }
 
+template <int Stage, bool MIX>
+__global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) { col9_fwd_body<Stage, MIX>(A, wg_self()); }
+
+template <int Stage, bool MIX>
+__global__ __launch_bounds__(COL_THREADS) void km_col9_fwd(const ColFwdArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
+                                     const uint16_t *__restrict__ owner) {
+    WG wg;
+    const uint32_t i = wg_multi(geo, owner, wg);
+    if (i != MULTI_NONE) col9_fwd_body<Stage, MIX>(tab[i], wg);
+}
+
 // Column pass for 1024-row tiles of 8 columns (N1 = 2^10): the 512-row
 // kernel's scheme with one more row bit.  Step A: radix-8 across rows 128
 // apart straight from the unpacked limbs, times omega_1024^(n1 brev(s));
@@ -621,12 +683,12 @@ constexpr uint32_t C10_LG = 10, C10_CLG = 3;
 __device__ __forceinline__ constexpr uint32_t swz_c10(uint32_t i) { return i ^ (((i >> 7) & 7u) << 3); }
 
 template <int Stage, bool MIX>
-__global__ __launch_bounds__(COL_THREADS) void k_col10_fwd(ColFwdArgs A) {
+__device__ __forceinline__ void col10_fwd_body(const ColFwdArgs &A, const WG &wg) {
     constexpr uint32_t NSUB = MIX ? 3u : 1u;
     constexpr int X0_ROWS = MIX ? 8 : 4;  // step-A rows of a task holding x_n (x_(n+Nsub): rows < 4)
     __shared__ uint32_t L10[1u << (C10_LG + C10_CLG)];  // one 1024 x 8 tile
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t arr = blockIdx.y + A.arr0;
+    const uint32_t tile = xcd_tile(wg.x, wg.gx);
+    const uint32_t arr = wg.y + A.arr0;
     const uint64_t c0 = (uint64_t)tile << C10_CLG;
     const bool is_key = (A.mode == 0) && arr < A.k;
     const uint32_t full = (uint32_t)((1ull << A.B) - 1), topv = (uint32_t)((1ull << A.s_top) - 1);
@@ -661,15 +723,15 @@ __global__ __launch_bounds__(COL_THREADS) void k_col10_fwd(ColFwdArgs A) {
         }
     }
     // the transforms (primes x radix-3 branches) of this workgroup's z slice:
-    // gridDim.z divides NSUB * NPRIMES
-    const uint32_t per_z = NSUB * NPRIMES / gridDim.z;
-    const uint32_t it0 = blockIdx.z * per_z, it1 = it0 + per_z;
+    // wg.gz divides NSUB * NPRIMES
+    const uint32_t per_z = NSUB * NPRIMES / wg.gz;
+    const uint32_t it0 = wg.z * per_z, it1 = it0 + per_z;
 #pragma unroll 1
     for (uint32_t it = it0; it < it1; ++it) {
         const uint32_t k0 = it / NPRIMES, pq = it - NPRIMES * k0;
         const PrimeConst M = A.P.c[pq];
         const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.tw + ((uint64_t)pq << C10_LG), 1u << C10_LG);
-        uint32_t *out = A.X + ((uint64_t)blockIdx.y * NPRIMES + pq) * A.N + (uint64_t)k0 * Ns;
+        uint32_t *out = A.X + ((uint64_t)wg.y * NPRIMES + pq) * A.N + (uint64_t)k0 * Ns;
         const __amdgpu_buffer_rsrc_t ro = rsrc_of(out, Ns);  // this transform's Nsub words
         // radix-3 row twiddles of transform k0 (tables g0, g1 of k_tw_g3)
         __amdgpu_buffer_rsrc_t rg0 = rtw, rg1 = rtw;
@@ -738,6 +800,17 @@ __global__ __launch_bounds__(COL_THREADS) void k_col10_fwd(ColFwdArgs A) {
             for (int j = 0; j < 16; ++j) bstore(v[j], ro, vo, ((uint32_t)j << A.m2) << 2);
         }
     }
+}
+
+template <int Stage, bool MIX>
+__global__ __launch_bounds__(COL_THREADS) void k_col10_fwd(ColFwdArgs A) { col10_fwd_body<Stage, MIX>(A, wg_self()); }
+
+template <int Stage, bool MIX>
+__global__ __launch_bounds__(COL_THREADS) void km_col10_fwd(const ColFwdArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
+                                     const uint16_t *__restrict__ owner) {
+    WG wg;
+    const uint32_t i = wg_multi(geo, owner, wg);
+    if (i != MULTI_NONE) col10_fwd_body<Stage, MIX>(tab[i], wg);
 }
 
 struct RowArgs {
@@ -815,9 +888,9 @@ __device__ __forceinline__ void row_last_inv_step(const uint32_t *buf, uint32_t 
 // before the inverse transform (all threads pass the same barriers: a group
 // without a pair in a round transforms a stand-in pair and discards it).
 template <int Stage>
-__global__ __launch_bounds__(ROW_MAX_THREADS) void k_row(RowArgs A) {
+__device__ __forceinline__ void row_body(const RowArgs &A, const WG &wg) {
     uint32_t *lds = lds_dyn;
-    const uint32_t pq = blockIdx.y;
+    const uint32_t pq = wg.y;
     const PrimeConst M = A.P.c[pq];
     const uint32_t lg = A.m2;
     const uint32_t N2 = 1u << lg;
@@ -825,7 +898,7 @@ __global__ __launch_bounds__(ROW_MAX_THREADS) void k_row(RowArgs A) {
     const uint32_t Tg = A.row_group, G = T / Tg;  // blockDim.x = G * Tg, Tg * ROW_EPT >= N2
     const uint32_t g = threadIdx.x / Tg, tg = threadIdx.x - g * Tg;
     uint32_t *buf = lds + g * N2;
-    const uint32_t rho = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t rho = xcd_tile(wg.x, wg.gx);
     const uint64_t rbase = (uint64_t)rho << lg;
     const uint32_t *wf = A.Wf + pq * A.N + rbase;
     const uint32_t *twf = A.twf + ((uint64_t)pq << lg);
@@ -881,6 +954,17 @@ __global__ __launch_bounds__(ROW_MAX_THREADS) void k_row(RowArgs A) {
     row_last_inv_step(lds, A.out + pq * A.N + rbase, A.Wi + pq * A.N + rbase, lg, twi, M, threadIdx.x, T);
 }
 
+template <int Stage>
+__global__ __launch_bounds__(ROW_MAX_THREADS) void k_row(RowArgs A) { row_body<Stage>(A, wg_self()); }
+
+template <int Stage>
+__global__ __launch_bounds__(ROW_MAX_THREADS) void km_row(const RowArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
+                                     const uint16_t *__restrict__ owner) {
+    WG wg;
+    const uint32_t i = wg_multi(geo, owner, wg);
+    if (i != MULTI_NONE) row_body<Stage>(tab[i], wg);
+}
+
 // ---- 4096-point rows: three register radix-16 steps --------------------------
 // Thread t (256 per workgroup) owns 16 values in every step:
 //   step 1 (sub-length 4096, stride 256): elements t + 256 j (straight from
@@ -907,16 +991,16 @@ __device__ __forceinline__ constexpr uint32_t swz_r16(uint32_t i) {
 }
 
 template <int Stage>
-__global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
+__device__ __forceinline__ void row16_body(const RowArgs &A, const WG &wg) {
     __shared__ uint32_t L16[2 * R16_LEN];
     // LDS: the x row's buffer at byte 0, the a row's at byte R16_BA.  Accesses
     // go through byte addresses base ^ (4 * swz(offset)): one XOR each, the
     // buffer base folded in beforehand (bit 14 is disjoint from every
     // swizzled offset, so adding it commutes with the XOR).
-    const uint32_t pq = blockIdx.y;
+    const uint32_t pq = wg.y;
     const PrimeConst M = A.P.c[pq];
     const uint32_t t = threadIdx.x;
-    const uint32_t rho = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t rho = xcd_tile(wg.x, wg.gx);
     const uint64_t rbase = (uint64_t)rho * R16_LEN;
     const uint32_t t4 = t * 4u;  // byte offset of element t in a row
     // swizzled bases of this thread's three access patterns
@@ -940,6 +1024,11 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
         pend[j] = 0ull;
     }
     uint32_t npend = 0;
+    // the row's four-step twiddles: the same for every pair and both sides,
+    // loaded once (16 registers) instead of once per pair and side
+    uint32_t wv[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) wv[j] = bload(rw, t4, 1024u * j);
 
     for (uint64_t i = 0; i < A.npairs; ++i) {
         const uint32_t *xrow = A.X + i * A.pair_stride + pq * A.N + rbase;
@@ -951,15 +1040,12 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
             const __amdgpu_buffer_rsrc_t rg = rsrc_of(side ? arow : xrow, R16_LEN);
             const uint32_t t4l = opaque(t4), a1 = opaque((side ? R16_BA : 0u) + s1b);
             // step 1: from global, four-step twiddle, radix-16, step twiddles.
-            // All 32 loads are issued before the first use (the scheduling
+            // All 31 loads are issued before the first use (the scheduling
             // barrier keeps the compiler from interleaving load, wait and
             // use, which would expose the memory latency 16 times).
-            uint32_t v[16], wv[16], w[16];
+            uint32_t v[16], w[16];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                v[j] = bload(rg, t4l, 1024u * j);
-                wv[j] = bload(rw, t4l, 1024u * j);
-            }
+            for (int j = 0; j < 16; ++j) v[j] = bload(rg, t4l, 1024u * j);
 #pragma unroll
             for (int j = 1; j < 16; ++j) w[j] = bload(rt, t4l, 1024u * j);
             __builtin_amdgcn_sched_barrier(0);
@@ -1029,15 +1115,25 @@ __global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) {
     for (int j = 0; j < 16; ++j) v[j] = lds_word(L16, s1b ^ (swz_r16(256u * j) << 2));
     const __amdgpu_buffer_rsrc_t ro = rsrc_of(A.out + pq * A.N + rbase, R16_LEN);
     const __amdgpu_buffer_rsrc_t rwi = rsrc_of(A.Wi + pq * A.N + rbase, R16_LEN);
-    uint32_t wv[16];
 #pragma unroll
     for (int s = 1; s < 16; ++s) w[s] = bload(rti, t4, 1024u * s);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) wv[j] = bload(rwi, t4, 1024u * j);
+    for (int j = 0; j < 16; ++j) wv[j] = bload(rwi, t4, 1024u * j);  // now the inverse four-step twiddles
     __builtin_amdgcn_sched_barrier(0);
     dft_inv_tw<16>(v, w, M);
 #pragma unroll
     for (int j = 0; j < 16; ++j) bstore(mont(v[j], wv[j], M), ro, t4, 1024u * j);
+}
+
+template <int Stage>
+__global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) { row16_body<Stage>(A, wg_self()); }
+
+template <int Stage>
+__global__ __launch_bounds__(R16_THREADS, 4) void km_row16(const RowArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
+                                     const uint16_t *__restrict__ owner) {
+    WG wg;
+    const uint32_t i = wg_multi(geo, owner, wg);
+    if (i != MULTI_NONE) row16_body<Stage>(tab[i], wg);
 }
 
 struct ColInvArgs {
@@ -1075,13 +1171,13 @@ __device__ __forceinline__ void col_first_inv(const uint32_t *__restrict__ cc, u
 // Inverse column pass (bit-reversed rows in, natural rows out), in place:
 // first step straight from global memory, last step straight back.
 template <int Stage>
-__global__ __launch_bounds__(COL_THREADS) void k_col_inv(ColInvArgs A) {
+__device__ __forceinline__ void col_inv_body(const ColInvArgs &A, const WG &wg) {
     uint32_t *lds = lds_dyn;
-    const uint32_t pq = blockIdx.y;
+    const uint32_t pq = wg.y;
     const PrimeConst M = A.P.c[pq];
     const uint32_t *twi = A.twi + ((uint64_t)pq << A.m1);
-    uint32_t *cc = A.Cc + pq * A.N + blockIdx.z * A.Nsub;
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    uint32_t *cc = A.Cc + pq * A.N + wg.z * A.Nsub;
+    const uint32_t tile = xcd_tile(wg.x, wg.gx);
     const uint32_t c_lg = A.c_lg, lg = A.m1;
     const uint32_t cmask = (1u << c_lg) - 1;
     const uint64_t c0 = (uint64_t)tile << c_lg;
@@ -1123,6 +1219,17 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_inv(ColInvArgs A) {
             if (n1 + ((uint32_t)j << lgMp) < A.row_lim)
                 cc[((uint64_t)(n1 + ((uint32_t)j << lgMp)) << A.m2) + c0 + q] = canon(red2(v[j], M), M);
     }
+}
+
+template <int Stage>
+__global__ __launch_bounds__(COL_THREADS) void k_col_inv(ColInvArgs A) { col_inv_body<Stage>(A, wg_self()); }
+
+template <int Stage>
+__global__ __launch_bounds__(COL_THREADS) void km_col_inv(const ColInvArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
+                                     const uint16_t *__restrict__ owner) {
+    WG wg;
+    const uint32_t i = wg_multi(geo, owner, wg);
+    if (i != MULTI_NONE) col_inv_body<Stage>(tab[i], wg);
 }
 
 // ------------------------------------------------------------------ carry scan
@@ -1214,15 +1321,15 @@ __device__ void block_scan(CFn f, CFn &excl, CFn &total) {
 // residues.  Inverse twiddles multiply a task's inputs (fused into the first
 // DIT stage).
 template <int Stage>
-__global__ __launch_bounds__(COL_THREADS) void k_col9_inv(ColInvArgs A) {
+__device__ __forceinline__ void col9_inv_body(const ColInvArgs &A, const WG &wg) {
     __shared__ uint32_t L9[1u << (C9_LG + C9_CLG)];  // one 512 x 16 tile
-    const uint32_t pq = blockIdx.y;
+    const uint32_t pq = wg.y;
     const PrimeConst M = A.P.c[pq];
     const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.twi + ((uint64_t)pq << C9_LG), 1u << C9_LG);
     // this transform's Nsub words, through a buffer resource: lane offset plus
     // a uniform row offset per access
-    const __amdgpu_buffer_rsrc_t rc = rsrc_of(A.Cc + pq * A.N + blockIdx.z * A.Nsub, (uint32_t)A.Nsub);
-    const uint32_t c0 = xcd_tile(blockIdx.x, gridDim.x) << C9_CLG;
+    const __amdgpu_buffer_rsrc_t rc = rsrc_of(A.Cc + pq * A.N + wg.z * A.Nsub, (uint32_t)A.Nsub);
+    const uint32_t c0 = xcd_tile(wg.x, wg.gx) << C9_CLG;
     const uint32_t t = threadIdx.x;
 #pragma unroll 1
     for (uint32_t u = 0; u < 4; ++u) {  // sub-length 8: rows 8 b + j
@@ -1272,6 +1379,17 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_inv(ColInvArgs A) {
     }
 }
 
+template <int Stage>
+__global__ __launch_bounds__(COL_THREADS) void k_col9_inv(ColInvArgs A) { col9_inv_body<Stage>(A, wg_self()); }
+
+template <int Stage>
+__global__ __launch_bounds__(COL_THREADS) void km_col9_inv(const ColInvArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
+                                     const uint16_t *__restrict__ owner) {
+    WG wg;
+    const uint32_t i = wg_multi(geo, owner, wg);
+    if (i != MULTI_NONE) col9_inv_body<Stage>(tab[i], wg);
+}
+
 // Inverse column pass for 1024-row tiles of 8 columns (N1 = 2^10), the mirror
 // of k_col10_fwd: radix-16 on 16 consecutive (bit-reversed) rows straight
 // from global memory, radix-8 across rows 16 apart, radix-8 across rows 128
@@ -1279,15 +1397,15 @@ __global__ __launch_bounds__(COL_THREADS) void k_col9_inv(ColInvArgs A) {
 // row_lim).  Inverse twiddles multiply a task's inputs (fused into the first
 // DIT stage).
 template <int Stage>
-__global__ __launch_bounds__(COL_THREADS) void k_col10_inv(ColInvArgs A) {
+__device__ __forceinline__ void col10_inv_body(const ColInvArgs &A, const WG &wg) {
     __shared__ uint32_t L10[1u << (C10_LG + C10_CLG)];  // one 1024 x 8 tile
-    const uint32_t pq = blockIdx.y;
+    const uint32_t pq = wg.y;
     const PrimeConst M = A.P.c[pq];
     const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.twi + ((uint64_t)pq << C10_LG), 1u << C10_LG);
     // this transform's Nsub words, through a buffer resource: lane offset plus
     // a uniform row offset per access
-    const __amdgpu_buffer_rsrc_t rc = rsrc_of(A.Cc + pq * A.N + blockIdx.z * A.Nsub, (uint32_t)A.Nsub);
-    const uint32_t c0 = xcd_tile(blockIdx.x, gridDim.x) << C10_CLG;
+    const __amdgpu_buffer_rsrc_t rc = rsrc_of(A.Cc + pq * A.N + wg.z * A.Nsub, (uint32_t)A.Nsub);
+    const uint32_t c0 = xcd_tile(wg.x, wg.gx) << C10_CLG;
     const uint32_t t = threadIdx.x;
 #pragma unroll 1
     for (uint32_t u = 0; u < 2; ++u) {  // sub-length 16: rows 16 b + j
@@ -1337,6 +1455,17 @@ __global__ __launch_bounds__(COL_THREADS) void k_col10_inv(ColInvArgs A) {
     }
 }
 
+template <int Stage>
+__global__ __launch_bounds__(COL_THREADS) void k_col10_inv(ColInvArgs A) { col10_inv_body<Stage>(A, wg_self()); }
+
+template <int Stage>
+__global__ __launch_bounds__(COL_THREADS) void km_col10_inv(const ColInvArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
+                                     const uint16_t *__restrict__ owner) {
+    WG wg;
+    const uint32_t i = wg_multi(geo, owner, wg);
+    if (i != MULTI_NONE) col10_inv_body<Stage>(tab[i], wg);
+}
+
 // Garner's reconstruction: canonical residues r_q mod p_q of a value below
 // p0 p1 p2 -> the value.
 __device__ __forceinline__ unsigned __int128 garner(uint32_t r0, uint32_t r1, uint32_t r2, const PrimeSet &P,
@@ -1371,9 +1500,9 @@ struct Crt3Args {
 // twiddle already applied), multiplies s_1, s_2 by the row part
 // omega_N^(-k0 r N2) (j1 = r N2 + c), runs the 3-point inverse DFT and
 // reconstructs the coefficients j1 + n0 Nsub (n0 < 3) below `count`.
-__global__ void k_crt3(Crt3Args A) {
-    const uint64_t j1 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (A.notones && blockIdx.x == 0) {
+__device__ __forceinline__ void crt3_body(const Crt3Args &A, const WG &wg) {
+    const uint64_t j1 = (uint64_t)wg.x * blockDim.x + threadIdx.x;
+    if (A.notones && wg.x == 0) {
         bool reload = false;
         for (uint64_t i = threadIdx.x; i < A.k; i += blockDim.x) reload |= (A.notones[i] == 0u);
         const int any = __syncthreads_or(reload);
@@ -1405,6 +1534,15 @@ __global__ void k_crt3(Crt3Args A) {
         A.c96[A.N + j] = (uint32_t)(c >> 32);
         A.c96[2 * A.N + j] = (uint32_t)(c >> 64);
     }
+}
+
+__global__ void k_crt3(Crt3Args A) { crt3_body(A, wg_self()); }
+
+__global__ void km_crt3(const Crt3Args *__restrict__ tab, const MultiGeo *__restrict__ geo,
+                                     const uint16_t *__restrict__ owner) {
+    WG wg;
+    const uint32_t i = wg_multi(geo, owner, wg);
+    if (i != MULTI_NONE) crt3_body(tab[i], wg);
 }
 
 __device__ __forceinline__ unsigned __int128 coef(const uint32_t *__restrict__ c96, uint64_t N, uint64_t j) {
@@ -1468,26 +1606,6 @@ __device__ __forceinline__ uint64_t fold_digit(const DigitArgs &A, uint64_t m) {
     return sum;
 }
 
-// The second fold (Sec. 3.1): with the folded sum normalised into limbs s
-// (M1 of them), T = T_lo + 2^gamma V with T_lo = T mod 2^gamma and V < 2^92;
-// returns V mod p (p = 2^gamma - 1), which the wrap chain adds to T_lo.
-__device__ __forceinline__ unsigned __int128 wrap_value(const uint32_t *__restrict__ s, uint64_t gamma, uint32_t B,
-                                                        uint64_t M1) {
-    unsigned __int128 V = 0;
-    for (uint64_t idx = gamma / B; idx < M1; ++idx) {
-        const uint64_t lo_bit = idx * B;
-        const unsigned __int128 limb = s[idx];
-        if (lo_bit < gamma) V += limb >> (gamma - lo_bit);
-        else if (lo_bit - gamma < 128) V += limb << (lo_bit - gamma);  // higher limbs are zero
-    }
-    if (gamma < 128) {
-        const unsigned __int128 pm = (((unsigned __int128)1) << gamma) - 1;
-        while (V >> gamma) V = (V & pm) + (V >> gamma);
-        if (V == pm) V = 0;
-    }
-    return V;
-}
-
 // MH digit m < L: the limbs of c plus the pieces of the product coefficients
 // below limb L (everything at or above bit gamma is dropped, mod 2^gamma).
 __device__ __forceinline__ uint64_t mh_digit(const DigitArgs &A, uint64_t m) {
@@ -1513,8 +1631,8 @@ __device__ __forceinline__ uint64_t mh_digit(const DigitArgs &A, uint64_t m) {
 // (many waves in flight: the digits gather from several coefficients); writes
 // the digit sums and the tile's composed carry function (digits below M only).
 template <int MODE>
-__global__ __launch_bounds__(CARRY_TILE) void k_digit_tile(DigitArgs A) {
-    const uint64_t m = (uint64_t)blockIdx.x * CARRY_TILE + threadIdx.x;
+__device__ __forceinline__ void digit_tile_body(const DigitArgs &A, const WG &wg) {
+    const uint64_t m = (uint64_t)wg.x * CARRY_TILE + threadIdx.x;
     CFn f = cf_id();
     if (m < A.ndig) {
         const uint64_t d = MODE == DIG_FOLD ? fold_digit(A, m) : mh_digit(A, m);
@@ -1522,7 +1640,18 @@ __global__ __launch_bounds__(CARRY_TILE) void k_digit_tile(DigitArgs A) {
         if (m < A.M) f = cf_limb(d, A.B);
     }
     const CFn total = block_reduce<CARRY_TILE>(f);
-    if (threadIdx.x == 0) A.agg[blockIdx.x] = total;
+    if (threadIdx.x == 0) A.agg[wg.x] = total;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(CARRY_TILE) void k_digit_tile(DigitArgs A) { digit_tile_body<MODE>(A, wg_self()); }
+
+template <int MODE>
+__global__ __launch_bounds__(CARRY_TILE) void km_digit_tile(const DigitArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
+                                     const uint16_t *__restrict__ owner) {
+    WG wg;
+    const uint32_t i = wg_multi(geo, owner, wg);
+    if (i != MULTI_NONE) digit_tile_body<MODE>(tab[i], wg);
 }
 
 // The same digits straight from the convolution residues, for transform
@@ -1547,15 +1676,15 @@ struct DigitCrtArgs {
 };
 
 template <int MODE>
-__global__ __launch_bounds__(CARRY_TILE) void k_digit_crt(DigitCrtArgs A) {
+__device__ __forceinline__ void digit_crt_body(const DigitCrtArgs &A, const WG &wg) {
     constexpr int SPAN = CARRY_TILE + DIG_HALO;
     constexpr int HS = MODE == DIG_FOLD ? SPAN : 1;  // the high range: FOLD only
     __shared__ uint32_t lo[3][SPAN];
     __shared__ uint32_t hi[3][HS];
     const DigitArgs &D = A.D;
     const uint32_t t = threadIdx.x;
-    const uint64_t m0 = (uint64_t)blockIdx.x * CARRY_TILE;
-    if (A.notones && blockIdx.x == 0) {
+    const uint64_t m0 = (uint64_t)wg.x * CARRY_TILE;
+    if (A.notones && wg.x == 0) {
         bool reload = false;
         for (uint64_t i = t; i < A.k; i += CARRY_TILE) reload |= (A.notones[i] == 0u);
         const int any = __syncthreads_or(reload);
@@ -1626,10 +1755,24 @@ __global__ __launch_bounds__(CARRY_TILE) void k_digit_crt(DigitCrtArgs A) {
         if (m < D.M) f = cf_limb(d, D.B);
     }
     const CFn total = block_reduce<CARRY_TILE>(f);
-    if (t == 0) D.agg[blockIdx.x] = total;
+    if (t == 0) D.agg[wg.x] = total;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(CARRY_TILE) void k_digit_crt(DigitCrtArgs A) { digit_crt_body<MODE>(A, wg_self()); }
+
+template <int MODE>
+__global__ __launch_bounds__(CARRY_TILE) void km_digit_crt(const DigitCrtArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
+                                     const uint16_t *__restrict__ owner) {
+    WG wg;
+    const uint32_t i = wg_multi(geo, owner, wg);
+    if (i != MULTI_NONE) digit_crt_body<MODE>(tab[i], wg);
 }
 
 constexpr int APPLY_PLAIN = 0, APPLY_FOLD = 1, APPLY_WRAP = 2;
+constexpr uint32_t WRAP_LO = 32;     // lowest limbs of y written by the second fold's usual case
+constexpr uint32_t WRAP_TOP = 24;    // >= digits of the folded sum at and above limb gamma / B
+constexpr uint32_t EXTRA_LIMBS = 10; // >= ceil(64 / B) + 1 limbs past a tile an output word reaches
 
 struct ScanArgs {
     const uint64_t *t;   // digit sums: M regular limbs, then the top limb at index M if has_top
@@ -1639,11 +1782,115 @@ struct ScanArgs {
     uint64_t ntiles;     // ceil(M / CARRY_TILE)
     const CFn *agg;      // tile carry functions of this chain
     CFn *agg_w;          // FOLD: tile carry functions of the wrap chain, out
-    uint64_t Mw;         // FOLD: regular digits of the wrap chain (L - 1)
+    uint64_t Mw;         // FOLD, WRAP: regular limbs of y (L - 1; y's top limb is index Mw)
     const uint32_t *s;   // WRAP: normalised limbs of the folded sum (M1)
-    uint64_t gamma, M1;  // WRAP
+    uint64_t gamma, M1;  // FOLD, WRAP
     uint32_t qv;         // FOLD, WRAP: wrap digits below qv = ceil(128 / B) take pieces of V mod p
+    uint32_t *y;         // FOLD: the limbs of y (usual case of the second fold)
+    uint32_t *flag;      // FOLD: 1 when the usual case does not apply, else 0; WRAP: runs only on 1
+    uint64_t *zout;      // PLAIN: if set, z = bits [gamma - r, gamma) of the result, packed
+    uint64_t out_words, r;
+    const uint32_t *status;  // PLAIN with zout: final status flags at index 1 (no output unless 0)
+    uint32_t *dst;           // PLAIN with zout: the final flags are copied here
 };
+
+// V mod p for V < 2^128 and p = 2^gamma - 1 (identity for gamma >= 128).
+__device__ __forceinline__ unsigned __int128 mod_mersenne128(unsigned __int128 V, uint64_t gamma) {
+    if (gamma < 128) {
+        const unsigned __int128 pm = (((unsigned __int128)1) << gamma) - 1;
+        while (V >> gamma) V = (V & pm) + (V >> gamma);
+        if (V == pm) V = 0;
+    }
+    return V;
+}
+
+// The second fold (Sec. 3.1): with the folded sum normalised into limbs s
+// (M1 of them), T = T_lo + 2^gamma V with T_lo = T mod 2^gamma and V < 2^92;
+// returns V mod p (p = 2^gamma - 1), which the wrap chain adds to T_lo.
+__device__ __forceinline__ unsigned __int128 wrap_value(const uint32_t *__restrict__ s, uint64_t gamma, uint32_t B,
+                                                        uint64_t M1) {
+    unsigned __int128 V = 0;
+    for (uint64_t idx = gamma / B; idx < M1; ++idx) {
+        const uint64_t lo_bit = idx * B;
+        const unsigned __int128 limb = s[idx];
+        if (lo_bit < gamma) V += limb >> (gamma - lo_bit);
+        else if (lo_bit - gamma < 128) V += limb << (lo_bit - gamma);  // higher limbs are zero
+    }
+    return mod_mersenne128(V, gamma);
+}
+
+// The second fold's usual case, run by one extra workgroup of the first
+// fold's apply beside the tiles (no workgroup waits for another): it
+// evaluates the first fold's carry chain itself at the limbs above bit gamma
+// (the tiles' functions below the tile of limb gamma / B, then that tile's
+// digits up to it) to get V mod p, normalises the lowest WRAP_LO digits
+// (the chain's carry-in is 0), adds V's pieces to the lowest qv of them and
+// lets the carry run.  y = T_lo + V then differs from T_lo only below the
+// limb where the carry stops; it is canonical (below p) when some limb above
+// that one, still below WRAP_LO, is not all ones: then no carry reaches bit
+// gamma and not every bit of y is one.  In that case this workgroup writes
+// y's lowest limbs (the tiles write the rest) and clears the flag; otherwise
+// it sets the flag and the general wrap chain recomputes y.
+__device__ void wrap_usual_case(const ScanArgs &A) {
+    __shared__ uint64_t tlo[WRAP_LO], ttop[WRAP_TOP];
+    const uint32_t t = threadIdx.x;
+    const uint64_t mask = (1ull << A.B) - 1;
+    const uint64_t d0 = A.gamma / A.B, T = d0 / CARRY_TILE, nv = A.M - d0;
+    if (t < WRAP_LO) tlo[t] = t < A.M ? A.t[t] : 0ull;
+    if (t < nv) ttop[t] = A.t[d0 + t];
+    const uint64_t per = (T + SCAN_THREADS - 1) / SCAN_THREADS;
+    const uint64_t j0 = min((uint64_t)t * per, T), j1 = min(j0 + per, T);
+    CFn f = cf_id();
+    for (uint64_t j = j0; j < j1; ++j) f = cf_compose(f, A.agg[j]);
+    const CFn below = block_reduce<SCAN_THREADS>(f);
+    __syncthreads();
+    CFn g = cf_id();
+    const uint64_t base = T * CARRY_TILE + (uint64_t)t * CARRY_PER_THREAD;
+#pragma unroll
+    for (int v = 0; v < CARRY_PER_THREAD; ++v)
+        if (base + v < d0) g = cf_compose(g, cf_limb(A.t[base + v], A.B));
+    const CFn within = block_reduce<SCAN_THREADS>(g);
+    __syncthreads();
+    if (t != 0) return;
+    uint32_t c = cf_eval(cf_compose(below, within), 0u);
+    unsigned __int128 V = 0;
+    for (uint64_t i = 0; i < nv; ++i) {
+        const uint64_t v = ttop[i] + c;
+        const unsigned __int128 limb = v & mask;
+        c = (uint32_t)(v >> A.B);
+        const uint64_t lo_bit = (d0 + i) * A.B;
+        if (lo_bit < A.gamma) V += limb >> (A.gamma - lo_bit);
+        else if (lo_bit - A.gamma < 128) V += limb << (lo_bit - A.gamma);
+    }
+    V = mod_mersenne128(V, A.gamma);
+    const uint32_t nlo = (uint32_t)min((uint64_t)WRAP_LO, A.Mw);
+    uint32_t slo[WRAP_LO];
+    c = 0;
+    for (uint32_t m = 0; m < nlo; ++m) {
+        const uint64_t v = tlo[m] + c;
+        slo[m] = (uint32_t)(v & mask);
+        c = (uint32_t)(v >> A.B);
+    }
+    bool usual = A.qv < nlo;
+    uint32_t first_same = nlo;  // y's limbs from here on equal T_lo's
+    uint32_t c2 = 0;
+    for (uint32_t m = 0; usual && m < nlo; ++m) {
+        const uint64_t add = m < A.qv ? (uint64_t)(V >> (A.B * m)) & mask : 0ull;
+        const uint64_t v = (uint64_t)slo[m] + add + c2;
+        c2 = (uint32_t)(v >> A.B);
+        slo[m] = (uint32_t)(v & mask);
+        if (m + 1 >= A.qv && c2 == 0) {
+            first_same = m + 1;
+            break;
+        }
+    }
+    bool guard = false;
+    for (uint32_t m = first_same; m < nlo; ++m) guard |= slo[m] != (uint32_t)mask;
+    usual = usual && c2 == 0 && guard;
+    if (usual)
+        for (uint32_t m = 0; m < nlo; ++m) A.y[m] = slo[m];
+    *A.flag = usual ? 0u : 1u;
+}
 
 // Normalise one tile.  The carry into the tile is the composition of the
 // aggregates of all earlier tiles evaluated at the chain's carry-in (every
@@ -1652,18 +1899,46 @@ struct ScanArgs {
 // carry-in 0 and 1; in dual mode the chain takes carry-in 1 when carry-in 1
 // leaves a nonzero value above the top limb's width, i.e. when the sum is at
 // least p (see launch_fold), and workgroup 0 writes the top limb.  Launched
-// with max(1, ntiles) workgroups.
+// with max(1, ntiles) workgroups (FOLD: one more, see below).
 //
 // APPLY_FOLD also composes, per tile, the carry functions of the limbs it
-// writes as digits of the wrap chain (digits [qv, Mw) only), into agg_w.
-// APPLY_WRAP runs the wrap chain itself: its digits are read from the limbs
-// s of the folded sum, the lowest qv with the pieces of V mod p added and the
-// top one cut to s_top bits; the carry functions of digits [0, qv), which
-// depend on V, are composed here (thread 0 prepends them to the aggregates).
+// writes as digits of the wrap chain (digits [qv, Mw) only), into agg_w,
+// writes its limbs from WRAP_LO up as y's limbs (y's top limb cut to s_top
+// bits), and its extra workgroup (index ntiles) runs the second fold's usual
+// case.  APPLY_WRAP, which runs only when the flag says the usual case does
+// not apply, runs the general wrap chain: its digits are read from the limbs
+// s of the folded sum, the lowest qv with the pieces of V mod p added and
+// the top one cut to s_top bits; the carry functions of digits [0, qv),
+// which depend on V, are composed here (thread 0 prepends them to the
+// aggregates).
+// APPLY_PLAIN with zout also packs the output z (Alg. 1: the top r of the
+// gamma bits): each workgroup places its limbs and the next EXTRA_LIMBS
+// (normalised from the tile's carry out) in LDS and writes the output words
+// that start in its limbs (the last workgroup: up to bit gamma), unless the
+// status flags are set; workgroup 0 copies the flags to dst.
 template <int AM>
-__global__ __launch_bounds__(SCAN_THREADS) void k_carry_apply(ScanArgs A) {
-    const uint64_t b = blockIdx.x;
+__device__ __forceinline__ void carry_apply_body(const ScanArgs &A, const WG &wg) {
+    const uint64_t b = wg.x;
+    if constexpr (AM == APPLY_WRAP) {
+        if (*(const volatile uint32_t *)A.flag == 0u) return;
+    }
+    if constexpr (AM == APPLY_FOLD) {
+        if (b == A.ntiles) {
+            wrap_usual_case(A);
+            return;
+        }
+    }
     const uint64_t mask = (1ull << A.B) - 1;
+    constexpr bool EXTRACT = AM == APPLY_PLAIN;
+    __shared__ uint32_t lb[EXTRACT ? CARRY_TILE + EXTRA_LIMBS : 1];
+    __shared__ uint64_t tx[EXTRACT ? EXTRA_LIMBS : 1];
+    __shared__ uint32_t cout;
+    const uint64_t tile_end = min((b + 1) * CARRY_TILE, A.M);
+    const uint64_t tile_len = b < A.ntiles ? tile_end - b * CARRY_TILE : 0;
+    if (EXTRACT && A.zout && threadIdx.x < EXTRA_LIMBS) {
+        const uint64_t m = (b < A.ntiles ? tile_end : 0) + threadIdx.x;
+        tx[threadIdx.x] = (m < A.M || (A.has_top && m == A.M)) ? A.t[m] : 0ull;
+    }
     // the tile's digit sums (WRAP: limbs) first: their loads overlap the
     // composition below
     const uint64_t base = b * CARRY_TILE + (uint64_t)threadIdx.x * CARRY_PER_THREAD;
@@ -1718,45 +1993,104 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_carry_apply(ScanArgs A) {
         if (b == 0 && threadIdx.x == 0)
             A.out[A.M] = (uint32_t)((tt + (sel ? ct1 : ct0)) & ((1ull << A.s_top) - 1));
     }
-    if (b >= A.ntiles) return;
-    CFn f = cf_id();
+    if (b < A.ntiles) {
+        CFn f = cf_id();
 #pragma unroll
-    for (int v = 0; v < CARRY_PER_THREAD; ++v)
-        if (base + v < A.M) f = cf_compose(f, cf_limb(tv[v], A.B));
-    CFn excl, total;
-    block_scan<SCAN_THREADS>(f, excl, total);
-    uint32_t carry = cf_eval(excl, cf_eval(before, sel));
-    CFn fw = cf_id();
+        for (int v = 0; v < CARRY_PER_THREAD; ++v)
+            if (base + v < A.M) f = cf_compose(f, cf_limb(tv[v], A.B));
+        CFn excl, total;
+        block_scan<SCAN_THREADS>(f, excl, total);
+        uint32_t carry = cf_eval(excl, cf_eval(before, sel));
+        CFn fw = cf_id();
 #pragma unroll
-    for (int v = 0; v < CARRY_PER_THREAD; ++v) {
-        const uint64_t idx = base + v;
-        if (idx < A.M) {
-            const uint64_t val = tv[v] + carry;
-            const uint32_t limb = (uint32_t)(val & mask);
-            A.out[idx] = limb;
-            carry = (uint32_t)(val >> A.B);
-            if (AM == APPLY_FOLD && idx >= A.qv && idx < A.Mw) fw = cf_compose(fw, cf_limb(limb, A.B));
+        for (int v = 0; v < CARRY_PER_THREAD; ++v) {
+            const uint64_t idx = base + v;
+            if (idx < A.M) {
+                const uint64_t val = tv[v] + carry;
+                const uint32_t limb = (uint32_t)(val & mask);
+                A.out[idx] = limb;
+                carry = (uint32_t)(val >> A.B);
+                if constexpr (AM == APPLY_FOLD) {
+                    if (idx >= A.qv && idx < A.Mw) fw = cf_compose(fw, cf_limb(limb, A.B));
+                    if (idx >= WRAP_LO && idx < A.Mw) A.y[idx] = limb;
+                    if (idx == A.Mw) A.y[idx] = limb & (uint32_t)((1ull << A.s_top) - 1);
+                }
+                if constexpr (EXTRACT) lb[idx - b * CARRY_TILE] = limb;
+                if (EXTRACT && idx + 1 == tile_end) cout = carry;
+            }
+        }
+        if constexpr (AM == APPLY_FOLD) {
+            const CFn tw = block_reduce<SCAN_THREADS>(fw);
+            if (threadIdx.x == 0) A.agg_w[b] = tw;
         }
     }
-    if constexpr (AM == APPLY_FOLD) {
-        const CFn tw = block_reduce<SCAN_THREADS>(fw);
-        if (threadIdx.x == 0) A.agg_w[b] = tw;
+    if constexpr (EXTRACT) {
+        if (!A.zout) return;
+        const uint32_t st = A.status[1];
+        if (b == 0 && threadIdx.x == 0) *A.dst = st;
+        if (st != 0u) return;
+        __syncthreads();
+        if (threadIdx.x == 0) {  // the limbs past the tile, from its carry out
+            const uint64_t e0 = b < A.ntiles ? tile_end : 0;
+            uint32_t c = b < A.ntiles ? cout : 0u;
+            for (uint32_t i = 0; i < EXTRA_LIMBS; ++i) {
+                const uint64_t m = e0 + i;
+                uint32_t limb = 0;
+                if (m < A.M) {
+                    const uint64_t v = tx[i] + c;
+                    limb = (uint32_t)(v & mask);
+                    c = (uint32_t)(v >> A.B);
+                } else if (A.has_top && m == A.M) {
+                    limb = (uint32_t)((tx[i] + c) & ((1ull << A.s_top) - 1));
+                }
+                lb[tile_len + i] = limb;
+            }
+        }
+        __syncthreads();
+        // output words starting in bits [lo, hi) of the result
+        const uint64_t off = A.gamma - A.r;  // bit 0 of z
+        const bool last = b + 1 >= max(A.ntiles, (uint64_t)1);
+        const uint64_t lo = b * CARRY_TILE * A.B, hi = last ? A.gamma : tile_end * A.B;
+        const uint64_t w0 = lo <= off ? 0 : (lo - off + 63) / 64;
+        const uint64_t w1 = min(hi <= off ? 0 : (hi - off + 63) / 64, A.out_words);
+        for (uint64_t w = w0 + threadIdx.x; w < w1; w += SCAN_THREADS) {
+            const uint32_t pos = (uint32_t)(off + 64 * w - lo);  // bit position in lb
+            uint64_t v = 0;
+            if (A.B == 32) {  // two funnel shifts of three limbs
+                const uint32_t j = pos >> 5, sh = pos & 31u;
+                const uint32_t l0 = lb[j], l1 = lb[j + 1], l2 = lb[j + 2];
+                v = (uint64_t)__builtin_amdgcn_alignbit(l1, l0, sh) |
+                    (uint64_t)__builtin_amdgcn_alignbit(l2, l1, sh) << 32;
+            } else {
+                uint32_t got = 0;
+                while (got < 64) {
+                    const uint32_t q = pos + got;
+                    const uint32_t j = q / A.B;
+                    const uint32_t sh = q - j * A.B;
+                    const uint32_t take = min(A.B - sh, 64u - got);
+                    v |= (((uint64_t)lb[j] >> sh) & ((1ull << take) - 1)) << got;
+                    got += take;
+                }
+            }
+            const uint64_t left = A.r - 64 * w;
+            if (left < 64) v &= (1ull << left) - 1;
+            A.zout[w] = v;
+        }
     }
+}
+
+template <int AM>
+__global__ __launch_bounds__(SCAN_THREADS) void k_carry_apply(ScanArgs A) { carry_apply_body<AM>(A, wg_self()); }
+
+template <int AM>
+__global__ __launch_bounds__(SCAN_THREADS) void km_carry_apply(const ScanArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
+                                     const uint16_t *__restrict__ owner) {
+    WG wg;
+    const uint32_t i = wg_multi(geo, owner, wg);
+    if (i != MULTI_NONE) carry_apply_body<AM>(tab[i], wg);
 }
 
 // ------------------------------------------------------------------ output
-
-// Also copies the final status word to `dst` (workgroup 0).
-__global__ void k_extract(const uint32_t *__restrict__ U, uint64_t *out, uint64_t out_words, uint64_t r,
-                          uint64_t gamma, uint32_t B, const uint32_t *status, uint32_t *dst) {
-    uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w == 0) *dst = status[1];
-    if (w >= out_words || status[1] != 0u) return;
-    uint64_t v = limbs_get64(U, B, gamma, gamma - r + 64 * w);
-    uint64_t left = r - 64 * w;
-    if (left < 64) v &= (1ull << left) - 1;
-    out[w] = v;
-}
 
 __global__ void k_pack(const uint32_t *__restrict__ limbs, uint64_t *out, uint64_t words, uint64_t gamma,
                        uint32_t B, const uint32_t *status) {
@@ -1767,6 +2101,33 @@ __global__ void k_pack(const uint32_t *__restrict__ limbs, uint64_t *out, uint64
 
 
 inline unsigned blocks_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+// Launch a kernel of the hash sequence on `st`, or record it (with its
+// multi-block form) when the plan records its launches.
+template <class Args>
+void emit(pa_plan *p, int step, const void *single, const void *multi, dim3 grid, dim3 block, size_t lds,
+          const Args &A, hipStream_t st) {
+    static_assert(sizeof(Args) <= KARGS_MAX, "argument struct too large to record");
+    if (p->rec) {
+        p->rec->emplace_back();
+        KLaunch &L = p->rec->back();
+        L.step = step;
+        L.single = single;
+        L.multi = multi;
+        L.grid = grid;
+        L.block = block;
+        L.lds = (uint32_t)lds;
+        L.args_size = (uint32_t)sizeof(Args);
+        std::memcpy(L.args, &A, sizeof(Args));
+        return;
+    }
+    void *args[] = {(void *)&A};
+    (void)hipLaunchKernel(single, grid, block, args, lds, st);
+}
+
+// The single- and multi-block forms of a kernel instance.
+#define PA_KERN(name, ...) (const void *)&k_##name<__VA_ARGS__>, (const void *)&km_##name<__VA_ARGS__>
+#define PA_KERN0(name) (const void *)&k_##name, (const void *)&km_##name
 
 // Pair groups of the generic row kernel: rows shorter than 2048 words run
 // several pairs side by side, a group per pair with one thread per radix-8
@@ -1913,8 +2274,8 @@ hipError_t launch_twiddles(pa_plan *p, hipStream_t st, uint32_t *hdr, uint32_t w
 hipError_t launch_prologue(pa_plan *p, const uint64_t *a, const uint64_t *b, const uint64_t *c,
                            hipStream_t st) {
     phase_mark(p, PA_PH_PROLOGUE, true, st);
-    hipLaunchKernelGGL(k_prologue, dim3(1), dim3(256), 0, st, a, b, c, p->k, p->W, p->gamma, p->notones,
-                       p->status);
+    const PrologueArgs A{a, b, c, p->k, p->W, p->gamma, p->notones, p->status};
+    emit(p, SP_PROLOGUE, PA_KERN0(prologue), dim3(1), dim3(256), 0, A, st);
     phase_mark(p, PA_PH_PROLOGUE, false, st);
     return hipGetLastError();
 }
@@ -1952,6 +2313,7 @@ static ColFwdArgs col_args(pa_plan *p, uint32_t mode) {
 template <int Stage, bool MIX>
 static void launch_col_fwd_generic(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, unsigned zsplit,
                                    hipStream_t st) {
+    const int step = Stage == STAGE_MMH ? SP_MMH_COL : SP_MH_COL;
     const dim3 grid(1u << (p->m2 - cf.c_lg), narrays, zsplit);
     const size_t col_lds = ((size_t)4 << p->m1) << cf.c_lg;
     const uint32_t ntask = (1u << (p->m1 - 3)) << cf.c_lg;
@@ -1959,7 +2321,7 @@ static void launch_col_fwd_generic(pa_plan *p, const ColFwdArgs &cf, unsigned na
 #define PA_COL_FIXED(LGv, CLGv)                                                                              \
     if (p->m1 == LGv && cf.c_lg == CLGv) {                                                                   \
         constexpr int T = (1 << (LGv - 3 + CLGv)) <= COL_THREADS ? 1 : (1 << (LGv - 3 + CLGv)) / COL_THREADS; \
-        hipLaunchKernelGGL((k_col_fwd<Stage, MIX, T, LGv, CLGv>), grid, dim3(COL_THREADS), 0, st, cf);        \
+        emit(p, step, PA_KERN(col_fwd, Stage, MIX, T, LGv, CLGv), grid, dim3(COL_THREADS), 0, cf, st);      \
         return;                                                                                              \
     }
     PA_COL_FIXED(3, 4) PA_COL_FIXED(3, 7) PA_COL_FIXED(3, 8)
@@ -1969,13 +2331,13 @@ static void launch_col_fwd_generic(pa_plan *p, const ColFwdArgs &cf, unsigned na
     PA_COL_FIXED(7, 4) PA_COL_FIXED(8, 4) PA_COL_FIXED(10, 3) PA_COL_FIXED(10, 4)
 #undef PA_COL_FIXED
     if (ntask <= COL_THREADS)
-        hipLaunchKernelGGL((k_col_fwd<Stage, MIX, 1>), grid, dim3(COL_THREADS), col_lds, st, cf);
+        emit(p, step, PA_KERN(col_fwd, Stage, MIX, 1), grid, dim3(COL_THREADS), col_lds, cf, st);
     else if (ntask <= 2 * COL_THREADS)
-        hipLaunchKernelGGL((k_col_fwd<Stage, MIX, 2>), grid, dim3(COL_THREADS), col_lds, st, cf);
+        emit(p, step, PA_KERN(col_fwd, Stage, MIX, 2), grid, dim3(COL_THREADS), col_lds, cf, st);
     else if (ntask <= 4 * COL_THREADS)
-        hipLaunchKernelGGL((k_col_fwd<Stage, MIX, 4>), grid, dim3(COL_THREADS), col_lds, st, cf);
+        emit(p, step, PA_KERN(col_fwd, Stage, MIX, 4), grid, dim3(COL_THREADS), col_lds, cf, st);
     else
-        hipLaunchKernelGGL((k_col_fwd<Stage, MIX, 8>), grid, dim3(COL_THREADS), col_lds, st, cf);
+        emit(p, step, PA_KERN(col_fwd, Stage, MIX, 8), grid, dim3(COL_THREADS), col_lds, cf, st);
 }
 
 // zsplit (1 or 3) workgroups share a tile's transforms, each taking the
@@ -1989,18 +2351,16 @@ static void launch_col_fwd(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, u
     // faster there); the radix-3 key-chunk pass runs the generic kernel's
     // compile-time 1024 x 8 instance, which measured faster for it
     const bool c10 = p->m1 == C10_LG && cf.c_lg == C10_CLG && (!p->mix || Stage == STAGE_MH);
+    const int step = Stage == STAGE_MMH ? SP_MMH_COL : SP_MH_COL;
+    const dim3 grid(ncol_tiles, narrays, zsplit);
     if (c10 && p->mix)
-        hipLaunchKernelGGL((k_col10_fwd<Stage, true>), dim3(ncol_tiles, narrays, zsplit), dim3(COL_THREADS), 0, st,
-                           cf);
+        emit(p, step, PA_KERN(col10_fwd, Stage, true), grid, dim3(COL_THREADS), 0, cf, st);
     else if (c10)
-        hipLaunchKernelGGL((k_col10_fwd<Stage, false>), dim3(ncol_tiles, narrays, zsplit), dim3(COL_THREADS), 0, st,
-                           cf);
+        emit(p, step, PA_KERN(col10_fwd, Stage, false), grid, dim3(COL_THREADS), 0, cf, st);
     else if (c9 && p->mix)  // three primes and radix-3 transforms per tile
-        hipLaunchKernelGGL((k_col9_fwd<Stage, true>), dim3(ncol_tiles, narrays, zsplit), dim3(COL_THREADS), 0, st,
-                           cf);
+        emit(p, step, PA_KERN(col9_fwd, Stage, true), grid, dim3(COL_THREADS), 0, cf, st);
     else if (c9)  // three primes per tile
-        hipLaunchKernelGGL((k_col9_fwd<Stage, false>), dim3(ncol_tiles, narrays, zsplit), dim3(COL_THREADS), 0, st,
-                           cf);
+        emit(p, step, PA_KERN(col9_fwd, Stage, false), grid, dim3(COL_THREADS), 0, cf, st);
     else if (p->mix)
         launch_col_fwd_generic<Stage, true>(p, cf, narrays, zsplit, st);
     else
@@ -2030,12 +2390,13 @@ static RowArgs row_args(pa_plan *p, uint64_t npairs, const uint32_t *seed_side) 
 template <int Stage>
 static void launch_row(pa_plan *p, const RowArgs &ra, hipStream_t st) {
     const unsigned rows = (unsigned)(p->N >> p->m2);  // 2^m1, or 3 * 2^m1 for N = 3 * 2^m
+    const int step = Stage == STAGE_MMH ? SP_MMH_ROW : SP_MH_ROW;
     if (p->m2 == 12) {
-        hipLaunchKernelGGL(k_row16<Stage>, dim3(rows, NPRIMES), dim3(R16_THREADS), 0, st, ra);
+        emit(p, step, PA_KERN(row16, Stage), dim3(rows, NPRIMES), dim3(R16_THREADS), 0, ra, st);
     } else {
         const unsigned groups = row_groups(p, ra.npairs);
-        hipLaunchKernelGGL(k_row<Stage>, dim3(rows, NPRIMES), dim3(groups * ra.row_group),
-                           (size_t)groups * 4 << p->m2, st, ra);
+        emit(p, step, PA_KERN(row, Stage), dim3(rows, NPRIMES), dim3(groups * ra.row_group),
+             (size_t)groups * 4 << p->m2, ra, st);
     }
 }
 
@@ -2055,16 +2416,17 @@ static ColInvArgs colinv_args(pa_plan *p) {
 
 template <int Stage>
 static void launch_col_inv(pa_plan *p, const ColInvArgs &ci, hipStream_t st) {
-    const unsigned nsub = p->mix ? 3u : 1u;  // blockIdx.z: transform of the radix-3 split
+    const unsigned nsub = p->mix ? 3u : 1u;  // grid z: transform of the radix-3 split
+    const int step = Stage == STAGE_MMH ? SP_MMH_COLINV : SP_MH_COLINV;
     if (p->m1 == C9_LG && p->m2 >= C9_CLG)
-        hipLaunchKernelGGL(k_col9_inv<Stage>, dim3(1u << (p->m2 - C9_CLG), NPRIMES, nsub), dim3(COL_THREADS), 0, st,
-                           ci);
+        emit(p, step, PA_KERN(col9_inv, Stage), dim3(1u << (p->m2 - C9_CLG), NPRIMES, nsub), dim3(COL_THREADS), 0,
+             ci, st);
     else if (p->m1 == C10_LG && p->m2 >= C10_CLG)
-        hipLaunchKernelGGL(k_col10_inv<Stage>, dim3(1u << (p->m2 - C10_CLG), NPRIMES, nsub), dim3(COL_THREADS), 0,
-                           st, ci);
+        emit(p, step, PA_KERN(col10_inv, Stage), dim3(1u << (p->m2 - C10_CLG), NPRIMES, nsub), dim3(COL_THREADS),
+             0, ci, st);
     else
-        hipLaunchKernelGGL(k_col_inv<Stage>, dim3(1u << (p->m2 - p->ci_lg), NPRIMES, nsub), dim3(COL_THREADS),
-                           ((size_t)4 << p->m1) << p->ci_lg, st, ci);
+        emit(p, step, PA_KERN(col_inv, Stage), dim3(1u << (p->m2 - p->ci_lg), NPRIMES, nsub), dim3(COL_THREADS),
+             ((size_t)4 << p->m1) << p->ci_lg, ci, st);
 }
 
 hipError_t launch_mmh(pa_plan *p, const uint64_t *key, const uint64_t *a, hipStream_t st) {
@@ -2107,7 +2469,7 @@ static DigitArgs digit_args(pa_plan *p) {
 }
 
 static ScanArgs scan_args(pa_plan *p, uint32_t *out, uint64_t M, bool top, bool dual) {
-    ScanArgs S;
+    ScanArgs S{};
     S.t = p->t;
     S.out = out;
     S.M = M;
@@ -2123,12 +2485,17 @@ static ScanArgs scan_args(pa_plan *p, uint32_t *out, uint64_t M, bool top, bool 
     S.gamma = p->gamma;
     S.M1 = p->M1;
     S.qv = (128 + p->B - 1) / p->B;
+    S.y = p->y;
+    S.flag = p->status + 2;  // the second fold's general case is needed
     return S;
 }
 
+// FOLD: one workgroup more than the tiles (the second fold's usual case).
 template <int AM>
-static void launch_apply(const ScanArgs &S, hipStream_t st) {
-    hipLaunchKernelGGL(k_carry_apply<AM>, dim3((unsigned)(S.ntiles ? S.ntiles : 1)), dim3(SCAN_THREADS), 0, st, S);
+static void launch_apply(pa_plan *p, const ScanArgs &S, hipStream_t st) {
+    const uint64_t wg = AM == APPLY_FOLD ? S.ntiles + 1 : (S.ntiles ? S.ntiles : 1);
+    const int step = AM == APPLY_FOLD ? SP_FOLD_APPLY : AM == APPLY_WRAP ? SP_FOLD_WRAP : SP_MH_APPLY;
+    emit(p, step, PA_KERN(carry_apply, AM), dim3((unsigned)wg), dim3(SCAN_THREADS), 0, S, st);
 }
 
 // Carry normalisation of the digit sums A.t[0..M) (plus the top limb at M if
@@ -2138,24 +2505,32 @@ static void launch_apply(const ScanArgs &S, hipStream_t st) {
 // coefficient word planes.
 template <int MODE>
 static hipError_t run_carry(pa_plan *p, DigitArgs A, uint32_t *out, uint64_t ndig, uint64_t M, bool top,
-                            bool dual, hipStream_t st, DigitCrtArgs *crt) {
+                            bool dual, hipStream_t st, DigitCrtArgs *crt, uint64_t *zout = nullptr,
+                            uint32_t *dst = nullptr) {
     A.ndig = ndig;
     A.M = M;
     const uint64_t tiles_t = (ndig + CARRY_TILE - 1) / CARRY_TILE;
+    const int step = MODE == DIG_FOLD ? SP_FOLD_DIGIT : SP_MH_DIGIT;
     if (tiles_t && crt) {
         crt->D = A;
-        hipLaunchKernelGGL(k_digit_crt<MODE>, dim3((unsigned)tiles_t), dim3(CARRY_TILE), 0, st, *crt);
+        emit(p, step, PA_KERN(digit_crt, MODE), dim3((unsigned)tiles_t), dim3(CARRY_TILE), 0, *crt, st);
     } else if (tiles_t) {
-        hipLaunchKernelGGL(k_digit_tile<MODE>, dim3((unsigned)tiles_t), dim3(CARRY_TILE), 0, st, A);
+        emit(p, step, PA_KERN(digit_tile, MODE), dim3((unsigned)tiles_t), dim3(CARRY_TILE), 0, A, st);
     }
-    launch_apply<MODE == DIG_FOLD ? APPLY_FOLD : APPLY_PLAIN>(scan_args(p, out, M, top, dual), st);
+    ScanArgs S = scan_args(p, out, M, top, dual);
+    S.zout = zout;  // MH: the output extraction rides on the apply
+    S.out_words = p->out_words;
+    S.r = p->r;
+    S.status = p->status;
+    S.dst = dst;
+    launch_apply<MODE == DIG_FOLD ? APPLY_FOLD : APPLY_PLAIN>(p, S, st);
     return hipGetLastError();
 }
 
 // Coefficients [0, count) of the convolution for N = 3 * 2^m from the
 // residues in Cc, as word planes in C96 (with notones: also the RELOAD
 // status).  For N = 2^m the digit kernels reconstruct the coefficients.
-static void launch_crt3(pa_plan *p, uint64_t count, const uint32_t *notones, hipStream_t st) {
+static void launch_crt3(pa_plan *p, uint64_t count, const uint32_t *notones, int step, hipStream_t st) {
     Crt3Args A;
     A.cc = p->Cc;
     A.c96 = p->C96;
@@ -2171,7 +2546,7 @@ static void launch_crt3(pa_plan *p, uint64_t count, const uint32_t *notones, hip
     A.notones = notones;
     A.k = notones ? p->k : 0;
     A.status = p->status;
-    hipLaunchKernelGGL(k_crt3, dim3(blocks_for(count < p->Nsub ? count : p->Nsub, 256)), dim3(256), 0, st, A);
+    emit(p, step, PA_KERN0(crt3), dim3(blocks_for(count < p->Nsub ? count : p->Nsub, 256)), dim3(256), 0, A, st);
 }
 
 // Reconstruction inside the digit kernel (N = 2^m); nullptr for N = 3 * 2^m,
@@ -2192,23 +2567,26 @@ hipError_t launch_fold(pa_plan *p, hipStream_t st) {
     const uint64_t ncoef = 2 * p->L - 1;  // nonzero coefficients of the product
     DigitCrtArgs C;
     DigitCrtArgs *crt = residue_digits(p, C, p->notones);
-    if (!crt) launch_crt3(p, ncoef, p->notones, st);
-    // first fold at bit gamma, normalised over M1 digits (the sum fits: no carry out)
+    if (!crt) launch_crt3(p, ncoef, p->notones, SP_FOLD_CRT3, st);
+    // first fold at bit gamma, normalised over M1 digits (the sum fits: no carry out);
+    // its apply also writes y for the second fold's usual case (V mod p changes only
+    // the lowest limbs) and sets a flag when that case does not apply
     hipError_t e = run_carry<DIG_FOLD>(p, digit_args(p), p->s, p->M1, p->M1, false, false, st, crt);
     if (e != hipSuccess) return e;
-    // second fold: y = T_lo + (V mod p) over L limbs, straight from the limbs of the
-    // first (whose apply left the wrap chain's tile aggregates); the dual
-    // evaluation (carry-in 0 or 1) selects S or S + 1 - 2^gamma, which maps a
-    // sum equal to p to 0
+    // second fold, general case (runs only when flagged): y = T_lo + (V mod p) over L
+    // limbs, straight from the limbs of the first (whose apply left the wrap chain's
+    // tile aggregates); the dual evaluation (carry-in 0 or 1) selects S or
+    // S + 1 - 2^gamma, which maps a sum equal to p to 0
     ScanArgs S = scan_args(p, p->y, p->L - 1, true, true);
     S.agg = p->agg_w;
-    launch_apply<APPLY_WRAP>(S, st);
+    launch_apply<APPLY_WRAP>(p, S, st);
     e = hipGetLastError();
     phase_mark(p, PA_PH_FOLD, false, st);
     return e;
 }
 
-hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, hipStream_t st) {
+hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, uint64_t *out, uint32_t *d_status,
+                     hipStream_t st) {
     ColFwdArgs cf = col_args(p, 1);
     cf.b = b;
     cf.ylimbs = p->y;
@@ -2234,19 +2612,18 @@ hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, hipStream
     // only the coefficients below limb L matter mod 2^gamma
     DigitCrtArgs C;
     DigitCrtArgs *crt = residue_digits(p, C, nullptr);
-    if (!crt) launch_crt3(p, p->L, nullptr, st);
+    if (!crt) launch_crt3(p, p->L, nullptr, SP_MH_CRT3, st);
     DigitArgs A = digit_args(p);
     A.cseed = c;
-    hipError_t e = run_carry<DIG_MH>(p, A, p->U, p->L, p->L - 1, true, false, st, crt);
+    // the apply also extracts z and copies the status flags out
+    hipError_t e = run_carry<DIG_MH>(p, A, p->U, p->L, p->L - 1, true, false, st, crt, out,
+                                     d_status ? d_status : p->status_out);
     phase_mark(p, PA_PH_MH_CARRY, false, st);
     return e;
 }
 
-hipError_t launch_finish(pa_plan *p, uint64_t *out, uint32_t *d_status, uint64_t *y_out, uint64_t *U_out,
-                         hipStream_t st) {
+hipError_t launch_finish(pa_plan *p, uint64_t *y_out, uint64_t *U_out, hipStream_t st) {
     phase_mark(p, PA_PH_FINISH, true, st);
-    hipLaunchKernelGGL(k_extract, dim3(blocks_for(p->out_words, 256)), dim3(256), 0, st, p->U, out,
-                       p->out_words, p->r, p->gamma, p->B, p->status, d_status ? d_status : p->status_out);
     if (y_out)
         hipLaunchKernelGGL(k_pack, dim3(blocks_for(p->W, 256)), dim3(256), 0, st, p->y, y_out, p->W, p->gamma,
                            p->B, p->status);

@@ -9,8 +9,13 @@
 // completion event.  pa_poll reports PA_PENDING until the request is done, then its
 // status and timing.  Each admitted request's device memory (scratch, key,
 // output) is placed first-fit in one arena of the configured budget, so the
-// budget is exact.  Twiddle tables are built once per transform length and
-// shared by every slot.
+// budget is exact.  The twiddle tables of each transform length and the seed
+// transforms of each (session, class, shape) are resident sets in a second
+// arena of the resident budget (pa_resident.hpp): shared by every slot,
+// built on a stream of their own the first time a request needs them (the
+// request's stream waits for the build's event, the worker does not), and
+// evicted least recently used first when a new set needs room and no
+// admitted request holds them.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -25,6 +30,7 @@
 #include <vector>
 
 #include "pa_internal.hpp"
+#include "pa_resident.hpp"
 
 namespace {
 
@@ -39,9 +45,6 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Seeds {
     uint64_t gamma, kmax;
     uint64_t *d_a, *d_b, *d_c;  // one device allocation: kmax*W + W + W words
-    // column-pass transforms of a (kmax x 3 x N words) and b (3 x N words),
-    // per transform shape (limb width B << 8 | pa::len_key), built on first use
-    std::map<uint32_t, uint32_t *> trans;
 };
 
 struct Request {
@@ -51,6 +54,8 @@ struct Request {
     pa::PlanLayout lay{};
     size_t footprint = 0;  // scratch + key + output bytes on the device
     size_t offset = 0;     // placement in the arena while admitted
+    pa::ResidentKey tkey{}, skey{};  // its resident sets: twiddle tables, seed transforms
+    size_t tbytes = 0, sbytes = 0;
     Clock::time_point t_submit, t_admit;
 };
 
@@ -97,7 +102,10 @@ struct pa_server {
     void *arena = nullptr;       // hbm_budget_bytes
     Placer placer;
     std::map<uint64_t, Seeds> seeds;  // key: seed_key(session, gamma)
-    std::vector<std::pair<uint32_t, void *>> tables;  // transform length -> twiddle tables
+    void *res_arena = nullptr;        // resident_budget_bytes: twiddle tables and seed transforms
+    pa::ResidentCache resident{0};
+    hipStream_t build = nullptr;      // resident sets are built here
+    std::vector<hipEvent_t> ev_pool;  // build events of evicted sets, for reuse
     std::vector<Slot> slots;
     uint64_t next_ticket = 1;
     bool stop = false;
@@ -107,26 +115,6 @@ struct pa_server {
 namespace {
 
 uint64_t seed_key(uint32_t session, uint64_t gamma) { return ((uint64_t)session << 32) ^ gamma; }
-
-// Twiddle tables for r's transform length; built synchronously on `st` the
-// first time (worker thread only).
-void *tables_for(pa_server *s, Request &r, hipStream_t st) {
-    for (auto &t : s->tables)
-        if (t.first == pa::len_key(r.plan)) return t.second;
-    void *base = nullptr;
-    if (hipMalloc(&base, r.lay.table_bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-    }
-    pa::bind_tables(&r.plan, base, r.lay);
-    if (pa::launch_twiddles(&r.plan, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipFree(base);
-        return nullptr;
-    }
-    s->tables.emplace_back(pa::len_key(r.plan), base);
-    return base;
-}
 
 void finish(pa_server *s, Request &r, pa_status st, double device_ms) {
     Done d;
@@ -139,47 +127,100 @@ void finish(pa_server *s, Request &r, pa_status st, double device_ms) {
     s->done[r.ticket] = d;
 }
 
-// Resident seed transforms of sd for r's shape; built synchronously on `st`
-// the first time (worker thread only).
-uint32_t *seed_transforms(Seeds &sd, Request &r, hipStream_t st) {
-    const uint32_t key = r.plan.B << 8 | pa::len_key(r.plan);
-    auto it = sd.trans.find(key);
-    if (it != sd.trans.end()) return it->second;
-    const size_t words = (size_t)(sd.kmax + 1) * pa::NPRIMES * r.plan.N;
-    uint32_t *d = nullptr;
-    if (hipMalloc((void **)&d, words * 4) != hipSuccess) {
+uint32_t shape_of(const pa_plan &p) { return p.B << 8 | pa::len_key(p); }
+
+hipEvent_t take_event(pa_server *s) {
+    if (!s->ev_pool.empty()) {
+        hipEvent_t e = s->ev_pool.back();
+        s->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         return nullptr;
     }
-    uint32_t *db = d + (size_t)sd.kmax * pa::NPRIMES * r.plan.N;
-    if (pa::launch_seed_transforms(&r.plan, sd.d_a, sd.kmax, sd.d_b, d, db, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipFree(d);
-        return nullptr;
-    }
-    sd.trans[key] = d;
-    return d;
+    return e;
 }
 
-// Enqueue request r on slot sl (worker thread).  Returns PA_OK or an error
-// (then nothing of r is in flight).
-pa_status launch(pa_server *s, Slot &sl, Request &r, Seeds &sd) {
-    // r's arena range: scratch, then the key, then the output
-    void *tb = tables_for(s, r, sl.st);
-    if (!tb) return PA_ERR_NOMEM;
-    pa::bind_tables(&r.plan, tb, r.lay);
-    uint32_t *tr = seed_transforms(sd, r, sl.st);
-    if (!tr) return PA_ERR_NOMEM;
-    r.plan.res_a = tr;
-    r.plan.res_b = tr + (size_t)sd.kmax * pa::NPRIMES * r.plan.N;
+// The resident sets of r (twiddle tables, then seed transforms): found, or
+// placed (evicting idle sets) and their builds enqueued on the build stream,
+// each followed by its ready event (entry->aux).  Both are held by r on
+// success.  Returns false when they cannot be placed now (nothing changed
+// then) or a build could not be enqueued (worker thread, lock held).
+bool acquire_resident(pa_server *s, Request &r, Seeds &sd, bool *failed) {
+    *failed = false;
+    pa::ResidentCache &C = s->resident;
+    std::vector<pa::ResidentCache::Entry> evicted;
+    pa::ResidentCache::Entry *te = C.find(r.tkey);
+    const bool new_t = te == nullptr;
+    if (new_t) te = C.insert(r.tkey, r.tbytes, &evicted);
+    if (!te) return false;
+    C.acquire(te);
+    pa::ResidentCache::Entry *se = C.find(r.skey);
+    const bool new_s = se == nullptr;
+    if (new_s) se = C.insert(r.skey, r.sbytes, &evicted);
+    for (const auto &e : evicted)
+        if (e.aux) s->ev_pool.push_back((hipEvent_t)e.aux);
+    if (!se) {
+        C.release(te);
+        if (new_t) C.erase(r.tkey);
+        return false;
+    }
+    C.acquire(se);
+    char *base = (char *)s->res_arena;
+    pa::bind_tables(&r.plan, base + te->off, r.lay);
+    bool ok = true;
+    if (new_t) {
+        hipEvent_t ev = take_event(s);
+        ok = ev && pa::launch_twiddles(&r.plan, s->build) == hipSuccess && hipEventRecord(ev, s->build) == hipSuccess;
+        te->aux = ev;
+    }
+    uint32_t *d = (uint32_t *)(base + se->off);
+    uint32_t *db = d + (size_t)sd.kmax * pa::NPRIMES * r.plan.N;
+    if (ok && new_s) {
+        hipEvent_t ev = take_event(s);
+        ok = ev && pa::launch_seed_transforms(&r.plan, sd.d_a, sd.kmax, sd.d_b, d, db, s->build) == hipSuccess &&
+             hipEventRecord(ev, s->build) == hipSuccess;
+        se->aux = ev;
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        C.release(te);
+        C.release(se);
+        if (new_s) {
+            if (se->aux) s->ev_pool.push_back((hipEvent_t)se->aux);
+            C.erase(r.skey);
+        }
+        if (new_t) {
+            if (te->aux) s->ev_pool.push_back((hipEvent_t)te->aux);
+            C.erase(r.tkey);
+        }
+        *failed = true;
+        return false;
+    }
+    r.plan.res_a = d;
+    r.plan.res_b = db;
+    return true;
+}
+
+void release_resident(pa_server *s, Request &r) {
+    if (pa::ResidentCache::Entry *e = s->resident.find(r.tkey)) s->resident.release(e);
+    if (pa::ResidentCache::Entry *e = s->resident.find(r.skey)) s->resident.release(e);
+}
+
+// Enqueue request r on slot sl (worker thread), its resident sets acquired:
+// the slot's stream waits for their builds.  Returns PA_OK or an error (then
+// nothing of r is in flight).
+pa_status launch(pa_server *s, Slot &sl, Request &r, Seeds &sd, hipEvent_t ev_t, hipEvent_t ev_s) {
     char *base = (char *)s->arena + r.offset;
     pa::bind_scratch(&r.plan, base, r.lay);
     uint64_t *d_key = (uint64_t *)(base + r.lay.scratch_bytes);
     uint64_t *d_out = (uint64_t *)(base + r.lay.scratch_bytes + align256(r.plan.key_words * 8));
     const size_t key_bytes = (size_t)r.plan.key_words * 8, out_bytes = (size_t)r.plan.out_words * 8;
     if (hipEventRecord(sl.ev0, sl.st) != hipSuccess ||
-        hipMemcpyAsync(d_key, r.req.key, key_bytes, hipMemcpyHostToDevice, sl.st) != hipSuccess) {
+        hipMemcpyAsync(d_key, r.req.key, key_bytes, hipMemcpyHostToDevice, sl.st) != hipSuccess ||
+        hipStreamWaitEvent(sl.st, ev_t, 0) != hipSuccess || hipStreamWaitEvent(sl.st, ev_s, 0) != hipSuccess) {
         (void)hipGetLastError();
         return PA_ERR_DEVICE;
     }
@@ -218,6 +259,7 @@ void worker_main(pa_server *s) {
             }
             sl.busy = false;
             s->placer.release(sl.cur.offset);
+            release_resident(s, sl.cur);
             Request r = sl.cur;
             lk.unlock();
             finish(s, r, st, dev_ms);
@@ -234,21 +276,36 @@ void worker_main(pa_server *s) {
                 }
             size_t off = 0;
             if (!free_slot || !s->placer.place(head.footprint, &off)) break;
+            // presence checked at submission; seeds are never removed, and map
+            // nodes stay put, so the reference outlives the lock
+            Seeds &sd = s->seeds.find(seed_key(head.req.session, head.plan.gamma))->second;
+            bool failed = false;
+            if (!acquire_resident(s, head, sd, &failed) && !failed) {
+                s->placer.release(off);  // the resident sets in use leave no room yet
+                break;
+            }
             Request r = head;
             r.offset = off;
             s->queue.pop_front();
-            // presence checked at submission; seeds are never removed, and map
-            // nodes stay put, so the reference outlives the lock
-            Seeds &sd = s->seeds.find(seed_key(r.req.session, r.plan.gamma))->second;
             r.t_admit = Clock::now();
+            if (failed) {
+                s->placer.release(off);
+                lk.unlock();
+                finish(s, r, PA_ERR_DEVICE, 0.0);
+                lk.lock();
+                continue;
+            }
+            const hipEvent_t ev_t = (hipEvent_t)s->resident.find(r.tkey)->aux;
+            const hipEvent_t ev_s = (hipEvent_t)s->resident.find(r.skey)->aux;
             free_slot->busy = true;
             free_slot->cur = r;
             lk.unlock();
-            pa_status e = launch(s, *free_slot, free_slot->cur, sd);
+            pa_status e = launch(s, *free_slot, free_slot->cur, sd, ev_t, ev_s);
             lk.lock();
             if (e != PA_OK) {
                 free_slot->busy = false;
                 s->placer.release(r.offset);
+                release_resident(s, r);
                 lk.unlock();
                 finish(s, r, e, 0.0);
                 lk.lock();
@@ -274,12 +331,14 @@ void release(pa_server *s) {
         if (sl.h_status) (void)hipHostFree(sl.h_status);
         if (sl.st) (void)hipStreamDestroy(sl.st);
     }
-    for (auto &t : s->tables) (void)hipFree(t.second);
-    for (auto &kv : s->seeds) {
-        (void)hipFree(kv.second.d_a);
-        for (auto &t : kv.second.trans) (void)hipFree(t.second);
-    }
+    if (s->build) (void)hipStreamSynchronize(s->build);
+    for (const auto &e : s->resident.all())
+        if (e.aux) (void)hipEventDestroy((hipEvent_t)e.aux);
+    for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+    if (s->build) (void)hipStreamDestroy(s->build);
+    for (auto &kv : s->seeds) (void)hipFree(kv.second.d_a);
     if (s->arena) (void)hipFree(s->arena);
+    if (s->res_arena) (void)hipFree(s->res_arena);
     (void)hipGetLastError();
     delete s;
 }
@@ -297,13 +356,16 @@ pa_status pa_server_create(const pa_server_cfg *cfg, pa_server **out) {
     pa_server *s = new (std::nothrow) pa_server();
     if (!s) return PA_ERR_NOMEM;
     s->cfg = *cfg;
-    if (hipMalloc(&s->arena, cfg->hbm_budget_bytes) != hipSuccess) {
+    if (s->cfg.resident_budget_bytes == 0) s->cfg.resident_budget_bytes = cfg->hbm_budget_bytes;
+    if (hipMalloc(&s->arena, cfg->hbm_budget_bytes) != hipSuccess ||
+        hipMalloc(&s->res_arena, s->cfg.resident_budget_bytes) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->build, hipStreamNonBlocking) != hipSuccess) {
         (void)hipGetLastError();
-        s->arena = nullptr;
         release(s);
         return PA_ERR_NOMEM;
     }
     s->placer.size = cfg->hbm_budget_bytes;
+    s->resident = pa::ResidentCache(s->cfg.resident_budget_bytes);
     s->slots.resize(cfg->max_inflight);
     for (Slot &sl : s->slots) {
         bool ok = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) == hipSuccess &&
@@ -386,11 +448,18 @@ pa_status pa_submit(pa_server *s, const pa_request *req, uint64_t *ticket) {
     r.plan.device = s->cfg.device;
     r.footprint = r.lay.scratch_bytes + align256(r.plan.key_words * 8) + align256(r.plan.out_words * 8);
     if (r.footprint > s->cfg.hbm_budget_bytes) return PA_ERR_LIMIT;
+    r.tkey = pa::ResidentKey{0, 0, 0, shape_of(r.plan)};
+    r.skey = pa::ResidentKey{1, req->session, r.plan.gamma, shape_of(r.plan)};
+    r.tbytes = r.lay.table_bytes;
     r.t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> g(s->mu);
         auto it = s->seeds.find(seed_key(req->session, r.plan.gamma));
         if (it == s->seeds.end() || it->second.kmax < r.plan.k) return PA_ERR_ARG;
+        // the seed transforms: kmax + 1 arrays of 3 x N words; with the
+        // tables they must fit the resident budget on their own
+        r.sbytes = (size_t)(it->second.kmax + 1) * pa::NPRIMES * r.plan.N * 4;
+        if (align256(r.tbytes) + align256(r.sbytes) > s->cfg.resident_budget_bytes) return PA_ERR_LIMIT;
         if (s->stop) return PA_ERR_BUSY;
         r.ticket = s->next_ticket++;
         *ticket = r.ticket;

@@ -1,6 +1,6 @@
 """GPU parity of the batched entry point (pa_hash_batched): blocks of uneven
-(n, r) in one call against the CPU oracle (small blocks) and against one
-pa_hash call per block (large blocks).  Every case prints its name, seed and
+(n, r) in one call against the CPU oracle (small and mid-size blocks) and
+against the oracle's stored digests (the full uneven-batch range).  Every case prints its name, seed and
 shapes before it touches the GPU."""
 import sys
 
@@ -69,25 +69,21 @@ def test_batched_small_blocks_against_oracle(pa):
     assert per[-3] == 2 and per[-2] == -5  # RELOAD, SEED_B_EVEN
 
 
-def test_batched_large_uneven_blocks_against_per_block_calls(pa):
-    """Sixteen blocks drawn like the uneven-batch workload (seed 3, n
-    log-uniform in [2^22, 2^26]): every output equals the single-block
-    pa_hash output for the same inputs, and a second call with a different
-    batch (new transform lengths, larger arenas) on the same plan still does.
-    The single-block path is the one the full-size oracle digests pin."""
-    import torch
+def test_batched_mid_size_blocks_against_oracle(pa):
+    """Sixteen blocks drawn like the uneven-batch workload but with n
+    log-uniform in [2^18, 2^22] (seed 3), then six more (seed 35) in a second
+    call on the same plan (new transform lengths, a larger arena): every
+    output equals the oracle's."""
     with pa.BatchPlan(64, 1 << 36) as bp:
         for seed, count in ((3, 16), (35, 6)):
-            blocks = synth.uneven_blocks(seed, count, _shape, 22, 26)
-            say(f"[case] batched large seed={seed}:", [(b.n, b.r, b.gamma, b.k) for b in blocks])
+            blocks = synth.uneven_blocks(seed, count, _shape, 18, 22)
+            say(f"[case] batched mid-size seed={seed}:", [(b.n, b.r, b.gamma, b.k) for b in blocks])
             dev = [_dev(pa, b) for b in blocks]
             st, per = bp.hash(dev)
             assert st == 0 and all(s == 0 for s in per), per
             for blk, d in zip(blocks, dev):
-                with pa.Plan(blk.n, blk.r) as plan:
-                    s1, out1 = plan.hash(*d[2:6])
-                assert s1 == 0
-                assert torch.equal(out1, d[6]), (blk.n, blk.r)
+                st_o, out_o = oracle.hash(blk.key, blk.n, blk.r, blk.gamma, blk.a, blk.b, blk.c)
+                assert st_o == 0 and np.array_equal(pa.from_device(d[6]), out_o), (blk.n, blk.r)
 
 
 def test_batched_call_errors(pa):
@@ -107,7 +103,7 @@ def test_batched_call_errors(pa):
 def test_batched_tuned_equals_untuned(pa):
     """After pa_batch_plan_tune the same blocks (now built with the tuned
     limb width, length form and tile width per (gamma, k) class) hash to the
-    same outputs."""
+    same outputs, which equal the oracle's."""
     import torch
     blocks = synth.uneven_blocks(41, 8, _shape, 18, 23)
     say("[case] batched tuned:", [(b.n, b.r, b.gamma, b.k) for b in blocks])
@@ -125,6 +121,9 @@ def test_batched_tuned_equals_untuned(pa):
         assert st == 0 and all(x == 0 for x in per), per
         for o, d in zip(outs, dev):
             assert torch.equal(o, d[6])
+    for blk, d in zip(blocks, dev):
+        st_o, out_o = oracle.hash(blk.key, blk.n, blk.r, blk.gamma, blk.a, blk.b, blk.c)
+        assert st_o == 0 and np.array_equal(pa.from_device(d[6]), out_o), (blk.n, blk.r)
 
 
 def test_batched_graph_replay(pa):
@@ -175,3 +174,47 @@ def test_batched_graph_replay(pa):
         dev[0][2].copy_(pa.to_device(b0.key))
         st, per = bp.hash(dev)
         assert st == 0 and all(torch.equal(o, d[6]) for o, d in zip(ref, dev))
+
+
+def test_batched_uneven_draws_against_oracle_digests(pa):
+    """The uneven-batch draws stored by tests/golden/make_golden.py (oracle
+    only): 16 blocks with n log-uniform in [2^22, 2^28] and r/n in
+    [0.05, 0.30] (seed 3), 4 blocks from [2^27, 2^28] (seed 15) and the
+    range's top corner n = 2^28 - 1, r = 0.3 n, all in one batched call;
+    every output's digest equals the oracle's.  Then the same call again
+    with the blocks in reverse order (different placement in the arena and
+    in the multi-block launches)."""
+    import hashlib
+    import json
+    import os
+    import torch
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "full_size.json")))
+    blocks, want = [], []
+    for name in ("batched_seed3_16", "batched_top_seed15_4"):
+        recs = sorted((v for k, v in gold.items() if k.startswith(name + "/")), key=lambda v: v["index"])
+        g0 = recs[0]
+        drawn = synth.uneven_blocks(g0["seed"], g0["count"], _shape, g0["n_lo_log2"], g0["n_hi_log2"], g0["f_lo"],
+                                    g0["f_hi"])
+        assert len(recs) == g0["count"] == len(drawn)
+        for blk, rec in zip(drawn, recs):
+            assert (blk.n, blk.r, blk.gamma, blk.k) == (rec["n"], rec["r"], rec["gamma"], rec["k"])
+            blocks.append(blk)
+            want.append(rec)
+    c = gold["corner_2p28_r03"]
+    blocks.append(synth.single_block(c["seed"], c["n"], c["r"], c["gamma"], c["k"]))
+    want.append(c)
+    say("[case] batched oracle digests:", [(b.n, b.r, b.gamma, b.k) for b in blocks])
+    dev = [_dev(pa, b) for b in blocks]
+    total = sum(b.n for b in blocks)
+    with pa.BatchPlan(64, total) as bp:
+        for rnd, idx in enumerate((list(range(len(dev))), list(range(len(dev)))[::-1])):
+            for d in dev:
+                d[6].zero_()
+            st, per = bp.hash([dev[i] for i in idx])
+            assert st == 0 and all(s == 0 for s in per), (rnd, per)
+            for i in idx:
+                out = pa.from_device(dev[i][6])
+                dig = hashlib.sha256(np.ascontiguousarray(out, dtype=np.uint64).tobytes()).hexdigest()
+                assert want[i]["status"] == 0 and dig == want[i]["out_sha256"], (rnd, i, blocks[i].n, blocks[i].r)
+    del dev
+    torch.cuda.empty_cache()

@@ -371,7 +371,8 @@ def _digest(words):
 
 @pytest.mark.parametrize("flags", [0, 1])
 @pytest.mark.parametrize("name", ["single_block_2p20", "single_block_2p6e8", "paper_cv_block",
-                                  "max_length_single_chunk", "len_2p22_single_chunk", "len_2p23_single_chunk"])
+                                  "max_length_single_chunk", "len_2p22_single_chunk", "len_2p23_single_chunk",
+                                  "cv_8e8_block", "corner_2p28_r03"])
 def test_full_size_blocks_against_stored_oracle_digest(pa, name, flags):
     """Full-size blocks, in the launch configuration the benchmark times,
     against digests written by tests/golden/make_golden.py (oracle only);
@@ -480,3 +481,26 @@ def test_power_of_two_seeds_1024_row_columns(pa):
     assert (i3["N"], i3["log2N1"]) == (3 << 21, 9)
     assert pa.plan_query(n, r)[1]["N"] == 1 << 22
     _rotation_closed_form(pa, n, r, 78, "1024-row columns")
+
+
+@pytest.mark.parametrize("gamma,k,flags,B", [(4423, 5, 0, 0), (4423, 5, 0, 8), (44497, 3, 2, 0), (44497, 3, 1, 8),
+                                             (110503, 10, 1, 0), (756839, 2, 2, 8)])
+def test_key_bits_past_n_are_ignored(pa, gamma, k, flags, B):
+    """Bits >= n of the key's last word are ignored (the split zero-pads the
+    key past bit n, Alg. 1): with every such bit set, the output equals the
+    oracle's for the same words and the output of the masked key; ragged n
+    on both length forms, at the automatic limb width and at B = 8."""
+    n = k * gamma - 1000 - (gamma % 61)
+    assert n % 64 != 0
+    r = gamma // 4
+    st, g, kk = defn.plan_shape(n, r, gamma)
+    assert st == 0 and kk == k
+    blk = synth.single_block(9000 + gamma + B + flags, n, r, g, kk)
+    masked = blk.key.copy()
+    blk.key[-1] |= ~np.uint64((1 << (n % 64)) - 1)  # every bit >= n of the last word
+    assert blk.key[-1] != masked[-1]
+    label = f"tail bits set gamma={gamma} k={k} n%64={n % 64} flags={flags} B={B}"
+    _, out_tail = check_block(pa, blk, B=B, flags=flags, label=label)
+    blk.key = masked
+    _, out_masked = check_block(pa, blk, B=B, flags=flags, label=label + " (masked)")
+    assert np.array_equal(out_tail, out_masked)
