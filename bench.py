@@ -388,6 +388,10 @@ def bench_batched(args):
     log(f"[bench] batched: {len(blocks)} blocks, {total} key bits")
     K, Wm = args.steps, max(1, args.warmup)
     leg, bp = batched_leg(pa, blocks, bufs, dev, K, Wm)
+    if args.core_only:  # the batched and serial calls only (for a profiler)
+        bp.close()
+        print(json.dumps({"batched": leg}), flush=True)
+        return
     outs_b = [x[6].clone() for x in bufs]
     stream = torch.cuda.current_stream(dev)
 
@@ -432,6 +436,45 @@ def bench_batched(args):
         "small_blocks": small,
     }
     print(json.dumps(rec), flush=True)
+
+
+def bench_rule(args):
+    """The plan rule's length form against device timings: for every (gamma, k)
+    class of the uneven-batch workload, pa_plan_tune times the candidates of
+    each length form alone (round robin, median; the form fixed by its flag),
+    and the class counts as agreeing when the form the rule picks is within
+    3% of the faster form.  One JSON line per class, then a summary line."""
+    import paper_2105_13678_amd as pa
+    from paper_2105_13678_amd import synth
+
+    def shape(n, r):
+        st, info = pa.plan_query(n, r)
+        assert st == 0, (n, r, st)
+        return info["gamma"], info["k"]
+
+    blocks = synth.uneven_blocks(BATCH_SEED, BATCH_COUNT, shape, 22, 28)
+    classes = {}
+    for b in blocks:
+        classes.setdefault(shape(b.n, b.r), (b.n, b.r))
+    agree, rows = 0, []
+    for (g, k), (n, r) in sorted(classes.items()):
+        _, rule = pa.plan_query(n, r)
+        rec = {"gamma": g, "k": k, "n": n, "r": r,
+               "rule": {"N": rule["N"], "B": rule["B"], "form": "radix3" if rule["len_factor"] == 3 else "pow2"}}
+        for label, flags in (("pow2", pa.PA_FLAG_POW2_LENGTHS), ("radix3", pa.PA_FLAG_RADIX3_LENGTHS)):
+            st, info = pa.plan_query(n, r, flags=flags)
+            if st != 0:
+                continue
+            best, ms = pa.plan_tune(n, r, reps=5, flags=flags)
+            rec[label] = {"N": info["N"], "ms": round(ms, 4), "B": best["B"], "col_lg": best["col_lg"]}
+        forms = [rec[f]["ms"] for f in ("pow2", "radix3") if f in rec]
+        rec["agree"] = rec[rec["rule"]["form"]]["ms"] <= 1.03 * min(forms)
+        agree += rec["agree"]
+        rows.append(rec)
+        print(json.dumps(rec), flush=True)
+    print(json.dumps({"metric": "plan rule agrees with the faster length form (within 3%)",
+                      "classes": len(rows), "agree": agree, "fraction": round(agree / len(rows), 3),
+                      "workload": "the (gamma, k) classes of 64 uneven blocks, splitmix64 seed 3"}), flush=True)
 
 
 LENGTH_BLOCKS = [(800_000_000, 80_000_000, 6), (1 << 32, 1 << 27, 7), (500_000_000, 50_000_000, 5)]
@@ -582,7 +625,7 @@ def bench_serving(args):
         live = {}  # ticket -> (index, t_submit)
         free = list(range(len(outs)))
         t0 = time.perf_counter()
-        i = 0
+        i = done = 0
         while i < len(schedule) or live:
             now = time.perf_counter() - t0
             while i < len(schedule) and schedule[i][0] <= now and free:
@@ -601,6 +644,9 @@ def bench_serving(args):
                 lat[j] = (time.perf_counter() - ts) * 1e3
                 tm[j] = timing
                 free.append(slot)
+                done += 1
+                if done % 1000 == 0:
+                    log(f"[bench] serving: {done}/{len(schedule)} requests done")
             time.sleep(0.0001)
         return lat, tm, time.perf_counter() - t0
 
@@ -655,18 +701,20 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed region, copy a buffer of this many MiB with a plain device "
                          "copy kernel (reference point for the HBM byte counters)")
-    ap.add_argument("--workload", choices=["single", "batched", "serving", "lengths"], default="single",
+    ap.add_argument("--workload", choices=["single", "batched", "serving", "lengths", "rule"], default="single",
                     help="single: the 2.6e8-bit block (the headline); batched: 64 uneven blocks in one "
                          "pa_hash_batched call against the same blocks as serial calls; serving: Poisson "
                          "arrivals from 16 sessions through the serving loop (latency percentiles); lengths: "
-                         "the 8e8-, 2^32- and 5e8-bit blocks with transform lengths 3 * 2^m against 2^m")
+                         "the 8e8-, 2^32- and 5e8-bit blocks with transform lengths 3 * 2^m against 2^m; rule: "
+                         "the plan rule's length form against device timings of both forms per class")
     ap.add_argument("--requests", type=int, default=600, help="serving: number of Poisson arrivals")
     ap.add_argument("--block", type=int, choices=range(len(LENGTH_BLOCKS)), default=None,
                     help="lengths: run only this block (0: 8e8 bits, 1: 2^32 bits, 2: 5e8 bits)")
     ap.add_argument("--mode", choices=["radix3", "pow2"], default=None, help="lengths: run only this length form")
     ap.add_argument("--core-only", action="store_true",
-                    help="single: time only the K main steps (no per-step statistics, key-upload or pipelined "
-                         "passes), so that a profiler sees exactly those launches")
+                    help="single: time only the K main steps (no per-step statistics, key-upload, pipelined or "
+                         "batched passes), so that a profiler sees exactly those launches; batched: only the "
+                         "batched and serial calls (no autotuning, no small blocks)")
     ap.add_argument("--pipeline", type=int, default=3,
                     help="single: also time the same K steps spread over this many streams (one plan "
                          "each), reported as `pipelined`; 1 disables")
@@ -681,6 +729,8 @@ def main():
         return bench_serving(args)
     if args.workload == "lengths":
         return bench_lengths(args)
+    if args.workload == "rule":
+        return bench_rule(args)
 
     import torch
     import paper_2105_13678_amd as pa
@@ -762,6 +812,16 @@ def main():
         "duration_ms": round(dom_ms, 4),
         "butterflies_per_launch": work[dom],
     }
+    # the second, measured ceiling: the same lazy butterfly run from registers
+    # in every lane of every SIMD (no memory, no LDS), timed on this GPU
+    try:
+        probed, plain = pa.probe_valu(0)
+        roof["peak_probe"] = round(probed / 1e9, 1)
+        roof["frac_probe"] = round(bfly_per_s / probed, 3)
+        roof["probe_plain_lane_ops"] = round(plain / 1e12, 2)
+    except RuntimeError as e:
+        log("[bench] VALU probe failed: %s" % e)
+        roof["peak_probe"] = roof["frac_probe"] = None
     rec = {
         "metric": "PA input throughput (Mbit/s) at n=2.6e8, bit-exact",
         "value": round(value, 1),

@@ -384,6 +384,18 @@ pa_status pa_plan_set_profiling(pa_plan *plan, uint32_t phase_mask);
  * PA_PH_COUNT entries, host memory), and reset the sums. */
 pa_status pa_plan_read_profile(pa_plan *plan, double *ms, uint64_t *calls);
 
+/* Measurement utility: the VALU rate the transform kernels' instruction mix
+ * reaches on HIP device `hip_device` when nothing else limits it.  Runs two
+ * register-only probe kernels on every SIMD (blocking, a few milliseconds):
+ * independent lazy radix-2 butterflies modulo a prime below 2^30 (sum
+ * reduced to [0, 2p), difference shifted by 2p, Montgomery product: eight
+ * VALU instructions, three of them 32x32 -> 64-bit multiply-adds or 32-bit
+ * multiplies), and a stream of plain 32-bit adds and xors of the same
+ * shape.  *bfly_per_s receives butterflies per second, *plain_per_s lane
+ * instructions per second.  Returns PA_ERR_ARG, PA_ERR_NOMEM,
+ * PA_ERR_DEVICE or PA_OK. */
+pa_status pa_probe_valu(int hip_device, double *bfly_per_s, double *plain_per_s);
+
 /* Map a device status word written by pa_hash_async to a status code. */
 pa_status pa_decode_status(uint32_t flags);
 

@@ -8,6 +8,7 @@ device); torch supplies memory and the current HIP stream, nothing else.
 from __future__ import annotations
 
 import ctypes
+import functools
 import os
 import re
 
@@ -132,6 +133,8 @@ def lib():
         L.pa_submit.restype = ctypes.c_int
         L.pa_poll.argtypes = [_VP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Timing)]
         L.pa_poll.restype = ctypes.c_int
+        L.pa_probe_valu.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.pa_probe_valu.restype = ctypes.c_int
         L.pa_decode_status.argtypes = [ctypes.c_uint32]
         L.pa_decode_status.restype = ctypes.c_int
         L.pa_status_string.argtypes = [ctypes.c_int]
@@ -166,6 +169,16 @@ def plan_query(n: int, r: int, gamma: int = 0, B: int = 0, flags: int = 0, col_l
     return st, (info.as_dict() if st == PA_OK else None)
 
 
+def probe_valu(device: int = 0):
+    """pa_probe_valu: (butterflies per second, plain lane instructions per
+    second) that register-only probe kernels reach on the device."""
+    b, p = ctypes.c_double(), ctypes.c_double()
+    st = lib().pa_probe_valu(int(device), ctypes.byref(b), ctypes.byref(p))
+    if st != PA_OK:
+        raise PAError(st, "pa_probe_valu")
+    return b.value, p.value
+
+
 def plan_tune(n: int, r: int, reps: int = 5, device: int = 0, gamma: int = 0, B: int = 0, flags: int = 0,
               col_lg: int = 0):
     """Time the candidate shapes of (n, r) on the device (pa_plan_tune);
@@ -177,6 +190,16 @@ def plan_tune(n: int, r: int, reps: int = 5, device: int = 0, gamma: int = 0, B:
     if st != PA_OK:
         raise PAError(st, "pa_plan_tune")
     return {name: getattr(best, name) for name, _ in Params._fields_ if name != "reserved"}, ms.value
+
+
+@functools.lru_cache(maxsize=4096)
+def _buffer_words(n: int, r: int):
+    """(key, a, seed, out) buffer words of shape (n, r) under the default plan
+    rule, or None when it admits no plan (a pure function of (n, r))."""
+    st, info = plan_query(n, r)
+    if st != PA_OK:
+        return None
+    return info["key_words"], info["a_words"], info["seed_words"], info["out_words"]
 
 
 def _dev_ptr(t, min_words: int, what: str, device) -> int:
@@ -365,13 +388,11 @@ class BatchPlan:
         import torch
         arr = (Block * len(blocks))()
         for i, (n, r, key, a, b, c, out) in enumerate(blocks):
-            st, info = plan_query(n, r)
-            if st == PA_OK:
-                ptrs = (_dev_ptr(key, info["key_words"], "key", self.device),
-                        _dev_ptr(a, info["a_words"], "a", self.device),
-                        _dev_ptr(b, info["seed_words"], "b", self.device),
-                        _dev_ptr(c, info["seed_words"], "c", self.device),
-                        _dev_ptr(out, info["out_words"], "out", self.device))
+            w = _buffer_words(n, r)
+            if w is not None:
+                ptrs = (_dev_ptr(key, w[0], "key", self.device), _dev_ptr(a, w[1], "a", self.device),
+                        _dev_ptr(b, w[2], "b", self.device), _dev_ptr(c, w[2], "c", self.device),
+                        _dev_ptr(out, w[3], "out", self.device))
             else:
                 ptrs = tuple(t.data_ptr() if t is not None else 0 for t in (key, a, b, c, out))
             arr[i] = Block(n, r, *ptrs)

@@ -20,7 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpa.so")
 ARCH = "gfx950"
 
-SOURCES = ["pa_api.cpp", "pa_batch.cpp", "pa_server.cpp", "pa_tune.cpp", "pa_kernels.hip", "pa_noalloc.hip"]
+SOURCES = ["pa_api.cpp", "pa_batch.cpp", "pa_server.cpp", "pa_tune.cpp", "pa_kernels.hip", "pa_noalloc.hip",
+           "pa_probe.hip"]
 HEADERS = ["pa_internal.hpp", "ntt_device.hpp", "pa_multi.hpp", "pa_resident.hpp"]
 DEVICE_SOURCES = ["pa_kernels.hip", "ntt_device.hpp", "pa_multi.hpp"]
 

@@ -22,6 +22,11 @@ const uint64_t kMersenne[] = {
     136279841};
 
 constexpr uint64_t kMaxK = 4096;
+// Lengths 3 * 2^m with m below this cost kMixSmallCost times their
+// butterfly count in the plan rule (see derive_plan).
+constexpr uint32_t kMinLog2Mix = 19;
+constexpr double kMixSmallCost = 1.6;
+constexpr double kLog2Of3 = 1.5849625007211562;
 constexpr uint32_t kMinLog2N = 6;
 constexpr uint32_t kMaxLdsLog2 = 14;  // 2^14 words = 64 KiB of LDS per tile
 
@@ -115,8 +120,8 @@ bool exact(uint64_t k, uint64_t L, uint32_t B, const pa::PrimeTriple &T) {
     const unsigned __int128 P3 = (unsigned __int128)T.p[0] * T.p[1] * T.p[2];
     const unsigned __int128 lim = ((unsigned __int128)1 << B) - 1;
     const unsigned __int128 kL = (unsigned __int128)k * L;
-    // compare k*L*lim^2 < P3 without overflow (kL < 2^45, lim^2 < 2^64)
-    return kL * lim <= (P3 - 1) / lim && kL * lim * lim < P3;
+    // kL < 2^37 (k <= kMaxK = 2^12, L < 2^25) and lim^2 < 2^64: the product fits in 128 bits
+    return kL * lim * lim < P3;
 }
 
 }  // namespace
@@ -134,8 +139,12 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     const uint32_t mx_hi = (prm->flags & PA_FLAG_POW2_LENGTHS) ? 1u : 2u;
     // Candidate lengths for limb width b: the shortest 2^m and 3 * 2^m that
     // hold the product, each with its own primes.  Cost model: butterflies
-    // N log2 N, plus one pass over N for the radix-3 step.  `seen` records
-    // whether some candidate length was within the supported range.
+    // N log2 N, plus one pass over N for the radix-3 step; lengths 3 * 2^m
+    // with m < kMinLog2Mix count kMixSmallCost times that (timed on the
+    // device, candidates round robin: at 3 * 2^10 ... 3 * 2^16 they take
+    // 1.06 - 1.24x the time of the 4/3 longer power of two, at 3 * 2^19 the
+    // same, at 3 * 2^20 and 3 * 2^21 0.92x and 0.56x).  `seen` records whether
+    // some candidate length was within the supported range.
     bool seen = false;
     auto choose = [&](uint32_t b, uint32_t *m_out, uint32_t *mix_out, double *cost_out) {
         const uint64_t Lb = (gamma + b - 1) / b;
@@ -147,7 +156,8 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
             seen = true;
             if (!exact(k, Lb, b, *T)) continue;
             const double Nl = (double)((uint64_t)(mx ? 3 : 1) << mb);
-            const double cost = Nl * (std::log2(Nl) + (mx ? 1.0 : 0.0));
+            const double lgN = mb + (mx ? kLog2Of3 : 0.0);
+            const double cost = Nl * (lgN + (mx ? 1.0 : 0.0)) * (mx && mb < kMinLog2Mix ? kMixSmallCost : 1.0);
             if (!ok || cost < *cost_out) {
                 ok = true;
                 *m_out = mb;

@@ -45,8 +45,8 @@ struct Group {
     uint32_t lds;
     uint32_t args_size;
     std::vector<const pa::KLaunch *> members;
-    uint32_t total;                 // workgroups of the multi launch
-    size_t o_args, o_geo, o_owner;  // table offsets
+    uint32_t total;                      // workgroups of the multi launch
+    size_t o_args, o_geo, o_owner, end;  // table offsets
 };
 
 // A captured block list: replayable while no arena or table it points into
@@ -171,7 +171,7 @@ size_t build_groups(const std::vector<std::vector<pa::KLaunch>> &recs, const std
                         groups[j].block.y == L.block.y && groups[j].block.z == L.block.z)
                         g = &groups[j];
                 if (!g) {
-                    groups.push_back(Group{L.single, L.multi, L.block, L.lds, L.args_size, {}, 0, 0, 0, 0});
+                    groups.push_back(Group{L.single, L.multi, L.block, L.lds, L.args_size, {}, 0, 0, 0, 0, 0});
                     g = &groups.back();
                 }
                 g->members.push_back(&L);
@@ -184,24 +184,39 @@ size_t build_groups(const std::vector<std::vector<pa::KLaunch>> &recs, const std
             g.o_args = lay.o_args;
             g.o_geo = lay.o_geo;
             g.o_owner = lay.o_owner;
+            g.end = lay.end;
             off = lay.end;
         }
     }
     return off;
 }
 
-void fill_tables(const std::vector<Group> &groups, unsigned char *h) {
-    for (const Group &g : groups) {
+// Tables of groups [g0, g1) into the staging buffer `h`; returns their byte
+// range [*lo, *hi) (empty when every group is a plain launch).
+void fill_tables(const std::vector<Group> &groups, size_t g0, size_t g1, unsigned char *h, size_t *lo, size_t *hi) {
+    *lo = *hi = 0;
+    for (size_t gi = g0; gi < g1; ++gi) {
+        const Group &g = groups[gi];
         if (g.members.size() == 1) continue;
+        if (*hi == 0) *lo = g.o_args;
+        *hi = g.end;
         const std::vector<pa::MultiMember> mem = members_of(g);
         const pa::MultiLayout lay = pa::multi_layout(mem, g.args_size, g.o_args);
         pa::multi_fill(mem, g.args_size, lay, h);
     }
 }
 
-hipError_t launch_groups(const std::vector<Group> &groups, const unsigned char *d_tab, hipStream_t st) {
+// End of the run of groups that starts at g0 and belongs to one step.
+size_t step_end(const std::vector<Group> &groups, size_t g0) {
+    size_t g1 = g0;
+    while (g1 < groups.size() && groups[g1].members[0]->step == groups[g0].members[0]->step) ++g1;
+    return g1;
+}
+
+hipError_t launch_groups(const std::vector<Group> &groups, size_t g0, size_t g1, const unsigned char *d_tab,
+                         hipStream_t st) {
     static const bool dbg = std::getenv("PA_DEBUG") != nullptr;
-    for (size_t gi = 0; gi < groups.size(); ++gi) {
+    for (size_t gi = g0; gi < g1; ++gi) {
         const Group &g = groups[gi];
         hipError_t e;
         if (g.members.size() == 1) {
@@ -329,7 +344,7 @@ pa_status pa_hash_batched(pa_batch_plan *bp, const pa_block *blocks, uint32_t co
     for (uint32_t i : order) {
         const pa_block &bk = blocks[i];
         pa::bind_scratch(&plans[i], (char *)bp->arena + at[i], lays[i]);
-        recs[i].reserve(16);
+        recs[i].reserve(24);
         plans[i].rec = &recs[i];
         const pa_status s = pa::enqueue_hash(&plans[i], bk.key, bk.a, bk.b, bk.c, bk.out, bp->d_status + i, nullptr,
                                              nullptr, stream);
@@ -353,25 +368,32 @@ pa_status pa_hash_batched(pa_batch_plan *bp, const pa_block *blocks, uint32_t co
         *have = sz;
         return true;
     };
-    if (tab_bytes) {
-        // the staging buffer and the device tables are free: the previous call synchronised
-        if (!grow((void **)&bp->h_tab, &bp->h_tab_bytes, tab_bytes, true)) return PA_ERR_NOMEM;
-        fill_tables(groups, bp->h_tab);
-    }
+    // the staging buffer and the device tables are free: the previous call synchronised
+    if (tab_bytes && !grow((void **)&bp->h_tab, &bp->h_tab_bytes, tab_bytes, true)) return PA_ERR_NOMEM;
 
     if (!bp->graphs_on) {
-        if (tab_bytes) {
-            if (!grow(&bp->d_tab, &bp->d_tab_bytes, tab_bytes, false)) return PA_ERR_NOMEM;
-            if (hipMemcpyAsync(bp->d_tab, bp->h_tab, tab_bytes, hipMemcpyHostToDevice, stream) != hipSuccess) {
+        if (tab_bytes && !grow(&bp->d_tab, &bp->d_tab_bytes, tab_bytes, false)) return PA_ERR_NOMEM;
+        // step by step: stage and upload one step's tables, then launch the
+        // step, so the device starts on the first steps while the host still
+        // prepares the later ones (each step's table range is its own)
+        for (size_t g0 = 0; g0 < groups.size();) {
+            const size_t g1 = step_end(groups, g0);
+            size_t lo, hi;
+            fill_tables(groups, g0, g1, bp->h_tab, &lo, &hi);
+            if (hi > lo && hipMemcpyAsync((unsigned char *)bp->d_tab + lo, bp->h_tab + lo, hi - lo,
+                                          hipMemcpyHostToDevice, stream) != hipSuccess) {
                 (void)hipGetLastError();
                 return PA_DEVICE_ERROR;
             }
-        }
-        if (launch_groups(groups, (const unsigned char *)bp->d_tab, stream) != hipSuccess) {
-            (void)hipGetLastError();
-            return PA_DEVICE_ERROR;
+            if (launch_groups(groups, g0, g1, (const unsigned char *)bp->d_tab, stream) != hipSuccess) {
+                (void)hipGetLastError();
+                return PA_DEVICE_ERROR;
+            }
+            g0 = g1;
         }
     } else {
+        size_t lo, hi;
+        fill_tables(groups, 0, groups.size(), bp->h_tab, &lo, &hi);
         // replay the captured list, or capture it now (its tables copied to a
         // buffer of its own first); `cap` runs after `stream`'s earlier work
         // and `stream` continues after the graph
@@ -400,7 +422,7 @@ pa_status pa_hash_batched(pa_batch_plan *bp, const pa_block *blocks, uint32_t co
                 (void)hipFree(d_tab);
                 return PA_DEVICE_ERROR;
             }
-            const hipError_t el = launch_groups(groups, (const unsigned char *)d_tab, bp->cap);
+            const hipError_t el = launch_groups(groups, 0, groups.size(), (const unsigned char *)d_tab, bp->cap);
             const hipError_t e = hipStreamEndCapture(bp->cap, &graph);
             hipError_t ei = hipErrorUnknown;
             if (el == hipSuccess && e == hipSuccess) ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);

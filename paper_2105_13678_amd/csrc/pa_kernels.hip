@@ -26,6 +26,8 @@
 // inside a workgroup and a reduce / tile-prefix / apply sequence across
 // workgroups.
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "ntt_device.hpp"
 #include "pa_internal.hpp"
@@ -383,6 +385,43 @@ __device__ __forceinline__ void col_last_fwd(const uint32_t *buf, uint32_t lg, u
     }
 }
 
+// Tiles of 128 or 256 rows x 16 columns (compile-time shapes) finish with a
+// radix-16 step on 16 consecutive rows (and the 256-row tiles start with
+// one): two LDS passes instead of three.  Their LDS swizzle XORs index bits
+// 8-9 into bits 4-5, so that both a step over rows 16 apart (a wave covers 4
+// consecutive rows of all 16 columns) and the final step (a wave covers 4
+// blocks of 16 rows) touch 64 distinct banks.
+template <int LG, int CLG>
+struct ColR16 {
+    static constexpr bool last = CLG == 4 && (LG == 7 || LG == 8);  // last step radix 16
+    static constexpr bool first = CLG == 4 && LG == 8;               // first step radix 16
+};
+
+template <int LG, int CLG>
+__device__ __forceinline__ uint32_t col_swz(uint32_t i, uint32_t c_lg) {
+    if constexpr (ColR16<LG, CLG>::last) return i ^ (((i >> 8) & 3u) << 4);
+    else return tile_swz(i, c_lg);
+}
+
+// Last forward step of a 2^lg x 16 tile in the ColR16 layout: radix 16 on
+// rows 16 b .. 16 b + 15, straight to global memory (slot s -> row 16 b + s).
+template <int LG>
+__device__ __forceinline__ void col_last16_fwd(const uint32_t *buf, uint32_t m2, uint64_t c0,
+                                               __amdgpu_buffer_rsrc_t out, const PrimeConst &M, uint32_t tid) {
+    constexpr uint32_t ntask = 1u << LG;  // (2^LG / 16 blocks) x 16 columns
+    for (uint32_t task = tid; task < ntask; task += COL_THREADS) {
+        const uint32_t q = task & 15u;
+        const uint32_t row0 = task & ~15u;  // (task >> 4) << 4
+        uint32_t v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = buf[col_swz<LG, 4>(((row0 + j) << 4) + q, 4)];
+        dft_fwd<16>(v, M);
+        const uint32_t vo = ((row0 << m2) + (uint32_t)c0 + q) << 2;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) bstore(v[j], out, vo, ((uint32_t)j << m2) << 2);
+    }
+}
+
 // Unpack + forward column pass.  blockIdx.y selects the array: in MMH mode
 // arrays 0..k-1 are the key chunks x_i and k..2k-1 the seed chunks a_i; in
 // MH mode array 0 is y and array 1 is b.  Limb j of a chunk is its bits
@@ -405,7 +444,10 @@ __device__ __forceinline__ void col_last_fwd(const uint32_t *buf, uint32_t lg, u
 template <int Stage, bool MIX, int TPT, int LG, int CLG>
 __device__ __forceinline__ void col_fwd_body(const ColFwdArgs &A, const WG &wg) {
     constexpr uint32_t NSUB = MIX ? 3u : 1u;
-    constexpr int XR = MIX ? 8 : 4;  // first-step rows of a task that hold x_n
+    constexpr int FR = ColR16<LG, CLG>::first ? 16 : 8;  // radix of the first step
+    constexpr int FLR = FR == 16 ? 4 : 3;
+    constexpr int XR = MIX ? FR : FR / 2;  // first-step rows of a task that hold x_n
+    constexpr int XR1 = MIX ? FR / 2 : 1;  // ... and x_(n+Nsub) (N = 3 Nsub)
     __shared__ uint32_t Lt[LG && CLG ? 1u << (LG + CLG) : 1u];
     uint32_t *lds = LG && CLG ? Lt : lds_dyn;
     const uint32_t tile = xcd_tile(wg.x, wg.gx);
@@ -415,11 +457,11 @@ __device__ __forceinline__ void col_fwd_body(const ColFwdArgs &A, const WG &wg) 
     const uint64_t c0 = (uint64_t)tile << c_lg;
     const bool is_key = (A.mode == 0) && arr < A.k;
     const uint32_t full = (uint32_t)((1ull << A.B) - 1), topv = (uint32_t)((1ull << A.s_top) - 1);
-    const uint32_t lgMp = lg - 3;
+    const uint32_t lgMp = lg - FLR;
     const uint32_t ntask = (1u << lgMp) << c_lg;  // at most TPT * COL_THREADS
     const uint32_t Ns = (uint32_t)A.Nsub;
     const uint32_t t = threadIdx.x;
-    uint32_t x[TPT][XR], x1[TPT][MIX ? 4 : 1];
+    uint32_t x[TPT][XR], x1[TPT][XR1];
     {
         const LimbSrc S = limb_src(A, arr);
         const uint32_t L = (uint32_t)A.L;
@@ -434,7 +476,7 @@ __device__ __forceinline__ void col_fwd_body(const ColFwdArgs &A, const WG &wg) 
                 x[u][jj] = task < ntask ? limb_at(S, j) : 0u;
                 if (is_key && task < ntask && j < L) not_ones |= (x[u][jj] != (j == L - 1 ? topv : full));
                 if constexpr (MIX) {
-                    if (jj >= 4) continue;
+                    if (jj >= FR / 2) continue;
                     x1[u][jj] = task < ntask ? limb_at(S, j + Ns) : 0u;
                     if (is_key && task < ntask && j + Ns < L)
                         not_ones |= (x1[u][jj] != (j + Ns == L - 1 ? topv : full));
@@ -469,34 +511,40 @@ __device__ __forceinline__ void col_fwd_body(const ColFwdArgs &A, const WG &wg) 
             const uint32_t task = tl + COL_THREADS * u;
             if (task >= ntask) continue;
             const uint32_t q = task & cmask, n1 = task >> c_lg;
-            uint32_t v[8];
+            uint32_t v[FR];
             if constexpr (MIX) {
 #pragma unroll
-                for (int jj = 0; jj < 8; ++jj) {
+                for (int jj = 0; jj < FR; ++jj) {
                     const uint32_t row = n1 + ((uint32_t)jj << lgMp);
-                    v[jj] = jj < 4 ? red2(mont(x[u][jj], g0[row], M) + mont(x1[u][jj & 3], g1[row], M), M)
-                                   : mont(x[u][jj], g0[row], M);  // in [0, 2p)
+                    v[jj] = jj < FR / 2
+                                ? red2(mont(x[u][jj], g0[row], M) + mont(x1[u][jj & (FR / 2 - 1)], g1[row], M), M)
+                                : mont(x[u][jj], g0[row], M);  // in [0, 2p)
                 }
             } else {
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) v[jj] = mont(x[u][jj], M.one, M);  // x mod p, in [0, 2p)
+                for (int jj = 0; jj < FR / 2; ++jj) v[jj] = mont(x[u][jj], M.one, M);  // x mod p, in [0, 2p)
             }
-            if (lg > 3) {
-                uint32_t w[8];
+            if (lg > (uint32_t)FLR) {
+                uint32_t w[FR];
 #pragma unroll
-                for (int s = 1; s < 8; ++s) w[s] = tw[n1 * brev_small(s, 3)];
-                dft_fwd_x<8, !MIX, true>(v, w, M);
+                for (int s = 1; s < FR; ++s) w[s] = tw[n1 * brev_small(s, FLR)];
+                dft_fwd_x<FR, !MIX, true>(v, w, M);
 #pragma unroll
-                for (int jj = 0; jj < 8; ++jj)
-                    lds[tile_swz(((n1 + ((uint32_t)jj << lgMp)) << c_lg) + q, c_lg)] = v[jj];
+                for (int jj = 0; jj < FR; ++jj)
+                    lds[col_swz<LG, CLG>(((n1 + ((uint32_t)jj << lgMp)) << c_lg) + q, c_lg)] = v[jj];
             } else {
-                dft_fwd_x<8, !MIX, false>(v, nullptr, M);
+                dft_fwd_x<FR, !MIX, false>(v, nullptr, M);
 #pragma unroll
-                for (int jj = 0; jj < 8; ++jj) out[((uint64_t)jj << A.m2) + c0 + q] = v[jj];
+                for (int jj = 0; jj < FR; ++jj) out[((uint64_t)jj << A.m2) + c0 + q] = v[jj];
             }
         }
-        if (lg == 3) continue;  // single-step transform: written straight to global memory
+        if (lg == (uint32_t)FLR) continue;  // single-step transform: written straight to global memory
         __syncthreads();
+        if constexpr (ColR16<LG, CLG>::last) {
+            // 2^7 = 8 x 16 and 2^8 = 16 x 16: the rest is one radix-16 step
+            col_last16_fwd<LG>(lds, A.m2, c0, ro, M, tl);
+            continue;
+        }
         fwd_middle_steps(lds, lg, lg - 3, c_lg, tw, M, tl, COL_THREADS);
         const uint32_t ll = last_lgM(lg);
         if (ll == 3)
@@ -1224,6 +1272,75 @@ __device__ __forceinline__ void col_inv_body(const ColInvArgs &A, const WG &wg) 
 template <int Stage>
 __global__ __launch_bounds__(COL_THREADS) void k_col_inv(ColInvArgs A) { col_inv_body<Stage>(A, wg_self()); }
 
+// Inverse column pass of 128-row (32 columns) and 256-row (16 columns) tiles
+// in two LDS passes, the inverse of the forward's radix-16 schedule: radix 16
+// on rows 16 b .. 16 b + 15 straight from global memory, then radix 8 (128
+// rows) or 16 (256 rows) with twiddles on rows n1 + 16 j (n1 < 16) straight
+// back.  256 first-step tasks per tile either way.  LDS swizzle: the block
+// index's low bits (index bits 9, or 8-9) XORed into the bits above the
+// column, so both steps touch 64 distinct banks per wave.
+template <int LG, int CLG>
+__device__ __forceinline__ uint32_t inv16_swz(uint32_t i) {
+    if constexpr (CLG == 5) return i ^ (((i >> 9) & 1u) << 5);
+    else return i ^ (((i >> 8) & 3u) << 4);
+}
+
+template <int Stage, int LG, int CLG>
+__device__ __forceinline__ void col_inv16_body(const ColInvArgs &A, const WG &wg) {
+    static_assert((LG == 7 && CLG == 5) || (LG == 8 && CLG == 4), "tile shapes of the two-pass inverse");
+    constexpr int LR = LG - 4;  // last step: radix 2^LR
+    constexpr int RL = 1 << LR;
+    constexpr uint32_t cmask = (1u << CLG) - 1;
+    __shared__ uint32_t T[1u << (LG + CLG)];
+    const uint32_t pq = wg.y;
+    const PrimeConst M = A.P.c[pq];
+    const uint32_t *twi = A.twi + ((uint64_t)pq << LG);
+    uint32_t *cc = A.Cc + pq * A.N + wg.z * A.Nsub;
+    const uint32_t tile = xcd_tile(wg.x, wg.gx);
+    const uint64_t c0 = (uint64_t)tile << CLG;
+    for (uint32_t task = threadIdx.x; task < (1u << (LG - 4 + CLG)); task += COL_THREADS) {
+        const uint32_t q = task & cmask;
+        const uint32_t row0 = (task >> CLG) << 4;
+        uint32_t v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = cc[((uint64_t)(row0 + j) << A.m2) + c0 + q];
+        dft_inv<16>(v, M);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) T[inv16_swz<LG, CLG>(((row0 + j) << CLG) + q)] = v[j];
+    }
+    __syncthreads();
+    for (uint32_t task = threadIdx.x; task < (16u << CLG); task += COL_THREADS) {
+        const uint32_t q = task & cmask;
+        const uint32_t n1 = task >> CLG;
+        uint32_t v[RL], w[RL];
+#pragma unroll
+        for (int j = 0; j < RL; ++j) v[j] = T[inv16_swz<LG, CLG>(((n1 + ((uint32_t)j << 4)) << CLG) + q)];
+#pragma unroll
+        for (int s = 1; s < RL; ++s) w[s] = twi[n1 * brev_small(s, LR)];
+        dft_inv_tw<RL>(v, w, M);
+        // canonical residues for the Chinese-remainder step
+#pragma unroll
+        for (int j = 0; j < RL; ++j) {
+            const uint32_t row = n1 + ((uint32_t)j << 4);
+            if (row < A.row_lim) cc[((uint64_t)row << A.m2) + c0 + q] = canon(red2(v[j], M), M);
+        }
+    }
+}
+
+template <int Stage, int LG, int CLG>
+__global__ __launch_bounds__(COL_THREADS) void k_col_inv16(ColInvArgs A) {
+    col_inv16_body<Stage, LG, CLG>(A, wg_self());
+}
+
+template <int Stage, int LG, int CLG>
+__global__ __launch_bounds__(COL_THREADS) void km_col_inv16(const ColInvArgs *__restrict__ tab,
+                                                          const MultiGeo *__restrict__ geo,
+                                                          const uint16_t *__restrict__ owner) {
+    WG wg;
+    const uint32_t i = wg_multi(geo, owner, wg);
+    if (i != MULTI_NONE) col_inv16_body<Stage, LG, CLG>(tab[i], wg);
+}
+
 template <int Stage>
 __global__ __launch_bounds__(COL_THREADS) void km_col_inv(const ColInvArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
                                      const uint16_t *__restrict__ owner) {
@@ -1266,6 +1383,21 @@ __device__ __forceinline__ CFn cf_shfl_up(CFn f, int d) {
 
 __device__ __forceinline__ CFn cf_shfl_down(CFn f, int d) {
     return CFn{(uint32_t)__shfl_down((int)f.g, d, 64), (uint32_t)__shfl_down((int)f.th, d, 64)};
+}
+
+// Exclusive prefix composition of the carry functions of a wavefront's
+// lanes (lane 0 first): lane l receives the composition of lanes [0, l).
+__device__ __forceinline__ CFn wave_scan_excl(CFn f) {
+    const int lane = threadIdx.x & 63;
+    CFn w = f;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const CFn o = cf_shfl_up(w, d);
+        if (lane >= d) w = cf_compose(o, w);
+    }
+    CFn ex = cf_shfl_up(w, 1);
+    if (lane == 0) ex = cf_id();
+    return ex;
 }
 
 // Block-wide ordered composition of the threads' carry functions (thread 0
@@ -1834,62 +1966,75 @@ __device__ __forceinline__ unsigned __int128 wrap_value(const uint32_t *__restri
 __device__ void wrap_usual_case(const ScanArgs &A) {
     __shared__ uint64_t tlo[WRAP_LO], ttop[WRAP_TOP];
     const uint32_t t = threadIdx.x;
-    const uint64_t mask = (1ull << A.B) - 1;
     const uint64_t d0 = A.gamma / A.B, T = d0 / CARRY_TILE, nv = A.M - d0;
-    if (t < WRAP_LO) tlo[t] = t < A.M ? A.t[t] : 0ull;
-    if (t < nv) ttop[t] = A.t[d0 + t];
+    // every global load of the job first (one round trip to memory): the
+    // lowest and the top digits, this thread's digits of tile T below d0,
+    // its first aggregates of the tiles below T
+    const uint64_t lo_d = t < WRAP_LO && t < A.M ? A.t[t] : 0ull;
+    const uint64_t top_d = t < nv ? A.t[d0 + t] : 0ull;
+    const uint64_t base = T * CARRY_TILE + (uint64_t)t * CARRY_PER_THREAD;
+    uint64_t dv[CARRY_PER_THREAD];
+#pragma unroll
+    for (int v = 0; v < CARRY_PER_THREAD; ++v) dv[v] = base + v < d0 ? A.t[base + v] : 0ull;
     const uint64_t per = (T + SCAN_THREADS - 1) / SCAN_THREADS;
     const uint64_t j0 = min((uint64_t)t * per, T), j1 = min(j0 + per, T);
+    constexpr int PRE = 8;
+    CFn pre[PRE];
+#pragma unroll
+    for (int q = 0; q < PRE; ++q) pre[q] = j0 + q < j1 ? A.agg[j0 + q] : cf_id();
     CFn f = cf_id();
-    for (uint64_t j = j0; j < j1; ++j) f = cf_compose(f, A.agg[j]);
+#pragma unroll
+    for (int q = 0; q < PRE; ++q) f = cf_compose(f, pre[q]);
+    for (uint64_t j = j0 + PRE; j < j1; ++j) f = cf_compose(f, A.agg[j]);  // beyond 8 tiles per thread
+    if (t < WRAP_LO) tlo[t] = lo_d;
+    if (t < nv) ttop[t] = top_d;
     const CFn below = block_reduce<SCAN_THREADS>(f);
     __syncthreads();
     CFn g = cf_id();
-    const uint64_t base = T * CARRY_TILE + (uint64_t)t * CARRY_PER_THREAD;
 #pragma unroll
     for (int v = 0; v < CARRY_PER_THREAD; ++v)
-        if (base + v < d0) g = cf_compose(g, cf_limb(A.t[base + v], A.B));
+        if (base + v < d0) g = cf_compose(g, cf_limb(dv[v], A.B));
     const CFn within = block_reduce<SCAN_THREADS>(g);
     __syncthreads();
-    if (t != 0) return;
-    uint32_t c = cf_eval(cf_compose(below, within), 0u);
-    unsigned __int128 V = 0;
-    for (uint64_t i = 0; i < nv; ++i) {
-        const uint64_t v = ttop[i] + c;
-        const unsigned __int128 limb = v & mask;
-        c = (uint32_t)(v >> A.B);
-        const uint64_t lo_bit = (d0 + i) * A.B;
-        if (lo_bit < A.gamma) V += limb >> (A.gamma - lo_bit);
-        else if (lo_bit - A.gamma < 128) V += limb << (lo_bit - A.gamma);
-    }
-    V = mod_mersenne128(V, A.gamma);
-    const uint32_t nlo = (uint32_t)min((uint64_t)WRAP_LO, A.Mw);
-    uint32_t slo[WRAP_LO];
-    c = 0;
-    for (uint32_t m = 0; m < nlo; ++m) {
-        const uint64_t v = tlo[m] + c;
-        slo[m] = (uint32_t)(v & mask);
-        c = (uint32_t)(v >> A.B);
-    }
-    bool usual = A.qv < nlo;
-    uint32_t first_same = nlo;  // y's limbs from here on equal T_lo's
-    uint32_t c2 = 0;
-    for (uint32_t m = 0; usual && m < nlo; ++m) {
-        const uint64_t add = m < A.qv ? (uint64_t)(V >> (A.B * m)) & mask : 0ull;
-        const uint64_t v = (uint64_t)slo[m] + add + c2;
-        c2 = (uint32_t)(v >> A.B);
-        slo[m] = (uint32_t)(v & mask);
-        if (m + 1 >= A.qv && c2 == 0) {
-            first_same = m + 1;
-            break;
+    __shared__ uint64_t vw[2];  // V mod p, broadcast to wave 0
+    const uint64_t mask = (1ull << A.B) - 1;
+    if (t == 0) {  // V from the top digits (at most WRAP_TOP, one after another)
+        uint32_t c = cf_eval(cf_compose(below, within), 0u);
+        unsigned __int128 V = 0;
+        for (uint64_t i = 0; i < nv; ++i) {
+            const uint64_t v = ttop[i] + c;
+            const unsigned __int128 limb = v & mask;
+            c = (uint32_t)(v >> A.B);
+            const uint64_t lo_bit = (d0 + i) * A.B;
+            if (lo_bit < A.gamma) V += limb >> (A.gamma - lo_bit);
+            else if (lo_bit - A.gamma < 128) V += limb << (lo_bit - A.gamma);
         }
+        V = mod_mersenne128(V, A.gamma);
+        vw[0] = (uint64_t)V;
+        vw[1] = (uint64_t)(V >> 64);
     }
-    bool guard = false;
-    for (uint32_t m = first_same; m < nlo; ++m) guard |= slo[m] != (uint32_t)mask;
-    usual = usual && c2 == 0 && guard;
-    if (usual)
-        for (uint32_t m = 0; m < nlo; ++m) A.y[m] = slo[m];
-    *A.flag = usual ? 0u : 1u;
+    __syncthreads();
+    if (t >= 64) return;
+    // wave 0, lane m < nlo: limb m of T_lo (the first fold's chain from
+    // carry-in 0), then y = T_lo + V on the lowest limbs: two carry chains as
+    // lane prefix compositions of the digits' carry functions
+    const uint32_t nlo = (uint32_t)min((uint64_t)WRAP_LO, A.Mw);
+    const bool on = t < nlo;
+    const unsigned __int128 V = (unsigned __int128)vw[0] | ((unsigned __int128)vw[1] << 64);
+    const uint64_t d = on ? tlo[t] : 0ull;
+    const uint32_t c1 = cf_eval(wave_scan_excl(on ? cf_limb(d, A.B) : cf_id()), 0u);
+    const uint64_t sl = (d + c1) & mask;  // limb t of T_lo
+    const uint64_t e = sl + (on && t < A.qv ? (uint64_t)(V >> (A.B * t)) & mask : 0ull);
+    const uint32_t c2 = cf_eval(wave_scan_excl(on ? cf_limb(e, A.B) : cf_id()), 0u);
+    const uint64_t ys = e + c2;  // limb t of y and its carry out
+    // the carry stops at the first limb m >= qv - 1 with no carry out; y's
+    // limbs above it are T_lo's
+    const uint64_t stop = __ballot(on && t + 1 >= A.qv && (ys >> A.B) == 0);
+    const uint32_t first_same = stop ? (uint32_t)__ffsll((unsigned long long)stop) : nlo + 1;  // limb index + 1
+    const uint64_t guard = __ballot(on && t >= first_same && sl != mask);
+    const bool usual = A.qv < nlo && first_same <= nlo && guard != 0;
+    if (usual && on) A.y[t] = (uint32_t)(ys & mask);
+    if (t == 0) *A.flag = usual ? 0u : 1u;
 }
 
 // Normalise one tile.  The carry into the tile is the composition of the
@@ -1904,8 +2049,8 @@ __device__ void wrap_usual_case(const ScanArgs &A) {
 // APPLY_FOLD also composes, per tile, the carry functions of the limbs it
 // writes as digits of the wrap chain (digits [qv, Mw) only), into agg_w,
 // writes its limbs from WRAP_LO up as y's limbs (y's top limb cut to s_top
-// bits), and its extra workgroup (index ntiles) runs the second fold's usual
-// case.  APPLY_WRAP, which runs only when the flag says the usual case does
+// bits), and its extra workgroup (index 0; tile b runs in workgroup b + 1)
+// runs the second fold's usual case.  APPLY_WRAP, which runs only when the flag says the usual case does
 // not apply, runs the general wrap chain: its digits are read from the limbs
 // s of the folded sum, the lowest qv with the pieces of V mod p added and
 // the top one cut to s_top bits; the carry functions of digits [0, qv),
@@ -1918,16 +2063,16 @@ __device__ void wrap_usual_case(const ScanArgs &A) {
 // status flags are set; workgroup 0 copies the flags to dst.
 template <int AM>
 __device__ __forceinline__ void carry_apply_body(const ScanArgs &A, const WG &wg) {
-    const uint64_t b = wg.x;
     if constexpr (AM == APPLY_WRAP) {
         if (*(const volatile uint32_t *)A.flag == 0u) return;
     }
     if constexpr (AM == APPLY_FOLD) {
-        if (b == A.ntiles) {
+        if (wg.x == 0) {  // dispatched first: its chain of loads and reductions overlaps the tiles
             wrap_usual_case(A);
             return;
         }
     }
+    const uint64_t b = AM == APPLY_FOLD ? wg.x - 1 : wg.x;
     const uint64_t mask = (1ull << A.B) - 1;
     constexpr bool EXTRACT = AM == APPLY_PLAIN;
     __shared__ uint32_t lb[EXTRACT ? CARRY_TILE + EXTRA_LIMBS : 1];
@@ -2190,11 +2335,9 @@ uint32_t root_of_len(uint32_t p, uint32_t log2n, uint32_t mix) {
     return hmul(hpow(w, a, p), c, p);
 }
 
-}  // namespace
-
-namespace pa {
-
-void init_prime_constants(pa_plan *p, const uint32_t primes[NPRIMES]) {
+// The constants of one prime triple at one transform length, computed from
+// scratch (modular exponentiations; a few microseconds).
+void compute_prime_constants(pa_plan *p, const uint32_t primes[NPRIMES]) {
     for (int q = 0; q < NPRIMES; ++q) {
         const uint32_t pr = primes[q];
         PrimeConst &C = p->primes.c[q];
@@ -2230,6 +2373,40 @@ void init_prime_constants(pa_plan *p, const uint32_t primes[NPRIMES]) {
             p->mix3.h[q] = hmont(hmul((w3sq + pr - w3) % pr, (pr + 1) / 2, pr), pr);
         }
     }
+}
+
+// Prime constants already computed, by (primes, m, mix): a batched call
+// derives a plan per block, so each distinct shape pays the exponentiations
+// once per process.
+struct ConstEntry {
+    uint32_t p[NPRIMES], m, mix;
+    PrimeSet primes;
+    CrtConst crt;
+    Mix3Const mix3;
+};
+
+}  // namespace
+
+namespace pa {
+
+void init_prime_constants(pa_plan *p, const uint32_t primes[NPRIMES]) {
+    static std::mutex mu;
+    static std::vector<ConstEntry> cache;
+    constexpr size_t kMaxEntries = 256;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        for (const ConstEntry &e : cache)
+            if (e.m == p->m && e.mix == p->mix && e.p[0] == primes[0] && e.p[1] == primes[1] && e.p[2] == primes[2]) {
+                p->primes = e.primes;
+                p->crt = e.crt;
+                p->mix3 = e.mix3;
+                return;
+            }
+    }
+    compute_prime_constants(p, primes);
+    ConstEntry e{{primes[0], primes[1], primes[2]}, p->m, p->mix, p->primes, p->crt, p->mix3};
+    std::lock_guard<std::mutex> lock(mu);
+    if (cache.size() < kMaxEntries) cache.push_back(e);
 }
 
 hipError_t launch_twiddles(pa_plan *p, hipStream_t st, uint32_t *hdr, uint32_t want) {
@@ -2320,7 +2497,8 @@ static void launch_col_fwd_generic(pa_plan *p, const ColFwdArgs &cf, unsigned na
     // common tile shapes (2^m1 rows x 2^c_lg columns) with compile-time sizes
 #define PA_COL_FIXED(LGv, CLGv)                                                                              \
     if (p->m1 == LGv && cf.c_lg == CLGv) {                                                                   \
-        constexpr int T = (1 << (LGv - 3 + CLGv)) <= COL_THREADS ? 1 : (1 << (LGv - 3 + CLGv)) / COL_THREADS; \
+        constexpr int NT = 1 << (LGv - (ColR16<LGv, CLGv>::first ? 4 : 3) + CLGv); /* first-step tasks */    \
+        constexpr int T = NT <= COL_THREADS ? 1 : NT / COL_THREADS;                                          \
         emit(p, step, PA_KERN(col_fwd, Stage, MIX, T, LGv, CLGv), grid, dim3(COL_THREADS), 0, cf, st);      \
         return;                                                                                              \
     }
@@ -2424,6 +2602,12 @@ static void launch_col_inv(pa_plan *p, const ColInvArgs &ci, hipStream_t st) {
     else if (p->m1 == C10_LG && p->m2 >= C10_CLG)
         emit(p, step, PA_KERN(col10_inv, Stage), dim3(1u << (p->m2 - C10_CLG), NPRIMES, nsub), dim3(COL_THREADS),
              0, ci, st);
+    else if (p->m1 == 7 && p->m2 >= 5)  // 128 x 32 tiles, two LDS passes
+        emit(p, step, PA_KERN(col_inv16, Stage, 7, 5), dim3(1u << (p->m2 - 5), NPRIMES, nsub), dim3(COL_THREADS), 0,
+             ci, st);
+    else if (p->m1 == 8 && p->m2 >= 4)  // 256 x 16 tiles, two LDS passes
+        emit(p, step, PA_KERN(col_inv16, Stage, 8, 4), dim3(1u << (p->m2 - 4), NPRIMES, nsub), dim3(COL_THREADS), 0,
+             ci, st);
     else
         emit(p, step, PA_KERN(col_inv, Stage), dim3(1u << (p->m2 - p->ci_lg), NPRIMES, nsub), dim3(COL_THREADS),
              ((size_t)4 << p->m1) << p->ci_lg, ci, st);

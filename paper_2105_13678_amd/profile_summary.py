@@ -31,6 +31,9 @@ from .build import source_digest
 
 
 def short_name(name: str) -> str:
+    m = re.search(r"at::native::\w*elementwise_kernel<.*FillFunctor<(\w+)>", name)
+    if m:  # torch's fill of the benchmark's output and status buffers
+        return {"long": "torch fill (int64)", "int": "torch fill (int32)"}.get(m.group(1), "torch fill")
     name = name.replace("(anonymous namespace)::", "")
     name = re.sub(r"^void ", "", name)
     depth, out = 0, []
@@ -91,7 +94,8 @@ def hbm(fetch_dir: str, write_dir: str, calib_bytes: int) -> str:
     digest = source_digest()
     for nm, (f, w) in by.items():
         if f and w:
-            lines.append(f"    traffic {nm} fetch={sum(f) / len(f):.0f} write={sum(w) / len(w):.0f} "
+            key = re.sub(r"[ ()]+", "_", nm).strip("_") if " " in nm else nm
+            lines.append(f"    traffic {key} fetch={sum(f) / len(f):.0f} write={sum(w) / len(w):.0f} "
                          f"sources={digest}")
     return "\n".join(lines)
 

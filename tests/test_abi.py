@@ -119,10 +119,10 @@ def test_prime_triples_are_the_largest_with_the_roots():
     every length up to 2^20, and every length 3 * 2^m up to 3 * 2^18)."""
     seen = set()
     rng = random.Random(5)
-    for _ in range(600):
+    for i in range(600):
         r = int(2 ** rng.uniform(0, 27.0))
         n = r + 1 + int(2 ** rng.uniform(0, 31))
-        st, info = binding.plan_query(n, r)
+        st, info = binding.plan_query(n, r, flags=binding.PA_FLAG_RADIX3_LENGTHS if i % 2 else 0)
         if st != 0:
             continue
         m, f = info["log2N"], info["len_factor"]
@@ -136,9 +136,11 @@ def test_prime_triples_are_the_largest_with_the_roots():
 
 def length_cost(info) -> float:
     """The plan rule's cost of a transform length: N log2 N butterflies, plus
-    one pass over N for the radix-3 step of the lengths 3 * 2^m."""
+    one pass over N for the radix-3 step of the lengths 3 * 2^m, which count
+    1.6 times below 3 * 2^19 (measured slower there)."""
     N = info["N"]
-    return N * (math.log2(N) + (1.0 if info["len_factor"] == 3 else 0.0))
+    mix = info["len_factor"] == 3
+    return N * (math.log2(N) + (1.0 if mix else 0.0)) * (1.6 if mix and info["log2N"] < 19 else 1.0)
 
 
 def test_auto_limb_width_is_cheapest_exact():
@@ -186,7 +188,7 @@ def test_power_of_two_flag():
         if B < 32:
             assert binding.plan_query(n, r, B=B + 1, flags=binding.PA_FLAG_POW2_LENGTHS)[0] in (
                 binding.PA_ERR_INEXACT, binding.PA_ERR_LIMIT)
-    assert mixed > 20
+    assert mixed >= 15  # the rule still takes lengths 3 * 2^m (from 3 * 2^19 up) for many shapes
     assert binding.plan_query(1000, 10, flags=4)[0] == binding.PA_ERR_ARG
 
 

@@ -147,6 +147,35 @@ def test_two_to_the_21_transform_two_chunks(pa):
     check_block(pa, blk, label="N=2^21 k=2")
 
 
+@pytest.mark.parametrize("gamma,variants", [
+    (6972593, [(0, 1)]),                      # 2^19: 128-row columns
+    (13466917, [(0, 1), (0, 2), (16, 2)]),    # 2^20 (256 rows), 3 * 2^19 (128 rows), 3 * 2^20 (256 rows)
+])
+def test_two_pass_column_shapes(pa, gamma, variants):
+    """Columns of 128 and 256 rows (the forward pass's radix-16 last step,
+    the 256-row tiles' radix-16 first step and the two-pass inverse), in both
+    length forms and both stages, one chunk with a ragged tail, against the
+    oracle's output and stage values (computed once per block)."""
+    n, r = gamma - 1234, gamma // 9
+    st, g, k = defn.plan_shape(n, r, gamma)
+    assert st == 0 and k == 1
+    blk = synth.single_block(gamma % 97, n, r, g, k)
+    st_o, out_o, y_o, U_o = oracle.hash(blk.key, n, r, g, blk.a, blk.b, blk.c, stages=True)
+    assert st_o == 0
+    for B, flags in variants:
+        info = pa.plan_query(n, r, g, B=B, flags=flags)[1]
+        assert info["log2N1"] in (7, 8) and info["col_lg"] == 4, info
+        say(f"[case] two-pass columns gamma={g} n={n} r={r} B={B} flags={flags} N={info['N']} "
+            f"m1={info['log2N1']}")
+        plan = pa.Plan(n, r, gamma=g, B=B, flags=flags)
+        try:
+            st_g, out_g, y_g, U_g = run_gpu(pa, plan, blk, stages=True)
+        finally:
+            plan.close()
+        assert st_g == 0
+        assert np.array_equal(y_g, y_o) and np.array_equal(U_g, U_o) and np.array_equal(out_g, out_o), info
+
+
 # (gamma, k) whose transform length is 3 * 2^m, m = 6 .. 16: column passes of
 # 2^3 .. 2^7 rows (the 8-row one single-step), rows of 2^3 .. 2^12 words.
 RADIX3_SHAPES = [(2203, 2), (4253, 3), (9689, 1), (19937, 2), (44497, 3), (86243, 2), (132049, 3),
@@ -161,10 +190,11 @@ def test_radix3_lengths_against_oracle(pa, gamma, k):
     n, r = k * gamma - 7, gamma // 3
     st, g, kk = defn.plan_shape(n, r, gamma)
     assert st == 0 and kk == k
-    info = pa.plan_query(n, r, gamma)[1]
+    info = pa.plan_query(n, r, gamma, flags=pa.PA_FLAG_RADIX3_LENGTHS)[1]
     assert info["len_factor"] == 3, info
     blk = synth.single_block(3 * gamma + k, n, r, g, kk)
-    _, out3 = check_block(pa, blk, label=f"radix-3 N={info['N']} gamma={gamma} k={k}")
+    _, out3 = check_block(pa, blk, label=f"radix-3 N={info['N']} gamma={gamma} k={k}",
+                          flags=pa.PA_FLAG_RADIX3_LENGTHS)
     _, out2 = check_block(pa, blk, label=f"power-of-two gamma={gamma} k={k}", flags=pa.PA_FLAG_POW2_LENGTHS)
     assert np.array_equal(out3, out2)
 
@@ -178,7 +208,7 @@ def test_radix3_against_power_of_two_lengths(pa, n, r):
     st, g, k = defn.plan_shape(n, r)
     assert st == 0
     i3, i2 = pa.plan_query(n, r)[1], pa.plan_query(n, r, flags=pa.PA_FLAG_POW2_LENGTHS)[1]
-    assert i3["len_factor"] == 3 and i2["len_factor"] == 1 and i3["N"] < i2["N"]
+    assert i3["len_factor"] == 3 and i2["len_factor"] == 1 and i3["N"] < i2["N"]  # the rule takes 3 * 2^m
     blk = synth.single_block(5, n, r, g, k)
     res = []
     for flags in (0, pa.PA_FLAG_POW2_LENGTHS):
@@ -369,21 +399,21 @@ def _digest(words):
     return hashlib.sha256(np.ascontiguousarray(words, dtype=np.uint64).tobytes()).hexdigest()
 
 
-@pytest.mark.parametrize("flags", [0, 1])
+@pytest.mark.parametrize("flags", [0, 1, 2])
 @pytest.mark.parametrize("name", ["single_block_2p20", "single_block_2p6e8", "paper_cv_block",
                                   "max_length_single_chunk", "len_2p22_single_chunk", "len_2p23_single_chunk",
                                   "cv_8e8_block", "corner_2p28_r03"])
 def test_full_size_blocks_against_stored_oracle_digest(pa, name, flags):
     """Full-size blocks, in the launch configuration the benchmark times,
     against digests written by tests/golden/make_golden.py (oracle only);
-    with flags = 1 (PA_FLAG_POW2_LENGTHS) also on power-of-two lengths where
-    the plan rule picks a length 3 * 2^m."""
+    with flags = 1 or 2 (PA_FLAG_POW2_LENGTHS, PA_FLAG_RADIX3_LENGTHS) also on
+    the other length form than the plan rule's."""
     gold = json.load(open(os.path.join(HERE, "golden", "full_size.json")))[name]
     n, r = gold["n"], gold["r"]
     st, g, k = defn.plan_shape(n, r)
     assert (g, k) == (gold["gamma"], gold["k"])
-    if flags and pa.plan_query(n, r)[1]["len_factor"] == 1:
-        pytest.skip("the plan rule already picks a power-of-two length")
+    if flags and pa.plan_query(n, r)[1]["len_factor"] == (1 if flags == 1 else 3):
+        pytest.skip("the plan rule already picks this length form")
     blk = synth.single_block(gold["seed"], n, r, g, k)
     say(f"[case] full size {name} n={n} r={r} gamma={g} k={k} flags={flags}")
     plan = pa.Plan(n, r, flags=flags)
