@@ -146,6 +146,17 @@ pa_status pa_hash_stages(pa_plan *plan, const uint64_t *key, const uint64_t *a,
                          const uint64_t *b, const uint64_t *c, uint64_t *out,
                          uint64_t *y_out, uint64_t *U_out, hipStream_t stream);
 
+/* Debug aid (determinism check): enqueue on `stream` a fill of every word of
+ * the plan's scratch memory (transform arrays, residues, digit sums, limbs,
+ * carry functions, flags: everything the plan owns except the twiddle
+ * tables) with `word`.  A hash reads no scratch word that it has not written
+ * itself, so its result must not depend on what the scratch held: tests
+ * poison it with patterns between hashes and compare outputs bit for bit.
+ * Ordered with the plan's hashes on the same stream; calls that overlap a
+ * hash of the same plan on another stream race.  Returns PA_ERR_ARG for a
+ * null plan, PA_ERR_DEVICE when the launch fails. */
+pa_status pa_plan_fill_scratch(pa_plan *plan, uint32_t word, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Hashing without any allocation, for callers that cannot allocate device
  * memory (code under HIP graph capture, serving loops or harnesses that

@@ -105,6 +105,8 @@ def lib():
         L.pa_hash_stages.restype = ctypes.c_int
         L.pa_hash_noalloc.argtypes = [ctypes.POINTER(Params), ctypes.c_int] + [_VP] * 7
         L.pa_hash_noalloc.restype = ctypes.c_int
+        L.pa_plan_fill_scratch.argtypes = [_VP, ctypes.c_uint32, _VP]
+        L.pa_plan_fill_scratch.restype = ctypes.c_int
         L.pa_plan_set_profiling.argtypes = [_VP, ctypes.c_uint32]
         L.pa_plan_set_profiling.restype = ctypes.c_int
         L.pa_plan_read_profile.argtypes = [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)]
@@ -319,6 +321,11 @@ class Plan:
         args = self._args(key, a, b, c, out)
         st = lib().pa_hash_stages(self._h, *args, y.data_ptr(), U.data_ptr(), self._stream(stream))
         return st, out, y, U
+
+    def fill_scratch(self, word: int, stream=None) -> int:
+        """pa_plan_fill_scratch: fill the plan's scratch memory with a 32-bit
+        pattern (enqueued on the stream; a debug aid for determinism tests)."""
+        return lib().pa_plan_fill_scratch(self._h, int(word) & 0xFFFFFFFF, self._stream(stream))
 
 
 NOALLOC_MAX_BYTES = 64 << 20  # PA_NOALLOC_MAX_BYTES

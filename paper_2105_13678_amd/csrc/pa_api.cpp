@@ -276,6 +276,7 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     lay->total = off;
     lay->table_bytes = off - lay->scratch_bytes;
     p->workspace_bytes = off;
+    p->scratch_bytes = lay->scratch_bytes;
     return PA_OK;
 }
 
@@ -379,6 +380,17 @@ pa_status pa_plan_create(const pa_params *prm, int hip_device, pa_plan **out) {
         return PA_ERR_DEVICE;
     }
     *out = p;
+    return PA_OK;
+}
+
+pa_status pa_plan_fill_scratch(pa_plan *p, uint32_t word, hipStream_t stream) {
+    if (!p) return PA_ERR_ARG;
+    pa::DeviceGuard guard(p->device);
+    if (!guard.ok) return PA_ERR_DEVICE;
+    if (pa::launch_fill((uint32_t *)p->base, p->scratch_bytes / 4, word, stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return PA_ERR_DEVICE;
+    }
     return PA_OK;
 }
 

@@ -162,6 +162,7 @@ struct pa_plan {
     // device memory (one allocation, carved)
     void *base;
     size_t workspace_bytes;
+    size_t scratch_bytes;  // [base, base + scratch_bytes): everything but the twiddle tables
     uint32_t *X;        // 2k arrays x 3 primes x N words: column-pass outputs of x_i (0..k-1), a_i (k..2k-1)
     uint32_t *Cc;       // 3 x N words: convolution residues
     uint64_t *t;        // digit sums (max(M1, L) + pad)
@@ -255,6 +256,8 @@ hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, uint64_t 
                      hipStream_t st);
 // Stage values for pa_hash_stages (y, U packed into words; nullptr skips).
 hipError_t launch_finish(pa_plan *p, uint64_t *y_out, uint64_t *U_out, hipStream_t st);
+// Fills `count` words at dst with `word` (pa_plan_fill_scratch).
+hipError_t launch_fill(uint32_t *dst, uint64_t count, uint32_t word, hipStream_t st);
 hipError_t launch_seed_transforms(pa_plan *p, const uint64_t *a, uint64_t kmax, const uint64_t *b,
                                   uint32_t *dst_a, uint32_t *dst_b, hipStream_t st);
 

@@ -25,6 +25,7 @@
 // (exact for the small carries that occur), composed with wavefront shuffles
 // inside a workgroup and a reduce / tile-prefix / apply sequence across
 // workgroups.
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -174,6 +175,13 @@ __device__ __forceinline__ bool tw_present(const uint32_t *hdr, uint32_t want) {
 // Records the key of the table set just built (after every table kernel).
 __global__ void k_tw_mark(uint32_t *hdr, uint32_t want) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *hdr = want;
+}
+
+// Every word of [dst, dst + count) set to `word` (grid-stride; a fill kernel
+// rather than a memset node, so the call may also be captured in a graph).
+__global__ void k_fill32(uint32_t *dst, uint64_t count, uint32_t word) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = word;
 }
 
 // dst[q*count + j] = scale_q * base_q^j mod p_q  (blockIdx.y = prime q)
@@ -450,6 +458,30 @@ __device__ __forceinline__ void col_fwd_body(const ColFwdArgs &A, const WG &wg) 
     constexpr int XR1 = MIX ? FR / 2 : 1;  // ... and x_(n+Nsub) (N = 3 Nsub)
     __shared__ uint32_t Lt[LG && CLG ? 1u << (LG + CLG) : 1u];
     uint32_t *lds = LG && CLG ? Lt : lds_dyn;
+    // Compile-time tiles of 16 .. 256 rows stage the first step's twiddles
+    // in LDS, transform by transform: the column twiddles omega_N1^e of the
+    // prime (N1 words) and, for N = 3 Nsub, the radix-3 row twiddles g0 (N1
+    // words) and g1 (its rows below N1 / 2): LDS reads instead of a dozen or
+    // more global loads per task and transform.  The next transform's tables
+    // are written after the barrier that ends the current first step (no
+    // thread reads them any more), and the barrier at the top of the next
+    // transform publishes them.
+    constexpr bool STAGE = LG >= 4 && LG <= 8 && CLG != 0;
+    constexpr uint32_t N1S = STAGE ? 1u << LG : 0u;
+    __shared__ uint32_t Tg[STAGE ? (MIX ? N1S * 2 + N1S / 2 : N1S) : 1u];
+    auto stage = [&](uint32_t it) {
+        if constexpr (STAGE) {
+            const uint32_t k0 = it / NPRIMES, pq = it - NPRIMES * k0;
+            const uint32_t *twq = A.tw + ((uint64_t)pq << LG);
+            for (uint32_t e = threadIdx.x; e < N1S; e += COL_THREADS) Tg[e] = twq[e];
+            if constexpr (MIX) {
+                const uint32_t *g0 = A.g3 + (((size_t)pq * 3 + k0) << LG);
+                const uint32_t *g1 = g0 + ((size_t)NPRIMES * 3 << LG);
+                for (uint32_t e = threadIdx.x; e < N1S; e += COL_THREADS) Tg[N1S + e] = g0[e];
+                for (uint32_t e = threadIdx.x; e < N1S / 2; e += COL_THREADS) Tg[2 * N1S + e] = g1[e];
+            }
+        }
+    };
     const uint32_t tile = xcd_tile(wg.x, wg.gx);
     const uint32_t arr = wg.y + A.arr0;
     const uint32_t c_lg = CLG ? (uint32_t)CLG : A.c_lg, lg = LG ? (uint32_t)LG : A.m1;
@@ -492,6 +524,10 @@ __device__ __forceinline__ void col_fwd_body(const ColFwdArgs &A, const WG &wg) 
     // wg.gz divides NSUB * NPRIMES
     const uint32_t per_z = NSUB * NPRIMES / wg.gz;
     const uint32_t it0 = wg.z * per_z, it1 = it0 + per_z;
+    if constexpr (STAGE) {
+        stage(it0);
+        __syncthreads();
+    }
 #pragma unroll 1
     for (uint32_t it = it0; it < it1; ++it) {
         const uint32_t k0 = it / NPRIMES, pq = it - NPRIMES * k0;
@@ -500,7 +536,12 @@ __device__ __forceinline__ void col_fwd_body(const ColFwdArgs &A, const WG &wg) 
         uint32_t *out = A.X + ((uint64_t)wg.y * NPRIMES + pq) * A.N + (uint64_t)k0 * Ns;
         const __amdgpu_buffer_rsrc_t ro = rsrc_of(out, Ns);  // this transform's Nsub words
         const uint32_t *g0 = nullptr, *g1 = nullptr;  // radix-3 row twiddles of transform k0 (k_tw_g3)
-        if constexpr (MIX) {
+        const uint32_t *tw1 = tw;                       // first-step twiddles
+        if constexpr (STAGE) {
+            tw1 = Tg;
+            g0 = Tg + N1S;
+            g1 = Tg + 2 * N1S;
+        } else if constexpr (MIX) {
             g0 = A.g3 + (((size_t)pq * 3 + k0) << lg);
             g1 = g0 + ((size_t)NPRIMES * 3 << lg);
         }
@@ -527,7 +568,7 @@ __device__ __forceinline__ void col_fwd_body(const ColFwdArgs &A, const WG &wg) 
             if (lg > (uint32_t)FLR) {
                 uint32_t w[FR];
 #pragma unroll
-                for (int s = 1; s < FR; ++s) w[s] = tw[n1 * brev_small(s, FLR)];
+                for (int s = 1; s < FR; ++s) w[s] = tw1[n1 * brev_small(s, FLR)];
                 dft_fwd_x<FR, !MIX, true>(v, w, M);
 #pragma unroll
                 for (int jj = 0; jj < FR; ++jj)
@@ -540,6 +581,7 @@ __device__ __forceinline__ void col_fwd_body(const ColFwdArgs &A, const WG &wg) 
         }
         if (lg == (uint32_t)FLR) continue;  // single-step transform: written straight to global memory
         __syncthreads();
+        if (it + 1 < it1) stage(it + 1);
         if constexpr (ColR16<LG, CLG>::last) {
             // 2^7 = 8 x 16 and 2^8 = 16 x 16: the rest is one radix-16 step
             col_last16_fwd<LG>(lds, A.m2, c0, ro, M, tl);
@@ -2804,6 +2846,13 @@ hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, uint64_t 
                                      d_status ? d_status : p->status_out);
     phase_mark(p, PA_PH_MH_CARRY, false, st);
     return e;
+}
+
+hipError_t launch_fill(uint32_t *dst, uint64_t count, uint32_t word, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    const uint64_t groups = std::min<uint64_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill32, dim3((unsigned)groups), dim3(256), 0, st, dst, count, word);
+    return hipGetLastError();
 }
 
 hipError_t launch_finish(pa_plan *p, uint64_t *y_out, uint64_t *U_out, hipStream_t st) {

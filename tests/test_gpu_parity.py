@@ -176,6 +176,34 @@ def test_two_pass_column_shapes(pa, gamma, variants):
         assert np.array_equal(y_g, y_o) and np.array_equal(U_g, U_o) and np.array_equal(out_g, out_o), info
 
 
+@pytest.mark.parametrize("n,r,flags", [
+    (1 << 20, (1 << 20) // 10, 0),        # 8192-point transforms: generic column and row kernels
+    (3 * 44497 - 7, 44497 // 3, 2),       # 3 * 2^m: radix-3 column pass, coefficient planes, digit tiles
+    (2 * 1257787 - 9, 1257787 // 5, 1),   # 2^17: 4096-point register rows, 32-row columns
+    (6972593 - 1234, 6972593 // 9, 1),    # 2^19: two-pass 128-row columns
+])
+def test_poisoned_scratch_does_not_change_results(pa, n, r, flags):
+    """Determinism against stale memory: the plan's scratch (everything but
+    the twiddle tables) is filled with a pattern before each hash
+    (pa_plan_fill_scratch); output and both stage values stay the oracle's
+    for every pattern, so no kernel reads a scratch word it has not written."""
+    st, g, k = defn.plan_shape(n, r)
+    assert st == 0
+    blk = synth.single_block(n % 1009, n, r, g, k)
+    st_o, out_o, y_o, U_o = oracle.hash(blk.key, n, r, g, blk.a, blk.b, blk.c, stages=True)
+    assert st_o == 0
+    plan = pa.Plan(n, r, flags=flags)
+    try:
+        for word in (0x00000000, 0xFFFFFFFF, 0xA5A5A5A5, 0x3FFFFFFF, 0x80000001):
+            say(f"[case] poisoned scratch n={n} r={r} gamma={g} k={k} flags={flags} word={word:#010x}")
+            assert plan.fill_scratch(word) == 0
+            st_g, out_g, y_g, U_g = run_gpu(pa, plan, blk, stages=True)
+            assert st_g == 0
+            assert np.array_equal(out_g, out_o) and np.array_equal(y_g, y_o) and np.array_equal(U_g, U_o), word
+    finally:
+        plan.close()
+
+
 # (gamma, k) whose transform length is 3 * 2^m, m = 6 .. 16: column passes of
 # 2^3 .. 2^7 rows (the 8-row one single-step), rows of 2^3 .. 2^12 words.
 RADIX3_SHAPES = [(2203, 2), (4253, 3), (9689, 1), (19937, 2), (44497, 3), (86243, 2), (132049, 3),
