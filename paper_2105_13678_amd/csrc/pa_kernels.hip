@@ -1063,42 +1063,34 @@ __global__ __launch_bounds__(ROW_MAX_THREADS) void km_row(const RowArgs *__restr
 //   step 3 (sub-length 16): elements 16 t .. 16 t + 15 (output in registers).
 // The x and a rows of a pair go through the steps together (two LDS
 // buffers), and their product accumulates in registers; the inverse starts
-// from those registers.  LDS addresses use an invertible XOR-linear swizzle
-// (bits 4..11 XORed into bits 0..5) that makes all three access patterns
-// free of bank conflicts for 32- and 64-bank LDS; because it is linear, each
-// thread computes the swizzled bases once and offsets them by constants.
+// from those registers.  LDS layout: element i of a row at word
+// i + floor(i / 16) (one pad word per 16), so each access is a per-thread
+// base plus a constant (the ds instructions' immediate offset, no address
+// arithmetic): step 1 at t + t/16 + 272 j, step 2 at 272 (t/16) + t%16 + 17 j,
+// step 3 at 17 t + j.  Steps 2 and 3 touch 64 distinct banks per wave; step
+// 1 at most two lanes per bank (three lane pairs).
 
 constexpr int R16_THREADS = 256;
 constexpr uint32_t R16_LEN = 4096;
-constexpr uint32_t R16_BA = 4 * R16_LEN;  // byte offset of the second row buffer
-
-
-
-__device__ __forceinline__ constexpr uint32_t swz_r16(uint32_t i) {
-    return i ^ (((i >> 4) & 1u) * 11u) ^ (((i >> 5) & 1u) * 5u) ^ (((i >> 6) & 1u) * 28u) ^
-           (((i >> 7) & 1u) * 13u) ^ (((i >> 8) & 1u) * 29u) ^ (((i >> 9) & 1u) * 60u) ^
-           (((i >> 10) & 1u) * 25u) ^ (((i >> 11) & 1u) * 43u);
-}
+constexpr uint32_t R16_PLEN = R16_LEN + R16_LEN / 16;  // padded row buffer, words
+constexpr uint32_t R16_BA = 4 * R16_PLEN;              // byte offset of the second row buffer
 
 template <int Stage>
 __device__ __forceinline__ void row16_body(const RowArgs &A, const WG &wg) {
-    __shared__ uint32_t L16[2 * R16_LEN];
-    // LDS: the x row's buffer at byte 0, the a row's at byte R16_BA.  Accesses
-    // go through byte addresses base ^ (4 * swz(offset)): one XOR each, the
-    // buffer base folded in beforehand (bit 14 is disjoint from every
-    // swizzled offset, so adding it commutes with the XOR).
+    __shared__ uint32_t L16[2 * R16_PLEN];
+    // LDS: the x row's buffer at byte 0, the a row's at byte R16_BA; byte
+    // addresses are a base (buffer plus the thread's padded offset) plus a
+    // constant per element.
     const uint32_t pq = wg.y;
     const PrimeConst M = A.P.c[pq];
     const uint32_t t = threadIdx.x;
     const uint32_t rho = xcd_tile(wg.x, wg.gx);
     const uint64_t rbase = (uint64_t)rho * R16_LEN;
     const uint32_t t4 = t * 4u;  // byte offset of element t in a row
-    // swizzled bases of this thread's three access patterns
-    const uint32_t s1 = swz_r16(t);                                  // t + 256 j
-    const uint32_t b2 = (t >> 4) * 256u + (t & 15u);
-    const uint32_t s2 = swz_r16(b2);                                 // b2 + 16 j
-    const uint32_t s3 = swz_r16(16u * t);                            // 16 t + j
-    const uint32_t s1b = s1 << 2, s2b = s2 << 2, s3b = s3 << 2;        // byte addresses
+    // padded bases (bytes) of this thread's three access patterns
+    const uint32_t s1b = 4u * (t + (t >> 4));                 // element t + 256 j at + 1088 j
+    const uint32_t s2b = 4u * (272u * (t >> 4) + (t & 15u));  // element 256 (t/16) + t%16 + 16 j at + 68 j
+    const uint32_t s3b = 68u * t;                             // element 16 t + j at + 4 j
     const uint32_t n1b = t & 15u;
     // step twiddles (step 1 omega_4096^(t k2), step 2 omega_4096^(16 n1 k2))
     // from a table in thread order, so each is one coalesced load per use
@@ -1143,7 +1135,7 @@ __device__ __forceinline__ void row16_body(const RowArgs &A, const WG &wg) {
             for (int j = 0; j < 16; ++j) v[j] = mont(v[j], wv[j], M);
             dft_fwd_tw<16>(v, w, M);
 #pragma unroll
-            for (int j = 0; j < 16; ++j) lds_word(L16, a1 ^ (swz_r16(256u * j) << 2)) = v[j];
+            for (int j = 0; j < 16; ++j) lds_word(L16, a1 + 1088u * j) = v[j];
         }
         __syncthreads();
 #pragma unroll 1
@@ -1152,23 +1144,23 @@ __device__ __forceinline__ void row16_body(const RowArgs &A, const WG &wg) {
             uint32_t v[16], w[16];
             // step 2: radix-16 on stride 16, step twiddles
 #pragma unroll
-            for (int j = 0; j < 16; ++j) v[j] = lds_word(L16, a2 ^ (swz_r16(16u * j) << 2));
+            for (int j = 0; j < 16; ++j) v[j] = lds_word(L16, a2 + 68u * j);
 #pragma unroll
             for (int j = 1; j < 16; ++j) w[j] = bload(rt, n4l, 16384u + 64u * j);
             __builtin_amdgcn_sched_barrier(0);
             dft_fwd_tw<16>(v, w, M);
 #pragma unroll
-            for (int j = 0; j < 16; ++j) lds_word(L16, a2 ^ (swz_r16(16u * j) << 2)) = v[j];
+            for (int j = 0; j < 16; ++j) lds_word(L16, a2 + 68u * j) = v[j];
         }
         __syncthreads();
         // step 3: radix-16 on 16 consecutive values of each row, then multiply-accumulate
         uint32_t vx[16], va[16];
         const uint32_t a3 = opaque(s3b);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) vx[j] = lds_word(L16, a3 ^ (4u * j));
+        for (int j = 0; j < 16; ++j) vx[j] = lds_word(L16, a3 + 4u * j);
         dft_fwd<16>(vx, M);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) va[j] = lds_word(L16, R16_BA + (a3 ^ (4u * j)));
+        for (int j = 0; j < 16; ++j) va[j] = lds_word(L16, R16_BA + a3 + 4u * j);
         dft_fwd<16>(va, M);
 #pragma unroll
         for (int j = 0; j < 16; ++j) pend[j] += (uint64_t)vx[j] * va[j];
@@ -1188,21 +1180,21 @@ __device__ __forceinline__ void row16_body(const RowArgs &A, const WG &wg) {
     const __amdgpu_buffer_rsrc_t rti = rsrc_of(A.r16i + pq * R16_TW, R16_TW);
     dft_inv<16>(acc, M);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) lds_word(L16, s3b ^ (4u * j)) = acc[j];
+    for (int j = 0; j < 16; ++j) lds_word(L16, s3b + 4u * j) = acc[j];
     __syncthreads();
     uint32_t v[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = lds_word(L16, s2b ^ (swz_r16(16u * j) << 2));
+    for (int j = 0; j < 16; ++j) v[j] = lds_word(L16, s2b + 68u * j);
     uint32_t w[16];
 #pragma unroll
     for (int s = 1; s < 16; ++s) w[s] = bload(rti, 4u * n1b, 16384u + 64u * s);
     __builtin_amdgcn_sched_barrier(0);
     dft_inv_tw<16>(v, w, M);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) lds_word(L16, s2b ^ (swz_r16(16u * j) << 2)) = v[j];
+    for (int j = 0; j < 16; ++j) lds_word(L16, s2b + 68u * j) = v[j];
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = lds_word(L16, s1b ^ (swz_r16(256u * j) << 2));
+    for (int j = 0; j < 16; ++j) v[j] = lds_word(L16, s1b + 1088u * j);
     const __amdgpu_buffer_rsrc_t ro = rsrc_of(A.out + pq * A.N + rbase, R16_LEN);
     const __amdgpu_buffer_rsrc_t rwi = rsrc_of(A.Wi + pq * A.N + rbase, R16_LEN);
 #pragma unroll
