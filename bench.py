@@ -481,8 +481,9 @@ LENGTH_BLOCKS = [(800_000_000, 80_000_000, 6), (1 << 32, 1 << 27, 7), (500_000_0
 
 
 def bench_lengths(args):
-    """Blocks hashed with transform lengths 3 * 2^m (PA_FLAG_RADIX3_LENGTHS)
-    and 2^m (PA_FLAG_POW2_LENGTHS), same inputs; outputs must agree.  Two
+    """Blocks hashed with transform lengths 3 * 2^m (PA_FLAG_RADIX3_LENGTHS),
+    2^m (PA_FLAG_POW2_LENGTHS) and, where one holds the product (m <= 20),
+    5 * 2^m (PA_FLAG_RADIX5_LENGTHS), same inputs; outputs must agree.  Two
     product lengths 2L - 1 fall just above a power of two, where the plan
     rule takes 3 * 2^m: the paper's largest CV block (n = 8e8, r = n/10:
     0.62 * 2^23) and the 2^32-bit block (r = 2^27: 0.52 * 2^24); one falls
@@ -496,7 +497,8 @@ def bench_lengths(args):
     K, Wm = args.steps, max(1, args.warmup)
     rows = []
     blocks = LENGTH_BLOCKS if args.block is None else [LENGTH_BLOCKS[args.block]]
-    modes = [m for m in (("radix3", pa.PA_FLAG_RADIX3_LENGTHS), ("pow2", pa.PA_FLAG_POW2_LENGTHS))
+    modes = [m for m in (("radix3", pa.PA_FLAG_RADIX3_LENGTHS), ("pow2", pa.PA_FLAG_POW2_LENGTHS),
+                         ("radix5", pa.PA_FLAG_RADIX5_LENGTHS))
              if args.mode in (None, m[0])]
     for n, r, seed in blocks:
         st, info = pa.plan_query(n, r)
@@ -506,6 +508,8 @@ def bench_lengths(args):
         del blk
         res = {}
         for label, flags in modes:
+            if pa.plan_query(n, r, flags=flags)[0] != 0:
+                continue  # no such length holds this product (5 * 2^m: m <= 20)
             plan = pa.Plan(n, r, device=0, flags=flags)
             out = plan.new_out()
             d_status = torch.zeros(K + Wm, dtype=torch.int32, device=dev)
@@ -526,9 +530,13 @@ def bench_lengths(args):
             plan.close()
         row = {"n": n, "r": r, "gamma": info["gamma"], "k": info["k"],
                "rule": "radix3" if info["len_factor"] == 3 else "pow2"}
-        if len(res) == 2:
-            row["outputs_equal"] = torch.equal(res["radix3"]["out"], res["pow2"]["out"])
+        if len(res) >= 2:
+            outs = [res[lab]["out"] for lab in res]
+            row["outputs_equal"] = all(torch.equal(outs[0], o) for o in outs[1:])
+        if "radix3" in res and "pow2" in res:
             row["speedup"] = round(res["pow2"]["ms_per_block"] / res["radix3"]["ms_per_block"], 3)
+        if "radix5" in res and "radix3" in res:
+            row["radix5_vs_radix3"] = round(res["radix3"]["ms_per_block"] / res["radix5"]["ms_per_block"], 3)
         for label in res:
             res[label].pop("out")
             row[label] = res[label]
@@ -710,7 +718,8 @@ def main():
     ap.add_argument("--requests", type=int, default=600, help="serving: number of Poisson arrivals")
     ap.add_argument("--block", type=int, choices=range(len(LENGTH_BLOCKS)), default=None,
                     help="lengths: run only this block (0: 8e8 bits, 1: 2^32 bits, 2: 5e8 bits)")
-    ap.add_argument("--mode", choices=["radix3", "pow2"], default=None, help="lengths: run only this length form")
+    ap.add_argument("--mode", choices=["radix3", "pow2", "radix5"], default=None,
+                    help="lengths: run only this length form")
     ap.add_argument("--core-only", action="store_true",
                     help="single: time only the K main steps (no per-step statistics, key-upload, pipelined or "
                          "batched passes), so that a profiler sees exactly those launches; batched: only the "

@@ -63,19 +63,22 @@ typedef enum pa_status {
 
 /* Plan request.  gamma = 0 picks the smallest Mersenne exponent above r.
  * The product of two L-limb numbers needs a cyclic convolution of length
- * N >= 2L - 1; N is either a power of two or three times one (a radix-3 step
- * over three power-of-two transforms), whichever is cheaper among the exact
- * choices.  B = 0 picks the limb width (at most 32 bits) that gives the
- * cheapest exact transform, the widest among equals; otherwise 8 <= B <= 32.
- * The output never depends on B or N. */
+ * N >= 2L - 1; N is a power of two or three times one (a radix-3 step over
+ * three power-of-two transforms), whichever is cheaper among the exact
+ * choices; lengths five times a power of two (a radix-5 step over five
+ * power-of-two transforms, N <= 5 * 2^20) are taken only on request.
+ * B = 0 picks the limb width (at most 32 bits) that gives the cheapest exact
+ * transform, the widest among equals; otherwise 8 <= B <= 32.  At most one
+ * length flag may be set.  The output never depends on B or N. */
 #define PA_FLAG_POW2_LENGTHS 1u   /* flags: power-of-two transform lengths only   */
 #define PA_FLAG_RADIX3_LENGTHS 2u /* flags: lengths 3 * 2^m only                  */
+#define PA_FLAG_RADIX5_LENGTHS 4u /* flags: lengths 5 * 2^m only (m <= 20)        */
 typedef struct pa_params {
     uint64_t n;       /* input key length in bits, n >= 2                    */
     uint64_t r;       /* output length in bits, 1 <= r < n and r < gamma     */
     uint64_t gamma;   /* Mersenne exponent, or 0 for automatic               */
     uint32_t B;       /* limb width in bits (the paper's 2^B-ary words), 0 = auto */
-    uint32_t flags;   /* 0, PA_FLAG_POW2_LENGTHS or PA_FLAG_RADIX3_LENGTHS  */
+    uint32_t flags;   /* 0 or one of the PA_FLAG_*_LENGTHS                  */
     uint32_t col_lg;  /* columns per tile of the key-chunk column pass,
                          2^col_lg; 0 = automatic; otherwise at most the row
                          length 2^log2N2, with log2N1 + col_lg <= 14       */
@@ -98,7 +101,7 @@ typedef struct pa_plan_info {
     uint32_t log2N2;        /* row-pass length 2^log2N2 (2^log2N = 2^(log2N1 + log2N2)) */
     uint32_t nprimes;       /* NTT primes per transform (3)                 */
     uint32_t primes[3];     /* the NTT primes p0, p1, p2 of this length     */
-    uint32_t len_factor;    /* 1, or 3 for the lengths N = 3 * 2^log2N      */
+    uint32_t len_factor;    /* 1, 3 or 5 (N = len_factor * 2^log2N)         */
     uint32_t col_lg;        /* column-tile width exponent of the key-chunk pass */
 } pa_plan_info;
 

@@ -22,6 +22,7 @@ PA_ERR_SEED_B_EVEN, PA_ERR_SEED_RANGE, PA_ERR_NOMEM, PA_ERR_DEVICE = -5, -6, -7,
 PA_ERR_BUSY, PA_ERR_LIMIT = -9, -10
 PA_FLAG_POW2_LENGTHS = 1  # pa_params.flags: power-of-two transform lengths only
 PA_FLAG_RADIX3_LENGTHS = 2  # pa_params.flags: lengths 3 * 2^m only
+PA_FLAG_RADIX5_LENGTHS = 4  # pa_params.flags: lengths 5 * 2^m only (m <= 20)
 
 # pa_phase, in order
 PHASES = ["prologue", "mmh_col", "mmh_row", "mmh_colinv", "fold", "mh_col", "mh_row", "mh_colinv",

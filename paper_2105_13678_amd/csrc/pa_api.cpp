@@ -27,14 +27,16 @@ constexpr uint64_t kMaxK = 4096;
 constexpr uint32_t kMinLog2Mix = 19;
 constexpr double kMixSmallCost = 1.6;
 constexpr double kLog2Of3 = 1.5849625007211562;
+constexpr double kLog2Of5 = 2.321928094887362;
 constexpr uint32_t kMinLog2N = 6;
 constexpr uint32_t kMaxLdsLog2 = 14;  // 2^14 words = 64 KiB of LDS per tile
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 pa_status plan_shape(const pa_params *prm, uint64_t *gamma, uint64_t *k, uint32_t *B) {
-    const uint32_t both = PA_FLAG_POW2_LENGTHS | PA_FLAG_RADIX3_LENGTHS;
-    if (!prm || (prm->flags & ~both) != 0 || (prm->flags & both) == both || prm->reserved != 0) return PA_ERR_ARG;
+    const uint32_t forms = PA_FLAG_POW2_LENGTHS | PA_FLAG_RADIX3_LENGTHS | PA_FLAG_RADIX5_LENGTHS;
+    if (!prm || (prm->flags & ~forms) != 0 || (prm->flags & (prm->flags - 1)) != 0 || prm->reserved != 0)
+        return PA_ERR_ARG;  // at most one length flag
     const uint64_t n = prm->n, r = prm->r;
     if (n < 2 || r < 1 || r >= n) return PA_ERR_ARG;
     uint64_t g = 0;
@@ -93,17 +95,24 @@ pa_status pa_decode_status(uint32_t flags) {
 namespace {
 
 // Transform length exponent for L limbs: the smallest m >= kMinLog2N with
-// f * 2^m >= 2L - 1 (f = 1 or 3; the full product of two L-limb numbers fits
-// without wrap).
+// f * 2^m >= 2L - 1 (f = 1, 3 or 5; the full product of two L-limb numbers
+// fits without wrap).
 uint32_t log2_len(uint64_t L, uint32_t f = 1) {
     uint32_t m = kMinLog2N;
     while ((uint64_t)f << m < 2 * L - 1) ++m;
     return m;
 }
 
-// Prime triple for transforms of length 2^m (mix = 0, m <= MAX_LOG2N) or
-// 3 * 2^m (mix = 1, m <= MAX_LOG2N_MIX); null beyond those lengths.
+// Prime triple for transforms of length 2^m (mix 0, m <= MAX_LOG2N), 3 * 2^m
+// (mix 1, m <= MAX_LOG2N_MIX) or 5 * 2^m (mix 2, m <= MAX_LOG2N_MIX5); null
+// beyond those lengths.
 const pa::PrimeTriple *triple_for(uint32_t m, uint32_t mix) {
+    if (mix == 2) {
+        if (m > pa::MAX_LOG2N_MIX5) return nullptr;
+        for (const pa::PrimeTriple &t : pa::PRIME_TRIPLES_5)
+            if (m <= t.max_lg) return &t;
+        return nullptr;
+    }
     if (mix) {
         for (const pa::PrimeTriple &t : pa::PRIME_TRIPLES_3)
             if (m <= t.max_lg) return &t;
@@ -135,8 +144,9 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     pa_status st = plan_shape(prm, &gamma, &k, &B);
     if (st != PA_OK) return st;
     if (k > kMaxK) return PA_ERR_LIMIT;
-    const uint32_t mx_lo = (prm->flags & PA_FLAG_RADIX3_LENGTHS) ? 1u : 0u;
-    const uint32_t mx_hi = (prm->flags & PA_FLAG_POW2_LENGTHS) ? 1u : 2u;
+    // length forms tried: the flagged one, else 2^m and 3 * 2^m (5 * 2^m only on request)
+    const uint32_t mx_lo = (prm->flags & PA_FLAG_RADIX5_LENGTHS) ? 2u : (prm->flags & PA_FLAG_RADIX3_LENGTHS) ? 1u : 0u;
+    const uint32_t mx_hi = (prm->flags & PA_FLAG_RADIX5_LENGTHS) ? 3u : (prm->flags & PA_FLAG_POW2_LENGTHS) ? 1u : 2u;
     // Candidate lengths for limb width b: the shortest 2^m and 3 * 2^m that
     // hold the product, each with its own primes.  Cost model: butterflies
     // N log2 N, plus one pass over N for the radix-3 step; lengths 3 * 2^m
@@ -150,13 +160,14 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
         const uint64_t Lb = (gamma + b - 1) / b;
         bool ok = false;
         for (uint32_t mx = mx_lo; mx < mx_hi; ++mx) {
-            const uint32_t mb = log2_len(Lb, mx ? 3 : 1);
+            const uint32_t f = pa::len_factor_of(mx);
+            const uint32_t mb = log2_len(Lb, f);
             const pa::PrimeTriple *T = triple_for(mb, mx);
             if (!T) continue;
             seen = true;
             if (!exact(k, Lb, b, *T)) continue;
-            const double Nl = (double)((uint64_t)(mx ? 3 : 1) << mb);
-            const double lgN = mb + (mx ? kLog2Of3 : 0.0);
+            const double Nl = (double)((uint64_t)f << mb);
+            const double lgN = mb + (mx == 2 ? kLog2Of5 : mx ? kLog2Of3 : 0.0);
             const double cost = Nl * (lgN + (mx ? 1.0 : 0.0)) * (mx && mb < kMinLog2Mix ? kMixSmallCost : 1.0);
             if (!ok || cost < *cost_out) {
                 ok = true;
@@ -196,8 +207,9 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     p->B = B;
     p->L = L;
     p->mix = mix;
+    p->rf = pa::len_factor_of(mix);
     p->Nsub = 1ull << m;
-    p->N = (mix ? 3ull : 1ull) << m;
+    p->N = (uint64_t)p->rf << m;
     p->W = (gamma + 63) / 64;
     p->key_words = (prm->n + 63) / 64;
     p->out_words = (prm->r + 63) / 64;
@@ -272,7 +284,9 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     lay->oT2 = carve(P3 * n2 * 4 * 2);
     lay->oW = carve(P3 * N * 4 * 2);
     lay->oR16 = carve(P3 * pa::R16_TW * 4 * 2);
-    lay->oG3 = carve(mix ? 3 * P3 * 3 * n1 * 4 : 0);
+    // radix-3 / radix-5 row twiddles: (f + 1) / 2 forward tables and one inverse table,
+    // each NPRIMES x f x N1 words
+    lay->oG3 = carve(mix ? (size_t)((p->rf + 1) / 2 + 1) * P3 * p->rf * n1 * 4 : 0);
     lay->total = off;
     lay->table_bytes = off - lay->scratch_bytes;
     p->workspace_bytes = off;
@@ -415,7 +429,7 @@ pa_status pa_plan_get_info(const pa_plan *p, pa_plan_info *info) {
     info->log2N2 = p->m2;
     info->nprimes = pa::NPRIMES;
     for (int q = 0; q < pa::NPRIMES; ++q) info->primes[q] = p->primes.c[q].p;
-    info->len_factor = p->mix ? 3 : 1;
+    info->len_factor = p->rf;
     info->col_lg = p->c_lg;
     return PA_OK;
 }

@@ -24,6 +24,10 @@ namespace pa {
 constexpr int NPRIMES = 3;
 constexpr uint32_t MAX_LOG2N = 24;      // longest power-of-two transform with three such primes
 constexpr uint32_t MAX_LOG2N_MIX = 23;  // longest transform 3 * 2^m
+constexpr uint32_t MAX_LOG2N_MIX5 = 20; // longest transform 5 * 2^m (column passes of at most 256 rows)
+
+// Length forms: mix 0 for N = 2^m, 1 for N = 3 * 2^m, 2 for N = 5 * 2^m.
+constexpr uint32_t len_factor_of(uint32_t mix) { return mix == 2 ? 5u : mix == 1 ? 3u : 1u; }
 
 // The three largest primes p < 2^30 with 2^max_lg | p - 1 (product 2^log2P),
 // for the transform lengths 2^m, m <= max_lg, not served by an earlier row.
@@ -47,6 +51,13 @@ constexpr PrimeTriple PRIME_TRIPLES_3[] = {
     {21, {1012924417u, 975175681u, 962592769u}},    // 2^89.619
     {22, {943718401u, 918552577u, 880803841u}},     // 2^89.303
     {23, {880803841u, 754974721u, 377487361u}},     // 2^87.698
+};
+// The same for the lengths 5 * 2^m: the three largest primes p < 2^30 with
+// 5 * 2^max_lg | p - 1.
+constexpr PrimeTriple PRIME_TRIPLES_5[] = {
+    {18, {1073479681u, 1068236801u, 1056440321u}},  // 2^89.969
+    {19, {1056440321u, 1053818881u, 985661441u}},   // 2^89.826
+    {20, {1053818881u, 985661441u, 975175681u}},    // 2^89.711
 };
 
 // Per-prime constants (Montgomery form x*2^32 mod p where noted).
@@ -78,6 +89,12 @@ struct CrtConst {
 struct Mix3Const {
     uint32_t neg_half[NPRIMES];  // -1/2 mod p
     uint32_t h[NPRIMES];
+};
+
+// Inverse radix-5 step of the lengths N = 5 * 2^m: omega_5^-e (omega_5 =
+// omega_N^(N/5)) for e < 5, Montgomery form, per prime.
+struct Mix5Const {
+    uint32_t wi[NPRIMES][5];
 };
 
 // ---------------------------------------------------------------- carry functions
@@ -145,7 +162,9 @@ struct pa_plan {
     uint64_t n, r, gamma, k, L, N, W;
     uint64_t key_words, out_words;
     uint32_t B;
-    uint32_t mix;               // 1: N = 3 * 2^m (a radix-3 step over three length-2^m transforms); 0: N = 2^m
+    uint32_t mix;               // length form: 0: N = 2^m; 1: N = 3 * 2^m, 2: N = 5 * 2^m (a radix-3 or
+                                // radix-5 step over three or five length-2^m transforms)
+    uint32_t rf;                // N / 2^m: 1, 3 or 5
     uint64_t Nsub;              // 2^m: length of the power-of-two transforms
     uint32_t m, m1, m2;         // 2^m = 2^m1 (column length) * 2^m2 (row length)
     uint32_t c_lg, c_lg_mh;     // 2^c columns per tile of the forward column pass: key chunks and seeds; MH stage
@@ -158,6 +177,7 @@ struct pa_plan {
     pa::PrimeSet primes;
     pa::CrtConst crt;
     pa::Mix3Const mix3;
+    pa::Mix5Const mix5;
 
     // device memory (one allocation, carved)
     void *base;
@@ -226,7 +246,7 @@ struct DeviceGuard {
 };
 
 // Identifies a plan's transform length (and so its primes and twiddle tables).
-inline uint32_t len_key(const pa_plan &p) { return p.mix << 7 | p.m; }
+inline uint32_t len_key(const pa_plan &p) { return p.rf << 7 | p.m; }
 
 // Host-side plan derivation (no device access) and buffer binding (pa_api.cpp).
 pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay);

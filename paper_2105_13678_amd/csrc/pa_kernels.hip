@@ -226,25 +226,29 @@ __global__ void k_tw_four(uint32_t *Wf, uint32_t *Wi, uint32_t m1, uint32_t m2, 
     }
 }
 
-// Row parts of the radix-3 twiddles of the lengths N = 3 * 2^m (m = m1 + m2),
-// per prime q and transform k0 < 3, indexed by the column-pass row r < 2^m1:
-// g[0] = omega_N^(k0 r N2) and g[1] = omega_N^(k0 (r N2 + N/3)) (forward;
-// the second includes omega_3^k0), g[2] = omega_N^(-k0 r N2) (inverse), each
-// table NPRIMES x 3 x 2^m1 words, Montgomery form (scale of the arguments).
-__global__ void k_tw_g3(uint32_t *g, uint32_t m1, uint32_t m2, TwArgs F, TwArgs I, const uint32_t *hdr,
+// Row parts of the radix-f twiddles of the lengths N = f * 2^m (f = 3, 5;
+// m = m1 + m2), per prime q and transform k0 < f, indexed by the column-pass
+// row r < 2^m1: forward tables n0 < (f + 1) / 2, g[n0] = omega_N^(k0 (r N2 +
+// n0 N/f)) (n0 = 0: the row part of omega_N^(k0 n); n0 > 0 also carry
+// omega_f^(k0 n0) for the input x_(n + n0 N/f)), then the inverse table
+// omega_N^(-k0 r N2); each table NPRIMES x f x 2^m1 words, Montgomery form
+// (scale of the arguments).
+__global__ void k_tw_gx(uint32_t *g, uint32_t f, uint32_t m1, uint32_t m2, TwArgs F, TwArgs I, const uint32_t *hdr,
                         uint32_t want) {
     if (tw_present(hdr, want)) return;
     const uint32_t q = blockIdx.y;
     const uint32_t n1 = 1u << m1;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 3u * n1) return;
+    if (i >= f * n1) return;
     const uint32_t k0 = i >> m1, r = i & (n1 - 1);
+    const uint32_t nf = (f + 1) / 2;
+    const size_t tab = (size_t)NPRIMES * f * n1;
     const uint64_t e = (uint64_t)k0 * ((uint64_t)r << m2);
-    const uint64_t e3 = (uint64_t)k0 * (((uint64_t)r << m2) + (1ull << (m1 + m2)));
-    const size_t tab = (size_t)NPRIMES * 3 * n1;
-    g[q * 3 * n1 + i] = mulmod_slow(F.scale[q], powmod_slow(F.base[q], e, F.p[q]), F.p[q]);
-    g[tab + q * 3 * n1 + i] = mulmod_slow(F.scale[q], powmod_slow(F.base[q], e3, F.p[q]), F.p[q]);
-    g[2 * tab + q * 3 * n1 + i] = mulmod_slow(I.scale[q], powmod_slow(I.base[q], e, I.p[q]), I.p[q]);
+    for (uint32_t n0 = 0; n0 < nf; ++n0) {
+        const uint64_t en = (uint64_t)k0 * (((uint64_t)r << m2) + ((uint64_t)n0 << (m1 + m2)));
+        g[n0 * tab + q * f * n1 + i] = mulmod_slow(F.scale[q], powmod_slow(F.base[q], en, F.p[q]), F.p[q]);
+    }
+    g[nf * tab + q * f * n1 + i] = mulmod_slow(I.scale[q], powmod_slow(I.base[q], e, I.p[q]), I.p[q]);
 }
 
 // Step twiddles of the 4096-point row kernel rearranged so that the lanes of
@@ -317,7 +321,7 @@ struct ColFwdArgs {
     uint32_t *notones;
     const uint32_t *tw;  // per prime: omega_{N1}^e, e < N1
     uint64_t Nsub;       // length of the power-of-two transforms (N or N/3)
-    const uint32_t *g3;  // N = 3 Nsub: the radix-3 row twiddle tables (k_tw_g3)
+    const uint32_t *g3;  // N = 3 Nsub or 5 Nsub: the row twiddle tables (k_tw_gx)
     PrimeSet P;
 };
 
@@ -439,46 +443,58 @@ __device__ __forceinline__ void col_last16_fwd(const uint32_t *buf, uint32_t m2,
 // N = 2^m (MIX false): since N >= 2L - 1, every limb index >= N/2 is padding,
 // so rows n1 >= N1/2 of the column tile are zero and the first radix-8 step
 // unpacks only four inputs.
-// N = 3 Nsub (MIX true): for each of the three transforms k0 of the radix-3
+// N = 3 Nsub (RADIX 3): for each of the three transforms k0 of the radix-3
 // split as well, whose input at n < Nsub is (x_n + omega_3^k0 x_(n+Nsub))
 // omega_N^(k0 n); x_(n+2Nsub) is padding since L <= Nsub * 3/2, and
-// x_(n+Nsub) only reaches rows < N1/2.  Only the row part omega_N^(k0 r N2)
-// of the twiddle (n = r N2 + c) is applied here; the column part
-// omega_N^(k0 c) rides on the four-step twiddle of the row pass.
+// x_(n+Nsub) only reaches rows < N1/2.  N = 5 Nsub (RADIX 5): five
+// transforms, inputs (x_n + omega_5^k0 x_(n+Nsub) + omega_5^(2 k0)
+// x_(n+2Nsub)) omega_N^(k0 n) (L <= Nsub * 5/2: x_(n+Nsub) reaches every row,
+// x_(n+2Nsub) the rows < N1/2, higher terms are padding).  Only the row part
+// omega_N^(k0 r N2) of the twiddle (n = r N2 + c) is applied here; the column
+// part omega_N^(k0 c) rides on the four-step twiddle of the row pass.
 // The last step writes its rows straight to global memory.
 // LG, CLG (nonzero): the column length 2^m1 and tile width 2^c_lg fixed at
 // compile time for the common tile shapes (shifts, masks and swizzles fold
 // into constants; the tile lives in static LDS).
-template <int Stage, bool MIX, int TPT, int LG, int CLG>
+template <int Stage, int RADIX, int TPT, int LG, int CLG>
 __device__ __forceinline__ void col_fwd_body(const ColFwdArgs &A, const WG &wg) {
-    constexpr uint32_t NSUB = MIX ? 3u : 1u;
+    static_assert(RADIX == 1 || RADIX == 3 || RADIX == 5, "length factors 1, 3, 5");
+    constexpr bool MIX = RADIX != 1;
+    constexpr uint32_t NSUB = (uint32_t)RADIX;
     constexpr int FR = ColR16<LG, CLG>::first ? 16 : 8;  // radix of the first step
     constexpr int FLR = FR == 16 ? 4 : 3;
-    constexpr int XR = MIX ? FR : FR / 2;  // first-step rows of a task that hold x_n
-    constexpr int XR1 = MIX ? FR / 2 : 1;  // ... and x_(n+Nsub) (N = 3 Nsub)
+    constexpr int XR = MIX ? FR : FR / 2;                          // first-step rows of a task that hold x_n
+    constexpr int XR1 = RADIX == 5 ? FR : RADIX == 3 ? FR / 2 : 1;  // ... x_(n+Nsub)
+    constexpr int XR2 = RADIX == 5 ? FR / 2 : 1;                    // ... x_(n+2Nsub)
     __shared__ uint32_t Lt[LG && CLG ? 1u << (LG + CLG) : 1u];
     uint32_t *lds = LG && CLG ? Lt : lds_dyn;
     // Compile-time tiles of 16 .. 256 rows stage the first step's twiddles
     // in LDS, transform by transform: the column twiddles omega_N1^e of the
-    // prime (N1 words) and, for N = 3 Nsub, the radix-3 row twiddles g0 (N1
-    // words) and g1 (its rows below N1 / 2): LDS reads instead of a dozen or
+    // prime (N1 words) and, for N = 3 Nsub or 5 Nsub, the row twiddles g0 (N1
+    // words), g1 (N1 words for radix 5, its rows below N1 / 2 for radix 3)
+    // and for radix 5 g2 (rows below N1 / 2): LDS reads instead of a dozen or
     // more global loads per task and transform.  The next transform's tables
     // are written after the barrier that ends the current first step (no
     // thread reads them any more), and the barrier at the top of the next
     // transform publishes them.
     constexpr bool STAGE = LG >= 4 && LG <= 8 && CLG != 0;
     constexpr uint32_t N1S = STAGE ? 1u << LG : 0u;
-    __shared__ uint32_t Tg[STAGE ? (MIX ? N1S * 2 + N1S / 2 : N1S) : 1u];
+    constexpr uint32_t G1S = RADIX == 5 ? N1S : N1S / 2;  // staged rows of g1
+    __shared__ uint32_t Tg[STAGE ? (RADIX == 5 ? 3 * N1S + N1S / 2 : MIX ? N1S * 2 + N1S / 2 : N1S) : 1u];
     auto stage = [&](uint32_t it) {
         if constexpr (STAGE) {
             const uint32_t k0 = it / NPRIMES, pq = it - NPRIMES * k0;
             const uint32_t *twq = A.tw + ((uint64_t)pq << LG);
             for (uint32_t e = threadIdx.x; e < N1S; e += COL_THREADS) Tg[e] = twq[e];
             if constexpr (MIX) {
-                const uint32_t *g0 = A.g3 + (((size_t)pq * 3 + k0) << LG);
-                const uint32_t *g1 = g0 + ((size_t)NPRIMES * 3 << LG);
+                const uint32_t *g0 = A.g3 + (((size_t)pq * RADIX + k0) << LG);
+                const uint32_t *g1 = g0 + ((size_t)NPRIMES * RADIX << LG);
                 for (uint32_t e = threadIdx.x; e < N1S; e += COL_THREADS) Tg[N1S + e] = g0[e];
-                for (uint32_t e = threadIdx.x; e < N1S / 2; e += COL_THREADS) Tg[2 * N1S + e] = g1[e];
+                for (uint32_t e = threadIdx.x; e < G1S; e += COL_THREADS) Tg[2 * N1S + e] = g1[e];
+                if constexpr (RADIX == 5) {
+                    const uint32_t *g2 = g1 + ((size_t)NPRIMES * RADIX << LG);
+                    for (uint32_t e = threadIdx.x; e < N1S / 2; e += COL_THREADS) Tg[2 * N1S + G1S + e] = g2[e];
+                }
             }
         }
     };
@@ -493,7 +509,7 @@ __device__ __forceinline__ void col_fwd_body(const ColFwdArgs &A, const WG &wg) 
     const uint32_t ntask = (1u << lgMp) << c_lg;  // at most TPT * COL_THREADS
     const uint32_t Ns = (uint32_t)A.Nsub;
     const uint32_t t = threadIdx.x;
-    uint32_t x[TPT][XR], x1[TPT][XR1];
+    uint32_t x[TPT][XR], x1[TPT][XR1], x2[TPT][XR2];
     {
         const LimbSrc S = limb_src(A, arr);
         const uint32_t L = (uint32_t)A.L;
@@ -508,10 +524,16 @@ __device__ __forceinline__ void col_fwd_body(const ColFwdArgs &A, const WG &wg) 
                 x[u][jj] = task < ntask ? limb_at(S, j) : 0u;
                 if (is_key && task < ntask && j < L) not_ones |= (x[u][jj] != (j == L - 1 ? topv : full));
                 if constexpr (MIX) {
-                    if (jj >= FR / 2) continue;
+                    if (jj >= XR1) continue;
                     x1[u][jj] = task < ntask ? limb_at(S, j + Ns) : 0u;
                     if (is_key && task < ntask && j + Ns < L)
                         not_ones |= (x1[u][jj] != (j + Ns == L - 1 ? topv : full));
+                }
+                if constexpr (RADIX == 5) {
+                    if (jj >= XR2) continue;
+                    x2[u][jj] = task < ntask ? limb_at(S, j + 2 * Ns) : 0u;
+                    if (is_key && task < ntask && j + 2 * Ns < L)
+                        not_ones |= (x2[u][jj] != (j + 2 * Ns == L - 1 ? topv : full));
                 }
             }
         }
@@ -520,7 +542,7 @@ __device__ __forceinline__ void col_fwd_body(const ColFwdArgs &A, const WG &wg) 
             if (any && t == 0) A.notones[arr] = 1u;
         }
     }
-    // the transforms (primes x radix-3 branches) of this workgroup's z slice:
+    // the transforms (primes x radix-3 or radix-5 branches) of this workgroup's z slice:
     // wg.gz divides NSUB * NPRIMES
     const uint32_t per_z = NSUB * NPRIMES / wg.gz;
     const uint32_t it0 = wg.z * per_z, it1 = it0 + per_z;
@@ -535,15 +557,18 @@ __device__ __forceinline__ void col_fwd_body(const ColFwdArgs &A, const WG &wg) 
         const uint32_t *tw = A.tw + ((uint64_t)pq << lg);
         uint32_t *out = A.X + ((uint64_t)wg.y * NPRIMES + pq) * A.N + (uint64_t)k0 * Ns;
         const __amdgpu_buffer_rsrc_t ro = rsrc_of(out, Ns);  // this transform's Nsub words
-        const uint32_t *g0 = nullptr, *g1 = nullptr;  // radix-3 row twiddles of transform k0 (k_tw_g3)
-        const uint32_t *tw1 = tw;                       // first-step twiddles
+        // row twiddles of transform k0 (k_tw_gx tables g0, g1, g2)
+        const uint32_t *g0 = nullptr, *g1 = nullptr, *g2 = nullptr;
+        const uint32_t *tw1 = tw;  // first-step twiddles
         if constexpr (STAGE) {
             tw1 = Tg;
             g0 = Tg + N1S;
             g1 = Tg + 2 * N1S;
+            g2 = Tg + 2 * N1S + G1S;
         } else if constexpr (MIX) {
-            g0 = A.g3 + (((size_t)pq * 3 + k0) << lg);
-            g1 = g0 + ((size_t)NPRIMES * 3 << lg);
+            g0 = A.g3 + (((size_t)pq * RADIX + k0) << lg);
+            g1 = g0 + ((size_t)NPRIMES * RADIX << lg);
+            g2 = g1 + ((size_t)NPRIMES * RADIX << lg);
         }
         if (it != it0) __syncthreads();  // the previous transform's last step has read the buffer
         const uint32_t tl = opaque(t);  // task addresses are recomputed per transform, not kept live
@@ -553,7 +578,14 @@ __device__ __forceinline__ void col_fwd_body(const ColFwdArgs &A, const WG &wg) 
             if (task >= ntask) continue;
             const uint32_t q = task & cmask, n1 = task >> c_lg;
             uint32_t v[FR];
-            if constexpr (MIX) {
+            if constexpr (RADIX == 5) {
+#pragma unroll
+                for (int jj = 0; jj < FR; ++jj) {
+                    const uint32_t row = n1 + ((uint32_t)jj << lgMp);
+                    v[jj] = red2(mont(x[u][jj], g0[row], M) + mont(x1[u][jj], g1[row], M), M);  // in [0, 2p)
+                    if (jj < FR / 2) v[jj] = red2(v[jj] + mont(x2[u][jj & (FR / 2 - 1)], g2[row], M), M);
+                }
+            } else if constexpr (MIX) {
 #pragma unroll
                 for (int jj = 0; jj < FR; ++jj) {
                     const uint32_t row = n1 + ((uint32_t)jj << lgMp);
@@ -598,15 +630,15 @@ __device__ __forceinline__ void col_fwd_body(const ColFwdArgs &A, const WG &wg) 
     }
 }
 
-template <int Stage, bool MIX, int TPT, int LG = 0, int CLG = 0>
-__global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) { col_fwd_body<Stage, MIX, TPT, LG, CLG>(A, wg_self()); }
+template <int Stage, int RADIX, int TPT, int LG = 0, int CLG = 0>
+__global__ __launch_bounds__(COL_THREADS) void k_col_fwd(ColFwdArgs A) { col_fwd_body<Stage, RADIX, TPT, LG, CLG>(A, wg_self()); }
 
-template <int Stage, bool MIX, int TPT, int LG = 0, int CLG = 0>
+template <int Stage, int RADIX, int TPT, int LG = 0, int CLG = 0>
 __global__ __launch_bounds__(COL_THREADS) void km_col_fwd(const ColFwdArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
                                      const uint16_t *__restrict__ owner) {
     WG wg;
     const uint32_t i = wg_multi(geo, owner, wg);
-    if (i != MULTI_NONE) col_fwd_body<Stage, MIX, TPT, LG, CLG>(tab[i], wg);
+    if (i != MULTI_NONE) col_fwd_body<Stage, RADIX, TPT, LG, CLG>(tab[i], wg);
 }
 
 // ---- 512-row column tiles (N1 = 2^9), 16 columns: compile-time shape -------
@@ -680,7 +712,7 @@ __device__ __forceinline__ void col9_fwd_body(const ColFwdArgs &A, const WG &wg)
         const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.tw + ((uint64_t)pq << C9_LG), 1u << C9_LG);
         uint32_t *out = A.X + ((uint64_t)wg.y * NPRIMES + pq) * A.N + (uint64_t)k0 * Ns;
         const __amdgpu_buffer_rsrc_t ro = rsrc_of(out, Ns);  // this transform's Nsub words
-        // radix-3 row twiddles of transform k0 (tables g0, g1 of k_tw_g3)
+        // radix-3 row twiddles of transform k0 (tables g0, g1 of k_tw_gx)
         __amdgpu_buffer_rsrc_t rg0 = rtw, rg1 = rtw;
         if constexpr (MIX) {
             const uint32_t *g0 = A.g3 + (((size_t)pq * 3 + k0) << C9_LG);
@@ -823,7 +855,7 @@ __device__ __forceinline__ void col10_fwd_body(const ColFwdArgs &A, const WG &wg
         const __amdgpu_buffer_rsrc_t rtw = rsrc_of(A.tw + ((uint64_t)pq << C10_LG), 1u << C10_LG);
         uint32_t *out = A.X + ((uint64_t)wg.y * NPRIMES + pq) * A.N + (uint64_t)k0 * Ns;
         const __amdgpu_buffer_rsrc_t ro = rsrc_of(out, Ns);  // this transform's Nsub words
-        // radix-3 row twiddles of transform k0 (tables g0, g1 of k_tw_g3)
+        // radix-3 row twiddles of transform k0 (tables g0, g1 of k_tw_gx)
         __amdgpu_buffer_rsrc_t rg0 = rtw, rg1 = rtw;
         if constexpr (MIX) {
             const uint32_t *g0 = A.g3 + (((size_t)pq * 3 + k0) << C10_LG);
@@ -1651,7 +1683,7 @@ struct Crt3Args {
     uint32_t *c96;
     uint64_t N, Nsub, count;
     uint32_t m1, m2;
-    const uint32_t *gi;  // inverse radix-3 row twiddles [q][k0][r] (third k_tw_g3 table)
+    const uint32_t *gi;  // inverse radix-3 row twiddles [q][k0][r] (third k_tw_gx table)
     PrimeSet P;
     CrtConst K;
     Mix3Const X;
@@ -1709,6 +1741,78 @@ __global__ void km_crt3(const Crt3Args *__restrict__ tab, const MultiGeo *__rest
     WG wg;
     const uint32_t i = wg_multi(geo, owner, wg);
     if (i != MULTI_NONE) crt3_body(tab[i], wg);
+}
+
+struct Crt5Args {
+    const uint32_t *cc;  // 3 primes x N residues: five inverse transforms of Nsub words each
+    uint32_t *c96;
+    uint64_t N, Nsub, count;
+    uint32_t m1, m2;
+    const uint32_t *gi;  // inverse radix-5 row twiddles [q][k0][r] (the last k_tw_gx table)
+    PrimeSet P;
+    CrtConst K;
+    Mix5Const X;
+    const uint32_t *notones;
+    uint64_t k;
+    uint32_t *status;
+};
+
+// The reconstruction for N = 5 Nsub, fused with the inverse radix-5 step:
+// thread j1 < Nsub takes the residues s_k0 at j1 of the five inverse
+// transforms (canonical, 1/N and the column part omega_N^(-k0 c) of the
+// twiddle already applied), multiplies s_k0 (k0 > 0) by the row part
+// omega_N^(-k0 r N2) (j1 = r N2 + c), evaluates the 5-point inverse DFT
+// x_(n0) = sum_k0 u_k0 omega_5^(-k0 n0) term by term (each partial sum kept
+// below 2p) and reconstructs the coefficients j1 + n0 Nsub below `count`.
+__device__ __forceinline__ void crt5_body(const Crt5Args &A, const WG &wg) {
+    const uint64_t j1 = (uint64_t)wg.x * blockDim.x + threadIdx.x;
+    if (A.notones && wg.x == 0) {
+        bool reload = false;
+        for (uint64_t i = threadIdx.x; i < A.k; i += blockDim.x) reload |= (A.notones[i] == 0u);
+        const int any = __syncthreads_or(reload);
+        if (threadIdx.x == 0) A.status[1] = A.status[0] | (any ? ST_RELOAD : 0u);
+    }
+    if (j1 >= A.Nsub || j1 >= A.count) return;
+    const uint32_t r = (uint32_t)(j1 >> A.m2);
+    uint32_t x[5][NPRIMES];  // [n0][prime], canonical
+#pragma unroll
+    for (int q = 0; q < NPRIMES; ++q) {
+        const PrimeConst &M = A.P.c[q];
+        const uint32_t *c = A.cc + q * A.N + j1;
+        const uint32_t *gi = A.gi + (((size_t)q * 5) << A.m1);
+        uint32_t u[5];
+        u[0] = c[0];  // canonical, below p
+#pragma unroll
+        for (int k0 = 1; k0 < 5; ++k0) u[k0] = mont(c[(uint64_t)k0 * A.Nsub], gi[((uint32_t)k0 << A.m1) + r], M);
+#pragma unroll
+        for (int n0 = 0; n0 < 5; ++n0) {
+            uint32_t acc = u[0];  // [0, 2p) throughout
+#pragma unroll
+            for (int k0 = 1; k0 < 5; ++k0) {
+                const uint32_t term = n0 ? mont(u[k0], A.X.wi[q][(k0 * n0) % 5], M) : u[k0];
+                acc = red2(acc + term, M);
+            }
+            x[n0][q] = canon(acc, M);
+        }
+    }
+#pragma unroll
+    for (int n0 = 0; n0 < 5; ++n0) {
+        const uint64_t j = j1 + (uint64_t)n0 * A.Nsub;
+        if (j >= A.count) break;
+        const unsigned __int128 c = garner(x[n0][0], x[n0][1], x[n0][2], A.P, A.K);
+        A.c96[j] = (uint32_t)c;
+        A.c96[A.N + j] = (uint32_t)(c >> 32);
+        A.c96[2 * A.N + j] = (uint32_t)(c >> 64);
+    }
+}
+
+__global__ void k_crt5(Crt5Args A) { crt5_body(A, wg_self()); }
+
+__global__ void km_crt5(const Crt5Args *__restrict__ tab, const MultiGeo *__restrict__ geo,
+                        const uint16_t *__restrict__ owner) {
+    WG wg;
+    const uint32_t i = wg_multi(geo, owner, wg);
+    if (i != MULTI_NONE) crt5_body(tab[i], wg);
 }
 
 __device__ __forceinline__ unsigned __int128 coef(const uint32_t *__restrict__ c96, uint64_t N, uint64_t j) {
@@ -2352,20 +2456,21 @@ uint32_t root_of_unity(uint32_t p, uint32_t log2n) {
     return hpow(g, (uint64_t)(p - 1) >> log2n, p);
 }
 
-// A primitive root of unity of order 2^log2n (mix = 0) or 3 * 2^log2n (mix =
-// 1; 3 * 2^log2n | p - 1).  For mix = 1 it is w^a c with w = root_of_unity(p,
-// log2n), a = 3^-1 mod 2^log2n and c = h^((p-1)/3) != 1 for the smallest such
-// h: its cube is w itself, so the three power-of-two transforms of the
-// radix-3 split use exactly the roots (and the radix-16 constants) of the
+// A primitive root of unity of order f * 2^log2n, f = 1, 3 or 5 (mix 0, 1,
+// 2; f * 2^log2n | p - 1).  For f > 1 it is w^a c with w = root_of_unity(p,
+// log2n), a = f^-1 mod 2^log2n and c = h^((p-1)/f) != 1 for the smallest such
+// h: its f-th power is w itself, so the f power-of-two transforms of the
+// radix-f split use exactly the roots (and the radix-16 constants) of the
 // plain length-2^log2n transform.
 uint32_t root_of_len(uint32_t p, uint32_t log2n, uint32_t mix) {
     const uint32_t w = root_of_unity(p, log2n);
     if (!mix) return w;
-    uint64_t inv3 = 3;  // 3^-1 mod 2^64 by Newton iteration (3 * 3 = 1 mod 8)
-    for (int i = 0; i < 5; ++i) inv3 *= 2 - 3 * inv3;
-    const uint64_t a = inv3 & ((1ull << log2n) - 1);
+    const uint64_t f = len_factor_of(mix);
+    uint64_t inv = f;  // f^-1 mod 2^64 by Newton iteration (f * f = 1 mod 8 for f = 3, 5)
+    for (int i = 0; i < 5; ++i) inv *= 2 - f * inv;
+    const uint64_t a = inv & ((1ull << log2n) - 1);
     uint32_t c = 1;
-    for (uint32_t h = 2; c == 1; ++h) c = hpow(h, (p - 1) / 3, p);
+    for (uint32_t h = 2; c == 1; ++h) c = hpow(h, (p - 1) / (uint32_t)f, p);
     return hmul(hpow(w, a, p), c, p);
 }
 
@@ -2400,7 +2505,16 @@ void compute_prime_constants(pa_plan *p, const uint32_t primes[NPRIMES]) {
         const uint32_t pr = primes[q];
         p->mix3.neg_half[q] = hmont((pr - 1) / 2, pr);
         p->mix3.h[q] = 0;
-        if (p->mix) {
+        for (int e = 0; e < 5; ++e) p->mix5.wi[q][e] = 0;
+        if (p->mix == 2) {
+            const uint32_t w5 = hpow(root_of_len(pr, p->m, 2), p->Nsub, pr);  // omega_N^(N/5) = omega_5
+            const uint32_t w5i = hinv(w5, pr);
+            uint32_t x = 1;
+            for (int e = 0; e < 5; ++e) {
+                p->mix5.wi[q][e] = hmont(x, pr);
+                x = hmul(x, w5i, pr);
+            }
+        } else if (p->mix) {
             const uint32_t w3 = hpow(root_of_len(pr, p->m, 1), p->Nsub, pr);  // omega_N^(N/3) = omega_3
             const uint32_t w3sq = hmul(w3, w3, pr);                         // omega_3^-1
             // (omega_3^-1 - omega_3^-2) / 2
@@ -2417,6 +2531,7 @@ struct ConstEntry {
     PrimeSet primes;
     CrtConst crt;
     Mix3Const mix3;
+    Mix5Const mix5;
 };
 
 }  // namespace
@@ -2434,18 +2549,19 @@ void init_prime_constants(pa_plan *p, const uint32_t primes[NPRIMES]) {
                 p->primes = e.primes;
                 p->crt = e.crt;
                 p->mix3 = e.mix3;
+                p->mix5 = e.mix5;
                 return;
             }
     }
     compute_prime_constants(p, primes);
-    ConstEntry e{{primes[0], primes[1], primes[2]}, p->m, p->mix, p->primes, p->crt, p->mix3};
+    ConstEntry e{{primes[0], primes[1], primes[2]}, p->m, p->mix, p->primes, p->crt, p->mix3, p->mix5};
     std::lock_guard<std::mutex> lock(mu);
     if (cache.size() < kMaxEntries) cache.push_back(e);
 }
 
 hipError_t launch_twiddles(pa_plan *p, hipStream_t st, uint32_t *hdr, uint32_t want) {
     const uint64_t N = p->N, n1 = 1ull << p->m1, n2 = 1ull << p->m2;
-    const uint32_t sub = p->mix ? 3u : 1u;  // omega_{N/sub} = omega_N^sub
+    const uint32_t sub = p->rf;  // omega_{N/sub} = omega_N^sub
     TwArgs t1f, t1i, t2f, t2i, Ff, Fi, Gi;
     for (int q = 0; q < NPRIMES; ++q) {
         const uint32_t pr = p->primes.c[q].p;
@@ -2470,8 +2586,8 @@ hipError_t launch_twiddles(pa_plan *p, hipStream_t st, uint32_t *hdr, uint32_t w
     hipLaunchKernelGGL(k_tw_four, dim3(blocks_for(N / TW4_RUN, 256), NPRIMES), dim3(256), 0, st, p->Wf, p->Wi,
                        p->m1, p->m2, sub, Ff, Fi, hdr, want);
     if (p->mix)
-        hipLaunchKernelGGL(k_tw_g3, dim3(blocks_for(3 * n1, 256), NPRIMES), dim3(256), 0, st, p->G3, p->m1, p->m2,
-                           Ff, Gi, hdr, want);
+        hipLaunchKernelGGL(k_tw_gx, dim3(blocks_for(p->rf * n1, 256), NPRIMES), dim3(256), 0, st, p->G3, p->rf, p->m1,
+                           p->m2, Ff, Gi, hdr, want);
     if (p->m2 == 12) {
         hipLaunchKernelGGL(k_tw_r16, dim3(blocks_for(R16_TW, 256), NPRIMES), dim3(256), 0, st, p->tw2f, p->R16f,
                            hdr, want);
@@ -2521,7 +2637,9 @@ static ColFwdArgs col_args(pa_plan *p, uint32_t mode) {
 
 // Column pass of any shape: one workgroup per (tile, array), first-step tasks
 // per thread as the tile needs (2^(m1 - 3 + c_lg) tasks, m1 + c_lg <= 14).
-template <int Stage, bool MIX>
+// RADIX: the length factor (1, 3 or 5; lengths 5 * 2^m have columns of at
+// most 256 rows).
+template <int Stage, int RADIX>
 static void launch_col_fwd_generic(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, unsigned zsplit,
                                    hipStream_t st) {
     const int step = Stage == STAGE_MMH ? SP_MMH_COL : SP_MH_COL;
@@ -2530,11 +2648,13 @@ static void launch_col_fwd_generic(pa_plan *p, const ColFwdArgs &cf, unsigned na
     const uint32_t ntask = (1u << (p->m1 - 3)) << cf.c_lg;
     // common tile shapes (2^m1 rows x 2^c_lg columns) with compile-time sizes
 #define PA_COL_FIXED(LGv, CLGv)                                                                              \
-    if (p->m1 == LGv && cf.c_lg == CLGv) {                                                                   \
-        constexpr int NT = 1 << (LGv - (ColR16<LGv, CLGv>::first ? 4 : 3) + CLGv); /* first-step tasks */    \
-        constexpr int T = NT <= COL_THREADS ? 1 : NT / COL_THREADS;                                          \
-        emit(p, step, PA_KERN(col_fwd, Stage, MIX, T, LGv, CLGv), grid, dim3(COL_THREADS), 0, cf, st);      \
-        return;                                                                                              \
+    if constexpr (RADIX != 5 || LGv <= 8) {                                                                  \
+        if (p->m1 == LGv && cf.c_lg == CLGv) {                                                               \
+            constexpr int NT = 1 << (LGv - (ColR16<LGv, CLGv>::first ? 4 : 3) + CLGv); /* first-step tasks */\
+            constexpr int T = NT <= COL_THREADS ? 1 : NT / COL_THREADS;                                      \
+            emit(p, step, PA_KERN(col_fwd, Stage, RADIX, T, LGv, CLGv), grid, dim3(COL_THREADS), 0, cf, st);\
+            return;                                                                                          \
+        }                                                                                                    \
     }
     PA_COL_FIXED(3, 4) PA_COL_FIXED(3, 7) PA_COL_FIXED(3, 8)
     PA_COL_FIXED(4, 4) PA_COL_FIXED(4, 6) PA_COL_FIXED(4, 7)
@@ -2543,18 +2663,19 @@ static void launch_col_fwd_generic(pa_plan *p, const ColFwdArgs &cf, unsigned na
     PA_COL_FIXED(7, 4) PA_COL_FIXED(8, 4) PA_COL_FIXED(10, 3) PA_COL_FIXED(10, 4)
 #undef PA_COL_FIXED
     if (ntask <= COL_THREADS)
-        emit(p, step, PA_KERN(col_fwd, Stage, MIX, 1), grid, dim3(COL_THREADS), col_lds, cf, st);
+        emit(p, step, PA_KERN(col_fwd, Stage, RADIX, 1), grid, dim3(COL_THREADS), col_lds, cf, st);
     else if (ntask <= 2 * COL_THREADS)
-        emit(p, step, PA_KERN(col_fwd, Stage, MIX, 2), grid, dim3(COL_THREADS), col_lds, cf, st);
+        emit(p, step, PA_KERN(col_fwd, Stage, RADIX, 2), grid, dim3(COL_THREADS), col_lds, cf, st);
     else if (ntask <= 4 * COL_THREADS)
-        emit(p, step, PA_KERN(col_fwd, Stage, MIX, 4), grid, dim3(COL_THREADS), col_lds, cf, st);
+        emit(p, step, PA_KERN(col_fwd, Stage, RADIX, 4), grid, dim3(COL_THREADS), col_lds, cf, st);
     else
-        emit(p, step, PA_KERN(col_fwd, Stage, MIX, 8), grid, dim3(COL_THREADS), col_lds, cf, st);
+        emit(p, step, PA_KERN(col_fwd, Stage, RADIX, 8), grid, dim3(COL_THREADS), col_lds, cf, st);
 }
 
 // zsplit (1 or 3) workgroups share a tile's transforms, each taking the
-// primes (and radix-3 branches) of its slice: more workgroups for passes with
-// few arrays, at the cost of unpacking the tile's limbs once per slice.
+// primes (and radix-3 or radix-5 branches) of its slice: more workgroups for
+// passes with few arrays, at the cost of unpacking the tile's limbs once per
+// slice.
 template <int Stage>
 static void launch_col_fwd(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, unsigned zsplit, hipStream_t st) {
     const unsigned ncol_tiles = 1u << (p->m2 - cf.c_lg);
@@ -2565,7 +2686,9 @@ static void launch_col_fwd(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, u
     const bool c10 = p->m1 == C10_LG && cf.c_lg == C10_CLG && (!p->mix || Stage == STAGE_MH);
     const int step = Stage == STAGE_MMH ? SP_MMH_COL : SP_MH_COL;
     const dim3 grid(ncol_tiles, narrays, zsplit);
-    if (c10 && p->mix)
+    if (p->rf == 5)  // columns of at most 256 rows
+        launch_col_fwd_generic<Stage, 5>(p, cf, narrays, zsplit, st);
+    else if (c10 && p->mix)
         emit(p, step, PA_KERN(col10_fwd, Stage, true), grid, dim3(COL_THREADS), 0, cf, st);
     else if (c10)
         emit(p, step, PA_KERN(col10_fwd, Stage, false), grid, dim3(COL_THREADS), 0, cf, st);
@@ -2574,9 +2697,9 @@ static void launch_col_fwd(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, u
     else if (c9)  // three primes per tile
         emit(p, step, PA_KERN(col9_fwd, Stage, false), grid, dim3(COL_THREADS), 0, cf, st);
     else if (p->mix)
-        launch_col_fwd_generic<Stage, true>(p, cf, narrays, zsplit, st);
+        launch_col_fwd_generic<Stage, 3>(p, cf, narrays, zsplit, st);
     else
-        launch_col_fwd_generic<Stage, false>(p, cf, narrays, zsplit, st);
+        launch_col_fwd_generic<Stage, 1>(p, cf, narrays, zsplit, st);
 }
 
 static RowArgs row_args(pa_plan *p, uint64_t npairs, const uint32_t *seed_side) {
@@ -2628,7 +2751,7 @@ static ColInvArgs colinv_args(pa_plan *p) {
 
 template <int Stage>
 static void launch_col_inv(pa_plan *p, const ColInvArgs &ci, hipStream_t st) {
-    const unsigned nsub = p->mix ? 3u : 1u;  // grid z: transform of the radix-3 split
+    const unsigned nsub = p->rf;  // grid z: transform of the radix-3 or radix-5 split
     const int step = Stage == STAGE_MMH ? SP_MMH_COLINV : SP_MH_COLINV;
     if (p->m1 == C9_LG && p->m2 >= C9_CLG)
         emit(p, step, PA_KERN(col9_inv, Stage), dim3(1u << (p->m2 - C9_CLG), NPRIMES, nsub), dim3(COL_THREADS), 0,
@@ -2748,7 +2871,30 @@ static hipError_t run_carry(pa_plan *p, DigitArgs A, uint32_t *out, uint64_t ndi
 // Coefficients [0, count) of the convolution for N = 3 * 2^m from the
 // residues in Cc, as word planes in C96 (with notones: also the RELOAD
 // status).  For N = 2^m the digit kernels reconstruct the coefficients.
+static void launch_crt5(pa_plan *p, uint64_t count, const uint32_t *notones, int step, hipStream_t st) {
+    Crt5Args A;
+    A.cc = p->Cc;
+    A.c96 = p->C96;
+    A.N = p->N;
+    A.Nsub = p->Nsub;
+    A.count = count;
+    A.m1 = p->m1;
+    A.m2 = p->m2;
+    A.gi = p->G3 + (size_t)3 * NPRIMES * 5 * ((size_t)1 << p->m1);  // after the three forward tables
+    A.P = p->primes;
+    A.K = p->crt;
+    A.X = p->mix5;
+    A.notones = notones;
+    A.k = notones ? p->k : 0;
+    A.status = p->status;
+    emit(p, step, PA_KERN0(crt5), dim3(blocks_for(count < p->Nsub ? count : p->Nsub, 256)), dim3(256), 0, A, st);
+}
+
 static void launch_crt3(pa_plan *p, uint64_t count, const uint32_t *notones, int step, hipStream_t st) {
+    if (p->rf == 5) {
+        launch_crt5(p, count, notones, step, st);
+        return;
+    }
     Crt3Args A;
     A.cc = p->Cc;
     A.c96 = p->C96;

@@ -189,7 +189,37 @@ def test_power_of_two_flag():
             assert binding.plan_query(n, r, B=B + 1, flags=binding.PA_FLAG_POW2_LENGTHS)[0] in (
                 binding.PA_ERR_INEXACT, binding.PA_ERR_LIMIT)
     assert mixed >= 15  # the rule still takes lengths 3 * 2^m (from 3 * 2^19 up) for many shapes
-    assert binding.plan_query(1000, 10, flags=4)[0] == binding.PA_ERR_ARG
+    assert binding.plan_query(1000, 10, flags=8)[0] == binding.PA_ERR_ARG  # unknown bit
+    for two in (3, 5, 6, 7):  # at most one length flag
+        assert binding.plan_query(1000, 10, flags=two)[0] == binding.PA_ERR_ARG
+
+
+def test_radix5_flag():
+    """PA_FLAG_RADIX5_LENGTHS: the shortest exact length 5 * 2^m (m <= 20,
+    columns of at most 256 rows) with its own primes (5 * 2^m | p - 1); the
+    default rule never takes it."""
+    rng = random.Random(15)
+    seen = 0
+    for _ in range(300):
+        r = int(2 ** rng.uniform(0, 26))
+        n = r + 1 + int(2 ** rng.uniform(0, 30))
+        st0, info0 = binding.plan_query(n, r)
+        st, info = binding.plan_query(n, r, flags=binding.PA_FLAG_RADIX5_LENGTHS)
+        if st0 == 0:
+            assert info0["len_factor"] in (1, 3)
+        if st != 0:
+            assert st in (binding.PA_ERR_LIMIT, binding.PA_ERR_INEXACT)
+            continue
+        seen += 1
+        N, m = info["N"], info["log2N"]
+        assert info["len_factor"] == 5 and N == 5 << m and m <= 20 and info["log2N1"] <= 8
+        assert N >= 2 * info["L"] - 1 and (m == 6 or (5 << (m - 1)) < 2 * info["L"] - 1)
+        assert all((p - 1) % N == 0 and p < 1 << 30 for p in info["primes"])
+        assert info["k"] * info["L"] * (2 ** info["B"] - 1) ** 2 < math.prod(info["primes"])
+    assert seen > 100
+    # the paper's 8e8-bit CV block: 2L - 1 = 0.62 * 2^23 fits 5 * 2^20 (1.02x) instead of 3 * 2^21 (1.22x)
+    st, info = binding.plan_query(800_000_000, 80_000_000, flags=binding.PA_FLAG_RADIX5_LENGTHS)
+    assert st == 0 and info["N"] == 5 << 20 and info["log2N1"] == 8
 
 
 def test_plan_errors():

@@ -227,6 +227,28 @@ def test_radix3_lengths_against_oracle(pa, gamma, k):
     assert np.array_equal(out3, out2)
 
 
+# (gamma, k) for lengths 5 * 2^m, m = 6 .. 20: column passes of 8 .. 256 rows
+# (compile-time tiles and the generic kernel), rows of 8 .. 4096 words.
+RADIX5_SHAPES = [(2203, 2), (4253, 3), (9689, 1), (19937, 2), (44497, 3), (86243, 2), (132049, 3),
+                 (756839, 2), (1257787, 3), (2976221, 2), (6972593, 1), (13466917, 1)]
+
+
+@pytest.mark.parametrize("gamma,k", RADIX5_SHAPES)
+def test_radix5_lengths_against_oracle(pa, gamma, k):
+    """Lengths N = 5 * 2^m (PA_FLAG_RADIX5_LENGTHS: radix-5 step fused into
+    the unpacking column pass, five transforms per tile and prime, and the
+    inverse radix-5 step fused into the reconstruction), ragged n, output and
+    both stage values against the oracle."""
+    n, r = k * gamma - 7, gamma // 3
+    st, g, kk = defn.plan_shape(n, r, gamma)
+    assert st == 0 and kk == k
+    info = pa.plan_query(n, r, gamma, flags=pa.PA_FLAG_RADIX5_LENGTHS)[1]
+    assert info["len_factor"] == 5, info
+    blk = synth.single_block(5 * gamma + k, n, r, g, kk)
+    check_block(pa, blk, label=f"radix-5 N={info['N']} m1={info['log2N1']} c={info['col_lg']} gamma={gamma} k={k}",
+                flags=pa.PA_FLAG_RADIX5_LENGTHS)
+
+
 @pytest.mark.parametrize("n,r", [(3 * 20996011 - 99, 14_000_000), (800_000_000, 80_000_000)])
 def test_radix3_against_power_of_two_lengths(pa, n, r):
     """Larger radix-3 shapes (3 * 2^19 with 128-row columns and 4096-word
@@ -427,7 +449,7 @@ def _digest(words):
     return hashlib.sha256(np.ascontiguousarray(words, dtype=np.uint64).tobytes()).hexdigest()
 
 
-@pytest.mark.parametrize("flags", [0, 1, 2])
+@pytest.mark.parametrize("flags", [0, 1, 2, 4])
 @pytest.mark.parametrize("name", ["single_block_2p20", "single_block_2p6e8", "paper_cv_block",
                                   "max_length_single_chunk", "len_2p22_single_chunk", "len_2p23_single_chunk",
                                   "cv_8e8_block", "corner_2p28_r03"])
@@ -435,13 +457,16 @@ def test_full_size_blocks_against_stored_oracle_digest(pa, name, flags):
     """Full-size blocks, in the launch configuration the benchmark times,
     against digests written by tests/golden/make_golden.py (oracle only);
     with flags = 1 or 2 (PA_FLAG_POW2_LENGTHS, PA_FLAG_RADIX3_LENGTHS) also on
-    the other length form than the plan rule's."""
+    the other length form than the plan rule's, and with flags = 4
+    (PA_FLAG_RADIX5_LENGTHS) on lengths 5 * 2^m where they exist (m <= 20)."""
     gold = json.load(open(os.path.join(HERE, "golden", "full_size.json")))[name]
     n, r = gold["n"], gold["r"]
     st, g, k = defn.plan_shape(n, r)
     assert (g, k) == (gold["gamma"], gold["k"])
-    if flags and pa.plan_query(n, r)[1]["len_factor"] == (1 if flags == 1 else 3):
+    if flags in (1, 2) and pa.plan_query(n, r)[1]["len_factor"] == (1 if flags == 1 else 3):
         pytest.skip("the plan rule already picks this length form")
+    if flags == 4 and pa.plan_query(n, r, flags=4)[0] != 0:
+        pytest.skip("no length 5 * 2^m with m <= 20 holds this product")
     blk = synth.single_block(gold["seed"], n, r, g, k)
     say(f"[case] full size {name} n={n} r={r} gamma={g} k={k} flags={flags}")
     plan = pa.Plan(n, r, flags=flags)
