@@ -143,9 +143,11 @@ def kernel_name(phase, info):
     by the library's launch rule: rows of 4096 words run k_row16; columns of
     512 rows in tiles of 16 columns run k_col9_*; columns of 1024 rows in
     tiles of 8 run k_col10_* (the forward key-chunk pass of lengths 3 * 2^m
-    excepted); everything else the generic kernels."""
+    excepted); everything else, and every forward pass of lengths 5 * 2^m,
+    the generic kernels (named here by stage and radix alone)."""
     stage = 0 if phase.startswith("mmh") else 1
-    m1, m2, mix = info["log2N1"], info["log2N2"], info["len_factor"] == 3
+    m1, m2, rf = info["log2N1"], info["log2N2"], info["len_factor"]
+    mix = rf == 3
     if phase.endswith("_row"):
         return f"k_row16<{stage}>" if m2 == 12 else f"k_row<{stage}>"
     if phase.endswith("_colinv"):
@@ -157,11 +159,11 @@ def kernel_name(phase, info):
     fit = lambda c: min(c, m2, 14 - m1)  # noqa: E731  (the column-tile width rule)
     c_lg = info["col_lg"] if stage == 0 else fit(3 if m1 == 10 else 4)
     flag = "true" if mix else "false"
-    if m1 == 10 and c_lg == 3 and (not mix or stage == 1):
+    if rf != 5 and m1 == 10 and c_lg == 3 and (not mix or stage == 1):
         return f"k_col10_fwd<{stage}, {flag}>"
-    if m1 == 9 and c_lg == 4:
+    if rf != 5 and m1 == 9 and c_lg == 4:
         return f"k_col9_fwd<{stage}, {flag}>"
-    return f"k_col_fwd<{stage}, {flag}>"
+    return f"k_col_fwd<{stage}, {rf}>"
 
 
 # Peak butterfly rate of the VALU for this arithmetic: a radix-2 butterfly
@@ -460,14 +462,16 @@ def bench_rule(args):
     for (g, k), (n, r) in sorted(classes.items()):
         _, rule = pa.plan_query(n, r)
         rec = {"gamma": g, "k": k, "n": n, "r": r,
-               "rule": {"N": rule["N"], "B": rule["B"], "form": "radix3" if rule["len_factor"] == 3 else "pow2"}}
-        for label, flags in (("pow2", pa.PA_FLAG_POW2_LENGTHS), ("radix3", pa.PA_FLAG_RADIX3_LENGTHS)):
+               "rule": {"N": rule["N"], "B": rule["B"],
+                        "form": {1: "pow2", 3: "radix3", 5: "radix5"}[rule["len_factor"]]}}
+        for label, flags in (("pow2", pa.PA_FLAG_POW2_LENGTHS), ("radix3", pa.PA_FLAG_RADIX3_LENGTHS),
+                             ("radix5", pa.PA_FLAG_RADIX5_LENGTHS)):
             st, info = pa.plan_query(n, r, flags=flags)
             if st != 0:
                 continue
             best, ms = pa.plan_tune(n, r, reps=5, flags=flags)
             rec[label] = {"N": info["N"], "ms": round(ms, 4), "B": best["B"], "col_lg": best["col_lg"]}
-        forms = [rec[f]["ms"] for f in ("pow2", "radix3") if f in rec]
+        forms = [rec[f]["ms"] for f in ("pow2", "radix3", "radix5") if f in rec]
         rec["agree"] = rec[rec["rule"]["form"]]["ms"] <= 1.03 * min(forms)
         agree += rec["agree"]
         rows.append(rec)
@@ -484,11 +488,11 @@ def bench_lengths(args):
     """Blocks hashed with transform lengths 3 * 2^m (PA_FLAG_RADIX3_LENGTHS),
     2^m (PA_FLAG_POW2_LENGTHS) and, where one holds the product (m <= 20),
     5 * 2^m (PA_FLAG_RADIX5_LENGTHS), same inputs; outputs must agree.  Two
-    product lengths 2L - 1 fall just above a power of two, where the plan
-    rule takes 3 * 2^m: the paper's largest CV block (n = 8e8, r = n/10:
-    0.62 * 2^23) and the 2^32-bit block (r = 2^27: 0.52 * 2^24); one falls
-    below, where it takes 2^m: n = 5e8, r = n/10 (0.86 * 2^22, columns of
-    1024 rows).  `rule` names the plan rule's form."""
+    product lengths 2L - 1 fall just above a power of two: the paper's
+    largest CV block (n = 8e8, r = n/10: 0.62 * 2^23, where the plan rule
+    takes 5 * 2^20) and the 2^32-bit block (r = 2^27: 0.52 * 2^24, where it
+    takes 3 * 2^22); one falls below, where it takes 2^m: n = 5e8, r = n/10
+    (0.86 * 2^22, columns of 1024 rows).  `rule` names the plan rule's form."""
     import torch
     import paper_2105_13678_amd as pa
     from paper_2105_13678_amd import synth
@@ -529,7 +533,7 @@ def bench_lengths(args):
             log(f"[bench] lengths n={n} r={r} {label}: N={plan.N} B={plan.B} {ms:.3f} ms")
             plan.close()
         row = {"n": n, "r": r, "gamma": info["gamma"], "k": info["k"],
-               "rule": "radix3" if info["len_factor"] == 3 else "pow2"}
+               "rule": {1: "pow2", 3: "radix3", 5: "radix5"}[info["len_factor"]]}
         if len(res) >= 2:
             outs = [res[lab]["out"] for lab in res]
             row["outputs_equal"] = all(torch.equal(outs[0], o) for o in outs[1:])
@@ -543,7 +547,7 @@ def bench_lengths(args):
         rows.append(row)
         del key, a, b, c
         torch.cuda.empty_cache()
-    rec = {"metric": "PA input throughput (Mbit/s) with transform lengths 3 * 2^m vs 2^m, bit-exact",
+    rec = {"metric": "PA input throughput (Mbit/s) with transform lengths 2^m, 3 * 2^m and 5 * 2^m, bit-exact",
            "unit": "Mbit/s", "n_gpus": 1, "steps": K, "warmup": Wm, "higher_is_better": True,
            "data": "synthetic", "blocks": rows}
     print(json.dumps(rec), flush=True)

@@ -63,10 +63,10 @@ typedef enum pa_status {
 
 /* Plan request.  gamma = 0 picks the smallest Mersenne exponent above r.
  * The product of two L-limb numbers needs a cyclic convolution of length
- * N >= 2L - 1; N is a power of two or three times one (a radix-3 step over
- * three power-of-two transforms), whichever is cheaper among the exact
- * choices; lengths five times a power of two (a radix-5 step over five
- * power-of-two transforms, N <= 5 * 2^20) are taken only on request.
+ * N >= 2L - 1; N is a power of two, three times one or five times one (a
+ * radix-3 or radix-5 step over three or five power-of-two transforms;
+ * N <= 3 * 2^23 and N <= 5 * 2^20), whichever is cheapest among the exact
+ * choices by the library's cost model.
  * B = 0 picks the limb width (at most 32 bits) that gives the cheapest exact
  * transform, the widest among equals; otherwise 8 <= B <= 32.  At most one
  * length flag may be set.  The output never depends on B or N. */

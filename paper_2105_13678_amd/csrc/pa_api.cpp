@@ -26,6 +26,14 @@ constexpr uint64_t kMaxK = 4096;
 // butterfly count in the plan rule (see derive_plan).
 constexpr uint32_t kMinLog2Mix = 19;
 constexpr double kMixSmallCost = 1.6;
+// Lengths 5 * 2^m: their radix-5 passes (five inputs combined per column
+// element, 16 products per coefficient in the reconstruction) count as
+// kMix5Extra passes over N, and below 5 * 2^19 (generic column kernels only)
+// kMix5SmallCost times the whole (device timings, candidates round robin:
+// 5 * 2^19 and 5 * 2^20 take 0.92x and 0.89x the time of the 6/5 longer
+// 3 * 2^20 and 3 * 2^21, 5 * 2^14 1.4x the time of the 8/5 longer 2^17).
+constexpr double kMix5Extra = 3.0;
+constexpr double kMix5SmallCost = 2.0;
 constexpr double kLog2Of3 = 1.5849625007211562;
 constexpr double kLog2Of5 = 2.321928094887362;
 constexpr uint32_t kMinLog2N = 6;
@@ -144,17 +152,18 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     pa_status st = plan_shape(prm, &gamma, &k, &B);
     if (st != PA_OK) return st;
     if (k > kMaxK) return PA_ERR_LIMIT;
-    // length forms tried: the flagged one, else 2^m and 3 * 2^m (5 * 2^m only on request)
+    // length forms tried: the flagged one, else all three
     const uint32_t mx_lo = (prm->flags & PA_FLAG_RADIX5_LENGTHS) ? 2u : (prm->flags & PA_FLAG_RADIX3_LENGTHS) ? 1u : 0u;
-    const uint32_t mx_hi = (prm->flags & PA_FLAG_RADIX5_LENGTHS) ? 3u : (prm->flags & PA_FLAG_POW2_LENGTHS) ? 1u : 2u;
-    // Candidate lengths for limb width b: the shortest 2^m and 3 * 2^m that
-    // hold the product, each with its own primes.  Cost model: butterflies
-    // N log2 N, plus one pass over N for the radix-3 step; lengths 3 * 2^m
-    // with m < kMinLog2Mix count kMixSmallCost times that (timed on the
-    // device, candidates round robin: at 3 * 2^10 ... 3 * 2^16 they take
-    // 1.06 - 1.24x the time of the 4/3 longer power of two, at 3 * 2^19 the
-    // same, at 3 * 2^20 and 3 * 2^21 0.92x and 0.56x).  `seen` records whether
-    // some candidate length was within the supported range.
+    const uint32_t mx_hi = (prm->flags & PA_FLAG_RADIX3_LENGTHS) ? 2u : (prm->flags & PA_FLAG_POW2_LENGTHS) ? 1u : 3u;
+    // Candidate lengths for limb width b: the shortest 2^m, 3 * 2^m and
+    // 5 * 2^m that hold the product, each with its own primes.  Cost model:
+    // butterflies N log2 N, plus one pass over N for the radix-3 step
+    // (kMix5Extra for the radix-5 step); lengths 3 * 2^m with m < kMinLog2Mix
+    // count kMixSmallCost times that (timed on the device, candidates round
+    // robin: at 3 * 2^10 ... 3 * 2^16 they take 1.06 - 1.24x the time of the
+    // 4/3 longer power of two, at 3 * 2^19 the same, at 3 * 2^20 and 3 * 2^21
+    // 0.92x and 0.56x), lengths 5 * 2^m kMix5SmallCost times.  `seen` records
+    // whether some candidate length was within the supported range.
     bool seen = false;
     auto choose = [&](uint32_t b, uint32_t *m_out, uint32_t *mix_out, double *cost_out) {
         const uint64_t Lb = (gamma + b - 1) / b;
@@ -168,7 +177,9 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
             if (!exact(k, Lb, b, *T)) continue;
             const double Nl = (double)((uint64_t)f << mb);
             const double lgN = mb + (mx == 2 ? kLog2Of5 : mx ? kLog2Of3 : 0.0);
-            const double cost = Nl * (lgN + (mx ? 1.0 : 0.0)) * (mx && mb < kMinLog2Mix ? kMixSmallCost : 1.0);
+            const double extra = mx == 2 ? kMix5Extra : mx ? 1.0 : 0.0;
+            const double small = mb >= kMinLog2Mix ? 1.0 : mx == 2 ? kMix5SmallCost : mx ? kMixSmallCost : 1.0;
+            const double cost = Nl * (lgN + extra) * small;
             if (!ok || cost < *cost_out) {
                 ok = true;
                 *m_out = mb;

@@ -77,7 +77,7 @@ pa_status pa_plan_tune(const pa_params *params, int hip_device, uint32_t reps, p
     // column-tile width and its neighbours (or the requested tile width)
     std::vector<pa_params> cands;
     std::vector<pa_plan> shapes;
-    const uint32_t forms[2] = {PA_FLAG_POW2_LENGTHS, PA_FLAG_RADIX3_LENGTHS};
+    const uint32_t forms[3] = {PA_FLAG_POW2_LENGTHS, PA_FLAG_RADIX3_LENGTHS, PA_FLAG_RADIX5_LENGTHS};
     for (uint32_t f : forms) {
         if (params->flags && params->flags != f) continue;
         pa_params q = *params;

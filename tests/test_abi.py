@@ -53,9 +53,10 @@ def test_plan_rule_matches_oracle():
     (1 << 20, (1 << 20) // 10, 0, 110503, 10, 32, 3454, 1 << 13),
     (260_000_000, 26_000_000, 0, 30402457, 9, 32, 950077, 1 << 21),
     (10 * 25964951, 25237932, 0, 25964951, 10, 32, 811405, 1 << 21),
-    # the paper's largest CV block (8e8 bits, r = n/10): 3 * 2^21 instead of 2^23
-    (800_000_000, 80_000_000, 0, 82589933, 10, 32, 2580936, 3 << 21),
+    # the paper's largest CV block (8e8 bits, r = n/10): 5 * 2^20 instead of 2^23 (or 3 * 2^21)
+    (800_000_000, 80_000_000, 0, 82589933, 10, 32, 2580936, 5 << 20),
     (800_000_000, 80_000_000, 1, 82589933, 10, 32, 2580936, 1 << 23),
+    (800_000_000, 80_000_000, 2, 82589933, 10, 32, 2580936, 3 << 21),
     # the largest block: 3 * 2^22 at B = 31 instead of 2^24 at B = 29
     (1 << 32, 1 << 27, 0, 136279841, 32, 31, 4396124, 3 << 22),
     (1 << 32, 1 << 27, 1, 136279841, 32, 29, 4699305, 1 << 24),
@@ -66,7 +67,7 @@ def test_derived_shapes(n, r, flags, gamma, k, B, L, N):
     assert (info["gamma"], info["k"], info["B"], info["L"], info["N"]) == (gamma, k, B, L, N)
     f = info["len_factor"]
     assert info["nprimes"] == 3 and info["log2N1"] + info["log2N2"] == info["log2N"]
-    assert N == f << info["log2N"] and f in (1, 3) and (flags == 0 or f == 1)
+    assert N == f << info["log2N"] and f in (1, 3, 5) and (flags == 0 or f == {1: 1, 2: 3, 4: 5}[flags])
     # the primes: the three largest below 2^30 with f * 2^max(log2N, 20 or 18) | p - 1
     assert sorted(info["primes"]) == sorted(largest_ntt_primes(max(info["log2N"], 20 if f == 1 else 18), f=f))
     # exactness: k L (2^B - 1)^2 below the product of the three NTT primes
@@ -136,11 +137,13 @@ def test_prime_triples_are_the_largest_with_the_roots():
 
 def length_cost(info) -> float:
     """The plan rule's cost of a transform length: N log2 N butterflies, plus
-    one pass over N for the radix-3 step of the lengths 3 * 2^m, which count
-    1.6 times below 3 * 2^19 (measured slower there)."""
-    N = info["N"]
-    mix = info["len_factor"] == 3
-    return N * (math.log2(N) + (1.0 if mix else 0.0)) * (1.6 if mix and info["log2N"] < 19 else 1.0)
+    one pass over N for the radix-3 step of the lengths 3 * 2^m (three for
+    the radix-5 step of 5 * 2^m), which count 1.6 (2.0) times below
+    3 * 2^19 (5 * 2^19) (measured slower there)."""
+    N, f = info["N"], info["len_factor"]
+    extra = {1: 0.0, 3: 1.0, 5: 3.0}[f]
+    small = 1.0 if f == 1 or info["log2N"] >= 19 else (1.6 if f == 3 else 2.0)
+    return N * (math.log2(N) + extra) * small
 
 
 def test_auto_limb_width_is_cheapest_exact():
@@ -181,14 +184,14 @@ def test_power_of_two_flag():
         assert (st == 0) == (st0 == 0)
         if st != 0:
             continue
-        mixed += info0["len_factor"] == 3
+        mixed += info0["len_factor"] != 1
         assert info["len_factor"] == 1 and info["N"] == 1 << info["log2N"]
         assert length_cost(info0) <= length_cost(info)
         B = info["B"]
         if B < 32:
             assert binding.plan_query(n, r, B=B + 1, flags=binding.PA_FLAG_POW2_LENGTHS)[0] in (
                 binding.PA_ERR_INEXACT, binding.PA_ERR_LIMIT)
-    assert mixed >= 15  # the rule still takes lengths 3 * 2^m (from 3 * 2^19 up) for many shapes
+    assert mixed >= 15  # the rule still takes lengths 3 * 2^m and 5 * 2^m (from 2^19 up) for many shapes
     assert binding.plan_query(1000, 10, flags=8)[0] == binding.PA_ERR_ARG  # unknown bit
     for two in (3, 5, 6, 7):  # at most one length flag
         assert binding.plan_query(1000, 10, flags=two)[0] == binding.PA_ERR_ARG
@@ -196,8 +199,7 @@ def test_power_of_two_flag():
 
 def test_radix5_flag():
     """PA_FLAG_RADIX5_LENGTHS: the shortest exact length 5 * 2^m (m <= 20,
-    columns of at most 256 rows) with its own primes (5 * 2^m | p - 1); the
-    default rule never takes it."""
+    columns of at most 256 rows) with its own primes (5 * 2^m | p - 1)."""
     rng = random.Random(15)
     seen = 0
     for _ in range(300):
@@ -206,7 +208,7 @@ def test_radix5_flag():
         st0, info0 = binding.plan_query(n, r)
         st, info = binding.plan_query(n, r, flags=binding.PA_FLAG_RADIX5_LENGTHS)
         if st0 == 0:
-            assert info0["len_factor"] in (1, 3)
+            assert info0["len_factor"] in (1, 3, 5)
         if st != 0:
             assert st in (binding.PA_ERR_LIMIT, binding.PA_ERR_INEXACT)
             continue

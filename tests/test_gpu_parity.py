@@ -257,11 +257,12 @@ def test_radix3_against_power_of_two_lengths(pa, n, r):
     output and both stage values."""
     st, g, k = defn.plan_shape(n, r)
     assert st == 0
-    i3, i2 = pa.plan_query(n, r)[1], pa.plan_query(n, r, flags=pa.PA_FLAG_POW2_LENGTHS)[1]
-    assert i3["len_factor"] == 3 and i2["len_factor"] == 1 and i3["N"] < i2["N"]  # the rule takes 3 * 2^m
+    i3 = pa.plan_query(n, r, flags=pa.PA_FLAG_RADIX3_LENGTHS)[1]
+    i2 = pa.plan_query(n, r, flags=pa.PA_FLAG_POW2_LENGTHS)[1]
+    assert i3["len_factor"] == 3 and i2["len_factor"] == 1 and i3["N"] < i2["N"]
     blk = synth.single_block(5, n, r, g, k)
     res = []
-    for flags in (0, pa.PA_FLAG_POW2_LENGTHS):
+    for flags in (pa.PA_FLAG_RADIX3_LENGTHS, pa.PA_FLAG_POW2_LENGTHS):
         say(f"[case] radix-3 vs power-of-two n={n} r={r} gamma={g} k={k} flags={flags}")
         plan = pa.Plan(n, r, flags=flags)
         try:
@@ -305,7 +306,7 @@ def test_tuned_plans_match(pa):
         st, g, k = defn.plan_shape(n, r)
         say(f"[case] tune n={n} r={r}")
         best, ms = pa.plan_tune(n, r, reps=2)
-        assert best["B"] >= 8 and best["flags"] in (1, 2) and best["col_lg"] >= 1 and ms > 0
+        assert best["B"] >= 8 and best["flags"] in (1, 2, 4) and best["col_lg"] >= 1 and ms > 0
         info = pa.plan_query(n, r, B=best["B"], flags=best["flags"], col_lg=best["col_lg"])[1]
         assert info["k"] * info["L"] * (2 ** info["B"] - 1) ** 2 < math.prod(info["primes"])
         blk = synth.single_block(77, n, r, g, k)
@@ -456,17 +457,17 @@ def _digest(words):
 def test_full_size_blocks_against_stored_oracle_digest(pa, name, flags):
     """Full-size blocks, in the launch configuration the benchmark times,
     against digests written by tests/golden/make_golden.py (oracle only);
-    with flags = 1 or 2 (PA_FLAG_POW2_LENGTHS, PA_FLAG_RADIX3_LENGTHS) also on
-    the other length form than the plan rule's, and with flags = 4
-    (PA_FLAG_RADIX5_LENGTHS) on lengths 5 * 2^m where they exist (m <= 20)."""
+    with flags = 1, 2 or 4 (PA_FLAG_POW2_LENGTHS, PA_FLAG_RADIX3_LENGTHS,
+    PA_FLAG_RADIX5_LENGTHS) also on the length forms other than the plan
+    rule's (5 * 2^m where one holds the product, m <= 20)."""
     gold = json.load(open(os.path.join(HERE, "golden", "full_size.json")))[name]
     n, r = gold["n"], gold["r"]
     st, g, k = defn.plan_shape(n, r)
     assert (g, k) == (gold["gamma"], gold["k"])
-    if flags in (1, 2) and pa.plan_query(n, r)[1]["len_factor"] == (1 if flags == 1 else 3):
-        pytest.skip("the plan rule already picks this length form")
     if flags == 4 and pa.plan_query(n, r, flags=4)[0] != 0:
         pytest.skip("no length 5 * 2^m with m <= 20 holds this product")
+    if flags and pa.plan_query(n, r)[1]["len_factor"] == {1: 1, 2: 3, 4: 5}[flags]:
+        pytest.skip("the plan rule already picks this length form")
     blk = synth.single_block(gold["seed"], n, r, g, k)
     say(f"[case] full size {name} n={n} r={r} gamma={g} k={k} flags={flags}")
     plan = pa.Plan(n, r, flags=flags)

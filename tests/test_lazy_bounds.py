@@ -16,14 +16,15 @@ composition the kernels use with residues at the top of their ranges:
   pointwise products, the Chinese-remainder value).
 
 Compositions modelled (each named after its kernel): the unpacking step of
-the forward column pass (both length forms), the radix-2/4/8/16 forward DFTs
+the forward column pass (all three length forms), the radix-2/4/8/16 forward DFTs
 with and without the zero-upper-half first stage and fused step twiddles,
 the inverse DFTs with and without fused step twiddles, the row passes'
 multiply-accumulate (64-bit pending products reduced once per three pairs in
 the 4096-point row kernel; Montgomery products accumulated per pair in the
 generic one, whose pair groups are then summed), the four-step twiddles on
 load and store, the canonicalisation at the end of the inverse column pass,
-the inverse radix-3 step of the lengths 3 * 2^m and Garner's reconstruction.
+the inverse radix-3 and radix-5 steps of the lengths 3 * 2^m and 5 * 2^m and
+Garner's reconstruction.
 """
 import os
 import random
@@ -39,10 +40,10 @@ M64 = 1 << 64
 
 
 def table_primes():
-    """Every prime of both prime tables of the library's internal header."""
+    """Every prime of the library's prime tables (lengths 2^m, 3 * 2^m, 5 * 2^m)."""
     text = open(INTERNAL).read()
     primes = set()
-    for body in re.findall(r"PRIME_TRIPLES(?:_3)?\[\]\s*=\s*\{(.*?)\};", text, flags=re.S):
+    for body in re.findall(r"PRIME_TRIPLES(?:_3|_5)?\[\]\s*=\s*\{(.*?)\};", text, flags=re.S):
         primes.update(int(x) for x in re.findall(r"(\d+)u", body))
     assert len(primes) >= 10
     return sorted(primes)
@@ -288,6 +289,14 @@ def test_column_unpack_and_row_passes(p):
         for g0, g1 in ((p - 1, p - 1), (rng.randrange(p), rng.randrange(p))):
             s = F.red2(F.add(F.mont(V(x, M32), V(g0, p)), F.mont(V(x1, M32), V(g1, p))))
             assert s.hi <= 2 * p
+    # N = 5 * 2^m: three row-twiddled limbs (the third on rows < N1/2), the
+    # first two summed and reduced, then the third added and reduced
+    for x, x1, x2 in ((M32 - 1, M32 - 1, M32 - 1), (0, M32 - 1, M32 - 1), (M32 - 1, 0, 0)):
+        for g0, g1, g2 in ((p - 1, p - 1, p - 1), (rng.randrange(p), rng.randrange(p), rng.randrange(p))):
+            s = F.red2(F.add(F.mont(V(x, M32), V(g0, p)), F.mont(V(x1, M32), V(g1, p))))
+            s = F.red2(F.add(s, F.mont(V(x2, M32), V(g2, p))))
+            assert s.hi <= 2 * p
+            assert s.v % p == (x * g0 + x1 * g1 + x2 * g2) * F.rinv % p
     # 4096-point row kernel: four-step twiddle on load, three radix-16 steps
     # (two with step twiddles), raw products pending, reduced once per three pairs
     for xs in extreme_inputs(F, 2 * p, 16, rng):
@@ -346,6 +355,32 @@ def test_inverse_radix3_step(p):
             x1 = F.canon(F.red2(F.add(S0, F.red2(F.add(a, d)))))
             x2 = F.canon(F.red2(F.add(S0, F.red2(F.sub2p(a, d)))))
             assert max(x0.hi, x1.hi, x2.hi) <= p
+
+
+@pytest.mark.parametrize("p", PRIMES)
+def test_inverse_radix5_step(p):
+    """The reconstruction kernel's inverse radix-5 step on canonical residues
+    s_k0: u_0 = s_0, u_k0 = s_k0 * gi_k0 (Montgomery, k0 > 0), then
+    x_n0 = u_0 + sum_(k0 > 0) u_k0 * w^(k0 n0 mod 5) (w^0 taken as u_k0 itself
+    for n0 = 0), each partial sum reduced below 2p, canonical at the end."""
+    F = Field(p)
+    rng = random.Random(p + 5)
+    for ss in ([p - 1] * 5, [0, p - 1, 0, p - 1, 0], [p - 1, 0, 0, 0, p - 1], [rng.randrange(p) for _ in range(5)]):
+        for gi in ([p - 1] * 5, [rng.randrange(p) for _ in range(5)]):
+            wi = [V(rng.randrange(p) if e else F.one, p) for e in range(5)]
+            wi[1] = V(p - 1, p)
+            S = [V(x, p) for x in ss]
+            u = [S[0]] + [F.mont(S[k0], V(gi[k0], p)) for k0 in range(1, 5)]
+            assert all(t.hi <= 2 * p for t in u)
+            for n0 in range(5):
+                acc = u[0]
+                want = u[0].v
+                for k0 in range(1, 5):
+                    term = F.mont(u[k0], wi[(k0 * n0) % 5]) if n0 else u[k0]
+                    acc = F.red2(F.add(acc, term))
+                    want += term.v
+                x = F.canon(acc)
+                assert x.hi <= p and x.v == want % p
 
 
 def test_garner_at_the_corners():
