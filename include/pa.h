@@ -372,7 +372,7 @@ pa_status pa_poll(pa_server *server, uint64_t ticket, pa_status *result, pa_timi
 /* Phases of the per-block launch sequence, for pa_plan_read_profile.  Each
  * of the NTT phases is exactly one kernel launch. */
 typedef enum pa_phase {
-    PA_PH_PROLOGUE = 0,   /* seed checks, flag reset                         */
+    PA_PH_PROLOGUE = 0,   /* no launch (the seed checks run in the fold); 0   */
     PA_PH_MMH_COL = 1,    /* unpack + forward column pass of 2k arrays, reload check */
     PA_PH_MMH_ROW = 2,    /* row pass: k pairs forward, multiply-accumulate, inverse */
     PA_PH_MMH_COLINV = 3, /* inverse column pass -> convolution coefficients */

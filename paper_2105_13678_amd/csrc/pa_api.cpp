@@ -287,7 +287,8 @@ pa_status derive_plan(const pa_params *prm, pa_plan *p, PlanLayout *lay) {
     lay->oY = carve(L * 4);
     lay->oU = carve(L * 4);
     lay->oAgg = carve(2 * p->ntiles_max * sizeof(pa::CFn));  // fold and wrap chains
-    lay->oNo = carve(k * 4);
+    lay->oNo = carve((k << p->m2) * 4);  // reload flags per key chunk and column tile (at most 2^m2)
+    lay->oTf = carve(p->ntiles_max * 4);
     lay->oSt = carve(4 * 4);
     lay->oSo = carve(4 * 4);
     lay->scratch_bytes = off;
@@ -318,6 +319,7 @@ void bind_scratch(pa_plan *p, void *scratch, const PlanLayout &lay) {
     p->agg_w = p->agg + p->ntiles_max;
     p->notones = (uint32_t *)(b + lay.oNo);
     p->status = (uint32_t *)(b + lay.oSt);
+    p->tflags = (uint32_t *)(b + lay.oTf);
     p->status_out = (uint32_t *)(b + lay.oSo);
 }
 
@@ -340,10 +342,11 @@ pa_status enqueue_hash(pa_plan *p, const uint64_t *key, const uint64_t *a, const
                        const uint64_t *c, uint64_t *out, uint32_t *d_status, uint64_t *y_out,
                        uint64_t *U_out, hipStream_t st) {
     if (!p || !key || !a || !b || !c || !out) return PA_ERR_ARG;
-    hipError_t e = pa::launch_prologue(p, a, b, c, st);
-    if (e == hipSuccess) e = pa::launch_mmh(p, key, a, st);
-    if (e == hipSuccess) e = pa::launch_fold(p, st);
+    hipError_t e = pa::launch_mmh(p, key, a, st);
+    if (e == hipSuccess) e = pa::launch_fold(p, pa::Seeds{a, b, c}, st);
     if (e == hipSuccess) e = pa::launch_mh(p, b, c, out, d_status, st);
+    // y as an output: the second fold's general case, if flagged, after the MH stage
+    if (e == hipSuccess && y_out && pa::wrap_inline(p)) e = pa::launch_wrap(p, st);
     if (e == hipSuccess && (y_out || U_out)) e = pa::launch_finish(p, y_out, U_out, st);
     if (e != hipSuccess) {
         (void)hipGetLastError();

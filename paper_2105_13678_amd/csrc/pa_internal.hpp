@@ -116,8 +116,7 @@ constexpr uint32_t R16_TW = 16 * 256 + 16 * 16;  // words per prime of the row-k
 // block's launches with their step and runs every step of all blocks as
 // multi-block launches, in this order.
 enum Step : int {
-    SP_PROLOGUE = 0,
-    SP_MMH_COL,
+    SP_MMH_COL = 0,
     SP_MMH_ROW,
     SP_MMH_COLINV,
     SP_FOLD_CRT3,
@@ -148,7 +147,7 @@ struct KLaunch {
     alignas(16) unsigned char args[KARGS_MAX];
 };
 
-// Device status flag bits (written by the prologue and status kernels).
+// Device status flag bits (written by the fold's reconstruction kernel).
 constexpr uint32_t ST_SEED_RANGE = 1u;
 constexpr uint32_t ST_B_EVEN = 2u;
 constexpr uint32_t ST_RELOAD = 4u;
@@ -193,7 +192,8 @@ struct pa_plan {
                         // (bits 0-31, 32-63, 64-95); for N = 2^m the digit kernels reconstruct them
     pa::CFn *agg;       // carry functions of CARRY_TILE-digit tiles
     pa::CFn *agg_w;     // the same for the wrap chain (second fold)
-    uint32_t *notones;  // k flags: chunk i has a limb that is not all ones
+    uint32_t *tflags;   // per first-fold tile: its limbs in [min(32, L - 1), L) all ones
+    uint32_t *notones;  // k x 2^m2 words: tile x of key chunk i saw a limb that is not all ones (i * tiles + x)
     uint32_t *status;   // seed/reload flags
     uint32_t *status_out;  // final flags of the last call (pa_hash reads it back)
     uint32_t *tw1f, *tw1i;  // per prime: omega_{N1}^+-j, j < N1 (Montgomery form)
@@ -224,7 +224,7 @@ namespace pa {
 // [0, scratch_bytes), the read-only twiddle tables (which depend only on the
 // transform length) the following table_bytes.
 struct PlanLayout {
-    size_t oX, oC, oC96, oT, oS, oY, oU, oAgg, oNo, oSt, oSo;
+    size_t oX, oC, oC96, oT, oS, oY, oU, oAgg, oNo, oSt, oSo, oTf;
     size_t oT1, oT2, oW, oR16, oG3;
     size_t scratch_bytes, table_bytes, total;
 };
@@ -266,10 +266,18 @@ void init_prime_constants(pa_plan *p, const uint32_t primes[NPRIMES]);
 // With hdr (a device word): skip the build when *hdr == want, else build and
 // then set *hdr = want (tables kept in memory that outlives one call).
 hipError_t launch_twiddles(pa_plan *p, hipStream_t st, uint32_t *hdr = nullptr, uint32_t want = 0);
-hipError_t launch_prologue(pa_plan *p, const uint64_t *a, const uint64_t *b, const uint64_t *c,
-                           hipStream_t st);
 hipError_t launch_mmh(pa_plan *p, const uint64_t *key, const uint64_t *a, hipStream_t st);
-hipError_t launch_fold(pa_plan *p, hipStream_t st);
+// The seeds of a hash call (device words), for the status checks of the fold.
+struct Seeds {
+    const uint64_t *a, *b, *c;
+};
+hipError_t launch_fold(pa_plan *p, const Seeds &seeds, hipStream_t st);
+// The second fold's general case (a no-op unless the first fold flagged it):
+// recomputes y.  launch_fold runs it unless wrap_inline(p); with the inline
+// form the MH stage corrects for the rare case itself and y is recomputed
+// only where y is an output (pa_hash_stages), after the MH stage.
+bool wrap_inline(const pa_plan *p);
+hipError_t launch_wrap(pa_plan *p, hipStream_t st);
 // The MH stage ends with the output extraction (z into out, flags into d_status,
 // or the plan's own status word when d_status is null).
 hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, uint64_t *out, uint32_t *d_status,

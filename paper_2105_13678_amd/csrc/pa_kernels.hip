@@ -271,41 +271,40 @@ __global__ void k_tw_r16(const uint32_t *tw, uint32_t *dst, const uint32_t *hdr,
 
 // ------------------------------------------------------------------ status
 
-// Clears the chunk flags and checks the seeds: any bit >= gamma in a seed
-// word -> SEED_RANGE; even b -> B_EVEN (MH needs gcd(b, 2) = 1).
-struct PrologueArgs {
+// The status of a hash (Alg. 1, Sec. 3.1), taken by the first workgroup of
+// the fold's reconstruction kernel: any bit >= gamma in a seed word ->
+// SEED_RANGE; even b -> B_EVEN (MH needs gcd(b, 2) = 1); a key chunk none of
+// whose column tiles saw a limb that is not all ones -> RELOAD.  The tile
+// flags are written, 0 or 1, by every workgroup of the key-chunk column pass,
+// so no flag needs clearing before a hash.
+struct StatusArgs {
     const uint64_t *a, *b, *c;
     uint64_t k, W, gamma;
-    uint32_t *notones, *status;
+    const uint32_t *notones;  // k x nt flags: tile x of chunk i at i * nt + x
+    uint32_t nt;
+    uint32_t *status;  // status[1] written
 };
 
-__device__ __forceinline__ void prologue_body(const PrologueArgs &A, const WG &wg) {
-    const uint64_t *a = A.a, *b = A.b, *c = A.c;
-    const uint64_t k = A.k, W = A.W, gamma = A.gamma;
-    uint32_t *notones = A.notones, *status = A.status;
-    uint64_t topmask = (gamma & 63) ? ((1ull << (gamma & 63)) - 1) : ~0ull;
-    bool range = false;
-    for (uint64_t i = threadIdx.x; i < k; i += blockDim.x) {
-        notones[i] = 0u;
-        range |= (a[i * W + W - 1] & ~topmask) != 0;
+__device__ void hash_status(const StatusArgs &S) {
+    const uint64_t topmask = (S.gamma & 63) ? ((1ull << (S.gamma & 63)) - 1) : ~0ull;
+    bool range = false, reload = false;
+    for (uint64_t i = threadIdx.x; i < S.k; i += blockDim.x) range |= (S.a[i * S.W + S.W - 1] & ~topmask) != 0;
+    if (threadIdx.x == 0) range |= ((S.b[S.W - 1] | S.c[S.W - 1]) & ~topmask) != 0;
+    // one wavefront per chunk (the loop bounds are uniform over a wavefront)
+    const uint32_t lane = threadIdx.x & 63u, nw = blockDim.x >> 6;
+    for (uint64_t i = threadIdx.x >> 6; i < S.k; i += nw) {
+        bool seen = false;
+        for (uint32_t x = lane; x < S.nt; x += 64) seen |= S.notones[i * S.nt + x] != 0u;
+        if (!__any(seen)) reload = true;
     }
-    if (threadIdx.x == 0) range |= ((b[W - 1] | c[W - 1]) & ~topmask) != 0;
-    int any = __syncthreads_or(range);
+    const int bad_range = __syncthreads_or(range);
+    const int bad_chunk = __syncthreads_or(reload);
     if (threadIdx.x == 0) {
-        uint32_t f = any ? ST_SEED_RANGE : 0u;
-        if ((b[0] & 1ull) == 0) f |= ST_B_EVEN;
-        status[0] = f;
-        status[1] = 0u;
+        uint32_t f = bad_range ? ST_SEED_RANGE : 0u;
+        if ((S.b[0] & 1ull) == 0) f |= ST_B_EVEN;
+        if (bad_chunk) f |= ST_RELOAD;
+        S.status[1] = f;
     }
-}
-
-__global__ void k_prologue(PrologueArgs A) { prologue_body(A, wg_self()); }
-
-__global__ void km_prologue(const PrologueArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
-                                     const uint16_t *__restrict__ owner) {
-    WG wg;
-    const uint32_t i = wg_multi(geo, owner, wg);
-    if (i != MULTI_NONE) prologue_body(tab[i], wg);
 }
 
 // After the MMH column pass: RELOAD if some chunk had only all-ones limbs.
@@ -537,9 +536,9 @@ __device__ __forceinline__ void col_fwd_body(const ColFwdArgs &A, const WG &wg) 
                 }
             }
         }
-        if (is_key) {
+        if (is_key) {  // this tile's reload flag, written whatever its value
             int any = __syncthreads_or(not_ones);
-            if (any && t == 0) A.notones[arr] = 1u;
+            if (t == 0 && wg.z == 0) A.notones[(uint64_t)arr * wg.gx + wg.x] = any ? 1u : 0u;
         }
     }
     // the transforms (primes x radix-3 or radix-5 branches) of this workgroup's z slice:
@@ -696,9 +695,9 @@ __device__ __forceinline__ void col9_fwd_body(const ColFwdArgs &A, const WG &wg)
             }
             if constexpr (MIX) __builtin_amdgcn_sched_barrier(0);  // 24 limb loads in flight at most
         }
-        if (is_key) {
+        if (is_key) {  // this tile's reload flag, written whatever its value
             int any = __syncthreads_or(not_ones);
-            if (any && t == 0) A.notones[arr] = 1u;
+            if (t == 0 && wg.z == 0) A.notones[(uint64_t)arr * wg.gx + wg.x] = any ? 1u : 0u;
         }
     }
     // the transforms (primes x radix-3 branches) of this workgroup's z slice:
@@ -839,9 +838,9 @@ __device__ __forceinline__ void col10_fwd_body(const ColFwdArgs &A, const WG &wg
             }
             if constexpr (MIX) __builtin_amdgcn_sched_barrier(0);  // 24 limb loads in flight at most
         }
-        if (is_key) {
+        if (is_key) {  // this tile's reload flag, written whatever its value
             int any = __syncthreads_or(not_ones);
-            if (any && t == 0) A.notones[arr] = 1u;
+            if (t == 0 && wg.z == 0) A.notones[(uint64_t)arr * wg.gx + wg.x] = any ? 1u : 0u;
         }
     }
     // the transforms (primes x radix-3 branches) of this workgroup's z slice:
@@ -1687,9 +1686,7 @@ struct Crt3Args {
     PrimeSet P;
     CrtConst K;
     Mix3Const X;
-    const uint32_t *notones;
-    uint64_t k;
-    uint32_t *status;
+    StatusArgs S;  // with S.notones set (the fold): its first workgroup writes the hash status
 };
 
 // The same reconstruction for N = 3 Nsub, fused with the inverse radix-3
@@ -1700,12 +1697,7 @@ struct Crt3Args {
 // reconstructs the coefficients j1 + n0 Nsub (n0 < 3) below `count`.
 __device__ __forceinline__ void crt3_body(const Crt3Args &A, const WG &wg) {
     const uint64_t j1 = (uint64_t)wg.x * blockDim.x + threadIdx.x;
-    if (A.notones && wg.x == 0) {
-        bool reload = false;
-        for (uint64_t i = threadIdx.x; i < A.k; i += blockDim.x) reload |= (A.notones[i] == 0u);
-        const int any = __syncthreads_or(reload);
-        if (threadIdx.x == 0) A.status[1] = A.status[0] | (any ? ST_RELOAD : 0u);
-    }
+    if (A.S.notones && wg.x == 0) hash_status(A.S);
     if (j1 >= A.Nsub || j1 >= A.count) return;
     const uint32_t r = (uint32_t)(j1 >> A.m2);
     uint32_t x[3][NPRIMES];  // [n0][prime], canonical
@@ -1752,9 +1744,7 @@ struct Crt5Args {
     PrimeSet P;
     CrtConst K;
     Mix5Const X;
-    const uint32_t *notones;
-    uint64_t k;
-    uint32_t *status;
+    StatusArgs S;  // with S.notones set (the fold): its first workgroup writes the hash status
 };
 
 // The reconstruction for N = 5 Nsub, fused with the inverse radix-5 step:
@@ -1766,12 +1756,7 @@ struct Crt5Args {
 // below 2p) and reconstructs the coefficients j1 + n0 Nsub below `count`.
 __device__ __forceinline__ void crt5_body(const Crt5Args &A, const WG &wg) {
     const uint64_t j1 = (uint64_t)wg.x * blockDim.x + threadIdx.x;
-    if (A.notones && wg.x == 0) {
-        bool reload = false;
-        for (uint64_t i = threadIdx.x; i < A.k; i += blockDim.x) reload |= (A.notones[i] == 0u);
-        const int any = __syncthreads_or(reload);
-        if (threadIdx.x == 0) A.status[1] = A.status[0] | (any ? ST_RELOAD : 0u);
-    }
+    if (A.S.notones && wg.x == 0) hash_status(A.S);
     if (j1 >= A.Nsub || j1 >= A.count) return;
     const uint32_t r = (uint32_t)(j1 >> A.m2);
     uint32_t x[5][NPRIMES];  // [n0][prime], canonical
@@ -1830,10 +1815,27 @@ __device__ __forceinline__ unsigned __int128 coef(const uint32_t *__restrict__ c
 // normalises its tile.  No workgroup waits for another.  The second fold has
 // no digit kernel: the first fold's apply leaves its tile functions.
 constexpr int DIG_FOLD = 0, DIG_MH = 2;
+constexpr uint32_t WRAP_LO = 32;  // lowest limbs of y written by the first fold's extra workgroup
+
+// The second fold's rare case, settled inside the MH digits.  The first
+// fold's apply writes y' = S - c 2^(nlo B) (S = T_lo + (V mod p) unreduced,
+// below 2p; nlo = min(32, L - 1); c the carry into limb nlo), the word
+// c | (S's limbs below nlo all ones) << 1, and per tile whether its limbs in
+// [nlo, L) are all ones.  Then y = S - w p with w = [S >= p] = (c or the low
+// limbs all ones) and the upper limbs all ones (c = 1 leaves S's low limbs
+// below V < 2^128, never all ones), and b y + c_seed = b y' + c_seed +
+// c b 2^(nlo B) + w b (mod 2^gamma): digit m gains c b_(m - nlo) + w b_m.
+struct WrapFix {
+    const uint64_t *b;       // MH seed b (W words), nullptr: no correction
+    const uint32_t *info;    // the word c | lo_ones << 1
+    const uint32_t *tflags;  // per first-fold tile: its limbs in [nlo, L) all ones
+    uint64_t ntiles;         // first-fold tiles
+};
 
 struct DigitArgs {
     const uint32_t *c96;  // product coefficients, three word planes (FOLD, MH)
     const uint64_t *cseed;  // c (MH)
+    WrapFix fix;            // MH
     uint64_t *t;          // digit sums out
     CFn *agg;             // tile carry functions out
     uint64_t N, ndig, M;  // digits produced; digits in the carry chain (the rest is the top limb)
@@ -1896,6 +1898,29 @@ __device__ __forceinline__ uint64_t mh_digit(const DigitArgs &A, uint64_t m) {
     return sum;
 }
 
+// The info word of WrapFix (0 without a correction); loaded early, used by
+// wrap_fix_bits after the workgroup's own loads.
+__device__ __forceinline__ uint32_t wrap_fix_info(const WrapFix &F) { return F.b ? *F.info : 0u; }
+
+// (c, w) of WrapFix as bits 0 and 1, for the calling workgroup (uniform):
+// 0 in the usual case, where the info word is 0.
+__device__ uint32_t wrap_fix_bits(const WrapFix &F, uint32_t info) {
+    if ((info & 3u) == 0u) return 0u;
+    bool all = true;
+    for (uint64_t i = threadIdx.x; i < F.ntiles; i += blockDim.x) all &= F.tflags[i] != 0u;
+    const int upper = __syncthreads_and(all);
+    return (info & 1u) | (upper ? 2u : 0u);
+}
+
+// The WrapFix terms of MH digit m < L.
+__device__ __forceinline__ uint64_t wrap_fix_terms(const DigitArgs &A, uint32_t fx, uint64_t m) {
+    uint64_t add = 0;
+    const uint64_t nlo = (A.L - 1) < WRAP_LO ? (A.L - 1) : WRAP_LO;
+    if ((fx & 1u) && m >= nlo) add += bits_at(A.fix.b, A.gamma, (m - nlo) * A.B, A.B);
+    if (fx & 2u) add += bits_at(A.fix.b, A.gamma, m * A.B, A.B);
+    return add;
+}
+
 // Digits from the coefficients' word planes (N = 3 * 2^m, after k_crt3).
 // Workgroup b covers digits [b CARRY_TILE, +CARRY_TILE), one per thread
 // (many waves in flight: the digits gather from several coefficients); writes
@@ -1903,9 +1928,17 @@ __device__ __forceinline__ uint64_t mh_digit(const DigitArgs &A, uint64_t m) {
 template <int MODE>
 __device__ __forceinline__ void digit_tile_body(const DigitArgs &A, const WG &wg) {
     const uint64_t m = (uint64_t)wg.x * CARRY_TILE + threadIdx.x;
+    uint32_t info = 0;
+    if constexpr (MODE == DIG_MH) info = wrap_fix_info(A.fix);
+    uint64_t d = 0;
+    if (m < A.ndig) d = MODE == DIG_FOLD ? fold_digit(A, m) : mh_digit(A, m);
+    uint32_t fx = 0;
+    if constexpr (MODE == DIG_MH) fx = wrap_fix_bits(A.fix, info);
     CFn f = cf_id();
     if (m < A.ndig) {
-        const uint64_t d = MODE == DIG_FOLD ? fold_digit(A, m) : mh_digit(A, m);
+        if constexpr (MODE == DIG_MH) {
+            if (fx) d += wrap_fix_terms(A, fx, m);
+        }
         A.t[m] = d;
         if (m < A.M) f = cf_limb(d, A.B);
     }
@@ -1940,9 +1973,7 @@ struct DigitCrtArgs {
     const uint32_t *cc;  // 3 primes x N canonical residues
     PrimeSet P;
     CrtConst K;
-    const uint32_t *notones;
-    uint64_t k;
-    uint32_t *status;
+    StatusArgs S;  // with S.notones set (the fold): its first workgroup writes the hash status
 };
 
 template <int MODE>
@@ -1954,12 +1985,11 @@ __device__ __forceinline__ void digit_crt_body(const DigitCrtArgs &A, const WG &
     const DigitArgs &D = A.D;
     const uint32_t t = threadIdx.x;
     const uint64_t m0 = (uint64_t)wg.x * CARRY_TILE;
-    if (A.notones && wg.x == 0) {
-        bool reload = false;
-        for (uint64_t i = t; i < A.k; i += CARRY_TILE) reload |= (A.notones[i] == 0u);
-        const int any = __syncthreads_or(reload);
-        if (t == 0) A.status[1] = A.status[0] | (any ? ST_RELOAD : 0u);
+    if constexpr (MODE == DIG_FOLD) {
+        if (A.S.notones && wg.x == 0) hash_status(A.S);
     }
+    uint32_t info = 0;
+    if constexpr (MODE == DIG_MH) info = wrap_fix_info(D.fix);
     const uint32_t *cc = A.cc;
     for (uint32_t sl = t; sl < (uint32_t)SPAN; sl += CARRY_TILE) {
         const bool pos = m0 + sl >= (uint64_t)DIG_HALO;
@@ -1979,6 +2009,8 @@ __device__ __forceinline__ void digit_crt_body(const DigitCrtArgs &A, const WG &
         }
     }
     __syncthreads();
+    uint32_t fx = 0;
+    if constexpr (MODE == DIG_MH) fx = wrap_fix_bits(D.fix, info);
     const uint64_t m = m0 + t;
     CFn f = cf_id();
     if (m < D.ndig) {
@@ -2021,6 +2053,9 @@ __device__ __forceinline__ void digit_crt_body(const DigitCrtArgs &A, const WG &
                 d += bits_at(D.cseed, D.gamma, m * D.B, D.B);
             }
         }
+        if constexpr (MODE == DIG_MH) {
+            if (fx) d += wrap_fix_terms(D, fx, m);
+        }
         D.t[m] = d;
         if (m < D.M) f = cf_limb(d, D.B);
     }
@@ -2040,7 +2075,6 @@ __global__ __launch_bounds__(CARRY_TILE) void km_digit_crt(const DigitCrtArgs *_
 }
 
 constexpr int APPLY_PLAIN = 0, APPLY_FOLD = 1, APPLY_WRAP = 2;
-constexpr uint32_t WRAP_LO = 32;     // lowest limbs of y written by the second fold's usual case
 constexpr uint32_t WRAP_TOP = 24;    // >= digits of the folded sum at and above limb gamma / B
 constexpr uint32_t EXTRA_LIMBS = 10; // >= ceil(64 / B) + 1 limbs past a tile an output word reaches
 
@@ -2058,6 +2092,8 @@ struct ScanArgs {
     uint32_t qv;         // FOLD, WRAP: wrap digits below qv = ceil(128 / B) take pieces of V mod p
     uint32_t *y;         // FOLD: the limbs of y (usual case of the second fold)
     uint32_t *flag;      // FOLD: 1 when the usual case does not apply, else 0; WRAP: runs only on 1
+    uint32_t *wrapinfo;  // FOLD: c | (low limbs of S all ones) << 1 (see WrapFix), 0 without inline wrap
+    uint32_t *tflags;    // FOLD: per tile, 1 when its limbs in [nlo, L) are all ones (top limb: s_top bits)
     uint64_t *zout;      // PLAIN: if set, z = bits [gamma - r, gamma) of the result, packed
     uint64_t out_words, r;
     const uint32_t *status;  // PLAIN with zout: final status flags at index 1 (no output unless 0)
@@ -2171,7 +2207,19 @@ __device__ void wrap_usual_case(const ScanArgs &A) {
     const uint32_t first_same = stop ? (uint32_t)__ffsll((unsigned long long)stop) : nlo + 1;  // limb index + 1
     const uint64_t guard = __ballot(on && t >= first_same && sl != mask);
     const bool usual = A.qv < nlo && first_same <= nlo && guard != 0;
-    if (usual && on) A.y[t] = (uint32_t)(ys & mask);
+    if (A.qv < nlo) {
+        // y's lowest limbs are those of S = T_lo + (V mod p) whatever the case:
+        // with the tiles' limbs above them, y' = S - c 2^(nlo B) (c the carry
+        // into limb nlo), which the MH digits correct (WrapFix) unless c = 0
+        // and the low limbs are not all ones (then y' = y)
+        if (on) A.y[t] = (uint32_t)(ys & mask);
+        const uint32_t c = (uint32_t)__shfl((int)(uint32_t)(ys >> A.B), (int)nlo - 1, 64);
+        const uint64_t ones = __ballot(on && (ys & mask) == mask);
+        const bool lo_ones = ones == (nlo >= 64 ? ~0ull : (1ull << nlo) - 1);
+        if (t == 0) *A.wrapinfo = c | (lo_ones ? 2u : 0u);
+    } else if (t == 0) {
+        *A.wrapinfo = 0u;
+    }
     if (t == 0) *A.flag = usual ? 0u : 1u;
 }
 
@@ -2200,9 +2248,21 @@ __device__ void wrap_usual_case(const ScanArgs &A) {
 // that start in its limbs (the last workgroup: up to bit gamma), unless the
 // status flags are set; workgroup 0 copies the flags to dst.
 template <int AM>
+__device__ __forceinline__ void apply_tile(const ScanArgs &A, uint64_t b, unsigned __int128 W);
+
+template <int AM>
 __device__ __forceinline__ void carry_apply_body(const ScanArgs &A, const WG &wg) {
     if constexpr (AM == APPLY_WRAP) {
         if (*(const volatile uint32_t *)A.flag == 0u) return;
+        // the general case is rare: a small grid (its early exit is then
+        // cheap), each workgroup taking tiles wg.x, wg.x + gx, ...
+        const unsigned __int128 W = wrap_value(A.s, A.gamma, A.B, A.M1);
+        const uint64_t nb = A.ntiles ? A.ntiles : 1;
+        for (uint64_t b = wg.x; b < nb; b += wg.gx) {
+            apply_tile<AM>(A, b, W);
+            __syncthreads();  // the next tile reuses the scans' LDS
+        }
+        return;
     }
     if constexpr (AM == APPLY_FOLD) {
         if (wg.x == 0) {  // dispatched first: its chain of loads and reductions overlaps the tiles
@@ -2210,7 +2270,12 @@ __device__ __forceinline__ void carry_apply_body(const ScanArgs &A, const WG &wg
             return;
         }
     }
-    const uint64_t b = AM == APPLY_FOLD ? wg.x - 1 : wg.x;
+    apply_tile<AM>(A, AM == APPLY_FOLD ? wg.x - 1 : wg.x, 0);
+}
+
+// Tile b of an apply launch (W: V mod p of the wrap chain, APPLY_WRAP only).
+template <int AM>
+__device__ __forceinline__ void apply_tile(const ScanArgs &A, uint64_t b, unsigned __int128 W) {
     const uint64_t mask = (1ull << A.B) - 1;
     constexpr bool EXTRACT = AM == APPLY_PLAIN;
     __shared__ uint32_t lb[EXTRACT ? CARRY_TILE + EXTRA_LIMBS : 1];
@@ -2229,9 +2294,7 @@ __device__ __forceinline__ void carry_apply_body(const ScanArgs &A, const WG &wg
 #pragma unroll
     for (int v = 0; v < CARRY_PER_THREAD; ++v)
         tv[v] = base + v < A.M ? (AM == APPLY_WRAP ? (uint64_t)A.s[base + v] : A.t[base + v]) : 0ull;
-    unsigned __int128 W = 0;
     if constexpr (AM == APPLY_WRAP) {
-        W = wrap_value(A.s, A.gamma, A.B, A.M1);
 #pragma unroll
         for (int v = 0; v < CARRY_PER_THREAD; ++v)
             if (base + v < A.qv && base + v < A.M) tv[v] += (uint64_t)(W >> (A.B * (base + v))) & mask;
@@ -2285,6 +2348,10 @@ __device__ __forceinline__ void carry_apply_body(const ScanArgs &A, const WG &wg
         block_scan<SCAN_THREADS>(f, excl, total);
         uint32_t carry = cf_eval(excl, cf_eval(before, sel));
         CFn fw = cf_id();
+        // FOLD: this thread's limbs in [nlo, Mw] all ones (limb Mw: its s_top bits)
+        [[maybe_unused]] const uint64_t nlo = A.Mw < WRAP_LO ? A.Mw : WRAP_LO;
+        [[maybe_unused]] const uint32_t topmask = (uint32_t)((1ull << A.s_top) - 1);
+        [[maybe_unused]] bool upper_ones = true;
 #pragma unroll
         for (int v = 0; v < CARRY_PER_THREAD; ++v) {
             const uint64_t idx = base + v;
@@ -2296,7 +2363,9 @@ __device__ __forceinline__ void carry_apply_body(const ScanArgs &A, const WG &wg
                 if constexpr (AM == APPLY_FOLD) {
                     if (idx >= A.qv && idx < A.Mw) fw = cf_compose(fw, cf_limb(limb, A.B));
                     if (idx >= WRAP_LO && idx < A.Mw) A.y[idx] = limb;
-                    if (idx == A.Mw) A.y[idx] = limb & (uint32_t)((1ull << A.s_top) - 1);
+                    if (idx == A.Mw) A.y[idx] = limb & topmask;
+                    if (idx >= nlo && idx < A.Mw) upper_ones &= limb == (uint32_t)mask;
+                    if (idx == A.Mw) upper_ones &= (limb & topmask) == topmask;
                 }
                 if constexpr (EXTRACT) lb[idx - b * CARRY_TILE] = limb;
                 if (EXTRACT && idx + 1 == tile_end) cout = carry;
@@ -2305,6 +2374,8 @@ __device__ __forceinline__ void carry_apply_body(const ScanArgs &A, const WG &wg
         if constexpr (AM == APPLY_FOLD) {
             const CFn tw = block_reduce<SCAN_THREADS>(fw);
             if (threadIdx.x == 0) A.agg_w[b] = tw;
+            const int ones = __syncthreads_and(upper_ones);
+            if (threadIdx.x == 0) A.tflags[b] = ones ? 1u : 0u;
         }
     }
     if constexpr (EXTRACT) {
@@ -2598,15 +2669,6 @@ hipError_t launch_twiddles(pa_plan *p, hipStream_t st, uint32_t *hdr, uint32_t w
     return hipGetLastError();
 }
 
-hipError_t launch_prologue(pa_plan *p, const uint64_t *a, const uint64_t *b, const uint64_t *c,
-                           hipStream_t st) {
-    phase_mark(p, PA_PH_PROLOGUE, true, st);
-    const PrologueArgs A{a, b, c, p->k, p->W, p->gamma, p->notones, p->status};
-    emit(p, SP_PROLOGUE, PA_KERN0(prologue), dim3(1), dim3(256), 0, A, st);
-    phase_mark(p, PA_PH_PROLOGUE, false, st);
-    return hipGetLastError();
-}
-
 static ColFwdArgs col_args(pa_plan *p, uint32_t mode) {
     ColFwdArgs cf;
     cf.X = p->X;
@@ -2795,6 +2857,7 @@ static DigitArgs digit_args(pa_plan *p) {
     DigitArgs A;
     A.c96 = p->C96;
     A.cseed = nullptr;
+    A.fix = WrapFix{};
     A.t = p->t;
     A.agg = p->agg;
     A.N = p->N;
@@ -2828,13 +2891,27 @@ static ScanArgs scan_args(pa_plan *p, uint32_t *out, uint64_t M, bool top, bool 
     S.qv = (128 + p->B - 1) / p->B;
     S.y = p->y;
     S.flag = p->status + 2;  // the second fold's general case is needed
+    S.wrapinfo = p->status + 3;
+    S.tflags = p->tflags;
     return S;
 }
 
+// The first fold's extra workgroup writes y's lowest limbs itself when
+// V mod p fits below limb min(32, L - 1) (ceil(128 / B) limbs), always true
+// but for the smallest blocks.
+bool wrap_inline(const pa_plan *p) {
+    const uint64_t nlo = std::min<uint64_t>(WRAP_LO, p->L - 1);
+    return (128 + p->B - 1) / p->B < nlo;
+}
+
 // FOLD: one workgroup more than the tiles (the second fold's usual case).
+// WRAP: at most WRAP_GRID workgroups, looping over the tiles.
+constexpr uint64_t WRAP_GRID = 128;
+
 template <int AM>
 static void launch_apply(pa_plan *p, const ScanArgs &S, hipStream_t st) {
-    const uint64_t wg = AM == APPLY_FOLD ? S.ntiles + 1 : (S.ntiles ? S.ntiles : 1);
+    const uint64_t nt = S.ntiles ? S.ntiles : 1;
+    const uint64_t wg = AM == APPLY_FOLD ? S.ntiles + 1 : AM == APPLY_WRAP ? std::min(nt, WRAP_GRID) : nt;
     const int step = AM == APPLY_FOLD ? SP_FOLD_APPLY : AM == APPLY_WRAP ? SP_FOLD_WRAP : SP_MH_APPLY;
     emit(p, step, PA_KERN(carry_apply, AM), dim3((unsigned)wg), dim3(SCAN_THREADS), 0, S, st);
 }
@@ -2868,10 +2945,27 @@ static hipError_t run_carry(pa_plan *p, DigitArgs A, uint32_t *out, uint64_t ndi
     return hipGetLastError();
 }
 
+// The hash status check for the fold's reconstruction kernel; seeds nullptr
+// (the MH stage): none.
+static StatusArgs status_args(pa_plan *p, const Seeds *seeds) {
+    StatusArgs S{};
+    if (!seeds) return S;
+    S.a = seeds->a;
+    S.b = seeds->b;
+    S.c = seeds->c;
+    S.k = p->k;
+    S.W = p->W;
+    S.gamma = p->gamma;
+    S.notones = p->notones;
+    S.nt = 1u << (p->m2 - p->c_lg);  // column tiles of the key-chunk pass
+    S.status = p->status;
+    return S;
+}
+
 // Coefficients [0, count) of the convolution for N = 3 * 2^m from the
 // residues in Cc, as word planes in C96 (with notones: also the RELOAD
 // status).  For N = 2^m the digit kernels reconstruct the coefficients.
-static void launch_crt5(pa_plan *p, uint64_t count, const uint32_t *notones, int step, hipStream_t st) {
+static void launch_crt5(pa_plan *p, uint64_t count, const Seeds *seeds, int step, hipStream_t st) {
     Crt5Args A;
     A.cc = p->Cc;
     A.c96 = p->C96;
@@ -2884,15 +2978,13 @@ static void launch_crt5(pa_plan *p, uint64_t count, const uint32_t *notones, int
     A.P = p->primes;
     A.K = p->crt;
     A.X = p->mix5;
-    A.notones = notones;
-    A.k = notones ? p->k : 0;
-    A.status = p->status;
+    A.S = status_args(p, seeds);
     emit(p, step, PA_KERN0(crt5), dim3(blocks_for(count < p->Nsub ? count : p->Nsub, 256)), dim3(256), 0, A, st);
 }
 
-static void launch_crt3(pa_plan *p, uint64_t count, const uint32_t *notones, int step, hipStream_t st) {
+static void launch_crt3(pa_plan *p, uint64_t count, const Seeds *seeds, int step, hipStream_t st) {
     if (p->rf == 5) {
-        launch_crt5(p, count, notones, step, st);
+        launch_crt5(p, count, seeds, step, st);
         return;
     }
     Crt3Args A;
@@ -2907,36 +2999,42 @@ static void launch_crt3(pa_plan *p, uint64_t count, const uint32_t *notones, int
     A.P = p->primes;
     A.K = p->crt;
     A.X = p->mix3;
-    A.notones = notones;
-    A.k = notones ? p->k : 0;
-    A.status = p->status;
+    A.S = status_args(p, seeds);
     emit(p, step, PA_KERN0(crt3), dim3(blocks_for(count < p->Nsub ? count : p->Nsub, 256)), dim3(256), 0, A, st);
 }
 
 // Reconstruction inside the digit kernel (N = 2^m); nullptr for N = 3 * 2^m,
 // whose coefficients need the inverse radix-3 step of k_crt3 first.
-static DigitCrtArgs *residue_digits(pa_plan *p, DigitCrtArgs &C, const uint32_t *notones) {
+static DigitCrtArgs *residue_digits(pa_plan *p, DigitCrtArgs &C, const Seeds *seeds) {
     if (p->mix) return nullptr;
     C.cc = p->Cc;
     C.P = p->primes;
     C.K = p->crt;
-    C.notones = notones;
-    C.k = notones ? p->k : 0;
-    C.status = p->status;
+    C.S = status_args(p, seeds);
     return &C;
 }
 
-hipError_t launch_fold(pa_plan *p, hipStream_t st) {
+hipError_t launch_fold(pa_plan *p, const Seeds &seeds, hipStream_t st) {
     phase_mark(p, PA_PH_FOLD, true, st);
     const uint64_t ncoef = 2 * p->L - 1;  // nonzero coefficients of the product
     DigitCrtArgs C;
-    DigitCrtArgs *crt = residue_digits(p, C, p->notones);
-    if (!crt) launch_crt3(p, ncoef, p->notones, SP_FOLD_CRT3, st);
+    DigitCrtArgs *crt = residue_digits(p, C, &seeds);
+    if (!crt) launch_crt3(p, ncoef, &seeds, SP_FOLD_CRT3, st);
     // first fold at bit gamma, normalised over M1 digits (the sum fits: no carry out);
     // its apply also writes y for the second fold's usual case (V mod p changes only
     // the lowest limbs) and sets a flag when that case does not apply
     hipError_t e = run_carry<DIG_FOLD>(p, digit_args(p), p->s, p->M1, p->M1, false, false, st, crt);
     if (e != hipSuccess) return e;
+    // without the inline form (the lowest limbs cannot hold V mod p), the
+    // general case runs here (see launch_wrap); with it, the MH digits settle
+    // the rare case (WrapFix) and y itself is recomputed only for pa_hash_stages
+    if (!wrap_inline(p)) (void)launch_wrap(p, st);
+    e = hipGetLastError();
+    phase_mark(p, PA_PH_FOLD, false, st);
+    return e;
+}
+
+hipError_t launch_wrap(pa_plan *p, hipStream_t st) {
     // second fold, general case (runs only when flagged): y = T_lo + (V mod p) over L
     // limbs, straight from the limbs of the first (whose apply left the wrap chain's
     // tile aggregates); the dual evaluation (carry-in 0 or 1) selects S or
@@ -2944,9 +3042,7 @@ hipError_t launch_fold(pa_plan *p, hipStream_t st) {
     ScanArgs S = scan_args(p, p->y, p->L - 1, true, true);
     S.agg = p->agg_w;
     launch_apply<APPLY_WRAP>(p, S, st);
-    e = hipGetLastError();
-    phase_mark(p, PA_PH_FOLD, false, st);
-    return e;
+    return hipGetLastError();
 }
 
 hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, uint64_t *out, uint32_t *d_status,
@@ -2979,6 +3075,7 @@ hipError_t launch_mh(pa_plan *p, const uint64_t *b, const uint64_t *c, uint64_t 
     if (!crt) launch_crt3(p, p->L, nullptr, SP_MH_CRT3, st);
     DigitArgs A = digit_args(p);
     A.cseed = c;
+    if (wrap_inline(p)) A.fix = WrapFix{b, p->status + 3, p->tflags, (p->M1 + CARRY_TILE - 1) / CARRY_TILE};
     // the apply also extracts z and copies the status flags out
     hipError_t e = run_carry<DIG_MH>(p, A, p->U, p->L, p->L - 1, true, false, st, crt, out,
                                      d_status ? d_status : p->status_out);

@@ -348,9 +348,14 @@ def test_fold_canonical_cases(pa, gamma, B, flags):
     c = rng.randrange(1 << gamma)
     r = max(1, gamma // 3)
     for label, chunks, a in [("S=p", [p - 1, 1], [1, 1]), ("S=p+1", [p - 1, 2], [1, 1]),
-                             ("S=2p", [p - 1, 1], [2, 2]), ("S=0", [0, 0], [5, 7])]:
-        blk = _blk(chunks, a, 1, c, gamma, 2 * gamma, r)
+                             ("S=2p", [p - 1, 1], [2, 2]), ("S=0", [0, 0], [5, 7]),
+                             ("S=2^gamma", [p - 1, p - 1, 3], [1, 1, 1])]:
+        blk = _blk(chunks, a, 1, c, gamma, len(chunks) * gamma, r)
         check_block(pa, blk, B=B, flags=flags, label=f"fold {label}")
+    if gamma > 32 * (B or 32) + 64:  # V's carry into limb 32 of y, b odd and > 1
+        R = rng.randrange(1 << (gamma - 32 * (B or 32) - 1))
+        blk = _blk([p - 1, 1 + ((R + 1) << (32 * (B or 32)))], [1, 1], 3, c, gamma, 2 * gamma, r)
+        check_block(pa, blk, B=B, flags=flags, label="fold carry into limb 32")
     x = rng.randrange(p)
     s = rng.randrange(gamma)
     blk = _blk([0, x, 0], [0, 1 << s, 0], 1, 0, gamma, 3 * gamma, r)
@@ -361,6 +366,40 @@ def test_fold_canonical_cases(pa, gamma, B, flags):
     blk = _blk([p - 1, p - 2, p ^ 1], [p - 1, p - 1, p - 1], (1 << gamma) - 1, (1 << gamma) - 1,
                gamma, 3 * gamma, r)
     check_block(pa, blk, B=B, flags=flags, label="long carries")
+
+
+def _wrap_cases(gamma, B, rng, c):
+    """(label, chunks, a, b, c) for the second fold's cases with a_i = 1:
+    S = T_lo + (T >> gamma) equal to p (y = 0); T = 2^gamma (S = 1); the
+    lowest 32 limbs of T_lo all ones and T >= 2^gamma, so that V's carry runs
+    into limb 32 (upper limbs random: y = S; all ones: S = 2^gamma, y = 1);
+    long carries with b = c = p."""
+    p = (1 << gamma) - 1
+    lo = 32 * B if B else 32 * 32
+    R = rng.randrange(1 << (gamma - lo - 1))
+    return [("S=p", [p - 1, 1], [1, 1], 1, c),
+            ("S=p+1", [p - 1, 2], [1, 1], 1, c),
+            ("carry into limb 32", [p - 1, 1 + ((R + 1) << lo)], [1, 1], 3, c),
+            ("S=2^gamma", [p - 1, p - 1, 3], [1, 1, 1], 5, c),
+            ("long carries", [p - 1, p - 2], [p - 1, p - 1], p, p)]
+
+
+@pytest.mark.parametrize("flags", [1, 2])
+def test_general_wrap_over_many_tiles(pa, flags):
+    """The second fold's general case (S = p folds to 0, S = p + 1 to 1, long
+    carries) on more carry tiles than the general wrap kernel has
+    workgroups (gamma = 1,257,787 at B = 8: 154 tiles), so its workgroups
+    take several tiles each."""
+    gamma = 1257787
+    p = (1 << gamma) - 1
+    rng = random.Random(flags)
+    c = rng.randrange(1 << gamma)
+    r = gamma // 3
+    info = pa.plan_query(2 * gamma, r, gamma, B=8, flags=flags)[1]
+    assert -(-(info["L"] - 1) // 1024) > 128, info
+    for label, chunks, a, b, cc in _wrap_cases(gamma, 8, rng, c):
+        blk = _blk(chunks, a, b, cc, gamma, len(chunks) * gamma, r)
+        check_block(pa, blk, B=8, flags=flags, label=f"general wrap {label}")
 
 
 def test_status_codes_and_untouched_output(pa):
