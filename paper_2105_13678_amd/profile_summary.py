@@ -1,7 +1,7 @@
 """Short text summaries of rocprofv3 output for libpa's kernels.
 
     python -m paper_2105_13678_amd.profile_summary stats TRACE_DIR
-        per-kernel call count and average duration from a
+        per-kernel call count, average and median duration from a
         `rocprofv3 --kernel-trace --stats --output-format csv -o run` directory
 
     python -m paper_2105_13678_amd.profile_summary hbm FETCH_DIR WRITE_DIR --calib-bytes BYTES
@@ -14,7 +14,8 @@
     python -m paper_2105_13678_amd.profile_summary valu SQ_DIR
         per-kernel VALU instruction counts and issue utilisation from a
         `rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU
-        SQ_BUSY_CYCLES ...` directory (first launch of each kernel)
+        SQ_BUSY_CYCLES ...` directory (per kernel the counts of its largest
+        launch and the median duration of the launches with those counts)
 
 Kernel names are shortened (namespaces and argument lists dropped, template
 arguments kept).  Output is Markdown on stdout.
@@ -46,12 +47,31 @@ def short_name(name: str) -> str:
     return "".join(out).strip()
 
 
+def _durations(trace_dir: str):
+    """Per-kernel launch durations (ns) from run_kernel_trace.csv, if present."""
+    path = os.path.join(trace_dir, "run_kernel_trace.csv")
+    out = collections.defaultdict(list)
+    if os.path.exists(path):
+        for r in csv.DictReader(open(path)):
+            out[short_name(r["Kernel_Name"])].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return out
+
+
+def _median(v):
+    v = sorted(v)
+    n = len(v)
+    return (v[n // 2] + v[(n - 1) // 2]) / 2 if n else float("nan")
+
+
 def stats(trace_dir: str) -> str:
     rows = list(csv.DictReader(open(os.path.join(trace_dir, "run_kernel_stats.csv"))))
-    lines = ["| kernel | calls | average µs | min µs | max µs | share of GPU time |",
-             "|---|---:|---:|---:|---:|---:|"]
+    durs = _durations(trace_dir)
+    lines = ["| kernel | calls | average µs | median µs | min µs | max µs | share of GPU time |",
+             "|---|---:|---:|---:|---:|---:|---:|"]
     for r in rows:
-        lines.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+        nm = short_name(r["Name"])
+        lines.append(f"| `{nm}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{_median(durs.get(nm, [])) / 1e3:.2f} | "
                      f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f}% |")
     return "\n".join(lines)
 
@@ -112,14 +132,27 @@ def valu(sq_dir: str, cus: int = 256, simds: int = 4, ghz: float = 2.4) -> str:
         c = agg.setdefault(key, collections.defaultdict(float))
         c[r["Counter_Name"]] += float(r["Counter_Value"])
         dur[key] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
-    lines = ["| kernel | µs (counting run) | waves | VALU instr (wave) | VALU issue util | LDS instr | LDS bank conflicts |",
+    # per kernel: the counts of its largest launch (most VALU instructions;
+    # the launches of a hash kernel all have the same counts) and the median
+    # duration of the launches with those counts
+    top = {}
+    for key, c in agg.items():
+        if key[1] not in top or c["SQ_INSTS_VALU"] > agg[top[key[1]]]["SQ_INSTS_VALU"]:
+            top[key[1]] = key
+    med = collections.defaultdict(list)
+    for key, ns in dur.items():
+        if agg[key]["SQ_INSTS_VALU"] == agg[top[key[1]]]["SQ_INSTS_VALU"]:
+            med[key[1]].append(ns)
+    lines = ["| kernel | µs (counting run, median) | waves | VALU instr (wave) | VALU issue util | LDS instr | LDS bank conflicts |",
              "|---|---:|---:|---:|---:|---:|---:|"]
     seen = set()
-    for key, c in agg.items():
-        if key[1] in seen:
+    for key0 in agg:
+        if key0[1] in seen:
             continue
-        seen.add(key[1])
-        ns = dur[key]
+        seen.add(key0[1])
+        key = top[key0[1]]
+        c = agg[key]
+        ns = _median(med[key[1]])
         util = c["SQ_INSTS_VALU"] * 4 / (ns * ghz * cus * simds) if ns else 0.0
         lines.append(f"| `{key[1]}` | {ns / 1e3:.1f} | {c['SQ_WAVES']:.0f} | {c['SQ_INSTS_VALU']:.4g} | {util:.2f} | "
                      f"{c['SQ_INSTS_LDS']:.4g} | {c['SQ_LDS_BANK_CONFLICT']:.4g} |")
