@@ -77,9 +77,9 @@ struct PrimeSet {
 // Constants for the Chinese-remainder (Garner) reconstruction.
 struct CrtConst {
     uint32_t inv_p0_mod_p1;     // p0^-1 mod p1, Montgomery form (mod p1)
-    uint32_t p0_mod_p2;         // p0 mod p2, Montgomery form (mod p2)
+    uint32_t one_sub;           // 1 when p0, p1 < 2 p2 and p0 < 2 p1: a conditional subtraction reduces
     uint32_t inv_p0p1_mod_p2;   // (p0 p1)^-1 mod p2, Montgomery form (mod p2)
-    uint32_t pad;
+    uint32_t inv_p1_mod_p2;     // p1^-1 mod p2, Montgomery form (mod p2)
     uint64_t p0p1;              // p0 * p1
 };
 

@@ -1664,16 +1664,24 @@ __global__ __launch_bounds__(COL_THREADS) void km_col10_inv(const ColInvArgs *__
 }
 
 // Garner's reconstruction: canonical residues r_q mod p_q of a value below
-// p0 p1 p2 -> the value.
+// p0 p1 p2 -> the value r0 + v1 p0 + v2 p0 p1.  With the primes of a triple
+// within a factor 2 of each other (K.one_sub; all but the two longest
+// power-of-two lengths' triples) a value below one prime is reduced modulo
+// another by one conditional subtraction, else by a Montgomery product with
+// 2^32 mod p; v2 = (r2 - r0) / (p0 p1) - v1 / p1 mod p2 takes one Montgomery
+// reduction of the 64-bit sum of both products.
 __device__ __forceinline__ unsigned __int128 garner(uint32_t r0, uint32_t r1, uint32_t r2, const PrimeSet &P,
                                                     const CrtConst &K) {
     const PrimeConst &M1 = P.c[1], &M2 = P.c[2];
+    const bool sub = K.one_sub != 0u;  // uniform
+    const uint32_t r0a = sub ? min(r0, r0 - M1.p) : mmul(r0, M1.one, M1);
+    const uint32_t r0b = sub ? min(r0, r0 - M2.p) : mmul(r0, M2.one, M2);
     // v1 = (r1 - r0) / p0 mod p1
-    const uint32_t v1 = mmul(msub(r1, mmul(r0, M1.one, M1), M1), K.inv_p0_mod_p1, M1);
-    // v2 = (r2 - r0 - v1 p0) / (p0 p1) mod p2
-    const uint32_t r0m = mmul(r0, M2.one, M2);
-    const uint32_t v1p0 = mmul(v1, K.p0_mod_p2, M2);
-    const uint32_t v2 = mmul(msub(msub(r2, r0m, M2), v1p0, M2), K.inv_p0p1_mod_p2, M2);
+    const uint32_t v1 = mmul(msub(r1, r0a, M1), K.inv_p0_mod_p1, M1);
+    const uint32_t v1b = sub ? min(v1, v1 - M2.p) : mmul(v1, M2.one, M2);
+    // T < 2 p2^2 < 2^61; its reduction is below 2 p2
+    const uint64_t T = (uint64_t)msub(r2, r0b, M2) * K.inv_p0p1_mod_p2 + (uint64_t)(M2.p - v1b) * K.inv_p1_mod_p2;
+    const uint32_t v2 = canon(redc64(T, M2), M2);
     return (unsigned __int128)r0 + (unsigned __int128)v1 * P.c[0].p + (unsigned __int128)v2 * K.p0p1;
 }
 
@@ -1815,6 +1823,12 @@ __device__ __forceinline__ unsigned __int128 coef(const uint32_t *__restrict__ c
 // normalises its tile.  No workgroup waits for another.  The second fold has
 // no digit kernel: the first fold's apply leaves its tile functions.
 constexpr int DIG_FOLD = 0, DIG_MH = 2;
+// Digit kernels: DIG_THREADS threads per CARRY_TILE-digit tile, DIG_PER_THREAD
+// consecutive digits each (four 512-thread workgroups fit a CU, so every tile
+// of a 2^21-point block is resident at once; with 1024 threads, two per CU,
+// they ran in two rounds)
+constexpr int DIG_THREADS = 512;
+constexpr int DIG_PER_THREAD = CARRY_TILE / DIG_THREADS;
 constexpr uint32_t WRAP_LO = 32;  // lowest limbs of y written by the first fold's extra workgroup
 
 // The second fold's rare case, settled inside the MH digits.  The first
@@ -1922,35 +1936,42 @@ __device__ __forceinline__ uint64_t wrap_fix_terms(const DigitArgs &A, uint32_t 
 }
 
 // Digits from the coefficients' word planes (N = 3 * 2^m, after k_crt3).
-// Workgroup b covers digits [b CARRY_TILE, +CARRY_TILE), one per thread
-// (many waves in flight: the digits gather from several coefficients); writes
-// the digit sums and the tile's composed carry function (digits below M only).
+// Workgroup b covers digits [b CARRY_TILE, +CARRY_TILE), DIG_PER_THREAD
+// consecutive ones per thread (the digits gather from several coefficients);
+// writes the digit sums and the tile's composed carry function (digits below
+// M only).
 template <int MODE>
 __device__ __forceinline__ void digit_tile_body(const DigitArgs &A, const WG &wg) {
-    const uint64_t m = (uint64_t)wg.x * CARRY_TILE + threadIdx.x;
+    const uint64_t m0 = (uint64_t)wg.x * CARRY_TILE + (uint64_t)threadIdx.x * DIG_PER_THREAD;
     uint32_t info = 0;
     if constexpr (MODE == DIG_MH) info = wrap_fix_info(A.fix);
-    uint64_t d = 0;
-    if (m < A.ndig) d = MODE == DIG_FOLD ? fold_digit(A, m) : mh_digit(A, m);
+    uint64_t d[DIG_PER_THREAD];
+#pragma unroll
+    for (int v = 0; v < DIG_PER_THREAD; ++v)
+        d[v] = m0 + v < A.ndig ? (MODE == DIG_FOLD ? fold_digit(A, m0 + v) : mh_digit(A, m0 + v)) : 0u;
     uint32_t fx = 0;
     if constexpr (MODE == DIG_MH) fx = wrap_fix_bits(A.fix, info);
     CFn f = cf_id();
-    if (m < A.ndig) {
-        if constexpr (MODE == DIG_MH) {
-            if (fx) d += wrap_fix_terms(A, fx, m);
+#pragma unroll
+    for (int v = 0; v < DIG_PER_THREAD; ++v) {
+        const uint64_t m = m0 + v;
+        if (m < A.ndig) {
+            if constexpr (MODE == DIG_MH) {
+                if (fx) d[v] += wrap_fix_terms(A, fx, m);
+            }
+            A.t[m] = d[v];
+            if (m < A.M) f = cf_compose(f, cf_limb(d[v], A.B));
         }
-        A.t[m] = d;
-        if (m < A.M) f = cf_limb(d, A.B);
     }
-    const CFn total = block_reduce<CARRY_TILE>(f);
+    const CFn total = block_reduce<DIG_THREADS>(f);
     if (threadIdx.x == 0) A.agg[wg.x] = total;
 }
 
 template <int MODE>
-__global__ __launch_bounds__(CARRY_TILE) void k_digit_tile(DigitArgs A) { digit_tile_body<MODE>(A, wg_self()); }
+__global__ __launch_bounds__(DIG_THREADS) void k_digit_tile(DigitArgs A) { digit_tile_body<MODE>(A, wg_self()); }
 
 template <int MODE>
-__global__ __launch_bounds__(CARRY_TILE) void km_digit_tile(const DigitArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
+__global__ __launch_bounds__(DIG_THREADS) void km_digit_tile(const DigitArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
                                      const uint16_t *__restrict__ owner) {
     WG wg;
     const uint32_t i = wg_multi(geo, owner, wg);
@@ -1964,8 +1985,9 @@ __global__ __launch_bounds__(CARRY_TILE) void km_digit_tile(const DigitArgs *__r
 // at or below its own index), then forms the digit sums from there.  Slot s
 // of `lo` holds coefficient m0 - DIG_HALO + s of the range [0, L) and slot s
 // of `hi` coefficient L + m0 - DIG_HALO + s of [L, 2L - 1) (FOLD only),
-// zero outside those ranges.  With notones, workgroup 0 also finishes the
-// status word (Sec. 3.1 reload rule).
+// zero outside those ranges; each thread then forms DIG_PER_THREAD
+// consecutive digits.  In the fold, workgroup 0 also writes the hash status
+// (seed ranges, b odd, the Sec. 3.1 reload rule).
 constexpr int DIG_HALO = 16;  // >= pieces per coefficient - 1 (at most 12 for B >= 8)
 
 struct DigitCrtArgs {
@@ -1991,7 +2013,7 @@ __device__ __forceinline__ void digit_crt_body(const DigitCrtArgs &A, const WG &
     uint32_t info = 0;
     if constexpr (MODE == DIG_MH) info = wrap_fix_info(D.fix);
     const uint32_t *cc = A.cc;
-    for (uint32_t sl = t; sl < (uint32_t)SPAN; sl += CARRY_TILE) {
+    for (uint32_t sl = t; sl < (uint32_t)SPAN; sl += DIG_THREADS) {
         const bool pos = m0 + sl >= (uint64_t)DIG_HALO;
         const uint64_t j = m0 + sl - DIG_HALO;  // meaningful when pos
         unsigned __int128 c = 0;
@@ -2011,63 +2033,67 @@ __device__ __forceinline__ void digit_crt_body(const DigitCrtArgs &A, const WG &
     __syncthreads();
     uint32_t fx = 0;
     if constexpr (MODE == DIG_MH) fx = wrap_fix_bits(D.fix, info);
-    const uint64_t m = m0 + t;
     CFn f = cf_id();
-    if (m < D.ndig) {
-        const uint32_t s0 = t + DIG_HALO;  // slot of coefficient m; m - q is at s0 - q
-        uint64_t d = 0;
-        if (D.B == 32) {
 #pragma unroll
-            for (uint32_t q = 0; q < 3; ++q) d += lo[q][s0 - q];
-            if constexpr (MODE == DIG_FOLD) {
-                // the folded part shifted left by e < 32: a funnel shift of two planes
+    for (int dv = 0; dv < DIG_PER_THREAD; ++dv) {
+        const uint32_t tl = t * DIG_PER_THREAD + dv;  // this digit's place in the tile
+        const uint64_t m = m0 + tl;
+        if (m < D.ndig) {
+            const uint32_t s0 = tl + DIG_HALO;  // slot of coefficient m; m - q is at s0 - q
+            uint64_t d = 0;
+            if (D.B == 32) {
 #pragma unroll
-                for (uint32_t q = 0; q < 4; ++q) {
-                    if (q >= D.Q2) continue;
-                    const uint32_t h = q < 3 ? hi[q][s0 - q] : 0u;
-                    const uint32_t l = q >= 1 ? hi[q - 1][s0 - q] : 0u;
-                    d += D.e ? __builtin_amdgcn_alignbit(h, l, 32u - D.e) : h;
+                for (uint32_t q = 0; q < 3; ++q) d += lo[q][s0 - q];
+                if constexpr (MODE == DIG_FOLD) {
+                    // the folded part shifted left by e < 32: a funnel shift of two planes
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; ++q) {
+                        if (q >= D.Q2) continue;
+                        const uint32_t h = q < 3 ? hi[q][s0 - q] : 0u;
+                        const uint32_t l = q >= 1 ? hi[q - 1][s0 - q] : 0u;
+                        d += D.e ? __builtin_amdgcn_alignbit(h, l, 32u - D.e) : h;
+                    }
+                } else {
+                    const uint64_t bit = 32 * m;
+                    uint32_t cw = bit < D.gamma ? ((const uint32_t *)D.cseed)[m] : 0u;
+                    if (bit + 32 > D.gamma && bit < D.gamma) cw &= (1u << (D.gamma - bit)) - 1u;
+                    d += cw;
                 }
             } else {
-                const uint64_t bit = 32 * m;
-                uint32_t cw = bit < D.gamma ? ((const uint32_t *)D.cseed)[m] : 0u;
-                if (bit + 32 > D.gamma && bit < D.gamma) cw &= (1u << (D.gamma - bit)) - 1u;
-                d += cw;
-            }
-        } else {
-            const uint64_t mask = (1ull << D.B) - 1;
-            for (uint32_t q = 0; q < D.Q; ++q) {
-                const uint32_t sl = s0 - q;
-                const unsigned __int128 c = (unsigned __int128)lo[0][sl] | ((unsigned __int128)lo[1][sl] << 32) |
-                                            ((unsigned __int128)lo[2][sl] << 64);
-                d += (uint64_t)(c >> (D.B * q)) & mask;
-            }
-            if constexpr (MODE == DIG_FOLD) {
-                for (uint32_t q = 0; q < D.Q2; ++q) {
+                const uint64_t mask = (1ull << D.B) - 1;
+                for (uint32_t q = 0; q < D.Q; ++q) {
                     const uint32_t sl = s0 - q;
-                    const unsigned __int128 h = (unsigned __int128)hi[0][sl] | ((unsigned __int128)hi[1][sl] << 32) |
-                                                ((unsigned __int128)hi[2][sl] << 64);
-                    d += (uint64_t)((h << D.e) >> (D.B * q)) & mask;
+                    const unsigned __int128 c = (unsigned __int128)lo[0][sl] | ((unsigned __int128)lo[1][sl] << 32) |
+                                                ((unsigned __int128)lo[2][sl] << 64);
+                    d += (uint64_t)(c >> (D.B * q)) & mask;
                 }
-            } else {
-                d += bits_at(D.cseed, D.gamma, m * D.B, D.B);
+                if constexpr (MODE == DIG_FOLD) {
+                    for (uint32_t q = 0; q < D.Q2; ++q) {
+                        const uint32_t sl = s0 - q;
+                        const unsigned __int128 h = (unsigned __int128)hi[0][sl] | ((unsigned __int128)hi[1][sl] << 32) |
+                                                    ((unsigned __int128)hi[2][sl] << 64);
+                        d += (uint64_t)((h << D.e) >> (D.B * q)) & mask;
+                    }
+                } else {
+                    d += bits_at(D.cseed, D.gamma, m * D.B, D.B);
+                }
             }
+            if constexpr (MODE == DIG_MH) {
+                if (fx) d += wrap_fix_terms(D, fx, m);
+            }
+            D.t[m] = d;
+            if (m < D.M) f = cf_compose(f, cf_limb(d, D.B));
         }
-        if constexpr (MODE == DIG_MH) {
-            if (fx) d += wrap_fix_terms(D, fx, m);
-        }
-        D.t[m] = d;
-        if (m < D.M) f = cf_limb(d, D.B);
     }
-    const CFn total = block_reduce<CARRY_TILE>(f);
+    const CFn total = block_reduce<DIG_THREADS>(f);
     if (t == 0) D.agg[wg.x] = total;
 }
 
 template <int MODE>
-__global__ __launch_bounds__(CARRY_TILE) void k_digit_crt(DigitCrtArgs A) { digit_crt_body<MODE>(A, wg_self()); }
+__global__ __launch_bounds__(DIG_THREADS) void k_digit_crt(DigitCrtArgs A) { digit_crt_body<MODE>(A, wg_self()); }
 
 template <int MODE>
-__global__ __launch_bounds__(CARRY_TILE) void km_digit_crt(const DigitCrtArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
+__global__ __launch_bounds__(DIG_THREADS) void km_digit_crt(const DigitCrtArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
                                      const uint16_t *__restrict__ owner) {
     WG wg;
     const uint32_t i = wg_multi(geo, owner, wg);
@@ -2568,9 +2594,9 @@ void compute_prime_constants(pa_plan *p, const uint32_t primes[NPRIMES]) {
     }
     const uint32_t p0 = primes[0], p1 = primes[1], p2 = primes[2];
     p->crt.inv_p0_mod_p1 = hmont(hinv(p0 % p1, p1), p1);
-    p->crt.p0_mod_p2 = hmont(p0 % p2, p2);
+    p->crt.one_sub = (p0 < 2ull * p1 && p0 < 2ull * p2 && p1 < 2ull * p2) ? 1u : 0u;
     p->crt.inv_p0p1_mod_p2 = hmont(hinv(hmul(p0 % p2, p1 % p2, p2), p2), p2);
-    p->crt.pad = 0;
+    p->crt.inv_p1_mod_p2 = hmont(hinv(p1 % p2, p2), p2);
     p->crt.p0p1 = (uint64_t)p0 * p1;
     for (int q = 0; q < NPRIMES; ++q) {
         const uint32_t pr = primes[q];
@@ -2931,9 +2957,9 @@ static hipError_t run_carry(pa_plan *p, DigitArgs A, uint32_t *out, uint64_t ndi
     const int step = MODE == DIG_FOLD ? SP_FOLD_DIGIT : SP_MH_DIGIT;
     if (tiles_t && crt) {
         crt->D = A;
-        emit(p, step, PA_KERN(digit_crt, MODE), dim3((unsigned)tiles_t), dim3(CARRY_TILE), 0, *crt, st);
+        emit(p, step, PA_KERN(digit_crt, MODE), dim3((unsigned)tiles_t), dim3(DIG_THREADS), 0, *crt, st);
     } else if (tiles_t) {
-        emit(p, step, PA_KERN(digit_tile, MODE), dim3((unsigned)tiles_t), dim3(CARRY_TILE), 0, A, st);
+        emit(p, step, PA_KERN(digit_tile, MODE), dim3((unsigned)tiles_t), dim3(DIG_THREADS), 0, A, st);
     }
     ScanArgs S = scan_args(p, out, M, top, dual);
     S.zout = zout;  // MH: the output extraction rides on the apply

@@ -104,6 +104,12 @@ class Field:
         assert r % self.p == x.v % self.p
         return V(r, min(x.hi, self.p2))
 
+    def csub(self, x):  # min(x, x - p) as 32-bit unsigned, for x < 2p
+        assert x.hi <= self.p2, "one conditional subtraction needs x < 2p"
+        r = min(x.v, (x.v - self.p) % M32)
+        assert r < self.p and r == x.v % self.p
+        return V(r, self.p)
+
     def canon(self, x):
         assert x.hi <= self.p2, "canon input must be below 2p"
         r = min(x.v, (x.v - self.p) % M32)
@@ -393,15 +399,23 @@ def test_garner_at_the_corners():
     for p0, p1, p2 in triples:
         F1, F2 = Field(p1), Field(p2)
         inv_p0_mod_p1 = V(pow(p0, -1, p1) * M32 % p1, p1)
-        p0_mod_p2 = V(p0 % p2 * M32 % p2, p2)
         inv_p0p1_mod_p2 = V(pow(p0 * p1, -1, p2) * M32 % p2, p2)
-        cases = [(p0 - 1, p1 - 1, p2 - 1), (0, 0, 0), (p0 - 1, 0, 0), (0, p1 - 1, 0), (0, 0, p2 - 1)]
+        inv_p1_mod_p2 = V(pow(p1, -1, p2) * M32 % p2, p2)
+        one_sub = p0 < 2 * p1 and p0 < 2 * p2 and p1 < 2 * p2  # as the library's host code
+
+        def reduce(F, x):  # a canonical value of a larger prime, reduced modulo F.p
+            return F.csub(x) if one_sub else F.mmul(x, V(F.one, F.p))
+        cases = [(p0 - 1, p1 - 1, p2 - 1), (0, 0, 0), (p0 - 1, 0, 0), (0, p1 - 1, 0), (0, 0, p2 - 1),
+                 (p1, p1 - 1, p2), (p2, 0, p2 - 1)]
+        cases = [(a % p0, b % p1, c % p2) for a, b, c in cases]
         cases += [(rng.randrange(p0), rng.randrange(p1), rng.randrange(p2)) for _ in range(20)]
         for r0, r1, r2 in cases:
-            v1 = F1.mmul(F1.msub(V(r1, p1), F1.mmul(V(r0, M32), V(F1.one, p1))), inv_p0_mod_p1)
-            r0m = F2.mmul(V(r0, M32), V(F2.one, p2))
-            v1p0 = F2.mmul(V(v1.v, M32), p0_mod_p2)
-            v2 = F2.mmul(F2.msub(F2.msub(V(r2, p2), r0m), v1p0), inv_p0p1_mod_p2)
+            r0a, r0b = reduce(F1, V(r0, p0)), reduce(F2, V(r0, p0))
+            v1 = F1.mmul(F1.msub(V(r1, p1), r0a), inv_p0_mod_p1)
+            v1b = reduce(F2, V(v1.v, p1))
+            T = F2.add64(F2.mul64(F2.msub(V(r2, p2), r0b), inv_p0p1_mod_p2),
+                         F2.mul64(V(p2 - v1b.v, p2 + 1), inv_p1_mod_p2))
+            v2 = F2.canon(F2.redc64(T))
             c = r0 + v1.v * p0 + v2.v * p0 * p1
             assert c < p0 * p1 * p2
             assert (c % p0, c % p1, c % p2) == (r0, r1, r2)
