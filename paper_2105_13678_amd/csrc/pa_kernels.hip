@@ -747,6 +747,14 @@ __device__ __forceinline__ void col9_fwd_body(const ColFwdArgs &A, const WG &wg)
             for (int jj = 0; jj < 8; ++jj) lds_word(L9, (sb ^ (1024u * jj)) << 2) = v[jj];
         }
         __syncthreads();
+        // step B's twiddles depend on (t / 16) % 8 only: loaded once, after the
+        // barrier (a barrier waits for loads in flight)
+        uint32_t wb[8];
+        {
+            const uint32_t n1 = (t >> 4) & 7u;
+#pragma unroll
+            for (int s = 1; s < 8; ++s) wb[s] = bload(rtw, (n1 * brev_small(s, 3)) << 5, 0);
+        }
 #pragma unroll 1
         for (uint32_t u = 0; u < 4; ++u) {  // step B
             const uint32_t tau = t + 256u * u;
@@ -755,10 +763,7 @@ __device__ __forceinline__ void col9_fwd_body(const ColFwdArgs &A, const WG &wg)
             uint32_t v[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) v[j] = lds_word(L9, (sb ^ swz_c9(128u * j)) << 2);
-            uint32_t w[8];
-#pragma unroll
-            for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 5, 0);
-            dft_fwd_tw<8>(v, w, M);
+            dft_fwd_tw<8>(v, wb, M);
 #pragma unroll
             for (int j = 0; j < 8; ++j) lds_word(L9, (sb ^ swz_c9(128u * j)) << 2) = v[j];
         }
@@ -1528,33 +1533,50 @@ __device__ __forceinline__ void col9_inv_body(const ColInvArgs &A, const WG &wg)
     const __amdgpu_buffer_rsrc_t rc = rsrc_of(A.Cc + pq * A.N + wg.z * A.Nsub, (uint32_t)A.Nsub);
     const uint32_t c0 = xcd_tile(wg.x, wg.gx) << C9_CLG;
     const uint32_t t = threadIdx.x;
-#pragma unroll 1
-    for (uint32_t u = 0; u < 4; ++u) {  // sub-length 8: rows 8 b + j
-        const uint32_t tau = t + 256u * u;
-        const uint32_t q = tau & 15u, b = tau >> 4;
-        const uint32_t vo = (((8u * b) << A.m2) + c0 + q) << 2;
-        uint32_t v[8];
+    {
+        // sub-length 8: rows 8 b + j.  The launch has few workgroups (three
+        // per CU), so each thread issues the loads of all four tasks before
+        // the first use: one exposed memory latency instead of four.
+        uint32_t v[4][8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = bload(rc, vo, ((uint32_t)j << A.m2) << 2);
-        dft_inv<8>(v, M);
-        const uint32_t sb = swz_c9(128u * b + q);
+        for (uint32_t u = 0; u < 4; ++u) {
+            const uint32_t tau = t + 256u * u;
+            const uint32_t q = tau & 15u, b = tau >> 4;
+            const uint32_t vo = (((8u * b) << A.m2) + c0 + q) << 2;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) lds_word(L9, (sb ^ (16u * j)) << 2) = v[j];
+            for (int j = 0; j < 8; ++j) v[u][j] = bload(rc, vo, ((uint32_t)j << A.m2) << 2);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            const uint32_t tau = t + 256u * u;
+            const uint32_t q = tau & 15u, b = tau >> 4;
+            dft_inv<8>(v[u], M);
+            const uint32_t sb = swz_c9(128u * b + q);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) lds_word(L9, (sb ^ (16u * j)) << 2) = v[u][j];
+        }
     }
     __syncthreads();
-#pragma unroll 1
-    for (uint32_t u = 0; u < 4; ++u) {  // sub-length 64: rows 64 b + n1 + 8 j
-        const uint32_t tau = t + 256u * u;
-        const uint32_t q = tau & 15u, n1 = (tau >> 4) & 7u, b = tau >> 7;
-        const uint32_t sb = swz_c9(1024u * b + 16u * n1 + q);
-        uint32_t v[8], w[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = lds_word(L9, (sb ^ swz_c9(128u * j)) << 2);
+    {
+        // sub-length 64: rows 64 b + n1 + 8 j; the twiddles depend on
+        // (t / 16) % 8 only, loaded once after the barrier
+        uint32_t w[8];
+        const uint32_t n1 = (t >> 4) & 7u;
 #pragma unroll
         for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 5, 0);
-        dft_inv_tw<8>(v, w, M);
+#pragma unroll 1
+        for (uint32_t u = 0; u < 4; ++u) {
+            const uint32_t tau = t + 256u * u;
+            const uint32_t q = tau & 15u, b = tau >> 7;
+            const uint32_t sb = swz_c9(1024u * b + 16u * n1 + q);
+            uint32_t v[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) lds_word(L9, (sb ^ swz_c9(128u * j)) << 2) = v[j];
+            for (int j = 0; j < 8; ++j) v[j] = lds_word(L9, (sb ^ swz_c9(128u * j)) << 2);
+            dft_inv_tw<8>(v, w, M);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) lds_word(L9, (sb ^ swz_c9(128u * j)) << 2) = v[j];
+        }
     }
     __syncthreads();
 #pragma unroll 1
