@@ -410,6 +410,17 @@ pa_status pa_plan_read_profile(pa_plan *plan, double *ms, uint64_t *calls);
  * PA_ERR_DEVICE or PA_OK. */
 pa_status pa_probe_valu(int hip_device, double *bfly_per_s, double *plain_per_s);
 
+/* Measurement utility for the transform design: the rate of lazy radix-2
+ * butterflies modulo the 64-bit prime P = 2^64 - 2^32 + 1, whose 2^m-th roots
+ * of 2 (m <= 26) a single-prime weighted transform (Crandall-Fagin) of the
+ * products mod 2^gamma - 1 would need, on HIP device `hip_device`.  Same
+ * register-only setup as pa_probe_valu; *mul_bfly_per_s receives butterflies
+ * per second with a general 64-bit twiddle product, *shift_bfly_per_s with
+ * twiddles 2^(3j) (those of a 64-point DFT modulo P, 2 having order 192),
+ * whose products are shifts.  Returns PA_ERR_ARG, PA_ERR_NOMEM,
+ * PA_ERR_DEVICE or PA_OK. */
+pa_status pa_probe_goldilocks(int hip_device, double *mul_bfly_per_s, double *shift_bfly_per_s);
+
 /* Map a device status word written by pa_hash_async to a status code. */
 pa_status pa_decode_status(uint32_t flags);
 

@@ -6,12 +6,12 @@ input generators.  Importing the package loads nothing; the library is loaded
 on first use and a missing library is an error, never a fallback.
 """
 from .binding import (PA_FLAG_POW2_LENGTHS, PA_FLAG_RADIX3_LENGTHS, PA_FLAG_RADIX5_LENGTHS, PA_OK, PA_PENDING, PA_RELOAD,  # noqa: F401
-                      BatchPlan, PAError, Plan, Server, decode_status, lib, plan_query, plan_tune, probe_valu,
+                      BatchPlan, PAError, Plan, Server, decode_status, lib, plan_query, plan_tune, probe_goldilocks, probe_valu,
                       status_string)
 
 __all__ = ["Plan", "BatchPlan", "Server", "PAError", "plan_query", "status_string", "decode_status", "lib", "PA_OK",
            "PA_RELOAD", "PA_FLAG_POW2_LENGTHS", "PA_FLAG_RADIX3_LENGTHS", "PA_FLAG_RADIX5_LENGTHS", "plan_tune",
-           "probe_valu", "to_device", "from_device"]
+           "probe_goldilocks", "probe_valu", "to_device", "from_device"]
 
 
 def to_device(words, device="cuda"):

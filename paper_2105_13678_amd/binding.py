@@ -138,6 +138,9 @@ def lib():
         L.pa_poll.restype = ctypes.c_int
         L.pa_probe_valu.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.pa_probe_valu.restype = ctypes.c_int
+        L.pa_probe_goldilocks.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double)]
+        L.pa_probe_goldilocks.restype = ctypes.c_int
         L.pa_decode_status.argtypes = [ctypes.c_uint32]
         L.pa_decode_status.restype = ctypes.c_int
         L.pa_status_string.argtypes = [ctypes.c_int]
@@ -180,6 +183,16 @@ def probe_valu(device: int = 0):
     if st != PA_OK:
         raise PAError(st, "pa_probe_valu")
     return b.value, p.value
+
+
+def probe_goldilocks(device: int = 0):
+    """pa_probe_goldilocks: (butterflies per second with a general twiddle
+    product, with shift twiddles) modulo 2^64 - 2^32 + 1."""
+    m, s = ctypes.c_double(), ctypes.c_double()
+    st = lib().pa_probe_goldilocks(int(device), ctypes.byref(m), ctypes.byref(s))
+    if st != PA_OK:
+        raise PAError(st, "pa_probe_goldilocks")
+    return m.value, s.value
 
 
 def plan_tune(n: int, r: int, reps: int = 5, device: int = 0, gamma: int = 0, B: int = 0, flags: int = 0,
