@@ -15,7 +15,9 @@ its launches in the last tenth of the timed steps; HBM bytes per launch from the
 summary when it was taken on the current sources, else null), `batched`
 (the uneven-batch workload: 64 blocks in one pa_hash_batched call against
 the same blocks as 64 serial calls, outputs checked against the oracle's
-stored digests) and `cpu_baseline` (the CPU oracle on the same block, its
+stored digests), `paper_block` (the block the paper times: gamma =
+25,964,951, k = 10, ratio 0.0972; the paper's 261 Mbit/s on a 4-core laptop
+CPU beside it, another machine) and `cpu_baseline` (the CPU oracle on the same block, its
 k products on min(k, nproc) threads; a single-thread sample and the Python
 definition on the 2^20-bit block beside it).
 
@@ -136,6 +138,42 @@ def small_block(pa, synth, dev, K):
     plan.close()
     return {"us_per_block": round(us, 1), "value": round(n / (us / 1e6) / 1e6, 1), "unit": "Mbit/s",
             "N": info["N"], "verified_vs_oracle_digest": ok}
+
+
+def paper_block(pa, synth, dev, K):
+    """The block the paper times (Sec. 4, Table 6: 2.6e8 bits, compression
+    ratio 0.0972, k = 10; gamma = 25,964,951 is inferred, 10 gamma = n =
+    259,649,510), K back-to-back hashes on one stream, checked against the
+    oracle's stored digest.  Context for the paper's own figure, which was
+    taken on another machine (a 4-core laptop CPU)."""
+    import torch
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "full_size.json")))["paper_cv_block"]
+    n, r = gold["n"], gold["r"]
+    st, info = pa.plan_query(n, r)
+    assert st == 0 and (info["gamma"], info["k"]) == (gold["gamma"], gold["k"]), info
+    blk = synth.single_block(gold["seed"], n, r, info["gamma"], info["k"])
+    key, a, b, c = (pa.to_device(x, dev) for x in (blk.key, blk.a, blk.b, blk.c))
+    plan = pa.Plan(n, r, device=0)
+    out = plan.new_out()
+    ds = torch.zeros(K + 10, dtype=torch.int32, device=dev)
+    for i in range(10):
+        plan.hash_async(key, a, b, c, out, ds[i:i + 1])
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(K):
+        plan.hash_async(key, a, b, c, out, ds[10 + i:11 + i])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / K
+    assert (ds.cpu().numpy() == 0).all()
+    ok = hashlib.sha256(pa.from_device(out).tobytes()).hexdigest() == gold["out_sha256"]
+    plan.close()
+    return {"n": n, "r": r, "gamma": info["gamma"], "k": info["k"], "N": info["N"], "ms_per_block": round(ms, 4),
+            "value": round(n / (ms / 1e3) / 1e6, 1), "unit": "Mbit/s", "verified_vs_oracle_digest": ok,
+            "paper_value_other_machine": {"value": 261, "unit": "Mbit/s",
+                                          "hardware": "4-core laptop CPU (GMP), the paper's Table 6"}}
 
 
 def kernel_name(phase, info):
@@ -868,6 +906,7 @@ def main():
         rec["pipelined"] = pipelined(pa, plan, key, a, b, c, K, args.pipeline, dev, gold_digest=gold_digest)
     if not args.core_only:
         rec["small_block_2p20"] = small_block(pa, synth, dev, max(K, 2000))
+        rec["paper_block"] = paper_block(pa, synth, dev, K)
     if not args.core_only and not args.no_batched:
         blocks, bufs = batched_blocks(pa, synth, dev)
         leg, bp = batched_leg(pa, blocks, bufs, dev, max(5, min(K // 2, 50)), 2)
