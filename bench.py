@@ -753,12 +753,14 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed region, copy a buffer of this many MiB with a plain device "
                          "copy kernel (reference point for the HBM byte counters)")
-    ap.add_argument("--workload", choices=["single", "batched", "serving", "lengths", "rule"], default="single",
+    ap.add_argument("--workload", choices=["single", "batched", "serving", "lengths", "rule", "small"],
+                    default="single",
                     help="single: the 2.6e8-bit block (the headline); batched: 64 uneven blocks in one "
                          "pa_hash_batched call against the same blocks as serial calls; serving: Poisson "
                          "arrivals from 16 sessions through the serving loop (latency percentiles); lengths: "
                          "the 8e8-, 2^32- and 5e8-bit blocks with transform lengths 3 * 2^m against 2^m; rule: "
-                         "the plan rule's length form against device timings of both forms per class")
+                         "the plan rule's length form against device timings of the three forms per class; "
+                         "small: only the 2^20-bit block, K hashes (for a profiler)")
     ap.add_argument("--requests", type=int, default=600, help="serving: number of Poisson arrivals")
     ap.add_argument("--block", type=int, choices=range(len(LENGTH_BLOCKS)), default=None,
                     help="lengths: run only this block (0: 8e8 bits, 1: 2^32 bits, 2: 5e8 bits)")
@@ -784,6 +786,13 @@ def main():
         return bench_lengths(args)
     if args.workload == "rule":
         return bench_rule(args)
+    if args.workload == "small":
+        import torch
+        import paper_2105_13678_amd as pa
+        from paper_2105_13678_amd import synth
+        print(json.dumps({"small_block_2p20": small_block(pa, synth, torch.device("cuda", 0), args.steps)}),
+              flush=True)
+        return None
 
     import torch
     import paper_2105_13678_amd as pa
