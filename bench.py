@@ -187,7 +187,15 @@ def kernel_name(phase, info):
     m1, m2, rf = info["log2N1"], info["log2N2"], info["len_factor"]
     mix = rf == 3
     if phase.endswith("_row"):
-        return f"k_row16<{stage}>" if m2 == 12 else f"k_row<{stage}>"
+        if m2 == 12:
+            return f"k_row16<{stage}>"
+        # the generic row kernel: pair groups of N2/8 threads (or one group of
+        # max(64, N2/16)); groups of at most a wavefront use its wave-synchronised form
+        npairs = info["k"] if stage == 0 else 1
+        t8 = (1 << m2) // 8
+        groups = min(npairs, 256 // t8) if 0 < t8 < 256 else 1
+        tg = t8 if groups > 1 else max(64, (1 << m2) // 16)
+        return f"k_row<{stage}, {'true' if tg <= 64 else 'false'}>"
     if phase.endswith("_colinv"):
         if m1 == 9 and m2 >= 4:
             return f"k_col9_inv<{stage}>"

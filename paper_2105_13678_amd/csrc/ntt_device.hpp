@@ -246,22 +246,37 @@ __device__ __forceinline__ void inv_task(uint32_t *buf, uint32_t task, uint32_t 
     for (int j = 0; j < R; ++j) buf[tile_swz(((base + ((uint32_t)j << lgMp)) << cnt_lg) + q, cnt_lg)] = v[j];
 }
 
-template <int R, bool TW>
+// The synchronisation between two LDS steps: the workgroup's barrier, or
+// (WS) only the calling wavefront's, when every thread that shares the
+// buffer is in that wavefront: its LDS accesses are then ordered by the
+// wavefront-scope fences alone.
+template <bool WS>
+__device__ __forceinline__ void step_sync() {
+    if constexpr (WS) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+template <int R, bool TW, bool WS = false>
 __device__ __forceinline__ void fwd_step(uint32_t *buf, uint32_t lg, uint32_t lgM, uint32_t cnt_lg,
                                          const uint32_t *__restrict__ tw, const PrimeConst &M, uint32_t tid,
                                          uint32_t nt) {
     const uint32_t ntask = (1u << (lg - Lg<R>::v)) << cnt_lg;
     for (uint32_t t = tid; t < ntask; t += nt) fwd_task<R, TW>(buf, t, lg, lgM, cnt_lg, tw, M);
-    __syncthreads();
+    step_sync<WS>();
 }
 
-template <int R, bool TW>
+template <int R, bool TW, bool WS = false>
 __device__ __forceinline__ void inv_step(uint32_t *buf, uint32_t lg, uint32_t lgM, uint32_t cnt_lg,
                                          const uint32_t *__restrict__ twi, const PrimeConst &M, uint32_t tid,
                                          uint32_t nt) {
     const uint32_t ntask = (1u << (lg - Lg<R>::v)) << cnt_lg;
     for (uint32_t t = tid; t < ntask; t += nt) inv_task<R, TW>(buf, t, lg, lgM, cnt_lg, twi, M);
-    __syncthreads();
+    step_sync<WS>();
 }
 
 // Sub-length of the last (twiddle-free) step of a length-2^lg transform:
@@ -290,33 +305,35 @@ __device__ __forceinline__ void inv_middle_steps(uint32_t *buf, uint32_t lg, uin
 // Forward steps of a length-2^lg transform from sub-length 2^first_lgM down:
 // radix-8 while at least 3 bits remain, then one radix-2 or radix-4 step at
 // the bottom (whose twiddles are all 1).
+template <bool WS = false>
 __device__ __forceinline__ void fwd_steps_from(uint32_t *buf, uint32_t lg, uint32_t first_lgM, uint32_t cnt_lg,
                                                const uint32_t *__restrict__ tw, const PrimeConst &M, uint32_t tid,
                                                uint32_t nt) {
     uint32_t lgM = first_lgM;
     while (lgM >= 3) {
         if (lgM > 3)
-            fwd_step<8, true>(buf, lg, lgM, cnt_lg, tw, M, tid, nt);
+            fwd_step<8, true, WS>(buf, lg, lgM, cnt_lg, tw, M, tid, nt);
         else
-            fwd_step<8, false>(buf, lg, lgM, cnt_lg, tw, M, tid, nt);
+            fwd_step<8, false, WS>(buf, lg, lgM, cnt_lg, tw, M, tid, nt);
         lgM -= 3;
     }
-    if (lgM == 2) fwd_step<4, false>(buf, lg, 2, cnt_lg, tw, M, tid, nt);
-    if (lgM == 1) fwd_step<2, false>(buf, lg, 1, cnt_lg, tw, M, tid, nt);
+    if (lgM == 2) fwd_step<4, false, WS>(buf, lg, 2, cnt_lg, tw, M, tid, nt);
+    if (lgM == 1) fwd_step<2, false, WS>(buf, lg, 1, cnt_lg, tw, M, tid, nt);
 }
 
 // Inverse steps bottom-up, up to and including sub-length 2^last_lgM.
+template <bool WS = false>
 __device__ __forceinline__ void inv_steps_to(uint32_t *buf, uint32_t lg, uint32_t last_lgM, uint32_t cnt_lg,
                                              const uint32_t *__restrict__ twi, const PrimeConst &M, uint32_t tid,
                                              uint32_t nt) {
     const uint32_t r = lg % 3;
-    if (r == 2) inv_step<4, false>(buf, lg, 2, cnt_lg, twi, M, tid, nt);
-    if (r == 1) inv_step<2, false>(buf, lg, 1, cnt_lg, twi, M, tid, nt);
+    if (r == 2) inv_step<4, false, WS>(buf, lg, 2, cnt_lg, twi, M, tid, nt);
+    if (r == 1) inv_step<2, false, WS>(buf, lg, 1, cnt_lg, twi, M, tid, nt);
     for (uint32_t lgM = r + 3; lgM <= last_lgM; lgM += 3) {
         if (lgM > 3)
-            inv_step<8, true>(buf, lg, lgM, cnt_lg, twi, M, tid, nt);
+            inv_step<8, true, WS>(buf, lg, lgM, cnt_lg, twi, M, tid, nt);
         else
-            inv_step<8, false>(buf, lg, lgM, cnt_lg, twi, M, tid, nt);
+            inv_step<8, false, WS>(buf, lg, lgM, cnt_lg, twi, M, tid, nt);
     }
 }
 

@@ -953,6 +953,7 @@ struct RowArgs {
 
 // First forward step of a row straight from global memory: four-step
 // twiddle on load, radix-8 DFT, step twiddles, into LDS.
+template <bool WS = false>
 __device__ __forceinline__ void row_first_step(const uint32_t *__restrict__ g, const uint32_t *__restrict__ w,
                                                uint32_t *buf, uint32_t lg, const uint32_t *__restrict__ tw,
                                                const PrimeConst &M, uint32_t tid, uint32_t nt) {
@@ -975,7 +976,7 @@ __device__ __forceinline__ void row_first_step(const uint32_t *__restrict__ g, c
 #pragma unroll
         for (int j = 0; j < 8; ++j) buf[swz(n1 + ((uint32_t)j << lgMp))] = v[j];
     }
-    __syncthreads();
+    step_sync<WS>();
 }
 
 // Last inverse step of a row straight to global memory (with the inverse
@@ -1013,7 +1014,10 @@ __device__ __forceinline__ void row_last_inv_step(const uint32_t *buf, uint32_t 
 // pairs i = g (mod G) with its own LDS row, and the groups' sums are added
 // before the inverse transform (all threads pass the same barriers: a group
 // without a pair in a round transforms a stand-in pair and discards it).
-template <int Stage>
+// WS: every group lies in one wavefront (A.row_group <= 64), so the steps of
+// a group synchronise that wavefront only; the groups' sums meet at one
+// workgroup barrier, and group 0 runs the inverse transform alone.
+template <int Stage, bool WS>
 __device__ __forceinline__ void row_body(const RowArgs &A, const WG &wg) {
     uint32_t *lds = lds_dyn;
     const uint32_t pq = wg.y;
@@ -1040,22 +1044,22 @@ __device__ __forceinline__ void row_body(const RowArgs &A, const WG &wg) {
         const uint64_t i = active ? i0 + g : A.npairs - 1;
         const uint32_t *xrow = A.X + i * A.pair_stride + pq * A.N + rbase;
         const uint32_t *arow = A.A + i * A.pair_stride + pq * A.N + rbase;
-        row_first_step(xrow, wf, buf, lg, twf, M, tg, Tg);
-        fwd_steps_from(buf, lg, lg - 3, 0, twf, M, tg, Tg);
+        row_first_step<WS>(xrow, wf, buf, lg, twf, M, tg, Tg);
+        fwd_steps_from<WS>(buf, lg, lg - 3, 0, twf, M, tg, Tg);
 #pragma unroll
         for (int q = 0; q < ROW_EPT; ++q) {
             uint32_t e = tg + q * Tg;
             if (e < N2) xr[q] = buf[swz(e)];
         }
-        __syncthreads();
-        row_first_step(arow, wf, buf, lg, twf, M, tg, Tg);
-        fwd_steps_from(buf, lg, lg - 3, 0, twf, M, tg, Tg);
+        step_sync<WS>();
+        row_first_step<WS>(arow, wf, buf, lg, twf, M, tg, Tg);
+        fwd_steps_from<WS>(buf, lg, lg - 3, 0, twf, M, tg, Tg);
 #pragma unroll
         for (int q = 0; q < ROW_EPT; ++q) {
             uint32_t e = tg + q * Tg;
             if (active && e < N2) acc[q] = red2(acc[q] + mont(xr[q], buf[swz(e)], M), M);
         }
-        __syncthreads();
+        step_sync<WS>();
     }
 #pragma unroll
     for (int q = 0; q < ROW_EPT; ++q) {
@@ -1076,19 +1080,25 @@ __device__ __forceinline__ void row_body(const RowArgs &A, const WG &wg) {
         }
         __syncthreads();
     }
-    inv_steps_to(lds, lg, lg - 3, 0, twi, M, threadIdx.x, T);
-    row_last_inv_step(lds, A.out + pq * A.N + rbase, A.Wi + pq * A.N + rbase, lg, twi, M, threadIdx.x, T);
+    if constexpr (WS) {  // group 0, one wavefront
+        if (threadIdx.x >= Tg) return;
+        inv_steps_to<true>(lds, lg, lg - 3, 0, twi, M, threadIdx.x, Tg);
+        row_last_inv_step(lds, A.out + pq * A.N + rbase, A.Wi + pq * A.N + rbase, lg, twi, M, threadIdx.x, Tg);
+    } else {
+        inv_steps_to(lds, lg, lg - 3, 0, twi, M, threadIdx.x, T);
+        row_last_inv_step(lds, A.out + pq * A.N + rbase, A.Wi + pq * A.N + rbase, lg, twi, M, threadIdx.x, T);
+    }
 }
 
-template <int Stage>
-__global__ __launch_bounds__(ROW_MAX_THREADS) void k_row(RowArgs A) { row_body<Stage>(A, wg_self()); }
+template <int Stage, bool WS>
+__global__ __launch_bounds__(ROW_MAX_THREADS) void k_row(RowArgs A) { row_body<Stage, WS>(A, wg_self()); }
 
-template <int Stage>
+template <int Stage, bool WS>
 __global__ __launch_bounds__(ROW_MAX_THREADS) void km_row(const RowArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
                                      const uint16_t *__restrict__ owner) {
     WG wg;
     const uint32_t i = wg_multi(geo, owner, wg);
-    if (i != MULTI_NONE) row_body<Stage>(tab[i], wg);
+    if (i != MULTI_NONE) row_body<Stage, WS>(tab[i], wg);
 }
 
 // ---- 4096-point rows: three register radix-16 steps --------------------------
@@ -2840,8 +2850,13 @@ static void launch_row(pa_plan *p, const RowArgs &ra, hipStream_t st) {
         emit(p, step, PA_KERN(row16, Stage), dim3(rows, NPRIMES), dim3(R16_THREADS), 0, ra, st);
     } else {
         const unsigned groups = row_groups(p, ra.npairs);
-        emit(p, step, PA_KERN(row, Stage), dim3(rows, NPRIMES), dim3(groups * ra.row_group),
-             (size_t)groups * 4 << p->m2, ra, st);
+        // groups of at most a wavefront synchronise their steps within it
+        if (ra.row_group <= 64)
+            emit(p, step, PA_KERN(row, Stage, true), dim3(rows, NPRIMES), dim3(groups * ra.row_group),
+                 (size_t)groups * 4 << p->m2, ra, st);
+        else
+            emit(p, step, PA_KERN(row, Stage, false), dim3(rows, NPRIMES), dim3(groups * ra.row_group),
+                 (size_t)groups * 4 << p->m2, ra, st);
     }
 }
 
