@@ -101,4 +101,4 @@ def dump_asm(out_dir: str) -> None:
 if __name__ == "__main__":
     print(build(verbose=True))
     if "--asm" in sys.argv:
-        dump_asm(os.path.join(ROOT, "_work", "asm"))
+        dump_asm(os.path.join(ROOT, "build", "asm"))  # build/ is not tracked
