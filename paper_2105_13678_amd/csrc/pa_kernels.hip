@@ -1532,6 +1532,11 @@ __device__ void block_scan(CFn f, CFn &excl, CFn &total) {
 // the sub-length-512 step straight back to global memory as canonical
 // residues.  Inverse twiddles multiply a task's inputs (fused into the first
 // DIT stage).
+// 512 threads, two of the tile's 1024 tasks each (task index tau = t + 512 u,
+// u < 2): the launch is a single round of workgroups, so a shorter chain per
+// thread finishes it sooner.
+constexpr uint32_t C9I_THREADS = 512, C9I_TASKS = 1024 / C9I_THREADS;
+
 template <int Stage>
 __device__ __forceinline__ void col9_inv_body(const ColInvArgs &A, const WG &wg) {
     __shared__ uint32_t L9[1u << (C9_LG + C9_CLG)];  // one 512 x 16 tile
@@ -1545,12 +1550,12 @@ __device__ __forceinline__ void col9_inv_body(const ColInvArgs &A, const WG &wg)
     const uint32_t t = threadIdx.x;
     {
         // sub-length 8: rows 8 b + j.  The launch has few workgroups (three
-        // per CU), so each thread issues the loads of all four tasks before
-        // the first use: one exposed memory latency instead of four.
-        uint32_t v[4][8];
+        // per CU), so each thread issues the loads of both its tasks before
+        // the first use: one exposed memory latency instead of two.
+        uint32_t v[C9I_TASKS][8];
 #pragma unroll
-        for (uint32_t u = 0; u < 4; ++u) {
-            const uint32_t tau = t + 256u * u;
+        for (uint32_t u = 0; u < C9I_TASKS; ++u) {
+            const uint32_t tau = t + C9I_THREADS * u;
             const uint32_t q = tau & 15u, b = tau >> 4;
             const uint32_t vo = (((8u * b) << A.m2) + c0 + q) << 2;
 #pragma unroll
@@ -1558,8 +1563,8 @@ __device__ __forceinline__ void col9_inv_body(const ColInvArgs &A, const WG &wg)
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (uint32_t u = 0; u < 4; ++u) {
-            const uint32_t tau = t + 256u * u;
+        for (uint32_t u = 0; u < C9I_TASKS; ++u) {
+            const uint32_t tau = t + C9I_THREADS * u;
             const uint32_t q = tau & 15u, b = tau >> 4;
             dft_inv<8>(v[u], M);
             const uint32_t sb = swz_c9(128u * b + q);
@@ -1576,8 +1581,8 @@ __device__ __forceinline__ void col9_inv_body(const ColInvArgs &A, const WG &wg)
 #pragma unroll
         for (int s = 1; s < 8; ++s) w[s] = bload(rtw, (n1 * brev_small(s, 3)) << 5, 0);
 #pragma unroll 1
-        for (uint32_t u = 0; u < 4; ++u) {
-            const uint32_t tau = t + 256u * u;
+        for (uint32_t u = 0; u < C9I_TASKS; ++u) {
+            const uint32_t tau = t + C9I_THREADS * u;
             const uint32_t q = tau & 15u, b = tau >> 7;
             const uint32_t sb = swz_c9(1024u * b + 16u * n1 + q);
             uint32_t v[8];
@@ -1590,8 +1595,8 @@ __device__ __forceinline__ void col9_inv_body(const ColInvArgs &A, const WG &wg)
     }
     __syncthreads();
 #pragma unroll 1
-    for (uint32_t u = 0; u < 4; ++u) {  // sub-length 512: rows n1 + 64 j, to global memory
-        const uint32_t tau = t + 256u * u;
+    for (uint32_t u = 0; u < C9I_TASKS; ++u) {  // sub-length 512: rows n1 + 64 j, to global memory
+        const uint32_t tau = t + C9I_THREADS * u;
         const uint32_t q = tau & 15u, n1 = tau >> 4;
         const uint32_t sb = swz_c9(tau);
         uint32_t v[8], w[8];
@@ -1609,10 +1614,10 @@ __device__ __forceinline__ void col9_inv_body(const ColInvArgs &A, const WG &wg)
 }
 
 template <int Stage>
-__global__ __launch_bounds__(COL_THREADS) void k_col9_inv(ColInvArgs A) { col9_inv_body<Stage>(A, wg_self()); }
+__global__ __launch_bounds__(C9I_THREADS) void k_col9_inv(ColInvArgs A) { col9_inv_body<Stage>(A, wg_self()); }
 
 template <int Stage>
-__global__ __launch_bounds__(COL_THREADS) void km_col9_inv(const ColInvArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
+__global__ __launch_bounds__(C9I_THREADS) void km_col9_inv(const ColInvArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
                                      const uint16_t *__restrict__ owner) {
     WG wg;
     const uint32_t i = wg_multi(geo, owner, wg);
@@ -2879,7 +2884,7 @@ static void launch_col_inv(pa_plan *p, const ColInvArgs &ci, hipStream_t st) {
     const unsigned nsub = p->rf;  // grid z: transform of the radix-3 or radix-5 split
     const int step = Stage == STAGE_MMH ? SP_MMH_COLINV : SP_MH_COLINV;
     if (p->m1 == C9_LG && p->m2 >= C9_CLG)
-        emit(p, step, PA_KERN(col9_inv, Stage), dim3(1u << (p->m2 - C9_CLG), NPRIMES, nsub), dim3(COL_THREADS), 0,
+        emit(p, step, PA_KERN(col9_inv, Stage), dim3(1u << (p->m2 - C9_CLG), NPRIMES, nsub), dim3(C9I_THREADS), 0,
              ci, st);
     else if (p->m1 == C10_LG && p->m2 >= C10_CLG)
         emit(p, step, PA_KERN(col10_inv, Stage), dim3(1u << (p->m2 - C10_CLG), NPRIMES, nsub), dim3(COL_THREADS),
