@@ -1253,15 +1253,122 @@ __device__ __forceinline__ void row16_body(const RowArgs &A, const WG &wg) {
     for (int j = 0; j < 16; ++j) bstore(mont(v[j], wv[j], M), ro, t4, 1024u * j);
 }
 
+// The MH stage's row pass multiplies one pair: the x row's spectrum stays in
+// registers while the seed row goes through the same LDS buffer, so a
+// workgroup holds one row buffer (17 KiB) and no 64-bit accumulators, and
+// more workgroups fit on a CU.  Thread mapping, LDS layout and tables as in
+// row16_body.
+__device__ __forceinline__ void row16_single_body(const RowArgs &A, const WG &wg) {
+    __shared__ uint32_t L16[R16_PLEN];
+    const uint32_t pq = wg.y;
+    const PrimeConst M = A.P.c[pq];
+    const uint32_t t = threadIdx.x;
+    const uint32_t rho = xcd_tile(wg.x, wg.gx);
+    const uint64_t rbase = (uint64_t)rho * R16_LEN;
+    const uint32_t t4 = t * 4u;
+    const uint32_t s1b = 4u * (t + (t >> 4));
+    const uint32_t s2b = 4u * (272u * (t >> 4) + (t & 15u));
+    const uint32_t s3b = 68u * t;
+    const uint32_t n1b = t & 15u;
+    const __amdgpu_buffer_rsrc_t rw = rsrc_of(A.Wf + pq * A.N + rbase, R16_LEN);
+    const __amdgpu_buffer_rsrc_t rt = rsrc_of(A.r16f + pq * R16_TW, R16_TW);
+    uint32_t vx[16], v[16];
+#pragma unroll 1
+    for (int side = 0; side < 2; ++side) {
+        const __amdgpu_buffer_rsrc_t rg = rsrc_of((side ? A.A : A.X) + pq * A.N + rbase, R16_LEN);
+        const uint32_t t4l = opaque(t4), a1 = opaque(s1b), a2 = opaque(s2b), a3 = opaque(s3b);
+        if (side) __syncthreads();  // every thread has read the x row's last step
+        // step 1: from global, four-step twiddle (reloaded per side: 16
+        // registers fewer), radix-16, step twiddles
+        uint32_t w[16], wv[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = bload(rg, t4l, 1024u * j);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) wv[j] = bload(rw, t4l, 1024u * j);
+#pragma unroll
+        for (int j = 1; j < 16; ++j) w[j] = bload(rt, t4l, 1024u * j);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = mont(v[j], wv[j], M);
+        dft_fwd_tw<16>(v, w, M);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) lds_word(L16, a1 + 1088u * j) = v[j];
+        __syncthreads();
+        // step 2: radix-16 on stride 16, step twiddles
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = lds_word(L16, a2 + 68u * j);
+#pragma unroll
+        for (int j = 1; j < 16; ++j) w[j] = bload(rt, 4u * n1b, 16384u + 64u * j);
+        __builtin_amdgcn_sched_barrier(0);
+        dft_fwd_tw<16>(v, w, M);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) lds_word(L16, a2 + 68u * j) = v[j];
+        __syncthreads();
+        // step 3: radix-16 on 16 consecutive values (this thread's own words)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = lds_word(L16, a3 + 4u * j);
+        dft_fwd<16>(v, M);
+        if (side == 0) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) vx[j] = v[j];
+        }
+    }
+    // the pointwise product: both factors below 2p, the product below 4p^2,
+    // its reduction below 2p
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = red2(redc64((uint64_t)vx[j] * v[j], M), M);
+
+    // inverse: step 3 (this thread's own words), step 2, step 1 to global
+    const __amdgpu_buffer_rsrc_t rti = rsrc_of(A.r16i + pq * R16_TW, R16_TW);
+    dft_inv<16>(v, M);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) lds_word(L16, s3b + 4u * j) = v[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = lds_word(L16, s2b + 68u * j);
+    uint32_t w[16];
+#pragma unroll
+    for (int s = 1; s < 16; ++s) w[s] = bload(rti, 4u * n1b, 16384u + 64u * s);
+    __builtin_amdgcn_sched_barrier(0);
+    dft_inv_tw<16>(v, w, M);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) lds_word(L16, s2b + 68u * j) = v[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = lds_word(L16, s1b + 1088u * j);
+    const __amdgpu_buffer_rsrc_t ro = rsrc_of(A.out + pq * A.N + rbase, R16_LEN);
+    const __amdgpu_buffer_rsrc_t rwi = rsrc_of(A.Wi + pq * A.N + rbase, R16_LEN);
+    uint32_t wv[16];
+#pragma unroll
+    for (int s = 1; s < 16; ++s) w[s] = bload(rti, t4, 1024u * s);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) wv[j] = bload(rwi, t4, 1024u * j);
+    __builtin_amdgcn_sched_barrier(0);
+    dft_inv_tw<16>(v, w, M);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) bstore(mont(v[j], wv[j], M), ro, t4, 1024u * j);
+}
+
+// The MMH stage (k pairs) runs row16_body, the MH stage (one pair)
+// row16_single_body, at up to four and six waves per SIMD.
+constexpr int r16_waves(int stage) { return stage == STAGE_MH ? 6 : 4; }
 template <int Stage>
-__global__ __launch_bounds__(R16_THREADS, 4) void k_row16(RowArgs A) { row16_body<Stage>(A, wg_self()); }
+__device__ __forceinline__ void row16_stage_body(const RowArgs &A, const WG &wg) {
+    if constexpr (Stage == STAGE_MH)
+        row16_single_body(A, wg);
+    else
+        row16_body<Stage>(A, wg);
+}
 
 template <int Stage>
-__global__ __launch_bounds__(R16_THREADS, 4) void km_row16(const RowArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
+__global__ __launch_bounds__(R16_THREADS, r16_waves(Stage)) void k_row16(RowArgs A) { row16_stage_body<Stage>(A, wg_self()); }
+
+template <int Stage>
+__global__ __launch_bounds__(R16_THREADS, r16_waves(Stage)) void km_row16(const RowArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
                                      const uint16_t *__restrict__ owner) {
     WG wg;
     const uint32_t i = wg_multi(geo, owner, wg);
-    if (i != MULTI_NONE) row16_body<Stage>(tab[i], wg);
+    if (i != MULTI_NONE) row16_stage_body<Stage>(tab[i], wg);
 }
 
 struct ColInvArgs {
