@@ -644,7 +644,7 @@ __global__ __launch_bounds__(COL_THREADS) void km_col_fwd(const ColFwdArgs *__re
 // A workgroup unpacks its tile's limbs once and transforms them for each of
 // the three primes in turn (and, for N = 3 Nsub, for each of the three
 // transforms of the radix-3 split: nine transforms per unpack).
-// Three radix-8 steps; task index tau = t + 256 u (u < 4) in every step:
+// Three radix-8 steps; task index tau = t + T u (u < 1024 / T) in every step:
 //   step A (sub-length 512, stride 64): q = tau & 15, n1 = tau >> 4, rows
 //          n1 + 64 j; from the unpacked limbs (power-of-two N: rows >= 256
 //          are padding; N = 3 Nsub: all rows carry x_n, rows < 256 also
@@ -660,10 +660,16 @@ constexpr uint32_t C9_LG = 9, C9_CLG = 4;
 
 __device__ __forceinline__ constexpr uint32_t swz_c9(uint32_t i) { return i ^ (((i >> 7) & 3u) << 4); }
 
+// Threads of a 512-row forward tile: 512 (two tasks each) for the MH stage's
+// power-of-two lengths, whose 3 x (one or two) arrays of tiles exceed one round
+// of workgroups; 256 (four tasks each) otherwise, which measured faster there.
+constexpr uint32_t c9f_threads(int stage, bool mix) { return stage == STAGE_MH && !mix ? 512u : 256u; }
+
 template <int Stage, bool MIX>
 __device__ __forceinline__ void col9_fwd_body(const ColFwdArgs &A, const WG &wg) {
     constexpr uint32_t NSUB = MIX ? 3u : 1u;
     constexpr int X0_ROWS = MIX ? 8 : 4;  // step-A rows of a task holding x_n (x_(n+Nsub): rows < 4)
+    constexpr uint32_t T = c9f_threads(Stage, MIX), U = 1024u / T;  // threads, tasks per thread
     __shared__ uint32_t L9[1u << (C9_LG + C9_CLG)];  // one 512 x 16 tile
     const uint32_t tile = xcd_tile(wg.x, wg.gx);
     const uint32_t arr = wg.y + A.arr0;
@@ -673,14 +679,14 @@ __device__ __forceinline__ void col9_fwd_body(const ColFwdArgs &A, const WG &wg)
     const uint32_t t = threadIdx.x;
     const uint32_t Ns = (uint32_t)A.Nsub;
     // the tile's limbs of the four step-A tasks, unpacked once
-    uint32_t x[4][X0_ROWS], x1[4][MIX ? 4 : 1];
+    uint32_t x[U][X0_ROWS], x1[U][MIX ? 4 : 1];
     {
         const LimbSrc S = limb_src(A, arr);
         const uint32_t L = (uint32_t)A.L;
         bool not_ones = false;
 #pragma unroll
-        for (uint32_t u = 0; u < 4; ++u) {
-            const uint32_t tau = t + 256u * u;
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t tau = t + T * u;
             const uint32_t q = tau & 15u, n1 = tau >> 4;
 #pragma unroll
             for (int jj = 0; jj < X0_ROWS; ++jj) {
@@ -721,8 +727,8 @@ __device__ __forceinline__ void col9_fwd_body(const ColFwdArgs &A, const WG &wg)
         if (it != it0) __syncthreads();  // the previous transform's last step has read the buffer
         const uint32_t tl = MIX ? opaque(t) : t;  // radix-3 split: recompute the task addresses per transform
 #pragma unroll
-        for (uint32_t u = 0; u < 4; ++u) {  // step A
-            const uint32_t tau = tl + 256u * u;
+        for (uint32_t u = 0; u < U; ++u) {  // step A
+            const uint32_t tau = tl + T * u;
             const uint32_t n1 = tau >> 4;
             uint32_t v[8], w[8];
             if constexpr (MIX) {
@@ -756,8 +762,8 @@ __device__ __forceinline__ void col9_fwd_body(const ColFwdArgs &A, const WG &wg)
             for (int s = 1; s < 8; ++s) wb[s] = bload(rtw, (n1 * brev_small(s, 3)) << 5, 0);
         }
 #pragma unroll 1
-        for (uint32_t u = 0; u < 4; ++u) {  // step B
-            const uint32_t tau = t + 256u * u;
+        for (uint32_t u = 0; u < U; ++u) {  // step B
+            const uint32_t tau = t + T * u;
             const uint32_t q = tau & 15u, n1 = (tau >> 4) & 7u, b = tau >> 7;
             const uint32_t sb = swz_c9(1024u * b + 16u * n1 + q);
             uint32_t v[8];
@@ -769,8 +775,8 @@ __device__ __forceinline__ void col9_fwd_body(const ColFwdArgs &A, const WG &wg)
         }
         __syncthreads();
 #pragma unroll 1
-        for (uint32_t u = 0; u < 4; ++u) {  // step C
-            const uint32_t tau = t + 256u * u;
+        for (uint32_t u = 0; u < U; ++u) {  // step C
+            const uint32_t tau = t + T * u;
             const uint32_t q = tau & 15u, b = tau >> 4;
             const uint32_t sb = swz_c9(128u * b + q);
             uint32_t v[8];
@@ -786,10 +792,10 @@ __device__ __forceinline__ void col9_fwd_body(const ColFwdArgs &A, const WG &wg)
 }
 
 template <int Stage, bool MIX>
-__global__ __launch_bounds__(COL_THREADS) void k_col9_fwd(ColFwdArgs A) { col9_fwd_body<Stage, MIX>(A, wg_self()); }
+__global__ __launch_bounds__(c9f_threads(Stage, MIX)) void k_col9_fwd(ColFwdArgs A) { col9_fwd_body<Stage, MIX>(A, wg_self()); }
 
 template <int Stage, bool MIX>
-__global__ __launch_bounds__(COL_THREADS) void km_col9_fwd(const ColFwdArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
+__global__ __launch_bounds__(c9f_threads(Stage, MIX)) void km_col9_fwd(const ColFwdArgs *__restrict__ tab, const MultiGeo *__restrict__ geo,
                                      const uint16_t *__restrict__ owner) {
     WG wg;
     const uint32_t i = wg_multi(geo, owner, wg);
@@ -2925,9 +2931,9 @@ static void launch_col_fwd(pa_plan *p, const ColFwdArgs &cf, unsigned narrays, u
     else if (c10)
         emit(p, step, PA_KERN(col10_fwd, Stage, false), grid, dim3(COL_THREADS), 0, cf, st);
     else if (c9 && p->mix)  // three primes and radix-3 transforms per tile
-        emit(p, step, PA_KERN(col9_fwd, Stage, true), grid, dim3(COL_THREADS), 0, cf, st);
+        emit(p, step, PA_KERN(col9_fwd, Stage, true), grid, dim3(c9f_threads(Stage, true)), 0, cf, st);
     else if (c9)  // three primes per tile
-        emit(p, step, PA_KERN(col9_fwd, Stage, false), grid, dim3(COL_THREADS), 0, cf, st);
+        emit(p, step, PA_KERN(col9_fwd, Stage, false), grid, dim3(c9f_threads(Stage, false)), 0, cf, st);
     else if (p->mix)
         launch_col_fwd_generic<Stage, 3>(p, cf, narrays, zsplit, st);
     else
